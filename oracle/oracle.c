@@ -1,0 +1,280 @@
+/*
+ * oracle.c -- FP64 CPU oracle for the FReSCo structure-factor loss and its
+ * position gradient (Shih, Casiulis & Martiniani, "Fast Generation of
+ * Spectrally-Shaped Disorder", arXiv 2305.15693).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file exists so that tests, the smoke check
+ * and the CPU-baseline leg of the benchmark have an independent, plainly
+ * correct reference.  The product (the HIP library) never links, loads or
+ * calls it, and it shares no code, header, table or constant with the HIP
+ * path.
+ *
+ * Everything is evaluated by direct sums straight from the definitions; no
+ * nonuniform FFT, no grids, no approximation:
+ *
+ *   rho(k)  = sum_j c_j exp(+i k.r_j)                 (Methods, Eq. ft; c_j = 1)
+ *   S(k)    = |rho(k)|^2 / N                          (Eq. structure_factor)
+ *   L       = sum_{k in K} W(k) (S(k) - S0(k))^2      (Methods, loss with W)
+ *   C_a(k)  = -4 i k_a W(k) (S(k) - S0(k)) rho(k) / N
+ *   dL/dr_ja = Re sum_{k in K} C_a(k) exp(-i k.r_j)   (Eq. gradient /
+ *                                                      Eq. losspositiongradient)
+ *
+ * Wave vectors are k = 2 pi n / L_a for integer mode vectors n; the caller
+ * passes the constrained set K as an explicit list of mode vectors (the full
+ * set, both n and -n, exactly as the sum in the loss runs).  Positions are read
+ * exactly as given (fp32 inputs are widened to fp64 by the caller, which is
+ * exact) and are not wrapped: exp(i k.r) has period L in every coordinate.
+ *
+ * The per-point factors exp(i 2 pi m r_a / L_a), m = -M..M, are taken from
+ * direct libm cos/sin calls (no recurrences), and the multi-dimensional
+ * exponential is their product, which is the same number up to rounding.
+ *
+ * Determinism: points are processed in fixed blocks; within a block each mode
+ * is owned by one thread and summed in point order, so results do not depend
+ * on the thread count.
+ *
+ * Pinning: see tests/test_oracle_pins.py (lattice Bragg values, N=1 and N=2
+ * closed forms, the pair form of S, Friedel/translation/permutation
+ * invariance, the gradient sum rule, Poisson statistics and finite
+ * differences).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_EINVAL -1
+#define OR_ENOMEM -2
+
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* largest |n_a| over the mode list, per dimension */
+static void mode_extent(int d, long long K, const int* modes, int* M) {
+  for (int a = 0; a < 3; ++a) M[a] = 0;
+  for (long long q = 0; q < K; ++q)
+    for (int a = 0; a < d; ++a) {
+      int v = modes[q * d + a];
+      if (v < 0) v = -v;
+      if (v > M[a]) M[a] = v;
+    }
+}
+
+/* table for one point: tab[a][m + M_a] = exp(i 2 pi m r_a / L_a), m in [-M_a, M_a]
+ * layout: re/im interleaved; offsets off[a] into the point's table. */
+static void point_table(int d, const double* L, const double* r, const int* M,
+                        const long long* off, double* tab) {
+  for (int a = 0; a < d; ++a) {
+    double* t = tab + 2 * off[a];
+    for (int m = -M[a]; m <= M[a]; ++m) {
+      double ph = TWO_PI * (double)m * r[a] / L[a];
+      t[2 * (m + M[a])] = cos(ph);
+      t[2 * (m + M[a]) + 1] = sin(ph);
+    }
+  }
+}
+
+/* exp(i k.r) for mode n from the point's table: product over dimensions */
+static inline void mode_exp(int d, const int* n, const int* M, const long long* off,
+                            const double* tab, double* re, double* im) {
+  double pr = 1.0, pi = 0.0;
+  for (int a = 0; a < d; ++a) {
+    const double* t = tab + 2 * (off[a] + n[a] + M[a]);
+    double xr = pr * t[0] - pi * t[1];
+    double xi = pr * t[1] + pi * t[0];
+    pr = xr;
+    pi = xi;
+  }
+  *re = pr;
+  *im = pi;
+}
+
+#define BLOCK 512
+
+/* rho(k) = sum_j exp(+i k.r_j) over the listed modes; rho is [K][2] (re, im). */
+int oracle_rho(int d, long long N, const double* L, const double* pos, long long K,
+               const int* modes, double* rho) {
+  if (d < 1 || d > 3 || N < 0 || K < 0 || !L || (N && !pos) || (K && (!modes || !rho)))
+    return OR_EINVAL;
+  int M[3];
+  mode_extent(d, K, modes, M);
+  long long off[3], tlen = 0;
+  for (int a = 0; a < d; ++a) { off[a] = tlen; tlen += 2 * M[a] + 1; }
+  double* tabs = (double*)malloc(sizeof(double) * 2 * tlen * BLOCK);
+  if (!tabs) return OR_ENOMEM;
+  for (long long q = 0; q < 2 * K; ++q) rho[q] = 0.0;
+  for (long long j0 = 0; j0 < N; j0 += BLOCK) {
+    long long nb = (N - j0 < BLOCK) ? N - j0 : BLOCK;
+#pragma omp parallel for schedule(static)
+    for (long long b = 0; b < nb; ++b)
+      point_table(d, L, pos + (j0 + b) * d, M, off, tabs + 2 * tlen * b);
+#pragma omp parallel for schedule(static)
+    for (long long q = 0; q < K; ++q) {
+      double sr = 0.0, si = 0.0;
+      for (long long b = 0; b < nb; ++b) {
+        double er, ei;
+        mode_exp(d, modes + q * d, M, off, tabs + 2 * tlen * b, &er, &ei);
+        sr += er;
+        si += ei;
+      }
+      rho[2 * q] += sr;
+      rho[2 * q + 1] += si;
+    }
+  }
+  free(tabs);
+  return OR_OK;
+}
+
+/*
+ * Loss and gradient from the definitions.
+ *   W, S0       : per listed mode (W already includes any 1/S0^2 normalisation)
+ *   S_out       : [K] structure factor (may be NULL)
+ *   rho_out     : [K][2] (may be NULL)
+ *   loss_out    : scalar (may be NULL)
+ *   G, gidx     : gradient wanted for points gidx[0..G) (gidx NULL: points 0..G-1)
+ *   grad_out    : [G][d] (may be NULL)
+ */
+int oracle_loss_grad(int d, long long N, const double* L, const double* pos, long long K,
+                     const int* modes, const double* W, const double* S0, double* S_out,
+                     double* rho_out, double* loss_out, long long G, const long long* gidx,
+                     double* grad_out) {
+  if (d < 1 || d > 3 || N <= 0 || K < 0 || !L || !pos || (K && (!modes || !W || !S0)))
+    return OR_EINVAL;
+  if (G < 0 || (G && !grad_out)) return OR_EINVAL;
+  double* rho = (double*)malloc(sizeof(double) * 2 * (K ? K : 1));
+  double* C = (double*)malloc(sizeof(double) * 2 * d * (K ? K : 1));
+  if (!rho || !C) { free(rho); free(C); return OR_ENOMEM; }
+  int st = oracle_rho(d, N, L, pos, K, modes, rho);
+  if (st) { free(rho); free(C); return st; }
+  double loss = 0.0;
+  for (long long q = 0; q < K; ++q) {
+    double S = (rho[2 * q] * rho[2 * q] + rho[2 * q + 1] * rho[2 * q + 1]) / (double)N;
+    double res = S - S0[q];
+    loss += W[q] * res * res;
+    if (S_out) S_out[q] = S;
+    /* C_a = -4 i k_a W res rho / N  =  (4 k_a W res / N) * (-i rho) */
+    for (int a = 0; a < d; ++a) {
+      double ka = TWO_PI * (double)modes[q * d + a] / L[a];
+      double f = 4.0 * ka * W[q] * res / (double)N;
+      C[2 * (q * d + a)] = f * rho[2 * q + 1];      /* Re(-i rho) = Im rho */
+      C[2 * (q * d + a) + 1] = -f * rho[2 * q];     /* Im(-i rho) = -Re rho */
+    }
+  }
+  if (rho_out) memcpy(rho_out, rho, sizeof(double) * 2 * K);
+  if (loss_out) *loss_out = loss;
+  if (G && grad_out) {
+    int M[3];
+    mode_extent(d, K, modes, M);
+    long long off[3], tlen = 0;
+    for (int a = 0; a < d; ++a) { off[a] = tlen; tlen += 2 * M[a] + 1; }
+    int fail = 0;
+#pragma omp parallel
+    {
+      double* tab = (double*)malloc(sizeof(double) * 2 * tlen);
+      if (!tab) {
+#pragma omp atomic write
+        fail = 1;
+      } else {
+#pragma omp for schedule(dynamic, 16)
+        for (long long g = 0; g < G; ++g) {
+          long long j = gidx ? gidx[g] : g;
+          double acc[3] = {0.0, 0.0, 0.0};
+          if (j >= 0 && j < N) {
+            point_table(d, L, pos + j * d, M, off, tab);
+            for (long long q = 0; q < K; ++q) {
+              double er, ei; /* exp(+i k.r_j); exp(-i k.r_j) is its conjugate */
+              mode_exp(d, modes + q * d, M, off, tab, &er, &ei);
+              for (int a = 0; a < d; ++a) {
+                const double* c = C + 2 * (q * d + a);
+                /* Re[c * (er - i ei)] = c_re er + c_im ei */
+                acc[a] += c[0] * er + c[1] * ei;
+              }
+            }
+          }
+          for (int a = 0; a < d; ++a) grad_out[g * d + a] = acc[a];
+        }
+        free(tab);
+      }
+    }
+    if (fail) { free(rho); free(C); return OR_ENOMEM; }
+  }
+  free(rho);
+  free(C);
+  return OR_OK;
+}
+
+/*
+ * Central finite differences of L along single coordinates, computed without
+ * cancellation: moving r_ja by +-h changes rho(k) by
+ *   delta_pm(k) = exp(i k.r_j) (exp(+-i k_a h) - 1),
+ * with exp(i t) - 1 = -2 sin^2(t/2) + i sin t, so that
+ *   S_pm - S   = [2 Re(conj(rho) delta_pm) + |delta_pm|^2] / N,
+ *   L_+ - L_-  = sum_k W (S_+ - S_-) (S_+ + S_- - 2 S0).
+ * out[c] = (L_+ - L_-) / (2h) for coordinate (cj[c], ca[c]).
+ */
+int oracle_fd(int d, long long N, const double* L, const double* pos, long long K,
+              const int* modes, const double* W, const double* S0, long long nc,
+              const long long* cj, const int* ca, double h, double* out) {
+  if (d < 1 || d > 3 || N <= 0 || K < 0 || !L || !pos || nc < 0 || (nc && (!cj || !ca || !out)))
+    return OR_EINVAL;
+  double* rho = (double*)malloc(sizeof(double) * 2 * (K ? K : 1));
+  if (!rho) return OR_ENOMEM;
+  int st = oracle_rho(d, N, L, pos, K, modes, rho);
+  if (st) { free(rho); return st; }
+  int M[3];
+  mode_extent(d, K, modes, M);
+  long long off[3], tlen = 0;
+  for (int a = 0; a < d; ++a) { off[a] = tlen; tlen += 2 * M[a] + 1; }
+  int fail = 0;
+#pragma omp parallel
+  {
+    double* tab = (double*)malloc(sizeof(double) * 2 * tlen);
+    if (!tab) {
+#pragma omp atomic write
+      fail = 1;
+    } else {
+#pragma omp for schedule(dynamic, 1)
+      for (long long c = 0; c < nc; ++c) {
+        long long j = cj[c];
+        int a = ca[c];
+        double dl = 0.0;
+        if (j >= 0 && j < N && a >= 0 && a < d) {
+          point_table(d, L, pos + j * d, M, off, tab);
+          for (long long q = 0; q < K; ++q) {
+            double er, ei;
+            mode_exp(d, modes + q * d, M, off, tab, &er, &ei);
+            double ka = TWO_PI * (double)modes[q * d + a] / L[a];
+            double t = ka * h;
+            double s2 = sin(0.5 * t);
+            double cm1 = -2.0 * s2 * s2; /* cos t - 1 */
+            double sn = sin(t);
+            /* delta_+ = e (cm1 + i sn), delta_- = e (cm1 - i sn) */
+            double dpr = er * cm1 - ei * sn, dpi = er * sn + ei * cm1;
+            double dmr = er * cm1 + ei * sn, dmi = -er * sn + ei * cm1;
+            double rr = rho[2 * q], ri = rho[2 * q + 1];
+            double Sp_minus_S = (2.0 * (rr * dpr + ri * dpi) + dpr * dpr + dpi * dpi) / (double)N;
+            double Sm_minus_S = (2.0 * (rr * dmr + ri * dmi) + dmr * dmr + dmi * dmi) / (double)N;
+            double S = (rr * rr + ri * ri) / (double)N;
+            double dS = Sp_minus_S - Sm_minus_S;
+            double sumS = 2.0 * S + Sp_minus_S + Sm_minus_S;
+            dl += W[q] * dS * (sumS - 2.0 * S0[q]);
+          }
+        }
+        out[c] = dl / (2.0 * h);
+      }
+      free(tab);
+    }
+  }
+  free(rho);
+  return fail ? OR_ENOMEM : OR_OK;
+}

@@ -1,0 +1,196 @@
+"""FP64 CPU oracle for the FReSCo loss, structure factor and position gradient.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by ``__graft_entry__.smoke()`` and
+by the ``cpu_baseline`` leg of ``bench.py``.  The product library never uses it,
+and this module shares no code with the HIP path (it does not import the
+product package; the product package does not import it).
+
+The arithmetic lives in ``oracle.c`` (direct sums from the definitions, see the
+header there); this module marshals numpy arrays and turns the dense mode-cube
+description of a problem (targets S0 and weights w on every integer mode
+vector n with |n_a| <= M, C order, n_a running from -M to M) into the explicit
+list of constrained modes that the sums run over.
+
+Weight convention (Methods, "Analytical gradients"): the loss is
+``sum_k W(k) (S(k) - S0(k))^2`` with ``W = w / S0^2`` where ``S0 != 0`` and
+``W = w`` otherwise when the relative loss of Eq. (loss) is asked for
+(``relative=True``); with ``relative=False`` the weights are used as given.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, OpenMP, portable x86-64 code)."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off",
+               os.path.join(_HERE, "oracle.c"), "-o", _SO + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        lib = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lp = ctypes.POINTER(ctypes.c_longlong)
+        ll = ctypes.c_longlong
+        lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_rho.argtypes = [ctypes.c_int, ll, dp, dp, ll, ip, dp]
+        lib.oracle_rho.restype = ctypes.c_int
+        lib.oracle_loss_grad.argtypes = [ctypes.c_int, ll, dp, dp, ll, ip, dp, dp, dp, dp, dp,
+                                         ll, lp, dp]
+        lib.oracle_loss_grad.restype = ctypes.c_int
+        lib.oracle_fd.argtypes = [ctypes.c_int, ll, dp, dp, ll, ip, dp, dp, ll, lp, ip,
+                                  ctypes.c_double, dp]
+        lib.oracle_fd.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a, ct):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def _box(L, d):
+    L = np.broadcast_to(np.asarray(L, dtype=np.float64), (d,))
+    return np.ascontiguousarray(L, dtype=np.float64)
+
+
+def _pos(pos):
+    pos = np.asarray(pos)
+    if pos.ndim != 2:
+        raise ValueError("positions must be [N][d]")
+    return np.ascontiguousarray(pos, dtype=np.float64)  # fp32 -> fp64 is exact
+
+
+def mode_vectors(d: int, M: int) -> np.ndarray:
+    """All integer mode vectors of the cube, C order, n_a = -M..M: [(2M+1)^d][d]."""
+    ax = np.arange(-M, M + 1, dtype=np.int32)
+    grids = np.meshgrid(*([ax] * d), indexing="ij")
+    return np.stack([g.reshape(-1) for g in grids], axis=1).astype(np.int32)
+
+
+def effective_weights(w, S0, relative: bool):
+    """W = w / S0^2 where S0 != 0 (relative loss, Eq. loss), else w."""
+    w = np.asarray(w, dtype=np.float64)
+    S0 = np.asarray(S0, dtype=np.float64)
+    if not relative:
+        return w.copy()
+    W = w.copy()
+    nz = S0 != 0
+    W[nz] = w[nz] / (S0[nz] * S0[nz])
+    return W
+
+
+def constrained_set(d: int, M: int, w_cube, S0_cube, relative: bool = False):
+    """Explicit constrained set from dense cubes: modes with w != 0 (the k = 0 mode is
+    never part of the set).  Returns (modes [K][d] int32, W [K], S0 [K])."""
+    n = mode_vectors(d, M)
+    w = np.asarray(w_cube, dtype=np.float64).reshape(-1)
+    S0 = np.zeros_like(w) if S0_cube is None else np.asarray(S0_cube, dtype=np.float64).reshape(-1)
+    keep = (w != 0) & np.any(n != 0, axis=1)
+    W = effective_weights(w[keep], S0[keep], relative)
+    return np.ascontiguousarray(n[keep]), np.ascontiguousarray(W), np.ascontiguousarray(S0[keep])
+
+
+def rho(pos, L, modes) -> np.ndarray:
+    """rho(k) = sum_j exp(+i k.r_j) for the listed integer modes (k = 2 pi n / L)."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    out = np.zeros((modes.shape[0], 2), dtype=np.float64)
+    st = _load().oracle_rho(d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double),
+                            modes.shape[0], _p(modes, ctypes.c_int), _p(out, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle_rho failed ({st})")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def structure_factor(pos, L, modes) -> np.ndarray:
+    """S(k) = |rho(k)|^2 / N (Eq. structure_factor)."""
+    r = rho(pos, L, modes)
+    return (r.real ** 2 + r.imag ** 2) / np.asarray(pos).shape[0]
+
+
+def structure_factor_cube(pos, L, M: int) -> np.ndarray:
+    """S on the full mode cube (2M+1)^d, C order, including S(0) = N."""
+    d = np.asarray(pos).shape[1]
+    S = structure_factor(pos, L, mode_vectors(d, M))
+    return S.reshape((2 * M + 1,) * d)
+
+
+def loss_grad(pos, L, modes, W, S0, grad_points=None, want_grad: bool = True):
+    """Loss, structure factor on the listed modes and the gradient.
+
+    grad_points: None for every point, or an index array for a subset.
+    Returns dict(loss, S, rho, grad)."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    K = modes.shape[0]
+    W = np.ascontiguousarray(W, dtype=np.float64).reshape(K)
+    S0 = np.ascontiguousarray(S0, dtype=np.float64).reshape(K)
+    S = np.zeros(K)
+    rh = np.zeros((K, 2))
+    loss = np.zeros(1)
+    if not want_grad:
+        G, gidx, grad = 0, None, None
+    elif grad_points is None:
+        G, gidx = N, None
+        grad = np.zeros((N, d))
+    else:
+        gidx = np.ascontiguousarray(grad_points, dtype=np.int64)
+        G = gidx.shape[0]
+        grad = np.zeros((G, d))
+    st = _load().oracle_loss_grad(
+        d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double), K,
+        _p(modes, ctypes.c_int), _p(W, ctypes.c_double), _p(S0, ctypes.c_double),
+        _p(S, ctypes.c_double), _p(rh, ctypes.c_double), _p(loss, ctypes.c_double), G,
+        _p(gidx, ctypes.c_longlong), _p(grad, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle_loss_grad failed ({st})")
+    return {"loss": float(loss[0]), "S": S, "rho": rh[:, 0] + 1j * rh[:, 1], "grad": grad}
+
+
+def finite_difference(pos, L, modes, W, S0, coords, h: float) -> np.ndarray:
+    """Central differences (L(r + h e) - L(r - h e)) / (2h) for coordinates
+    coords = [(j, a), ...], evaluated without cancellation (see oracle.c)."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    K = modes.shape[0]
+    coords = np.asarray(coords, dtype=np.int64).reshape(-1, 2)
+    cj = np.ascontiguousarray(coords[:, 0], dtype=np.int64)
+    ca = np.ascontiguousarray(coords[:, 1], dtype=np.int32)
+    out = np.zeros(coords.shape[0])
+    W = np.ascontiguousarray(W, dtype=np.float64).reshape(K)
+    S0 = np.ascontiguousarray(S0, dtype=np.float64).reshape(K)
+    st = _load().oracle_fd(d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double), K,
+                           _p(modes, ctypes.c_int), _p(W, ctypes.c_double),
+                           _p(S0, ctypes.c_double), coords.shape[0],
+                           _p(cj, ctypes.c_longlong), _p(ca, ctypes.c_int), float(h),
+                           _p(out, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle_fd failed ({st})")
+    return out
