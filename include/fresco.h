@@ -1,0 +1,161 @@
+/*
+ * fresco.h -- C ABI of an MI355X (gfx950) implementation of the FReSCo
+ * structure-factor loss and its position gradient.
+ *
+ * Problem (main text, "Algorithm"; Methods, "Analytical gradients"):
+ *   N points r_j in a periodic box [0, L_0) x ... x [0, L_{d-1}), d = 2 or 3,
+ *   unit weights c_j = 1;  k = 2 pi n / L for integer mode vectors n;
+ *   rho(k)  = sum_j exp(+i k.r_j)                     (Methods, Eq. ft)
+ *   S(k)    = |rho(k)|^2 / N                          (Eq. structure_factor)
+ *   L_S     = sum_{k in K} W(k) (S(k) - S0(k))^2      (Eqs. SF_loss, loss with W)
+ *   dL_S/dr_j = Re sum_k C(k) exp(-i k.r_j),
+ *   C(k)    = -4 i k W(k) (S(k) - S0(k)) rho(k) / N   (Eq. gradient)
+ * evaluated as one type-1 nonuniform FFT and d type-2 nonuniform FFTs (the
+ * "NUwU" variant of the Methods), all on the GPU.
+ *
+ * Conventions shared by every call:
+ *   - Mode cube: the constrained region, targets and weights live on the dense
+ *     cube of integer modes |n_a| <= M_a ("kmax"), stored in C order over
+ *     (n_0, ..., n_{d-1}), index of n = (n_0 + M_0, ..., n_{d-1} + M_{d-1}).
+ *     The region K is the set of modes with nonzero weight; n = 0 is never in K.
+ *     The sum over K runs over the full set (both n and -n), as in Eq. SF_loss.
+ *   - Positions and gradients: device arrays [n][d] (row-major) of the problem's
+ *     dtype (float or double).  Positions may take any finite value; they are
+ *     wrapped into the box (exp(i k.r) is L-periodic), which is not an error.
+ *   - Streams: a context is bound to one HIP stream (passed as void*, NULL for the
+ *     default stream).  Calls enqueue work on that stream and return; the ones
+ *     taking a host pointer for the loss synchronise the stream before returning.
+ *     A context must not be used from two threads at once.
+ *   - Ownership: the context owns all scratch memory; the caller owns every
+ *     pointer it passes and keeps device buffers alive until the stream has
+ *     consumed them.
+ *   - Errors: every call returns 0 (FRESCO_OK) or a negative FRESCO_E* code; no
+ *     exception crosses the ABI.  fresco_error_string() describes a code and
+ *     fresco_last_hip_error() returns the last hipError_t seen by the library.
+ */
+#ifndef FRESCO_H
+#define FRESCO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fresco_dtype { FRESCO_F32 = 0, FRESCO_F64 = 1 };
+
+/* How the caller's weights w become the W of the loss (Methods, "Analytical
+ * gradients"): ABS uses W = w; RELATIVE uses W = w / S0^2 where S0 != 0 and
+ * W = w where S0 == 0, which is the relative loss of Eq. loss. */
+enum fresco_weight_mode { FRESCO_WEIGHT_ABS = 0, FRESCO_WEIGHT_RELATIVE = 1 };
+
+enum fresco_status {
+  FRESCO_OK = 0,
+  FRESCO_EINVAL = -1,      /* invalid argument (null pointer, bad size or option) */
+  FRESCO_ENOMEM = -2,      /* device or host allocation failed */
+  FRESCO_EHIP = -3,        /* a HIP runtime call failed (see fresco_last_hip_error) */
+  FRESCO_ENOTSUP = -4,     /* valid request outside what this build supports */
+  FRESCO_ENONFINITE = -5,  /* a position was NaN or infinite (synchronous calls only) */
+  FRESCO_ELINESEARCH = -6  /* line search failed repeatedly (optimizer) */
+};
+
+typedef struct fresco_problem {
+  int32_t dim;          /* d = 2 or 3 */
+  int32_t dtype;        /* FRESCO_F32 or FRESCO_F64: positions, gradient, S, arithmetic */
+  int64_t n;            /* number of points N >= 1 */
+  double box[3];        /* box sides L_a > 0 (entries beyond dim ignored) */
+  int32_t kmax[3];      /* mode cube half-widths M_a >= 0 */
+  double k_cut;         /* used only when w == NULL: weight 1 on 0 < |n| <= k_cut */
+  const double* s0;     /* host, mode cube of targets S0(n); NULL means S0 = 0 */
+  const double* w;      /* host, mode cube of weights w(n) >= 0; NULL: see k_cut */
+  int32_t weight_mode;  /* fresco_weight_mode */
+  double tol;           /* requested relative accuracy of the nonuniform FFTs, e.g. 1e-6 */
+  double upsampfac;     /* fine-grid upsampling factor; 2.0 is the only value supported */
+} fresco_problem;
+
+typedef struct fresco_ctx fresco_ctx;
+
+/* Plan geometry chosen by fresco_create (for reporting and tests). */
+typedef struct fresco_plan_info {
+  int32_t dim;
+  int32_t dtype;
+  int64_t n;
+  int32_t nf[3];        /* fine grid size per dimension (even, 5-smooth) */
+  int32_t kmax[3];
+  int32_t width;        /* kernel width w (grid cells) */
+  double beta;          /* exponential-of-semicircle shape parameter */
+  int32_t tile[3];      /* spreading tile per dimension */
+  int64_t nbins;        /* number of tiles */
+  int64_t n_constrained;/* number of modes with nonzero weight (full set) */
+  int64_t device_bytes; /* scratch memory held by the context */
+} fresco_plan_info;
+
+/* Create a context for one problem.  Chooses the fine grid, kernel width and
+ * tiles, allocates every scratch buffer and copies targets and weights (host
+ * cubes of (2M_0+1)...(2M_{d-1}+1) doubles) to the device.
+ * Errors: EINVAL (null out/p, dim not 2 or 3, n < 1, L <= 0, M < 0, tol not in
+ * (0, 0.1], upsampfac != 2, a weight < 0 or non-finite, dtype unknown),
+ * ENOTSUP (more than 2^31 - 1 points, or a grid beyond the 32-bit index
+ * ranges of the passes), ENOMEM, EHIP.  On error *out is set to NULL. */
+int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream);
+
+/* Release a context (synchronises its stream first).  NULL is accepted. */
+int fresco_destroy(fresco_ctx* ctx);
+
+/* Geometry of a context.  EINVAL on null arguments. */
+int fresco_plan_info_get(const fresco_ctx* ctx, fresco_plan_info* out);
+
+/* Structure factor S(n) on the whole mode cube (Eq. structure_factor), written to
+ * the device array S of (2M_0+1)...(2M_{d-1}+1) elements of the dtype, C order;
+ * S(0) = N is included.  pos: device [n][d].  Stream-ordered; returns after
+ * enqueueing.  Errors: EINVAL (null pointers), EHIP. */
+int fresco_structure_factor(fresco_ctx* ctx, const void* pos, void* S);
+
+/* Loss L_S and gradient dL_S/dr_j (Eq. gradient).  pos: device [n][d];
+ * grad: device [n][d], overwritten.  loss: HOST pointer to one double; the call
+ * synchronises the stream and then also reports non-finite positions
+ * (ENONFINITE; the outputs are then meaningless).  Errors: EINVAL, EHIP,
+ * ENONFINITE. */
+int fresco_loss_grad(fresco_ctx* ctx, const void* pos, double* loss, void* grad);
+
+/* As fresco_loss_grad, but loss_dev is a DEVICE pointer to one double and the
+ * call only enqueues work (no synchronisation, no non-finite report), so it can
+ * be captured in a HIP graph.  Errors: EINVAL, EHIP. */
+int fresco_loss_grad_async(fresco_ctx* ctx, const void* pos, double* loss_dev, void* grad);
+
+/* Stages of one evaluation, for fresco_set_timing / fresco_read_timing. */
+enum fresco_stage {
+  FRESCO_STAGE_BIN = 0,          /* wrap, split, counting sort by tile */
+  FRESCO_STAGE_SPREAD = 1,       /* points -> fine grid (type-1 spreading) */
+  FRESCO_STAGE_FFT_ROWS_FWD = 2, /* real rows -> half spectrum along axis 0 */
+  FRESCO_STAGE_FFT_COLS_FWD = 3, /* forward columns before the last axis (3D) */
+  FRESCO_STAGE_MODES = 4,        /* last forward axis + S, loss, coefficients + first inverse */
+  FRESCO_STAGE_FFT_COLS_INV = 5, /* inverse columns after the first (3D) */
+  FRESCO_STAGE_FFT_ROWS_INV = 6, /* half spectra -> real grids along axis 0 */
+  FRESCO_STAGE_INTERP = 7,       /* grids -> gradient at the points (type-2 interpolation) */
+  FRESCO_STAGE_COUNT = 8
+};
+
+/* Diagnostics: bracket the launches of the stages whose bit (1 << stage) is set
+ * in stage_mask with HIP events on the context's stream (0 turns timing off).
+ * Errors: EINVAL. */
+int fresco_set_timing(fresco_ctx* ctx, uint32_t stage_mask);
+
+/* Synchronise the stream, add the durations of all bracketed launches since the
+ * last read to the running totals and return them: ms_total[s] is the summed
+ * duration in milliseconds and launches[s] the number of timed evaluations of
+ * stage s (arrays of FRESCO_STAGE_COUNT entries; either may be NULL).  reset != 0
+ * clears the totals after copying.  Errors: EINVAL, EHIP. */
+int fresco_read_timing(fresco_ctx* ctx, double* ms_total, int64_t* launches, int reset);
+
+/* Describe a status code (static string). */
+const char* fresco_error_string(int code);
+
+/* Last hipError_t value the library observed (0 if none). */
+int fresco_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRESCO_H */

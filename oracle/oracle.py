@@ -84,10 +84,15 @@ def _pos(pos):
     return np.ascontiguousarray(pos, dtype=np.float64)  # fp32 -> fp64 is exact
 
 
-def mode_vectors(d: int, M: int) -> np.ndarray:
-    """All integer mode vectors of the cube, C order, n_a = -M..M: [(2M+1)^d][d]."""
-    ax = np.arange(-M, M + 1, dtype=np.int32)
-    grids = np.meshgrid(*([ax] * d), indexing="ij")
+def _extent(d, M):
+    return [int(m) for m in np.broadcast_to(np.asarray(M, dtype=np.int64), (d,))]
+
+
+def mode_vectors(d: int, M) -> np.ndarray:
+    """All integer mode vectors of the cube, C order, n_a = -M_a..M_a (M an int or
+    one value per dimension): [prod (2M_a+1)][d]."""
+    axes = [np.arange(-m, m + 1, dtype=np.int32) for m in _extent(d, M)]
+    grids = np.meshgrid(*axes, indexing="ij")
     return np.stack([g.reshape(-1) for g in grids], axis=1).astype(np.int32)
 
 
@@ -103,7 +108,7 @@ def effective_weights(w, S0, relative: bool):
     return W
 
 
-def constrained_set(d: int, M: int, w_cube, S0_cube, relative: bool = False):
+def constrained_set(d: int, M, w_cube, S0_cube, relative: bool = False):
     """Explicit constrained set from dense cubes: modes with w != 0 (the k = 0 mode is
     never part of the set).  Returns (modes [K][d] int32, W [K], S0 [K])."""
     n = mode_vectors(d, M)
@@ -133,11 +138,11 @@ def structure_factor(pos, L, modes) -> np.ndarray:
     return (r.real ** 2 + r.imag ** 2) / np.asarray(pos).shape[0]
 
 
-def structure_factor_cube(pos, L, M: int) -> np.ndarray:
-    """S on the full mode cube (2M+1)^d, C order, including S(0) = N."""
+def structure_factor_cube(pos, L, M) -> np.ndarray:
+    """S on the full mode cube prod (2M_a+1), C order, including S(0) = N."""
     d = np.asarray(pos).shape[1]
     S = structure_factor(pos, L, mode_vectors(d, M))
-    return S.reshape((2 * M + 1,) * d)
+    return S.reshape(tuple(2 * m + 1 for m in _extent(d, M)))
 
 
 def loss_grad(pos, L, modes, W, S0, grad_points=None, want_grad: bool = True):

@@ -1,0 +1,746 @@
+// C ABI of the FReSCo loss/gradient library: context lifetime, argument
+// checking, buffers and the launch sequence of one evaluation.
+//
+// One evaluation of L_S and its gradient (the NUwU variant of the Methods: one
+// type-1 transform for S, d type-2 transforms for the gradient) is, on the
+// context's stream:
+//   bin      wrap, split and counting-sort the points by tile        (spread.hip)
+//   spread   tiles -> real fine grid b                               (spread.hip)
+//   rows     b -> half spectrum along axis 0                         (fft.hip)
+//   cols     remaining axes; the last forward axis is fused with the mode
+//            stage (deconvolve, S, loss, gradient coefficients) and with the
+//            first inverse transforms of the d coefficient fields     (fft.hip)
+//   cols/rows inverse transforms back to d real grids                 (fft.hip)
+//   interp   d grids -> gradient at every point                       (spread.hip)
+//   reduce   FP64 loss partials -> loss                              (here)
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "fft.h"
+#include "plan.h"
+
+using namespace fresco;
+
+static int g_last_hip = 0;
+
+#define HIPCHK(x)                       \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) {             \
+      g_last_hip = (int)e_;             \
+      return FRESCO_EHIP;               \
+    }                                   \
+  } while (0)
+
+namespace {
+
+template <class R>
+struct State {
+  AxisFft<R> ax[3];  // [0] rows: complex length nf0/2; [1], [2]: columns along axes 1, 2
+  uint32_t* key = nullptr;
+  uint32_t* rank = nullptr;
+  uint32_t* count = nullptr;
+  long long* start = nullptr;
+  Rec<R>* rec = nullptr;
+  int* perm = nullptr;
+  int* flag = nullptr;
+  R* grid = nullptr;
+  cpx<R>* A1 = nullptr;
+  cpx<R>* A2 = nullptr;
+  cpx<R>* V1[3] = {nullptr, nullptr, nullptr};
+  cpx<R>* V2[3] = {nullptr, nullptr, nullptr};
+  R* v[3] = {nullptr, nullptr, nullptr};
+  R* dec[3] = {nullptr, nullptr, nullptr};
+  R* Wp = nullptr;
+  R* S0p = nullptr;
+  R* Wm = nullptr;
+  R* S0m = nullptr;
+  cpx<R>* rho = nullptr;
+  double* loss_part = nullptr;
+  double* loss_dev = nullptr;
+  RowParams<R> rows;
+  ColParams<R> col1;   // axis 1 (3D: forward / inverse; 2D: fused)
+  ColParams<R> col2;   // axis 2 (3D: fused)
+  long long nloss_part = 0;
+};
+
+}  // namespace
+
+struct fresco_ctx {
+  Geom g;
+  int dtype;
+  hipStream_t st;
+  long long n_constrained;
+  long long bytes = 0;
+  std::vector<void*> allocs;
+  double* host_loss = nullptr;  // pinned
+  int* host_flag = nullptr;     // pinned
+  void* state = nullptr;
+  // per-stage timing (diagnostics): event pairs recorded on the stream
+  uint32_t timing_mask = 0;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[FRESCO_STAGE_COUNT];
+  double stage_ms[FRESCO_STAGE_COUNT] = {};
+  long long stage_n[FRESCO_STAGE_COUNT] = {};
+};
+
+namespace {
+
+hipEvent_t take_event(fresco_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches of one stage with events when its timing bit is set.
+struct StageTimer {
+  fresco_ctx* c;
+  int s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  StageTimer(fresco_ctx* c_, int s_) : c(c_), s(s_) {
+    if (c->timing_mask & (1u << s)) {
+      e0 = take_event(c);
+      e1 = take_event(c);
+      if (e0 && e1) (void)hipEventRecord(e0, c->st);
+    }
+  }
+  ~StageTimer() {
+    if (e0 && e1) {
+      (void)hipEventRecord(e1, c->st);
+      c->pending[s].push_back({e0, e1});
+    } else {
+      if (e0) c->event_pool.push_back(e0);
+      if (e1) c->event_pool.push_back(e1);
+    }
+  }
+};
+
+int dalloc(fresco_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    (void)hipGetLastError();
+    return FRESCO_ENOMEM;
+  }
+  c->allocs.push_back(*p);
+  c->bytes += (long long)bytes;
+  return FRESCO_OK;
+}
+
+template <class T>
+int dalloc_t(fresco_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  int st = dalloc(c, &q, count * sizeof(T));
+  *p = (T*)q;
+  return st;
+}
+
+template <class R>
+int upload(fresco_ctx* c, R** dst, const std::vector<double>& src) {
+  int st = dalloc_t(c, dst, src.size());
+  if (st) return st;
+  std::vector<R> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (R)src[i];
+  HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice));
+  return FRESCO_OK;
+}
+
+template <class R>
+int setup_axis(fresco_ctx* c, AxisFft<R>* ax, int n, bool rows_twn) {
+  if (!plan_factors(n, &ax->F, &ax->rmin)) return FRESCO_ENOTSUP;
+  std::vector<double> t = twiddles(n, n);
+  R* p = nullptr;
+  int st = upload<R>(c, &p, t);
+  if (st) return st;
+  ax->tw = (cpx<R>*)p;
+  if (rows_twn) {
+    std::vector<double> t2 = twiddles(2 * n, n);
+    st = upload<R>(c, &p, t2);
+    if (st) return st;
+    ax->twN = (cpx<R>*)p;
+  }
+  return FRESCO_OK;
+}
+
+// launch shape of a row pass: lines per block and block size
+bool shape_rows(int H, int rmin, long long nrows, size_t cs, int* lpb, int* threads) {
+  int l = 1;
+  while (l * 2 <= 16 && (size_t)(l * 2) * (H + 1) * cs <= 32768 && nrows / (l * 2) >= 1024) l *= 2;
+  int t = 256;
+  for (;;) {
+    int JT = t / l;
+    int need = (H + rmin * JT - 1) / (rmin * JT);
+    if (need <= 8) break;
+    if (t < 1024) t *= 2;
+    else if (l > 1) l /= 2;
+    else return false;
+  }
+  if ((size_t)l * (H + 1) * cs > 160 * 1024) return false;
+  *lpb = l;
+  *threads = t;
+  return true;
+}
+
+// launch shape of a column pass: columns per block and block size
+bool shape_cols(int n, int rmin, long long ncols, size_t cs, int* bc, int* threads) {
+  int b = 1;
+  while (b * 2 <= 16 && (size_t)(b * 2) * n * cs <= 49152 && ncols / (b * 2) >= 512) b *= 2;
+  int t = 256;
+  for (;;) {
+    int JT = t / b;
+    int need = (n + rmin * JT - 1) / (rmin * JT);
+    if (need <= 8) break;
+    if (t < 1024) t *= 2;
+    else if (b > 1) b /= 2;
+    else return false;
+  }
+  if ((size_t)b * n * cs * 3 / 2 > 160 * 1024) return false;
+  *bc = b;
+  *threads = t;
+  return true;
+}
+
+__global__ void reduce_loss_kernel(const double* __restrict__ part, long long n,
+                                   double* __restrict__ out) {
+  __shared__ double s[256];
+  double v = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) v += part[i];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+template <class R>
+int create_state(fresco_ctx* c, const fresco_problem* p) {
+  State<R>* S = new (std::nothrow) State<R>();
+  if (!S) return FRESCO_ENOMEM;
+  c->state = S;
+  Geom& g = c->g;
+  const int d = g.d;
+  const size_t cs = sizeof(cpx<R>);
+  int st;
+  // FFT plans
+  if ((st = setup_axis<R>(c, &S->ax[0], g.nf[0] / 2, true))) return st;
+  if ((st = setup_axis<R>(c, &S->ax[1], g.nf[1], false))) return st;
+  if (d == 3 && (st = setup_axis<R>(c, &S->ax[2], g.nf[2], false))) return st;
+  // binning
+  const long long N = g.N;
+  if ((st = dalloc_t(c, &S->key, N))) return st;
+  if ((st = dalloc_t(c, &S->rank, N))) return st;
+  if ((st = dalloc_t(c, &S->count, g.nbins))) return st;
+  if ((st = dalloc_t(c, &S->start, g.nbins + 1))) return st;
+  if ((st = dalloc_t(c, &S->rec, N))) return st;
+  if ((st = dalloc_t(c, &S->perm, N))) return st;
+  if ((st = dalloc_t(c, &S->flag, 1))) return st;
+  // grids
+  const long long H0 = g.M[0] + 1;
+  const long long P1 = 2 * g.M[1] + 1;
+  const long long nf1 = g.nf[1], nf2 = (d == 3) ? g.nf[2] : 1;
+  if ((st = dalloc_t(c, &S->grid, g.ngrid))) return st;
+  if ((st = dalloc_t(c, &S->A1, nf2 * nf1 * H0))) return st;
+  if (d == 3 && (st = dalloc_t(c, &S->A2, nf2 * P1 * H0))) return st;
+  for (int a = 0; a < d; ++a) {
+    if ((st = dalloc_t(c, &S->V1[a], nf2 * nf1 * H0))) return st;
+    if (d == 3 && (st = dalloc_t(c, &S->V2[a], nf2 * P1 * H0))) return st;
+    if ((st = dalloc_t(c, &S->v[a], g.ngrid))) return st;
+  }
+  // deconvolution factors dec_a(n) = h_a / psihat_a(n)
+  for (int a = 0; a < d; ++a) {
+    std::vector<double> ph = kernel_fourier(g.M[a], g.w, g.beta, g.nf[a]);
+    const double h = 2.0 * M_PI / g.nf[a];
+    for (auto& x : ph) x = h / x;
+    if ((st = upload<R>(c, &S->dec[a], ph))) return st;
+  }
+  if ((st = dalloc_t(c, &S->rho, g.nhalf))) return st;
+  if ((st = dalloc_t(c, &S->loss_dev, 1))) return st;
+
+  // launch shapes
+  RowParams<R>& rp = S->rows;
+  std::memset(&rp, 0, sizeof(rp));
+  rp.nrows = nf1 * nf2;
+  rp.M0 = g.M[0];
+  if (!shape_rows(g.nf[0] / 2, S->ax[0].rmin, rp.nrows, cs, &rp.lines_per_block, &rp.threads))
+    return FRESCO_ENOTSUP;
+  auto fill_modes = [&](ColParams<R>& cp) {
+    cp.d = d;
+    cp.M0 = g.M[0];
+    cp.M1 = g.M[1];
+    cp.M2 = (d == 3) ? g.M[2] : 0;
+    cp.P1 = 2 * g.M[1] + 1;
+    cp.P2 = (d == 3) ? 2 * g.M[2] + 1 : 1;
+    cp.h0div = make_fastdiv((uint32_t)H0);
+    for (int a = 0; a < 3; ++a) {
+      cp.dec[a] = (a < d) ? S->dec[a] : nullptr;
+      cp.kscale[a] = (a < d) ? (R)(2.0 * M_PI / g.L[a]) : R(0);
+    }
+    cp.invN = (R)(1.0 / (double)g.N);
+  };
+  ColParams<R>& c1 = S->col1;
+  std::memset(&c1, 0, sizeof(c1));
+  fill_modes(c1);
+  if (d == 2) {
+    // fused pass along axis 1 over the H0 columns of A1[l1][n0]
+    c1.ncols = H0;
+    c1.M = g.M[1];
+    c1.cdiv = make_fastdiv((uint32_t)H0);
+    c1.in_outer = 0;
+    c1.in_line = H0;
+    c1.out_outer = 0;
+    c1.out_line = H0;
+    if (!shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads))
+      return FRESCO_ENOTSUP;
+    S->nloss_part = (c1.ncols + c1.bc - 1) / c1.bc;
+  } else {
+    // axis 1, columns (l2, n0): A1[l2][l1][n0] <-> A2[l2][m1][n0]
+    c1.ncols = nf2 * H0;
+    c1.M = g.M[1];
+    c1.cdiv = make_fastdiv((uint32_t)H0);
+    if (!shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads))
+      return FRESCO_ENOTSUP;
+    ColParams<R>& c2 = S->col2;
+    std::memset(&c2, 0, sizeof(c2));
+    fill_modes(c2);
+    c2.ncols = P1 * H0;
+    c2.M = g.M[2];
+    c2.cdiv = make_fastdiv((uint32_t)c2.ncols);
+    c2.in_outer = 0;
+    c2.in_line = P1 * H0;
+    c2.out_outer = 0;
+    c2.out_line = P1 * H0;
+    if (!shape_cols(g.nf[2], S->ax[2].rmin, c2.ncols, cs, &c2.bc, &c2.threads))
+      return FRESCO_ENOTSUP;
+    S->nloss_part = (c2.ncols + c2.bc - 1) / c2.bc;
+  }
+  if ((st = dalloc_t(c, &S->loss_part, S->nloss_part))) return st;
+  return FRESCO_OK;
+}
+
+// half-spectrum weights from the caller's cubes
+template <class R>
+int upload_weights(fresco_ctx* c, const fresco_problem* p, const std::vector<double>& Wc,
+                   const std::vector<double>& S0c) {
+  State<R>* S = (State<R>*)c->state;
+  const Geom& g = c->g;
+  const int d = g.d;
+  const long long H0 = g.M[0] + 1, P1 = 2 * g.M[1] + 1, P2 = (d == 3) ? 2 * g.M[2] + 1 : 1;
+  const long long nlast = (d == 2) ? P1 : P2;
+  const long long ncols = (d == 2) ? H0 : P1 * H0;
+  std::vector<double> wp(g.nhalf), sp(g.nhalf), wm(g.nhalf), sm(g.nhalf);
+  auto cube_index = [&](int n0, int n1, int n2) -> long long {
+    if (d == 2) return (long long)(n0 + g.M[0]) * P1 + (n1 + g.M[1]);
+    return ((long long)(n0 + g.M[0]) * P1 + (n1 + g.M[1])) * P2 + (n2 + g.M[2]);
+  };
+  for (long long m = 0; m < nlast; ++m) {
+    for (long long cidx = 0; cidx < ncols; ++cidx) {
+      int n0, n1, n2 = 0;
+      if (d == 2) {
+        n0 = (int)cidx;
+        n1 = (int)m - g.M[1];
+      } else {
+        n0 = (int)(cidx % H0);
+        n1 = (int)(cidx / H0) - g.M[1];
+        n2 = (int)m - g.M[2];
+      }
+      long long h = cidx + ncols * m;
+      long long ip = cube_index(n0, n1, n2), im = cube_index(-n0, -n1, -n2);
+      wp[h] = Wc[ip];
+      sp[h] = S0c[ip];
+      wm[h] = Wc[im];
+      sm[h] = S0c[im];
+    }
+  }
+  int st;
+  if ((st = upload<R>(c, &S->Wp, wp))) return st;
+  if ((st = upload<R>(c, &S->S0p, sp))) return st;
+  if ((st = upload<R>(c, &S->Wm, wm))) return st;
+  if ((st = upload<R>(c, &S->S0m, sm))) return st;
+  return FRESCO_OK;
+}
+
+// ---------------------------------------------------------------- stages
+template <class R>
+int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
+  State<R>* S = (State<R>*)c->state;
+  const Geom& g = c->g;
+  hipStream_t st = c->st;
+  {
+    StageTimer t(c, FRESCO_STAGE_BIN);
+    launch_fill_u32(S->count, g.nbins, 0u, st);
+    launch_bin_count<R>(g, pos, S->key, S->rank, S->count, S->flag, st);
+    launch_scan_bins(g, S->count, S->start, st);
+    launch_bin_scatter<R>(g, pos, S->key, S->rank, S->start, S->rec, S->perm, st);
+  }
+  {
+    StageTimer t(c, FRESCO_STAGE_SPREAD);
+    launch_fill<R>(S->grid, g.ngrid, R(0), st);
+    launch_spread<R>(g, S->rec, S->start, S->grid, st);
+  }
+  RowParams<R> rp = S->rows;
+  rp.rin = S->grid;
+  rp.cout = S->A1;
+  {
+    StageTimer t(c, FRESCO_STAGE_FFT_ROWS_FWD);
+    HIPCHK(launch_rows<R>(false, rp, S->ax[0], 1, st));
+  }
+  return FRESCO_OK;
+}
+
+// mode stage + inverse transforms + interpolation; mode = COL_FUSED or COL_BWD
+template <class R>
+int run_modes_to_grad(fresco_ctx* c, int mode, R* S_cube, const R* g_cube, R* grad,
+                      double* loss_dev) {
+  State<R>* S = (State<R>*)c->state;
+  const Geom& g = c->g;
+  const int d = g.d;
+  hipStream_t st = c->st;
+  const long long H0 = g.M[0] + 1, P1 = 2 * g.M[1] + 1;
+  const long long nf1 = g.nf[1];
+  ColParams<R> last = (d == 2) ? S->col1 : S->col2;
+  last.in[0] = (d == 2) ? S->A1 : S->A2;
+  for (int a = 0; a < d; ++a) last.out[a] = (d == 2) ? S->V1[a] : S->V2[a];
+  last.Wp = S->Wp;
+  last.S0p = S->S0p;
+  last.Wm = S->Wm;
+  last.S0m = S->S0m;
+  last.loss_part = S->loss_part;
+  last.S_cube = S_cube;
+  last.rho_save = S->rho;
+  last.g_cube = g_cube;
+  {
+    StageTimer t(c, FRESCO_STAGE_MODES);
+    HIPCHK(launch_cols<R>(mode, last, S->ax[d - 1], d, st));
+  }
+  if (d == 3) {
+    ColParams<R> inv = S->col1;
+    inv.in_outer = P1 * H0;
+    inv.in_line = H0;
+    inv.out_outer = nf1 * H0;
+    inv.out_line = H0;
+    for (int a = 0; a < 3; ++a) {
+      inv.in[a] = S->V2[a];
+      inv.out[a] = S->V1[a];
+    }
+    StageTimer t(c, FRESCO_STAGE_FFT_COLS_INV);
+    HIPCHK(launch_cols<R>(COL_INV, inv, S->ax[1], 3, st));
+  }
+  RowParams<R> rp = S->rows;
+  for (int a = 0; a < d; ++a) {
+    rp.cin[a] = S->V1[a];
+    rp.rout[a] = S->v[a];
+  }
+  {
+    StageTimer t(c, FRESCO_STAGE_FFT_ROWS_INV);
+    HIPCHK(launch_rows<R>(true, rp, S->ax[0], d, st));
+  }
+  const R* comps[3] = {S->v[0], S->v[1], d == 3 ? S->v[2] : nullptr};
+  {
+    StageTimer t(c, FRESCO_STAGE_INTERP);
+    launch_interp<R>(g, S->rec, S->start, S->perm, comps, d, grad, st);
+  }
+  if (mode == COL_FUSED && loss_dev) {
+    reduce_loss_kernel<<<1, 256, 0, st>>>(S->loss_part, S->nloss_part, loss_dev);
+  }
+  HIPCHK(hipGetLastError());
+  return FRESCO_OK;
+}
+
+template <class R>
+int run_forward_3d_axis1(fresco_ctx* c) {
+  State<R>* S = (State<R>*)c->state;
+  const Geom& g = c->g;
+  const long long H0 = g.M[0] + 1, P1 = 2 * g.M[1] + 1;
+  ColParams<R> fw = S->col1;
+  fw.in_outer = (long long)g.nf[1] * H0;
+  fw.in_line = H0;
+  fw.out_outer = P1 * H0;
+  fw.out_line = H0;
+  fw.in[0] = S->A1;
+  fw.out[0] = S->A2;
+  StageTimer t(c, FRESCO_STAGE_FFT_COLS_FWD);
+  HIPCHK(launch_cols<R>(COL_FWD, fw, S->ax[1], 1, c->st));
+  return FRESCO_OK;
+}
+
+template <class R>
+int loss_grad_impl(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
+  State<R>* S = (State<R>*)c->state;
+  int st;
+  launch_fill_u32((uint32_t*)S->flag, 1, 0u, c->st);
+  if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
+  if (c->g.d == 3 && (st = run_forward_3d_axis1<R>(c))) return st;
+  return run_modes_to_grad<R>(c, COL_FUSED, nullptr, nullptr, (R*)grad, loss_dev);
+}
+
+template <class R>
+int structure_factor_impl(fresco_ctx* c, const void* pos, void* Sout) {
+  State<R>* S = (State<R>*)c->state;
+  const Geom& g = c->g;
+  int st;
+  launch_fill_u32((uint32_t*)S->flag, 1, 0u, c->st);
+  if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
+  if (g.d == 3 && (st = run_forward_3d_axis1<R>(c))) return st;
+  ColParams<R> last = (g.d == 2) ? S->col1 : S->col2;
+  last.in[0] = (g.d == 2) ? S->A1 : S->A2;
+  last.S_cube = (R*)Sout;
+  last.rho_save = S->rho;
+  StageTimer t(c, FRESCO_STAGE_MODES);
+  HIPCHK(launch_cols<R>(COL_SF, last, S->ax[g.d - 1], 1, c->st));
+  return FRESCO_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* fresco_error_string(int code) {
+  switch (code) {
+    case FRESCO_OK: return "ok";
+    case FRESCO_EINVAL: return "invalid argument";
+    case FRESCO_ENOMEM: return "out of memory";
+    case FRESCO_EHIP: return "HIP runtime error";
+    case FRESCO_ENOTSUP: return "not supported by this build";
+    case FRESCO_ENONFINITE: return "non-finite position";
+    case FRESCO_ELINESEARCH: return "line search failed";
+    default: return "unknown status";
+  }
+}
+
+int fresco_last_hip_error(void) { return g_last_hip; }
+
+int fresco_destroy(fresco_ctx* c) {
+  if (!c) return FRESCO_OK;
+  (void)hipStreamSynchronize(c->st);
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->host_loss) (void)hipHostFree(c->host_loss);
+  if (c->host_flag) (void)hipHostFree(c->host_flag);
+  for (int s = 0; s < FRESCO_STAGE_COUNT; ++s)
+    for (auto& pr : c->pending[s]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->state) {
+    if (c->dtype == FRESCO_F32) delete (State<float>*)c->state;
+    else delete (State<double>*)c->state;
+  }
+  delete c;
+  return FRESCO_OK;
+}
+
+int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
+  if (!out) return FRESCO_EINVAL;
+  *out = nullptr;
+  if (!p) return FRESCO_EINVAL;
+  const int d = p->dim;
+  if (d != 2 && d != 3) return FRESCO_EINVAL;
+  if (p->dtype != FRESCO_F32 && p->dtype != FRESCO_F64) return FRESCO_EINVAL;
+  if (p->n < 1) return FRESCO_EINVAL;
+  if (p->n > 2147483647LL) return FRESCO_ENOTSUP;
+  if (!(p->tol > 0.0 && p->tol <= 0.1)) return FRESCO_EINVAL;
+  if (p->upsampfac != 2.0) return FRESCO_EINVAL;
+  if (p->weight_mode != FRESCO_WEIGHT_ABS && p->weight_mode != FRESCO_WEIGHT_RELATIVE)
+    return FRESCO_EINVAL;
+  for (int a = 0; a < d; ++a) {
+    if (!(p->box[a] > 0.0) || !std::isfinite(p->box[a])) return FRESCO_EINVAL;
+    if (p->kmax[a] < 0) return FRESCO_EINVAL;
+  }
+  if (!p->w && !(p->k_cut >= 0.0)) return FRESCO_EINVAL;
+
+  fresco_ctx* c = new (std::nothrow) fresco_ctx();
+  if (!c) return FRESCO_ENOMEM;
+  c->dtype = p->dtype;
+  c->st = (hipStream_t)stream;
+  Geom& g = c->g;
+  std::memset(&g, 0, sizeof(g));
+  g.d = d;
+  g.N = p->n;
+  g.w = kernel_width(p->tol);
+  g.beta = kernel_beta(g.w);
+  g.nbins = 1;
+  g.ngrid = 1;
+  g.nhalf = 1;
+  g.ncube = 1;
+  const int tdef = (d == 2) ? 32 : (p->dtype == FRESCO_F32 ? 16 : 8);
+  for (int a = 0; a < 3; ++a) {
+    if (a < d) {
+      g.L[a] = p->box[a];
+      g.M[a] = p->kmax[a];
+      long long need = 2LL * (2LL * g.M[a] + 1);
+      if (need < 2LL * g.w) need = 2LL * g.w;
+      if (need > (1LL << 26)) { delete c; return FRESCO_ENOTSUP; }
+      g.nf[a] = next_smooth_even(need);
+      g.T[a] = tdef < g.nf[a] ? tdef : g.nf[a];
+      g.nt[a] = (g.nf[a] + g.T[a] - 1) / g.T[a];
+      g.E[a] = g.T[a] + g.w - 1;
+      g.nbins *= g.nt[a];
+      g.ngrid *= g.nf[a];
+      g.ncube *= 2LL * g.M[a] + 1;
+      g.nhalf *= (a == 0) ? (g.M[a] + 1) : (2LL * g.M[a] + 1);
+    } else {
+      g.L[a] = 1.0;
+      g.M[a] = 0;
+      g.nf[a] = 1;
+      g.T[a] = 1;
+      g.nt[a] = 1;
+      g.E[a] = 1;
+    }
+  }
+  // row FFT length nf0 / 2 and 32-bit index ranges of the passes
+  if (g.ngrid > (1LL << 31) * 4 || g.nhalf > (1LL << 31)) { delete c; return FRESCO_ENOTSUP; }
+
+  // weights and targets on the full cube (FP64, host)
+  std::vector<double> Wc(g.ncube, 0.0), S0c(g.ncube, 0.0);
+  if (p->s0)
+    for (long long i = 0; i < g.ncube; ++i) S0c[i] = p->s0[i];
+  long long ncons = 0;
+  int bad = 0;
+  for (long long i = 0; i < g.ncube; ++i) {
+    long long r = i;
+    long long n2 = 0;
+    bool zero = true;
+    for (int a = d - 1; a >= 0; --a) {
+      long long P = 2LL * g.M[a] + 1;
+      long long na = r % P - g.M[a];
+      r /= P;
+      n2 += na * na;
+      if (na != 0) zero = false;
+    }
+    double w;
+    if (p->w) w = p->w[i];
+    else w = (n2 > 0 && (double)n2 <= p->k_cut * p->k_cut) ? 1.0 : 0.0;
+    if (!(w >= 0.0) || !std::isfinite(w) || !std::isfinite(S0c[i])) bad = 1;
+    if (zero) w = 0.0;  // k = 0 is never constrained
+    double W = w;
+    if (p->weight_mode == FRESCO_WEIGHT_RELATIVE && S0c[i] != 0.0) W = w / (S0c[i] * S0c[i]);
+    Wc[i] = W;
+    if (W != 0.0) ++ncons;
+  }
+  if (bad) { delete c; return FRESCO_EINVAL; }
+  c->n_constrained = ncons;
+
+  int st;
+  if (p->dtype == FRESCO_F32) {
+    st = create_state<float>(c, p);
+    if (!st) st = upload_weights<float>(c, p, Wc, S0c);
+  } else {
+    st = create_state<double>(c, p);
+    if (!st) st = upload_weights<double>(c, p, Wc, S0c);
+  }
+  if (!st) {
+    hipError_t e = hipHostMalloc((void**)&c->host_loss, sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->host_flag, sizeof(int));
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      st = FRESCO_ENOMEM;
+    }
+  }
+  if (st) {
+    fresco_destroy(c);
+    return st;
+  }
+  *out = c;
+  return FRESCO_OK;
+}
+
+int fresco_plan_info_get(const fresco_ctx* c, fresco_plan_info* o) {
+  if (!c || !o) return FRESCO_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->dim = c->g.d;
+  o->dtype = c->dtype;
+  o->n = c->g.N;
+  for (int a = 0; a < 3; ++a) {
+    o->nf[a] = a < c->g.d ? c->g.nf[a] : 0;
+    o->kmax[a] = a < c->g.d ? c->g.M[a] : 0;
+    o->tile[a] = a < c->g.d ? c->g.T[a] : 0;
+  }
+  o->width = c->g.w;
+  o->beta = c->g.beta;
+  o->nbins = c->g.nbins;
+  o->n_constrained = c->n_constrained;
+  o->device_bytes = c->bytes;
+  return FRESCO_OK;
+}
+
+int fresco_set_timing(fresco_ctx* c, uint32_t mask) {
+  if (!c) return FRESCO_EINVAL;
+  c->timing_mask = mask & ((1u << FRESCO_STAGE_COUNT) - 1);
+  return FRESCO_OK;
+}
+
+int fresco_read_timing(fresco_ctx* c, double* ms_total, int64_t* launches, int reset) {
+  if (!c) return FRESCO_EINVAL;
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (int s = 0; s < FRESCO_STAGE_COUNT; ++s) {
+    for (auto& pr : c->pending[s]) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+      c->stage_ms[s] += ms;
+      c->stage_n[s] += 1;
+      c->event_pool.push_back(pr.first);
+      c->event_pool.push_back(pr.second);
+    }
+    c->pending[s].clear();
+    if (ms_total) ms_total[s] = c->stage_ms[s];
+    if (launches) launches[s] = c->stage_n[s];
+    if (reset) {
+      c->stage_ms[s] = 0.0;
+      c->stage_n[s] = 0;
+    }
+  }
+  return FRESCO_OK;
+}
+
+int fresco_structure_factor(fresco_ctx* c, const void* pos, void* S) {
+  if (!c || !pos || !S) return FRESCO_EINVAL;
+  if (c->dtype == FRESCO_F32) return structure_factor_impl<float>(c, pos, S);
+  return structure_factor_impl<double>(c, pos, S);
+}
+
+int fresco_loss_grad_async(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
+  if (!c || !pos || !loss_dev || !grad) return FRESCO_EINVAL;
+  if (c->dtype == FRESCO_F32) return loss_grad_impl<float>(c, pos, loss_dev, grad);
+  return loss_grad_impl<double>(c, pos, loss_dev, grad);
+}
+
+int fresco_loss_grad(fresco_ctx* c, const void* pos, double* loss, void* grad) {
+  if (!c || !pos || !loss || !grad) return FRESCO_EINVAL;
+  double* ldev;
+  int* flag;
+  int st;
+  if (c->dtype == FRESCO_F32) {
+    State<float>* S = (State<float>*)c->state;
+    ldev = S->loss_dev;
+    flag = S->flag;
+    st = loss_grad_impl<float>(c, pos, ldev, grad);
+  } else {
+    State<double>* S = (State<double>*)c->state;
+    ldev = S->loss_dev;
+    flag = S->flag;
+    st = loss_grad_impl<double>(c, pos, ldev, grad);
+  }
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(c->host_loss, ldev, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(c->host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  *loss = *c->host_loss;
+  if (*c->host_flag) return FRESCO_ENONFINITE;
+  return FRESCO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Internal declarations shared by the HIP translation units of the FReSCo
+// library: complex arithmetic, fast integer division, the plan geometry, the
+// per-point record produced by binning, and the launchers each unit exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "fresco.h"
+
+namespace fresco {
+
+// ---------------------------------------------------------------- complex
+template <class R>
+struct cpx {
+  R x, y;
+};
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return {a.x, -a.y}; }
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.x * s, a.y * s}; }
+// multiply by +i or -i
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cmul_i(cpx<R> a) { return {-a.y, a.x}; }
+template <class R>
+__host__ __device__ __forceinline__ cpx<R> cmul_mi(cpx<R> a) { return {a.y, -a.x}; }
+
+// ------------------------------------------------------- fast 32-bit divide
+// q = n / d for 0 <= n < 2^31 by multiply-high (Granlund & Montgomery 1994).
+struct FastDiv {
+  uint32_t d, m, s;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+  return f;
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return (__umulhi(n, f.m) + n) >> f.s;
+}
+
+// ------------------------------------------------------------ FFT factors
+constexpr int kMaxFactors = 20;
+struct FftFactors {
+  int n;                      // transform length
+  int nfac;                   // number of radix stages
+  int radix[kMaxFactors];     // radix of each stage (2, 3, 4 or 5)
+  FastDiv ns[kMaxFactors];    // Ns before each stage (product of earlier radices)
+  uint32_t twstep[kMaxFactors];  // n / (Ns * radix)
+};
+
+// ------------------------------------------------------------------ plan
+struct Geom {
+  int d;
+  long long N;
+  double L[3];
+  int M[3];       // mode half-widths
+  int nf[3];      // fine grid per dimension (nf[a] = 1 beyond d)
+  int w;          // kernel width
+  double beta;    // ES shape parameter
+  int T[3];       // tile size per dimension (1 beyond d)
+  int nt[3];      // tiles per dimension (1 beyond d)
+  int E[3];       // padded tile extent T + w - 1 (1 beyond d)
+  long long nbins;
+  long long ngrid;  // prod nf
+  long long nhalf;  // (M0+1) * prod_{a>0} (2M_a+1): half mode cube
+  long long ncube;  // prod (2M_a+1): full mode cube
+};
+
+// Sorted per-point record: offsets of the kernel footprint and the local cell.
+//   t[a]  = l0_a - u_a in [-w/2, -w/2 + 1), u_a = grid coordinate of the point,
+//           l0_a = first grid index of its footprint (before wrapping);
+//   cell  = local index of l0 inside its tile, 8 bits per dimension.
+template <class R>
+struct alignas(4 * sizeof(R)) Rec {
+  R t[3];
+  uint32_t cell;
+};
+
+// Launchers exported by the translation units (all enqueue on `st`).
+template <class R>
+void launch_bin_count(const Geom& g, const R* pos, uint32_t* key, uint32_t* rank,
+                      uint32_t* count, int* flag, hipStream_t st);
+void launch_scan_bins(const Geom& g, const uint32_t* count, long long* start, hipStream_t st);
+template <class R>
+void launch_bin_scatter(const Geom& g, const R* pos, const uint32_t* key, const uint32_t* rank,
+                        const long long* start, Rec<R>* rec, int* perm, hipStream_t st);
+template <class R>
+void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* grid,
+                   hipStream_t st);
+template <class R>
+void launch_interp(const Geom& g, const Rec<R>* rec, const long long* start, const int* perm,
+                   const R* const* comps, int ncomp, R* grad, hipStream_t st);
+template <class R>
+void launch_fill(R* p, long long n, R v, hipStream_t st);
+void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);
+
+// FFT passes (see fft.hip)
+struct FftTables;  // device twiddles and factors per axis
+enum ColMode { COL_FWD = 0, COL_INV = 1, COL_FUSED = 2, COL_SF = 3, COL_BWD = 4 };
+
+}  // namespace fresco

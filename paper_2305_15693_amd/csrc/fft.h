@@ -1,0 +1,64 @@
+// Parameter blocks of the FFT passes (see fft.hip).
+#pragma once
+
+#include "common.h"
+
+namespace fresco {
+
+// Device twiddles and stage plan of one transform length.
+template <class R>
+struct AxisFft {
+  FftFactors F;         // stages of the complex FFT of length F.n
+  int rmin;             // smallest radix used
+  cpx<R>* tw = nullptr;   // exp(+2 pi i q / F.n), q in [0, F.n)
+  cpx<R>* twN = nullptr;  // rows only: exp(+2 pi i q / (2 F.n)), q in [0, F.n)
+};
+
+template <class R>
+struct RowParams {
+  long long nrows;
+  int lines_per_block;
+  int threads;
+  int M0;
+  const R* rin;          // forward input rows (real, length 2H)
+  cpx<R>* cout;          // forward output rows (M0+1 complex)
+  const cpx<R>* cin[3];  // inverse inputs per component
+  R* rout[3];            // inverse outputs per component
+};
+
+template <class R>
+struct ColParams {
+  long long ncols;
+  int bc;        // columns per block (power of two)
+  int threads;   // block size
+  int M;         // mode half-width along this axis
+  FastDiv cdiv;  // columns per outer group
+  long long in_outer, in_line, out_outer, out_line;  // strides in complex elements
+  const cpx<R>* in[3];
+  cpx<R>* out[3];
+  // mode stage (last forward axis)
+  int d;
+  int M0, M1, M2;
+  int P1, P2;        // 2 M_1 + 1, 2 M_2 + 1 (cube indexing)
+  FastDiv h0div;     // M0 + 1
+  const R* dec[3];   // h_a / psihat_a(|n_a|), n_a in [0, M_a]
+  R kscale[3];       // 2 pi / L_a
+  R invN;
+  const R* Wp;       // half spectrum [m][c]: W(n), S0(n), W(-n), S0(-n)
+  const R* S0p;
+  const R* Wm;
+  const R* S0m;
+  double* loss_part; // one partial per block (FUSED)
+  R* S_cube;         // optional full-cube S
+  cpx<R>* rho_save;  // optional half-spectrum rho (written by FUSED / SF, read by BWD)
+  const R* g_cube;   // BWD: dL/dS on the full cube
+};
+
+template <class R>
+hipError_t launch_rows(bool inverse, const RowParams<R>& p, const AxisFft<R>& ax, int ncomp,
+                       hipStream_t st);
+template <class R>
+hipError_t launch_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax, int ncomp,
+                       hipStream_t st);
+
+}  // namespace fresco

@@ -1,0 +1,486 @@
+// LDS-staged mixed-radix Stockham FFT passes for gfx950, and the pointwise
+// mode stage fused into the last forward pass.
+//
+// The uniform part of the nonuniform transforms (Methods: type-1 = spread,
+// FFT, deconvolve; type-2 = pre-deconvolve, FFT, interpolate) runs as one pass
+// per axis over the fine grid, pruned to the |n_a| <= M_a modes that the loss
+// uses:
+//   rows (axis 0)  real <-> half spectrum n_0 in [0, M_0], through a complex FFT
+//                  of half the length (even/odd packing);
+//   columns        complex lines along axis 1 or 2, loading only the nonzero
+//                  modes on the inverse side and storing only the needed ones
+//                  on the forward side.
+// Forward passes use exp(+i n l h) (the paper's rho(k) sign), inverse passes
+// exp(-i n l h).  Every line is transformed inside LDS by a Stockham
+// autosort FFT whose stages read all their inputs into registers before any
+// write, so one LDS buffer suffices.
+#include <cmath>
+
+#include "common.h"
+#include "fft.h"
+
+namespace fresco {
+
+// ----------------------------------------------------------- small DFTs
+template <class R>
+struct Consts;
+template <>
+struct Consts<float> {
+  static constexpr float c3 = 0.86602540378443864676f;  // sin(2 pi / 3)
+  static constexpr float c51 = 0.30901699437494742410f;  // cos(2 pi / 5)
+  static constexpr float c52 = -0.80901699437494742410f; // cos(4 pi / 5)
+  static constexpr float s51 = 0.95105651629515357212f;  // sin(2 pi / 5)
+  static constexpr float s52 = 0.58778525229247312917f;  // sin(4 pi / 5)
+};
+template <>
+struct Consts<double> {
+  static constexpr double c3 = 0.86602540378443864676;
+  static constexpr double c51 = 0.30901699437494742410;
+  static constexpr double c52 = -0.80901699437494742410;
+  static constexpr double s51 = 0.95105651629515357212;
+  static constexpr double s52 = 0.58778525229247312917;
+};
+
+// V[u] = sum_t v[t] exp(s 2 pi i t u / r), s = +1 (forward) or -1 (inverse)
+template <class R, bool INV>
+__device__ __forceinline__ void dft2(cpx<R>* v) {
+  cpx<R> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <class R, bool INV>
+__device__ __forceinline__ void dft3(cpx<R>* v) {
+  cpx<R> t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+  cpx<R> a = {v[0].x - R(0.5) * t1.x, v[0].y - R(0.5) * t1.y};
+  cpx<R> b = cscale(t2, Consts<R>::c3);
+  b = INV ? cmul_mi(b) : cmul_i(b);
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(a, b);
+  v[2] = csub(a, b);
+}
+template <class R, bool INV>
+__device__ __forceinline__ void dft4(cpx<R>* v) {
+  cpx<R> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+  cpx<R> s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+  cpx<R> id13 = INV ? cmul_mi(d13) : cmul_i(d13);
+  v[0] = cadd(s02, s13);
+  v[1] = cadd(d02, id13);
+  v[2] = csub(s02, s13);
+  v[3] = csub(d02, id13);
+}
+template <class R, bool INV>
+__device__ __forceinline__ void dft5(cpx<R>* v) {
+  const R c1 = Consts<R>::c51, c2 = Consts<R>::c52, s1 = Consts<R>::s51, s2 = Consts<R>::s52;
+  cpx<R> b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+  cpx<R> d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+  cpx<R> A = {v[0].x + c1 * b1.x + c2 * b2.x, v[0].y + c1 * b1.y + c2 * b2.y};
+  cpx<R> C = {v[0].x + c2 * b1.x + c1 * b2.x, v[0].y + c2 * b1.y + c1 * b2.y};
+  cpx<R> B = {s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y};
+  cpx<R> D = {s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y};
+  B = INV ? cmul_mi(B) : cmul_i(B);
+  D = INV ? cmul_mi(D) : cmul_i(D);
+  v[0] = cadd(v[0], cadd(b1, b2));
+  v[1] = cadd(A, B);
+  v[4] = csub(A, B);
+  v[2] = cadd(C, D);
+  v[3] = csub(C, D);
+}
+
+// In-LDS Stockham FFT of the lines this thread group serves.
+// buf element (line b, index i) lives at buf[b * ls + i * es]; this thread works
+// on line `b` and on butterflies j = tj, tj + JT, ... of every stage.  All
+// threads of the block must call it (it contains barriers).
+template <class R, int MAXB, bool INV>
+__device__ void lds_fft(cpx<R>* buf, const FftFactors& F, const cpx<R>* __restrict__ tw,
+                        bool active, int b, int ls, int es, int tj, int JT) {
+  const int n = F.n;
+  for (int s = 0; s < F.nfac; ++s) {
+    const int r = F.radix[s];
+    const int nr = n / r;
+    cpx<R> v[MAXB][5];
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+      int j = tj + q * JT;
+      if (active && j < nr) {
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+          if (t < r) v[q][t] = buf[b * ls + (j + t * nr) * es];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+      int j = tj + q * JT;
+      if (active && j < nr) {
+        uint32_t jd = fdiv((uint32_t)j, F.ns[s]);
+        uint32_t k = (uint32_t)j - jd * F.ns[s].d;
+        uint32_t step = k * F.twstep[s];
+#pragma unroll
+        for (int t = 1; t < 5; ++t) {
+          if (t < r) {
+            cpx<R> w = tw[t * step];
+            v[q][t] = INV ? cmulc(v[q][t], w) : cmul(v[q][t], w);
+          }
+        }
+        if (r == 2) dft2<R, INV>(v[q]);
+        else if (r == 3) dft3<R, INV>(v[q]);
+        else if (r == 4) dft4<R, INV>(v[q]);
+        else dft5<R, INV>(v[q]);
+        uint32_t ob = jd * F.ns[s].d * r + k;
+#pragma unroll
+        for (int u = 0; u < 5; ++u)
+          if (u < r) buf[b * ls + (ob + u * F.ns[s].d) * es] = v[q][u];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ row passes
+// Forward rows: real line x[0..nf) -> X[k] = sum_l x_l exp(+2 pi i k l / nf) for
+// k in [0, M0], via z_m = x_2m + i x_2m+1 and a complex FFT of length H = nf/2:
+//   X[k] = (Z[k] + conj Z[H-k]) / 2 + exp(+2 pi i k / nf) (Z[k] - conj Z[H-k]) / (2i).
+template <class R, int MAXB>
+__global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __restrict__ twH,
+                                const cpx<R>* __restrict__ twN) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  const int H = F.n;
+  const int ls = H + 1;
+  const int JT = blockDim.x / p.lines_per_block;
+  const int b = threadIdx.x / JT, tj = threadIdx.x % JT;
+  const long long row = (long long)blockIdx.x * p.lines_per_block + b;
+  const bool active = row < p.nrows;
+  const R* __restrict__ x = p.rin + row * (2LL * H);
+  if (active) {
+    for (int m = tj; m < H; m += JT) {
+      const cpx<R> z = *reinterpret_cast<const cpx<R>*>(x + 2 * m);
+      buf[b * ls + m] = z;
+    }
+  }
+  __syncthreads();
+  lds_fft<R, MAXB, false>(buf, F, twH, active, b, ls, 1, tj, JT);
+  if (active) {
+    cpx<R>* __restrict__ out = p.cout + row * (long long)(p.M0 + 1);
+    for (int k = tj; k <= p.M0; k += JT) {
+      cpx<R> Zk = buf[b * ls + k];
+      cpx<R> Zc = cconj(buf[b * ls + (k == 0 ? 0 : H - k)]);
+      cpx<R> E = cscale(cadd(Zk, Zc), R(0.5));
+      cpx<R> O = cscale(cmul_mi(csub(Zk, Zc)), R(0.5));  // (Zk - Zc) / (2i)
+      out[k] = cadd(E, cmul(twN[k], O));
+    }
+  }
+}
+
+// Inverse rows: half spectrum X[0..M0] (Hermitian extension implied) ->
+// real x_l = sum_n X[n] exp(-2 pi i n l / nf), through
+//   Z[k] = E[k] + i O[k],  E[k] = X[k] + X[k-H],
+//   O[k] = exp(-2 pi i k / nf) (X[k] - X[k-H]),  X[k-H] = conj X[H-k],
+// and x_2m + i x_2m+1 = sum_k Z[k] exp(-2 pi i k m / H).  The imaginary part of
+// X[0] is not part of a real field and is dropped.
+template <class R, int MAXB>
+__global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __restrict__ twH,
+                                const cpx<R>* __restrict__ twN) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  const int H = F.n;
+  const int ls = H + 1;
+  const int JT = blockDim.x / p.lines_per_block;
+  const int b = threadIdx.x / JT, tj = threadIdx.x % JT;
+  const long long row = (long long)blockIdx.x * p.lines_per_block + b;
+  const bool active = row < p.nrows;
+  const int comp = blockIdx.y;
+  const int M0 = p.M0;
+  if (active) {
+    const cpx<R>* __restrict__ X = p.cin[comp] + row * (long long)(M0 + 1);
+    for (int k = tj; k < H; k += JT) {
+      cpx<R> xk = {R(0), R(0)}, xm = {R(0), R(0)};
+      if (k <= M0) xk = X[k];
+      if (k == 0) xk.y = R(0);
+      if (k > 0 && H - k <= M0) xm = cconj(X[H - k]);
+      cpx<R> E = cadd(xk, xm);
+      cpx<R> O = cmulc(csub(xk, xm), twN[k]);  // * exp(-2 pi i k / nf)
+      buf[b * ls + k] = cadd(E, cmul_i(O));
+    }
+  }
+  __syncthreads();
+  lds_fft<R, MAXB, true>(buf, F, twH, active, b, ls, 1, tj, JT);
+  if (active) {
+    R* __restrict__ y = p.rout[comp] + row * (2LL * H);
+    for (int m = tj; m < H; m += JT) *reinterpret_cast<cpx<R>*>(y + 2 * m) = buf[b * ls + m];
+  }
+}
+
+// --------------------------------------------------------- column passes
+// Columns c in [0, ncols): element i of column c sits at
+//   base(c) + i * line,  base(c) = (c / cdiv) * outer + c % cdiv.
+// A block serves `bc` consecutive columns (bc a power of two); LDS holds the
+// block as [i][b] so neighbouring threads touch neighbouring words.
+
+template <class R>
+__device__ __forceinline__ long long col_base(long long c, const FastDiv& cdiv, long long outer) {
+  uint32_t q = fdiv((uint32_t)c, cdiv);
+  return (long long)q * outer + (c - (long long)q * cdiv.d);
+}
+
+// dL/dS symmetrised over +-n, times the deconvolved density, gives the common
+// factor of the d gradient coefficient fields:
+//   q(n) = -2 i G(n) rho(n) prod_a dec_a(n_a) / N,
+//   rho(n) = B(n) prod_a dec_a(n_a),   dec_a = h_a / psihat_a,
+// and the coefficient for component a is k_a q(n) (type-2 input, already
+// divided by psihat and scaled by h^d).
+template <class R>
+__device__ __forceinline__ cpx<R> grad_factor(cpx<R> rho, R G, R dec, R invN) {
+  const R f = R(-2) * G * dec * invN;
+  return {-f * rho.y, f * rho.x};  // f * i * rho
+}
+
+template <class R, int MAXB, int MODE>
+__global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restrict__ tw) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  const int n = F.n;
+  const int bc = p.bc;
+  const int P = 2 * p.M + 1;               // modes along this axis
+  cpx<R>* qbuf = buf + (long long)n * bc;  // [m][b], FUSED / BWD only
+  const int JT = blockDim.x / bc;
+  const int b = threadIdx.x % bc, tj = threadIdx.x / bc;
+  const long long c = (long long)blockIdx.x * bc + b;
+  const bool active = c < p.ncols;
+  const int comp = (MODE == COL_INV) ? blockIdx.y : 0;
+  const long long ib = active ? col_base<R>(c, p.cdiv, p.in_outer) : 0;
+  const long long ob = active ? col_base<R>(c, p.cdiv, p.out_outer) : 0;
+
+  if (MODE == COL_FWD || MODE == COL_FUSED || MODE == COL_SF) {
+    // forward: load the full spatial line, transform with exp(+i ...)
+    if (active) {
+      const cpx<R>* __restrict__ in = p.in[0];
+      for (int i = tj; i < n; i += JT) buf[i * bc + b] = in[ib + (long long)i * p.in_line];
+    }
+    __syncthreads();
+    lds_fft<R, MAXB, false>(buf, F, tw, active, b, 1, bc, tj, JT);
+  }
+  if (MODE == COL_FWD) {
+    if (active) {
+      cpx<R>* __restrict__ out = p.out[0];
+      for (int m = tj; m < P; m += JT) {
+        int i = m - p.M;
+        if (i < 0) i += n;
+        out[ob + (long long)m * p.out_line] = buf[i * bc + b];
+      }
+    }
+    return;
+  }
+  if (MODE == COL_INV) {
+    // inverse: scatter the 2M+1 modes into a zeroed line, transform with exp(-i ...)
+    for (int i = tj; i < n; i += JT) buf[i * bc + b] = cpx<R>{R(0), R(0)};
+    __syncthreads();
+    if (active) {
+      const cpx<R>* __restrict__ in = p.in[comp];
+      for (int m = tj; m < P; m += JT) {
+        int i = m - p.M;
+        if (i < 0) i += n;
+        buf[i * bc + b] = in[ib + (long long)m * p.in_line];
+      }
+    }
+    __syncthreads();
+    lds_fft<R, MAXB, true>(buf, F, tw, active, b, 1, bc, tj, JT);
+    if (active) {
+      cpx<R>* __restrict__ out = p.out[comp];
+      for (int i = tj; i < n; i += JT) out[ob + (long long)i * p.out_line] = buf[i * bc + b];
+    }
+    return;
+  }
+
+  // ---- mode stage (FUSED, SF, BWD): this is the last axis; column c holds the
+  // half-spectrum modes (n_0, n_1[, n_2]) with n_last = m - M.
+  // Column -> leading mode indices: c = n0 + H0 * (n1 + M1) in 3D, c = n0 in 2D.
+  int n0 = 0, n1 = 0;
+  if (active) {
+    if (p.d == 2) {
+      n0 = (int)c;
+    } else {
+      uint32_t q = fdiv((uint32_t)c, p.h0div);
+      n0 = (int)(c - (long long)q * p.h0div.d);
+      n1 = (int)q - p.M1;
+    }
+  }
+  double lsum = 0.0;
+  if (active) {
+    const R dec0 = p.dec[0][n0];
+    const R dec1 = (p.d == 3) ? p.dec[1][n1 < 0 ? -n1 : n1] : R(1);
+    for (int m = tj; m < P; m += JT) {
+      const int nl = m - p.M;
+      const R decl = p.dec[p.d - 1][nl < 0 ? -nl : nl];
+      const R dec = dec0 * dec1 * decl;
+      const long long hidx = c + (long long)p.ncols * m;  // half-spectrum index
+      cpx<R> rho;
+      if (MODE == COL_BWD) {
+        rho = p.rho_save[hidx];
+      } else {
+        int i = nl < 0 ? nl + n : nl;
+        rho = cscale(buf[i * bc + b], dec);
+        if (p.rho_save) p.rho_save[hidx] = rho;
+      }
+      const R S = (rho.x * rho.x + rho.y * rho.y) * p.invN;
+      // full-cube indices of n and -n (C order over n_0..n_{d-1})
+      long long cp, cm;
+      if (p.d == 2) {
+        cp = (long long)(n0 + p.M0) * p.P1 + (nl + p.M1);
+        cm = (long long)(-n0 + p.M0) * p.P1 + (-nl + p.M1);
+      } else {
+        cp = ((long long)(n0 + p.M0) * p.P1 + (n1 + p.M1)) * p.P2 + (nl + p.M2);
+        cm = ((long long)(-n0 + p.M0) * p.P1 + (-n1 + p.M1)) * p.P2 + (-nl + p.M2);
+      }
+      if (MODE == COL_SF || (MODE == COL_FUSED && p.S_cube)) {
+        p.S_cube[cp] = S;
+        p.S_cube[cm] = S;
+      }
+      if (MODE == COL_FUSED || MODE == COL_BWD) {
+        R G;
+        if (MODE == COL_FUSED) {
+          const R wp = p.Wp[hidx], wm = p.Wm[hidx];
+          const R rp = S - p.S0p[hidx], rm = S - p.S0m[hidx];
+          // loss over the full set: n and -n both when n_0 > 0; the n_0 = 0 plane
+          // lists both members of every pair itself
+          lsum += (double)wp * (double)rp * (double)rp;
+          if (n0 > 0) lsum += (double)wm * (double)rm * (double)rm;
+          G = wp * rp + wm * rm;  // = (dL/dS(n) + dL/dS(-n)) / 2
+        } else {
+          G = R(0.5) * (p.g_cube[cp] + p.g_cube[cm]);
+        }
+        qbuf[m * bc + b] = grad_factor(rho, G, dec, p.invN);
+      }
+    }
+  }
+  if (MODE == COL_SF) return;
+  if (MODE == COL_FUSED) {
+    // block reduction of the loss partial (FP64), fixed order
+    __shared__ double red[1024 / 64];
+    double v = lsum;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+      p.loss_part[blockIdx.x] = t;
+    }
+  }
+  // inverse transforms of k_a q(n) for every component a
+  for (int a = 0; a < p.d; ++a) {
+    __syncthreads();
+    for (int i = tj; i < n; i += JT) buf[i * bc + b] = cpx<R>{R(0), R(0)};
+    __syncthreads();
+    if (active) {
+      R kfix = R(0);
+      if (a == 0) kfix = p.kscale[0] * (R)n0;
+      else if (a == 1 && p.d == 3) kfix = p.kscale[1] * (R)n1;
+      const bool along = (a == p.d - 1);
+      for (int m = tj; m < P; m += JT) {
+        const int nl = m - p.M;
+        const R ka = along ? p.kscale[a] * (R)nl : kfix;
+        int i = nl < 0 ? nl + n : nl;
+        buf[i * bc + b] = cscale(qbuf[m * bc + b], ka);
+      }
+    }
+    __syncthreads();
+    lds_fft<R, MAXB, true>(buf, F, tw, active, b, 1, bc, tj, JT);
+    if (active) {
+      cpx<R>* __restrict__ out = p.out[a];
+      for (int i = tj; i < n; i += JT) out[ob + (long long)i * p.out_line] = buf[i * bc + b];
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers
+static int pick_maxb(int need) {
+  if (need <= 1) return 1;
+  if (need <= 2) return 2;
+  if (need <= 4) return 4;
+  if (need <= 8) return 8;
+  return -1;
+}
+
+template <class R>
+hipError_t launch_rows(bool inverse, const RowParams<R>& p, const AxisFft<R>& ax, int ncomp,
+                       hipStream_t st) {
+  const int H = ax.F.n;
+  const int JT = p.threads / p.lines_per_block;
+  const int need = (H + ax.rmin * JT - 1) / (ax.rmin * JT);
+  const int mb = pick_maxb(need);
+  if (mb < 0) return hipErrorInvalidValue;
+  const size_t lds = (size_t)p.lines_per_block * (H + 1) * sizeof(cpx<R>);
+  dim3 grid((unsigned)((p.nrows + p.lines_per_block - 1) / p.lines_per_block), inverse ? ncomp : 1);
+  dim3 block(p.threads);
+#define ROWS_CASE(MB)                                                                          \
+  case MB:                                                                                     \
+    if (inverse) {                                                                             \
+      hipFuncSetAttribute((const void*)rows_c2r_kernel<R, MB>,                                \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
+      rows_c2r_kernel<R, MB><<<grid, block, lds, st>>>(p, ax.F, ax.tw, ax.twN);               \
+    } else {                                                                                   \
+      hipFuncSetAttribute((const void*)rows_r2c_kernel<R, MB>,                                \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
+      rows_r2c_kernel<R, MB><<<grid, block, lds, st>>>(p, ax.F, ax.tw, ax.twN);               \
+    }                                                                                          \
+    break;
+  switch (mb) {
+    ROWS_CASE(1)
+    ROWS_CASE(2)
+    ROWS_CASE(4)
+    ROWS_CASE(8)
+  }
+#undef ROWS_CASE
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax, int ncomp,
+                       hipStream_t st) {
+  const int n = ax.F.n;
+  const int JT = p.threads / p.bc;
+  const int need = (n + ax.rmin * JT - 1) / (ax.rmin * JT);
+  const int mb = pick_maxb(need);
+  if (mb < 0) return hipErrorInvalidValue;
+  size_t lds = (size_t)n * p.bc * sizeof(cpx<R>);
+  if (mode == COL_FUSED || mode == COL_BWD) lds += (size_t)(2 * p.M + 1) * p.bc * sizeof(cpx<R>);
+  dim3 grid((unsigned)((p.ncols + p.bc - 1) / p.bc), mode == COL_INV ? ncomp : 1);
+  dim3 block(p.threads);
+#define COLS_LAUNCH(MB, MD)                                                                     \
+  do {                                                                                          \
+    hipFuncSetAttribute((const void*)cols_kernel<R, MB, MD>,                                   \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
+    cols_kernel<R, MB, MD><<<grid, block, lds, st>>>(p, ax.F, ax.tw);                          \
+  } while (0)
+#define COLS_MODES(MB)                                   \
+  case MB:                                               \
+    switch (mode) {                                      \
+      case COL_FWD: COLS_LAUNCH(MB, COL_FWD); break;     \
+      case COL_INV: COLS_LAUNCH(MB, COL_INV); break;     \
+      case COL_FUSED: COLS_LAUNCH(MB, COL_FUSED); break; \
+      case COL_SF: COLS_LAUNCH(MB, COL_SF); break;       \
+      case COL_BWD: COLS_LAUNCH(MB, COL_BWD); break;     \
+    }                                                    \
+    break;
+  switch (mb) {
+    COLS_MODES(1)
+    COLS_MODES(2)
+    COLS_MODES(4)
+    COLS_MODES(8)
+  }
+#undef COLS_MODES
+#undef COLS_LAUNCH
+  return hipGetLastError();
+}
+
+template hipError_t launch_rows<float>(bool, const RowParams<float>&, const AxisFft<float>&, int,
+                                       hipStream_t);
+template hipError_t launch_rows<double>(bool, const RowParams<double>&, const AxisFft<double>&,
+                                        int, hipStream_t);
+template hipError_t launch_cols<float>(int, const ColParams<float>&, const AxisFft<float>&, int,
+                                       hipStream_t);
+template hipError_t launch_cols<double>(int, const ColParams<double>&, const AxisFft<double>&,
+                                        int, hipStream_t);
+
+}  // namespace fresco

@@ -1,0 +1,226 @@
+"""Python binding of libfresco (ctypes over the C ABI in include/fresco.h).
+
+Argument marshalling only: every step of an evaluation runs in the HIP
+library.  Device buffers are torch tensors on a HIP device (torch is used for
+memory and streams); if the compiled library is missing, importing this module
+raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfresco.so")
+
+F32, F64 = 0, 1
+WEIGHT_ABS, WEIGHT_RELATIVE = 0, 1
+OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENONFINITE, ELINESEARCH = 0, -1, -2, -3, -4, -5, -6
+STAGES = ["bin", "spread", "fft_rows_fwd", "fft_cols_fwd", "modes", "fft_cols_inv",
+          "fft_rows_inv", "interp"]
+
+
+class FrescoError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.fresco_error_string(code).decode() if _lib is not None else str(code)
+        hip = _lib.fresco_last_hip_error() if _lib is not None else 0
+        super().__init__(f"{where}: {msg} (status {code}, last hipError {hip})")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("box", ctypes.c_double * 3),
+        ("kmax", ctypes.c_int32 * 3),
+        ("k_cut", ctypes.c_double),
+        ("s0", ctypes.POINTER(ctypes.c_double)),
+        ("w", ctypes.POINTER(ctypes.c_double)),
+        ("weight_mode", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("upsampfac", ctypes.c_double),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("nf", ctypes.c_int32 * 3),
+        ("kmax", ctypes.c_int32 * 3),
+        ("width", ctypes.c_int32),
+        ("beta", ctypes.c_double),
+        ("tile", ctypes.c_int32 * 3),
+        ("nbins", ctypes.c_int64),
+        ("n_constrained", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2305_15693_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    i = ctypes.c_int
+    lib.fresco_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Problem), vp]
+    lib.fresco_create.restype = i
+    lib.fresco_destroy.argtypes = [vp]
+    lib.fresco_destroy.restype = i
+    lib.fresco_plan_info_get.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.fresco_plan_info_get.restype = i
+    lib.fresco_structure_factor.argtypes = [vp, vp, vp]
+    lib.fresco_structure_factor.restype = i
+    lib.fresco_loss_grad.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.fresco_loss_grad.restype = i
+    lib.fresco_loss_grad_async.argtypes = [vp, vp, vp, vp]
+    lib.fresco_loss_grad_async.restype = i
+    lib.fresco_set_timing.argtypes = [vp, ctypes.c_uint32]
+    lib.fresco_set_timing.restype = i
+    lib.fresco_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64), i]
+    lib.fresco_read_timing.restype = i
+    lib.fresco_error_string.argtypes = [i]
+    lib.fresco_error_string.restype = ctypes.c_char_p
+    lib.fresco_last_hip_error.argtypes = []
+    lib.fresco_last_hip_error.restype = i
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise FrescoError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """One problem (box, mode cube, targets, weights, accuracy) bound to a stream.
+
+    w_cube / s0_cube: host arrays on the mode cube (2M_0+1, ..., 2M_{d-1}+1), C order
+    (see include/fresco.h).  When w_cube is None the weight is 1 on 0 < |n| <= k_cut.
+    """
+
+    def __init__(self, dim: int, n: int, box, kmax, *, w_cube=None, s0_cube=None,
+                 k_cut: float = 0.0, relative: bool = False, tol: float = 1e-6,
+                 dtype: str = "f32", stream=None, device=None):
+        torch = _torch()
+        self.dim = int(dim)
+        self.n = int(n)
+        self.dtype = dtype
+        self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        box = np.broadcast_to(np.asarray(box, dtype=np.float64), (self.dim,))
+        kmax = np.broadcast_to(np.asarray(kmax, dtype=np.int64), (self.dim,))
+        self.box = tuple(float(x) for x in box)
+        self.kmax = tuple(int(x) for x in kmax)
+        self.cube_shape = tuple(2 * m + 1 for m in self.kmax)
+        p = Problem()
+        p.dim = self.dim
+        p.dtype = F32 if dtype == "f32" else F64
+        p.n = self.n
+        for a in range(3):
+            p.box[a] = self.box[a] if a < self.dim else 1.0
+            p.kmax[a] = self.kmax[a] if a < self.dim else 0
+        p.k_cut = float(k_cut)
+        self._w = self._s0 = None
+        if w_cube is not None:
+            self._w = np.ascontiguousarray(np.asarray(w_cube, dtype=np.float64).reshape(self.cube_shape))
+            p.w = self._w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if s0_cube is not None:
+            self._s0 = np.ascontiguousarray(np.asarray(s0_cube, dtype=np.float64).reshape(self.cube_shape))
+            p.s0 = self._s0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.weight_mode = WEIGHT_RELATIVE if relative else WEIGHT_ABS
+        p.tol = float(tol)
+        p.upsampfac = 2.0
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.fresco_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream)),
+                   "fresco_create")
+        self._h = h
+        self._loss = ctypes.c_double(0.0)
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.fresco_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def plan_info(self) -> dict:
+        info = PlanInfo()
+        _check(_lib.fresco_plan_info_get(self._h, ctypes.byref(info)), "fresco_plan_info_get")
+        d = self.dim
+        return dict(dim=info.dim, dtype=info.dtype, n=info.n, nf=list(info.nf)[:d],
+                    kmax=list(info.kmax)[:d], width=info.width, beta=info.beta,
+                    tile=list(info.tile)[:d], nbins=info.nbins,
+                    n_constrained=info.n_constrained, device_bytes=info.device_bytes)
+
+    def set_timing(self, stages):
+        """Bracket the named stages (see STAGES) with HIP events; [] turns it off."""
+        mask = 0
+        for s in stages:
+            mask |= 1 << STAGES.index(s)
+        _check(_lib.fresco_set_timing(self._h, mask), "fresco_set_timing")
+
+    def read_timing(self, reset: bool = True) -> dict:
+        """{stage: (total ms, timed evaluations)} since the last reset."""
+        ms = (ctypes.c_double * len(STAGES))()
+        cnt = (ctypes.c_int64 * len(STAGES))()
+        _check(_lib.fresco_read_timing(self._h, ms, cnt, 1 if reset else 0), "fresco_read_timing")
+        return {STAGES[s]: (ms[s], cnt[s]) for s in range(len(STAGES)) if cnt[s]}
+
+    def _pos(self, pos):
+        if pos.device != self.device or pos.dtype != self.torch_dtype:
+            raise ValueError(f"positions must be {self.torch_dtype} on {self.device}")
+        if tuple(pos.shape) != (self.n, self.dim) or not pos.is_contiguous():
+            raise ValueError(f"positions must be a contiguous [{self.n}][{self.dim}] tensor")
+        return ctypes.c_void_p(pos.data_ptr())
+
+    def structure_factor(self, pos, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.cube_shape, dtype=self.torch_dtype, device=self.device)
+        _check(_lib.fresco_structure_factor(self._h, self._pos(pos), ctypes.c_void_p(out.data_ptr())),
+               "fresco_structure_factor")
+        return out
+
+    def loss_grad(self, pos, grad=None):
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty((self.n, self.dim), dtype=self.torch_dtype, device=self.device)
+        _check(_lib.fresco_loss_grad(self._h, self._pos(pos), ctypes.byref(self._loss),
+                                     ctypes.c_void_p(grad.data_ptr())), "fresco_loss_grad")
+        return float(self._loss.value), grad
+
+    def loss_grad_async(self, pos, loss_dev, grad):
+        _check(_lib.fresco_loss_grad_async(self._h, self._pos(pos), ctypes.c_void_p(loss_dev.data_ptr()),
+                                           ctypes.c_void_p(grad.data_ptr())), "fresco_loss_grad_async")
+        return loss_dev, grad

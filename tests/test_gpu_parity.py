@@ -1,0 +1,206 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 direct-sum oracle.
+
+Error metric (normwise, as the relative error of a field): ||x - x_ref||_2 / ||x_ref||_2
+over all modes of the cube for S, over all N d components for the gradient.
+Bars: FP64 build at tol 1e-12: 1e-11; FP32 build at tol 1e-6: 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2305_15693_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def make_ctx(gpu, d, N, L, M, w, s0, tol, dtype, relative=False):
+    from paper_2305_15693_amd import fresco as F
+    return F.Context(d, N, L, M, w_cube=w, s0_cube=s0, relative=relative, tol=tol, dtype=dtype,
+                     device=gpu)
+
+
+def run_case(gpu, pos_np, L, M, w, s0, tol, dtype, relative=False):
+    import torch
+    N, d = pos_np.shape
+    ctx = make_ctx(gpu, d, N, L, M, w, s0, tol, dtype, relative)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    pos = torch.from_numpy(np.ascontiguousarray(pos_np)).to(device=gpu, dtype=tdt)
+    S = ctx.structure_factor(pos).cpu().numpy().astype(np.float64)
+    loss, grad = ctx.loss_grad(pos)
+    grad = grad.cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    ctx.close()
+    return S, loss, grad
+
+
+def oracle_case(pos_np, L, M, w, s0, relative=False, grad_points=None):
+    d = pos_np.shape[1]
+    pos64 = pos_np.astype(np.float64)
+    Scube = O.structure_factor_cube(pos64, L, M)
+    modes, W, S0 = O.constrained_set(d, M, w, s0, relative)
+    r = O.loss_grad(pos64, L, modes, W, S0, grad_points=grad_points)
+    return Scube, r["loss"], r["grad"]
+
+
+CASES = [
+    # name, d, N, L, M, kcut, tol, dtype, bar
+    ("2d_f64_n1024_m16", 2, 1024, 32.0, 16, 16.0, 1e-12, "f64", 1e-11),
+    ("2d_f32_n20000_m40", 2, 20000, 141.4, 40, 40.0, 1e-6, "f32", 1e-5),
+    ("3d_f32_n30000_m12", 3, 30000, 31.0, 12, 12.0, 1e-6, "f32", 1e-5),
+    ("3d_f64_n3000_m6", 3, 3000, 14.4, 6, 6.0, 1e-12, "f64", 1e-11),
+    ("2d_f32_n5000_m20_tol1e-5", 2, 5000, 70.7, 20, 20.0, 1e-5, "f32", 1e-4),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_stealthy_parity(gpu, case):
+    name, d, N, L, M, kcut, tol, dtype, bar = case
+    seed = 100 + sum(map(ord, name))
+    pos = I.positions(N, d, L, np.float32 if dtype == "f32" else np.float64, seed=seed)
+    w, s0 = I.stealthy_target(d, M, kcut)
+    S, loss, grad = run_case(gpu, pos, L, M, w, s0, tol, dtype)
+    So, lo, go = oracle_case(pos, L, M, w, s0)
+    print(name, "S", rel(S, So), "loss", abs(loss - lo) / abs(lo), "grad", rel(grad, go))
+    assert rel(S, So) < bar
+    assert abs(loss - lo) / abs(lo) < bar
+    assert rel(grad, go) < bar
+
+
+def test_anisotropic_box_and_modes(gpu):
+    # different sides and mode half-widths per dimension, FP64
+    rng = np.random.default_rng(4)
+    N, L, M = 1500, (30.0, 47.0), (9, 14)
+    pos = rng.uniform(0, 1, (N, 2)) * np.asarray(L)
+    shape = (2 * M[0] + 1, 2 * M[1] + 1)
+    w = rng.uniform(0.5, 1.5, shape)
+    w = 0.5 * (w + w[::-1, ::-1])  # symmetric weights
+    s0 = np.zeros(shape)
+    S, loss, grad = run_case(gpu, pos, L, M, w, s0, 1e-12, "f64")
+    So, lo, go = oracle_case(pos, L, M, w, s0)
+    assert rel(S, So) < 1e-11
+    assert abs(loss - lo) / lo < 1e-11
+    assert rel(grad, go) < 1e-11
+
+
+def test_asymmetric_weights_half_plane(gpu):
+    # weights and targets constrained on one half plane only (as in the Starry Night
+    # example of the main text); the loss still sums over the listed modes only
+    rng = np.random.default_rng(8)
+    N, L, M = 2000, 40.0, 12
+    pos = rng.uniform(0, L, (N, 2))
+    n = np.arange(-M, M + 1)
+    w = np.where(n[None, :] < 0, 1.0, 0.0) * np.ones((2 * M + 1, 1))
+    w[M, M] = 0
+    s0 = rng.uniform(0.0, 2.0, w.shape) * (w > 0)
+    S, loss, grad = run_case(gpu, pos, L, M, w, s0, 1e-12, "f64")
+    So, lo, go = oracle_case(pos, L, M, w, s0)
+    assert abs(loss - lo) / lo < 1e-11
+    assert rel(grad, go) < 1e-11
+
+
+def test_power_law_relative_weights(gpu):
+    # power-law target S0 = (|n|/K)^alpha on |n| < K with the relative loss of Eq. loss
+    N = 4096
+    L = 64.0
+    M, K = 20, 20.0
+    pos = I.positions(N, 2, L, np.float32, seed=77)
+    w, s0 = I.power_law_target(2, M, K, 2.0)
+    S, loss, grad = run_case(gpu, pos, L, M, w, s0, 1e-6, "f32", relative=True)
+    So, lo, go = oracle_case(pos, L, M, w, s0, relative=True)
+    assert rel(S, So) < 1e-5
+    assert abs(loss - lo) / lo < 1e-5
+    assert rel(grad, go) < 1e-5
+
+
+def test_wrapping_and_tiny_inputs(gpu):
+    # positions outside [0, L) are wrapped (exp(i k.r) is L-periodic); N = 1 and 2
+    rng = np.random.default_rng(3)
+    L, M = 12.0, 5
+    w, s0 = I.stealthy_target(2, M, 5.0)
+    base = rng.uniform(0, L, (64, 2))
+    shifted = base + L * rng.integers(-5, 6, base.shape)
+    shifted[0] = [0.0, 0.0]
+    shifted[1] = [L, -L]
+    base[0] = [0.0, 0.0]
+    base[1] = [0.0, 0.0]
+    S1, l1, g1 = run_case(gpu, shifted, L, M, w, s0, 1e-12, "f64")
+    So, lo, go = oracle_case(base, L, M, w, s0)
+    assert rel(S1, So) < 1e-11
+    assert abs(l1 - lo) / lo < 1e-11
+    assert rel(g1, go) < 1e-10
+    one = np.array([[3.3, 7.1]])
+    S, loss, grad = run_case(gpu, one, L, M, w, s0, 1e-12, "f64")
+    k = (2 * M + 1) ** 2
+    assert np.allclose(S, 1.0, atol=1e-11)
+    assert np.max(np.abs(grad)) < 1e-9
+    two = np.array([[1.0, 2.0], [5.5, 11.9]])
+    S, loss, grad = run_case(gpu, two, L, M, w, s0, 1e-12, "f64")
+    So, lo, go = oracle_case(two, L, M, w, s0)
+    assert rel(S, So) < 1e-11
+    assert rel(grad, go) < 1e-10
+
+
+def test_nonfinite_position_reported(gpu):
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    ctx = F.Context(2, 10, 5.0, 3, k_cut=3.0, tol=1e-6, dtype="f32", device=gpu)
+    pos = torch.rand(10, 2, device=gpu) * 5
+    pos[3, 1] = float("nan")
+    with pytest.raises(F.FrescoError) as e:
+        ctx.loss_grad(pos)
+    assert e.value.code == F.ENONFINITE
+    ctx.close()
+
+
+def _sparse_weights(d, M, kcut, count, seed):
+    """Weights 1 on `count` random constrained modes (and their mirrors) inside
+    0 < |n| <= kcut, 0 elsewhere: same grids, transforms and launch shapes as the
+    full stealthy problem, but an oracle cost of N * 2 count."""
+    rng = np.random.default_rng(seed)
+    w_full, _ = I.stealthy_target(d, M, kcut)
+    idx = np.flatnonzero(w_full.ravel())
+    pick = rng.choice(idx, count, replace=False)
+    w = np.zeros(w_full.size)
+    w[pick] = 1.0
+    w = w.reshape(w_full.shape)
+    flip = tuple(slice(None, None, -1) for _ in range(d))
+    w = np.maximum(w, w[flip])
+    return w
+
+
+@pytest.mark.parametrize("name", ["2d_n1e6_stealthy300_f32", "3d_n1e7_stealthy60_f32"])
+def test_full_size_sampled(gpu, name):
+    """Full-size workloads with the bench's grids and launch shapes.  The oracle
+    cannot afford all N_K constrained modes, so the weights sit on a random sample
+    of them (with their mirrors); the loss, every point's gradient and S on the
+    sampled modes are then exact direct sums."""
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    cfg = I.WORKLOADS[name]
+    d, N, L, M = cfg["d"], cfg["N"], cfg["L"], cfg["M"]
+    pos = I.positions(N, d, L, np.float32, seed=cfg["seed"])
+    w = _sparse_weights(d, M, cfg["kcut"], 96, seed=cfg["seed"] + 1)
+    ctx = F.Context(d, N, L, M, w_cube=w, tol=cfg["tol"], dtype="f32", device=gpu)
+    tpos = torch.from_numpy(pos).to(gpu)
+    S = ctx.structure_factor(tpos).cpu().numpy().astype(np.float64)
+    loss, grad = ctx.loss_grad(tpos)
+    grad = grad.cpu().numpy().astype(np.float64)
+    ctx.close()
+    modes, W, S0 = O.constrained_set(d, M, w, None)
+    rng = np.random.default_rng(5)
+    gp = rng.choice(N, 4096, replace=False)
+    r = O.loss_grad(pos, L, modes, W, S0, grad_points=gp)
+    cube_idx = tuple((modes[:, a] + M) for a in range(d))
+    print(name, "S", rel(S[cube_idx], r["S"]), "loss", abs(loss - r["loss"]) / r["loss"],
+          "grad", rel(grad[gp], r["grad"]))
+    assert rel(S[cube_idx], r["S"]) < 1e-5
+    assert abs(loss - r["loss"]) / r["loss"] < 1e-5
+    assert rel(grad[gp], r["grad"]) < 1e-5
