@@ -125,15 +125,16 @@ int fresco_loss_grad_async(fresco_ctx* ctx, const void* pos, double* loss_dev, v
 
 /* Stages of one evaluation, for fresco_set_timing / fresco_read_timing. */
 enum fresco_stage {
-  FRESCO_STAGE_BIN = 0,          /* wrap, split, counting sort by tile */
-  FRESCO_STAGE_SPREAD = 1,       /* points -> fine grid (type-1 spreading) */
-  FRESCO_STAGE_FFT_ROWS_FWD = 2, /* real rows -> half spectrum along axis 0 */
-  FRESCO_STAGE_FFT_COLS_FWD = 3, /* forward columns before the last axis (3D) */
-  FRESCO_STAGE_MODES = 4,        /* last forward axis + S, loss, coefficients + first inverse */
-  FRESCO_STAGE_FFT_COLS_INV = 5, /* inverse columns after the first (3D) */
-  FRESCO_STAGE_FFT_ROWS_INV = 6, /* half spectra -> real grids along axis 0 */
-  FRESCO_STAGE_INTERP = 7,       /* grids -> gradient at the points (type-2 interpolation) */
-  FRESCO_STAGE_COUNT = 8
+  FRESCO_STAGE_BIN = 0,          /* wrap, split, counting sort by tile (4 kernels) */
+  FRESCO_STAGE_SPREAD = 1,       /* points -> padded tile sums (type-1 spreading) */
+  FRESCO_STAGE_FOLD = 2,         /* padded tiles -> periodic fine grid */
+  FRESCO_STAGE_FFT_ROWS_FWD = 3, /* real rows -> half spectrum along axis 0 */
+  FRESCO_STAGE_FFT_COLS_FWD = 4, /* forward columns before the last axis (3D) */
+  FRESCO_STAGE_MODES = 5,        /* last forward axis + S, loss, coefficients + first inverse */
+  FRESCO_STAGE_FFT_COLS_INV = 6, /* inverse columns after the first (3D) */
+  FRESCO_STAGE_FFT_ROWS_INV = 7, /* half spectrum -> real field along axis 0 */
+  FRESCO_STAGE_INTERP = 8,       /* field -> gradient at the points (type-2 interpolation) */
+  FRESCO_STAGE_COUNT = 9
 };
 
 /* Diagnostics: bracket the launches of the stages whose bit (1 << stage) is set

@@ -1,20 +1,23 @@
 // C ABI of the FReSCo loss/gradient library: context lifetime, argument
 // checking, buffers and the launch sequence of one evaluation.
 //
-// One evaluation of L_S and its gradient (the NUwU variant of the Methods: one
-// type-1 transform for S, d type-2 transforms for the gradient) is, on the
+// One evaluation of L_S and its gradient (the NUwU variant of the Methods: a
+// type-1 transform for S, a type-2 transform for the gradient) is, on the
 // context's stream:
 //   bin      wrap, split and counting-sort the points by tile        (spread.hip)
-//   spread   tiles -> real fine grid b                               (spread.hip)
+//   spread   tiles -> padded tile sums -> fold into the fine grid b  (spread.hip)
 //   rows     b -> half spectrum along axis 0                         (fft.hip)
 //   cols     remaining axes; the last forward axis is fused with the mode
-//            stage (deconvolve, S, loss, gradient coefficients) and with the
-//            first inverse transforms of the d coefficient fields     (fft.hip)
-//   cols/rows inverse transforms back to d real grids                 (fft.hip)
-//   interp   d grids -> gradient at every point                       (spread.hip)
-//   reduce   FP64 loss partials -> loss                              (here)
+//            stage (deconvolve, S, loss, field coefficients) and with the
+//            first inverse transform                                  (fft.hip)
+//   cols/rows inverse transforms back to one real field              (fft.hip)
+//   interp   derivative of the field at every point = gradient        (spread.hip)
+//   finish   FP64 loss partials -> loss; non-finite flag             (here)
+// The asynchronous entry point replays a captured HIP graph of this sequence
+// when it sees the same buffers again.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -41,20 +44,19 @@ namespace {
 template <class R>
 struct State {
   AxisFft<R> ax[3];  // [0] rows: complex length nf0/2; [1], [2]: columns along axes 1, 2
-  uint32_t* key = nullptr;
-  uint32_t* rank = nullptr;
-  uint32_t* count = nullptr;
-  long long* start = nullptr;
-  Rec<R>* rec = nullptr;
-  int* perm = nullptr;
-  int* flag = nullptr;
+  BinPlan bp;
+  BinBuffers bb;
+  R* tiles = nullptr;  // padded spreading tiles
+  int* fold_off[3] = {nullptr, nullptr, nullptr};
+  int2* fold_ent[3] = {nullptr, nullptr, nullptr};
   R* grid = nullptr;
-  cpx<R>* A1 = nullptr;
-  cpx<R>* A2 = nullptr;
-  cpx<R>* V1[3] = {nullptr, nullptr, nullptr};
-  cpx<R>* V2[3] = {nullptr, nullptr, nullptr};
-  R* v[3] = {nullptr, nullptr, nullptr};
+  cpx<R>* A1 = nullptr;  // half spectrum after the row pass
+  cpx<R>* A2 = nullptr;  // 3D: after the axis-1 pass
+  cpx<R>* V2 = nullptr;  // 3D: field after the inverse axis-2 pass
+  cpx<R>* V1 = nullptr;  // field before the inverse row pass
+  R* v = nullptr;        // real field
   R* dec[3] = {nullptr, nullptr, nullptr};
+  R* deci[3] = {nullptr, nullptr, nullptr};
   R* Wp = nullptr;
   R* S0p = nullptr;
   R* Wm = nullptr;
@@ -62,10 +64,18 @@ struct State {
   cpx<R>* rho = nullptr;
   double* loss_part = nullptr;
   double* loss_dev = nullptr;
+  int* flag_out = nullptr;
   RowParams<R> rows;
-  ColParams<R> col1;   // axis 1 (3D: forward / inverse; 2D: fused)
-  ColParams<R> col2;   // axis 2 (3D: fused)
+  ColParams<R> col1;  // axis 1 (3D: forward / inverse; 2D: fused)
+  ColParams<R> col2;  // axis 2 (3D: fused)
   long long nloss_part = 0;
+};
+
+struct GraphEntry {
+  const void* pos;
+  const void* loss;
+  const void* grad;
+  hipGraphExec_t exec;
 };
 
 }  // namespace
@@ -80,6 +90,8 @@ struct fresco_ctx {
   double* host_loss = nullptr;  // pinned
   int* host_flag = nullptr;     // pinned
   void* state = nullptr;
+  bool use_graphs = true;
+  std::vector<GraphEntry> graphs;
   // per-stage timing (diagnostics): event pairs recorded on the stream
   uint32_t timing_mask = 0;
   std::vector<hipEvent_t> event_pool;
@@ -156,6 +168,14 @@ int upload(fresco_ctx* c, R** dst, const std::vector<double>& src) {
   return FRESCO_OK;
 }
 
+template <class T>
+int upload_raw(fresco_ctx* c, T** dst, const std::vector<T>& src) {
+  int st = dalloc_t(c, dst, src.size());
+  if (st) return st;
+  HIPCHK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FRESCO_OK;
+}
+
 template <class R>
 int setup_axis(fresco_ctx* c, AxisFft<R>* ax, int n, bool rows_twn) {
   if (!plan_factors(n, &ax->F, &ax->rmin)) return FRESCO_ENOTSUP;
@@ -186,7 +206,7 @@ bool shape_rows(int H, int rmin, long long nrows, size_t cs, int* lpb, int* thre
     else if (l > 1) l /= 2;
     else return false;
   }
-  if ((size_t)l * (H + 1) * cs > 160 * 1024) return false;
+  if (((size_t)l + 1) * (H + 1) * cs > 160 * 1024) return false;
   *lpb = l;
   *threads = t;
   return true;
@@ -205,14 +225,16 @@ bool shape_cols(int n, int rmin, long long ncols, size_t cs, int* bc, int* threa
     else if (b > 1) b /= 2;
     else return false;
   }
-  if ((size_t)b * n * cs * 3 / 2 > 160 * 1024) return false;
+  if (((size_t)b * 3 / 2 + 1) * n * cs > 160 * 1024) return false;
   *bc = b;
   *threads = t;
   return true;
 }
 
-__global__ void reduce_loss_kernel(const double* __restrict__ part, long long n,
-                                   double* __restrict__ out) {
+// loss = sum of the block partials (fixed order); hand the non-finite flag to
+// the host-visible slot and clear it for the next evaluation
+__global__ void finish_kernel(const double* __restrict__ part, long long n, double* __restrict__ out,
+                              int* __restrict__ flag, int* __restrict__ flag_out) {
   __shared__ double s[256];
   double v = 0.0;
   for (long long i = threadIdx.x; i < n; i += 256) v += part[i];
@@ -222,11 +244,38 @@ __global__ void reduce_loss_kernel(const double* __restrict__ part, long long n,
     if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = s[0];
+  if (threadIdx.x == 0) {
+    if (out) out[0] = s[0];
+    flag_out[0] = flag[0];
+    flag[0] = 0;
+  }
+}
+
+// per-axis CSR of the padded tiles covering each grid coordinate
+int build_fold_tables(fresco_ctx* c, int a, int** off_d, int2** ent_d) {
+  const Geom& g = c->g;
+  const int nf = g.nf[a], T = g.T[a], E = g.E[a], nt = g.nt[a];
+  std::vector<std::vector<int2>> lists(nf);
+  for (int t = 0; t < nt; ++t)
+    for (int l = 0; l < E; ++l) {
+      const int y = (int)(((long long)t * T + l) % nf);
+      lists[y].push_back(make_int2(t, l));
+    }
+  std::vector<int> off(nf + 1, 0);
+  std::vector<int2> ent;
+  for (int y = 0; y < nf; ++y) {
+    off[y] = (int)ent.size();
+    for (auto& e : lists[y]) ent.push_back(e);
+  }
+  off[nf] = (int)ent.size();
+  int st;
+  if ((st = upload_raw(c, off_d, off))) return st;
+  if ((st = upload_raw(c, ent_d, ent))) return st;
+  return FRESCO_OK;
 }
 
 template <class R>
-int create_state(fresco_ctx* c, const fresco_problem* p) {
+int create_state(fresco_ctx* c) {
   State<R>* S = new (std::nothrow) State<R>();
   if (!S) return FRESCO_ENOMEM;
   c->state = S;
@@ -240,13 +289,43 @@ int create_state(fresco_ctx* c, const fresco_problem* p) {
   if (d == 3 && (st = setup_axis<R>(c, &S->ax[2], g.nf[2], false))) return st;
   // binning
   const long long N = g.N;
-  if ((st = dalloc_t(c, &S->key, N))) return st;
-  if ((st = dalloc_t(c, &S->rank, N))) return st;
-  if ((st = dalloc_t(c, &S->count, g.nbins))) return st;
-  if ((st = dalloc_t(c, &S->start, g.nbins + 1))) return st;
-  if ((st = dalloc_t(c, &S->rec, N))) return st;
-  if ((st = dalloc_t(c, &S->perm, N))) return st;
-  if ((st = dalloc_t(c, &S->flag, 1))) return st;
+  BinPlan& bp = S->bp;
+  bp.privatized = g.nbins <= 16384;
+  if (bp.privatized) {
+    long long nblk = N / 4096;
+    if (nblk < 1) nblk = 1;
+    if (nblk > 1024) nblk = 1024;
+    long long chunk = (N + nblk - 1) / nblk;
+    if (chunk > 65535) {
+      nblk = (N + 65534) / 65535;
+      chunk = (N + nblk - 1) / nblk;
+    }
+    if (nblk > 4096) bp.privatized = false;
+    bp.nblk = (int)nblk;
+    bp.chunk = chunk;
+  }
+  BinBuffers& bb = S->bb;
+  if ((st = dalloc_t(c, &bb.kr, N))) return st;
+  if (bp.privatized) {
+    if ((st = dalloc_t(c, &bb.H, (size_t)g.nbins * bp.nblk))) return st;
+  } else {
+    if ((st = dalloc_t(c, &bb.key, N))) return st;
+  }
+  if ((st = dalloc_t(c, &bb.count, g.nbins))) return st;
+  if ((st = dalloc_t(c, &bb.start, g.nbins + 1))) return st;
+  Rec<R>* rec = nullptr;
+  if ((st = dalloc_t(c, &rec, N))) return st;
+  bb.rec = rec;
+  if ((st = dalloc_t(c, &bb.perm, N))) return st;
+  if ((st = dalloc_t(c, &bb.flag, 1))) return st;
+  if ((st = dalloc_t(c, &S->flag_out, 1))) return st;
+  HIPCHK(hipMemset(bb.flag, 0, sizeof(int)));
+  HIPCHK(hipMemset(S->flag_out, 0, sizeof(int)));
+  // spreading tiles and fold tables
+  const long long tcells = (long long)g.E[0] * g.E[1] * (d == 3 ? g.E[2] : 1);
+  if ((st = dalloc_t(c, &S->tiles, (size_t)(g.nbins * tcells)))) return st;
+  for (int a = 0; a < d; ++a)
+    if ((st = build_fold_tables(c, a, &S->fold_off[a], &S->fold_ent[a]))) return st;
   // grids
   const long long H0 = g.M[0] + 1;
   const long long P1 = 2 * g.M[1] + 1;
@@ -254,17 +333,18 @@ int create_state(fresco_ctx* c, const fresco_problem* p) {
   if ((st = dalloc_t(c, &S->grid, g.ngrid))) return st;
   if ((st = dalloc_t(c, &S->A1, nf2 * nf1 * H0))) return st;
   if (d == 3 && (st = dalloc_t(c, &S->A2, nf2 * P1 * H0))) return st;
+  if (d == 3 && (st = dalloc_t(c, &S->V2, nf2 * P1 * H0))) return st;
+  if ((st = dalloc_t(c, &S->V1, nf2 * nf1 * H0))) return st;
+  if ((st = dalloc_t(c, &S->v, g.ngrid))) return st;
+  // deconvolution factors h_a / psihat_a(n) for both kernels
   for (int a = 0; a < d; ++a) {
-    if ((st = dalloc_t(c, &S->V1[a], nf2 * nf1 * H0))) return st;
-    if (d == 3 && (st = dalloc_t(c, &S->V2[a], nf2 * P1 * H0))) return st;
-    if ((st = dalloc_t(c, &S->v[a], g.ngrid))) return st;
-  }
-  // deconvolution factors dec_a(n) = h_a / psihat_a(n)
-  for (int a = 0; a < d; ++a) {
-    std::vector<double> ph = kernel_fourier(g.M[a], g.w, g.beta, g.nf[a]);
     const double h = 2.0 * M_PI / g.nf[a];
+    std::vector<double> ph = kernel_fourier(g.M[a], g.w, g.beta, g.nf[a], false);
     for (auto& x : ph) x = h / x;
     if ((st = upload<R>(c, &S->dec[a], ph))) return st;
+    std::vector<double> pi = kernel_fourier(g.M[a], g.wi, g.beta_i, g.nf[a], true);
+    for (auto& x : pi) x = h / x;
+    if ((st = upload<R>(c, &S->deci[a], pi))) return st;
   }
   if ((st = dalloc_t(c, &S->rho, g.nhalf))) return st;
   if ((st = dalloc_t(c, &S->loss_dev, 1))) return st;
@@ -286,7 +366,7 @@ int create_state(fresco_ctx* c, const fresco_problem* p) {
     cp.h0div = make_fastdiv((uint32_t)H0);
     for (int a = 0; a < 3; ++a) {
       cp.dec[a] = (a < d) ? S->dec[a] : nullptr;
-      cp.kscale[a] = (a < d) ? (R)(2.0 * M_PI / g.L[a]) : R(0);
+      cp.deci[a] = (a < d) ? S->deci[a] : nullptr;
     }
     cp.invN = (R)(1.0 / (double)g.N);
   };
@@ -298,13 +378,14 @@ int create_state(fresco_ctx* c, const fresco_problem* p) {
     c1.ncols = H0;
     c1.M = g.M[1];
     c1.cdiv = make_fastdiv((uint32_t)H0);
-    c1.in_outer = 0;
     c1.in_line = H0;
-    c1.out_outer = 0;
     c1.out_line = H0;
     if (!shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads))
       return FRESCO_ENOTSUP;
     S->nloss_part = (c1.ncols + c1.bc - 1) / c1.bc;
+    HIPCHK(prepare_cols<R>(COL_FUSED, c1, S->ax[1]));
+    HIPCHK(prepare_cols<R>(COL_SF, c1, S->ax[1]));
+    HIPCHK(prepare_cols<R>(COL_BWD, c1, S->ax[1]));
   } else {
     // axis 1, columns (l2, n0): A1[l2][l1][n0] <-> A2[l2][m1][n0]
     c1.ncols = nf2 * H0;
@@ -312,28 +393,33 @@ int create_state(fresco_ctx* c, const fresco_problem* p) {
     c1.cdiv = make_fastdiv((uint32_t)H0);
     if (!shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads))
       return FRESCO_ENOTSUP;
+    HIPCHK(prepare_cols<R>(COL_FWD, c1, S->ax[1]));
+    HIPCHK(prepare_cols<R>(COL_INV, c1, S->ax[1]));
     ColParams<R>& c2 = S->col2;
     std::memset(&c2, 0, sizeof(c2));
     fill_modes(c2);
     c2.ncols = P1 * H0;
     c2.M = g.M[2];
     c2.cdiv = make_fastdiv((uint32_t)c2.ncols);
-    c2.in_outer = 0;
     c2.in_line = P1 * H0;
-    c2.out_outer = 0;
     c2.out_line = P1 * H0;
     if (!shape_cols(g.nf[2], S->ax[2].rmin, c2.ncols, cs, &c2.bc, &c2.threads))
       return FRESCO_ENOTSUP;
     S->nloss_part = (c2.ncols + c2.bc - 1) / c2.bc;
+    HIPCHK(prepare_cols<R>(COL_FUSED, c2, S->ax[2]));
+    HIPCHK(prepare_cols<R>(COL_SF, c2, S->ax[2]));
+    HIPCHK(prepare_cols<R>(COL_BWD, c2, S->ax[2]));
   }
+  HIPCHK(prepare_rows<R>(rp, S->ax[0]));
+  spread_prepare<R>(g);
+  HIPCHK(hipGetLastError());
   if ((st = dalloc_t(c, &S->loss_part, S->nloss_part))) return st;
   return FRESCO_OK;
 }
 
 // half-spectrum weights from the caller's cubes
 template <class R>
-int upload_weights(fresco_ctx* c, const fresco_problem* p, const std::vector<double>& Wc,
-                   const std::vector<double>& S0c) {
+int upload_weights(fresco_ctx* c, const std::vector<double>& Wc, const std::vector<double>& S0c) {
   State<R>* S = (State<R>*)c->state;
   const Geom& g = c->g;
   const int d = g.d;
@@ -356,8 +442,8 @@ int upload_weights(fresco_ctx* c, const fresco_problem* p, const std::vector<dou
         n1 = (int)(cidx / H0) - g.M[1];
         n2 = (int)m - g.M[2];
       }
-      long long h = cidx + ncols * m;
-      long long ip = cube_index(n0, n1, n2), im = cube_index(-n0, -n1, -n2);
+      const long long h = cidx + ncols * m;
+      const long long ip = cube_index(n0, n1, n2), im = cube_index(-n0, -n1, -n2);
       wp[h] = Wc[ip];
       sp[h] = S0c[ip];
       wm[h] = Wc[im];
@@ -380,15 +466,20 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
   hipStream_t st = c->st;
   {
     StageTimer t(c, FRESCO_STAGE_BIN);
-    launch_fill_u32(S->count, g.nbins, 0u, st);
-    launch_bin_count<R>(g, pos, S->key, S->rank, S->count, S->flag, st);
-    launch_scan_bins(g, S->count, S->start, st);
-    launch_bin_scatter<R>(g, pos, S->key, S->rank, S->start, S->rec, S->perm, st);
+    launch_bin(g, S->bp, pos, sizeof(R) == 8, S->bb, st);
   }
   {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
-    launch_fill<R>(S->grid, g.ngrid, R(0), st);
-    launch_spread<R>(g, S->rec, S->start, S->grid, st);
+    launch_spread<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
+  }
+  {
+    StageTimer t(c, FRESCO_STAGE_FOLD);
+    FoldTables ft;
+    for (int a = 0; a < 3; ++a) {
+      ft.off[a] = S->fold_off[a];
+      ft.ent[a] = S->fold_ent[a];
+    }
+    launch_fold<R>(g, S->tiles, S->grid, ft, st);
   }
   RowParams<R> rp = S->rows;
   rp.rin = S->grid;
@@ -396,6 +487,18 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
   {
     StageTimer t(c, FRESCO_STAGE_FFT_ROWS_FWD);
     HIPCHK(launch_rows<R>(false, rp, S->ax[0], 1, st));
+  }
+  if (g.d == 3) {
+    const long long H0 = g.M[0] + 1, P1 = 2 * g.M[1] + 1;
+    ColParams<R> fw = S->col1;
+    fw.in_outer = (long long)g.nf[1] * H0;
+    fw.in_line = H0;
+    fw.out_outer = P1 * H0;
+    fw.out_line = H0;
+    fw.in[0] = S->A1;
+    fw.out[0] = S->A2;
+    StageTimer t(c, FRESCO_STAGE_FFT_COLS_FWD);
+    HIPCHK(launch_cols<R>(COL_FWD, fw, S->ax[1], 1, st));
   }
   return FRESCO_OK;
 }
@@ -412,7 +515,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, R* S_cube, const R* g_cube, R* gr
   const long long nf1 = g.nf[1];
   ColParams<R> last = (d == 2) ? S->col1 : S->col2;
   last.in[0] = (d == 2) ? S->A1 : S->A2;
-  for (int a = 0; a < d; ++a) last.out[a] = (d == 2) ? S->V1[a] : S->V2[a];
+  last.out[0] = (d == 2) ? S->V1 : S->V2;
   last.Wp = S->Wp;
   last.S0p = S->S0p;
   last.Wm = S->Wm;
@@ -423,7 +526,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, R* S_cube, const R* g_cube, R* gr
   last.g_cube = g_cube;
   {
     StageTimer t(c, FRESCO_STAGE_MODES);
-    HIPCHK(launch_cols<R>(mode, last, S->ax[d - 1], d, st));
+    HIPCHK(launch_cols<R>(mode, last, S->ax[d - 1], 1, st));
   }
   if (d == 3) {
     ColParams<R> inv = S->col1;
@@ -431,59 +534,66 @@ int run_modes_to_grad(fresco_ctx* c, int mode, R* S_cube, const R* g_cube, R* gr
     inv.in_line = H0;
     inv.out_outer = nf1 * H0;
     inv.out_line = H0;
-    for (int a = 0; a < 3; ++a) {
-      inv.in[a] = S->V2[a];
-      inv.out[a] = S->V1[a];
-    }
+    inv.in[0] = S->V2;
+    inv.out[0] = S->V1;
     StageTimer t(c, FRESCO_STAGE_FFT_COLS_INV);
-    HIPCHK(launch_cols<R>(COL_INV, inv, S->ax[1], 3, st));
+    HIPCHK(launch_cols<R>(COL_INV, inv, S->ax[1], 1, st));
   }
   RowParams<R> rp = S->rows;
-  for (int a = 0; a < d; ++a) {
-    rp.cin[a] = S->V1[a];
-    rp.rout[a] = S->v[a];
-  }
+  rp.cin[0] = S->V1;
+  rp.rout[0] = S->v;
   {
     StageTimer t(c, FRESCO_STAGE_FFT_ROWS_INV);
-    HIPCHK(launch_rows<R>(true, rp, S->ax[0], d, st));
+    HIPCHK(launch_rows<R>(true, rp, S->ax[0], 1, st));
   }
-  const R* comps[3] = {S->v[0], S->v[1], d == 3 ? S->v[2] : nullptr};
   {
     StageTimer t(c, FRESCO_STAGE_INTERP);
-    launch_interp<R>(g, S->rec, S->start, S->perm, comps, d, grad, st);
+    launch_interp<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->bb.perm, S->v, grad, st);
   }
-  if (mode == COL_FUSED && loss_dev) {
-    reduce_loss_kernel<<<1, 256, 0, st>>>(S->loss_part, S->nloss_part, loss_dev);
-  }
+  finish_kernel<<<1, 256, 0, st>>>(S->loss_part, mode == COL_FUSED ? S->nloss_part : 0,
+                                   mode == COL_FUSED ? loss_dev : nullptr, S->bb.flag,
+                                   S->flag_out);
   HIPCHK(hipGetLastError());
   return FRESCO_OK;
 }
 
 template <class R>
-int run_forward_3d_axis1(fresco_ctx* c) {
-  State<R>* S = (State<R>*)c->state;
-  const Geom& g = c->g;
-  const long long H0 = g.M[0] + 1, P1 = 2 * g.M[1] + 1;
-  ColParams<R> fw = S->col1;
-  fw.in_outer = (long long)g.nf[1] * H0;
-  fw.in_line = H0;
-  fw.out_outer = P1 * H0;
-  fw.out_line = H0;
-  fw.in[0] = S->A1;
-  fw.out[0] = S->A2;
-  StageTimer t(c, FRESCO_STAGE_FFT_COLS_FWD);
-  HIPCHK(launch_cols<R>(COL_FWD, fw, S->ax[1], 1, c->st));
-  return FRESCO_OK;
+int loss_grad_eager(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
+  int st;
+  if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
+  return run_modes_to_grad<R>(c, COL_FUSED, nullptr, nullptr, (R*)grad, loss_dev);
 }
 
 template <class R>
 int loss_grad_impl(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
-  State<R>* S = (State<R>*)c->state;
-  int st;
-  launch_fill_u32((uint32_t*)S->flag, 1, 0u, c->st);
-  if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
-  if (c->g.d == 3 && (st = run_forward_3d_axis1<R>(c))) return st;
-  return run_modes_to_grad<R>(c, COL_FUSED, nullptr, nullptr, (R*)grad, loss_dev);
+  // the legacy default stream cannot be captured; timed stages run eagerly
+  if (!c->use_graphs || c->timing_mask || c->st == nullptr)
+    return loss_grad_eager<R>(c, pos, loss_dev, grad);
+  for (auto& e : c->graphs)
+    if (e.pos == pos && e.loss == loss_dev && e.grad == grad) {
+      HIPCHK(hipGraphLaunch(e.exec, c->st));
+      return FRESCO_OK;
+    }
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+  int st = loss_grad_eager<R>(c, pos, loss_dev, grad);
+  hipError_t e = hipStreamEndCapture(c->st, &graph);
+  if (st) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  HIPCHK(e);
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(e);
+  if (c->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({pos, loss_dev, grad, exec});
+  HIPCHK(hipGraphLaunch(exec, c->st));
+  return FRESCO_OK;
 }
 
 template <class R>
@@ -491,15 +601,17 @@ int structure_factor_impl(fresco_ctx* c, const void* pos, void* Sout) {
   State<R>* S = (State<R>*)c->state;
   const Geom& g = c->g;
   int st;
-  launch_fill_u32((uint32_t*)S->flag, 1, 0u, c->st);
   if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
-  if (g.d == 3 && (st = run_forward_3d_axis1<R>(c))) return st;
   ColParams<R> last = (g.d == 2) ? S->col1 : S->col2;
   last.in[0] = (g.d == 2) ? S->A1 : S->A2;
   last.S_cube = (R*)Sout;
   last.rho_save = S->rho;
-  StageTimer t(c, FRESCO_STAGE_MODES);
-  HIPCHK(launch_cols<R>(COL_SF, last, S->ax[g.d - 1], 1, c->st));
+  {
+    StageTimer t(c, FRESCO_STAGE_MODES);
+    HIPCHK(launch_cols<R>(COL_SF, last, S->ax[g.d - 1], 1, c->st));
+  }
+  finish_kernel<<<1, 256, 0, c->st>>>(S->loss_part, 0, nullptr, S->bb.flag, S->flag_out);
+  HIPCHK(hipGetLastError());
   return FRESCO_OK;
 }
 
@@ -526,6 +638,7 @@ int fresco_last_hip_error(void) { return g_last_hip; }
 int fresco_destroy(fresco_ctx* c) {
   if (!c) return FRESCO_OK;
   (void)hipStreamSynchronize(c->st);
+  for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->host_loss) (void)hipHostFree(c->host_loss);
   if (c->host_flag) (void)hipHostFree(c->host_flag);
@@ -566,12 +679,16 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
   if (!c) return FRESCO_ENOMEM;
   c->dtype = p->dtype;
   c->st = (hipStream_t)stream;
+  const char* eg = std::getenv("FRESCO_GRAPHS");
+  c->use_graphs = !(eg && eg[0] == '0');
   Geom& g = c->g;
   std::memset(&g, 0, sizeof(g));
   g.d = d;
   g.N = p->n;
   g.w = kernel_width(p->tol);
   g.beta = kernel_beta(g.w);
+  g.wi = g.w + 1;
+  g.beta_i = kernel_beta(g.wi);
   g.nbins = 1;
   g.ngrid = 1;
   g.nhalf = 1;
@@ -582,12 +699,16 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
       g.L[a] = p->box[a];
       g.M[a] = p->kmax[a];
       long long need = 2LL * (2LL * g.M[a] + 1);
-      if (need < 2LL * g.w) need = 2LL * g.w;
-      if (need > (1LL << 26)) { delete c; return FRESCO_ENOTSUP; }
+      if (need < 2LL * g.wi) need = 2LL * g.wi;
+      if (need > (1LL << 26)) {
+        delete c;
+        return FRESCO_ENOTSUP;
+      }
       g.nf[a] = next_smooth_even(need);
       g.T[a] = tdef < g.nf[a] ? tdef : g.nf[a];
       g.nt[a] = (g.nf[a] + g.T[a] - 1) / g.T[a];
       g.E[a] = g.T[a] + g.w - 1;
+      g.Ei[a] = g.T[a] + g.wi;
       g.nbins *= g.nt[a];
       g.ngrid *= g.nf[a];
       g.ncube *= 2LL * g.M[a] + 1;
@@ -599,10 +720,14 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
       g.T[a] = 1;
       g.nt[a] = 1;
       g.E[a] = 1;
+      g.Ei[a] = 1;
     }
   }
-  // row FFT length nf0 / 2 and 32-bit index ranges of the passes
-  if (g.ngrid > (1LL << 31) * 4 || g.nhalf > (1LL << 31)) { delete c; return FRESCO_ENOTSUP; }
+  // 32-bit index ranges of the passes
+  if (g.ngrid > (1LL << 33) || g.nhalf > (1LL << 31) || g.nbins > (1LL << 31)) {
+    delete c;
+    return FRESCO_ENOTSUP;
+  }
 
   // weights and targets on the full cube (FP64, host)
   std::vector<double> Wc(g.ncube, 0.0), S0c(g.ncube, 0.0);
@@ -631,16 +756,19 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
     Wc[i] = W;
     if (W != 0.0) ++ncons;
   }
-  if (bad) { delete c; return FRESCO_EINVAL; }
+  if (bad) {
+    delete c;
+    return FRESCO_EINVAL;
+  }
   c->n_constrained = ncons;
 
   int st;
   if (p->dtype == FRESCO_F32) {
-    st = create_state<float>(c, p);
-    if (!st) st = upload_weights<float>(c, p, Wc, S0c);
+    st = create_state<float>(c);
+    if (!st) st = upload_weights<float>(c, Wc, S0c);
   } else {
-    st = create_state<double>(c, p);
-    if (!st) st = upload_weights<double>(c, p, Wc, S0c);
+    st = create_state<double>(c);
+    if (!st) st = upload_weights<double>(c, Wc, S0c);
   }
   if (!st) {
     hipError_t e = hipHostMalloc((void**)&c->host_loss, sizeof(double));
@@ -721,22 +849,22 @@ int fresco_loss_grad_async(fresco_ctx* c, const void* pos, double* loss_dev, voi
 int fresco_loss_grad(fresco_ctx* c, const void* pos, double* loss, void* grad) {
   if (!c || !pos || !loss || !grad) return FRESCO_EINVAL;
   double* ldev;
-  int* flag;
+  int* fout;
   int st;
   if (c->dtype == FRESCO_F32) {
     State<float>* S = (State<float>*)c->state;
     ldev = S->loss_dev;
-    flag = S->flag;
+    fout = S->flag_out;
     st = loss_grad_impl<float>(c, pos, ldev, grad);
   } else {
     State<double>* S = (State<double>*)c->state;
     ldev = S->loss_dev;
-    flag = S->flag;
+    fout = S->flag_out;
     st = loss_grad_impl<double>(c, pos, ldev, grad);
   }
   if (st) return st;
   HIPCHK(hipMemcpyAsync(c->host_loss, ldev, sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipMemcpyAsync(c->host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(c->host_flag, fout, sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   *loss = *c->host_loss;
   if (*c->host_flag) return FRESCO_ENONFINITE;

@@ -75,11 +75,14 @@ struct Geom {
   double L[3];
   int M[3];       // mode half-widths
   int nf[3];      // fine grid per dimension (nf[a] = 1 beyond d)
-  int w;          // kernel width
-  double beta;    // ES shape parameter
+  int w;          // spreading kernel width
+  double beta;    // ES shape parameter of the spreading kernel
+  int wi;         // interpolation kernel width (w + 1)
+  double beta_i;  // ES shape parameter of the interpolation kernel
   int T[3];       // tile size per dimension (1 beyond d)
   int nt[3];      // tiles per dimension (1 beyond d)
-  int E[3];       // padded tile extent T + w - 1 (1 beyond d)
+  int E[3];       // padded spreading tile extent T + w - 1 (1 beyond d)
+  int Ei[3];      // interpolation field tile extent T + wi (1 beyond d)
   long long nbins;
   long long ngrid;  // prod nf
   long long nhalf;  // (M0+1) * prod_{a>0} (2M_a+1): half mode cube
@@ -96,20 +99,47 @@ struct alignas(4 * sizeof(R)) Rec {
   uint32_t cell;
 };
 
+// Counting sort of the points by tile.
+struct BinPlan {
+  bool privatized;  // block-private LDS histograms (tiles <= 16384) or global atomics
+  int nblk;         // blocks of the histogram pass
+  long long chunk;  // points per histogram block
+};
+struct BinBuffers {
+  uint32_t* kr = nullptr;     // privatized: tile | rank << 16; fallback: rank
+  uint32_t* key = nullptr;    // fallback: tile per point
+  uint32_t* H = nullptr;      // privatized: [tile][block] counts, then offsets
+  uint32_t* count = nullptr;  // points per tile
+  long long* start = nullptr; // tile starts (nbins + 1)
+  void* rec = nullptr;        // Rec<R>[N], sorted
+  int* perm = nullptr;        // sorted position -> original index
+  int* flag = nullptr;        // set when a position is not finite
+};
+
+// For each axis, the padded spreading tiles that cover every grid coordinate:
+// entries ent[a][off[a][y] .. off[a][y+1]) = (tile index, local index).
+struct FoldTables {
+  const int* off[3];
+  const int2* ent[3];
+};
+
 // Launchers exported by the translation units (all enqueue on `st`).
+void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, BinBuffers& b,
+                hipStream_t st);
 template <class R>
-void launch_bin_count(const Geom& g, const R* pos, uint32_t* key, uint32_t* rank,
-                      uint32_t* count, int* flag, hipStream_t st);
-void launch_scan_bins(const Geom& g, const uint32_t* count, long long* start, hipStream_t st);
+size_t spread_lds_bytes(const Geom& g);
 template <class R>
-void launch_bin_scatter(const Geom& g, const R* pos, const uint32_t* key, const uint32_t* rank,
-                        const long long* start, Rec<R>* rec, int* perm, hipStream_t st);
+size_t interp_lds_bytes(const Geom& g);
 template <class R>
-void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* grid,
+void spread_prepare(const Geom& g);
+template <class R>
+void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* tiles,
                    hipStream_t st);
 template <class R>
+void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, hipStream_t st);
+template <class R>
 void launch_interp(const Geom& g, const Rec<R>* rec, const long long* start, const int* perm,
-                   const R* const* comps, int ncomp, R* grad, hipStream_t st);
+                   const R* v, R* grad, hipStream_t st);
 template <class R>
 void launch_fill(R* p, long long n, R v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);

@@ -41,8 +41,8 @@ struct ColParams {
   int M0, M1, M2;
   int P1, P2;        // 2 M_1 + 1, 2 M_2 + 1 (cube indexing)
   FastDiv h0div;     // M0 + 1
-  const R* dec[3];   // h_a / psihat_a(|n_a|), n_a in [0, M_a]
-  R kscale[3];       // 2 pi / L_a
+  const R* dec[3];   // spreading kernel: h_a / psihat_a(|n_a|), n_a in [0, M_a]
+  const R* deci[3];  // interpolation kernel: h_a / psihat_i,a(|n_a|)
   R invN;
   const R* Wp;       // half spectrum [m][c]: W(n), S0(n), W(-n), S0(-n)
   const R* S0p;
@@ -54,6 +54,15 @@ struct ColParams {
   const R* g_cube;   // BWD: dL/dS on the full cube
 };
 
+template <class R>
+size_t rows_lds_bytes(const RowParams<R>& p, const AxisFft<R>& ax);
+template <class R>
+size_t cols_lds_bytes(int mode, const ColParams<R>& p, const AxisFft<R>& ax);
+// one-time kernel attributes for the launch shapes in p
+template <class R>
+hipError_t prepare_rows(const RowParams<R>& p, const AxisFft<R>& ax);
+template <class R>
+hipError_t prepare_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax);
 template <class R>
 hipError_t launch_rows(bool inverse, const RowParams<R>& p, const AxisFft<R>& ax, int ncomp,
                        hipStream_t st);

@@ -136,30 +136,37 @@ __device__ void lds_fft(cpx<R>* buf, const FftFactors& F, const cpx<R>* __restri
   }
 }
 
+// Copy a twiddle table into LDS (all threads; followed by a barrier in caller).
+template <class R>
+__device__ __forceinline__ void load_twiddles(cpx<R>* dst, const cpx<R>* __restrict__ src,
+                                              int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------ row passes
 // Forward rows: real line x[0..nf) -> X[k] = sum_l x_l exp(+2 pi i k l / nf) for
 // k in [0, M0], via z_m = x_2m + i x_2m+1 and a complex FFT of length H = nf/2:
 //   X[k] = (Z[k] + conj Z[H-k]) / 2 + exp(+2 pi i k / nf) (Z[k] - conj Z[H-k]) / (2i).
+// LDS: [twiddles H][lines x (H + 1)].
 template <class R, int MAXB>
 __global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __restrict__ twH,
                                 const cpx<R>* __restrict__ twN) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  extern __shared__ unsigned long long smem_u64[];
+  cpx<R>* tws = reinterpret_cast<cpx<R>*>(smem_u64);
   const int H = F.n;
+  cpx<R>* buf = tws + H;
   const int ls = H + 1;
   const int JT = blockDim.x / p.lines_per_block;
   const int b = threadIdx.x / JT, tj = threadIdx.x % JT;
   const long long row = (long long)blockIdx.x * p.lines_per_block + b;
   const bool active = row < p.nrows;
+  load_twiddles(tws, twH, H);
   const R* __restrict__ x = p.rin + row * (2LL * H);
   if (active) {
-    for (int m = tj; m < H; m += JT) {
-      const cpx<R> z = *reinterpret_cast<const cpx<R>*>(x + 2 * m);
-      buf[b * ls + m] = z;
-    }
+    for (int m = tj; m < H; m += JT) buf[b * ls + m] = *reinterpret_cast<const cpx<R>*>(x + 2 * m);
   }
   __syncthreads();
-  lds_fft<R, MAXB, false>(buf, F, twH, active, b, ls, 1, tj, JT);
+  lds_fft<R, MAXB, false>(buf, F, tws, active, b, ls, 1, tj, JT);
   if (active) {
     cpx<R>* __restrict__ out = p.cout + row * (long long)(p.M0 + 1);
     for (int k = tj; k <= p.M0; k += JT) {
@@ -181,9 +188,10 @@ __global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
 template <class R, int MAXB>
 __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __restrict__ twH,
                                 const cpx<R>* __restrict__ twN) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+  extern __shared__ unsigned long long smem_u64[];
+  cpx<R>* tws = reinterpret_cast<cpx<R>*>(smem_u64);
   const int H = F.n;
+  cpx<R>* buf = tws + H;
   const int ls = H + 1;
   const int JT = blockDim.x / p.lines_per_block;
   const int b = threadIdx.x / JT, tj = threadIdx.x % JT;
@@ -191,6 +199,7 @@ __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   const bool active = row < p.nrows;
   const int comp = blockIdx.y;
   const int M0 = p.M0;
+  load_twiddles(tws, twH, H);
   if (active) {
     const cpx<R>* __restrict__ X = p.cin[comp] + row * (long long)(M0 + 1);
     for (int k = tj; k < H; k += JT) {
@@ -204,7 +213,7 @@ __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
     }
   }
   __syncthreads();
-  lds_fft<R, MAXB, true>(buf, F, twH, active, b, ls, 1, tj, JT);
+  lds_fft<R, MAXB, true>(buf, F, tws, active, b, ls, 1, tj, JT);
   if (active) {
     R* __restrict__ y = p.rout[comp] + row * (2LL * H);
     for (int m = tj; m < H; m += JT) *reinterpret_cast<cpx<R>*>(y + 2 * m) = buf[b * ls + m];
@@ -216,6 +225,7 @@ __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
 //   base(c) + i * line,  base(c) = (c / cdiv) * outer + c % cdiv.
 // A block serves `bc` consecutive columns (bc a power of two); LDS holds the
 // block as [i][b] so neighbouring threads touch neighbouring words.
+// LDS: [twiddles n][n x bc data][(2M+1) x bc mode factors (FUSED, BWD)].
 
 template <class R>
 __device__ __forceinline__ long long col_base(long long c, const FastDiv& cdiv, long long outer) {
@@ -223,26 +233,15 @@ __device__ __forceinline__ long long col_base(long long c, const FastDiv& cdiv, 
   return (long long)q * outer + (c - (long long)q * cdiv.d);
 }
 
-// dL/dS symmetrised over +-n, times the deconvolved density, gives the common
-// factor of the d gradient coefficient fields:
-//   q(n) = -2 i G(n) rho(n) prod_a dec_a(n_a) / N,
-//   rho(n) = B(n) prod_a dec_a(n_a),   dec_a = h_a / psihat_a,
-// and the coefficient for component a is k_a q(n) (type-2 input, already
-// divided by psihat and scaled by h^d).
-template <class R>
-__device__ __forceinline__ cpx<R> grad_factor(cpx<R> rho, R G, R dec, R invN) {
-  const R f = R(-2) * G * dec * invN;
-  return {-f * rho.y, f * rho.x};  // f * i * rho
-}
-
 template <class R, int MAXB, int MODE>
-__global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restrict__ tw) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<R>* buf = reinterpret_cast<cpx<R>*>(smem_raw);
+__global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restrict__ twg) {
+  extern __shared__ unsigned long long smem_u64[];
   const int n = F.n;
   const int bc = p.bc;
-  const int P = 2 * p.M + 1;               // modes along this axis
+  cpx<R>* tws = reinterpret_cast<cpx<R>*>(smem_u64);
+  cpx<R>* buf = tws + n;
   cpx<R>* qbuf = buf + (long long)n * bc;  // [m][b], FUSED / BWD only
+  const int P = 2 * p.M + 1;               // modes along this axis
   const int JT = blockDim.x / bc;
   const int b = threadIdx.x % bc, tj = threadIdx.x / bc;
   const long long c = (long long)blockIdx.x * bc + b;
@@ -250,6 +249,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
   const int comp = (MODE == COL_INV) ? blockIdx.y : 0;
   const long long ib = active ? col_base<R>(c, p.cdiv, p.in_outer) : 0;
   const long long ob = active ? col_base<R>(c, p.cdiv, p.out_outer) : 0;
+  load_twiddles(tws, twg, n);
 
   if (MODE == COL_FWD || MODE == COL_FUSED || MODE == COL_SF) {
     // forward: load the full spatial line, transform with exp(+i ...)
@@ -258,7 +258,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       for (int i = tj; i < n; i += JT) buf[i * bc + b] = in[ib + (long long)i * p.in_line];
     }
     __syncthreads();
-    lds_fft<R, MAXB, false>(buf, F, tw, active, b, 1, bc, tj, JT);
+    lds_fft<R, MAXB, false>(buf, F, tws, active, b, 1, bc, tj, JT);
   }
   if (MODE == COL_FWD) {
     if (active) {
@@ -284,7 +284,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       }
     }
     __syncthreads();
-    lds_fft<R, MAXB, true>(buf, F, tw, active, b, 1, bc, tj, JT);
+    lds_fft<R, MAXB, true>(buf, F, tws, active, b, 1, bc, tj, JT);
     if (active) {
       cpx<R>* __restrict__ out = p.out[comp];
       for (int i = tj; i < n; i += JT) out[ob + (long long)i * p.out_line] = buf[i * bc + b];
@@ -307,18 +307,19 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
   }
   double lsum = 0.0;
   if (active) {
-    const R dec0 = p.dec[0][n0];
-    const R dec1 = (p.d == 3) ? p.dec[1][n1 < 0 ? -n1 : n1] : R(1);
+    const int a1 = n1 < 0 ? -n1 : n1;
+    const R dlead = p.dec[0][n0] * ((p.d == 3) ? p.dec[1][a1] : R(1));
+    const R ilead = p.deci[0][n0] * ((p.d == 3) ? p.deci[1][a1] : R(1));
     for (int m = tj; m < P; m += JT) {
       const int nl = m - p.M;
-      const R decl = p.dec[p.d - 1][nl < 0 ? -nl : nl];
-      const R dec = dec0 * dec1 * decl;
+      const int al = nl < 0 ? -nl : nl;
+      const R dec = dlead * p.dec[p.d - 1][al];
       const long long hidx = c + (long long)p.ncols * m;  // half-spectrum index
       cpx<R> rho;
       if (MODE == COL_BWD) {
         rho = p.rho_save[hidx];
       } else {
-        int i = nl < 0 ? nl + n : nl;
+        const int i = nl < 0 ? nl + n : nl;
         rho = cscale(buf[i * bc + b], dec);
         if (p.rho_save) p.rho_save[hidx] = rho;
       }
@@ -337,6 +338,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
         p.S_cube[cm] = S;
       }
       if (MODE == COL_FUSED || MODE == COL_BWD) {
+        // G: dL/dS symmetrised over the pair (n, -n)
         R G;
         if (MODE == COL_FUSED) {
           const R wp = p.Wp[hidx], wm = p.Wm[hidx];
@@ -345,11 +347,14 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
           // lists both members of every pair itself
           lsum += (double)wp * (double)rp * (double)rp;
           if (n0 > 0) lsum += (double)wm * (double)rm * (double)rm;
-          G = wp * rp + wm * rm;  // = (dL/dS(n) + dL/dS(-n)) / 2
+          G = wp * rp + wm * rm;
         } else {
           G = R(0.5) * (p.g_cube[cp] + p.g_cube[cm]);
         }
-        qbuf[m * bc + b] = grad_factor(rho, G, dec, p.invN);
+        // type-2 input of the field whose derivative is the gradient:
+        // C0 = 2 G rho / N, divided by psihat_i and scaled by h^d
+        const R f = R(2) * G * p.invN * ilead * p.deci[p.d - 1][al];
+        qbuf[m * bc + b] = cscale(rho, f);
       }
     }
   }
@@ -367,29 +372,22 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       p.loss_part[blockIdx.x] = t;
     }
   }
-  // inverse transforms of k_a q(n) for every component a
-  for (int a = 0; a < p.d; ++a) {
-    __syncthreads();
-    for (int i = tj; i < n; i += JT) buf[i * bc + b] = cpx<R>{R(0), R(0)};
-    __syncthreads();
-    if (active) {
-      R kfix = R(0);
-      if (a == 0) kfix = p.kscale[0] * (R)n0;
-      else if (a == 1 && p.d == 3) kfix = p.kscale[1] * (R)n1;
-      const bool along = (a == p.d - 1);
-      for (int m = tj; m < P; m += JT) {
-        const int nl = m - p.M;
-        const R ka = along ? p.kscale[a] * (R)nl : kfix;
-        int i = nl < 0 ? nl + n : nl;
-        buf[i * bc + b] = cscale(qbuf[m * bc + b], ka);
-      }
+  // inverse transform of the field coefficients along this axis
+  __syncthreads();
+  for (int i = tj; i < n; i += JT) buf[i * bc + b] = cpx<R>{R(0), R(0)};
+  __syncthreads();
+  if (active) {
+    for (int m = tj; m < P; m += JT) {
+      int i = m - p.M;
+      if (i < 0) i += n;
+      buf[i * bc + b] = qbuf[m * bc + b];
     }
-    __syncthreads();
-    lds_fft<R, MAXB, true>(buf, F, tw, active, b, 1, bc, tj, JT);
-    if (active) {
-      cpx<R>* __restrict__ out = p.out[a];
-      for (int i = tj; i < n; i += JT) out[ob + (long long)i * p.out_line] = buf[i * bc + b];
-    }
+  }
+  __syncthreads();
+  lds_fft<R, MAXB, true>(buf, F, tws, active, b, 1, bc, tj, JT);
+  if (active) {
+    cpx<R>* __restrict__ out = p.out[0];
+    for (int i = tj; i < n; i += JT) out[ob + (long long)i * p.out_line] = buf[i * bc + b];
   }
 }
 
@@ -403,84 +401,132 @@ static int pick_maxb(int need) {
 }
 
 template <class R>
+size_t rows_lds_bytes(const RowParams<R>& p, const AxisFft<R>& ax) {
+  const int H = ax.F.n;
+  return ((size_t)H + (size_t)p.lines_per_block * (H + 1)) * sizeof(cpx<R>);
+}
+template <class R>
+size_t cols_lds_bytes(int mode, const ColParams<R>& p, const AxisFft<R>& ax) {
+  const int n = ax.F.n;
+  size_t e = (size_t)n + (size_t)n * p.bc;
+  if (mode == COL_FUSED || mode == COL_BWD) e += (size_t)(2 * p.M + 1) * p.bc;
+  return e * sizeof(cpx<R>);
+}
+
+template <class R>
+static int rows_maxb(const RowParams<R>& p, const AxisFft<R>& ax) {
+  const int JT = p.threads / p.lines_per_block;
+  return pick_maxb((ax.F.n + ax.rmin * JT - 1) / (ax.rmin * JT));
+}
+template <class R>
+static int cols_maxb(const ColParams<R>& p, const AxisFft<R>& ax) {
+  const int JT = p.threads / p.bc;
+  return pick_maxb((ax.F.n + ax.rmin * JT - 1) / (ax.rmin * JT));
+}
+
+#define FRESCO_MB_SWITCH(MB_, CALL) \
+  switch (MB_) {                    \
+    case 1: CALL(1); break;         \
+    case 2: CALL(2); break;         \
+    case 4: CALL(4); break;         \
+    case 8: CALL(8); break;         \
+  }
+
+template <class R>
+hipError_t prepare_rows(const RowParams<R>& p, const AxisFft<R>& ax) {
+  const int mb = rows_maxb(p, ax);
+  if (mb < 0) return hipErrorInvalidValue;
+  const int lds = (int)rows_lds_bytes(p, ax);
+#define PREP(MB)                                                                      \
+  do {                                                                                \
+    hipFuncSetAttribute((const void*)rows_c2r_kernel<R, MB>,                         \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);             \
+    hipFuncSetAttribute((const void*)rows_r2c_kernel<R, MB>,                         \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);             \
+  } while (0)
+  FRESCO_MB_SWITCH(mb, PREP)
+#undef PREP
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t prepare_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax) {
+  const int mb = cols_maxb(p, ax);
+  if (mb < 0) return hipErrorInvalidValue;
+  const int lds = (int)cols_lds_bytes(mode, p, ax);
+#define PREP1(MB, MD)                                                                  \
+  hipFuncSetAttribute((const void*)cols_kernel<R, MB, MD>,                            \
+                      hipFuncAttributeMaxDynamicSharedMemorySize, lds)
+#define PREP(MB)                                        \
+  do {                                                  \
+    switch (mode) {                                     \
+      case COL_FWD: PREP1(MB, COL_FWD); break;          \
+      case COL_INV: PREP1(MB, COL_INV); break;          \
+      case COL_FUSED: PREP1(MB, COL_FUSED); break;      \
+      case COL_SF: PREP1(MB, COL_SF); break;            \
+      case COL_BWD: PREP1(MB, COL_BWD); break;          \
+    }                                                   \
+  } while (0)
+  FRESCO_MB_SWITCH(mb, PREP)
+#undef PREP
+#undef PREP1
+  return hipGetLastError();
+}
+
+template <class R>
 hipError_t launch_rows(bool inverse, const RowParams<R>& p, const AxisFft<R>& ax, int ncomp,
                        hipStream_t st) {
-  const int H = ax.F.n;
-  const int JT = p.threads / p.lines_per_block;
-  const int need = (H + ax.rmin * JT - 1) / (ax.rmin * JT);
-  const int mb = pick_maxb(need);
+  const int mb = rows_maxb(p, ax);
   if (mb < 0) return hipErrorInvalidValue;
-  const size_t lds = (size_t)p.lines_per_block * (H + 1) * sizeof(cpx<R>);
+  const size_t lds = rows_lds_bytes(p, ax);
   dim3 grid((unsigned)((p.nrows + p.lines_per_block - 1) / p.lines_per_block), inverse ? ncomp : 1);
   dim3 block(p.threads);
-#define ROWS_CASE(MB)                                                                          \
-  case MB:                                                                                     \
-    if (inverse) {                                                                             \
-      hipFuncSetAttribute((const void*)rows_c2r_kernel<R, MB>,                                \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
-      rows_c2r_kernel<R, MB><<<grid, block, lds, st>>>(p, ax.F, ax.tw, ax.twN);               \
-    } else {                                                                                   \
-      hipFuncSetAttribute((const void*)rows_r2c_kernel<R, MB>,                                \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);               \
-      rows_r2c_kernel<R, MB><<<grid, block, lds, st>>>(p, ax.F, ax.tw, ax.twN);               \
-    }                                                                                          \
-    break;
-  switch (mb) {
-    ROWS_CASE(1)
-    ROWS_CASE(2)
-    ROWS_CASE(4)
-    ROWS_CASE(8)
-  }
-#undef ROWS_CASE
+#define ROWS(MB)                                                                   \
+  do {                                                                             \
+    if (inverse)                                                                   \
+      rows_c2r_kernel<R, MB><<<grid, block, lds, st>>>(p, ax.F, ax.tw, ax.twN);   \
+    else                                                                           \
+      rows_r2c_kernel<R, MB><<<grid, block, lds, st>>>(p, ax.F, ax.tw, ax.twN);   \
+  } while (0)
+  FRESCO_MB_SWITCH(mb, ROWS)
+#undef ROWS
   return hipGetLastError();
 }
 
 template <class R>
 hipError_t launch_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax, int ncomp,
                        hipStream_t st) {
-  const int n = ax.F.n;
-  const int JT = p.threads / p.bc;
-  const int need = (n + ax.rmin * JT - 1) / (ax.rmin * JT);
-  const int mb = pick_maxb(need);
+  const int mb = cols_maxb(p, ax);
   if (mb < 0) return hipErrorInvalidValue;
-  size_t lds = (size_t)n * p.bc * sizeof(cpx<R>);
-  if (mode == COL_FUSED || mode == COL_BWD) lds += (size_t)(2 * p.M + 1) * p.bc * sizeof(cpx<R>);
+  const size_t lds = cols_lds_bytes(mode, p, ax);
   dim3 grid((unsigned)((p.ncols + p.bc - 1) / p.bc), mode == COL_INV ? ncomp : 1);
   dim3 block(p.threads);
-#define COLS_LAUNCH(MB, MD)                                                                     \
-  do {                                                                                          \
-    hipFuncSetAttribute((const void*)cols_kernel<R, MB, MD>,                                   \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
-    cols_kernel<R, MB, MD><<<grid, block, lds, st>>>(p, ax.F, ax.tw);                          \
+#define COLS1(MB, MD) cols_kernel<R, MB, MD><<<grid, block, lds, st>>>(p, ax.F, ax.tw)
+#define COLS(MB)                                        \
+  do {                                                  \
+    switch (mode) {                                     \
+      case COL_FWD: COLS1(MB, COL_FWD); break;          \
+      case COL_INV: COLS1(MB, COL_INV); break;          \
+      case COL_FUSED: COLS1(MB, COL_FUSED); break;      \
+      case COL_SF: COLS1(MB, COL_SF); break;            \
+      case COL_BWD: COLS1(MB, COL_BWD); break;          \
+    }                                                   \
   } while (0)
-#define COLS_MODES(MB)                                   \
-  case MB:                                               \
-    switch (mode) {                                      \
-      case COL_FWD: COLS_LAUNCH(MB, COL_FWD); break;     \
-      case COL_INV: COLS_LAUNCH(MB, COL_INV); break;     \
-      case COL_FUSED: COLS_LAUNCH(MB, COL_FUSED); break; \
-      case COL_SF: COLS_LAUNCH(MB, COL_SF); break;       \
-      case COL_BWD: COLS_LAUNCH(MB, COL_BWD); break;     \
-    }                                                    \
-    break;
-  switch (mb) {
-    COLS_MODES(1)
-    COLS_MODES(2)
-    COLS_MODES(4)
-    COLS_MODES(8)
-  }
-#undef COLS_MODES
-#undef COLS_LAUNCH
+  FRESCO_MB_SWITCH(mb, COLS)
+#undef COLS
+#undef COLS1
   return hipGetLastError();
 }
 
-template hipError_t launch_rows<float>(bool, const RowParams<float>&, const AxisFft<float>&, int,
-                                       hipStream_t);
-template hipError_t launch_rows<double>(bool, const RowParams<double>&, const AxisFft<double>&,
-                                        int, hipStream_t);
-template hipError_t launch_cols<float>(int, const ColParams<float>&, const AxisFft<float>&, int,
-                                       hipStream_t);
-template hipError_t launch_cols<double>(int, const ColParams<double>&, const AxisFft<double>&,
-                                        int, hipStream_t);
+#define FRESCO_FFT_INST(R)                                                                        \
+  template size_t rows_lds_bytes<R>(const RowParams<R>&, const AxisFft<R>&);                      \
+  template size_t cols_lds_bytes<R>(int, const ColParams<R>&, const AxisFft<R>&);                 \
+  template hipError_t prepare_rows<R>(const RowParams<R>&, const AxisFft<R>&);                    \
+  template hipError_t prepare_cols<R>(int, const ColParams<R>&, const AxisFft<R>&);               \
+  template hipError_t launch_rows<R>(bool, const RowParams<R>&, const AxisFft<R>&, int,           \
+                                     hipStream_t);                                                \
+  template hipError_t launch_cols<R>(int, const ColParams<R>&, const AxisFft<R>&, int, hipStream_t);
+FRESCO_FFT_INST(float)
+FRESCO_FFT_INST(double)
 
 }  // namespace fresco

@@ -60,9 +60,11 @@ static void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w
   }
 }
 
-std::vector<double> kernel_fourier(int nmax, int w, double beta, int nf) {
+std::vector<double> kernel_fourier(int nmax, int w, double beta, int nf, bool cosh_form) {
   // z = sin(theta), theta in [-pi/2, pi/2]:
-  //   int phi(z) cos(c z) dz = int exp(beta (cos theta - 1)) cos(c sin theta) cos theta dtheta
+  //   int phi(z) cos(c z) dz = int phi(sin theta) cos(c sin theta) cos theta dtheta
+  // with phi(sin theta) = exp(beta (cos theta - 1))            (spreading kernel)
+  //   or cosh(beta cos theta) / cosh(beta)                     (interpolation kernel)
   const int q = 2 * w + 60;
   std::vector<double> x, wt;
   gauss_legendre(q, x, wt);
@@ -73,7 +75,11 @@ std::vector<double> kernel_fourier(int nmax, int w, double beta, int nf) {
   for (int i = 0; i < q; ++i) {
     th[i] = 0.5 * M_PI * x[i];
     sn[i] = std::sin(th[i]);
-    f[i] = std::exp(beta * (std::cos(th[i]) - 1.0)) * std::cos(th[i]) * wt[i] * 0.5 * M_PI;
+    const double ct = std::cos(th[i]);
+    const double ph = cosh_form ? std::exp(beta * (ct - 1.0)) * (1.0 + std::exp(-2.0 * beta * ct)) /
+                                      (1.0 + std::exp(-2.0 * beta))
+                                : std::exp(beta * (ct - 1.0));
+    f[i] = ph * ct * wt[i] * 0.5 * M_PI;
   }
   for (int n = 0; n <= nmax; ++n) {
     double s = 0.0;

@@ -19,8 +19,9 @@ double kernel_beta(int w);
 
 // psihat(n) = alpha * int_{-1}^{1} phi(z) cos(n alpha z) dz with alpha = w h / 2,
 // h = 2 pi / nf, for n = 0..nmax (FP64 Gauss-Legendre in z = sin(theta), where
-// the integrand is smooth).
-std::vector<double> kernel_fourier(int nmax, int w, double beta, int nf);
+// the integrand is smooth).  phi is the exponential of semicircle, or with
+// cosh_form its even-in-sqrt(1 - z^2) variant cosh(beta sqrt(1 - z^2)) / cosh(beta).
+std::vector<double> kernel_fourier(int nmax, int w, double beta, int nf, bool cosh_form);
 
 // radix plan of a complex FFT of length n (radices 2, 3, 4, 5); false if n has
 // another prime factor or needs too many stages

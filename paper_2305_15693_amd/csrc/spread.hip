@@ -2,28 +2,41 @@
 // last step) for gfx950.
 //
 // Kernel: the exponential of semicircle  phi(z) = exp(beta (sqrt(1 - z^2) - 1))
-// on |z| <= 1 (Barnett, Magland & af Klinteberg, the kernel of the FINUFFT
-// library the paper's Methods use), scaled so that its support spans w grid
-// cells: psi(x - l h) = phi((u - l) * 2 / w) with u = x / h the coordinate in grid
-// units.
+// on |z| <= 1 (the kernel of the FINUFFT library used in the paper's Methods),
+// scaled so that its support spans w grid cells: psi(x - l h) = phi((l - u) 2 / w)
+// with u = x / h the coordinate in grid units.
 //
 // Binning.  Every point is mapped, in FP64, to u_a = r_a nf_a / L_a wrapped into
 // [0, nf_a), the first index of its footprint l0_a = ceil(u_a - w/2) and the
 // offset t_a = l0_a - u_a in [-w/2, -w/2 + 1) (kept in the working precision, so
 // that large grids lose no phase accuracy).  Points are counting-sorted by the
-// tile holding l0.
+// tile holding l0 with block-private LDS histograms (no global atomics):
+//   hist     each block counts its chunk of points per tile in LDS; the LDS
+//            atomic's return value is the point's rank inside (tile, block);
+//   rowscan  per tile, exclusive scan over the blocks -> offset of each block;
+//   scan     exclusive scan over tiles -> tile starts;
+//   scatter  sorted record written at start[tile] + offset[tile][block] + rank.
 //
 // Spreading.  One workgroup per tile accumulates its points into an LDS copy of
-// the tile padded by w - 1 cells.  Accumulation is in fixed point with integer
-// LDS atomics (gfx950 executes integer LDS atomics far faster than float ones,
-// and the integer sum is exact and order independent); the scale is a power of
-// two chosen per tile from its point count so that no cell can overflow.  The
-// padded tile is then added into the periodic fine grid with float atomics.
+// the tile padded by w - 1 cells, in fixed point with integer LDS atomics
+// (gfx950 executes integer LDS atomics far faster than float ones; the integer
+// sum is exact and independent of order).  The scale is a power of two chosen
+// per tile from its point count so that no cell can exceed 2^31; two adjacent
+// 32-bit cells therefore add as one 64-bit word without carries between them,
+// which halves the atomic count.  The padded tile is stored as is; a fold
+// kernel then sums, for every grid cell, the padded tiles that cover it
+// (deterministic, no float atomics).
 //
-// Interpolation.  One workgroup per tile stages the padded tile of every
-// gradient component grid in LDS and evaluates sum_l v(l) psi(x_j - l h) for its
-// points, writing the result at the point's original index.
+// Interpolation.  The gradient is the derivative of one interpolated field:
+// dL/dr_a = d/dr_a Re sum_k C0(k) exp(-i k.r) with C0 = 2 G rho / N, evaluated
+// with the derivative of the interpolation kernel,
+//   d psi / d r_a = phi_c'(z_a) (-2/w_i) (nf_a / L_a) prod_{b != a} phi_c(z_b),
+// at width w_i = w + 1 (one more cell keeps the derivative interpolation as
+// accurate as the plain one) with the cosh form phi_c of the kernel (finite
+// derivative at the support edge).  One workgroup per tile stages its padded
+// field tile in LDS.
 #include <cmath>
+#include <utility>
 
 #include "common.h"
 
@@ -33,6 +46,34 @@ template <class R>
 __device__ __forceinline__ R es_kernel(R z, R beta) {
   R s = (R(1) - z) * (R(1) + z);
   return s >= R(0) ? exp(beta * (sqrt(s) - R(1))) : R(0);
+}
+
+// Interpolation kernel and its derivative: phi_c(z) = cosh(beta s) / cosh(beta),
+// s = sqrt(1 - z^2).  It is the exponential of semicircle up to terms of order
+// exp(-2 beta s - beta), but even in s, so phi_c' = -beta z sinh(beta s) / (s cosh beta)
+// stays finite at |z| = 1 (the plain exponential's derivative diverges there,
+// which would make the gradient of points sitting on a grid node inaccurate).
+template <class R>
+__device__ __forceinline__ void cosh_kernel_d(R z, R beta, R inv_cosh_beta, R* f, R* df) {
+  const R s2 = (R(1) - z) * (R(1) + z);
+  if (!(s2 >= R(0))) {
+    *f = R(0);
+    *df = R(0);
+    return;
+  }
+  const R s = sqrt(s2);
+  const R bs = beta * s;
+  const R e = exp(bs);
+  const R ei = R(1) / e;
+  R shs;  // sinh(beta s) / s
+  if (bs > R(1e-2)) {
+    shs = R(0.5) * (e - ei) / s;
+  } else {
+    const R b2 = bs * bs;
+    shs = beta * (R(1) + b2 * (R(1) / R(6) + b2 * (R(1) / R(120))));
+  }
+  *f = R(0.5) * (e + ei) * inv_cosh_beta;
+  *df = -beta * z * shs * inv_cosh_beta;
 }
 
 // ------------------------------------------------------------------ fill
@@ -65,7 +106,6 @@ struct PointBin {
 template <class R>
 __device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* bad) {
   PointBin pb;
-  pb.bin = 0;
   pb.cell = 0;
   uint32_t tile[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) pb.t[a] = 0.0;
@@ -82,11 +122,11 @@ __device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* b
     if (u >= nf) u = 0.0;
     double l0 = ceil(u - 0.5 * g.w);
     pb.t[a] = l0 - u;
-    long long li = (long long)l0;
+    int li = (int)l0;
     if (li < 0) li += g.nf[a];
     if (li >= g.nf[a]) li -= g.nf[a];
-    uint32_t ta = (uint32_t)(li / g.T[a]);
-    uint32_t loc = (uint32_t)(li - (long long)ta * g.T[a]);
+    uint32_t ta = (uint32_t)li / (uint32_t)g.T[a];
+    uint32_t loc = (uint32_t)li - ta * (uint32_t)g.T[a];
     tile[a] = ta;
     pb.cell |= loc << (8 * a);
   }
@@ -94,6 +134,78 @@ __device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* b
   return pb;
 }
 
+// Block-private histogram.  kr[i] = tile | rank << 16 (tile < 2^16, rank < 2^16);
+// H[tile * nblk + block] = points of the block in the tile.
+template <class R>
+__global__ void bin_hist_kernel(Geom g, const R* __restrict__ pos, long long chunk, int nblk,
+                                uint32_t* __restrict__ kr, uint32_t* __restrict__ H,
+                                int* __restrict__ flag) {
+  extern __shared__ uint32_t hist[];
+  const int nb = (int)g.nbins;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const long long i0 = (long long)blockIdx.x * chunk;
+  long long i1 = i0 + chunk;
+  if (i1 > g.N) i1 = g.N;
+  bool bad = false;
+  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
+    uint32_t r = atomicAdd(&hist[pb.bin], 1u);
+    kr[i] = pb.bin | (r << 16);
+  }
+  if (bad) atomicOr(flag, 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) H[(long long)b * nblk + blockIdx.x] = hist[b];
+}
+
+// Per tile: exclusive scan of H[tile][0..nblk) in place; count[tile] = total.
+// One wavefront per tile.
+__global__ void bin_rowscan_kernel(uint32_t* __restrict__ H, int nblk, long long nbins,
+                                   uint32_t* __restrict__ count) {
+  const long long tile = (long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (tile >= nbins) return;
+  const int lane = threadIdx.x & 63;
+  uint32_t* row = H + tile * nblk;
+  uint32_t carry = 0;
+  for (int base = 0; base < nblk; base += 64) {
+    const int i = base + lane;
+    const uint32_t v = (i < nblk) ? row[i] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (i < nblk) row[i] = carry + x - v;
+    carry += __shfl(x, 63, 64);
+  }
+  if (lane == 0) count[tile] = carry;
+}
+
+template <class R>
+__global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, long long chunk, int nblk,
+                                   const uint32_t* __restrict__ kr,
+                                   const uint32_t* __restrict__ H,
+                                   const long long* __restrict__ start, Rec<R>* __restrict__ rec,
+                                   int* __restrict__ perm) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  bool bad = false;
+  PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
+  const uint32_t v = kr[i];
+  const uint32_t tile = v & 0xffffu, rank = v >> 16;
+  const long long blk = i / chunk;
+  const long long dst = start[tile] + H[(long long)tile * nblk + blk] + rank;
+  Rec<R> o;
+  o.t[0] = (R)pb.t[0];
+  o.t[1] = (R)pb.t[1];
+  o.t[2] = (R)pb.t[2];
+  o.cell = pb.cell;
+  rec[dst] = o;
+  perm[dst] = (int)i;
+}
+
+// Fallback for very many tiles: global atomic counts (key, rank per point).
 template <class R>
 __global__ void bin_count_kernel(Geom g, const R* __restrict__ pos, uint32_t* __restrict__ key,
                                  uint32_t* __restrict__ rank, uint32_t* __restrict__ count,
@@ -108,23 +220,16 @@ __global__ void bin_count_kernel(Geom g, const R* __restrict__ pos, uint32_t* __
 }
 
 template <class R>
-void launch_bin_count(const Geom& g, const R* pos, uint32_t* key, uint32_t* rank,
-                      uint32_t* count, int* flag, hipStream_t st) {
-  long long blocks = (g.N + 255) / 256;
-  bin_count_kernel<R><<<(unsigned)blocks, 256, 0, st>>>(g, pos, key, rank, count, flag);
-}
-
-template <class R>
-__global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos,
-                                   const uint32_t* __restrict__ key,
-                                   const uint32_t* __restrict__ rank,
-                                   const long long* __restrict__ start, Rec<R>* __restrict__ rec,
-                                   int* __restrict__ perm) {
+__global__ void bin_scatter_atomic_kernel(Geom g, const R* __restrict__ pos,
+                                          const uint32_t* __restrict__ key,
+                                          const uint32_t* __restrict__ rank,
+                                          const long long* __restrict__ start,
+                                          Rec<R>* __restrict__ rec, int* __restrict__ perm) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.N) return;
   bool bad = false;
   PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
-  long long dst = start[key[i]] + rank[i];
+  const long long dst = start[key[i]] + rank[i];
   Rec<R> o;
   o.t[0] = (R)pb.t[0];
   o.t[1] = (R)pb.t[1];
@@ -132,13 +237,6 @@ __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos,
   o.cell = pb.cell;
   rec[dst] = o;
   perm[dst] = (int)i;
-}
-
-template <class R>
-void launch_bin_scatter(const Geom& g, const R* pos, const uint32_t* key, const uint32_t* rank,
-                        const long long* start, Rec<R>* rec, int* perm, hipStream_t st) {
-  long long blocks = (g.N + 255) / 256;
-  bin_scatter_kernel<R><<<(unsigned)blocks, 256, 0, st>>>(g, pos, key, rank, start, rec, perm);
 }
 
 // Exclusive scan of the per-tile counts into start[0..nbins] (one workgroup,
@@ -168,29 +266,47 @@ __global__ void scan_bins_kernel(const uint32_t* __restrict__ count, long long n
   if (threadIdx.x == 0) start[nb] = carry;
 }
 
-void launch_scan_bins(const Geom& g, const uint32_t* count, long long* start, hipStream_t st) {
-  scan_bins_kernel<<<1, 1024, 0, st>>>(count, g.nbins, start);
+void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, BinBuffers& b,
+                hipStream_t st) {
+  const long long nblocks = (g.N + 255) / 256;
+  if (bp.privatized) {
+    const size_t lds = (size_t)g.nbins * sizeof(uint32_t);
+    if (f64)
+      bin_hist_kernel<double><<<bp.nblk, 1024, lds, st>>>(g, (const double*)pos, bp.chunk,
+                                                         bp.nblk, b.kr, b.H, b.flag);
+    else
+      bin_hist_kernel<float><<<bp.nblk, 1024, lds, st>>>(g, (const float*)pos, bp.chunk,
+                                                        bp.nblk, b.kr, b.H, b.flag);
+    bin_rowscan_kernel<<<(unsigned)((g.nbins + 3) / 4), 256, 0, st>>>(b.H, bp.nblk, g.nbins,
+                                                                       b.count);
+    scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, g.nbins, b.start);
+    if (f64)
+      bin_scatter_kernel<double><<<(unsigned)nblocks, 256, 0, st>>>(
+          g, (const double*)pos, bp.chunk, bp.nblk, b.kr, b.H, b.start, (Rec<double>*)b.rec,
+          b.perm);
+    else
+      bin_scatter_kernel<float><<<(unsigned)nblocks, 256, 0, st>>>(
+          g, (const float*)pos, bp.chunk, bp.nblk, b.kr, b.H, b.start, (Rec<float>*)b.rec,
+          b.perm);
+  } else {
+    launch_fill<uint32_t>(b.count, g.nbins, 0u, st);
+    if (f64)
+      bin_count_kernel<double><<<(unsigned)nblocks, 256, 0, st>>>(g, (const double*)pos, b.key,
+                                                                 b.kr, b.count, b.flag);
+    else
+      bin_count_kernel<float><<<(unsigned)nblocks, 256, 0, st>>>(g, (const float*)pos, b.key,
+                                                                b.kr, b.count, b.flag);
+    scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, g.nbins, b.start);
+    if (f64)
+      bin_scatter_atomic_kernel<double><<<(unsigned)nblocks, 256, 0, st>>>(
+          g, (const double*)pos, b.key, b.kr, b.start, (Rec<double>*)b.rec, b.perm);
+    else
+      bin_scatter_atomic_kernel<float><<<(unsigned)nblocks, 256, 0, st>>>(
+          g, (const float*)pos, b.key, b.kr, b.start, (Rec<float>*)b.rec, b.perm);
+  }
 }
 
 // ------------------------------------------------------------- spreading
-template <class R>
-struct FixedPoint;
-template <>
-struct FixedPoint<float> {
-  using T = uint32_t;
-  static constexpr int bits = 31;
-};
-template <>
-struct FixedPoint<double> {
-  using T = unsigned long long;
-  static constexpr int bits = 63;
-};
-
-__device__ __forceinline__ uint32_t to_fixed(float v) { return __float2uint_rn(v); }
-__device__ __forceinline__ unsigned long long to_fixed(double v) {
-  return (unsigned long long)(v + 0.5);
-}
-
 __device__ __forceinline__ void tile_coords(const Geom& g, long long bin, int* t) {
   t[0] = (int)(bin % g.nt[0]);
   long long r = bin / g.nt[0];
@@ -198,22 +314,59 @@ __device__ __forceinline__ void tile_coords(const Geom& g, long long bin, int* t
   t[2] = (int)(r / g.nt[1]);
 }
 
+// Fixed-point exponent for a tile of `cnt` points: (cnt + 1) 2^ex <= 2^bits.
+__device__ __forceinline__ int fixed_exponent(long long cnt, int bits) {
+  return (int)floor(log2(ldexp(1.0, bits) / (double)(cnt + 1)));
+}
+
+// add a row of W fixed-point values starting at acc[rb] with 64-bit atomics on
+// aligned pairs of 32-bit cells (no carry can cross: every cell stays < 2^32)
+template <int W, int I>
+__device__ __forceinline__ uint32_t q_at(const uint32_t* q) {
+  if constexpr (I >= 0 && I < W) return q[I];
+  else return 0u;
+}
+template <int W, int K>
+__device__ __forceinline__ void add_pair(unsigned long long* p, int par, const uint32_t* q) {
+  // cells rb - par + 2K and rb - par + 2K + 1 hold row elements 2K - par and 2K + 1 - par
+  const uint32_t lo = par ? q_at<W, 2 * K - 1>(q) : q_at<W, 2 * K>(q);
+  const uint32_t hi = par ? q_at<W, 2 * K>(q) : q_at<W, 2 * K + 1>(q);
+  const unsigned long long v = (unsigned long long)lo | ((unsigned long long)hi << 32);
+  if (v) atomicAdd(p + K, v);
+}
+template <int W, int... K>
+__device__ __forceinline__ void add_pairs(unsigned long long* p, int par, const uint32_t* q,
+                                          std::integer_sequence<int, K...>) {
+  (add_pair<W, K>(p, par, q), ...);
+}
+template <int W>
+__device__ __forceinline__ void add_row_pairs(uint32_t* acc, int rb, const uint32_t* q) {
+  const int par = rb & 1;
+  unsigned long long* p = reinterpret_cast<unsigned long long*>(acc + (rb - par));
+  add_pairs<W>(p, par, q, std::make_integer_sequence<int, (W + 2) / 2>{});
+}
+
 template <class R, int D, int W>
 __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
-                              const long long* __restrict__ start, R* __restrict__ grid) {
-  using A = typename FixedPoint<R>::T;
-  extern __shared__ unsigned char smem_raw[];
-  A* acc = reinterpret_cast<A*>(smem_raw);
+                              const long long* __restrict__ start, R* __restrict__ tiles) {
+  constexpr bool F32 = sizeof(R) == 4;
+  extern __shared__ unsigned long long smem_u64[];
+  uint32_t* acc32 = reinterpret_cast<uint32_t*>(smem_u64);
+  unsigned long long* acc64 = smem_u64;
   const long long bin = blockIdx.x;
   const int E0 = g.E[0], E1 = g.E[1], E2 = (D == 3) ? g.E[2] : 1;
   const int ncell = E0 * E1 * E2;
   const long long s = start[bin], e = start[bin + 1];
-  if (e == s) return;  // uniform across the block
-  for (int c = threadIdx.x; c < ncell; c += blockDim.x) acc[c] = 0;
-  // fixed-point scale 2^ex with (count + 1) 2^ex <= 2^bits: each contribution is
-  // at most 1, so no cell of the tile can overflow
-  const double cnt1 = (double)(e - s + 1);
-  const int ex = (int)floor(log2(ldexp(1.0, FixedPoint<R>::bits) / cnt1));
+  R* __restrict__ out = tiles + bin * (long long)ncell;
+  if (e == s) {
+    for (int c = threadIdx.x; c < ncell; c += blockDim.x) out[c] = R(0);
+    return;  // uniform across the block
+  }
+  for (int c = threadIdx.x; c < ncell + 2; c += blockDim.x) {
+    if (F32) acc32[c] = 0u;
+    else acc64[c] = 0ull;
+  }
+  const int ex = fixed_exponent(e - s, F32 ? 31 : 63);
   const R scale = (R)ldexp(1.0, ex);
   const R inv_scale = (R)ldexp(1.0, -ex);
   const R half_w_inv = R(2) / R(W);
@@ -229,34 +382,84 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
       if (D == 3) k2[i] = es_kernel<R>((p.t[2] + R(i)) * half_w_inv, beta);
     }
     const int l0 = p.cell & 0xff, l1 = (p.cell >> 8) & 0xff, l2 = (p.cell >> 16) & 0xff;
-    if (D == 2) {
+    const int zmax = (D == 3) ? W : 1;
+    for (int dz = 0; dz < zmax; ++dz) {
+      const R pz = (D == 3) ? k2[dz] * scale : scale;
 #pragma unroll
       for (int dy = 0; dy < W; ++dy) {
-        const R py = k1[dy] * scale;
-        A* row = acc + (l1 + dy) * E0 + l0;
+        const R py = k1[dy] * pz;
+        const int rb = ((D == 3 ? (l2 + dz) * E1 : 0) + (l1 + dy)) * E0 + l0;
+        if (F32) {
+          uint32_t q[W];
 #pragma unroll
-        for (int dx = 0; dx < W; ++dx) atomicAdd(row + dx, to_fixed(py * k0[dx]));
-      }
-    } else {
-      for (int dz = 0; dz < W; ++dz) {
-        const R pz = k2[dz] * scale;
+          for (int dx = 0; dx < W; ++dx) q[dx] = __float2uint_rn((float)(py * k0[dx]));
+          add_row_pairs<W>(acc32, rb, q);
+        } else {
 #pragma unroll
-        for (int dy = 0; dy < W; ++dy) {
-          const R py = k1[dy] * pz;
-          A* row = acc + ((l2 + dz) * E1 + (l1 + dy)) * E0 + l0;
-#pragma unroll
-          for (int dx = 0; dx < W; ++dx) atomicAdd(row + dx, to_fixed(py * k0[dx]));
+          for (int dx = 0; dx < W; ++dx)
+            atomicAdd(acc64 + rb + dx, (unsigned long long)((double)(py * k0[dx]) + 0.5));
         }
       }
     }
   }
   __syncthreads();
+  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+    if (F32) out[c] = (R)acc32[c] * inv_scale;
+    else out[c] = (R)acc64[c] * inv_scale;
+  }
+}
+
+// Fold: grid cell (x, y, z) = sum over the padded tiles that cover it.  For each
+// axis, cover[a] lists (tile, local index) pairs per grid coordinate (CSR).
+template <class R, int D>
+__global__ void fold_kernel(Geom g, FoldTables ft, const R* __restrict__ tiles,
+                            R* __restrict__ grid) {
+  const long long n = g.ngrid;
+  const long long ncell = (long long)g.E[0] * g.E[1] * (D == 3 ? g.E[2] : 1);
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(c % g.nf[0]);
+    const long long r = c / g.nf[0];
+    const int y = (int)(r % g.nf[1]);
+    const int z = (int)(r / g.nf[1]);
+    R acc = R(0);
+    const int zb = (D == 3) ? ft.off[2][z] : 0, ze = (D == 3) ? ft.off[2][z + 1] : 1;
+    for (int iz = zb; iz < ze; ++iz) {
+      const int tz = (D == 3) ? ft.ent[2][iz].x : 0, lz = (D == 3) ? ft.ent[2][iz].y : 0;
+      for (int iy = ft.off[1][y]; iy < ft.off[1][y + 1]; ++iy) {
+        const int ty = ft.ent[1][iy].x, ly = ft.ent[1][iy].y;
+        for (int ix = ft.off[0][x]; ix < ft.off[0][x + 1]; ++ix) {
+          const int tx = ft.ent[0][ix].x, lx = ft.ent[0][ix].y;
+          const long long bin = tx + (long long)g.nt[0] * (ty + (long long)g.nt[1] * tz);
+          acc += tiles[bin * ncell + ((long long)lz * g.E[1] + ly) * g.E[0] + lx];
+        }
+      }
+    }
+    grid[c] = acc;
+  }
+}
+
+// ---------------------------------------------------------- interpolation
+// Field tile origin is one cell before the spreading tile (width w + 1), extent
+// T + w + 1 per axis (g.Ei).
+template <class R, int D, int W>
+__global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
+                              const long long* __restrict__ start, const int* __restrict__ perm,
+                              const R* __restrict__ v, R* __restrict__ grad) {
+  constexpr int WI = W + 1;
+  extern __shared__ unsigned long long smem_u64[];
+  R* sub = reinterpret_cast<R*>(smem_u64);
+  const long long bin = blockIdx.x;
+  const int E0 = g.Ei[0], E1 = g.Ei[1], E2 = (D == 3) ? g.Ei[2] : 1;
+  const int ncell = E0 * E1 * E2;
+  const long long s = start[bin], e = start[bin + 1];
+  if (e == s) return;
   int t[3];
   tile_coords(g, bin, t);
-  const int o0 = t[0] * g.T[0], o1 = t[1] * g.T[1], o2 = t[2] * g.T[2];
+  const int o0 = t[0] * g.T[0] - 1 + g.nf[0];
+  const int o1 = t[1] * g.T[1] - 1 + g.nf[1];
+  const int o2 = (D == 3) ? t[2] * g.T[2] - 1 + g.nf[2] : 0;
   for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-    const A a = acc[c];
-    if (a == 0) continue;
     const int c0 = c % E0;
     const int r = c / E0;
     const int c1 = r % E1;
@@ -265,118 +468,67 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
     while (x >= g.nf[0]) x -= g.nf[0];
     while (y >= g.nf[1]) y -= g.nf[1];
     while (z >= g.nf[2]) z -= g.nf[2];
-    const long long gi = ((long long)z * g.nf[1] + y) * g.nf[0] + x;
-    unsafeAtomicAdd(grid + gi, (R)a * inv_scale);
-  }
-}
-
-// ---------------------------------------------------------- interpolation
-template <class R, int D, int W>
-__global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
-                              const long long* __restrict__ start, const int* __restrict__ perm,
-                              const R* __restrict__ v0, const R* __restrict__ v1,
-                              const R* __restrict__ v2, int c_first, int nc,
-                              R* __restrict__ grad) {
-  extern __shared__ unsigned char smem_raw[];
-  R* sub = reinterpret_cast<R*>(smem_raw);
-  const long long bin = blockIdx.x;
-  const int E0 = g.E[0], E1 = g.E[1], E2 = (D == 3) ? g.E[2] : 1;
-  const int ncell = E0 * E1 * E2;
-  const long long s = start[bin], e = start[bin + 1];
-  if (e == s) return;
-  int t[3];
-  tile_coords(g, bin, t);
-  const int o0 = t[0] * g.T[0], o1 = t[1] * g.T[1], o2 = t[2] * g.T[2];
-  const R* src[3] = {v0, v1, v2};
-  for (int k = 0; k < nc; ++k) {
-    const R* __restrict__ v = src[c_first + k];
-    for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-      const int c0 = c % E0;
-      const int r = c / E0;
-      const int c1 = r % E1;
-      const int c2 = r / E1;
-      int x = o0 + c0, y = o1 + c1, z = o2 + c2;
-      while (x >= g.nf[0]) x -= g.nf[0];
-      while (y >= g.nf[1]) y -= g.nf[1];
-      while (z >= g.nf[2]) z -= g.nf[2];
-      sub[k * ncell + c] = v[((long long)z * g.nf[1] + y) * g.nf[0] + x];
-    }
+    sub[c] = v[((long long)z * g.nf[1] + y) * g.nf[0] + x];
   }
   __syncthreads();
-  const R half_w_inv = R(2) / R(W);
-  const R beta = (R)g.beta;
+  const R half_w_inv = R(2) / R(WI);
+  const R beta = (R)g.beta_i;
+  const R icb = (R)(1.0 / cosh(g.beta_i));
+  const R lim = R(0.5) - R(W) * R(0.5);  // t >= lim: footprint of width W+1 starts one earlier
+  R gs[3];
+  for (int a = 0; a < 3; ++a) gs[a] = (a < D) ? (R)(-(double)g.nf[a] / g.L[a] * 2.0 / WI) : R(0);
   for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
     const Rec<R> p = rec[j];
-    R k0[W], k1[W], k2[W];
+    R f0[WI], d0[WI], f1[WI], d1[WI], f2[WI], d2[WI];
+    int l[3];
+    const int cl[3] = {(int)(p.cell & 0xff), (int)((p.cell >> 8) & 0xff),
+                       (int)((p.cell >> 16) & 0xff)};
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-      k0[i] = es_kernel<R>((p.t[0] + R(i)) * half_w_inv, beta);
-      k1[i] = es_kernel<R>((p.t[1] + R(i)) * half_w_inv, beta);
-      if (D == 3) k2[i] = es_kernel<R>((p.t[2] + R(i)) * half_w_inv, beta);
+    for (int a = 0; a < D; ++a) {
+      const int k = (p.t[a] >= lim) ? 1 : 0;
+      const R ti = p.t[a] - (R)k;
+      l[a] = cl[a] - k + 1;
+      R* f = a == 0 ? f0 : (a == 1 ? f1 : f2);
+      R* df = a == 0 ? d0 : (a == 1 ? d1 : d2);
+#pragma unroll
+      for (int i = 0; i < WI; ++i)
+        cosh_kernel_d<R>((ti + R(i)) * half_w_inv, beta, icb, f + i, df + i);
     }
-    const int l0 = p.cell & 0xff, l1 = (p.cell >> 8) & 0xff, l2 = (p.cell >> 16) & 0xff;
-    const long long o = (long long)perm[j] * D;
-    for (int k = 0; k < nc; ++k) {
-      const R* sg = sub + k * ncell;
-      R acc = R(0);
-      if (D == 2) {
+    R gx = R(0), gy = R(0), gz = R(0);
+    const int zmax = (D == 3) ? WI : 1;
+    for (int dz = 0; dz < zmax; ++dz) {
+      R sxy = R(0), sdxy = R(0), sxdy = R(0);
 #pragma unroll
-        for (int dy = 0; dy < W; ++dy) {
-          const R* row = sg + (l1 + dy) * E0 + l0;
-          R rs = R(0);
+      for (int dy = 0; dy < WI; ++dy) {
+        const R* row = sub + ((D == 3 ? (l[2] + dz) * E1 : 0) + (l[1] + dy)) * E0 + l[0];
+        R sx = R(0), sdx = R(0);
 #pragma unroll
-          for (int dx = 0; dx < W; ++dx) rs += row[dx] * k0[dx];
-          acc += rs * k1[dy];
+        for (int dx = 0; dx < WI; ++dx) {
+          const R vv = row[dx];
+          sx += vv * f0[dx];
+          sdx += vv * d0[dx];
         }
-      } else {
-        for (int dz = 0; dz < W; ++dz) {
-          R ps = R(0);
-#pragma unroll
-          for (int dy = 0; dy < W; ++dy) {
-            const R* row = sg + ((l2 + dz) * E1 + (l1 + dy)) * E0 + l0;
-            R rs = R(0);
-#pragma unroll
-            for (int dx = 0; dx < W; ++dx) rs += row[dx] * k0[dx];
-            ps += rs * k1[dy];
-          }
-          acc += ps * k2[dz];
-        }
+        sxy += sx * f1[dy];
+        sdxy += sdx * f1[dy];
+        sxdy += sx * d1[dy];
       }
-      grad[o + c_first + k] = acc;
+      if (D == 3) {
+        gx += sdxy * f2[dz];
+        gy += sxdy * f2[dz];
+        gz += sxy * d2[dz];
+      } else {
+        gx = sdxy;
+        gy = sxdy;
+      }
     }
+    const long long o = (long long)perm[j] * D;
+    grad[o] = gx * gs[0];
+    grad[o + 1] = gy * gs[1];
+    if (D == 3) grad[o + 2] = gz * gs[2];
   }
 }
 
 // --------------------------------------------------------------- launch
-template <class R, int D, int W>
-static void spread_launch_w(const Geom& g, const Rec<R>* rec, const long long* start, R* grid,
-                            hipStream_t st) {
-  using A = typename FixedPoint<R>::T;
-  const size_t lds = (size_t)g.E[0] * g.E[1] * (D == 3 ? g.E[2] : 1) * sizeof(A);
-  hipFuncSetAttribute((const void*)spread_kernel<R, D, W>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  spread_kernel<R, D, W><<<(unsigned)g.nbins, 256, lds, st>>>(g, rec, start, grid);
-}
-
-template <class R, int D, int W>
-static void interp_launch_w(const Geom& g, const Rec<R>* rec, const long long* start,
-                            const int* perm, const R* const* comps, int ncomp, R* grad,
-                            hipStream_t st) {
-  const size_t cell = (size_t)g.E[0] * g.E[1] * (D == 3 ? g.E[2] : 1) * sizeof(R);
-  int per = (int)((160 * 1024) / cell);
-  if (per > ncomp) per = ncomp;
-  if (per < 1) per = 1;
-  for (int c0 = 0; c0 < ncomp; c0 += per) {
-    const int nc = (ncomp - c0 < per) ? ncomp - c0 : per;
-    const size_t lds = cell * nc;
-    hipFuncSetAttribute((const void*)interp_kernel<R, D, W>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    interp_kernel<R, D, W><<<(unsigned)g.nbins, 256, lds, st>>>(
-        g, rec, start, perm, comps[0], ncomp > 1 ? comps[1] : nullptr,
-        ncomp > 2 ? comps[2] : nullptr, c0, nc, grad);
-  }
-}
-
 #define FRESCO_W_SWITCH(W_, CALL) \
   switch (W_) {                   \
     case 2: CALL(2); break;       \
@@ -397,50 +549,98 @@ static void interp_launch_w(const Geom& g, const Rec<R>* rec, const long long* s
   }
 
 template <class R>
-void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* grid,
+size_t spread_lds_bytes(const Geom& g) {
+  size_t ncell = (size_t)g.E[0] * g.E[1] * (g.d == 3 ? g.E[2] : 1);
+  return (ncell + 2) * (sizeof(R) == 4 ? 4 : 8);
+}
+template <class R>
+size_t interp_lds_bytes(const Geom& g) {
+  return (size_t)g.Ei[0] * g.Ei[1] * (g.d == 3 ? g.Ei[2] : 1) * sizeof(R);
+}
+
+// one-time kernel attributes (dynamic LDS above the default limit)
+template <class R>
+void spread_prepare(const Geom& g) {
+  const int sl = (int)spread_lds_bytes<R>(g), il = (int)interp_lds_bytes<R>(g);
+#define PREP(W)                                                                                  \
+  do {                                                                                           \
+    if (g.d == 2) {                                                                              \
+      hipFuncSetAttribute((const void*)spread_kernel<R, 2, W>,                                  \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, sl);                       \
+      hipFuncSetAttribute((const void*)interp_kernel<R, 2, W>,                                  \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, il);                       \
+    } else {                                                                                     \
+      hipFuncSetAttribute((const void*)spread_kernel<R, 3, W>,                                  \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, sl);                       \
+      hipFuncSetAttribute((const void*)interp_kernel<R, 3, W>,                                  \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, il);                       \
+    }                                                                                            \
+  } while (0)
+  FRESCO_W_SWITCH(g.w, PREP)
+#undef PREP
+  hipFuncSetAttribute((const void*)bin_hist_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)(g.nbins * 4 > 1024 ? g.nbins * 4 : 1024));
+}
+
+template <class R>
+void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* tiles,
                    hipStream_t st) {
-  if (g.d == 2) {
-#define SP2(W) spread_launch_w<R, 2, W>(g, rec, start, grid, st)
-    FRESCO_W_SWITCH(g.w, SP2)
-#undef SP2
-  } else {
-#define SP3(W) spread_launch_w<R, 3, W>(g, rec, start, grid, st)
-    FRESCO_W_SWITCH(g.w, SP3)
-#undef SP3
-  }
+  const size_t lds = spread_lds_bytes<R>(g);
+  const int threads = (g.d == 3) ? 512 : 256;
+#define SP(W)                                                                               \
+  do {                                                                                      \
+    if (g.d == 2)                                                                           \
+      spread_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, tiles); \
+    else                                                                                    \
+      spread_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, tiles); \
+  } while (0)
+  FRESCO_W_SWITCH(g.w, SP)
+#undef SP
+}
+
+template <class R>
+void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, hipStream_t st) {
+  long long blocks = (g.ngrid + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (g.d == 2) fold_kernel<R, 2><<<(unsigned)blocks, 256, 0, st>>>(g, ft, tiles, grid);
+  else fold_kernel<R, 3><<<(unsigned)blocks, 256, 0, st>>>(g, ft, tiles, grid);
 }
 
 template <class R>
 void launch_interp(const Geom& g, const Rec<R>* rec, const long long* start, const int* perm,
-                   const R* const* comps, int ncomp, R* grad, hipStream_t st) {
-  if (g.d == 2) {
-#define IP2(W) interp_launch_w<R, 2, W>(g, rec, start, perm, comps, ncomp, grad, st)
-    FRESCO_W_SWITCH(g.w, IP2)
-#undef IP2
-  } else {
-#define IP3(W) interp_launch_w<R, 3, W>(g, rec, start, perm, comps, ncomp, grad, st)
-    FRESCO_W_SWITCH(g.w, IP3)
-#undef IP3
-  }
+                   const R* v, R* grad, hipStream_t st) {
+  const size_t lds = interp_lds_bytes<R>(g);
+  const int threads = (g.d == 3) ? 512 : 256;
+#define IP(W)                                                                                  \
+  do {                                                                                         \
+    if (g.d == 2)                                                                              \
+      interp_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, perm, v, \
+                                                                      grad);                   \
+    else                                                                                       \
+      interp_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, perm, v, \
+                                                                      grad);                   \
+  } while (0)
+  FRESCO_W_SWITCH(g.w, IP)
+#undef IP
 }
 
-template void launch_bin_count<float>(const Geom&, const float*, uint32_t*, uint32_t*, uint32_t*,
-                                      int*, hipStream_t);
-template void launch_bin_count<double>(const Geom&, const double*, uint32_t*, uint32_t*,
-                                       uint32_t*, int*, hipStream_t);
-template void launch_bin_scatter<float>(const Geom&, const float*, const uint32_t*,
-                                        const uint32_t*, const long long*, Rec<float>*, int*,
-                                        hipStream_t);
-template void launch_bin_scatter<double>(const Geom&, const double*, const uint32_t*,
-                                         const uint32_t*, const long long*, Rec<double>*, int*,
-                                         hipStream_t);
+template size_t spread_lds_bytes<float>(const Geom&);
+template size_t spread_lds_bytes<double>(const Geom&);
+template size_t interp_lds_bytes<float>(const Geom&);
+template size_t interp_lds_bytes<double>(const Geom&);
+template void spread_prepare<float>(const Geom&);
+template void spread_prepare<double>(const Geom&);
 template void launch_spread<float>(const Geom&, const Rec<float>*, const long long*, float*,
                                    hipStream_t);
 template void launch_spread<double>(const Geom&, const Rec<double>*, const long long*, double*,
                                     hipStream_t);
+template void launch_fold<float>(const Geom&, const float*, float*, const FoldTables&,
+                                 hipStream_t);
+template void launch_fold<double>(const Geom&, const double*, double*, const FoldTables&,
+                                  hipStream_t);
 template void launch_interp<float>(const Geom&, const Rec<float>*, const long long*, const int*,
-                                   const float* const*, int, float*, hipStream_t);
+                                   const float*, float*, hipStream_t);
 template void launch_interp<double>(const Geom&, const Rec<double>*, const long long*,
-                                    const int*, const double* const*, int, double*, hipStream_t);
+                                    const int*, const double*, double*, hipStream_t);
 
 }  // namespace fresco

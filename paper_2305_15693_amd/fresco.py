@@ -18,8 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libfresco.so")
 F32, F64 = 0, 1
 WEIGHT_ABS, WEIGHT_RELATIVE = 0, 1
 OK, EINVAL, ENOMEM, EHIP, ENOTSUP, ENONFINITE, ELINESEARCH = 0, -1, -2, -3, -4, -5, -6
-STAGES = ["bin", "spread", "fft_rows_fwd", "fft_cols_fwd", "modes", "fft_cols_inv",
+STAGES = ["bin", "spread", "fold", "fft_rows_fwd", "fft_cols_fwd", "modes", "fft_cols_inv",
           "fft_rows_inv", "interp"]
+# stages made of exactly one kernel launch
+SINGLE_KERNEL_STAGES = ["spread", "fold", "fft_rows_fwd", "fft_cols_fwd", "modes",
+                        "fft_cols_inv", "fft_rows_inv", "interp"]
 
 
 class FrescoError(RuntimeError):
