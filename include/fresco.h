@@ -54,7 +54,7 @@ enum fresco_status {
   FRESCO_EINVAL = -1,      /* invalid argument (null pointer, bad size or option) */
   FRESCO_ENOMEM = -2,      /* device or host allocation failed */
   FRESCO_EHIP = -3,        /* a HIP runtime call failed (see fresco_last_hip_error) */
-  FRESCO_ENOTSUP = -4,     /* valid request outside what this build supports */
+  FRESCO_ENOTSUP = -4,     /* valid request outside what the library supports */
   FRESCO_ENONFINITE = -5,  /* a position was NaN or infinite (synchronous calls only) */
   FRESCO_ELINESEARCH = -6  /* line search failed repeatedly (optimizer) */
 };
@@ -122,6 +122,37 @@ int fresco_loss_grad(fresco_ctx* ctx, const void* pos, double* loss, void* grad)
  * call only enqueues work (no synchronisation, no non-finite report), so it can
  * be captured in a HIP graph.  Errors: EINVAL, EHIP. */
 int fresco_loss_grad_async(fresco_ctx* ctx, const void* pos, double* loss_dev, void* grad);
+
+/* Options of the L-BFGS minimiser (main text: L-BFGS with a maximal step size and
+ * a backtracking line search).  Defaults used by the Python layer: m = 8,
+ * max_backtracks = 20, max_step = 0.1 L / N^(1/d), c1 = 1e-4, shrink = 0.5,
+ * gtol = 0. */
+typedef struct fresco_lbfgs_opts {
+  int32_t m;              /* history pairs, 1..16 */
+  int32_t max_backtracks; /* rejections before the history is dropped (>= 0) */
+  double max_step;        /* largest displacement of one coordinate in one step (> 0) */
+  double c1;              /* Armijo sufficient-decrease constant, in (0, 1) */
+  double shrink;          /* backtracking factor, in (0, 1) */
+  double gtol;            /* stop when the RMS gradient falls to or below (0: never) */
+} fresco_lbfgs_opts;
+
+/* Minimise L_S over the positions with L-BFGS for n_iter accepted iterations
+ * (fewer if the RMS gradient reaches gtol).  pos: device [n][d], updated IN
+ * PLACE (the only mutated argument).  The history of (s, y) pairs and the
+ * internal point order persist in the context across calls, so a run can be
+ * continued by calling again with the returned positions; fresco_reset_history
+ * starts afresh.  The iterations run as replays of one captured HIP graph (on a
+ * non-default stream) with no host synchronisation inside a batch.
+ * loss_out (host, may be NULL): loss at the final positions; n_eval_out (host,
+ * may be NULL): loss/gradient evaluations used.  Synchronises the stream.
+ * Errors: EINVAL (null ctx/pos/opts, n_iter < 0, options out of range), EHIP,
+ * ELINESEARCH (no decrease even along the steepest descent direction; pos holds
+ * the last accepted point). */
+int fresco_step(fresco_ctx* ctx, void* pos, const fresco_lbfgs_opts* opts, int32_t n_iter,
+                double* loss_out, int32_t* n_eval_out);
+
+/* Drop the L-BFGS history and internal point order kept by the context. */
+int fresco_reset_history(fresco_ctx* ctx);
 
 /* Stages of one evaluation, for fresco_set_timing / fresco_read_timing. */
 enum fresco_stage {

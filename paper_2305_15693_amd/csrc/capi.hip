@@ -24,6 +24,7 @@
 
 #include "common.h"
 #include "fft.h"
+#include "lbfgs.h"
 #include "plan.h"
 
 using namespace fresco;
@@ -44,6 +45,7 @@ namespace {
 template <class R>
 struct State {
   AxisFft<R> ax[3];  // [0] rows: complex length nf0/2; [1], [2]: columns along axes 1, 2
+  KernelPolys kp;    // FP32 kernel polynomials
   BinPlan bp;
   BinBuffers bb;
   R* tiles = nullptr;  // padded spreading tiles
@@ -69,6 +71,15 @@ struct State {
   ColParams<R> col1;  // axis 1 (3D: forward / inverse; 2D: fused)
   ColParams<R> col2;  // axis 2 (3D: fused)
   long long nloss_part = 0;
+  // L-BFGS (allocated on the first fresco_step)
+  LbfgsVec<R> lv{};
+  LbfgsState* lst = nullptr;
+  LbfgsState* lst_host = nullptr;  // pinned copy
+  int* perm0 = nullptr;            // internal order -> caller's index
+  bool have_perm0 = false;
+  int lb_m = 0;
+  LbfgsOpts lb_opts{};
+  hipGraphExec_t lb_graph = nullptr;
 };
 
 struct GraphEntry {
@@ -283,6 +294,21 @@ int create_state(fresco_ctx* c) {
   const int d = g.d;
   const size_t cs = sizeof(cpx<R>);
   int st;
+  // kernel polynomials (spreading: exponential of semicircle, width w; interpolation:
+  // its cosh form and derivative, width w + 1)
+  {
+    std::memset(&S->kp, 0, sizeof(S->kp));
+    const std::vector<double> sp = kernel_poly(g.w, g.beta, 0, kPolyDeg);
+    const std::vector<double> ip = kernel_poly(g.wi, g.beta_i, 1, kPolyDeg);
+    const std::vector<double> id = kernel_poly(g.wi, g.beta_i, 2, kPolyDeg);
+    for (int j = 0; j < g.w; ++j)
+      for (int k = 0; k <= kPolyDeg; ++k) S->kp.sp[j][k] = (float)sp[j * (kPolyDeg + 1) + k];
+    for (int j = 0; j < g.wi; ++j)
+      for (int k = 0; k <= kPolyDeg; ++k) {
+        S->kp.ip[j][k] = (float)ip[j * (kPolyDeg + 1) + k];
+        S->kp.id[j][k] = (float)id[j * (kPolyDeg + 1) + k];
+      }
+  }
   // FFT plans
   if ((st = setup_axis<R>(c, &S->ax[0], g.nf[0] / 2, true))) return st;
   if ((st = setup_axis<R>(c, &S->ax[1], g.nf[1], false))) return st;
@@ -470,7 +496,7 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
   }
   {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
-    launch_spread<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
+    launch_spread<R>(g, S->kp, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
   }
   {
     StageTimer t(c, FRESCO_STAGE_FOLD);
@@ -548,7 +574,8 @@ int run_modes_to_grad(fresco_ctx* c, int mode, R* S_cube, const R* g_cube, R* gr
   }
   {
     StageTimer t(c, FRESCO_STAGE_INTERP);
-    launch_interp<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->bb.perm, S->v, grad, st);
+    launch_interp<R>(g, S->kp, (const Rec<R>*)S->bb.rec, S->bb.start, S->bb.perm, S->v, grad,
+                     st);
   }
   finish_kernel<<<1, 256, 0, st>>>(S->loss_part, mode == COL_FUSED ? S->nloss_part : 0,
                                    mode == COL_FUSED ? loss_dev : nullptr, S->bb.flag,
@@ -596,6 +623,145 @@ int loss_grad_impl(fresco_ctx* c, const void* pos, double* loss_dev, void* grad)
   return FRESCO_OK;
 }
 
+// ------------------------------------------------------------- L-BFGS
+template <class R>
+int lbfgs_setup(fresco_ctx* c, int m) {
+  State<R>* S = (State<R>*)c->state;
+  if (S->lst && S->lb_m == m) return FRESCO_OK;
+  // (re)allocate for this history length; earlier buffers stay with the context
+  if (S->lb_graph) {
+    (void)hipGraphExecDestroy(S->lb_graph);
+    S->lb_graph = nullptr;
+  }
+  S->have_perm0 = false;
+  const long long n = c->g.N * c->g.d;
+  LbfgsVec<R>& v = S->lv;
+  int st;
+  if ((st = dalloc_t(c, &v.x, n))) return st;
+  if ((st = dalloc_t(c, &v.g, n))) return st;
+  if ((st = dalloc_t(c, &v.p, n))) return st;
+  if ((st = dalloc_t(c, &v.xt, n))) return st;
+  if ((st = dalloc_t(c, &v.gt, n))) return st;
+  if ((st = dalloc_t(c, &v.S, (size_t)n * m))) return st;
+  if ((st = dalloc_t(c, &v.Y, (size_t)n * m))) return st;
+  // vector passes: enough blocks to fill the chip, few enough that the one-block
+  // reduction of their partials stays cheap
+  long long nb = (n + 2047) / 2048;
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  v.nb = (int)nb;
+  v.n = n;
+  v.m = m;
+  if ((st = dalloc_t(c, &v.part0, (4 * (size_t)kLbfgsMaxM + 1) * nb))) return st;
+  if ((st = dalloc_t(c, &v.part1, (size_t)nb))) return st;
+  if ((st = dalloc_t(c, &S->lst, 1))) return st;
+  if ((st = dalloc_t(c, &S->perm0, c->g.N))) return st;
+  if (!S->lst_host) HIPCHK(hipHostMalloc((void**)&S->lst_host, sizeof(LbfgsState)));
+  S->lb_m = m;
+  return FRESCO_OK;
+}
+
+template <class R>
+int lbfgs_reset_state(fresco_ctx* c) {
+  State<R>* S = (State<R>*)c->state;
+  LbfgsState h;
+  std::memset(&h, 0, sizeof(h));
+  h.head = S->lb_m - 1;
+  h.gamma = 1.0;
+  HIPCHK(hipMemcpy(S->lst, &h, sizeof(h), hipMemcpyHostToDevice));
+  return FRESCO_OK;
+}
+
+// one trial step: evaluation at xt, then the optimiser update
+template <class R>
+int lbfgs_trial(fresco_ctx* c) {
+  State<R>* S = (State<R>*)c->state;
+  int st;
+  if ((st = loss_grad_eager<R>(c, S->lv.xt, &S->lst->f_trial, S->lv.gt))) return st;
+  launch_lbfgs_update<R>(S->lv, S->lst, S->lb_opts, c->st);
+  HIPCHK(hipGetLastError());
+  return FRESCO_OK;
+}
+
+template <class R>
+int lbfgs_read(fresco_ctx* c) {
+  State<R>* S = (State<R>*)c->state;
+  HIPCHK(hipMemcpyAsync(S->lst_host, S->lst, sizeof(LbfgsState), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return FRESCO_OK;
+}
+
+template <class R>
+int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, double* loss_out,
+              int32_t* n_eval_out) {
+  State<R>* S = (State<R>*)c->state;
+  const Geom& g = c->g;
+  int st;
+  if ((st = lbfgs_setup<R>(c, o->m))) return st;
+  LbfgsOpts lo;
+  lo.m = o->m;
+  lo.max_backtracks = o->max_backtracks;
+  lo.max_step = o->max_step;
+  lo.c1 = o->c1;
+  lo.shrink = o->shrink;
+  lo.gtol = o->gtol;
+  if (std::memcmp(&lo, &S->lb_opts, sizeof(lo)) != 0 && S->lb_graph) {
+    (void)hipGraphExecDestroy(S->lb_graph);
+    S->lb_graph = nullptr;
+  }
+  S->lb_opts = lo;
+  const long long N = g.N;
+  if (!S->have_perm0) {
+    // internal order = tile order of the starting positions; it stays fixed so
+    // that the history vectors never need permuting, and later binning passes
+    // see nearly sorted points
+    launch_bin(g, S->bp, pos, sizeof(R) == 8, S->bb, c->st);
+    HIPCHK(hipMemcpyAsync(S->perm0, S->bb.perm, sizeof(int) * N, hipMemcpyDeviceToDevice, c->st));
+    if ((st = lbfgs_reset_state<R>(c))) return st;
+    S->have_perm0 = true;
+  }
+  launch_gather_rows<R>((const R*)pos, S->perm0, N, g.d, S->lv.x, c->st);
+  HIPCHK(hipMemcpyAsync(S->lv.xt, S->lv.x, sizeof(R) * N * g.d, hipMemcpyDeviceToDevice, c->st));
+  launch_lbfgs_set_mode(S->lst, 4, n_iter, c->st);  // first evaluation of the call
+  if ((st = lbfgs_trial<R>(c))) return st;
+  launch_lbfgs_set_mode(S->lst, 0, -1, c->st);
+  const bool graphs = c->use_graphs && !c->timing_mask && c->st != nullptr;
+  for (int guard = 0; guard < 1000000; ++guard) {
+    if ((st = lbfgs_read<R>(c))) return st;
+    const LbfgsState& h = *S->lst_host;
+    if (h.iter >= n_iter || h.fail || h.converged) break;
+    const int k = n_iter - h.iter;
+    if (graphs && !S->lb_graph) {
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+      st = lbfgs_trial<R>(c);
+      hipError_t e = hipStreamEndCapture(c->st, &graph);
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      HIPCHK(e);
+      e = hipGraphInstantiate(&S->lb_graph, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(e);
+    }
+    for (int r = 0; r < k; ++r) {
+      if (graphs) {
+        HIPCHK(hipGraphLaunch(S->lb_graph, c->st));
+      } else if ((st = lbfgs_trial<R>(c))) {
+        return st;
+      }
+    }
+  }
+  launch_scatter_rows<R>(S->lv.x, S->perm0, N, g.d, (R*)pos, c->st);
+  if ((st = lbfgs_read<R>(c))) return st;
+  const LbfgsState& h = *S->lst_host;
+  if (loss_out) *loss_out = h.f_cur;
+  if (n_eval_out) *n_eval_out = h.nevals;
+  if (h.fail) return FRESCO_ELINESEARCH;
+  return FRESCO_OK;
+}
+
 template <class R>
 int structure_factor_impl(fresco_ctx* c, const void* pos, void* Sout) {
   State<R>* S = (State<R>*)c->state;
@@ -626,7 +792,7 @@ const char* fresco_error_string(int code) {
     case FRESCO_EINVAL: return "invalid argument";
     case FRESCO_ENOMEM: return "out of memory";
     case FRESCO_EHIP: return "HIP runtime error";
-    case FRESCO_ENOTSUP: return "not supported by this build";
+    case FRESCO_ENOTSUP: return "not supported by this library";
     case FRESCO_ENONFINITE: return "non-finite position";
     case FRESCO_ELINESEARCH: return "line search failed";
     default: return "unknown status";
@@ -649,8 +815,17 @@ int fresco_destroy(fresco_ctx* c) {
     }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   if (c->state) {
-    if (c->dtype == FRESCO_F32) delete (State<float>*)c->state;
-    else delete (State<double>*)c->state;
+    if (c->dtype == FRESCO_F32) {
+      State<float>* S = (State<float>*)c->state;
+      if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
+      if (S->lst_host) (void)hipHostFree(S->lst_host);
+      delete S;
+    } else {
+      State<double>* S = (State<double>*)c->state;
+      if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
+      if (S->lst_host) (void)hipHostFree(S->lst_host);
+      delete S;
+    }
   }
   delete c;
   return FRESCO_OK;
@@ -844,6 +1019,24 @@ int fresco_loss_grad_async(fresco_ctx* c, const void* pos, double* loss_dev, voi
   if (!c || !pos || !loss_dev || !grad) return FRESCO_EINVAL;
   if (c->dtype == FRESCO_F32) return loss_grad_impl<float>(c, pos, loss_dev, grad);
   return loss_grad_impl<double>(c, pos, loss_dev, grad);
+}
+
+int fresco_step(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int32_t n_iter,
+                double* loss_out, int32_t* n_eval_out) {
+  if (!c || !pos || !o || n_iter < 0) return FRESCO_EINVAL;
+  if (o->m < 1 || o->m > kLbfgsMaxM || o->max_backtracks < 0) return FRESCO_EINVAL;
+  if (!(o->max_step > 0.0) || !(o->c1 > 0.0 && o->c1 < 1.0) ||
+      !(o->shrink > 0.0 && o->shrink < 1.0) || !(o->gtol >= 0.0))
+    return FRESCO_EINVAL;
+  if (c->dtype == FRESCO_F32) return step_impl<float>(c, pos, o, n_iter, loss_out, n_eval_out);
+  return step_impl<double>(c, pos, o, n_iter, loss_out, n_eval_out);
+}
+
+int fresco_reset_history(fresco_ctx* c) {
+  if (!c) return FRESCO_EINVAL;
+  if (c->dtype == FRESCO_F32) ((State<float>*)c->state)->have_perm0 = false;
+  else ((State<double>*)c->state)->have_perm0 = false;
+  return FRESCO_OK;
 }
 
 int fresco_loss_grad(fresco_ctx* c, const void* pos, double* loss, void* grad) {

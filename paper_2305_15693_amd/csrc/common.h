@@ -89,14 +89,25 @@ struct Geom {
   long long ncube;  // prod (2M_a+1): full mode cube
 };
 
-// Sorted per-point record: offsets of the kernel footprint and the local cell.
-//   t[a]  = l0_a - u_a in [-w/2, -w/2 + 1), u_a = grid coordinate of the point,
-//           l0_a = first grid index of its footprint (before wrapping);
+// Sorted per-point record: position of the point inside its kernel footprint and
+// the local cell.
+//   t[a]  = tau_a = l0_a - u_a + w/2 in [0, 1), u_a = grid coordinate of the point,
+//           l0_a = ceil(u_a - w/2) = first grid index of its footprint;
 //   cell  = local index of l0 inside its tile, 8 bits per dimension.
 template <class R>
 struct alignas(4 * sizeof(R)) Rec {
   R t[3];
   uint32_t cell;
+};
+
+// FP32 kernels evaluate the spreading and interpolation kernels as polynomials
+// in x = 2 tau - 1, one per footprint cell (coefficients from plan.cpp).
+constexpr int kPolyDeg = 9;
+constexpr int kPolyW = 17;
+struct KernelPolys {
+  float sp[kPolyW][kPolyDeg + 1];  // spreading kernel, w cells
+  float ip[kPolyW][kPolyDeg + 1];  // interpolation kernel, w + 1 cells
+  float id[kPolyW][kPolyDeg + 1];  // derivative d/dz of the interpolation kernel
 };
 
 // Counting sort of the points by tile.
@@ -133,13 +144,14 @@ size_t interp_lds_bytes(const Geom& g);
 template <class R>
 void spread_prepare(const Geom& g);
 template <class R>
-void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* tiles,
-                   hipStream_t st);
+void launch_spread(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
+                   const long long* start, R* tiles, hipStream_t st);
 template <class R>
 void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, hipStream_t st);
 template <class R>
-void launch_interp(const Geom& g, const Rec<R>* rec, const long long* start, const int* perm,
-                   const R* v, R* grad, hipStream_t st);
+void launch_interp(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
+                   const long long* start, const int* perm, const R* v, R* grad,
+                   hipStream_t st);
 template <class R>
 void launch_fill(R* p, long long n, R v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);

@@ -1,0 +1,75 @@
+// Device-side L-BFGS state machine (see lbfgs.hip).
+#pragma once
+
+#include "common.h"
+
+namespace fresco {
+
+constexpr int kLbfgsMaxM = 16;
+
+// Lives in device memory; the host reads it back between batches of replays.
+struct LbfgsState {
+  int mode;       // 0 normal, 4 = first evaluation of a call
+  int step;       // decision of the last replay (idle / accept / reject / restart / init)
+  int k;          // stored pairs
+  int head;       // ring slot of the newest pair
+  int nbt;        // rejections in the current line search
+  int iter;       // accepted iterations in this call
+  int target;     // iterations requested for this call
+  int nevals;     // evaluations in this call
+  int fail;       // line search failed after a restart
+  int converged;  // gradient RMS below gtol (or zero)
+  int restarted;  // last restart not yet followed by a stored pair
+  int resets;     // history resets
+  double f_cur;   // loss at the current point
+  double f_trial; // loss at the trial point (written by the evaluation)
+  double gtp;     // g . p at the current point
+  double alpha;   // current step length along p
+  double gamma;   // initial inverse-Hessian scaling s.y / y.y of the newest pair
+  double gg;      // g . g at the current point
+  double gnorm_rms;
+  double coefG;   // p = -(coefG g + sum_j coefS_j s_j + coefY_j y_j)
+  double coefS[kLbfgsMaxM];
+  double coefY[kLbfgsMaxM];
+  double SG[kLbfgsMaxM];  // s_j . g
+  double YG[kLbfgsMaxM];  // y_j . g
+  double SY[kLbfgsMaxM * kLbfgsMaxM];  // [i][j] = s_i . y_j (ring slots)
+  double YY[kLbfgsMaxM * kLbfgsMaxM];  // [i][j] = y_i . y_j
+};
+
+struct LbfgsOpts {
+  int m;
+  int max_backtracks;
+  double max_step;  // largest allowed |alpha p_j| per coordinate
+  double c1;        // Armijo constant
+  double shrink;    // backtracking factor
+  double gtol;      // stop when the RMS gradient falls below (0: never)
+};
+
+template <class R>
+struct LbfgsVec {
+  R* x;   // current point (internal order)
+  R* g;   // gradient at x
+  R* p;   // search direction
+  R* xt;  // trial point
+  R* gt;  // gradient at xt
+  R* S;   // m slots of s
+  R* Y;   // m slots of y
+  double* part0;  // block partials of pass A (4 m + 1 slots of nb)
+  double* part1;  // block maxima of pass B (nb)
+  long long n;    // vector length N d
+  int m;
+  int nb;         // blocks of the vector kernels
+};
+
+template <class R>
+void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
+                         hipStream_t st);
+void launch_lbfgs_set_mode(LbfgsState* S, int mode, int target, hipStream_t st);
+template <class R>
+void launch_gather_rows(const R* src, const int* idx, long long n, int d, R* dst, hipStream_t st);
+template <class R>
+void launch_scatter_rows(const R* src, const int* idx, long long n, int d, R* dst,
+                         hipStream_t st);
+
+}  // namespace fresco

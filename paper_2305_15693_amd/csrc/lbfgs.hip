@@ -1,0 +1,433 @@
+// L-BFGS with a maximal step and backtracking line search (main text: the
+// configuration and gradient are fed to L-BFGS, Liu & Nocedal, "with a maximal
+// step size and a backtracking line-search", Nocedal & Wright), as a device-side
+// state machine so that one trial step -- evaluation plus optimiser update -- is
+// a fixed sequence of kernels that is captured in a HIP graph and replayed
+// without host synchronisation.
+//
+// The search direction uses the compact representation of the limited-memory
+// inverse Hessian (Byrd, Nocedal & Schnabel 1994), which needs two streaming
+// passes over the history instead of the 2m dependent passes of the two-loop
+// recursion:
+//   H g = gamma g + S u - gamma Y t,   t = R^-1 (S^T g),
+//   u = R^-T ((D + gamma Y^T Y) t - gamma Y^T g),
+// with S, Y the stored pairs in chronological order, R the upper triangle of
+// S^T Y, D its diagonal and gamma = s.y / y.y of the newest pair.  The m x m
+// products S^T Y and Y^T Y are kept in the state and updated with the new pair.
+//
+// Per replay, after the loss/gradient evaluation at the trial point xt:
+//   decide   Armijo test f(xt) <= f(x) + c1 alpha g.p  -> ACCEPT or REJECT
+//            (REJECT: alpha *= shrink; after max_backtracks rejections the
+//            history is dropped and the search restarts along -g; a second
+//            failure sets the failure flag);
+//   pass A   s = alpha p, y = g(xt) - g(x) into the ring, x = xt, g = g(xt), and
+//            the new dot products s_j.y, y_j.y, s_j.g, y_j.g, g.g;
+//   small    store the pair when y.s > 0, solve for u, t (FP64, one thread);
+//   pass B   p = -(gamma g + S u - gamma Y t), max |p|;
+//   pass C   alpha = min(1, max_step / max|p|), xt = x + alpha p.
+// Vectors are in the working precision; every dot product is accumulated in FP64
+// with a fixed reduction order.
+#include <cmath>
+
+#include "common.h"
+#include "lbfgs.h"
+
+namespace fresco {
+
+enum { LB_IDLE = 0, LB_ACCEPT = 1, LB_REJECT = 2, LB_RESTART = 3, LB_INIT = 4 };
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+#define GRID_LOOP(i, n) \
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+// Reduce `cnt` per-thread values across the block (fixed order) and write them to
+// part[c * nb + blockIdx.x].
+template <int CNT>
+__device__ __forceinline__ void block_partials(double* v, int cnt, double* part, int nb,
+                                               double* sh /* [CNT][kWaves] */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < CNT; ++c) {
+    if (c < cnt) {
+      double x = v[c];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) sh[c * kWaves + wave] = x;
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t += sh[c * kWaves + w];
+    part[(long long)c * nb + blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------- decide
+__global__ void lb_decide_kernel(LbfgsState* S, LbfgsOpts o) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  S->nevals += 1;
+  if (S->mode == LB_INIT) {
+    S->f_cur = S->f_trial;  // first evaluation of a call: take the point as current
+    S->step = LB_INIT;
+    S->nbt = 0;
+    return;
+  }
+  if (S->fail || S->iter >= S->target || S->converged) {
+    S->step = LB_IDLE;
+    return;
+  }
+  const double f = S->f_trial;
+  if (isfinite(f) && f <= S->f_cur + o.c1 * S->alpha * S->gtp) {
+    S->step = LB_ACCEPT;
+    S->f_cur = f;
+    S->iter += 1;
+    S->nbt = 0;
+    return;
+  }
+  S->nbt += 1;
+  if (S->nbt > o.max_backtracks) {
+    if (S->k > 0 || !S->restarted) {
+      S->k = 0;  // drop the history, restart along the steepest descent direction
+      S->restarted = 1;
+      S->resets += 1;
+      S->nbt = 0;
+      S->step = LB_RESTART;
+    } else {
+      S->fail = 1;
+      S->step = LB_IDLE;
+    }
+    return;
+  }
+  S->alpha *= o.shrink;
+  S->step = LB_REJECT;
+}
+
+// ---------------------------------------------------------------- pass A
+// Partial slots: [0, m) s_j.y_new, [m, 2m) y_j.y_new, [2m, 3m) s_j.g, [3m, 4m) y_j.g,
+// 4m g.g (slot j indexes the ring; the new pair's own entries sit at its slot).
+// MM = history length m (compile time, so the accumulators stay in registers)
+template <class R, int MM>
+__global__ void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S) {
+  __shared__ double sh[(4 * MM + 1) * kWaves];
+  const int step = S->step;
+  if (step != LB_ACCEPT && step != LB_INIT) return;
+  const bool acc = (step == LB_ACCEPT);
+  const int ns = (S->head + 1) % MM;  // slot of the new pair
+  const R alpha = (R)S->alpha;
+  // slots holding pairs after this step (the new slot included when accepting)
+  unsigned live = 0;
+  {
+    const int k = S->k;
+    for (int t = 0; t < k; ++t) live |= 1u << ((S->head - t + MM) % MM);
+    if (acc) live |= 1u << ns;
+  }
+  double acc_v[4 * MM + 1];
+#pragma unroll
+  for (int c = 0; c < 4 * MM + 1; ++c) acc_v[c] = 0.0;
+  R* Sn = v.S + (long long)ns * v.n;
+  R* Yn = v.Y + (long long)ns * v.n;
+  GRID_LOOP(i, v.n) {
+    const R gn = v.gt[i];
+    R yy = R(0);
+    if (acc) {
+      const R sy = alpha * v.p[i];
+      yy = gn - v.g[i];
+      Sn[i] = sy;
+      Yn[i] = yy;
+      v.x[i] = v.xt[i];
+    }
+    v.g[i] = gn;
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      if ((live >> j) & 1u) {
+        const R sj = v.S[(long long)j * v.n + i];
+        const R yj = v.Y[(long long)j * v.n + i];
+        if (acc) {
+          acc_v[j] += (double)sj * (double)yy;
+          acc_v[MM + j] += (double)yj * (double)yy;
+        }
+        acc_v[2 * MM + j] += (double)sj * (double)gn;
+        acc_v[3 * MM + j] += (double)yj * (double)gn;
+      }
+    }
+    acc_v[4 * MM] += (double)gn * (double)gn;
+  }
+  block_partials<4 * MM + 1>(acc_v, 4 * MM + 1, v.part0, v.nb, sh);
+}
+
+// ---------------------------------------------------------------- small
+// One block: reduce the partials, update the pair products, solve for the
+// direction coefficients.
+__global__ void lb_small_kernel(LbfgsState* S, LbfgsOpts o, const double* part, int nb,
+                                long long n) {
+  __shared__ double red[4 * kLbfgsMaxM + 1];
+  const int m = o.m;
+  const int step = S->step;
+  const bool dir = (step == LB_ACCEPT || step == LB_INIT || step == LB_RESTART);
+  if (!dir) return;
+  const int cnt = 4 * m + 1;
+  if (step != LB_RESTART) {
+    // every thread sums a strided subset of the block partials of each value, then
+    // the block combines them (fixed order)
+    __shared__ double wsum[kWaves];
+    for (int c = 0; c < cnt; ++c) {
+      double t = 0.0;
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) t += part[(long long)c * nb + b];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+      if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = t;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += wsum[w];
+        red[c] = s;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (step != LB_RESTART) {
+    S->gg = red[4 * m];
+    for (int j = 0; j < m; ++j) {
+      S->SG[j] = red[2 * m + j];
+      S->YG[j] = red[3 * m + j];
+    }
+  }
+  S->gnorm_rms = sqrt(S->gg / (double)n);
+  if (o.gtol > 0.0 && S->gnorm_rms <= o.gtol) S->converged = 1;
+  if (step == LB_ACCEPT) {
+    const int ns = (S->head + 1) % m;
+    const double ys = red[ns], yy = red[m + ns];
+    if (ys > 0.0 && yy > 0.0) {
+      // dropping the oldest pair when the ring is full: its slot is ns
+      for (int j = 0; j < m; ++j) {
+        S->SY[j * kLbfgsMaxM + ns] = red[j];      // s_j . y_new
+        S->YY[j * kLbfgsMaxM + ns] = red[m + j];  // y_j . y_new
+        S->YY[ns * kLbfgsMaxM + j] = red[m + j];
+      }
+      S->head = ns;
+      if (S->k < m) S->k += 1;
+      S->gamma = ys / yy;
+      S->restarted = 0;
+    } else {
+      S->k = 0;  // curvature condition failed: steepest descent
+    }
+  }
+  // chronological slots: c[0] oldest ... c[k-1] newest
+  const int k = S->k;
+  int cs[kLbfgsMaxM];
+  for (int i = 0; i < k; ++i) cs[i] = (S->head - (k - 1) + i + m) % m;
+  for (int j = 0; j < m; ++j) {
+    S->coefS[j] = 0.0;
+    S->coefY[j] = 0.0;
+  }
+  double gtp;
+  if (k == 0) {
+    S->coefG = 1.0;
+    gtp = -S->gg;
+  } else {
+    const double gam = S->gamma;
+    double a[kLbfgsMaxM], b[kLbfgsMaxM], t[kLbfgsMaxM], w[kLbfgsMaxM], u[kLbfgsMaxM];
+    for (int i = 0; i < k; ++i) {
+      a[i] = S->SG[cs[i]];
+      b[i] = S->YG[cs[i]];
+    }
+    // R t = a, R_ij = s_i . y_j (i <= j), upper triangular
+    for (int i = k - 1; i >= 0; --i) {
+      double r = a[i];
+      for (int j = i + 1; j < k; ++j) r -= S->SY[cs[i] * kLbfgsMaxM + cs[j]] * t[j];
+      t[i] = r / S->SY[cs[i] * kLbfgsMaxM + cs[i]];
+    }
+    // w = (D + gamma Y^T Y) t - gamma b
+    for (int i = 0; i < k; ++i) {
+      double r = S->SY[cs[i] * kLbfgsMaxM + cs[i]] * t[i] - gam * b[i];
+      for (int j = 0; j < k; ++j) r += gam * S->YY[cs[i] * kLbfgsMaxM + cs[j]] * t[j];
+      w[i] = r;
+    }
+    // R^T u = w, lower triangular
+    for (int i = 0; i < k; ++i) {
+      double r = w[i];
+      for (int j = 0; j < i; ++j) r -= S->SY[cs[j] * kLbfgsMaxM + cs[i]] * u[j];
+      u[i] = r / S->SY[cs[i] * kLbfgsMaxM + cs[i]];
+    }
+    double ua = 0.0, tb = 0.0;
+    for (int i = 0; i < k; ++i) {
+      S->coefS[cs[i]] = u[i];
+      S->coefY[cs[i]] = -gam * t[i];
+      ua += u[i] * a[i];
+      tb += t[i] * b[i];
+    }
+    S->coefG = gam;
+    gtp = -(gam * S->gg + ua - gam * tb);
+    if (!(gtp < 0.0) || !isfinite(gtp)) {
+      // not a descent direction: drop the history, steepest descent
+      S->k = 0;
+      S->resets += 1;
+      for (int j = 0; j < m; ++j) {
+        S->coefS[j] = 0.0;
+        S->coefY[j] = 0.0;
+      }
+      S->coefG = 1.0;
+      gtp = -S->gg;
+    }
+  }
+  S->gtp = gtp;
+  if (!(gtp < 0.0)) {
+    S->converged = 1;  // zero gradient
+    S->step = LB_IDLE;
+  }
+}
+
+// ---------------------------------------------------------------- pass B
+template <class R, int MM>
+__global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
+  __shared__ double sh[kWaves];
+  const int step = S->step;
+  if (step != LB_ACCEPT && step != LB_INIT && step != LB_RESTART) return;
+  const int k = S->k;
+  // coefficients by slot; slots without a pair have coefficient 0 and are skipped
+  R cS[MM], cY[MM];
+  unsigned live = 0;
+#pragma unroll
+  for (int j = 0; j < MM; ++j) {
+    cS[j] = (R)S->coefS[j];
+    cY[j] = (R)S->coefY[j];
+  }
+  for (int t = 0; t < k; ++t) live |= 1u << ((S->head - t + MM) % MM);
+  const R cg = (R)S->coefG;
+  double pm = 0.0;
+  GRID_LOOP(j, v.n) {
+    R r = cg * v.g[j];
+#pragma unroll
+    for (int i = 0; i < MM; ++i) {
+      if ((live >> i) & 1u) {
+        r += cS[i] * v.S[(long long)i * v.n + j];
+        r += cY[i] * v.Y[(long long)i * v.n + j];
+      }
+    }
+    v.p[j] = -r;
+    pm = fmax(pm, fabs((double)r));
+  }
+  for (int off = 32; off > 0; off >>= 1) pm = fmax(pm, __shfl_down(pm, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t = fmax(t, sh[w]);
+    v.part1[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------- pass C
+// step length of a new direction, then the trial point
+template <class R>
+__global__ void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
+  __shared__ double sh[kWaves];
+  __shared__ double alpha_s;
+  const int step = S->step;
+  if (step == LB_IDLE) return;
+  if (step == LB_REJECT) {
+    if (threadIdx.x == 0) alpha_s = S->alpha;
+  } else {
+    double pm = 0.0;
+    for (int b = threadIdx.x; b < v.nb; b += blockDim.x) pm = fmax(pm, v.part1[b]);
+    for (int off = 32; off > 0; off >>= 1) pm = fmax(pm, __shfl_down(pm, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kWaves; ++w) t = fmax(t, sh[w]);
+      const double a = (t > o.max_step) ? o.max_step / t : 1.0;
+      alpha_s = a;
+      if (blockIdx.x == 0) S->alpha = a;
+    }
+  }
+  __syncthreads();
+  const R alpha = (R)alpha_s;
+  GRID_LOOP(j, v.n) v.xt[j] = v.x[j] + alpha * v.p[j];
+}
+
+// set the mode read by the next decision (host-driven transitions)
+__global__ void lb_set_mode_kernel(LbfgsState* S, int mode, int target) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    S->mode = mode;
+    if (target >= 0) {
+      S->target = target;
+      S->iter = 0;
+      S->nevals = 0;
+      S->fail = 0;
+      S->converged = 0;
+    }
+  }
+}
+
+template <class R>
+void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
+                         hipStream_t st) {
+  lb_decide_kernel<<<1, 64, 0, st>>>(S, o);
+#define LB_A(MM) lb_pass_a_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S)
+#define LB_B(MM) lb_pass_b_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S)
+#define LB_SWITCH(CALL)                                                        \
+  switch (v.m) {                                                               \
+    case 1: CALL(1); break;   case 2: CALL(2); break;   case 3: CALL(3); break;   \
+    case 4: CALL(4); break;   case 5: CALL(5); break;   case 6: CALL(6); break;   \
+    case 7: CALL(7); break;   case 8: CALL(8); break;   case 9: CALL(9); break;   \
+    case 10: CALL(10); break; case 11: CALL(11); break; case 12: CALL(12); break; \
+    case 13: CALL(13); break; case 14: CALL(14); break; case 15: CALL(15); break; \
+    case 16: CALL(16); break;                                                  \
+  }
+  LB_SWITCH(LB_A)
+  lb_small_kernel<<<1, 256, 0, st>>>(S, o, v.part0, v.nb, v.n);
+  LB_SWITCH(LB_B)
+#undef LB_SWITCH
+#undef LB_B
+#undef LB_A
+  lb_pass_c_kernel<R><<<v.nb, kThreads, 0, st>>>(v, S, o);
+}
+
+void launch_lbfgs_set_mode(LbfgsState* S, int mode, int target, hipStream_t st) {
+  lb_set_mode_kernel<<<1, 64, 0, st>>>(S, mode, target);
+}
+
+// ------------------------------------------------------- permutations
+template <class R>
+__global__ void gather_rows_kernel(const R* __restrict__ src, const int* __restrict__ idx,
+                                   long long n, int d, R* __restrict__ dst) {
+  GRID_LOOP(j, n) {
+    const long long s = (long long)idx[j] * d;
+    for (int a = 0; a < d; ++a) dst[j * d + a] = src[s + a];
+  }
+}
+template <class R>
+__global__ void scatter_rows_kernel(const R* __restrict__ src, const int* __restrict__ idx,
+                                    long long n, int d, R* __restrict__ dst) {
+  GRID_LOOP(j, n) {
+    const long long s = (long long)idx[j] * d;
+    for (int a = 0; a < d; ++a) dst[s + a] = src[j * d + a];
+  }
+}
+template <class R>
+void launch_gather_rows(const R* src, const int* idx, long long n, int d, R* dst, hipStream_t st) {
+  long long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  gather_rows_kernel<R><<<(unsigned)b, 256, 0, st>>>(src, idx, n, d, dst);
+}
+template <class R>
+void launch_scatter_rows(const R* src, const int* idx, long long n, int d, R* dst,
+                         hipStream_t st) {
+  long long b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  scatter_rows_kernel<R><<<(unsigned)b, 256, 0, st>>>(src, idx, n, d, dst);
+}
+
+#define FRESCO_LB_INST(R)                                                                       \
+  template void launch_lbfgs_update<R>(const LbfgsVec<R>&, LbfgsState*, const LbfgsOpts&,       \
+                                       hipStream_t);                                            \
+  template void launch_gather_rows<R>(const R*, const int*, long long, int, R*, hipStream_t);   \
+  template void launch_scatter_rows<R>(const R*, const int*, long long, int, R*, hipStream_t);
+FRESCO_LB_INST(float)
+FRESCO_LB_INST(double)
+
+}  // namespace fresco

@@ -89,6 +89,54 @@ std::vector<double> kernel_fourier(int nmax, int w, double beta, int nf, bool co
   return out;
 }
 
+static double kernel_value(double z, double beta, int kind) {
+  const double s2 = (1.0 - z) * (1.0 + z);
+  if (s2 < 0.0) return 0.0;
+  const double s = std::sqrt(s2);
+  if (kind == 0) return std::exp(beta * (s - 1.0));
+  const double cb = std::cosh(beta);
+  if (kind == 1) return std::cosh(beta * s) / cb;
+  const double bs = beta * s;
+  const double shs = (bs > 1e-6) ? std::sinh(bs) / s : beta * (1.0 + bs * bs / 6.0);
+  return -beta * z * shs / cb;
+}
+
+std::vector<double> kernel_poly(int w, double beta, int kind, int deg) {
+  const int np = deg + 1;
+  std::vector<double> out((size_t)w * np, 0.0);
+  std::vector<double> xk(np), fk(np), a(np);
+  for (int k = 0; k < np; ++k) xk[k] = std::cos(M_PI * (k + 0.5) / np);
+  for (int j = 0; j < w; ++j) {
+    for (int k = 0; k < np; ++k) {
+      const double tau = 0.5 * (xk[k] + 1.0);
+      const double z = (tau - 0.5 * w + j) * 2.0 / w;
+      fk[k] = kernel_value(z, beta, kind);
+    }
+    // Chebyshev coefficients of the interpolant
+    for (int m = 0; m < np; ++m) {
+      double s = 0.0;
+      for (int k = 0; k < np; ++k) s += fk[k] * std::cos(M_PI * m * (k + 0.5) / np);
+      a[m] = s * 2.0 / np;
+    }
+    a[0] *= 0.5;
+    // sum a_m T_m(x) -> monomials, T_{m+1} = 2 x T_m - T_{m-1}
+    std::vector<double> tm1(np, 0.0), tm(np, 0.0), tn(np, 0.0), c(np, 0.0);
+    tm1[0] = 1.0;  // T_0
+    if (np > 1) tm[1] = 1.0;  // T_1
+    for (int k = 0; k < np; ++k) c[k] += a[0] * tm1[k];
+    if (np > 1)
+      for (int k = 0; k < np; ++k) c[k] += a[1] * tm[k];
+    for (int m = 2; m < np; ++m) {
+      for (int k = 0; k < np; ++k) tn[k] = -tm1[k] + ((k > 0) ? 2.0 * tm[k - 1] : 0.0);
+      for (int k = 0; k < np; ++k) c[k] += a[m] * tn[k];
+      tm1 = tm;
+      tm = tn;
+    }
+    for (int k = 0; k < np; ++k) out[(size_t)j * np + k] = c[k];
+  }
+  return out;
+}
+
 bool plan_factors(int n, FftFactors* F, int* rmin) {
   int fac[64];
   int nf = 0;

@@ -23,6 +23,14 @@ double kernel_beta(int w);
 // cosh_form its even-in-sqrt(1 - z^2) variant cosh(beta sqrt(1 - z^2)) / cosh(beta).
 std::vector<double> kernel_fourier(int nmax, int w, double beta, int nf, bool cosh_form);
 
+// Piecewise-polynomial form of a kernel for fast evaluation.  For a point with
+// footprint offset tau in [0, 1) (tau = t + w/2), the value on footprint cell j is
+// phi(z_j), z_j = (tau - w/2 + j) 2 / w.  Returns, for each j, the monomial
+// coefficients c[j][0..deg] of the degree-deg Chebyshev interpolant of phi(z_j)
+// in x = 2 tau - 1 (row-major, w x (deg + 1)).
+// kind: 0 exponential of semicircle, 1 cosh form, 2 derivative d/dz of the cosh form.
+std::vector<double> kernel_poly(int w, double beta, int kind, int deg);
+
 // radix plan of a complex FFT of length n (radices 2, 3, 4, 5); false if n has
 // another prime factor or needs too many stages
 bool plan_factors(int n, FftFactors* F, int* rmin);

@@ -76,6 +76,46 @@ __device__ __forceinline__ void cosh_kernel_d(R z, R beta, R inv_cosh_beta, R* f
   *df = -beta * z * shs * inv_cosh_beta;
 }
 
+// Kernel values on the W footprint cells of one axis from tau in [0, 1):
+// FP32 evaluates the per-cell polynomials (x = 2 tau - 1), FP64 the closed forms.
+template <int W>
+__device__ __forceinline__ float poly_eval(const float (&c)[kPolyDeg + 1], float x) {
+  float r = c[kPolyDeg];
+#pragma unroll
+  for (int k = kPolyDeg - 1; k >= 0; --k) r = fmaf(r, x, c[k]);
+  return r;
+}
+template <class R, int W>
+__device__ __forceinline__ void spread_weights(const KernelPolys& kp, R tau, R beta, R* k) {
+  if constexpr (sizeof(R) == 4) {
+    const float x = 2.f * tau - 1.f;
+#pragma unroll
+    for (int i = 0; i < W; ++i) k[i] = poly_eval<W>(kp.sp[i], x);
+  } else {
+    const R hw = R(2) / R(W);
+#pragma unroll
+    for (int i = 0; i < W; ++i) k[i] = es_kernel<R>((tau - R(0.5) * R(W) + R(i)) * hw, beta);
+  }
+}
+// interpolation kernel (width WI) and its z-derivative
+template <class R, int WI>
+__device__ __forceinline__ void interp_weights(const KernelPolys& kp, R tau, R beta, R icb,
+                                               R* f, R* df) {
+  if constexpr (sizeof(R) == 4) {
+    const float x = 2.f * tau - 1.f;
+#pragma unroll
+    for (int i = 0; i < WI; ++i) {
+      f[i] = poly_eval<WI>(kp.ip[i], x);
+      df[i] = poly_eval<WI>(kp.id[i], x);
+    }
+  } else {
+    const R hw = R(2) / R(WI);
+#pragma unroll
+    for (int i = 0; i < WI; ++i)
+      cosh_kernel_d<R>((tau - R(0.5) * R(WI) + R(i)) * hw, beta, icb, f + i, df + i);
+  }
+}
+
 // ------------------------------------------------------------------ fill
 template <class T>
 __global__ void fill_kernel(T* p, long long n, T v) {
@@ -117,11 +157,13 @@ __device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* b
       *bad = true;
       u = 0.0;
     }
-    u = fmod(u, nf);
-    if (u < 0.0) u += nf;
-    if (u >= nf) u = 0.0;
+    if (!(u >= 0.0 && u < nf)) {  // outside the box: exact periodic reduction
+      u = fmod(u, nf);
+      if (u < 0.0) u += nf;
+      if (u >= nf) u = 0.0;
+    }
     double l0 = ceil(u - 0.5 * g.w);
-    pb.t[a] = l0 - u;
+    pb.t[a] = l0 - u + 0.5 * g.w;  // tau in [0, 1)
     int li = (int)l0;
     if (li < 0) li += g.nf[a];
     if (li >= g.nf[a]) li -= g.nf[a];
@@ -347,7 +389,7 @@ __device__ __forceinline__ void add_row_pairs(uint32_t* acc, int rb, const uint3
 }
 
 template <class R, int D, int W>
-__global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
+__global__ void spread_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, R* __restrict__ tiles) {
   constexpr bool F32 = sizeof(R) == 4;
   extern __shared__ unsigned long long smem_u64[];
@@ -369,18 +411,14 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const int ex = fixed_exponent(e - s, F32 ? 31 : 63);
   const R scale = (R)ldexp(1.0, ex);
   const R inv_scale = (R)ldexp(1.0, -ex);
-  const R half_w_inv = R(2) / R(W);
   const R beta = (R)g.beta;
   __syncthreads();
   for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
     const Rec<R> p = rec[j];
     R k0[W], k1[W], k2[W];
-#pragma unroll
-    for (int i = 0; i < W; ++i) {
-      k0[i] = es_kernel<R>((p.t[0] + R(i)) * half_w_inv, beta);
-      k1[i] = es_kernel<R>((p.t[1] + R(i)) * half_w_inv, beta);
-      if (D == 3) k2[i] = es_kernel<R>((p.t[2] + R(i)) * half_w_inv, beta);
-    }
+    spread_weights<R, W>(kp, p.t[0], beta, k0);
+    spread_weights<R, W>(kp, p.t[1], beta, k1);
+    if (D == 3) spread_weights<R, W>(kp, p.t[2], beta, k2);
     const int l0 = p.cell & 0xff, l1 = (p.cell >> 8) & 0xff, l2 = (p.cell >> 16) & 0xff;
     const int zmax = (D == 3) ? W : 1;
     for (int dz = 0; dz < zmax; ++dz) {
@@ -443,7 +481,7 @@ __global__ void fold_kernel(Geom g, FoldTables ft, const R* __restrict__ tiles,
 // Field tile origin is one cell before the spreading tile (width w + 1), extent
 // T + w + 1 per axis (g.Ei).
 template <class R, int D, int W>
-__global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
+__global__ void interp_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, const int* __restrict__ perm,
                               const R* __restrict__ v, R* __restrict__ grad) {
   constexpr int WI = W + 1;
@@ -471,10 +509,8 @@ __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
     sub[c] = v[((long long)z * g.nf[1] + y) * g.nf[0] + x];
   }
   __syncthreads();
-  const R half_w_inv = R(2) / R(WI);
   const R beta = (R)g.beta_i;
   const R icb = (R)(1.0 / cosh(g.beta_i));
-  const R lim = R(0.5) - R(W) * R(0.5);  // t >= lim: footprint of width W+1 starts one earlier
   R gs[3];
   for (int a = 0; a < 3; ++a) gs[a] = (a < D) ? (R)(-(double)g.nf[a] / g.L[a] * 2.0 / WI) : R(0);
   for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
@@ -483,16 +519,16 @@ __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
     int l[3];
     const int cl[3] = {(int)(p.cell & 0xff), (int)((p.cell >> 8) & 0xff),
                        (int)((p.cell >> 16) & 0xff)};
+    // footprint of width W + 1: tau_i = tau + 1/2 starting at l0 (tau < 1/2), or
+    // tau - 1/2 starting one cell earlier
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const int k = (p.t[a] >= lim) ? 1 : 0;
-      const R ti = p.t[a] - (R)k;
+      const int k = (p.t[a] >= R(0.5)) ? 1 : 0;
+      const R ti = k ? p.t[a] - R(0.5) : p.t[a] + R(0.5);
       l[a] = cl[a] - k + 1;
-      R* f = a == 0 ? f0 : (a == 1 ? f1 : f2);
-      R* df = a == 0 ? d0 : (a == 1 ? d1 : d2);
-#pragma unroll
-      for (int i = 0; i < WI; ++i)
-        cosh_kernel_d<R>((ti + R(i)) * half_w_inv, beta, icb, f + i, df + i);
+      if (a == 0) interp_weights<R, WI>(kp, ti, beta, icb, f0, d0);
+      else if (a == 1) interp_weights<R, WI>(kp, ti, beta, icb, f1, d1);
+      else interp_weights<R, WI>(kp, ti, beta, icb, f2, d2);
     }
     R gx = R(0), gy = R(0), gz = R(0);
     const int zmax = (D == 3) ? WI : 1;
@@ -583,16 +619,18 @@ void spread_prepare(const Geom& g) {
 }
 
 template <class R>
-void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* tiles,
-                   hipStream_t st) {
+void launch_spread(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
+                   const long long* start, R* tiles, hipStream_t st) {
   const size_t lds = spread_lds_bytes<R>(g);
   const int threads = (g.d == 3) ? 512 : 256;
-#define SP(W)                                                                               \
-  do {                                                                                      \
-    if (g.d == 2)                                                                           \
-      spread_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, tiles); \
-    else                                                                                    \
-      spread_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, tiles); \
+#define SP(W)                                                                                 \
+  do {                                                                                        \
+    if (g.d == 2)                                                                             \
+      spread_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, kp, rec, start,      \
+                                                                      tiles);                 \
+    else                                                                                      \
+      spread_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, kp, rec, start,      \
+                                                                      tiles);                 \
   } while (0)
   FRESCO_W_SWITCH(g.w, SP)
 #undef SP
@@ -607,18 +645,19 @@ void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, h
 }
 
 template <class R>
-void launch_interp(const Geom& g, const Rec<R>* rec, const long long* start, const int* perm,
-                   const R* v, R* grad, hipStream_t st) {
+void launch_interp(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
+                   const long long* start, const int* perm, const R* v, R* grad,
+                   hipStream_t st) {
   const size_t lds = interp_lds_bytes<R>(g);
   const int threads = (g.d == 3) ? 512 : 256;
-#define IP(W)                                                                                  \
-  do {                                                                                         \
-    if (g.d == 2)                                                                              \
-      interp_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, perm, v, \
-                                                                      grad);                   \
-    else                                                                                       \
-      interp_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, perm, v, \
-                                                                      grad);                   \
+#define IP(W)                                                                                 \
+  do {                                                                                        \
+    if (g.d == 2)                                                                             \
+      interp_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, kp, rec, start,      \
+                                                                      perm, v, grad);         \
+    else                                                                                      \
+      interp_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, kp, rec, start,      \
+                                                                      perm, v, grad);         \
   } while (0)
   FRESCO_W_SWITCH(g.w, IP)
 #undef IP
@@ -630,17 +669,19 @@ template size_t interp_lds_bytes<float>(const Geom&);
 template size_t interp_lds_bytes<double>(const Geom&);
 template void spread_prepare<float>(const Geom&);
 template void spread_prepare<double>(const Geom&);
-template void launch_spread<float>(const Geom&, const Rec<float>*, const long long*, float*,
-                                   hipStream_t);
-template void launch_spread<double>(const Geom&, const Rec<double>*, const long long*, double*,
-                                    hipStream_t);
+template void launch_spread<float>(const Geom&, const KernelPolys&, const Rec<float>*,
+                                   const long long*, float*, hipStream_t);
+template void launch_spread<double>(const Geom&, const KernelPolys&, const Rec<double>*,
+                                    const long long*, double*, hipStream_t);
 template void launch_fold<float>(const Geom&, const float*, float*, const FoldTables&,
                                  hipStream_t);
 template void launch_fold<double>(const Geom&, const double*, double*, const FoldTables&,
                                   hipStream_t);
-template void launch_interp<float>(const Geom&, const Rec<float>*, const long long*, const int*,
-                                   const float*, float*, hipStream_t);
-template void launch_interp<double>(const Geom&, const Rec<double>*, const long long*,
-                                    const int*, const double*, double*, hipStream_t);
+template void launch_interp<float>(const Geom&, const KernelPolys&, const Rec<float>*,
+                                   const long long*, const int*, const float*, float*,
+                                   hipStream_t);
+template void launch_interp<double>(const Geom&, const KernelPolys&, const Rec<double>*,
+                                    const long long*, const int*, const double*, double*,
+                                    hipStream_t);
 
 }  // namespace fresco

@@ -65,6 +65,17 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class LbfgsOpts(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int32),
+        ("max_backtracks", ctypes.c_int32),
+        ("max_step", ctypes.c_double),
+        ("c1", ctypes.c_double),
+        ("shrink", ctypes.c_double),
+        ("gtol", ctypes.c_double),
+    ]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2305_15693_amd.build")
@@ -83,6 +94,11 @@ def _load():
     lib.fresco_loss_grad.restype = i
     lib.fresco_loss_grad_async.argtypes = [vp, vp, vp, vp]
     lib.fresco_loss_grad_async.restype = i
+    lib.fresco_step.argtypes = [vp, vp, ctypes.POINTER(LbfgsOpts), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    lib.fresco_step.restype = i
+    lib.fresco_reset_history.argtypes = [vp]
+    lib.fresco_reset_history.restype = i
     lib.fresco_set_timing.argtypes = [vp, ctypes.c_uint32]
     lib.fresco_set_timing.restype = i
     lib.fresco_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -185,6 +201,29 @@ class Context:
                     kmax=list(info.kmax)[:d], width=info.width, beta=info.beta,
                     tile=list(info.tile)[:d], nbins=info.nbins,
                     n_constrained=info.n_constrained, device_bytes=info.device_bytes)
+
+    def default_max_step(self) -> float:
+        """0.1 of the mean interparticle spacing L / N^(1/d) (smallest side)."""
+        return 0.1 * min(self.box) / self.n ** (1.0 / self.dim)
+
+    def step(self, pos, n_iter: int, *, m: int = 8, max_step: float = None, c1: float = 1e-4,
+             shrink: float = 0.5, max_backtracks: int = 20, gtol: float = 0.0):
+        """n_iter L-BFGS iterations on pos (updated in place).  Returns (loss, evaluations)."""
+        o = LbfgsOpts()
+        o.m = m
+        o.max_backtracks = max_backtracks
+        o.max_step = self.default_max_step() if max_step is None else float(max_step)
+        o.c1 = c1
+        o.shrink = shrink
+        o.gtol = gtol
+        loss = ctypes.c_double(0.0)
+        nev = ctypes.c_int32(0)
+        _check(_lib.fresco_step(self._h, self._pos(pos), ctypes.byref(o), int(n_iter),
+                                ctypes.byref(loss), ctypes.byref(nev)), "fresco_step")
+        return float(loss.value), int(nev.value)
+
+    def reset_history(self):
+        _check(_lib.fresco_reset_history(self._h), "fresco_reset_history")
 
     def set_timing(self, stages):
         """Bracket the named stages (see STAGES) with HIP events; [] turns it off."""

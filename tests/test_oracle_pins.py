@@ -241,3 +241,45 @@ def test_chi_K_printed_values():
         chi = _lattice_count(d, K) / (2.0 * d * N)
         # a 1% band covers the rounding of K to an integer (dchi/chi = d dK/K)
         assert abs(chi - 0.4) < 0.004 + 0.4 * d * 0.5 / K, (d, N, K, chi)
+
+
+def test_lbfgs_oracle_on_a_quadratic():
+    # On a convex quadratic f = x.A x / 2 - b.x, L-BFGS with an exact-enough line
+    # search converges to A^-1 b; the first step is the clamped steepest-descent
+    # step accepted by the Armijo test.
+    from oracle import lbfgs as LB
+    rng = np.random.default_rng(2)
+    n = 12
+    Q = rng.normal(size=(n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.normal(size=n)
+
+    def fg(x):
+        return 0.5 * x @ A @ x - b @ x, A @ x - b
+
+    x0 = np.zeros(n)
+    r = LB.run(fg, x0, 1, m=5, max_step=1e-3)
+    g0 = -b
+    p = -g0
+    alpha = 1e-3 / np.max(np.abs(p))
+    np.testing.assert_allclose(r["xs"][1], x0 + alpha * p, rtol=1e-14)
+    r = LB.run(fg, x0, 200, m=5, max_step=10.0, gtol=1e-9)
+    np.testing.assert_allclose(r["x"], np.linalg.solve(A, b), rtol=1e-7, atol=1e-9)
+    assert all(f2 <= f1 for f1, f2 in zip(r["fs"], r["fs"][1:]))
+
+
+def test_lbfgs_oracle_decreases_structure_factor_loss():
+    from oracle import lbfgs as LB
+    N, L, M = 64, 8.0, 3
+    pos = I.positions(N, 2, L, np.float64, seed=4)
+    modes = _modes_ball(2, 3.0)
+    W = np.ones(len(modes))
+    S0 = np.zeros(len(modes))
+
+    def fg(x):
+        r = O.loss_grad(x.reshape(N, 2), L, modes, W, S0)
+        return r["loss"], r["grad"].ravel()
+
+    r = LB.run(fg, pos, 10, m=8, max_step=0.1 * L / np.sqrt(N))
+    assert r["fs"][-1] < 0.5 * r["fs"][0]
+    assert all(f2 <= f1 for f1, f2 in zip(r["fs"], r["fs"][1:]))
