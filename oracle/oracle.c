@@ -278,3 +278,219 @@ int oracle_fd(int d, long long N, const double* L, const double* pos, long long 
   free(rho);
   return fail ? OR_ENOMEM : OR_OK;
 }
+
+/*
+ * Vector-Jacobian product of the structure factor (the derivative of S with
+ * respect to a position, Methods, "Analytical gradients"):
+ *   dS(k)/dr_ja = (2/N) Re[conj(rho(k)) i k_a exp(i k.r_j)]
+ *               = (2 k_a / N) (Im rho Re e - Re rho Im e),   e = exp(i k.r_j),
+ *   grad_ja     = sum_{listed k} gS(k) dS(k)/dr_ja.
+ *   gS          : [K] weights of the listed modes
+ *   G, gidx     : points wanted (gidx NULL: points 0..G-1); grad_out [G][d]
+ */
+int oracle_sf_vjp(int d, long long N, const double* L, const double* pos, long long K,
+                  const int* modes, const double* gS, long long G, const long long* gidx,
+                  double* grad_out) {
+  if (d < 1 || d > 3 || N <= 0 || K < 0 || !L || !pos || (K && (!modes || !gS)))
+    return OR_EINVAL;
+  if (G < 0 || (G && !grad_out)) return OR_EINVAL;
+  double* rho = (double*)malloc(sizeof(double) * 2 * (K ? K : 1));
+  if (!rho) return OR_ENOMEM;
+  int st = oracle_rho(d, N, L, pos, K, modes, rho);
+  if (st) { free(rho); return st; }
+  int M[3];
+  mode_extent(d, K, modes, M);
+  long long off[3], tlen = 0;
+  for (int a = 0; a < d; ++a) { off[a] = tlen; tlen += 2 * M[a] + 1; }
+  int fail = 0;
+#pragma omp parallel
+  {
+    double* tab = (double*)malloc(sizeof(double) * 2 * tlen);
+    if (!tab) {
+#pragma omp atomic write
+      fail = 1;
+    } else {
+#pragma omp for schedule(dynamic, 16)
+      for (long long g = 0; g < G; ++g) {
+        long long j = gidx ? gidx[g] : g;
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (j >= 0 && j < N) {
+          point_table(d, L, pos + j * d, M, off, tab);
+          for (long long q = 0; q < K; ++q) {
+            double er, ei;
+            mode_exp(d, modes + q * d, M, off, tab, &er, &ei);
+            const double im = rho[2 * q + 1] * er - rho[2 * q] * ei;
+            for (int a = 0; a < d; ++a) {
+              double ka = TWO_PI * (double)modes[q * d + a] / L[a];
+              acc[a] += gS[q] * 2.0 * ka / (double)N * im;
+            }
+          }
+        }
+        for (int a = 0; a < d; ++a) grad_out[g * d + a] = acc[a];
+      }
+      free(tab);
+    }
+  }
+  free(rho);
+  return fail ? OR_ENOMEM : OR_OK;
+}
+
+/*
+ * Soft-core pair repulsion (the short-range term added to the spectral loss
+ * for packings, Results, "Stealthy hyperuniform packings"):
+ *   U(r) = (eps / alpha) (1 - r / sigma)^alpha  for r < sigma, else 0,
+ *   E    = sum_{i<j} U(|r_i - r_j|),  distances under the minimum image
+ *          convention of the periodic box (requires sigma < L_a / 2),
+ *   dE/dr_i = sum_{j != i} U'(r_ij) (r_i - r_j) / r_ij,
+ *   U'(r) = -(eps / sigma) (1 - r / sigma)^(alpha - 1).
+ * Coincident points (r = 0) have no direction and contribute energy only.
+ *
+ * oracle_pair        : brute force over all pairs, O(N^2).
+ * oracle_pair_cells  : the same sums over a cell list (cells of side >= sigma),
+ *                      for large N; checked against the brute force in tests.
+ * Both write energy (scalar) and grad [N][d]; each point's sum runs over its
+ * partners in increasing index order.
+ */
+static inline double min_image(double x, double L) { return x - L * nearbyint(x / L); }
+
+static inline void pair_term(int d, const double* L, const double* ri, const double* rj,
+                             double sigma, double eps, double alpha, double* u, double* g) {
+  double dx[3], r2 = 0.0;
+  for (int a = 0; a < d; ++a) {
+    dx[a] = min_image(ri[a] - rj[a], L[a]);
+    r2 += dx[a] * dx[a];
+  }
+  *u = 0.0;
+  for (int a = 0; a < d; ++a) g[a] = 0.0;
+  if (r2 >= sigma * sigma) return;
+  double r = sqrt(r2);
+  double x = 1.0 - r / sigma;
+  *u = eps / alpha * pow(x, alpha);
+  if (r > 0.0) {
+    double du = -eps / sigma * pow(x, alpha - 1.0);
+    for (int a = 0; a < d; ++a) g[a] = du * dx[a] / r;
+  }
+}
+
+static int pair_check(int d, long long N, const double* L, const double* pos, double sigma,
+                      double alpha) {
+  if (d < 1 || d > 3 || N < 0 || !L || (N && !pos) || !(sigma > 0.0) || !(alpha >= 1.0))
+    return OR_EINVAL;
+  for (int a = 0; a < d; ++a)
+    if (!(L[a] > 2.0 * sigma)) return OR_EINVAL;
+  return OR_OK;
+}
+
+int oracle_pair(int d, long long N, const double* L, const double* pos, double sigma, double eps,
+                double alpha, double* energy, double* grad) {
+  int st = pair_check(d, N, L, pos, sigma, alpha);
+  if (st) return st;
+  double e = 0.0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : e)
+  for (long long i = 0; i < N; ++i) {
+    double acc[3] = {0.0, 0.0, 0.0}, ei = 0.0;
+    for (long long j = 0; j < N; ++j) {
+      if (j == i) continue;
+      double u, g[3];
+      pair_term(d, L, pos + i * d, pos + j * d, sigma, eps, alpha, &u, g);
+      ei += u;
+      for (int a = 0; a < d; ++a) acc[a] += g[a];
+    }
+    e += 0.5 * ei;
+    if (grad)
+      for (int a = 0; a < d; ++a) grad[i * d + a] = acc[a];
+  }
+  if (energy) *energy = e;
+  return OR_OK;
+}
+
+static int cmp_ll(const void* a, const void* b) {
+  long long x = *(const long long*)a, y = *(const long long*)b;
+  return (x > y) - (x < y);
+}
+
+int oracle_pair_cells(int d, long long N, const double* L, const double* pos, double sigma,
+                      double eps, double alpha, double* energy, double* grad) {
+  int st = pair_check(d, N, L, pos, sigma, alpha);
+  if (st) return st;
+  long long nc[3] = {1, 1, 1}, ncell = 1;
+  for (int a = 0; a < d; ++a) {
+    nc[a] = (long long)floor(L[a] / sigma);
+    if (nc[a] < 1) nc[a] = 1;
+    ncell *= nc[a];
+  }
+  long long* cell = (long long*)malloc(sizeof(long long) * (N ? N : 1));
+  long long* head = (long long*)calloc((size_t)ncell + 1, sizeof(long long));
+  long long* list = (long long*)malloc(sizeof(long long) * (N ? N : 1));
+  if (!cell || !head || !list) { free(cell); free(head); free(list); return OR_ENOMEM; }
+  for (long long i = 0; i < N; ++i) {
+    long long c = 0;
+    for (int a = d - 1; a >= 0; --a) {
+      double u = pos[i * d + a] - L[a] * floor(pos[i * d + a] / L[a]);
+      long long k = (long long)floor(u / L[a] * (double)nc[a]);
+      if (k < 0) k = 0;
+      if (k >= nc[a]) k = nc[a] - 1;
+      c = c * nc[a] + k;
+    }
+    cell[i] = c;
+    head[c + 1]++;
+  }
+  for (long long c = 0; c < ncell; ++c) head[c + 1] += head[c];
+  {
+    long long* fill = (long long*)malloc(sizeof(long long) * (size_t)ncell);
+    if (!fill) { free(cell); free(head); free(list); return OR_ENOMEM; }
+    memcpy(fill, head, sizeof(long long) * (size_t)ncell);
+    for (long long i = 0; i < N; ++i) list[fill[cell[i]]++] = i;  /* increasing i per cell */
+    free(fill);
+  }
+  double e = 0.0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : e)
+  for (long long i = 0; i < N; ++i) {
+    long long ci[3] = {0, 0, 0}, c = cell[i];
+    for (int a = 0; a < d; ++a) { ci[a] = c % nc[a]; c /= nc[a]; }
+    /* distinct neighbour cells (fewer than 3 per axis when the box is narrow) */
+    long long nbr[27];
+    int nn = 0;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = (a < d) ? -1 : 0;
+      hi[a] = (a < d) ? 1 : 0;
+      if (a < d && nc[a] == 1) lo[a] = hi[a] = 0;
+      if (a < d && nc[a] == 2) { lo[a] = 0; hi[a] = 1; }
+    }
+    for (int oz = lo[2]; oz <= hi[2]; ++oz)
+      for (int oy = lo[1]; oy <= hi[1]; ++oy)
+        for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+          int o[3] = {ox, oy, oz};
+          long long q = 0;
+          for (int a = d - 1; a >= 0; --a) q = q * nc[a] + (ci[a] + o[a] + nc[a]) % nc[a];
+          nbr[nn++] = q;
+        }
+    /* partners in increasing index order, as the brute force visits them */
+    long long cand_n = 0;
+    for (int t = 0; t < nn; ++t) cand_n += head[nbr[t] + 1] - head[nbr[t]];
+    long long* cand = (long long*)malloc(sizeof(long long) * (cand_n ? cand_n : 1));
+    long long m = 0;
+    for (int t = 0; t < nn; ++t)
+      for (long long s = head[nbr[t]]; s < head[nbr[t] + 1]; ++s) cand[m++] = list[s];
+    qsort(cand, (size_t)m, sizeof(long long), cmp_ll);
+    double acc[3] = {0.0, 0.0, 0.0}, ei = 0.0;
+    for (long long s = 0; s < m; ++s) {
+      long long j = cand[s];
+      if (j == i) continue;
+      double u, g[3];
+      pair_term(d, L, pos + i * d, pos + j * d, sigma, eps, alpha, &u, g);
+      ei += u;
+      for (int a = 0; a < d; ++a) acc[a] += g[a];
+    }
+    free(cand);
+    e += 0.5 * ei;
+    if (grad)
+      for (int a = 0; a < d; ++a) grad[i * d + a] = acc[a];
+  }
+  free(cell);
+  free(head);
+  free(list);
+  if (energy) *energy = e;
+  return OR_OK;
+}

@@ -58,6 +58,12 @@ def _load():
         lib.oracle_fd.argtypes = [ctypes.c_int, ll, dp, dp, ll, ip, dp, dp, ll, lp, ip,
                                   ctypes.c_double, dp]
         lib.oracle_fd.restype = ctypes.c_int
+        lib.oracle_sf_vjp.argtypes = [ctypes.c_int, ll, dp, dp, ll, ip, dp, ll, lp, dp]
+        lib.oracle_sf_vjp.restype = ctypes.c_int
+        for f in (lib.oracle_pair, lib.oracle_pair_cells):
+            f.argtypes = [ctypes.c_int, ll, dp, dp, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_double, dp, dp]
+            f.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -199,3 +205,42 @@ def finite_difference(pos, L, modes, W, S0, coords, h: float) -> np.ndarray:
     if st:
         raise RuntimeError(f"oracle_fd failed ({st})")
     return out
+
+
+def sf_vjp(pos, L, modes, gS, grad_points=None) -> np.ndarray:
+    """sum over the listed modes of gS(k) dS(k)/dr_j (derivative of S, Methods,
+    "Analytical gradients"): the backward of r -> S for a given dF/dS.
+    Returns [N][d] (or [len(grad_points)][d])."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    K = modes.shape[0]
+    gS = np.ascontiguousarray(gS, dtype=np.float64).reshape(K)
+    if grad_points is None:
+        G, gidx = N, None
+    else:
+        gidx = np.ascontiguousarray(grad_points, dtype=np.int64)
+        G = gidx.shape[0]
+    grad = np.zeros((G, d))
+    st = _load().oracle_sf_vjp(d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double), K,
+                               _p(modes, ctypes.c_int), _p(gS, ctypes.c_double), G,
+                               _p(gidx, ctypes.c_longlong), _p(grad, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle_sf_vjp failed ({st})")
+    return grad
+
+
+def pair(pos, L, sigma: float, eps: float = 1.0, alpha: float = 2.0, cells: bool = False):
+    """Soft-core repulsion U = (eps/alpha)(1 - r/sigma)^alpha for r < sigma under the
+    minimum image: returns (energy, dE/dr [N][d]).  cells=False sums over all pairs,
+    cells=True over a cell list (same sums, O(N))."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    e = np.zeros(1)
+    grad = np.zeros((N, d))
+    f = _load().oracle_pair_cells if cells else _load().oracle_pair
+    st = f(d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double), float(sigma),
+           float(eps), float(alpha), _p(e, ctypes.c_double), _p(grad, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle pair term failed ({st})")
+    return float(e[0]), grad

@@ -283,3 +283,126 @@ def test_lbfgs_oracle_decreases_structure_factor_loss():
     r = LB.run(fg, pos, 10, m=8, max_step=0.1 * L / np.sqrt(N))
     assert r["fs"][-1] < 0.5 * r["fs"][0]
     assert all(f2 <= f1 for f1, f2 in zip(r["fs"], r["fs"][1:]))
+
+
+# ------------------------------------------------------------------ backward of S
+def test_sf_vjp_two_points_closed_form():
+    # N = 2: S(k) = 1 + cos(k.D), so dS/dr1 = -sin(k.D) k and dS/dr2 = +sin(k.D) k;
+    # the backward of S for weights g is sum_k g(k) dS(k)/dr.
+    rng = np.random.default_rng(21)
+    L = np.array([4.0, 6.5, 5.0])
+    pos = rng.uniform(0, 1, (2, 3)) * L
+    modes = _modes_ball(3, 3.0)
+    k = 2 * np.pi * modes / L
+    g = rng.normal(size=len(modes))
+    D = pos[0] - pos[1]
+    g1 = -np.sum((g * np.sin(k @ D))[:, None] * k, axis=0)
+    out = O.sf_vjp(pos, L, modes, g)
+    np.testing.assert_allclose(out[0], g1, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(out[1], -g1, rtol=1e-12, atol=1e-12)
+
+
+def test_sf_vjp_matches_finite_differences_of_S():
+    # Central differences of F = sum_k g(k) S(k), S from the direct sum, along
+    # single coordinates (FP64, h = 1e-5: truncation ~1e-10 relative).
+    rng = np.random.default_rng(22)
+    N, L = 40, 6.0
+    pos = rng.uniform(0, L, (N, 2))
+    modes = _modes_ball(2, 5.0, include_zero=True)
+    g = rng.normal(size=len(modes))
+    out = O.sf_vjp(pos, L, modes, g)
+    h = 1e-5
+    for j, a in [(0, 0), (3, 1), (17, 0), (39, 1)]:
+        pp, pm = pos.copy(), pos.copy()
+        pp[j, a] += h
+        pm[j, a] -= h
+        fd = (g @ O.structure_factor(pp, L, modes) - g @ O.structure_factor(pm, L, modes)) / (2 * h)
+        assert out[j, a] == pytest.approx(fd, rel=1e-7, abs=1e-8)
+
+
+def test_sf_vjp_of_loss_weights_is_loss_gradient():
+    # With g = dL/dS = 2 W (S - S0) the backward of S is the loss gradient of
+    # Eq. (gradient); the sum rule sum_j grad_j = 0 holds for any g.
+    rng = np.random.default_rng(23)
+    N, L = 50, 7.0
+    pos = rng.uniform(0, L, (N, 2))
+    modes = _modes_ball(2, 4.0)
+    W = rng.uniform(0.5, 2, len(modes))
+    S0 = rng.uniform(0, 1, len(modes))
+    r = O.loss_grad(pos, L, modes, W, S0)
+    out = O.sf_vjp(pos, L, modes, 2 * W * (r["S"] - S0))
+    np.testing.assert_allclose(out, r["grad"], rtol=1e-10, atol=1e-10)
+    g = rng.normal(size=len(modes))
+    assert np.abs(O.sf_vjp(pos, L, modes, g).sum(0)).max() < 1e-9
+
+
+# ------------------------------------------------------------- soft-core pair term
+@pytest.mark.parametrize("alpha", [2.0, 2.5])
+def test_pair_two_particles_closed_form(alpha):
+    # Two particles closer than sigma, placed across the periodic boundary so that
+    # only the minimum image is in range: E = (eps/alpha)(1 - r/sigma)^alpha and
+    # |dE/dr| = (eps/sigma)(1 - r/sigma)^(alpha-1), pushing the particles apart.
+    L, sigma, eps = np.array([5.0, 4.0, 6.0]), 0.5, 1.3
+    r = 0.3
+    u = np.array([0.6, 0.0, 0.8])
+    p1 = np.array([0.05, 2.0, 5.98])
+    p2 = p1 - r * u
+    p2 = p2 - L * np.floor(p2 / L)  # stored wrapped on the far side of the box
+    e, g = O.pair(np.stack([p1, p2]), L, sigma, eps, alpha)
+    x = 1 - r / sigma
+    assert e == pytest.approx(eps / alpha * x ** alpha, rel=1e-13)
+    np.testing.assert_allclose(g[0], -(eps / sigma) * x ** (alpha - 1) * u, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(g[1], -g[0], rtol=1e-12, atol=1e-14)
+    # out of range: nothing
+    e2, g2 = O.pair(np.stack([p1, p1 + np.array([0.0, 0.51, 0.0])]), L, sigma, eps, alpha)
+    assert e2 == 0.0 and np.all(g2 == 0.0)
+
+
+def test_pair_square_lattice_energy():
+    # Square lattice of spacing a < sigma < a sqrt(2): every particle has four
+    # partners at distance a, so E = N * 4 / 2 * U(a), and by symmetry no force.
+    m, a, sigma = 12, 0.4, 0.5
+    x = np.arange(m) * a
+    pos = np.stack(np.meshgrid(x, x, indexing="ij"), -1).reshape(-1, 2) + 0.013
+    e, g = O.pair(pos, m * a, sigma)
+    assert e == pytest.approx(m * m * 2 * 0.5 * (1 - a / sigma) ** 2, rel=1e-12)
+    assert np.abs(g).max() < 1e-12
+
+
+@pytest.mark.parametrize("d,L", [(2, 9.0), (3, 6.0), (3, (1.2, 5.0, 1.7))])
+def test_pair_cells_equal_brute_force_and_newton(d, L):
+    # The cell list (including boxes only two cells wide) finds exactly the pairs
+    # of the brute force; Newton's third law makes the forces sum to zero.
+    rng = np.random.default_rng(31 + d)
+    Lv = np.broadcast_to(np.asarray(L, float), (d,))
+    N = int(np.prod(Lv) * 3)
+    pos = rng.uniform(-1, 2, (N, d)) * Lv  # unwrapped coordinates are allowed
+    e1, g1 = O.pair(pos, Lv, 0.5, 1.0, 2.0)
+    e2, g2 = O.pair(pos, Lv, 0.5, 1.0, 2.0, cells=True)
+    assert e1 > 0
+    assert e2 == pytest.approx(e1, rel=1e-12)
+    np.testing.assert_allclose(g2, g1, rtol=1e-12, atol=1e-13)
+    assert np.abs(g1.sum(0)).max() < 1e-10
+
+
+def test_pair_gradient_matches_finite_differences():
+    # Central differences of the brute-force energy (FP64, h = 1e-6).
+    rng = np.random.default_rng(41)
+    L = 4.0
+    pos = rng.uniform(0, L, (80, 3))
+    _, g = O.pair(pos, L, 0.5, 1.0, 2.5)
+    h = 1e-6
+    checked = 0
+    for j in range(80):
+        if np.abs(g[j]).max() == 0:
+            continue
+        for a in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[j, a] += h
+            pm[j, a] -= h
+            fd = (O.pair(pp, L, 0.5, 1.0, 2.5)[0] - O.pair(pm, L, 0.5, 1.0, 2.5)[0]) / (2 * h)
+            assert g[j, a] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+        checked += 1
+        if checked == 6:
+            break
+    assert checked == 6
