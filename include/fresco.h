@@ -10,8 +10,11 @@
  *   L_S     = sum_{k in K} W(k) (S(k) - S0(k))^2      (Eqs. SF_loss, loss with W)
  *   dL_S/dr_j = Re sum_k C(k) exp(-i k.r_j),
  *   C(k)    = -4 i k W(k) (S(k) - S0(k)) rho(k) / N   (Eq. gradient)
- * evaluated as one type-1 nonuniform FFT and d type-2 nonuniform FFTs (the
- * "NUwU" variant of the Methods), all on the GPU.
+ * evaluated with nonuniform FFTs (the "NUwU" variant of the Methods), all on
+ * the GPU: one type-1 transform gives rho; the d components of the gradient
+ * are the derivatives of one type-2 field (coefficients 2 G(k) rho(k) / N with
+ * G = dL/dS), interpolated with the derivative of the kernel, which equals the
+ * d type-2 transforms of the Methods up to the transform accuracy.
  *
  * Conventions shared by every call:
  *   - Mode cube: the constrained region, targets and weights live on the dense
@@ -111,6 +114,24 @@ int fresco_plan_info_get(const fresco_ctx* ctx, fresco_plan_info* out);
  * enqueueing.  Errors: EINVAL (null pointers), EHIP. */
 int fresco_structure_factor(fresco_ctx* ctx, const void* pos, void* S);
 
+/* Backward of fresco_structure_factor, for automatic differentiation of any
+ * function F of S (derivative of S with respect to a position, Methods,
+ * "Analytical gradients"):
+ *   grad_ja = sum_{n in cube} gS(n) dS(n)/dr_ja,
+ *   dS(k)/dr_j = (2/N) Re[conj(rho(k)) i k exp(i k.r_j)].
+ * gS: device mode cube (same layout and dtype as S) holding dF/dS; since S is
+ * even in k only (gS(n) + gS(-n)) / 2 matters, and gS(0) is ignored (S(0) = N).
+ * grad: device [n][d], overwritten.  pos: the positions S was computed at.
+ * reuse != 0: take rho and the point order left by the latest call on this
+ * context, which must have been fresco_structure_factor with this same pos
+ * pointer (EINVAL otherwise), and the values at pos must not have changed since
+ * (not checkable here: the caller vouches for it).  reuse == 0: recompute them
+ * from pos first (one more forward pass).  Stream-ordered; returns after
+ * enqueueing.  Errors: EINVAL (null pointers, reuse without a matching forward),
+ * EHIP. */
+int fresco_structure_factor_backward(fresco_ctx* ctx, const void* pos, const void* gS,
+                                     void* grad, int32_t reuse);
+
 /* Loss L_S and gradient dL_S/dr_j (Eq. gradient).  pos: device [n][d];
  * grad: device [n][d], overwritten.  loss: HOST pointer to one double; the call
  * synchronises the stream and then also reports non-finite positions
@@ -123,8 +144,8 @@ int fresco_loss_grad(fresco_ctx* ctx, const void* pos, double* loss, void* grad)
  * be captured in a HIP graph.  Errors: EINVAL, EHIP. */
 int fresco_loss_grad_async(fresco_ctx* ctx, const void* pos, double* loss_dev, void* grad);
 
-/* Options of the L-BFGS minimiser (main text: L-BFGS with a maximal step size and
- * a backtracking line search).  Defaults used by the Python layer: m = 8,
+/* Options of the L-BFGS minimiser (main text, "Algorithm": L-BFGS with a cap on
+ * the step and a backtracking line search; the constants are this library's).  Defaults used by the Python layer: m = 8,
  * max_backtracks = 20, max_step = 0.1 L / N^(1/d), c1 = 1e-4, shrink = 0.5,
  * gtol = 0. */
 typedef struct fresco_lbfgs_opts {
@@ -153,6 +174,52 @@ int fresco_step(fresco_ctx* ctx, void* pos, const fresco_lbfgs_opts* opts, int32
 
 /* Drop the L-BFGS history and internal point order kept by the context. */
 int fresco_reset_history(fresco_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Soft-core pair repulsion (Results, stealthy hyperuniform packings: a short-
+ * range repulsion combined with the spectral loss keeps particles apart):
+ *   U(r) = (eps / alpha) (1 - r / sigma)^alpha for r < sigma, else 0,
+ *   E = sum over pairs i < j of U(|r_i - r_j|), minimum image convention,
+ *   dE/dr_i = -(eps / sigma) sum_j (1 - r_ij / sigma)^(alpha - 1) (r_i - r_j) / r_ij.
+ * alpha = 2 is the harmonic soft core, alpha = 2.5 the Hertzian one.  Evaluated
+ * on a cell list in O(N); the energy is accumulated in FP64 and the result does
+ * not depend on the order of the points' arrival (deterministic). */
+typedef struct fresco_pair_problem {
+  int32_t dim;     /* 2 or 3 */
+  int32_t dtype;   /* FRESCO_F32 or FRESCO_F64 (positions and gradient) */
+  int64_t n;       /* number of points >= 1 */
+  double box[3];   /* box sides; sigma < L_a / 2 is required */
+  double sigma;    /* contact diameter > 0 */
+  double eps;      /* energy scale > 0 */
+  double alpha;    /* exponent >= 1 */
+} fresco_pair_problem;
+
+typedef struct fresco_pair_ctx fresco_pair_ctx;
+
+/* Create a pair context (cell list of side >= sigma, at most 2^24 cells; larger
+ * boxes get larger cells).  Errors: EINVAL (null pointers, dim, n < 1, sigma,
+ * eps or alpha out of range, a side <= 2 sigma), ENOTSUP (n >= 2^31), ENOMEM. */
+int fresco_pair_create(fresco_pair_ctx** out, const fresco_pair_problem* p, void* stream);
+
+/* Release a pair context (synchronises its stream).  NULL is accepted.  A pair
+ * context attached to a loss context must outlive the attachment. */
+int fresco_pair_destroy(fresco_pair_ctx* pair);
+
+/* E and dE/dr at pos (device [n][d]); grad (device [n][d]) is overwritten.
+ * energy: HOST pointer; the call synchronises and reports non-finite positions
+ * (ENONFINITE).  Errors: EINVAL, EHIP, ENONFINITE. */
+int fresco_pair_energy_grad(fresco_pair_ctx* pair, const void* pos, double* energy, void* grad);
+
+/* As fresco_pair_energy_grad with a DEVICE energy pointer; only enqueues. */
+int fresco_pair_energy_grad_async(fresco_pair_ctx* pair, const void* pos, double* energy_dev,
+                                  void* grad);
+
+/* Add weight * E to every loss evaluation of ctx (fresco_loss_grad,
+ * fresco_loss_grad_async and fresco_step then minimise L_S + weight E); the pair
+ * work runs on ctx's stream.  pair = NULL detaches.  The pair context must match
+ * ctx in dim, dtype, n and box.  Synchronises ctx's stream and drops its captured
+ * graphs.  Errors: EINVAL (mismatch, weight <= 0 or non-finite), EHIP. */
+int fresco_attach_pair(fresco_ctx* ctx, fresco_pair_ctx* pair, double weight);
 
 /* Stages of one evaluation, for fresco_set_timing / fresco_read_timing. */
 enum fresco_stage {

@@ -25,6 +25,7 @@
 #include "common.h"
 #include "fft.h"
 #include "lbfgs.h"
+#include "pair.h"
 #include "plan.h"
 
 using namespace fresco;
@@ -103,6 +104,12 @@ struct fresco_ctx {
   void* state = nullptr;
   bool use_graphs = true;
   std::vector<GraphEntry> graphs;
+  // positions of the latest fresco_structure_factor whose rho and point order are
+  // still held (cleared by every other evaluation)
+  const void* sf_pos = nullptr;
+  // soft-core pair term added to every loss evaluation (not owned)
+  fresco_pair_ctx* pair = nullptr;
+  double pair_w = 0.0;
   // per-stage timing (diagnostics): event pairs recorded on the stream
   uint32_t timing_mask = 0;
   std::vector<hipEvent_t> event_pool;
@@ -242,11 +249,8 @@ bool shape_cols(int n, int rmin, long long ncols, size_t cs, int* bc, int* threa
   return true;
 }
 
-// loss = sum of the block partials (fixed order); hand the non-finite flag to
-// the host-visible slot and clear it for the next evaluation
-__global__ void finish_kernel(const double* __restrict__ part, long long n, double* __restrict__ out,
-                              int* __restrict__ flag, int* __restrict__ flag_out) {
-  __shared__ double s[256];
+// sum of n partials in a fixed order (one block of 256 threads)
+__device__ double block_sum_256(const double* __restrict__ part, long long n, double* s) {
   double v = 0.0;
   for (long long i = threadIdx.x; i < n; i += 256) v += part[i];
   s[threadIdx.x] = v;
@@ -255,8 +259,23 @@ __global__ void finish_kernel(const double* __restrict__ part, long long n, doub
     if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
     __syncthreads();
   }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// loss = sum of the block partials (fixed order), plus w2 times the sum of a
+// second set (an attached pair term); hand the non-finite flag to the
+// host-visible slot and clear it for the next evaluation
+__global__ void finish_kernel(const double* __restrict__ part, long long n,
+                              const double* __restrict__ part2, long long n2, double w2,
+                              double* __restrict__ out, int* __restrict__ flag,
+                              int* __restrict__ flag_out) {
+  __shared__ double s[256];
+  const double a = block_sum_256(part, n, s);
+  const double b = (n2 > 0) ? block_sum_256(part2, n2, s) : 0.0;
   if (threadIdx.x == 0) {
-    if (out) out[0] = s[0];
+    if (out) out[0] = (n2 > 0) ? a + w2 * b : a;
     flag_out[0] = flag[0];
     flag[0] = 0;
   }
@@ -321,11 +340,11 @@ int create_state(fresco_ctx* c) {
     long long nblk = N / 4096;
     if (nblk < 1) nblk = 1;
     if (nblk > 1024) nblk = 1024;
-    long long chunk = (N + nblk - 1) / nblk;
-    if (chunk > 65535) {
-      nblk = (N + 65534) / 65535;
-      chunk = (N + nblk - 1) / nblk;
-    }
+    // chunk: a multiple of 256 (the scatter pass finds its chunk from the block
+    // index) below 2^16 (ranks are 16-bit)
+    long long chunk = ((N + nblk - 1) / nblk + 255) / 256 * 256;
+    if (chunk > 65280) chunk = 65280;
+    nblk = (N + chunk - 1) / chunk;
     if (nblk > 4096) bp.privatized = false;
     bp.nblk = (int)nblk;
     bp.chunk = chunk;
@@ -531,7 +550,7 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
 
 // mode stage + inverse transforms + interpolation; mode = COL_FUSED or COL_BWD
 template <class R>
-int run_modes_to_grad(fresco_ctx* c, int mode, R* S_cube, const R* g_cube, R* grad,
+int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R* g_cube, R* grad,
                       double* loss_dev) {
   State<R>* S = (State<R>*)c->state;
   const Geom& g = c->g;
@@ -577,8 +596,16 @@ int run_modes_to_grad(fresco_ctx* c, int mode, R* S_cube, const R* g_cube, R* gr
     launch_interp<R>(g, S->kp, (const Rec<R>*)S->bb.rec, S->bb.start, S->bb.perm, S->v, grad,
                      st);
   }
+  // attached soft-core pair term: its gradient is added to grad, its energy to
+  // the loss
+  const bool pair = (mode == COL_FUSED && c->pair);
+  if (pair) {
+    int ps = pair_enqueue(c->pair, pos, grad, true, c->pair_w, st);
+    if (ps) return ps;
+  }
   finish_kernel<<<1, 256, 0, st>>>(S->loss_part, mode == COL_FUSED ? S->nloss_part : 0,
-                                   mode == COL_FUSED ? loss_dev : nullptr, S->bb.flag,
+                                   pair ? c->pair->part : nullptr, pair ? c->pair->nblocks : 0,
+                                   c->pair_w, mode == COL_FUSED ? loss_dev : nullptr, S->bb.flag,
                                    S->flag_out);
   HIPCHK(hipGetLastError());
   return FRESCO_OK;
@@ -588,11 +615,12 @@ template <class R>
 int loss_grad_eager(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
   int st;
   if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
-  return run_modes_to_grad<R>(c, COL_FUSED, nullptr, nullptr, (R*)grad, loss_dev);
+  return run_modes_to_grad<R>(c, COL_FUSED, (const R*)pos, nullptr, nullptr, (R*)grad, loss_dev);
 }
 
 template <class R>
 int loss_grad_impl(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
+  c->sf_pos = nullptr;
   // the legacy default stream cannot be captured; timed stages run eagerly
   if (!c->use_graphs || c->timing_mask || c->st == nullptr)
     return loss_grad_eager<R>(c, pos, loss_dev, grad);
@@ -697,6 +725,7 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   State<R>* S = (State<R>*)c->state;
   const Geom& g = c->g;
   int st;
+  c->sf_pos = nullptr;
   if ((st = lbfgs_setup<R>(c, o->m))) return st;
   LbfgsOpts lo;
   lo.m = o->m;
@@ -762,11 +791,13 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   return FRESCO_OK;
 }
 
+// S on the mode cube (Sout may be NULL: only rho and the point order are kept)
 template <class R>
 int structure_factor_impl(fresco_ctx* c, const void* pos, void* Sout) {
   State<R>* S = (State<R>*)c->state;
   const Geom& g = c->g;
   int st;
+  c->sf_pos = nullptr;
   if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
   ColParams<R> last = (g.d == 2) ? S->col1 : S->col2;
   last.in[0] = (g.d == 2) ? S->A1 : S->A2;
@@ -776,9 +807,22 @@ int structure_factor_impl(fresco_ctx* c, const void* pos, void* Sout) {
     StageTimer t(c, FRESCO_STAGE_MODES);
     HIPCHK(launch_cols<R>(COL_SF, last, S->ax[g.d - 1], 1, c->st));
   }
-  finish_kernel<<<1, 256, 0, c->st>>>(S->loss_part, 0, nullptr, S->bb.flag, S->flag_out);
+  finish_kernel<<<1, 256, 0, c->st>>>(S->loss_part, 0, nullptr, 0, 0.0, nullptr, S->bb.flag,
+                                      S->flag_out);
   HIPCHK(hipGetLastError());
+  c->sf_pos = pos;
   return FRESCO_OK;
+}
+
+// Backward of S: grad = sum_k gS(k) dS(k)/dr (derivative of S in the Methods'
+// gradient derivation), the same type-2 field-derivative pass as the loss
+// gradient with dL/dS replaced by the caller's gS.
+template <class R>
+int sf_backward_impl(fresco_ctx* c, const void* pos, const void* gS, void* grad, int reuse) {
+  int st;
+  if (reuse && c->sf_pos != pos) return FRESCO_EINVAL;
+  if (!reuse && (st = structure_factor_impl<R>(c, pos, nullptr))) return st;
+  return run_modes_to_grad<R>(c, COL_BWD, (const R*)pos, nullptr, (const R*)gS, (R*)grad, nullptr);
 }
 
 }  // namespace
@@ -880,7 +924,9 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
         return FRESCO_ENOTSUP;
       }
       g.nf[a] = next_smooth_even(need);
+      g.ufac[a] = (double)g.nf[a] / g.L[a];
       g.T[a] = tdef < g.nf[a] ? tdef : g.nf[a];
+      g.tdiv[a] = make_fastdiv((uint32_t)g.T[a]);
       g.nt[a] = (g.nf[a] + g.T[a] - 1) / g.T[a];
       g.E[a] = g.T[a] + g.w - 1;
       g.Ei[a] = g.T[a] + g.wi;
@@ -893,6 +939,8 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
       g.M[a] = 0;
       g.nf[a] = 1;
       g.T[a] = 1;
+      g.ufac[a] = 1.0;
+      g.tdiv[a] = make_fastdiv(1u);
       g.nt[a] = 1;
       g.E[a] = 1;
       g.Ei[a] = 1;
@@ -1015,6 +1063,13 @@ int fresco_structure_factor(fresco_ctx* c, const void* pos, void* S) {
   return structure_factor_impl<double>(c, pos, S);
 }
 
+int fresco_structure_factor_backward(fresco_ctx* c, const void* pos, const void* gS,
+                                     void* grad, int32_t reuse) {
+  if (!c || !pos || !gS || !grad) return FRESCO_EINVAL;
+  if (c->dtype == FRESCO_F32) return sf_backward_impl<float>(c, pos, gS, grad, reuse);
+  return sf_backward_impl<double>(c, pos, gS, grad, reuse);
+}
+
 int fresco_loss_grad_async(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
   if (!c || !pos || !loss_dev || !grad) return FRESCO_EINVAL;
   if (c->dtype == FRESCO_F32) return loss_grad_impl<float>(c, pos, loss_dev, grad);
@@ -1030,6 +1085,32 @@ int fresco_step(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int32_t n_
     return FRESCO_EINVAL;
   if (c->dtype == FRESCO_F32) return step_impl<float>(c, pos, o, n_iter, loss_out, n_eval_out);
   return step_impl<double>(c, pos, o, n_iter, loss_out, n_eval_out);
+}
+
+int fresco_attach_pair(fresco_ctx* c, fresco_pair_ctx* pc, double weight) {
+  if (!c) return FRESCO_EINVAL;
+  if (pc) {
+    if (pc->d != c->g.d || pc->dtype != c->dtype || pc->n != c->g.N) return FRESCO_EINVAL;
+    for (int a = 0; a < c->g.d; ++a)
+      if (pc->L[a] != c->g.L[a]) return FRESCO_EINVAL;
+    if (!(weight > 0.0) || !std::isfinite(weight)) return FRESCO_EINVAL;
+  }
+  HIPCHK(hipStreamSynchronize(c->st));
+  // captured graphs hold the previous launch sequence
+  for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
+  c->graphs.clear();
+  if (c->dtype == FRESCO_F32) {
+    State<float>* S = (State<float>*)c->state;
+    if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
+    S->lb_graph = nullptr;
+  } else {
+    State<double>* S = (State<double>*)c->state;
+    if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
+    S->lb_graph = nullptr;
+  }
+  c->pair = pc;
+  c->pair_w = pc ? weight : 0.0;
+  return FRESCO_OK;
 }
 
 int fresco_reset_history(fresco_ctx* c) {

@@ -83,6 +83,8 @@ struct Geom {
   int nt[3];      // tiles per dimension (1 beyond d)
   int E[3];       // padded spreading tile extent T + w - 1 (1 beyond d)
   int Ei[3];      // interpolation field tile extent T + wi (1 beyond d)
+  double ufac[3];   // nf / L: position -> grid coordinate
+  FastDiv tdiv[3];  // division by T
   long long nbins;
   long long ngrid;  // prod nf
   long long nhalf;  // (M0+1) * prod_{a>0} (2M_a+1): half mode cube

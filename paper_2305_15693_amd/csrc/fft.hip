@@ -333,7 +333,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
         cp = ((long long)(n0 + p.M0) * p.P1 + (n1 + p.M1)) * p.P2 + (nl + p.M2);
         cm = ((long long)(-n0 + p.M0) * p.P1 + (-n1 + p.M1)) * p.P2 + (-nl + p.M2);
       }
-      if (MODE == COL_SF || (MODE == COL_FUSED && p.S_cube)) {
+      if ((MODE == COL_SF || MODE == COL_FUSED) && p.S_cube) {
         p.S_cube[cp] = S;
         p.S_cube[cm] = S;
       }
@@ -349,7 +349,8 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
           if (n0 > 0) lsum += (double)wm * (double)rm * (double)rm;
           G = wp * rp + wm * rm;
         } else {
-          G = R(0.5) * (p.g_cube[cp] + p.g_cube[cm]);
+          // S(0) = N does not depend on the positions
+          G = (cp == cm) ? R(0) : R(0.5) * (p.g_cube[cp] + p.g_cube[cm]);
         }
         // type-2 input of the field whose derivative is the gradient:
         // C0 = 2 G rho / N, divided by psihat_i and scaled by h^d

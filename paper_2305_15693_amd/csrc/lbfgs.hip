@@ -1,7 +1,6 @@
-// L-BFGS with a maximal step and backtracking line search (main text: the
-// configuration and gradient are fed to L-BFGS, Liu & Nocedal, "with a maximal
-// step size and a backtracking line-search", Nocedal & Wright), as a device-side
-// state machine so that one trial step -- evaluation plus optimiser update -- is
+// L-BFGS (Liu & Nocedal) with a cap on the step length and a backtracking line
+// search (Nocedal & Wright), the optimiser the paper's main text feeds the
+// configuration and gradient to, written as a device-side state machine so that one trial step -- evaluation plus optimiser update -- is
 // a fixed sequence of kernels that is captured in a HIP graph and replayed
 // without host synchronisation.
 //
@@ -158,36 +157,48 @@ __global__ void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S) {
 }
 
 // ---------------------------------------------------------------- small
+__device__ __forceinline__ void lb_small_solve(LbfgsState* S, const LbfgsOpts& o,
+                                               const double* red, int step, long long n);
+
 // One block: reduce the partials, update the pair products, solve for the
 // direction coefficients.
-__global__ void lb_small_kernel(LbfgsState* S, LbfgsOpts o, const double* part, int nb,
+__global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part, int nb,
                                 long long n) {
   __shared__ double red[4 * kLbfgsMaxM + 1];
+  // the serial solves run on an LDS copy of the state (dependent global loads
+  // would dominate otherwise); it is written back at the end
+  __shared__ LbfgsState sh;
+  static_assert(sizeof(LbfgsState) % 4 == 0, "state copied as 32-bit words");
   const int m = o.m;
-  const int step = S->step;
+  const int step = Sg->step;
   const bool dir = (step == LB_ACCEPT || step == LB_INIT || step == LB_RESTART);
   if (!dir) return;
   const int cnt = 4 * m + 1;
   if (step != LB_RESTART) {
-    // every thread sums a strided subset of the block partials of each value, then
-    // the block combines them (fixed order)
-    __shared__ double wsum[kWaves];
-    for (int c = 0; c < cnt; ++c) {
+    // value c is reduced by wave c mod (waves): each lane sums a strided subset of
+    // the block partials, then the wave combines its lanes (fixed order)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = wave; c < cnt; c += (int)(blockDim.x >> 6)) {
       double t = 0.0;
-      for (int b = threadIdx.x; b < nb; b += blockDim.x) t += part[(long long)c * nb + b];
+      for (int b = lane; b < nb; b += 64) t += part[(long long)c * nb + b];
       for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
-      if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = t;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += wsum[w];
-        red[c] = s;
-      }
-      __syncthreads();
+      if (lane == 0) red[c] = t;
     }
   }
+  constexpr int kWords = (int)(sizeof(LbfgsState) / 4);
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&sh)[i] = reinterpret_cast<const uint32_t*>(Sg)[i];
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x == 0) lb_small_solve(&sh, o, red, step, n);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(Sg)[i] = reinterpret_cast<const uint32_t*>(&sh)[i];
+}
+
+// serial part of the small step (one thread, state in LDS)
+__device__ __forceinline__ void lb_small_solve(LbfgsState* S, const LbfgsOpts& o,
+                                               const double* red, int step, long long n) {
+  const int m = o.m;
   if (step != LB_RESTART) {
     S->gg = red[4 * m];
     for (int j = 0; j < m; ++j) {

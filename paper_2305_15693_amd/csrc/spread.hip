@@ -152,7 +152,7 @@ __device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* b
   for (int a = 0; a < g.d; ++a) {
     double x = (double)r[a];
     const double nf = (double)g.nf[a];
-    double u = x * (nf / g.L[a]);
+    double u = x * g.ufac[a];
     if (!isfinite(u)) {
       *bad = true;
       u = 0.0;
@@ -167,7 +167,7 @@ __device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* b
     int li = (int)l0;
     if (li < 0) li += g.nf[a];
     if (li >= g.nf[a]) li -= g.nf[a];
-    uint32_t ta = (uint32_t)li / (uint32_t)g.T[a];
+    uint32_t ta = fdiv((uint32_t)li, g.tdiv[a]);
     uint32_t loc = (uint32_t)li - ta * (uint32_t)g.T[a];
     tile[a] = ta;
     pb.cell |= loc << (8 * a);
@@ -224,8 +224,10 @@ __global__ void bin_rowscan_kernel(uint32_t* __restrict__ H, int nblk, long long
   if (lane == 0) count[tile] = carry;
 }
 
+// 256 threads per block; chunk is a multiple of 256, bpc = chunk / 256 blocks per
+// histogram chunk
 template <class R>
-__global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, long long chunk, int nblk,
+__global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, uint32_t bpc, int nblk,
                                    const uint32_t* __restrict__ kr,
                                    const uint32_t* __restrict__ H,
                                    const long long* __restrict__ start, Rec<R>* __restrict__ rec,
@@ -236,7 +238,7 @@ __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, long long 
   PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
   const uint32_t v = kr[i];
   const uint32_t tile = v & 0xffffu, rank = v >> 16;
-  const long long blk = i / chunk;
+  const uint32_t blk = blockIdx.x / bpc;
   const long long dst = start[tile] + H[(long long)tile * nblk + blk] + rank;
   Rec<R> o;
   o.t[0] = (R)pb.t[0];
@@ -324,11 +326,11 @@ void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, Bin
     scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, g.nbins, b.start);
     if (f64)
       bin_scatter_kernel<double><<<(unsigned)nblocks, 256, 0, st>>>(
-          g, (const double*)pos, bp.chunk, bp.nblk, b.kr, b.H, b.start, (Rec<double>*)b.rec,
+          g, (const double*)pos, (uint32_t)(bp.chunk / 256), bp.nblk, b.kr, b.H, b.start, (Rec<double>*)b.rec,
           b.perm);
     else
       bin_scatter_kernel<float><<<(unsigned)nblocks, 256, 0, st>>>(
-          g, (const float*)pos, bp.chunk, bp.nblk, b.kr, b.H, b.start, (Rec<float>*)b.rec,
+          g, (const float*)pos, (uint32_t)(bp.chunk / 256), bp.nblk, b.kr, b.H, b.start, (Rec<float>*)b.rec,
           b.perm);
   } else {
     launch_fill<uint32_t>(b.count, g.nbins, 0u, st);
@@ -448,32 +450,34 @@ __global__ void spread_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__
 }
 
 // Fold: grid cell (x, y, z) = sum over the padded tiles that cover it.  For each
-// axis, cover[a] lists (tile, local index) pairs per grid coordinate (CSR).
+// axis, cover[a] lists (tile, local index) pairs per grid coordinate (CSR).  One
+// block per grid row (y, z); the y and z cover lists are uniform across it.
 template <class R, int D>
 __global__ void fold_kernel(Geom g, FoldTables ft, const R* __restrict__ tiles,
                             R* __restrict__ grid) {
-  const long long n = g.ngrid;
   const long long ncell = (long long)g.E[0] * g.E[1] * (D == 3 ? g.E[2] : 1);
-  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < n;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(c % g.nf[0]);
-    const long long r = c / g.nf[0];
-    const int y = (int)(r % g.nf[1]);
-    const int z = (int)(r / g.nf[1]);
+  const uint32_t row = blockIdx.x;
+  const int y = (int)(row % (uint32_t)g.nf[1]);
+  const int z = (int)(row / (uint32_t)g.nf[1]);
+  const int yb = ft.off[1][y], ye = ft.off[1][y + 1];
+  const int zb = (D == 3) ? ft.off[2][z] : 0, ze = (D == 3) ? ft.off[2][z + 1] : 1;
+  R* __restrict__ out = grid + (long long)row * g.nf[0];
+  for (int x = threadIdx.x; x < g.nf[0]; x += blockDim.x) {
+    const int xb = ft.off[0][x], xe = ft.off[0][x + 1];
     R acc = R(0);
-    const int zb = (D == 3) ? ft.off[2][z] : 0, ze = (D == 3) ? ft.off[2][z + 1] : 1;
     for (int iz = zb; iz < ze; ++iz) {
       const int tz = (D == 3) ? ft.ent[2][iz].x : 0, lz = (D == 3) ? ft.ent[2][iz].y : 0;
-      for (int iy = ft.off[1][y]; iy < ft.off[1][y + 1]; ++iy) {
+      for (int iy = yb; iy < ye; ++iy) {
         const int ty = ft.ent[1][iy].x, ly = ft.ent[1][iy].y;
-        for (int ix = ft.off[0][x]; ix < ft.off[0][x + 1]; ++ix) {
-          const int tx = ft.ent[0][ix].x, lx = ft.ent[0][ix].y;
-          const long long bin = tx + (long long)g.nt[0] * (ty + (long long)g.nt[1] * tz);
-          acc += tiles[bin * ncell + ((long long)lz * g.E[1] + ly) * g.E[0] + lx];
+        const long long base = (long long)(g.nt[0] * (ty + g.nt[1] * tz)) * ncell +
+                               (lz * g.E[1] + ly) * g.E[0];
+        for (int ix = xb; ix < xe; ++ix) {
+          const int2 ex = ft.ent[0][ix];
+          acc += tiles[base + (long long)ex.x * ncell + ex.y];
         }
       }
     }
-    grid[c] = acc;
+    out[x] = acc;
   }
 }
 
@@ -638,10 +642,11 @@ void launch_spread(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
 
 template <class R>
 void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, hipStream_t st) {
-  long long blocks = (g.ngrid + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (g.d == 2) fold_kernel<R, 2><<<(unsigned)blocks, 256, 0, st>>>(g, ft, tiles, grid);
-  else fold_kernel<R, 3><<<(unsigned)blocks, 256, 0, st>>>(g, ft, tiles, grid);
+  const unsigned rows = (unsigned)(g.ngrid / g.nf[0]);
+  int threads = ((g.nf[0] + 63) / 64) * 64;
+  if (threads > 256) threads = 256;
+  if (g.d == 2) fold_kernel<R, 2><<<rows, threads, 0, st>>>(g, ft, tiles, grid);
+  else fold_kernel<R, 3><<<rows, threads, 0, st>>>(g, ft, tiles, grid);
 }
 
 template <class R>

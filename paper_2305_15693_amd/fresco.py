@@ -65,6 +65,18 @@ class PlanInfo(ctypes.Structure):
     ]
 
 
+class PairProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("box", ctypes.c_double * 3),
+        ("sigma", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+    ]
+
+
 class LbfgsOpts(ctypes.Structure):
     _fields_ = [
         ("m", ctypes.c_int32),
@@ -90,6 +102,8 @@ def _load():
     lib.fresco_plan_info_get.restype = i
     lib.fresco_structure_factor.argtypes = [vp, vp, vp]
     lib.fresco_structure_factor.restype = i
+    lib.fresco_structure_factor_backward.argtypes = [vp, vp, vp, vp, ctypes.c_int32]
+    lib.fresco_structure_factor_backward.restype = i
     lib.fresco_loss_grad.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.fresco_loss_grad.restype = i
     lib.fresco_loss_grad_async.argtypes = [vp, vp, vp, vp]
@@ -104,6 +118,16 @@ def _load():
     lib.fresco_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64), i]
     lib.fresco_read_timing.restype = i
+    lib.fresco_pair_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(PairProblem), vp]
+    lib.fresco_pair_create.restype = i
+    lib.fresco_pair_destroy.argtypes = [vp]
+    lib.fresco_pair_destroy.restype = i
+    lib.fresco_pair_energy_grad.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.fresco_pair_energy_grad.restype = i
+    lib.fresco_pair_energy_grad_async.argtypes = [vp, vp, vp, vp]
+    lib.fresco_pair_energy_grad_async.restype = i
+    lib.fresco_attach_pair.argtypes = [vp, vp, ctypes.c_double]
+    lib.fresco_attach_pair.restype = i
     lib.fresco_error_string.argtypes = [i]
     lib.fresco_error_string.restype = ctypes.c_char_p
     lib.fresco_last_hip_error.argtypes = []
@@ -176,6 +200,8 @@ class Context:
                    "fresco_create")
         self._h = h
         self._loss = ctypes.c_double(0.0)
+        self._calls = 0          # calls that took positions (each may replace the held state)
+        self._sf_token = None
 
     # ------------------------------------------------------------------
     def close(self):
@@ -222,6 +248,12 @@ class Context:
                                 ctypes.byref(loss), ctypes.byref(nev)), "fresco_step")
         return float(loss.value), int(nev.value)
 
+    def attach_pair(self, pair, weight: float = 1.0):
+        """Add weight * E of a PairContext to every loss evaluation (None detaches)."""
+        _check(_lib.fresco_attach_pair(self._h, pair.handle if pair is not None else None,
+                                       float(weight)), "fresco_attach_pair")
+        self._pair = pair  # keep it alive while attached
+
     def reset_history(self):
         _check(_lib.fresco_reset_history(self._h), "fresco_reset_history")
 
@@ -244,6 +276,7 @@ class Context:
             raise ValueError(f"positions must be {self.torch_dtype} on {self.device}")
         if tuple(pos.shape) != (self.n, self.dim) or not pos.is_contiguous():
             raise ValueError(f"positions must be a contiguous [{self.n}][{self.dim}] tensor")
+        self._calls += 1
         return ctypes.c_void_p(pos.data_ptr())
 
     def structure_factor(self, pos, out=None):
@@ -252,7 +285,33 @@ class Context:
             out = torch.empty(self.cube_shape, dtype=self.torch_dtype, device=self.device)
         _check(_lib.fresco_structure_factor(self._h, self._pos(pos), ctypes.c_void_p(out.data_ptr())),
                "fresco_structure_factor")
+        self._sf_token = (self._calls, pos.data_ptr())
         return out
+
+    def sf_token(self):
+        """Identifies the latest structure_factor call while no other call has run."""
+        return self._sf_token
+
+    def structure_factor_backward(self, pos, gS, grad=None, token=None):
+        """grad = sum_n gS(n) dS(n)/dr (backward of structure_factor; see
+        fresco_structure_factor_backward).  gS: mode cube of dF/dS.  token: the
+        sf_token() taken right after the forward call; when no other call has run
+        on this context since, the forward's state is reused, else recomputed."""
+        torch = _torch()
+        if (gS.device != self.device or gS.dtype != self.torch_dtype
+                or tuple(gS.shape) != self.cube_shape or not gS.is_contiguous()):
+            raise ValueError(f"gS must be a contiguous {self.cube_shape} {self.torch_dtype} tensor "
+                             f"on {self.device}")
+        if grad is None:
+            grad = torch.empty((self.n, self.dim), dtype=self.torch_dtype, device=self.device)
+        reuse = token is not None and token == self._sf_token and token[0] == self._calls \
+            and token[1] == pos.data_ptr()
+        _check(_lib.fresco_structure_factor_backward(self._h, self._pos(pos),
+                                                     ctypes.c_void_p(gS.data_ptr()),
+                                                     ctypes.c_void_p(grad.data_ptr()),
+                                                     1 if reuse else 0),
+               "fresco_structure_factor_backward")
+        return grad
 
     def loss_grad(self, pos, grad=None):
         torch = _torch()
@@ -266,3 +325,71 @@ class Context:
         _check(_lib.fresco_loss_grad_async(self._h, self._pos(pos), ctypes.c_void_p(loss_dev.data_ptr()),
                                            ctypes.c_void_p(grad.data_ptr())), "fresco_loss_grad_async")
         return loss_dev, grad
+
+
+class PairContext:
+    """Soft-core repulsion U = (eps/alpha)(1 - r/sigma)^alpha, r < sigma, on a cell
+    list (include/fresco.h, fresco_pair_*)."""
+
+    def __init__(self, dim: int, n: int, box, *, sigma: float = 0.5, eps: float = 1.0,
+                 alpha: float = 2.0, dtype: str = "f32", stream=None, device=None):
+        torch = _torch()
+        self.dim = int(dim)
+        self.n = int(n)
+        self.dtype = dtype
+        self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        box = np.broadcast_to(np.asarray(box, dtype=np.float64), (self.dim,))
+        p = PairProblem()
+        p.dim = self.dim
+        p.dtype = F32 if dtype == "f32" else F64
+        p.n = self.n
+        for a in range(3):
+            p.box[a] = float(box[a]) if a < self.dim else 1.0
+        p.sigma, p.eps, p.alpha = float(sigma), float(eps), float(alpha)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.fresco_pair_create(ctypes.byref(h), ctypes.byref(p),
+                                           ctypes.c_void_p(stream.cuda_stream)), "fresco_pair_create")
+        self._h = h
+        self._e = ctypes.c_double(0.0)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.fresco_pair_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _pos(self, pos):
+        if pos.device != self.device or pos.dtype != self.torch_dtype:
+            raise ValueError(f"positions must be {self.torch_dtype} on {self.device}")
+        if tuple(pos.shape) != (self.n, self.dim) or not pos.is_contiguous():
+            raise ValueError(f"positions must be a contiguous [{self.n}][{self.dim}] tensor")
+        return ctypes.c_void_p(pos.data_ptr())
+
+    def energy_grad(self, pos, grad=None):
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty((self.n, self.dim), dtype=self.torch_dtype, device=self.device)
+        _check(_lib.fresco_pair_energy_grad(self._h, self._pos(pos), ctypes.byref(self._e),
+                                            ctypes.c_void_p(grad.data_ptr())), "fresco_pair_energy_grad")
+        return float(self._e.value), grad
+
+    def energy_grad_async(self, pos, energy_dev, grad):
+        _check(_lib.fresco_pair_energy_grad_async(self._h, self._pos(pos),
+                                                  ctypes.c_void_p(energy_dev.data_ptr()),
+                                                  ctypes.c_void_p(grad.data_ptr())),
+               "fresco_pair_energy_grad_async")
+        return energy_dev, grad
