@@ -162,6 +162,134 @@ def measure(name, steps, warmup, dev, lbfgs_steps):
     return res
 
 
+def measure_autograd_pair(name, steps, dev):
+    """3D packing workload through torch.autograd: spectral loss + soft-core pair
+    term (sigma = 0.5, harmonic, weight 1) in one backward; also the pair pass alone."""
+    import numpy as np
+    import torch
+
+    from paper_2305_15693_amd import autograd as A
+    from paper_2305_15693_amd import fresco as F
+    from paper_2305_15693_amd import inputs as I
+
+    cfg = I.WORKLOADS[name]
+    d, N, L, M = cfg["d"], cfg["N"], cfg["L"], cfg["M"]
+    w, s0 = I.stealthy_target(d, M, cfg["kcut"])
+    ctx = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=cfg["tol"], dtype=cfg["dtype"], device=dev)
+    pctx = F.PairContext(d, N, L, sigma=cfg.get("sigma", 0.5), eps=1.0, alpha=2.0,
+                         dtype=cfg["dtype"], device=dev)
+    pos = torch.from_numpy(I.positions(N, d, L, np.float32, seed=cfg["seed"])).to(dev)
+    pos.requires_grad_(True)
+
+    def one():
+        pos.grad = None
+        total = A.loss(ctx, pos) + A.soft_core(pctx, pos)
+        total.backward()
+        return total
+
+    for _ in range(2):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        total = one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    e_dev = torch.zeros((), dtype=torch.float64, device=dev)
+    g = torch.empty_like(pos)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    pd = pos.detach()
+    pctx.energy_grad_async(pd, e_dev, g)
+    e0.record()
+    for _ in range(steps):
+        pctx.energy_grad_async(pd, e_dev, g)
+    e1.record()
+    torch.cuda.synchronize()
+    pair_ms = e0.elapsed_time(e1) / steps
+    out = {"autograd_evals_per_s": 1e3 / ms, "autograd_ms": ms, "pair_ms": pair_ms,
+           "pair_energy": float(e_dev), "total_loss": float(total)}
+    ctx.close()
+    pctx.close()
+    return out
+
+
+def measure_batch(dev, steps):
+    """Ragged batch of 256 2D configurations (N log-uniform in [1e3, 1e5], unit
+    density, power-law targets |k| < 2 pi 20 / L, relative weights): one persistent
+    batched launch per evaluation against a loop of the plain single-problem path
+    over the same configurations, and batched L-BFGS iterations under graph replay."""
+    import numpy as np
+    import torch
+
+    from paper_2305_15693_amd import fresco as F
+    from paper_2305_15693_amd import inputs as I
+
+    kcut, M = 20, 19
+    cfgs = I.ragged_batch(nb=256, kcut=kcut, seed=1004)
+    items, pos_l = [], []
+    for c in cfgs:
+        w, s0 = I.power_law_target(2, M, kcut, c["alpha"])
+        items.append(dict(n=c["N"], box=c["L"], w_cube=w, s0_cube=s0, relative=True))
+        pos_l.append(I.positions(c["N"], 2, c["L"], np.float32, seed=c["seed"]))
+    stream = torch.cuda.Stream(device=dev)
+    bc = F.BatchContext(2, M, items, tol=1e-6, dtype="f32", device=dev, stream=stream)
+    pos = torch.from_numpy(np.concatenate(pos_l, 0)).to(dev)
+    threads = bc.autotune(pos, reps=3)
+    grad = torch.empty_like(pos)
+    losses = torch.zeros(256, dtype=torch.float64, device=dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        bc.loss_grad_async(pos, losses, grad)
+    e0.record(stream)
+    for _ in range(steps):
+        bc.loss_grad_async(pos, losses, grad)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1) / steps
+    # loop of the plain path (each evaluation replayed from its captured graph)
+    ctxs, views, grads, ldev = [], [], [], torch.zeros(256, dtype=torch.float64, device=dev)
+    for b, c in enumerate(cfgs):
+        w, s0 = I.power_law_target(2, M, kcut, c["alpha"])
+        ctxs.append(F.Context(2, c["N"], c["L"], M, w_cube=w, s0_cube=s0, relative=True, tol=1e-6,
+                              dtype="f32", device=dev, stream=stream))
+        views.append(pos[bc.offsets[b]:bc.offsets[b + 1]])
+        grads.append(torch.empty_like(views[-1]))
+    for _ in range(2):
+        for b in range(256):
+            ctxs[b].loss_grad_async(views[b], ldev[b:b + 1], grads[b])
+    torch.cuda.synchronize()
+    reps = max(1, steps // 10)
+    e0.record(stream)
+    for _ in range(reps):
+        for b in range(256):
+            ctxs[b].loss_grad_async(views[b], ldev[b:b + 1], grads[b])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    loop_ms = e0.elapsed_time(e1) / reps
+    diff = float((ldev - losses).abs().max() / losses.abs().max())
+    for cx in ctxs:
+        cx.close()
+    # batched L-BFGS iterations
+    work = pos.clone()
+    bc.step(work, 2, max_step=0.05)
+    bc.reset_history()
+    work.copy_(pos)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    loss, nev = bc.step(work, steps, max_step=0.05)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    it_ms = e0.elapsed_time(e1) / steps
+    bc.close()
+    return {"workload": "2d_ragged256_powerlaw_f32", "configs": 256, "points": int(pos.shape[0]),
+            "autotuned_threads": threads, "batched_eval_ms": batch_ms, "loop_eval_ms": loop_ms,
+            "speedup": loop_ms / batch_ms, "loss_max_rel_diff_batch_vs_loop": diff,
+            "lbfgs_iter_ms": it_ms, "lbfgs_evals": nev, "lbfgs_iters": steps,
+            "lbfgs_loss_start": float(losses.sum()), "lbfgs_loss_end": loss}
+
+
 def cpu_baseline(res, budget_modes=256, grad_points=1024):
     """Oracle timed on a bounded sample of the same evaluation, scaled to one
     full evaluation (rho over all constrained modes for all points, then the
@@ -203,6 +331,7 @@ def main():
     ap.add_argument("--secondary", default="3d_n1e7_stealthy60_f32",
                     help="second workload measured the same way ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
@@ -227,6 +356,18 @@ def main():
                "plain_ms": s["plain_ms"], "roofline": s["roofline"],
                "stages_ms": s["stages_ms"], "stage_gbs": s["stage_gbs"],
                "nf": s["info"]["nf"], "width": s["info"]["width"]}
+        if s["cfg"]["d"] == 3:
+            ag = measure_autograd_pair(args.secondary, 5, dev)
+            print(f"[bench] {args.secondary} autograd (spectral + soft core): "
+                  f"{ag['autograd_evals_per_s']:.1f} evals/s, pair pass {ag['pair_ms']:.3f} ms",
+                  file=sys.stderr, flush=True)
+            sec["autograd_with_pair"] = ag
+    bat = None
+    if not args.no_batch:
+        bat = measure_batch(dev, 20)
+        print(f"[bench] ragged batch: {bat['batched_eval_ms']:.3f} ms batched vs "
+              f"{bat['loop_eval_ms']:.3f} ms loop ({bat['speedup']:.1f}x); L-BFGS iteration "
+              f"{bat['lbfgs_iter_ms']:.3f} ms", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(r)
@@ -258,6 +399,7 @@ def main():
         "stages_ms": r["stages_ms"],
         "stage_gbs": r["stage_gbs"],
         "secondary": sec,
+        "batch": bat,
     }
     print(json.dumps(out))
 

@@ -221,6 +221,62 @@ int fresco_pair_energy_grad_async(fresco_pair_ctx* pair, const void* pos, double
  * graphs.  Errors: EINVAL (mismatch, weight <= 0 or non-finite), EHIP. */
 int fresco_attach_pair(fresco_ctx* ctx, fresco_pair_ctx* pair, double weight);
 
+/* ---------------------------------------------------------------------------
+ * Ragged batches: many independent problems of the kind above (each with its
+ * own n, box, targets and weights; all with the same dim, dtype, kmax and tol)
+ * evaluated by one persistent kernel launch in which a workgroup keeps the whole
+ * fine grid of one configuration in LDS (spread, FFT, modes, inverse FFT and
+ * interpolation never leave the CU).  The grid must fit: roughly
+ * (16 or 24 bytes) x prod nf_a <= 156 KiB, e.g. kmax <= 19 in 2D for FP32 and
+ * FP64.  Positions and gradients are the configurations' [n_b][d] rows
+ * concatenated in order (row offsets from fresco_batch_offsets). */
+typedef struct fresco_batch_ctx fresco_batch_ctx;
+
+/* Create a batch of nb >= 1 problems ps[0..nb).  Errors: EINVAL (as for
+ * fresco_create, or problems that differ in dim, dtype, kmax, tol or
+ * upsampfac), ENOTSUP (grid does not fit in LDS, more than 2^31 - 1 points in
+ * total), ENOMEM, EHIP. */
+int fresco_batch_create(fresco_batch_ctx** out, int32_t nb, const fresco_problem* ps,
+                        void* stream);
+
+/* Release a batch context (synchronises its stream).  NULL is accepted. */
+int fresco_batch_destroy(fresco_batch_ctx* batch);
+
+/* offsets[0..nb]: first row of every configuration; offsets[nb] = total rows. */
+int fresco_batch_offsets(const fresco_batch_ctx* batch, int64_t* offsets);
+
+/* Loss of every configuration and the concatenated gradient.  losses: HOST array
+ * of nb doubles (may be NULL); synchronises, reports non-finite positions
+ * (ENONFINITE).  grad: device, overwritten. */
+int fresco_batch_loss_grad(fresco_batch_ctx* batch, const void* pos, double* losses, void* grad);
+
+/* As fresco_batch_loss_grad with a DEVICE losses array (may be NULL); only
+ * enqueues (graph-capturable). */
+int fresco_batch_loss_grad_async(fresco_batch_ctx* batch, const void* pos, double* losses_dev,
+                                 void* grad);
+
+/* L-BFGS on the sum of the configurations' losses (the configurations are
+ * independent, so its gradient is the concatenation of theirs) for n_iter
+ * accepted iterations; one trial step = one persistent launch plus the optimiser
+ * kernels, replayed from a captured HIP graph.  pos is updated in place; the
+ * history persists across calls (fresco_batch_reset_history clears it).
+ * loss_out: total loss at the final positions.  Errors as fresco_step. */
+int fresco_batch_step(fresco_batch_ctx* batch, void* pos, const fresco_lbfgs_opts* opts,
+                      int32_t n_iter, double* loss_out, int32_t* n_eval_out);
+
+/* Drop the batch's L-BFGS history. */
+int fresco_batch_reset_history(fresco_batch_ctx* batch);
+
+/* Autotuner: time `reps` evaluations at pos (grad: scratch [rows][d]) for each
+ * candidate workgroup size (256, 512, 1024 threads) and keep the fastest for
+ * all later calls; *threads_out (may be NULL) receives it.  Synchronises.
+ * Errors: EINVAL, EHIP. */
+int fresco_batch_autotune(fresco_batch_ctx* batch, const void* pos, void* grad, int32_t reps,
+                          int32_t* threads_out);
+
+/* Last hipError_t seen by the batch functions (0 if none). */
+int fresco_batch_last_hip_error(void);
+
 /* Stages of one evaluation, for fresco_set_timing / fresco_read_timing. */
 enum fresco_stage {
   FRESCO_STAGE_BIN = 0,          /* wrap, split, counting sort by tile (4 kernels) */

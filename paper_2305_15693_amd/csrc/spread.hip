@@ -21,7 +21,9 @@
 // the tile padded by w - 1 cells, in fixed point with integer LDS atomics
 // (gfx950 executes integer LDS atomics far faster than float ones; the integer
 // sum is exact and independent of order).  The scale is a power of two chosen
-// per tile from its point count so that no cell can exceed 2^31; two adjacent
+// per tile from a bound on the points that cover one cell (a box sum of the
+// tile's footprint-start counts), so that no cell can exceed 2^31 while the
+// rounding of each contribution stays far below the FP32 precision; two adjacent
 // 32-bit cells therefore add as one 64-bit word without carries between them,
 // which halves the atomic count.  The padded tile is stored as is; a fold
 // kernel then sums, for every grid cell, the padded tiles that cover it
@@ -39,82 +41,9 @@
 #include <utility>
 
 #include "common.h"
+#include "kernels.h"
 
 namespace fresco {
-
-template <class R>
-__device__ __forceinline__ R es_kernel(R z, R beta) {
-  R s = (R(1) - z) * (R(1) + z);
-  return s >= R(0) ? exp(beta * (sqrt(s) - R(1))) : R(0);
-}
-
-// Interpolation kernel and its derivative: phi_c(z) = cosh(beta s) / cosh(beta),
-// s = sqrt(1 - z^2).  It is the exponential of semicircle up to terms of order
-// exp(-2 beta s - beta), but even in s, so phi_c' = -beta z sinh(beta s) / (s cosh beta)
-// stays finite at |z| = 1 (the plain exponential's derivative diverges there,
-// which would make the gradient of points sitting on a grid node inaccurate).
-template <class R>
-__device__ __forceinline__ void cosh_kernel_d(R z, R beta, R inv_cosh_beta, R* f, R* df) {
-  const R s2 = (R(1) - z) * (R(1) + z);
-  if (!(s2 >= R(0))) {
-    *f = R(0);
-    *df = R(0);
-    return;
-  }
-  const R s = sqrt(s2);
-  const R bs = beta * s;
-  const R e = exp(bs);
-  const R ei = R(1) / e;
-  R shs;  // sinh(beta s) / s
-  if (bs > R(1e-2)) {
-    shs = R(0.5) * (e - ei) / s;
-  } else {
-    const R b2 = bs * bs;
-    shs = beta * (R(1) + b2 * (R(1) / R(6) + b2 * (R(1) / R(120))));
-  }
-  *f = R(0.5) * (e + ei) * inv_cosh_beta;
-  *df = -beta * z * shs * inv_cosh_beta;
-}
-
-// Kernel values on the W footprint cells of one axis from tau in [0, 1):
-// FP32 evaluates the per-cell polynomials (x = 2 tau - 1), FP64 the closed forms.
-template <int W>
-__device__ __forceinline__ float poly_eval(const float (&c)[kPolyDeg + 1], float x) {
-  float r = c[kPolyDeg];
-#pragma unroll
-  for (int k = kPolyDeg - 1; k >= 0; --k) r = fmaf(r, x, c[k]);
-  return r;
-}
-template <class R, int W>
-__device__ __forceinline__ void spread_weights(const KernelPolys& kp, R tau, R beta, R* k) {
-  if constexpr (sizeof(R) == 4) {
-    const float x = 2.f * tau - 1.f;
-#pragma unroll
-    for (int i = 0; i < W; ++i) k[i] = poly_eval<W>(kp.sp[i], x);
-  } else {
-    const R hw = R(2) / R(W);
-#pragma unroll
-    for (int i = 0; i < W; ++i) k[i] = es_kernel<R>((tau - R(0.5) * R(W) + R(i)) * hw, beta);
-  }
-}
-// interpolation kernel (width WI) and its z-derivative
-template <class R, int WI>
-__device__ __forceinline__ void interp_weights(const KernelPolys& kp, R tau, R beta, R icb,
-                                               R* f, R* df) {
-  if constexpr (sizeof(R) == 4) {
-    const float x = 2.f * tau - 1.f;
-#pragma unroll
-    for (int i = 0; i < WI; ++i) {
-      f[i] = poly_eval<WI>(kp.ip[i], x);
-      df[i] = poly_eval<WI>(kp.id[i], x);
-    }
-  } else {
-    const R hw = R(2) / R(WI);
-#pragma unroll
-    for (int i = 0; i < WI; ++i)
-      cosh_kernel_d<R>((tau - R(0.5) * R(WI) + R(i)) * hw, beta, icb, f + i, df + i);
-  }
-}
 
 // ------------------------------------------------------------------ fill
 template <class T>
@@ -390,6 +319,8 @@ __device__ __forceinline__ void add_row_pairs(uint32_t* acc, int rb, const uint3
   add_pairs<W>(p, par, q, std::make_integer_sequence<int, (W + 2) / 2>{});
 }
 
+constexpr int kCovTmp = 32 * 48;  // T <= 32 along the last two axes, w <= 16
+
 template <class R, int D, int W>
 __global__ void spread_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, R* __restrict__ tiles) {
@@ -406,11 +337,68 @@ __global__ void spread_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__
     for (int c = threadIdx.x; c < ncell; c += blockDim.x) out[c] = R(0);
     return;  // uniform across the block
   }
+  // Fixed-point scale from a bound on the number of points whose footprints
+  // cover one cell (each contributes at most 1): the tile's footprint starts are
+  // counted per column over the last two axes (2D: exactly per start cell), and
+  // the largest w x w box sum of those counts bounds every cell's contributors.
+  __shared__ uint32_t smax[16];
+  __shared__ uint32_t cov_tmp[kCovTmp];
+  uint32_t cov;
+  {
+    const int Ta = (D == 3) ? g.T[1] : g.T[0], Tb = (D == 3) ? g.T[2] : g.T[1];
+    const int Ea = Ta + W - 1, Eb = Tb + W - 1;
+    uint32_t* cnt = acc32;  // Ta Tb <= ncell words, before the accumulator is cleared
+    for (int c = threadIdx.x; c < Ta * Tb; c += blockDim.x) cnt[c] = 0u;
+    __syncthreads();
+    for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
+      const uint32_t cl = rec[j].cell;
+      const int la = (D == 3) ? (int)((cl >> 8) & 0xff) : (int)(cl & 0xff);
+      const int lb = (D == 3) ? (int)((cl >> 16) & 0xff) : (int)((cl >> 8) & 0xff);
+      atomicAdd(cnt + lb * Ta + la, 1u);
+    }
+    __syncthreads();
+    // separable box sum: along a into tmp[yb][ia], then along b
+    uint32_t mx = 0;
+    if (Tb * Ea <= kCovTmp) {
+      for (int o = threadIdx.x; o < Tb * Ea; o += blockDim.x) {
+        const int yb = o / Ea, ia = o - (o / Ea) * Ea;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int ta = 0; ta < W; ++ta) {
+          const int ya = ia - ta;
+          if (ya >= 0 && ya < Ta) sum += cnt[yb * Ta + ya];
+        }
+        cov_tmp[o] = sum;
+      }
+      __syncthreads();
+      for (int o = threadIdx.x; o < Ea * Eb; o += blockDim.x) {
+        const int ib = o / Ea, ia = o - (o / Ea) * Ea;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int tb = 0; tb < W; ++tb) {
+          const int yb = ib - tb;
+          if (yb >= 0 && yb < Tb) sum += cov_tmp[yb * Ea + ia];
+        }
+        mx = sum > mx ? sum : mx;
+      }
+    } else {
+      mx = (uint32_t)(e - s);  // every point of the tile
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t o = (uint32_t)__shfl_down((int)mx, off, 64);
+      mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    cov = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) cov = smax[w] > cov ? smax[w] : cov;
+    __syncthreads();
+  }
   for (int c = threadIdx.x; c < ncell + 2; c += blockDim.x) {
     if (F32) acc32[c] = 0u;
     else acc64[c] = 0ull;
   }
-  const int ex = fixed_exponent(e - s, F32 ? 31 : 63);
+  const int ex = fixed_exponent((long long)cov, F32 ? 31 : 63);
   const R scale = (R)ldexp(1.0, ex);
   const R inv_scale = (R)ldexp(1.0, -ex);
   const R beta = (R)g.beta;

@@ -128,6 +128,28 @@ def _load():
     lib.fresco_pair_energy_grad_async.restype = i
     lib.fresco_attach_pair.argtypes = [vp, vp, ctypes.c_double]
     lib.fresco_attach_pair.restype = i
+    lib.fresco_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
+                                        ctypes.POINTER(Problem), vp]
+    lib.fresco_batch_create.restype = i
+    lib.fresco_batch_destroy.argtypes = [vp]
+    lib.fresco_batch_destroy.restype = i
+    lib.fresco_batch_offsets.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.fresco_batch_offsets.restype = i
+    lib.fresco_batch_loss_grad.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.fresco_batch_loss_grad.restype = i
+    lib.fresco_batch_loss_grad_async.argtypes = [vp, vp, vp, vp]
+    lib.fresco_batch_loss_grad_async.restype = i
+    lib.fresco_batch_step.argtypes = [vp, vp, ctypes.POINTER(LbfgsOpts), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int32)]
+    lib.fresco_batch_step.restype = i
+    lib.fresco_batch_reset_history.argtypes = [vp]
+    lib.fresco_batch_reset_history.restype = i
+    lib.fresco_batch_autotune.argtypes = [vp, vp, vp, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32)]
+    lib.fresco_batch_autotune.restype = i
+    lib.fresco_batch_last_hip_error.argtypes = []
+    lib.fresco_batch_last_hip_error.restype = i
     lib.fresco_error_string.argtypes = [i]
     lib.fresco_error_string.restype = ctypes.c_char_p
     lib.fresco_last_hip_error.argtypes = []
@@ -393,3 +415,129 @@ class PairContext:
                                                   ctypes.c_void_p(grad.data_ptr())),
                "fresco_pair_energy_grad_async")
         return energy_dev, grad
+
+
+class BatchContext:
+    """A ragged batch of independent problems (include/fresco.h, fresco_batch_*).
+
+    items: list of dicts with keys n, box, and optionally w_cube, s0_cube, k_cut,
+    relative; all share dim, kmax, tol and dtype.  Positions and gradients are the
+    [n_b][dim] rows of every configuration concatenated in order.
+    """
+
+    def __init__(self, dim: int, kmax, items, *, tol: float = 1e-6, dtype: str = "f32",
+                 stream=None, device=None):
+        torch = _torch()
+        self.dim = int(dim)
+        self.dtype = dtype
+        self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        kmax = np.broadcast_to(np.asarray(kmax, dtype=np.int64), (self.dim,))
+        self.kmax = tuple(int(x) for x in kmax)
+        self.cube_shape = tuple(2 * m + 1 for m in self.kmax)
+        self.nb = len(items)
+        probs = (Problem * self.nb)()
+        self._keep = []
+        for b, it in enumerate(items):
+            p = probs[b]
+            p.dim = self.dim
+            p.dtype = F32 if dtype == "f32" else F64
+            p.n = int(it["n"])
+            box = np.broadcast_to(np.asarray(it["box"], dtype=np.float64), (self.dim,))
+            for a in range(3):
+                p.box[a] = float(box[a]) if a < self.dim else 1.0
+                p.kmax[a] = self.kmax[a] if a < self.dim else 0
+            p.k_cut = float(it.get("k_cut", 0.0))
+            if it.get("w_cube") is not None:
+                w = np.ascontiguousarray(np.asarray(it["w_cube"], dtype=np.float64).reshape(self.cube_shape))
+                self._keep.append(w)
+                p.w = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            if it.get("s0_cube") is not None:
+                s0 = np.ascontiguousarray(np.asarray(it["s0_cube"], dtype=np.float64).reshape(self.cube_shape))
+                self._keep.append(s0)
+                p.s0 = s0.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            p.weight_mode = WEIGHT_RELATIVE if it.get("relative", False) else WEIGHT_ABS
+            p.tol = float(tol)
+            p.upsampfac = 2.0
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.fresco_batch_create(ctypes.byref(h), self.nb, probs,
+                                            ctypes.c_void_p(stream.cuda_stream)), "fresco_batch_create")
+        self._h = h
+        self._keep = None
+        off = (ctypes.c_int64 * (self.nb + 1))()
+        _check(_lib.fresco_batch_offsets(self._h, off), "fresco_batch_offsets")
+        self.offsets = np.array(list(off), dtype=np.int64)
+        self.rows = int(self.offsets[-1])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.fresco_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _pos(self, pos):
+        if pos.device != self.device or pos.dtype != self.torch_dtype:
+            raise ValueError(f"positions must be {self.torch_dtype} on {self.device}")
+        if tuple(pos.shape) != (self.rows, self.dim) or not pos.is_contiguous():
+            raise ValueError(f"positions must be a contiguous [{self.rows}][{self.dim}] tensor")
+        return ctypes.c_void_p(pos.data_ptr())
+
+    def loss_grad(self, pos, grad=None):
+        """(per-configuration losses as a numpy array, concatenated gradient)."""
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty((self.rows, self.dim), dtype=self.torch_dtype, device=self.device)
+        losses = np.zeros(self.nb)
+        _check(_lib.fresco_batch_loss_grad(self._h, self._pos(pos),
+                                           losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           ctypes.c_void_p(grad.data_ptr())), "fresco_batch_loss_grad")
+        return losses, grad
+
+    def loss_grad_async(self, pos, losses_dev, grad):
+        _check(_lib.fresco_batch_loss_grad_async(
+            self._h, self._pos(pos),
+            ctypes.c_void_p(losses_dev.data_ptr()) if losses_dev is not None else None,
+            ctypes.c_void_p(grad.data_ptr())), "fresco_batch_loss_grad_async")
+        return losses_dev, grad
+
+    def step(self, pos, n_iter: int, *, m: int = 8, max_step: float, c1: float = 1e-4,
+             shrink: float = 0.5, max_backtracks: int = 20, gtol: float = 0.0):
+        """n_iter L-BFGS iterations on the batch (pos updated in place).
+        Returns (total loss, evaluations)."""
+        o = LbfgsOpts()
+        o.m = m
+        o.max_backtracks = max_backtracks
+        o.max_step = float(max_step)
+        o.c1 = c1
+        o.shrink = shrink
+        o.gtol = gtol
+        loss = ctypes.c_double(0.0)
+        nev = ctypes.c_int32(0)
+        _check(_lib.fresco_batch_step(self._h, self._pos(pos), ctypes.byref(o), int(n_iter),
+                                      ctypes.byref(loss), ctypes.byref(nev)), "fresco_batch_step")
+        return float(loss.value), int(nev.value)
+
+    def reset_history(self):
+        _check(_lib.fresco_batch_reset_history(self._h), "fresco_batch_reset_history")
+
+    def autotune(self, pos, reps: int = 5) -> int:
+        """Pick the fastest workgroup size for this batch; returns it."""
+        torch = _torch()
+        grad = torch.empty((self.rows, self.dim), dtype=self.torch_dtype, device=self.device)
+        t = ctypes.c_int32(0)
+        _check(_lib.fresco_batch_autotune(self._h, self._pos(pos), ctypes.c_void_p(grad.data_ptr()),
+                                          int(reps), ctypes.byref(t)), "fresco_batch_autotune")
+        return int(t.value)
