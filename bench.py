@@ -68,6 +68,41 @@ def stage_bytes(cfg, info, dtype_bytes):
     return b
 
 
+_STAGE_SOURCES = {
+    "spread.hip": ("bin", "spread", "fold", "interp"),
+    "fft.hip": ("fft_rows_fwd", "fft_cols_fwd", "modes", "fft_cols_inv", "fft_rows_inv"),
+}
+
+
+def stage_source_hash(stage):
+    """sha256 of the sources that define a stage's kernel (with their headers)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2305_15693_amd", "csrc")
+    main = [f for f, st in _STAGE_SOURCES.items() if stage in st]
+    files = main + ["kernels.h", "common.h"] if main == ["spread.hip"] else \
+        main + ["fft_lds.h", "fft.h", "common.h"]
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, stage):
+    """HBM bytes per launch of a stage's kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or None when there
+    is none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    k = t.get("kernels", {}).get(stage)
+    if not k or k.get("source_sha256") != stage_source_hash(stage):
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
 def measure(name, steps, warmup, dev, lbfgs_steps):
     import numpy as np
     import torch
@@ -134,8 +169,8 @@ def measure(name, steps, warmup, dev, lbfgs_steps):
                loss0=loss0,
                roofline={"bound": "hbm", "kernel": dominant, "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": None, "algorithmic_bytes": sbytes[dominant],
-                         "avg_ms": dom_ms},
+                         "traffic": measured_traffic(name, dominant),
+                         "algorithmic_bytes": sbytes[dominant], "avg_ms": dom_ms},
                pos_np=pos_np, w=w, s0=s0)
 
     if lbfgs_steps:
@@ -332,6 +367,8 @@ def main():
                     help="second workload measured the same way ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch measurement")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB device copy first (counter calibration in profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); "
@@ -342,6 +379,16 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # a plain device copy of known size, for scaling the HBM byte counters of a
+        # profiler run (FETCH_SIZE / WRITE_SIZE read for it vs 1 GiB moved each way)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     r = measure(args.workload, 50, args.warmup, dev, args.steps)
     print(f"[bench] {args.workload}: L-BFGS {r['lbfgs_evals_per_s']:.1f} evals/s, "
           f"plain {r['plain_evals_per_s']:.1f} evals/s", file=sys.stderr, flush=True)

@@ -23,7 +23,27 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
                 "-packed-fp32-ops"]
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-          "-Wno-unused-command-line-argument"]
+          "-I", OBJDIR, "-Wno-unused-command-line-argument"]
+
+
+def _generate_tables() -> None:
+    """Build and run csrc/gen_tables.cpp: writes _build/kernel_tables.h (the FP32
+    kernel polynomials as compile-time constants)."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    exe = os.path.join(OBJDIR, "gen_tables")
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           "-D__HIP_PLATFORM_AMD__", os.path.join(CSRC, "gen_tables.cpp"),
+           os.path.join(CSRC, "plan.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("table generator failed to build")
+    out = os.path.join(OBJDIR, "kernel_tables.h")
+    r = subprocess.run([exe, out + ".tmp"], capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("table generator failed")
+    os.replace(out + ".tmp", out)
 
 
 def _compile(src: str) -> str:
@@ -42,7 +62,8 @@ def _compile(src: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    _generate_tables()
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", *DEVICE_FLAGS, *objs, "-o", tmp]

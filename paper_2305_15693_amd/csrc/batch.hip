@@ -40,7 +40,6 @@ namespace fresco {
 constexpr int kBatchMaxB = 4;  // butterflies per thread per stage
 
 struct BatchTables {  // device memory, read with uniform loads
-  KernelPolys kp;
   FftFactors F[3];
 };
 
@@ -147,7 +146,6 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchGeom g, BatchPtrs<R> p
   U* acc = reinterpret_cast<U*>(buf + g.ngrid);
   cpx<R>* coef = reinterpret_cast<cpx<R>*>(acc);  // mode coefficients reuse the same space
   __shared__ double red[16];
-  const KernelPolys& kp = p.tab->kp;
   const int nf0 = g.nf[0], nf1 = g.nf[1], nf2 = g.nf[2];
   const R beta = (R)g.beta, beta_i = (R)g.beta_i;
   const R icb = (R)(1.0 / cosh(g.beta_i));
@@ -224,9 +222,9 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchGeom g, BatchPtrs<R> p
       for (int a = 0; a < D; ++a)
         tau[a] = (R)grid_split((double)pos[j * D + a], item.ufac[a], g.nf[a], hw, &l0[a], &bad);
       R k0[W], k1[W], k2[W];
-      spread_weights<R, W>(kp, tau[0], beta, k0);
-      spread_weights<R, W>(kp, tau[1], beta, k1);
-      if (D == 3) spread_weights<R, W>(kp, tau[2], beta, k2);
+      spread_weights<R, W>(tau[0], beta, k0);
+      spread_weights<R, W>(tau[1], beta, k1);
+      if (D == 3) spread_weights<R, W>(tau[2], beta, k2);
       int xs[W];
 #pragma unroll
       for (int dx = 0; dx < W; ++dx) xs[dx] = wrap_index(l0[0] + dx, nf0);
@@ -315,9 +313,9 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchGeom g, BatchPtrs<R> p
         const int k = (t >= R(0.5)) ? 1 : 0;
         const R ti = k ? t - R(0.5) : t + R(0.5);
         s[a] = l0 - k;
-        if (a == 0) interp_weights<R, WI>(kp, ti, beta_i, icb, f0, d0);
-        else if (a == 1) interp_weights<R, WI>(kp, ti, beta_i, icb, f1, d1);
-        else interp_weights<R, WI>(kp, ti, beta_i, icb, f2, d2);
+        if (a == 0) interp_weights<R, WI>(ti, beta_i, icb, f0, d0);
+        else if (a == 1) interp_weights<R, WI>(ti, beta_i, icb, f1, d1);
+        else interp_weights<R, WI>(ti, beta_i, icb, f2, d2);
       }
       int xs[WI];
 #pragma unroll
@@ -544,21 +542,9 @@ template <class R>
 int batch_build(fresco_batch_ctx* c, int nb, const fresco_problem* ps) {
   BatchGeom& g = c->g;
   const int d = g.d;
-  // shared tables: kernel polynomials and FFT plans
+  // shared tables: FFT plans
   BatchTables tab;
   std::memset(&tab, 0, sizeof(tab));
-  {
-    const std::vector<double> sp = kernel_poly(g.w, g.beta, 0, kPolyDeg);
-    const std::vector<double> ip = kernel_poly(g.wi, g.beta_i, 1, kPolyDeg);
-    const std::vector<double> id = kernel_poly(g.wi, g.beta_i, 2, kPolyDeg);
-    for (int j = 0; j < g.w; ++j)
-      for (int k = 0; k <= kPolyDeg; ++k) tab.kp.sp[j][k] = (float)sp[j * (kPolyDeg + 1) + k];
-    for (int j = 0; j < g.wi; ++j)
-      for (int k = 0; k <= kPolyDeg; ++k) {
-        tab.kp.ip[j][k] = (float)ip[j * (kPolyDeg + 1) + k];
-        tab.kp.id[j][k] = (float)id[j * (kPolyDeg + 1) + k];
-      }
-  }
   int st;
   for (int a = 0; a < d; ++a) {
     int rmin = 1;

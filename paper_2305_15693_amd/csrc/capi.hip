@@ -46,7 +46,6 @@ namespace {
 template <class R>
 struct State {
   AxisFft<R> ax[3];  // [0] rows: complex length nf0/2; [1], [2]: columns along axes 1, 2
-  KernelPolys kp;    // FP32 kernel polynomials
   BinPlan bp;
   BinBuffers bb;
   R* tiles = nullptr;  // padded spreading tiles
@@ -313,21 +312,6 @@ int create_state(fresco_ctx* c) {
   const int d = g.d;
   const size_t cs = sizeof(cpx<R>);
   int st;
-  // kernel polynomials (spreading: exponential of semicircle, width w; interpolation:
-  // its cosh form and derivative, width w + 1)
-  {
-    std::memset(&S->kp, 0, sizeof(S->kp));
-    const std::vector<double> sp = kernel_poly(g.w, g.beta, 0, kPolyDeg);
-    const std::vector<double> ip = kernel_poly(g.wi, g.beta_i, 1, kPolyDeg);
-    const std::vector<double> id = kernel_poly(g.wi, g.beta_i, 2, kPolyDeg);
-    for (int j = 0; j < g.w; ++j)
-      for (int k = 0; k <= kPolyDeg; ++k) S->kp.sp[j][k] = (float)sp[j * (kPolyDeg + 1) + k];
-    for (int j = 0; j < g.wi; ++j)
-      for (int k = 0; k <= kPolyDeg; ++k) {
-        S->kp.ip[j][k] = (float)ip[j * (kPolyDeg + 1) + k];
-        S->kp.id[j][k] = (float)id[j * (kPolyDeg + 1) + k];
-      }
-  }
   // FFT plans
   if ((st = setup_axis<R>(c, &S->ax[0], g.nf[0] / 2, true))) return st;
   if ((st = setup_axis<R>(c, &S->ax[1], g.nf[1], false))) return st;
@@ -515,7 +499,7 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
   }
   {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
-    launch_spread<R>(g, S->kp, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
+    launch_spread<R>(g,(const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
   }
   {
     StageTimer t(c, FRESCO_STAGE_FOLD);
@@ -593,7 +577,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
   }
   {
     StageTimer t(c, FRESCO_STAGE_INTERP);
-    launch_interp<R>(g, S->kp, (const Rec<R>*)S->bb.rec, S->bb.start, S->bb.perm, S->v, grad,
+    launch_interp<R>(g,(const Rec<R>*)S->bb.rec, S->bb.start, S->bb.perm, S->v, grad,
                      st);
   }
   // attached soft-core pair term: its gradient is added to grad, its energy to

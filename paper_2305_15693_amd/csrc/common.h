@@ -102,15 +102,9 @@ struct alignas(4 * sizeof(R)) Rec {
   uint32_t cell;
 };
 
-// FP32 kernels evaluate the spreading and interpolation kernels as polynomials
-// in x = 2 tau - 1, one per footprint cell (coefficients from plan.cpp).
+// FP32 kernels evaluate the spreading and interpolation kernels as per-cell
+// polynomials of this degree in x = 2 tau - 1 (see plan.h, kernel_poly).
 constexpr int kPolyDeg = 9;
-constexpr int kPolyW = 17;
-struct KernelPolys {
-  float sp[kPolyW][kPolyDeg + 1];  // spreading kernel, w cells
-  float ip[kPolyW][kPolyDeg + 1];  // interpolation kernel, w + 1 cells
-  float id[kPolyW][kPolyDeg + 1];  // derivative d/dz of the interpolation kernel
-};
 
 // Counting sort of the points by tile.
 struct BinPlan {
@@ -146,12 +140,12 @@ size_t interp_lds_bytes(const Geom& g);
 template <class R>
 void spread_prepare(const Geom& g);
 template <class R>
-void launch_spread(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
+void launch_spread(const Geom& g, const Rec<R>* rec,
                    const long long* start, R* tiles, hipStream_t st);
 template <class R>
 void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, hipStream_t st);
 template <class R>
-void launch_interp(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
+void launch_interp(const Geom& g, const Rec<R>* rec,
                    const long long* start, const int* perm, const R* v, R* grad,
                    hipStream_t st);
 template <class R>

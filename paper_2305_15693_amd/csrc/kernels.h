@@ -9,6 +9,7 @@
 #pragma once
 
 #include "common.h"
+#include "kernel_tables.h"
 
 namespace fresco {
 
@@ -47,20 +48,12 @@ __device__ __forceinline__ void cosh_kernel_d(R z, R beta, R inv_cosh_beta, R* f
 }
 
 // Kernel values on the W footprint cells of one axis from tau in [0, 1):
-// FP32 evaluates the per-cell polynomials (x = 2 tau - 1), FP64 the closed forms.
-template <int W>
-__device__ __forceinline__ float poly_eval(const float (&c)[kPolyDeg + 1], float x) {
-  float r = c[kPolyDeg];
-#pragma unroll
-  for (int k = kPolyDeg - 1; k >= 0; --k) r = fmaf(r, x, c[k]);
-  return r;
-}
+// FP32 evaluates the per-cell polynomials in x = 2 tau - 1 (coefficients are
+// compile-time literals from the generated kernel_tables.h), FP64 the closed forms.
 template <class R, int W>
-__device__ __forceinline__ void spread_weights(const KernelPolys& kp, R tau, R beta, R* k) {
+__device__ __forceinline__ void spread_weights(R tau, R beta, R* k) {
   if constexpr (sizeof(R) == 4) {
-    const float x = 2.f * tau - 1.f;
-#pragma unroll
-    for (int i = 0; i < W; ++i) k[i] = poly_eval<W>(kp.sp[i], x);
+    tab::Poly<W>::es(2.f * tau - 1.f, k);
   } else {
     const R hw = R(2) / R(W);
 #pragma unroll
@@ -69,15 +62,11 @@ __device__ __forceinline__ void spread_weights(const KernelPolys& kp, R tau, R b
 }
 // interpolation kernel (width WI) and its z-derivative
 template <class R, int WI>
-__device__ __forceinline__ void interp_weights(const KernelPolys& kp, R tau, R beta, R icb,
-                                               R* f, R* df) {
+__device__ __forceinline__ void interp_weights(R tau, R beta, R icb, R* f, R* df) {
   if constexpr (sizeof(R) == 4) {
     const float x = 2.f * tau - 1.f;
-#pragma unroll
-    for (int i = 0; i < WI; ++i) {
-      f[i] = poly_eval<WI>(kp.ip[i], x);
-      df[i] = poly_eval<WI>(kp.id[i], x);
-    }
+    tab::Poly<WI>::ch(x, f);
+    tab::Poly<WI>::dch(x, df);
   } else {
     const R hw = R(2) / R(WI);
 #pragma unroll

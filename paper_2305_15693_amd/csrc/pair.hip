@@ -44,6 +44,7 @@ struct PairGeom {
   long long n;
   double L[3];
   double cfac[3];  // nc / L
+  double invL[3];  // 1 / L
   int nc[3];
   double sigma, eps, alpha;
 };
@@ -59,7 +60,7 @@ __device__ __forceinline__ uint32_t pair_cell(const PairGeom& g, const R* r, int
         *bad = true;
         x = 0.0;
       }
-      double u = x - g.L[a] * floor(x / g.L[a]);
+      double u = x - g.L[a] * floor(x * g.invL[a]);  // clamped below if rounding lands on L
       ka = (int)(u * g.cfac[a]);
       if (ka < 0) ka = 0;
       if (ka >= g.nc[a]) ka = g.nc[a] - 1;
@@ -216,6 +217,23 @@ __global__ void pair_force_kernel(PairGeom g, const PairRec<R>* __restrict__ sor
     const double s2 = g.sigma * g.sigma;
     const double isig = 1.0 / g.sigma;
     double acc[3] = {0.0, 0.0, 0.0};
+    // the neighbour cells along x of one (y, z) row are consecutive in the cell
+    // order: at most two runs of records per row (one more where the row wraps)
+    int ra0[2], ra1[2], nrun;
+    {
+      const int n0 = g.nc[0], k0 = k[0];
+      if (lo[0] == 0 && hi[0] == 0) {
+        ra0[0] = 0; ra1[0] = 0; nrun = 1;
+      } else if (lo[0] == 0) {  // two cells along x
+        ra0[0] = 0; ra1[0] = 1; nrun = 1;
+      } else if (k0 == 0) {
+        ra0[0] = 0; ra1[0] = 1; ra0[1] = n0 - 1; ra1[1] = n0 - 1; nrun = 2;
+      } else if (k0 == n0 - 1) {
+        ra0[0] = n0 - 2; ra1[0] = n0 - 1; ra0[1] = 0; ra1[1] = 0; nrun = 2;
+      } else {
+        ra0[0] = k0 - 1; ra1[0] = k0 + 1; nrun = 1;
+      }
+    }
     for (int oz = lo[2]; oz <= hi[2]; ++oz) {
       int cz = k[2] + oz;
       if (cz < 0) cz += g.nc[2];
@@ -224,12 +242,9 @@ __global__ void pair_force_kernel(PairGeom g, const PairRec<R>* __restrict__ sor
         int cy = k[1] + oy;
         if (cy < 0) cy += g.nc[1];
         if (cy >= g.nc[1]) cy -= g.nc[1];
-        for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-          int cx = k[0] + ox;
-          if (cx < 0) cx += g.nc[0];
-          if (cx >= g.nc[0]) cx -= g.nc[0];
-          const uint32_t q = (uint32_t)cx + (uint32_t)g.nc[0] * ((uint32_t)cy + (uint32_t)g.nc[1] * (uint32_t)cz);
-          const uint32_t b = start[q], en = start[q + 1];
+        const uint32_t row = (uint32_t)g.nc[0] * ((uint32_t)cy + (uint32_t)g.nc[1] * (uint32_t)cz);
+        for (int rr = 0; rr < nrun; ++rr) {
+          const uint32_t b = start[row + ra0[rr]], en = start[row + ra1[rr] + 1];
           for (uint32_t t = b; t < en; ++t) {
             const PairRec<R> o = sorted[t];
             if (o.idx == me.idx) continue;
@@ -237,7 +252,7 @@ __global__ void pair_force_kernel(PairGeom g, const PairRec<R>* __restrict__ sor
             for (int a = 0; a < 3; ++a) {
               if (a < g.d) {
                 double v = (double)me.x[a] - (double)o.x[a];
-                v -= g.L[a] * rint(v / g.L[a]);
+                v -= g.L[a] * rint(v * g.invL[a]);
                 dx[a] = v;
                 r2 += v * v;
               } else {
@@ -307,6 +322,7 @@ static PairGeom pair_geom(const fresco_pair_ctx* pc) {
     g.L[a] = pc->L[a];
     g.nc[a] = pc->nc[a];
     g.cfac[a] = (double)pc->nc[a] / pc->L[a];
+    g.invL[a] = 1.0 / pc->L[a];
   }
   g.sigma = pc->sigma;
   g.eps = pc->eps;

@@ -322,7 +322,7 @@ __device__ __forceinline__ void add_row_pairs(uint32_t* acc, int rb, const uint3
 constexpr int kCovTmp = 32 * 48;  // T <= 32 along the last two axes, w <= 16
 
 template <class R, int D, int W>
-__global__ void spread_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__ rec,
+__global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, R* __restrict__ tiles) {
   constexpr bool F32 = sizeof(R) == 4;
   extern __shared__ unsigned long long smem_u64[];
@@ -406,9 +406,9 @@ __global__ void spread_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__
   for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
     const Rec<R> p = rec[j];
     R k0[W], k1[W], k2[W];
-    spread_weights<R, W>(kp, p.t[0], beta, k0);
-    spread_weights<R, W>(kp, p.t[1], beta, k1);
-    if (D == 3) spread_weights<R, W>(kp, p.t[2], beta, k2);
+    spread_weights<R, W>(p.t[0], beta, k0);
+    spread_weights<R, W>(p.t[1], beta, k1);
+    if (D == 3) spread_weights<R, W>(p.t[2], beta, k2);
     const int l0 = p.cell & 0xff, l1 = (p.cell >> 8) & 0xff, l2 = (p.cell >> 16) & 0xff;
     const int zmax = (D == 3) ? W : 1;
     for (int dz = 0; dz < zmax; ++dz) {
@@ -473,7 +473,7 @@ __global__ void fold_kernel(Geom g, FoldTables ft, const R* __restrict__ tiles,
 // Field tile origin is one cell before the spreading tile (width w + 1), extent
 // T + w + 1 per axis (g.Ei).
 template <class R, int D, int W>
-__global__ void interp_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__ rec,
+__global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, const int* __restrict__ perm,
                               const R* __restrict__ v, R* __restrict__ grad) {
   constexpr int WI = W + 1;
@@ -518,9 +518,9 @@ __global__ void interp_kernel(Geom g, KernelPolys kp, const Rec<R>* __restrict__
       const int k = (p.t[a] >= R(0.5)) ? 1 : 0;
       const R ti = k ? p.t[a] - R(0.5) : p.t[a] + R(0.5);
       l[a] = cl[a] - k + 1;
-      if (a == 0) interp_weights<R, WI>(kp, ti, beta, icb, f0, d0);
-      else if (a == 1) interp_weights<R, WI>(kp, ti, beta, icb, f1, d1);
-      else interp_weights<R, WI>(kp, ti, beta, icb, f2, d2);
+      if (a == 0) interp_weights<R, WI>(ti, beta, icb, f0, d0);
+      else if (a == 1) interp_weights<R, WI>(ti, beta, icb, f1, d1);
+      else interp_weights<R, WI>(ti, beta, icb, f2, d2);
     }
     R gx = R(0), gy = R(0), gz = R(0);
     const int zmax = (D == 3) ? WI : 1;
@@ -611,17 +611,17 @@ void spread_prepare(const Geom& g) {
 }
 
 template <class R>
-void launch_spread(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
+void launch_spread(const Geom& g, const Rec<R>* rec,
                    const long long* start, R* tiles, hipStream_t st) {
   const size_t lds = spread_lds_bytes<R>(g);
   const int threads = (g.d == 3) ? 512 : 256;
 #define SP(W)                                                                                 \
   do {                                                                                        \
     if (g.d == 2)                                                                             \
-      spread_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, kp, rec, start,      \
+      spread_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
                                                                       tiles);                 \
     else                                                                                      \
-      spread_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, kp, rec, start,      \
+      spread_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
                                                                       tiles);                 \
   } while (0)
   FRESCO_W_SWITCH(g.w, SP)
@@ -638,7 +638,7 @@ void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, h
 }
 
 template <class R>
-void launch_interp(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
+void launch_interp(const Geom& g, const Rec<R>* rec,
                    const long long* start, const int* perm, const R* v, R* grad,
                    hipStream_t st) {
   const size_t lds = interp_lds_bytes<R>(g);
@@ -646,10 +646,10 @@ void launch_interp(const Geom& g, const KernelPolys& kp, const Rec<R>* rec,
 #define IP(W)                                                                                 \
   do {                                                                                        \
     if (g.d == 2)                                                                             \
-      interp_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, kp, rec, start,      \
+      interp_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
                                                                       perm, v, grad);         \
     else                                                                                      \
-      interp_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, kp, rec, start,      \
+      interp_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
                                                                       perm, v, grad);         \
   } while (0)
   FRESCO_W_SWITCH(g.w, IP)
@@ -662,18 +662,18 @@ template size_t interp_lds_bytes<float>(const Geom&);
 template size_t interp_lds_bytes<double>(const Geom&);
 template void spread_prepare<float>(const Geom&);
 template void spread_prepare<double>(const Geom&);
-template void launch_spread<float>(const Geom&, const KernelPolys&, const Rec<float>*,
+template void launch_spread<float>(const Geom&, const Rec<float>*,
                                    const long long*, float*, hipStream_t);
-template void launch_spread<double>(const Geom&, const KernelPolys&, const Rec<double>*,
+template void launch_spread<double>(const Geom&, const Rec<double>*,
                                     const long long*, double*, hipStream_t);
 template void launch_fold<float>(const Geom&, const float*, float*, const FoldTables&,
                                  hipStream_t);
 template void launch_fold<double>(const Geom&, const double*, double*, const FoldTables&,
                                   hipStream_t);
-template void launch_interp<float>(const Geom&, const KernelPolys&, const Rec<float>*,
+template void launch_interp<float>(const Geom&, const Rec<float>*,
                                    const long long*, const int*, const float*, float*,
                                    hipStream_t);
-template void launch_interp<double>(const Geom&, const KernelPolys&, const Rec<double>*,
+template void launch_interp<double>(const Geom&, const Rec<double>*,
                                     const long long*, const int*, const double*, double*,
                                     hipStream_t);
 
