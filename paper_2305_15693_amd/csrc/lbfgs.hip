@@ -228,7 +228,9 @@ __device__ __forceinline__ void lb_small_solve(LbfgsState* S, const LbfgsOpts& o
   }
   // chronological slots: c[0] oldest ... c[k-1] newest
   const int k = S->k;
-  int cs[kLbfgsMaxM];
+  // small arrays with runtime indices live in LDS (private arrays would go to
+  // scratch memory)
+  __shared__ int cs[kLbfgsMaxM];
   for (int i = 0; i < k; ++i) cs[i] = (S->head - (k - 1) + i + m) % m;
   for (int j = 0; j < m; ++j) {
     S->coefS[j] = 0.0;
@@ -240,7 +242,8 @@ __device__ __forceinline__ void lb_small_solve(LbfgsState* S, const LbfgsOpts& o
     gtp = -S->gg;
   } else {
     const double gam = S->gamma;
-    double a[kLbfgsMaxM], b[kLbfgsMaxM], t[kLbfgsMaxM], w[kLbfgsMaxM], u[kLbfgsMaxM];
+    __shared__ double a[kLbfgsMaxM], b[kLbfgsMaxM], t[kLbfgsMaxM], w[kLbfgsMaxM],
+        u[kLbfgsMaxM];
     for (int i = 0; i < k; ++i) {
       a[i] = S->SG[cs[i]];
       b[i] = S->YG[cs[i]];
