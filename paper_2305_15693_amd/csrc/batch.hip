@@ -1,31 +1,31 @@
 // Batched evaluation of many independent small problems (a ragged batch of
-// configurations with their own N, box and target) in one persistent launch,
-// and L-BFGS over the batch with one captured graph per trial step.
+// configurations with their own N, box and target), and L-BFGS over the batch
+// with one captured graph per trial step.
 //
 // Every configuration is the problem of the main text (loss
 // sum_K W (S - S0)^2 and its position gradient, evaluated through nonuniform
-// FFTs as in the Methods), with the mode cube, accuracy and therefore the fine
-// grid shared by the batch.  A workgroup takes whole configurations (largest
-// first, round robin over the workgroups) and keeps the fine grid of the one it
-// works on in LDS from start to end:
-//   spread   points -> fixed-point LDS grid with integer LDS atomics (exact and
-//            order independent; scale 2^ex with (N + 1) 2^ex <= 2^31 or 2^63)
-//   FFT      full complex transform of the grid along every axis (Stockham, in
-//            LDS), exp(+i k.r)
-//   modes    every mode of the cube: rho = FFT * prod h / psihat, S = |rho|^2 / N,
-//            loss += W (S - S0)^2 (FP64), field coefficient
-//            C(n) = 4 W (S - S0) rho / N * prod h / psihat_i (no half-spectrum
-//            bookkeeping: both n and -n are visited)
-//   inverse  complex transform with exp(-i k.x); the field is its real part
-//   interp   derivative interpolation of the field at every point (cosh-form
-//            kernel of width w + 1) = gradient
-// Nothing of a configuration leaves the CU except its gradient rows and loss.
+// FFTs as in the Methods); the mode cube, the accuracy and therefore the fine
+// grid are shared by the batch, and a configuration's whole grid fits in LDS.
+// The points of all configurations are cut into chunks (work items) of at most
+// `chunk` points, so that a batch of very uneven configurations still spreads
+// its work evenly over the CUs.  One evaluation is three launches:
+//   spread   per work item: points -> fixed-point LDS grid with integer LDS
+//            atomics (exact, order independent; scale 2^ex from a bound on the
+//            points that cover one cell) -> the item's partial grid;
+//   modes    per configuration: sum of its items' partial grids (fixed order),
+//            full complex FFT in LDS (exp(+i k.r)), every mode of the cube:
+//            rho = FFT * prod h / psihat, S = |rho|^2 / N, loss += W (S - S0)^2
+//            (FP64), field coefficient C(n) = 4 W (S - S0) rho / N * prod h / psihat_i
+//            (both n and -n are visited, no half-spectrum bookkeeping), inverse
+//            FFT (exp(-i k.x)); the field is its real part;
+//   interp   per work item: the configuration's field in LDS, derivative
+//            interpolation at every point (cosh-form kernel of width w + 1).
+// The chunk size and the workgroup size are picked by the autotuner.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
-#include <numeric>
 #include <type_traits>
 #include <vector>
 
@@ -38,6 +38,8 @@
 namespace fresco {
 
 constexpr int kBatchMaxB = 4;  // butterflies per thread per stage
+constexpr int kChunkMin = 2048;
+constexpr int kChunks[5] = {2048, 4096, 8192, 16384, 32768};
 
 struct BatchTables {  // device memory, read with uniform loads
   FftFactors F[3];
@@ -67,7 +69,6 @@ template <class R>
 struct BatchPtrs {
   const BatchTables* tab;
   const BatchItem* items;
-  const int* order;  // configurations, largest first
   const R* W;        // [nb][ncube] weights (relative normalisation applied)
   const R* S0;       // [nb][ncube]
   const R* dec[3];   // h / psihat_a(|n|), n = 0..M_a (spreading kernel)
@@ -135,92 +136,97 @@ __device__ void batch_fft_axis(cpx<R>* buf, cpx<R>* tws, const cpx<R>* __restric
   __syncthreads();
 }
 
+// grid index of mode q of the cube (C order over n_0..n_{d-1}, n_{d-1} fastest)
+template <int D>
+__device__ __forceinline__ int mode_grid_index(const BatchGeom& g, int q, int* na) {
+  int rem = q;
+  for (int a = D - 1; a >= 0; --a) {
+    na[a] = rem % g.P[a] - g.M[a];
+    rem /= g.P[a];
+  }
+  int idx = 0, stride = 1;
+  for (int a = 0; a < D; ++a) {
+    idx += (na[a] < 0 ? na[a] + g.nf[a] : na[a]) * stride;
+    stride *= g.nf[a];
+  }
+  return idx;
+}
+
+// work item: x = configuration, y = first point inside it, z = points
 template <class R, int D, int W>
-__global__ void __launch_bounds__(1024) batch_kernel(BatchGeom g, BatchPtrs<R> p) {
+__global__ void __launch_bounds__(1024)
+    batch_spread_kernel(BatchGeom g, BatchPtrs<R> p, const int4* __restrict__ work, int nwork,
+                        R* __restrict__ part) {
   using U = typename std::conditional<sizeof(R) == 4, uint32_t, unsigned long long>::type;
   constexpr bool F32 = sizeof(R) == 4;
-  constexpr int WI = W + 1;
   extern __shared__ unsigned long long smem_u64[];
-  cpx<R>* tws = reinterpret_cast<cpx<R>*>(smem_u64);
-  cpx<R>* buf = tws + g.lds_tw;
-  U* acc = reinterpret_cast<U*>(buf + g.ngrid);
-  cpx<R>* coef = reinterpret_cast<cpx<R>*>(acc);  // mode coefficients reuse the same space
+  U* acc = reinterpret_cast<U*>(smem_u64);
+  uint32_t* tmp = reinterpret_cast<uint32_t*>(acc + g.ngrid);
   __shared__ double red[16];
   const int nf0 = g.nf[0], nf1 = g.nf[1], nf2 = g.nf[2];
-  const R beta = (R)g.beta, beta_i = (R)g.beta_i;
-  const R icb = (R)(1.0 / cosh(g.beta_i));
+  const R beta = (R)g.beta;
   const double hw = 0.5 * W;
-
-  for (int it = blockIdx.x; it < g.nb; it += gridDim.x) {
-    const int b = p.order[it];
-    const BatchItem item = p.items[b];
-    const R* __restrict__ pos = p.pos + item.off * D;
-    R* __restrict__ grad = p.grad + item.off * D;
-    const long long n = item.n;
-
-    // ---- fixed-point scale from the largest number of points whose footprints
-    // cover one cell: cnt = footprint starts per cell, cov = its periodic box sum
-    // over w^d cells (every contribution is at most 1, so a cell's sum stays below
-    // (cov + 1) 2^ex <= 2^bits)
+  for (int it = blockIdx.x; it < nwork; it += gridDim.x) {
+    const int4 wk = work[it];
+    const BatchItem item = p.items[wk.x];
+    const R* __restrict__ pos = p.pos + (item.off + wk.y) * D;
+    const int n = wk.z;
     bool bad = false;
-    double cov_max = 0.0;
-    {
-      uint32_t* cnt = reinterpret_cast<uint32_t*>(buf);  // complex grid unused until later
-      uint32_t* tmp = reinterpret_cast<uint32_t*>(acc);
-      for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) cnt[i] = 0u;
-      __syncthreads();
-      for (long long j = threadIdx.x; j < n; j += blockDim.x) {
-        int c = 0, stride = 1;
+    // fixed-point scale: cnt = footprint starts per cell, its periodic w^d box sum
+    // bounds the points covering one cell (each contributes at most 1)
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(acc);
+    for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) cnt[i] = 0u;
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      int c = 0, stride = 1;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          int l0;
-          (void)grid_split((double)pos[j * D + a], item.ufac[a], g.nf[a], hw, &l0, &bad);
-          c += wrap_index(l0, g.nf[a]) * stride;
-          stride *= g.nf[a];
-        }
-        atomicAdd(cnt + c, 1u);
-      }
-      __syncthreads();
-      uint32_t* src = cnt;
-      uint32_t* dst = tmp;
-      int stride = 1;
       for (int a = 0; a < D; ++a) {
-        const int nfa = g.nf[a];
-        for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) {
-          const int xa = (i / stride) % nfa;
-          uint32_t s = 0;
-          for (int t = 0; t < W; ++t) s += src[i + (wrap_index(xa - t, nfa) - xa) * stride];
-          dst[i] = s;
-        }
-        __syncthreads();
-        uint32_t* sw = src;
-        src = dst;
-        dst = sw;
-        stride *= nfa;
+        int l0;
+        (void)grid_split((double)pos[(long long)j * D + a], item.ufac[a], g.nf[a], hw, &l0, &bad);
+        c += wrap_index(l0, g.nf[a]) * stride;
+        stride *= g.nf[a];
       }
-      uint32_t mx = 0;
-      for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) mx = max(mx, src[i]);
-      for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_down((int)mx, off, 64));
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (double)mx;
-      __syncthreads();
-      double m = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-      cov_max = m;
-      __syncthreads();
+      atomicAdd(cnt + c, 1u);
     }
+    __syncthreads();
+    uint32_t* src = cnt;
+    uint32_t* dst = tmp;
+    int stride = 1;
+    for (int a = 0; a < D; ++a) {
+      const int nfa = g.nf[a];
+      for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) {
+        const int xa = (i / stride) % nfa;
+        uint32_t s = 0;
+        for (int t = 0; t < W; ++t) s += src[i + (wrap_index(xa - t, nfa) - xa) * stride];
+        dst[i] = s;
+      }
+      __syncthreads();
+      uint32_t* sw = src;
+      src = dst;
+      dst = sw;
+      stride *= nfa;
+    }
+    uint32_t mx = 0;
+    for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) mx = max(mx, src[i]);
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_down((int)mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (double)mx;
+    __syncthreads();
+    double cov = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) cov = fmax(cov, red[w]);
+    __syncthreads();
 
-    // ---- spread into the fixed-point grid
     for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) acc[i] = (U)0;
-    const int ex = (int)floor(log2(ldexp(1.0, F32 ? 31 : 63) / (cov_max + 1.0)));
+    const int ex = (int)floor(log2(ldexp(1.0, F32 ? 31 : 63) / (cov + 1.0)));
     const R scale = (R)ldexp(1.0, ex);
     const R inv_scale = (R)ldexp(1.0, -ex);
     __syncthreads();
-    for (long long j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
       int l0[3] = {0, 0, 0};
       R tau[3] = {R(0), R(0), R(0)};
 #pragma unroll
       for (int a = 0; a < D; ++a)
-        tau[a] = (R)grid_split((double)pos[j * D + a], item.ufac[a], g.nf[a], hw, &l0[a], &bad);
+        tau[a] = (R)grid_split((double)pos[(long long)j * D + a], item.ufac[a], g.nf[a], hw,
+                               &l0[a], &bad);
       R k0[W], k1[W], k2[W];
       spread_weights<R, W>(tau[0], beta, k0);
       spread_weights<R, W>(tau[1], beta, k1);
@@ -248,31 +254,43 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchGeom g, BatchPtrs<R> p
     }
     if (bad) atomicOr(p.flag, 1);
     __syncthreads();
-    for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x)
-      buf[i] = cpx<R>{(R)acc[i] * inv_scale, R(0)};
+    R* __restrict__ out = part + (long long)it * g.ngrid;
+    for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) out[i] = (R)acc[i] * inv_scale;
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+// citems[b] = (first work item of configuration b, its number of items)
+template <class R, int D>
+__global__ void __launch_bounds__(1024)
+    batch_modes_kernel(BatchGeom g, BatchPtrs<R> p, const int2* __restrict__ citems,
+                       const R* __restrict__ part, R* __restrict__ field) {
+  extern __shared__ unsigned long long smem_u64[];
+  cpx<R>* tws = reinterpret_cast<cpx<R>*>(smem_u64);
+  cpx<R>* buf = tws + g.lds_tw;
+  cpx<R>* coef = buf + g.ngrid;
+  __shared__ double red[16];
+  for (int b = blockIdx.x; b < g.nb; b += gridDim.x) {
+    const int2 ci = citems[b];
+    const BatchItem item = p.items[b];
+    for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) {
+      R s = R(0);
+      for (int c = 0; c < ci.y; ++c) s += part[(long long)(ci.x + c) * g.ngrid + i];
+      buf[i] = cpx<R>{s, R(0)};
+    }
     __syncthreads();
-
-    // ---- forward transform, exp(+i n l h)
     for (int a = 0; a < D; ++a) batch_fft_axis<R, false>(buf, tws, p.tw[a], p.tab->F[a], g, a);
-
-    // ---- modes: S, loss, field coefficients (into the scratch), then the grid
     double lsum = 0.0;
     const R* __restrict__ Wb = p.W + (long long)b * g.ncube;
     const R* __restrict__ S0b = p.S0 + (long long)b * g.ncube;
     for (int q = threadIdx.x; q < g.ncube; q += blockDim.x) {
-      int rem = q, idx = 0, stride = 1;
-      R dec = R(1), deci = R(1);
       int na[3] = {0, 0, 0};
-      for (int a = D - 1; a >= 0; --a) {
-        na[a] = rem % g.P[a] - g.M[a];
-        rem /= g.P[a];
-      }
+      const int idx = mode_grid_index<D>(g, q, na);
+      R dec = R(1), deci = R(1);
       for (int a = 0; a < D; ++a) {
         const int an = na[a] < 0 ? -na[a] : na[a];
         dec *= p.dec[a][an];
         deci *= p.deci[a][an];
-        idx += (na[a] < 0 ? na[a] + g.nf[a] : na[a]) * stride;
-        stride *= g.nf[a];
       }
       const cpx<R> rho = cscale(buf[idx], dec);
       const R S = (rho.x * rho.x + rho.y * rho.y) * (R)item.invN;
@@ -285,31 +303,53 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchGeom g, BatchPtrs<R> p
     for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) buf[i] = cpx<R>{R(0), R(0)};
     __syncthreads();
     for (int q = threadIdx.x; q < g.ncube; q += blockDim.x) {
-      int rem = q, idx = 0, stride = 1;
-      int na[3] = {0, 0, 0};
-      for (int a = D - 1; a >= 0; --a) {
-        na[a] = rem % g.P[a] - g.M[a];
-        rem /= g.P[a];
-      }
-      for (int a = 0; a < D; ++a) {
-        idx += (na[a] < 0 ? na[a] + g.nf[a] : na[a]) * stride;
-        stride *= g.nf[a];
-      }
-      buf[idx] = coef[q];
+      int na[3];
+      buf[mode_grid_index<D>(g, q, na)] = coef[q];
     }
     __syncthreads();
-
-    // ---- inverse transform, exp(-i n l h); the field is the real part
     for (int a = 0; a < D; ++a) batch_fft_axis<R, true>(buf, tws, p.tw[a], p.tab->F[a], g, a);
+    R* __restrict__ out = field + (long long)b * g.ngrid;
+    for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) out[i] = buf[i].x;
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+      p.loss[b] = t;
+    }
+    __syncthreads();  // LDS is reused by the next configuration
+  }
+}
 
-    // ---- gradient: derivative interpolation (width w + 1)
-    for (long long j = threadIdx.x; j < n; j += blockDim.x) {
+template <class R, int D, int W>
+__global__ void __launch_bounds__(1024)
+    batch_interp_kernel(BatchGeom g, BatchPtrs<R> p, const int4* __restrict__ work, int nwork,
+                        const R* __restrict__ field) {
+  constexpr int WI = W + 1;
+  extern __shared__ unsigned long long smem_u64[];
+  R* fl = reinterpret_cast<R*>(smem_u64);
+  const int nf0 = g.nf[0], nf1 = g.nf[1], nf2 = g.nf[2];
+  const R beta_i = (R)g.beta_i;
+  const R icb = (R)(1.0 / cosh(g.beta_i));
+  const double hw = 0.5 * W;
+  for (int it = blockIdx.x; it < nwork; it += gridDim.x) {
+    const int4 wk = work[it];
+    const BatchItem item = p.items[wk.x];
+    const R* __restrict__ src = field + (long long)wk.x * g.ngrid;
+    for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) fl[i] = src[i];
+    __syncthreads();
+    const R* __restrict__ pos = p.pos + (item.off + wk.y) * D;
+    R* __restrict__ grad = p.grad + (item.off + wk.y) * D;
+    bool bad = false;
+    for (int j = threadIdx.x; j < wk.z; j += blockDim.x) {
       int s[3] = {0, 0, 0};
       R f0[WI], d0[WI], f1[WI], d1[WI], f2[WI], d2[WI];
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         int l0;
-        const R t = (R)grid_split((double)pos[j * D + a], item.ufac[a], g.nf[a], hw, &l0, &bad);
+        const R t = (R)grid_split((double)pos[(long long)j * D + a], item.ufac[a], g.nf[a], hw,
+                                  &l0, &bad);
         const int k = (t >= R(0.5)) ? 1 : 0;
         const R ti = k ? t - R(0.5) : t + R(0.5);
         s[a] = l0 - k;
@@ -327,11 +367,11 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchGeom g, BatchPtrs<R> p
         R sxy = R(0), sdxy = R(0), sxdy = R(0);
 #pragma unroll
         for (int dy = 0; dy < WI; ++dy) {
-          const cpx<R>* row = buf + (z * nf1 + wrap_index(s[1] + dy, nf1)) * nf0;
+          const R* row = fl + (z * nf1 + wrap_index(s[1] + dy, nf1)) * nf0;
           R sx = R(0), sdx = R(0);
 #pragma unroll
           for (int dx = 0; dx < WI; ++dx) {
-            const R vv = row[xs[dx]].x;
+            const R vv = row[xs[dx]];
             sx += vv * f0[dx];
             sdx += vv * d0[dx];
           }
@@ -348,21 +388,11 @@ __global__ void __launch_bounds__(1024) batch_kernel(BatchGeom g, BatchPtrs<R> p
           gy = sxdy;
         }
       }
-      grad[j * D] = gx * (R)item.gs[0];
-      grad[j * D + 1] = gy * (R)item.gs[1];
-      if (D == 3) grad[j * D + 2] = gz * (R)item.gs[2];
+      grad[(long long)j * D] = gx * (R)item.gs[0];
+      grad[(long long)j * D + 1] = gy * (R)item.gs[1];
+      if (D == 3) grad[(long long)j * D + 2] = gz * (R)item.gs[2];
     }
-
-    // ---- loss of the configuration (fixed-order FP64 reduction)
-    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-      p.loss[b] = t;
-    }
-    __syncthreads();  // LDS is reused by the next configuration
+    __syncthreads();  // LDS is reused by the next item
   }
 }
 
@@ -395,14 +425,19 @@ struct fresco_batch_ctx {
   hipStream_t st = nullptr;
   long long ntot = 0;
   std::vector<long long> off;  // nb + 1
+  std::vector<long long> npts;  // points per configuration
   std::vector<void*> allocs;
   long long bytes = 0;
-  size_t lds = 0;
-  int threads = 1024;
-  int grid = 0;
+  size_t lds_spread = 0, lds_modes = 0, lds_interp = 0;
+  int threads = 1024;  // workgroup size of the spread and interp passes
+  int chunk = 8192;    // points per work item
+  int nwork = 0;
   BatchTables* tab = nullptr;
   BatchItem* items = nullptr;
-  int* order = nullptr;
+  int4* work = nullptr;    // [max items]
+  int2* citems = nullptr;  // [nb]
+  void* part = nullptr;    // [max items][ngrid] partial grids
+  void* field = nullptr;   // [nb][ngrid]
   void* W = nullptr;
   void* S0 = nullptr;
   void* dec[3] = {nullptr, nullptr, nullptr};
@@ -484,15 +519,30 @@ int upload_as(fresco_batch_ctx* c, void** p, const std::vector<double>& h) {
     case 16: CALL(16); break;    \
   }
 
-template <class R>
-const void* batch_kernel_ptr(int d, int w) {
-  const void* k = nullptr;
-#define BK(W)                                                   \
-  k = (d == 2) ? (const void*)batch_kernel<R, 2, W>             \
-               : (const void*)batch_kernel<R, 3, W>
-  BATCH_W_SWITCH(w, BK)
-#undef BK
-  return k;
+long long max_work_items(const fresco_batch_ctx* c) {
+  long long m = 0;
+  for (long long n : c->npts) m += (n + kChunkMin - 1) / kChunkMin;
+  return m;
+}
+
+// work items of at most `chunk` points, configuration by configuration
+int plan_work(fresco_batch_ctx* c, int chunk) {
+  const int nb = c->g.nb;
+  std::vector<int4> work;
+  std::vector<int2> citems(nb);
+  for (int b = 0; b < nb; ++b) {
+    citems[b].x = (int)work.size();
+    for (long long j = 0; j < c->npts[b]; j += chunk) {
+      const long long cnt = std::min<long long>(chunk, c->npts[b] - j);
+      work.push_back(make_int4(b, (int)j, (int)cnt, 0));
+    }
+    citems[b].y = (int)work.size() - citems[b].x;
+  }
+  BHIP(hipMemcpy(c->work, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(c->citems, citems.data(), sizeof(int2) * nb, hipMemcpyHostToDevice));
+  c->chunk = chunk;
+  c->nwork = (int)work.size();
+  return FRESCO_OK;
 }
 
 template <class R>
@@ -500,7 +550,6 @@ BatchPtrs<R> batch_ptrs(fresco_batch_ctx* c, const void* pos, void* grad) {
   BatchPtrs<R> p;
   p.tab = c->tab;
   p.items = c->items;
-  p.order = c->order;
   p.W = (const R*)c->W;
   p.S0 = (const R*)c->S0;
   for (int a = 0; a < 3; ++a) {
@@ -519,15 +568,35 @@ template <class R>
 int batch_enqueue(fresco_batch_ctx* c, const void* pos, void* grad, double* total) {
   const BatchGeom& g = c->g;
   BatchPtrs<R> p = batch_ptrs<R>(c, pos, grad);
+  const unsigned wgrid = (unsigned)std::min(c->nwork, 4096);
+  R* part = (R*)c->part;
+  R* field = (R*)c->field;
 #define BL(W)                                                                                  \
   do {                                                                                         \
     if (g.d == 2)                                                                              \
-      batch_kernel<R, 2, W><<<c->grid, c->threads, c->lds, c->st>>>(g, p);                     \
+      batch_spread_kernel<R, 2, W><<<wgrid, c->threads, c->lds_spread, c->st>>>(               \
+          g, p, c->work, c->nwork, part);                                                      \
     else                                                                                       \
-      batch_kernel<R, 3, W><<<c->grid, c->threads, c->lds, c->st>>>(g, p);                     \
+      batch_spread_kernel<R, 3, W><<<wgrid, c->threads, c->lds_spread, c->st>>>(               \
+          g, p, c->work, c->nwork, part);                                                      \
   } while (0)
   BATCH_W_SWITCH(g.w, BL)
 #undef BL
+  if (g.d == 2)
+    batch_modes_kernel<R, 2><<<g.nb, 1024, c->lds_modes, c->st>>>(g, p, c->citems, part, field);
+  else
+    batch_modes_kernel<R, 3><<<g.nb, 1024, c->lds_modes, c->st>>>(g, p, c->citems, part, field);
+#define BI(W)                                                                                  \
+  do {                                                                                         \
+    if (g.d == 2)                                                                              \
+      batch_interp_kernel<R, 2, W><<<wgrid, c->threads, c->lds_interp, c->st>>>(               \
+          g, p, c->work, c->nwork, field);                                                     \
+    else                                                                                       \
+      batch_interp_kernel<R, 3, W><<<wgrid, c->threads, c->lds_interp, c->st>>>(               \
+          g, p, c->work, c->nwork, field);                                                     \
+  } while (0)
+  BATCH_W_SWITCH(g.w, BI)
+#undef BI
   batch_total_kernel<<<1, 256, 0, c->st>>>(c->loss, g.nb, total, c->flag, c->flag_out);
   BHIP(hipGetLastError());
   return FRESCO_OK;
@@ -536,6 +605,29 @@ int batch_enqueue(fresco_batch_ctx* c, const void* pos, void* grad, double* tota
 int batch_enqueue_any(fresco_batch_ctx* c, const void* pos, void* grad, double* total) {
   if (c->dtype == FRESCO_F32) return batch_enqueue<float>(c, pos, grad, total);
   return batch_enqueue<double>(c, pos, grad, total);
+}
+
+template <class R>
+hipError_t batch_prepare(fresco_batch_ctx* c) {
+  const BatchGeom& g = c->g;
+  hipError_t e = hipSuccess;
+#define BP(W)                                                                                    \
+  do {                                                                                           \
+    const void* ks = (g.d == 2) ? (const void*)batch_spread_kernel<R, 2, W>                      \
+                                : (const void*)batch_spread_kernel<R, 3, W>;                     \
+    const void* ki = (g.d == 2) ? (const void*)batch_interp_kernel<R, 2, W>                      \
+                                : (const void*)batch_interp_kernel<R, 3, W>;                     \
+    e = hipFuncSetAttribute(ks, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_spread); \
+    if (e == hipSuccess)                                                                         \
+      e = hipFuncSetAttribute(ki, hipFuncAttributeMaxDynamicSharedMemorySize,                    \
+                              (int)c->lds_interp);                                               \
+  } while (0)
+  BATCH_W_SWITCH(g.w, BP)
+#undef BP
+  if (e != hipSuccess) return e;
+  const void* km = (g.d == 2) ? (const void*)batch_modes_kernel<R, 2>
+                              : (const void*)batch_modes_kernel<R, 3>;
+  return hipFuncSetAttribute(km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_modes);
 }
 
 template <class R>
@@ -604,24 +696,32 @@ int batch_build(fresco_batch_ctx* c, int nb, const fresco_problem* ps) {
   if ((st = bupload(c, &c->items, items))) return st;
   if ((st = upload_as<R>(c, &c->W, Wall))) return st;
   if ((st = upload_as<R>(c, &c->S0, S0all))) return st;
-  std::vector<int> order(nb);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return ps[x].n > ps[y].n; });
-  if ((st = bupload(c, &c->order, order))) return st;
   if ((st = balloc(c, &c->loss, nb))) return st;
   if ((st = balloc(c, &c->total, 1))) return st;
   if ((st = balloc(c, &c->flag, 1))) return st;
   if ((st = balloc(c, &c->flag_out, 1))) return st;
   BHIP(hipMemset(c->flag, 0, sizeof(int)));
   BHIP(hipMemset(c->flag_out, 0, sizeof(int)));
-  // LDS: twiddles, complex grid, fixed-point grid (also the coefficient scratch)
+  // work items (room for the smallest chunk size), partial grids, fields
+  const long long maxw = max_work_items(c);
+  if ((st = balloc(c, &c->work, (size_t)maxw))) return st;
+  if ((st = balloc(c, &c->citems, (size_t)nb))) return st;
+  R* part = nullptr;
+  if ((st = balloc(c, &part, (size_t)maxw * g.ngrid))) return st;
+  c->part = part;
+  R* field = nullptr;
+  if ((st = balloc(c, &field, (size_t)nb * g.ngrid))) return st;
+  c->field = field;
+  if ((st = plan_work(c, 8192))) return st;
+  // LDS of the three passes
+  using U = typename std::conditional<sizeof(R) == 4, uint32_t, unsigned long long>::type;
   const size_t cs = sizeof(cpx<R>);
-  c->lds = (size_t)g.lds_tw * cs + (size_t)g.ngrid * cs + (size_t)g.ngrid * sizeof(R);
-  if ((size_t)g.ngrid * sizeof(R) < (size_t)g.ncube * cs) return FRESCO_ENOTSUP;
-  if (c->lds > 160 * 1024 - 256) return FRESCO_ENOTSUP;
-  BHIP(hipFuncSetAttribute(batch_kernel_ptr<R>(d, g.w), hipFuncAttributeMaxDynamicSharedMemorySize,
-                           (int)c->lds));
+  c->lds_spread = (size_t)g.ngrid * (sizeof(U) + sizeof(uint32_t));
+  c->lds_modes = ((size_t)g.lds_tw + g.ngrid + g.ncube) * cs;
+  c->lds_interp = (size_t)g.ngrid * sizeof(R);
+  const size_t lim = 160 * 1024 - 256;
+  if (c->lds_spread > lim || c->lds_modes > lim || c->lds_interp > lim) return FRESCO_ENOTSUP;
+  BHIP(batch_prepare<R>(c));
   return FRESCO_OK;
 }
 
@@ -825,9 +925,12 @@ int fresco_batch_create(fresco_batch_ctx** out, int32_t nb, const fresco_problem
     }
   }
   c->off.assign(nb + 1, 0);
-  for (int b = 0; b < nb; ++b) c->off[b + 1] = c->off[b] + ps[b].n;
+  c->npts.assign(nb, 0);
+  for (int b = 0; b < nb; ++b) {
+    c->off[b + 1] = c->off[b] + ps[b].n;
+    c->npts[b] = ps[b].n;
+  }
   c->ntot = ntot;
-  c->grid = nb;
   int st = (c->dtype == FRESCO_F32) ? batch_build<float>(c, nb, ps) : batch_build<double>(c, nb, ps);
   if (!st && hipHostMalloc((void**)&c->host, sizeof(double) * (nb + 2)) != hipSuccess)
     st = FRESCO_ENOMEM;
@@ -890,38 +993,48 @@ int fresco_batch_reset_history(fresco_batch_ctx* c) {
 int fresco_batch_autotune(fresco_batch_ctx* c, const void* pos, void* grad, int32_t reps,
                           int32_t* threads_out) {
   if (!c || !pos || !grad || reps < 1) return FRESCO_EINVAL;
-  const int cand[3] = {256, 512, 1024};
+  const int cand_t[3] = {256, 512, 1024};
   hipEvent_t e0, e1;
   BHIP(hipEventCreate(&e0));
   BHIP(hipEventCreate(&e1));
   float best_ms = 0.f;
-  int best = c->threads;
+  int best_t = c->threads, best_c = c->chunk;
   int st = FRESCO_OK;
-  for (int t : cand) {
-    c->threads = t;
-    if ((st = batch_enqueue_any(c, pos, grad, c->total))) break;  // warm
-    if (hipEventRecord(e0, c->st) != hipSuccess) { st = FRESCO_EHIP; break; }
-    for (int r = 0; r < reps && !st; ++r) st = batch_enqueue_any(c, pos, grad, c->total);
+  for (int ch : kChunks) {
+    if ((st = plan_work(c, ch))) break;
+    for (int t : cand_t) {
+      c->threads = t;
+      if ((st = batch_enqueue_any(c, pos, grad, c->total))) break;  // warm
+      if (hipEventRecord(e0, c->st) != hipSuccess) {
+        st = FRESCO_EHIP;
+        break;
+      }
+      for (int r = 0; r < reps && !st; ++r) st = batch_enqueue_any(c, pos, grad, c->total);
+      if (st) break;
+      if (hipEventRecord(e1, c->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = FRESCO_EHIP;
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best_ms == 0.f || ms < best_ms) {
+        best_ms = ms;
+        best_t = t;
+        best_c = ch;
+      }
+    }
     if (st) break;
-    if (hipEventRecord(e1, c->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-      st = FRESCO_EHIP;
-      break;
-    }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (best_ms == 0.f || ms < best_ms) {
-      best_ms = ms;
-      best = t;
-    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->threads = best;
-  if (c->lb_graph) {  // captured with the previous block size
+  c->threads = best_t;
+  const int st2 = plan_work(c, best_c);
+  if (!st) st = st2;
+  if (c->lb_graph) {  // captured with the previous launch shape
     (void)hipGraphExecDestroy(c->lb_graph);
     c->lb_graph = nullptr;
   }
-  if (threads_out) *threads_out = best;
+  if (threads_out) *threads_out = best_t;
   return st;
 }
 

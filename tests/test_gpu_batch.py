@@ -117,7 +117,7 @@ def test_batch_full_workload_sampled(gpu):
     bc.close()
 
 
-def test_batch_repeatable_and_block_size_independent(gpu):
+def test_batch_repeatable_and_launch_shape_independent(gpu):
     import torch
     from paper_2305_15693_amd import fresco as F
     cfgs = I.ragged_batch(nb=24, nmin=1000, nmax=30000, kcut=KCUT, seed=8)
@@ -131,10 +131,13 @@ def test_batch_repeatable_and_block_size_independent(gpu):
     bc.autotune(pos, reps=2)
     l3, g3 = bc.loss_grad(pos)
     torch.cuda.synchronize()
-    # the gradient does not depend on the workgroup size; the loss only through
-    # the order of its FP64 partial sums
-    assert torch.equal(g1, g3)
-    np.testing.assert_allclose(l3, l1, rtol=1e-13)
+    # the launch shape the autotuner picks (points per work item, workgroup size)
+    # changes only the order of FP32 sums of partial grids and FP64 loss partials
+    g1n, g3n = g1.cpu().numpy(), g3.cpu().numpy()
+    assert rel(g3n, g1n) < 1e-5
+    np.testing.assert_allclose(l3, l1, rtol=1e-5)
+    l4, g4 = bc.loss_grad(pos)
+    assert np.array_equal(l3, l4) and torch.equal(g3, g4)
     bad = pos.clone()
     bad[5, 1] = float("nan")
     with pytest.raises(F.FrescoError) as ei:
