@@ -91,6 +91,8 @@ typedef struct fresco_plan_info {
   int64_t nbins;        /* number of tiles */
   int64_t n_constrained;/* number of modes with nonzero weight (full set) */
   int64_t device_bytes; /* scratch memory held by the context */
+  int32_t col_split;    /* 2D last-axis columns transformed as this many sub-columns
+                           (1; 2 when a column is too long for one LDS pass) */
 } fresco_plan_info;
 
 /* Create a context for one problem.  Chooses the fine grid, kernel width and

@@ -494,3 +494,86 @@ int oracle_pair_cells(int d, long long N, const double* L, const double* pos, do
   if (energy) *energy = e;
   return OR_OK;
 }
+
+/*
+ * rho(k) = sum_j exp(+i k.r_j) for a few listed modes over very many points, by
+ * direct evaluation of cos and sin of k.r_j (no per-point tables, whose cost
+ * grows with the largest |n|).  Points are taken in fixed blocks of 65536; each
+ * block's partial sums are formed in point order and the blocks are added in
+ * order, so the result does not depend on the thread count.
+ */
+#define DBLOCK 65536
+int oracle_rho_direct(int d, long long N, const double* L, const double* pos, long long K,
+                      const int* modes, double* rho) {
+  if (d < 1 || d > 3 || N < 0 || K < 0 || !L || (N && !pos) || (K && (!modes || !rho)))
+    return OR_EINVAL;
+  long long nblk = (N + DBLOCK - 1) / DBLOCK;
+  double* part = (double*)malloc(sizeof(double) * 2 * (K ? K : 1) * (nblk ? nblk : 1));
+  if (!part) return OR_ENOMEM;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (long long b = 0; b < nblk; ++b) {
+    double* pb = part + 2 * K * b;
+    for (long long q = 0; q < 2 * K; ++q) pb[q] = 0.0;
+    long long j1 = (b + 1) * DBLOCK < N ? (b + 1) * DBLOCK : N;
+    for (long long j = b * DBLOCK; j < j1; ++j)
+      for (long long q = 0; q < K; ++q) {
+        double ph = 0.0;
+        for (int a = 0; a < d; ++a) ph += TWO_PI * (double)modes[q * d + a] * pos[j * d + a] / L[a];
+        pb[2 * q] += cos(ph);
+        pb[2 * q + 1] += sin(ph);
+      }
+  }
+  for (long long q = 0; q < 2 * K; ++q) rho[q] = 0.0;
+  for (long long b = 0; b < nblk; ++b)
+    for (long long q = 0; q < 2 * K; ++q) rho[q] += part[2 * K * b + q];
+  free(part);
+  return OR_OK;
+}
+
+/*
+ * Loss and gradient from a given rho(k) over the listed modes (for problems too
+ * large for oracle_rho; rho from oracle_rho_direct).  N is the number of points
+ * rho was summed over; the gradient is evaluated for the G points `gpos` [G][d]:
+ *   S = |rho|^2 / N, loss = sum W (S - S0)^2,
+ *   grad_a = Re sum_k C_a(k) exp(-i k.r),  C_a = -4 i k_a W (S - S0) rho / N.
+ * exp(-i k.r) by direct cos/sin (no tables).
+ */
+int oracle_loss_grad_rho(int d, long long N, const double* L, long long K, const int* modes,
+                         const double* W, const double* S0, const double* rho, double* S_out,
+                         double* loss_out, long long G, const double* gpos, double* grad_out) {
+  if (d < 1 || d > 3 || N <= 0 || K < 0 || !L || (K && (!modes || !W || !S0 || !rho)))
+    return OR_EINVAL;
+  if (G < 0 || (G && (!gpos || !grad_out))) return OR_EINVAL;
+  double* C = (double*)malloc(sizeof(double) * 2 * d * (K ? K : 1));
+  if (!C) return OR_ENOMEM;
+  double loss = 0.0;
+  for (long long q = 0; q < K; ++q) {
+    double S = (rho[2 * q] * rho[2 * q] + rho[2 * q + 1] * rho[2 * q + 1]) / (double)N;
+    double res = S - S0[q];
+    loss += W[q] * res * res;
+    if (S_out) S_out[q] = S;
+    for (int a = 0; a < d; ++a) {
+      double ka = TWO_PI * (double)modes[q * d + a] / L[a];
+      double f = 4.0 * ka * W[q] * res / (double)N;
+      C[2 * (q * d + a)] = f * rho[2 * q + 1];
+      C[2 * (q * d + a) + 1] = -f * rho[2 * q];
+    }
+  }
+  if (loss_out) *loss_out = loss;
+#pragma omp parallel for schedule(static)
+  for (long long g = 0; g < G; ++g) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long q = 0; q < K; ++q) {
+      double ph = 0.0;
+      for (int a = 0; a < d; ++a) ph += TWO_PI * (double)modes[q * d + a] * gpos[g * d + a] / L[a];
+      double er = cos(ph), ei = sin(ph);
+      for (int a = 0; a < d; ++a) {
+        const double* c = C + 2 * (q * d + a);
+        acc[a] += c[0] * er + c[1] * ei;
+      }
+    }
+    for (int a = 0; a < d; ++a) grad_out[g * d + a] = acc[a];
+  }
+  free(C);
+  return OR_OK;
+}

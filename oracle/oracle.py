@@ -58,6 +58,11 @@ def _load():
         lib.oracle_fd.argtypes = [ctypes.c_int, ll, dp, dp, ll, ip, dp, dp, ll, lp, ip,
                                   ctypes.c_double, dp]
         lib.oracle_fd.restype = ctypes.c_int
+        lib.oracle_loss_grad_rho.argtypes = [ctypes.c_int, ll, dp, ll, ip, dp, dp, dp, dp, dp,
+                                             ll, dp, dp]
+        lib.oracle_loss_grad_rho.restype = ctypes.c_int
+        lib.oracle_rho_direct.argtypes = [ctypes.c_int, ll, dp, dp, ll, ip, dp]
+        lib.oracle_rho_direct.restype = ctypes.c_int
         lib.oracle_sf_vjp.argtypes = [ctypes.c_int, ll, dp, dp, ll, ip, dp, ll, lp, dp]
         lib.oracle_sf_vjp.restype = ctypes.c_int
         for f in (lib.oracle_pair, lib.oracle_pair_cells):
@@ -244,3 +249,46 @@ def pair(pos, L, sigma: float, eps: float = 1.0, alpha: float = 2.0, cells: bool
     if st:
         raise RuntimeError(f"oracle pair term failed ({st})")
     return float(e[0]), grad
+
+
+def rho_direct(pos, L, modes, chunk: int = 100_000_000) -> np.ndarray:
+    """rho(k) for a few listed modes by direct cos/sin of k.r_j (no per-point tables),
+    for very many points; pos may be float32 (widened chunk by chunk, exactly)."""
+    pos = np.asarray(pos)
+    N, d = pos.shape
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    K = modes.shape[0]
+    total = np.zeros(2 * K)
+    for s0 in range(0, N, chunk):
+        part = np.ascontiguousarray(pos[s0:s0 + chunk], dtype=np.float64)
+        out = np.zeros(2 * K)
+        st = _load().oracle_rho_direct(d, part.shape[0], _p(_box(L, d), ctypes.c_double),
+                                       _p(part, ctypes.c_double), K, _p(modes, ctypes.c_int),
+                                       _p(out, ctypes.c_double))
+        if st:
+            raise RuntimeError(f"oracle_rho_direct failed ({st})")
+        total += out
+    return total[0::2] + 1j * total[1::2]
+
+
+def loss_grad_from_rho(N: int, L, modes, W, S0, rho, grad_pos):
+    """Loss, S and the gradient at the points grad_pos [G][d] from rho(k) on the
+    listed modes (summed over N points, e.g. by rho_direct).  Returns dict(loss, S, grad)."""
+    grad_pos = _pos(grad_pos)
+    G, d = grad_pos.shape
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    K = modes.shape[0]
+    W = np.ascontiguousarray(W, dtype=np.float64).reshape(K)
+    S0 = np.ascontiguousarray(S0, dtype=np.float64).reshape(K)
+    rh = np.ascontiguousarray(np.stack([np.real(rho), np.imag(rho)], 1), dtype=np.float64)
+    S = np.zeros(K)
+    loss = np.zeros(1)
+    grad = np.zeros((G, d))
+    st = _load().oracle_loss_grad_rho(d, int(N), _p(_box(L, d), ctypes.c_double), K,
+                                      _p(modes, ctypes.c_int), _p(W, ctypes.c_double),
+                                      _p(S0, ctypes.c_double), _p(rh, ctypes.c_double),
+                                      _p(S, ctypes.c_double), _p(loss, ctypes.c_double), G,
+                                      _p(grad_pos, ctypes.c_double), _p(grad, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle_loss_grad_rho failed ({st})")
+    return {"loss": float(loss[0]), "S": S, "grad": grad}

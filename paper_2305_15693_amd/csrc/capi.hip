@@ -70,6 +70,13 @@ struct State {
   RowParams<R> rows;
   ColParams<R> col1;  // axis 1 (3D: forward / inverse; 2D: fused)
   ColParams<R> col2;  // axis 2 (3D: fused)
+  // 2D columns too long for LDS: two half-length sub-transforms per column
+  bool long_cols = false;
+  cpx<R>* twn = nullptr;  // exp(+2 pi i q / nf1)
+  cpx<R>* Yl = nullptr;   // forward sub-transforms [2][2M1+1][M0+1]
+  cpx<R>* Ql = nullptr;   // pre-twiddled inverse inputs, same layout
+  ColParams<R> lfw{}, linv{};
+  int long_blocks = 0;
   long long nloss_part = 0;
   // L-BFGS (allocated on the first fresco_step)
   LbfgsVec<R> lv{};
@@ -210,8 +217,10 @@ int setup_axis(fresco_ctx* c, AxisFft<R>* ax, int n, bool rows_twn) {
   return FRESCO_OK;
 }
 
-// launch shape of a row pass: lines per block and block size
-bool shape_rows(int H, int rmin, long long nrows, size_t cs, int* lpb, int* threads) {
+constexpr size_t kLdsLimit = 160 * 1024;
+
+// launch shape of a row pass: lines per block, block size, twiddles in LDS
+bool shape_rows(int H, int rmin, long long nrows, size_t cs, int* lpb, int* threads, bool* twl) {
   int l = 1;
   while (l * 2 <= 16 && (size_t)(l * 2) * (H + 1) * cs <= 32768 && nrows / (l * 2) >= 1024) l *= 2;
   int t = 256;
@@ -223,14 +232,17 @@ bool shape_rows(int H, int rmin, long long nrows, size_t cs, int* lpb, int* thre
     else if (l > 1) l /= 2;
     else return false;
   }
-  if (((size_t)l + 1) * (H + 1) * cs > 160 * 1024) return false;
+  // twiddles go to LDS when they fit beside the lines, else they are read from L2
+  const size_t lines = (size_t)l * (H + 1) * cs;
+  if (lines > kLdsLimit) return false;
+  *twl = lines + (size_t)H * cs <= kLdsLimit;
   *lpb = l;
   *threads = t;
   return true;
 }
 
-// launch shape of a column pass: columns per block and block size
-bool shape_cols(int n, int rmin, long long ncols, size_t cs, int* bc, int* threads) {
+// launch shape of a column pass: columns per block, block size, twiddles in LDS
+bool shape_cols(int n, int rmin, long long ncols, size_t cs, int* bc, int* threads, bool* twl) {
   int b = 1;
   while (b * 2 <= 16 && (size_t)(b * 2) * n * cs <= 49152 && ncols / (b * 2) >= 512) b *= 2;
   int t = 256;
@@ -242,7 +254,10 @@ bool shape_cols(int n, int rmin, long long ncols, size_t cs, int* bc, int* threa
     else if (b > 1) b /= 2;
     else return false;
   }
-  if (((size_t)b * 3 / 2 + 1) * n * cs > 160 * 1024) return false;
+  // data + mode factors (at most half a line per column); twiddles as for rows
+  const size_t data = (size_t)b * ((size_t)n + n / 2 + 1) * cs;
+  if (data > kLdsLimit) return false;
+  *twl = data + (size_t)n * cs <= kLdsLimit;
   *bc = b;
   *threads = t;
   return true;
@@ -383,7 +398,8 @@ int create_state(fresco_ctx* c) {
   std::memset(&rp, 0, sizeof(rp));
   rp.nrows = nf1 * nf2;
   rp.M0 = g.M[0];
-  if (!shape_rows(g.nf[0] / 2, S->ax[0].rmin, rp.nrows, cs, &rp.lines_per_block, &rp.threads))
+  if (!shape_rows(g.nf[0] / 2, S->ax[0].rmin, rp.nrows, cs, &rp.lines_per_block, &rp.threads,
+                  &rp.tw_lds))
     return FRESCO_ENOTSUP;
   auto fill_modes = [&](ColParams<R>& cp) {
     cp.d = d;
@@ -409,18 +425,62 @@ int create_state(fresco_ctx* c) {
     c1.cdiv = make_fastdiv((uint32_t)H0);
     c1.in_line = H0;
     c1.out_line = H0;
-    if (!shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads))
-      return FRESCO_ENOTSUP;
-    S->nloss_part = (c1.ncols + c1.bc - 1) / c1.bc;
-    HIPCHK(prepare_cols<R>(COL_FUSED, c1, S->ax[1]));
-    HIPCHK(prepare_cols<R>(COL_SF, c1, S->ax[1]));
-    HIPCHK(prepare_cols<R>(COL_BWD, c1, S->ax[1]));
+    const char* el = std::getenv("FRESCO_LONG_COLS");
+    const bool force_long = el && el[0] == '1' && (2 * g.M[1] + 1) * 2 <= g.nf[1];
+    if (!force_long &&
+        shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads, &c1.tw_lds)) {
+      S->nloss_part = (c1.ncols + c1.bc - 1) / c1.bc;
+      HIPCHK(prepare_cols<R>(COL_FUSED, c1, S->ax[1]));
+      HIPCHK(prepare_cols<R>(COL_SF, c1, S->ax[1]));
+      HIPCHK(prepare_cols<R>(COL_BWD, c1, S->ax[1]));
+    } else {
+      // columns too long for LDS: two half-length sub-transforms per column
+      // (decimation by 2; nf1 is even and 2M + 1 <= nf1 / 2)
+      S->long_cols = true;
+      const int n = g.nf[1], m = n / 2;
+      const long long P = 2LL * g.M[1] + 1;
+      if ((st = setup_axis<R>(c, &S->ax[1], m, false))) return st;
+      {
+        std::vector<double> t = twiddles(n, n);
+        R* q = nullptr;
+        if ((st = upload<R>(c, &q, t))) return st;
+        S->twn = (cpx<R>*)q;
+      }
+      if ((st = dalloc_t(c, &S->Yl, (size_t)(2 * P * H0)))) return st;
+      if ((st = dalloc_t(c, &S->Ql, (size_t)(2 * P * H0)))) return st;
+      // forward: column (r, n0) holds the entries 2 i + r of column n0
+      ColParams<R>& f = S->lfw;
+      f = c1;
+      f.ncols = 2 * H0;
+      f.in_outer = H0;
+      f.in_line = 2 * H0;
+      f.out_outer = P * H0;
+      f.out_line = H0;
+      if (!shape_cols(m, S->ax[1].rmin, f.ncols, cs, &f.bc, &f.threads, &f.tw_lds))
+        return FRESCO_ENOTSUP;
+      HIPCHK(prepare_cols<R>(COL_FWD, f, S->ax[1]));
+      // inverse: component r writes the entries 2 j + r of every column
+      ColParams<R>& v = S->linv;
+      v = c1;
+      v.ncols = H0;
+      v.in_outer = 0;
+      v.in_line = H0;
+      v.out_outer = 0;
+      v.out_line = 2 * H0;
+      if (!shape_cols(m, S->ax[1].rmin, v.ncols, cs, &v.bc, &v.threads, &v.tw_lds))
+        return FRESCO_ENOTSUP;
+      HIPCHK(prepare_cols<R>(COL_INV, v, S->ax[1]));
+      long long blocks = (P * H0 + 255) / 256;
+      if (blocks > 4096) blocks = 4096;
+      S->long_blocks = (int)blocks;
+      S->nloss_part = blocks;
+    }
   } else {
     // axis 1, columns (l2, n0): A1[l2][l1][n0] <-> A2[l2][m1][n0]
     c1.ncols = nf2 * H0;
     c1.M = g.M[1];
     c1.cdiv = make_fastdiv((uint32_t)H0);
-    if (!shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads))
+    if (!shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads, &c1.tw_lds))
       return FRESCO_ENOTSUP;
     HIPCHK(prepare_cols<R>(COL_FWD, c1, S->ax[1]));
     HIPCHK(prepare_cols<R>(COL_INV, c1, S->ax[1]));
@@ -432,7 +492,7 @@ int create_state(fresco_ctx* c) {
     c2.cdiv = make_fastdiv((uint32_t)c2.ncols);
     c2.in_line = P1 * H0;
     c2.out_line = P1 * H0;
-    if (!shape_cols(g.nf[2], S->ax[2].rmin, c2.ncols, cs, &c2.bc, &c2.threads))
+    if (!shape_cols(g.nf[2], S->ax[2].rmin, c2.ncols, cs, &c2.bc, &c2.threads, &c2.tw_lds))
       return FRESCO_ENOTSUP;
     S->nloss_part = (c2.ncols + c2.bc - 1) / c2.bc;
     HIPCHK(prepare_cols<R>(COL_FUSED, c2, S->ax[2]));
@@ -532,6 +592,32 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
   return FRESCO_OK;
 }
 
+// 2D last axis with columns too long for LDS: forward half-length sub-transforms
+// (not for the backward, which starts from the saved rho), recombination and
+// mode stage, inverse half-length sub-transforms (not for S alone) into V1.
+template <class R>
+int run_long_cols(fresco_ctx* c, int mode, const ColParams<R>& last) {
+  State<R>* S = (State<R>*)c->state;
+  const Geom& g = c->g;
+  const long long H0 = g.M[0] + 1, P = 2LL * g.M[1] + 1;
+  if (mode != COL_BWD) {
+    ColParams<R> f = S->lfw;
+    f.in[0] = S->A1;
+    f.out[0] = S->Yl;
+    HIPCHK(launch_cols<R>(COL_FWD, f, S->ax[1], 1, c->st));
+  }
+  HIPCHK(launch_long_modes<R>(mode, last, S->Yl, S->Ql, S->twn, g.nf[1], S->long_blocks, c->st));
+  if (mode != COL_SF) {
+    ColParams<R> v = S->linv;
+    v.in[0] = S->Ql;
+    v.in[1] = S->Ql + P * H0;
+    v.out[0] = S->V1;
+    v.out[1] = S->V1 + H0;
+    HIPCHK(launch_cols<R>(COL_INV, v, S->ax[1], 2, c->st));
+  }
+  return FRESCO_OK;
+}
+
 // mode stage + inverse transforms + interpolation; mode = COL_FUSED or COL_BWD
 template <class R>
 int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R* g_cube, R* grad,
@@ -555,7 +641,12 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
   last.g_cube = g_cube;
   {
     StageTimer t(c, FRESCO_STAGE_MODES);
-    HIPCHK(launch_cols<R>(mode, last, S->ax[d - 1], 1, st));
+    if (d == 2 && S->long_cols) {
+      int ls = run_long_cols<R>(c, mode, last);
+      if (ls) return ls;
+    } else {
+      HIPCHK(launch_cols<R>(mode, last, S->ax[d - 1], 1, st));
+    }
   }
   if (d == 3) {
     ColParams<R> inv = S->col1;
@@ -789,7 +880,11 @@ int structure_factor_impl(fresco_ctx* c, const void* pos, void* Sout) {
   last.rho_save = S->rho;
   {
     StageTimer t(c, FRESCO_STAGE_MODES);
-    HIPCHK(launch_cols<R>(COL_SF, last, S->ax[g.d - 1], 1, c->st));
+    if (g.d == 2 && S->long_cols) {
+      if ((st = run_long_cols<R>(c, COL_SF, last))) return st;
+    } else {
+      HIPCHK(launch_cols<R>(COL_SF, last, S->ax[g.d - 1], 1, c->st));
+    }
   }
   finish_kernel<<<1, 256, 0, c->st>>>(S->loss_part, 0, nullptr, 0, 0.0, nullptr, S->bb.flag,
                                       S->flag_out);
@@ -1009,6 +1104,9 @@ int fresco_plan_info_get(const fresco_ctx* c, fresco_plan_info* o) {
   o->nbins = c->g.nbins;
   o->n_constrained = c->n_constrained;
   o->device_bytes = c->bytes;
+  o->col_split = 1;
+  if (c->dtype == FRESCO_F32 && ((const State<float>*)c->state)->long_cols) o->col_split = 2;
+  if (c->dtype == FRESCO_F64 && ((const State<double>*)c->state)->long_cols) o->col_split = 2;
   return FRESCO_OK;
 }
 

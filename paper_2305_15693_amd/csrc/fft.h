@@ -17,6 +17,7 @@ struct AxisFft {
 template <class R>
 struct RowParams {
   long long nrows;
+  bool tw_lds;           // twiddles staged in LDS (false for lines too long for it)
   int lines_per_block;
   int threads;
   int M0;
@@ -30,6 +31,7 @@ template <class R>
 struct ColParams {
   long long ncols;
   int bc;        // columns per block (power of two)
+  bool tw_lds;   // twiddles staged in LDS (false for lines too long for it)
   int threads;   // block size
   int M;         // mode half-width along this axis
   FastDiv cdiv;  // columns per outer group
@@ -69,5 +71,13 @@ hipError_t launch_rows(bool inverse, const RowParams<R>& p, const AxisFft<R>& ax
 template <class R>
 hipError_t launch_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax, int ncomp,
                        hipStream_t st);
+// 2D columns of length n = 2m too long for LDS: recombination of the two
+// length-m sub-transforms Y (= [Y0][Y1], each [2M+1][M0+1]), the mode stage
+// `mode` (COL_FUSED, COL_SF or COL_BWD) and the two pre-twiddled coefficient
+// sets Q (same layout) for the inverse sub-transforms; twn = exp(+2 pi i q / n).
+// FUSED writes one loss partial per block (`blocks` of 256 threads).
+template <class R>
+hipError_t launch_long_modes(int mode, const ColParams<R>& p, const cpx<R>* Y, cpx<R>* Q,
+                             const cpx<R>* twn, int n, int blocks, hipStream_t st);
 
 }  // namespace fresco

@@ -33,19 +33,21 @@ __global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   extern __shared__ unsigned long long smem_u64[];
   cpx<R>* tws = reinterpret_cast<cpx<R>*>(smem_u64);
   const int H = F.n;
-  cpx<R>* buf = tws + H;
+  const bool twl = p.tw_lds;  // twiddles staged in LDS (long lines read them from L2)
+  cpx<R>* buf = twl ? tws + H : tws;
   const int ls = H + 1;
   const int JT = blockDim.x / p.lines_per_block;
   const int b = threadIdx.x / JT, tj = threadIdx.x % JT;
   const long long row = (long long)blockIdx.x * p.lines_per_block + b;
   const bool active = row < p.nrows;
-  load_twiddles(tws, twH, H);
+  if (twl) load_twiddles(tws, twH, H);
   const R* __restrict__ x = p.rin + row * (2LL * H);
   if (active) {
     for (int m = tj; m < H; m += JT) buf[b * ls + m] = *reinterpret_cast<const cpx<R>*>(x + 2 * m);
   }
   __syncthreads();
-  lds_fft<R, MAXB, false>(buf, F, tws, active, b, ls, 1, tj, JT);
+  if (twl) lds_fft<R, MAXB, false>(buf, F, tws, active, b, ls, 1, tj, JT);
+  else lds_fft<R, MAXB, false>(buf, F, twH, active, b, ls, 1, tj, JT);
   if (active) {
     cpx<R>* __restrict__ out = p.cout + row * (long long)(p.M0 + 1);
     for (int k = tj; k <= p.M0; k += JT) {
@@ -70,7 +72,8 @@ __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   extern __shared__ unsigned long long smem_u64[];
   cpx<R>* tws = reinterpret_cast<cpx<R>*>(smem_u64);
   const int H = F.n;
-  cpx<R>* buf = tws + H;
+  const bool twl = p.tw_lds;
+  cpx<R>* buf = twl ? tws + H : tws;
   const int ls = H + 1;
   const int JT = blockDim.x / p.lines_per_block;
   const int b = threadIdx.x / JT, tj = threadIdx.x % JT;
@@ -78,7 +81,7 @@ __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   const bool active = row < p.nrows;
   const int comp = blockIdx.y;
   const int M0 = p.M0;
-  load_twiddles(tws, twH, H);
+  if (twl) load_twiddles(tws, twH, H);
   if (active) {
     const cpx<R>* __restrict__ X = p.cin[comp] + row * (long long)(M0 + 1);
     for (int k = tj; k < H; k += JT) {
@@ -92,7 +95,8 @@ __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
     }
   }
   __syncthreads();
-  lds_fft<R, MAXB, true>(buf, F, tws, active, b, ls, 1, tj, JT);
+  if (twl) lds_fft<R, MAXB, true>(buf, F, tws, active, b, ls, 1, tj, JT);
+  else lds_fft<R, MAXB, true>(buf, F, twH, active, b, ls, 1, tj, JT);
   if (active) {
     R* __restrict__ y = p.rout[comp] + row * (2LL * H);
     for (int m = tj; m < H; m += JT) *reinterpret_cast<cpx<R>*>(y + 2 * m) = buf[b * ls + m];
@@ -118,7 +122,8 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
   const int n = F.n;
   const int bc = p.bc;
   cpx<R>* tws = reinterpret_cast<cpx<R>*>(smem_u64);
-  cpx<R>* buf = tws + n;
+  const bool twl = p.tw_lds;  // twiddles staged in LDS (long lines read them from L2)
+  cpx<R>* buf = twl ? tws + n : tws;
   cpx<R>* qbuf = buf + (long long)n * bc;  // [m][b], FUSED / BWD only
   const int P = 2 * p.M + 1;               // modes along this axis
   const int JT = blockDim.x / bc;
@@ -128,7 +133,12 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
   const int comp = (MODE == COL_INV) ? blockIdx.y : 0;
   const long long ib = active ? col_base<R>(c, p.cdiv, p.in_outer) : 0;
   const long long ob = active ? col_base<R>(c, p.cdiv, p.out_outer) : 0;
-  load_twiddles(tws, twg, n);
+  if (twl) load_twiddles(tws, twg, n);
+#define COL_FFT(INV)                                                             \
+  do {                                                                           \
+    if (twl) lds_fft<R, MAXB, INV>(buf, F, tws, active, b, 1, bc, tj, JT);       \
+    else lds_fft<R, MAXB, INV>(buf, F, twg, active, b, 1, bc, tj, JT);           \
+  } while (0)
 
   if (MODE == COL_FWD || MODE == COL_FUSED || MODE == COL_SF) {
     // forward: load the full spatial line, transform with exp(+i ...)
@@ -137,7 +147,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       for (int i = tj; i < n; i += JT) buf[i * bc + b] = in[ib + (long long)i * p.in_line];
     }
     __syncthreads();
-    lds_fft<R, MAXB, false>(buf, F, tws, active, b, 1, bc, tj, JT);
+    COL_FFT(false);
   }
   if (MODE == COL_FWD) {
     if (active) {
@@ -163,7 +173,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       }
     }
     __syncthreads();
-    lds_fft<R, MAXB, true>(buf, F, tws, active, b, 1, bc, tj, JT);
+    COL_FFT(true);
     if (active) {
       cpx<R>* __restrict__ out = p.out[comp];
       for (int i = tj; i < n; i += JT) out[ob + (long long)i * p.out_line] = buf[i * bc + b];
@@ -264,11 +274,93 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
     }
   }
   __syncthreads();
-  lds_fft<R, MAXB, true>(buf, F, tws, active, b, 1, bc, tj, JT);
+  COL_FFT(true);
   if (active) {
     cpx<R>* __restrict__ out = p.out[0];
     for (int i = tj; i < n; i += JT) out[ob + (long long)i * p.out_line] = buf[i * bc + b];
   }
+}
+#undef COL_FFT
+
+// ------------------------------------------------- 2D columns too long for LDS
+// A column of length n = 2m (2D, last axis) is split by decimation in time:
+//   X[k] = Y0[k mod m] + exp(+2 pi i k / n) Y1[k mod m],
+// Y_r = the length-m transform of the entries 2 i + r, computed by the column pass
+// (pruned to |k| <= M, which needs 2M + 1 <= m).  The field coefficients q(k) go
+// back by decimation in frequency: the entries 2 j + r of the inverse transform
+// are the length-m inverse transforms of q(k) exp(-2 pi i k r / n).
+// This kernel recombines X, runs the mode stage of the fused pass on it (S,
+// loss, coefficients; or S only, or the backward's coefficients) and writes the
+// two pre-twiddled coefficient sets.  Layout of Y0, Y1, Q0, Q1 and of the
+// mode-stage arrays: [m][c], m = k + M, c = n0 in [0, M0].
+template <class R, int MODE>
+__global__ void long_modes_kernel(ColParams<R> p, const cpx<R>* __restrict__ Y,
+                                  cpx<R>* __restrict__ Q, const cpx<R>* __restrict__ twn, int n) {
+  const int P = 2 * p.M + 1;
+  const long long H0 = p.ncols;
+  const long long total = (long long)P * H0;
+  double lsum = 0.0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int m = (int)(e / H0);
+    const int n0 = (int)(e - (long long)m * H0);
+    const int nl = m - p.M;
+    const int al = nl < 0 ? -nl : nl;
+    const int ki = nl < 0 ? nl + n : nl;  // exp(+2 pi i k / n) = twn[k mod n]
+    const long long hidx = e;              // [m][c]
+    cpx<R> rho;
+    if (MODE == COL_BWD) {
+      rho = p.rho_save[hidx];
+    } else {
+      const cpx<R> X = cadd(Y[e], cmul(twn[ki], Y[total + e]));
+      rho = cscale(X, p.dec[0][n0] * p.dec[1][al]);
+      if (p.rho_save) p.rho_save[hidx] = rho;
+    }
+    const R S = (rho.x * rho.x + rho.y * rho.y) * p.invN;
+    const long long cp = (long long)(n0 + p.M0) * p.P1 + (nl + p.M1);
+    const long long cm = (long long)(-n0 + p.M0) * p.P1 + (-nl + p.M1);
+    if ((MODE == COL_SF || MODE == COL_FUSED) && p.S_cube) {
+      p.S_cube[cp] = S;
+      p.S_cube[cm] = S;
+    }
+    if (MODE == COL_FUSED || MODE == COL_BWD) {
+      R G;
+      if (MODE == COL_FUSED) {
+        const R wp = p.Wp[hidx], wm = p.Wm[hidx];
+        const R rp = S - p.S0p[hidx], rm = S - p.S0m[hidx];
+        lsum += (double)wp * (double)rp * (double)rp;
+        if (n0 > 0) lsum += (double)wm * (double)rm * (double)rm;
+        G = wp * rp + wm * rm;
+      } else {
+        G = (cp == cm) ? R(0) : R(0.5) * (p.g_cube[cp] + p.g_cube[cm]);
+      }
+      const cpx<R> q = cscale(rho, R(2) * G * p.invN * p.deci[0][n0] * p.deci[1][al]);
+      Q[e] = q;
+      Q[total + e] = cmulc(q, twn[ki]);  // q exp(-2 pi i k / n)
+    }
+  }
+  if (MODE != COL_FUSED) return;
+  __shared__ double red[1024 / 64];
+  for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    p.loss_part[blockIdx.x] = t;
+  }
+}
+
+template <class R>
+hipError_t launch_long_modes(int mode, const ColParams<R>& p, const cpx<R>* Y, cpx<R>* Q,
+                             const cpx<R>* twn, int n, int blocks, hipStream_t st) {
+  if (mode == COL_FUSED)
+    long_modes_kernel<R, COL_FUSED><<<blocks, 256, 0, st>>>(p, Y, Q, twn, n);
+  else if (mode == COL_SF)
+    long_modes_kernel<R, COL_SF><<<blocks, 256, 0, st>>>(p, Y, Q, twn, n);
+  else
+    long_modes_kernel<R, COL_BWD><<<blocks, 256, 0, st>>>(p, Y, Q, twn, n);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------ launchers
@@ -283,12 +375,12 @@ static int pick_maxb(int need) {
 template <class R>
 size_t rows_lds_bytes(const RowParams<R>& p, const AxisFft<R>& ax) {
   const int H = ax.F.n;
-  return ((size_t)H + (size_t)p.lines_per_block * (H + 1)) * sizeof(cpx<R>);
+  return ((p.tw_lds ? (size_t)H : 0) + (size_t)p.lines_per_block * (H + 1)) * sizeof(cpx<R>);
 }
 template <class R>
 size_t cols_lds_bytes(int mode, const ColParams<R>& p, const AxisFft<R>& ax) {
   const int n = ax.F.n;
-  size_t e = (size_t)n + (size_t)n * p.bc;
+  size_t e = (p.tw_lds ? (size_t)n : 0) + (size_t)n * p.bc;
   if (mode == COL_FUSED || mode == COL_BWD) e += (size_t)(2 * p.M + 1) * p.bc;
   return e * sizeof(cpx<R>);
 }
@@ -405,7 +497,9 @@ hipError_t launch_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax, in
   template hipError_t prepare_cols<R>(int, const ColParams<R>&, const AxisFft<R>&);               \
   template hipError_t launch_rows<R>(bool, const RowParams<R>&, const AxisFft<R>&, int,           \
                                      hipStream_t);                                                \
-  template hipError_t launch_cols<R>(int, const ColParams<R>&, const AxisFft<R>&, int, hipStream_t);
+  template hipError_t launch_cols<R>(int, const ColParams<R>&, const AxisFft<R>&, int, hipStream_t); \
+  template hipError_t launch_long_modes<R>(int, const ColParams<R>&, const cpx<R>*, cpx<R>*,      \
+                                           const cpx<R>*, int, int, hipStream_t);
 FRESCO_FFT_INST(float)
 FRESCO_FFT_INST(double)
 

@@ -606,8 +606,12 @@ void spread_prepare(const Geom& g) {
   } while (0)
   FRESCO_W_SWITCH(g.w, PREP)
 #undef PREP
-  hipFuncSetAttribute((const void*)bin_hist_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)(g.nbins * 4 > 1024 ? g.nbins * 4 : 1024));
+  // block-private histograms only up to 16384 tiles (larger grids bin with
+  // global atomics)
+  if (g.nbins <= 16384)
+    hipFuncSetAttribute((const void*)bin_hist_kernel<R>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)(g.nbins * 4 > 1024 ? g.nbins * 4 : 1024));
 }
 
 template <class R>

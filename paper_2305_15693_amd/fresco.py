@@ -62,6 +62,7 @@ class PlanInfo(ctypes.Structure):
         ("nbins", ctypes.c_int64),
         ("n_constrained", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64),
+        ("col_split", ctypes.c_int32),
     ]
 
 
@@ -248,7 +249,8 @@ class Context:
         return dict(dim=info.dim, dtype=info.dtype, n=info.n, nf=list(info.nf)[:d],
                     kmax=list(info.kmax)[:d], width=info.width, beta=info.beta,
                     tile=list(info.tile)[:d], nbins=info.nbins,
-                    n_constrained=info.n_constrained, device_bytes=info.device_bytes)
+                    n_constrained=info.n_constrained, device_bytes=info.device_bytes,
+                    col_split=info.col_split)
 
     def default_max_step(self) -> float:
         """0.1 of the mean interparticle spacing L / N^(1/d) (smallest side)."""

@@ -204,3 +204,40 @@ def test_full_size_sampled(gpu, name):
     assert rel(S[cube_idx], r["S"]) < 1e-5
     assert abs(loss - r["loss"]) / r["loss"] < 1e-5
     assert rel(grad[gp], r["grad"]) < 1e-5
+
+
+@pytest.mark.parametrize("dtype,N,L,M,tol,bar", [("f64", 1024, 32.0, 16, 1e-12, 1e-11),
+                                                 ("f32", 20000, 141.4, 40, 1e-6, 1e-5)])
+def test_long_column_path(gpu, dtype, N, L, M, tol, bar):
+    # 2D columns transformed as two half-length sub-columns (the path used when a
+    # column does not fit in LDS, e.g. nf = 24300), forced here at a small size:
+    # S, loss, gradient and the backward of S against the oracle
+    import os
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    pos = I.positions(N, 2, L, np.float32 if dtype == "f32" else np.float64, seed=321)
+    w, s0 = I.stealthy_target(2, M, M)
+    os.environ["FRESCO_LONG_COLS"] = "1"
+    try:
+        ctx = make_ctx(gpu, 2, N, L, M, w, s0, tol, dtype)
+    finally:
+        os.environ.pop("FRESCO_LONG_COLS", None)
+    assert ctx.plan_info()["col_split"] == 2
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    tpos = torch.from_numpy(pos).to(device=gpu, dtype=tdt)
+    S = ctx.structure_factor(tpos).cpu().numpy().astype(np.float64)
+    gS = np.random.default_rng(5).normal(size=ctx.cube_shape)
+    gb = ctx.structure_factor_backward(tpos, torch.from_numpy(gS).to(device=gpu, dtype=tdt),
+                                       token=ctx.sf_token()).cpu().numpy()
+    loss, grad = ctx.loss_grad(tpos)
+    grad = grad.cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    ctx.close()
+    So, lo, go = oracle_case(pos, L, M, w, s0)
+    gbo = O.sf_vjp(pos.astype(np.float64), L, O.mode_vectors(2, M), gS.reshape(-1))
+    print(f"long columns {dtype}: S {rel(S, So):.2e} loss {abs(loss - lo) / lo:.2e} "
+          f"grad {rel(grad, go):.2e} backward {rel(gb, gbo):.2e}", flush=True)
+    assert rel(S, So) < bar
+    assert abs(loss - lo) / lo < bar
+    assert rel(grad, go) < bar
+    assert rel(gb, gbo) < bar

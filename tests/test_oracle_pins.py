@@ -406,3 +406,35 @@ def test_pair_gradient_matches_finite_differences():
         if checked == 6:
             break
     assert checked == 6
+
+
+def test_rho_direct_lattice_and_table_form():
+    # The direct-evaluation form (used for a few modes over very many points) on a
+    # 16 x 16 lattice: |rho| = N exactly on the Bragg peak (16, 0), 0 off it; and it
+    # agrees with the table form on random points.
+    pos = I.square_lattice(16, 32.0, 2, shift=(0.3, 1.7))
+    r = O.rho_direct(pos, 32.0, np.array([[16, 0], [5, 3], [0, 16]], np.int32), chunk=100)
+    assert abs(abs(r[0]) - 256.0) < 1e-10 and abs(r[1]) < 1e-10 and abs(abs(r[2]) - 256.0) < 1e-10
+    rng = np.random.default_rng(2)
+    p = rng.uniform(-5, 15, (2000, 3))
+    m = rng.integers(-9, 10, (7, 3)).astype(np.int32)
+    np.testing.assert_allclose(O.rho_direct(p, (10.0, 12.0, 9.0), m, chunk=333),
+                               O.rho(p, (10.0, 12.0, 9.0), m), rtol=1e-12, atol=1e-11)
+
+
+def test_loss_grad_from_rho_matches_direct_sums():
+    # Given the direct-evaluation rho, the loss, S and gradient equal those of the
+    # table-based oracle (both evaluate Eq. gradient; this pins the rho hand-over and
+    # the 1/N factors of the large-problem path).
+    rng = np.random.default_rng(3)
+    N, L = 500, 9.0
+    pos = rng.uniform(0, L, (N, 2))
+    modes = _modes_ball(2, 4.0)
+    W = rng.uniform(0.5, 2, len(modes))
+    S0 = rng.uniform(0, 1, len(modes))
+    ref = O.loss_grad(pos, L, modes, W, S0)
+    gp = [3, 77, 400]
+    r = O.loss_grad_from_rho(N, L, modes, W, S0, O.rho_direct(pos, L, modes), pos[gp])
+    assert r["loss"] == pytest.approx(ref["loss"], rel=1e-12)
+    np.testing.assert_allclose(r["S"], ref["S"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(r["grad"], ref["grad"][gp], rtol=1e-11, atol=1e-12)
