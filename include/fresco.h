@@ -93,6 +93,9 @@ typedef struct fresco_plan_info {
   int64_t device_bytes; /* scratch memory held by the context */
   int32_t col_split;    /* 2D last-axis columns transformed as this many sub-columns
                            (1; 2 when a column is too long for one LDS pass) */
+  int32_t bin_ranges;   /* points sorted by tile in one level (0), or in two levels
+                           through this many ranges of consecutive tiles (grids with
+                           more than 16384 tiles), or -1: global atomic counts */
 } fresco_plan_info;
 
 /* Create a context for one problem.  Chooses the fine grid, kernel width and

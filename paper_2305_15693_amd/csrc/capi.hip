@@ -334,28 +334,65 @@ int create_state(fresco_ctx* c) {
   // binning
   const long long N = g.N;
   BinPlan& bp = S->bp;
-  bp.privatized = g.nbins <= 16384;
-  if (bp.privatized) {
-    long long nblk = N / 4096;
-    if (nblk < 1) nblk = 1;
-    if (nblk > 1024) nblk = 1024;
+  bp.mode = BIN_ATOMIC;
+  bp.G = 1;
+  bp.nkeys = g.nbins;
+  bp.shift = 16;
+  bp.nblk = 0;
+  bp.chunk = 0;
+  {
+    // keys: the tiles themselves, or ranges of G consecutive tiles (at most
+    // 8192 ranges of at most 4096 tiles, so both LDS tables stay small)
+    long long G = 1, nkeys = g.nbins;
+    int mode = BIN_TILES;
+    // FRESCO_BIN_RANGES=K sorts in two levels with at most K ranges whatever
+    // the tile count (checks of the large-grid path at small sizes)
+    const char* er = std::getenv("FRESCO_BIN_RANGES");
+    long long kmax = er ? std::atoll(er) : 0;
+    if (kmax < 1 || kmax > 8192) kmax = 0;
+    if (kmax || g.nbins > 16384) {
+      if (!kmax) kmax = 8192;
+      G = (g.nbins + kmax - 1) / kmax;
+      nkeys = (g.nbins + G - 1) / G;
+      mode = BIN_RANGES;
+    }
+    int shift = 0;
+    while ((1ll << shift) < nkeys) ++shift;
+    if (mode == BIN_TILES) shift = 16;
     // chunk: a multiple of 256 (the scatter pass finds its chunk from the block
-    // index) below 2^16 (ranks are 16-bit)
+    // index) whose ranks fit in 32 - shift bits
+    const long long cmax = ((1ll << (32 - shift)) - 1) / 256 * 256;
+    long long nblk = (mode == BIN_TILES) ? N / 4096 : N / 65536;
+    if (nblk < 1) nblk = 1;
+    if (nblk > (mode == BIN_TILES ? 1024 : 2048)) nblk = (mode == BIN_TILES ? 1024 : 2048);
     long long chunk = ((N + nblk - 1) / nblk + 255) / 256 * 256;
-    if (chunk > 65280) chunk = 65280;
+    if (chunk > cmax) chunk = cmax;
     nblk = (N + chunk - 1) / chunk;
-    if (nblk > 4096) bp.privatized = false;
-    bp.nblk = (int)nblk;
-    bp.chunk = chunk;
+    if (G <= 4096 && nblk <= (mode == BIN_TILES ? 4096 : 8192)) {
+      bp.mode = mode;
+      bp.G = (int)G;
+      bp.nkeys = nkeys;
+      bp.shift = shift;
+      bp.nblk = (int)nblk;
+      bp.chunk = chunk;
+    }
   }
+  bp.kdiv = make_fastdiv((uint32_t)bp.G);
   BinBuffers& bb = S->bb;
   if ((st = dalloc_t(c, &bb.kr, N))) return st;
-  if (bp.privatized) {
-    if ((st = dalloc_t(c, &bb.H, (size_t)g.nbins * bp.nblk))) return st;
+  if (bp.mode != BIN_ATOMIC) {
+    if ((st = dalloc_t(c, &bb.H, (size_t)bp.nkeys * bp.nblk))) return st;
   } else {
     if ((st = dalloc_t(c, &bb.key, N))) return st;
   }
-  if ((st = dalloc_t(c, &bb.count, g.nbins))) return st;
+  if (bp.mode == BIN_RANGES) {
+    if ((st = dalloc_t(c, &bb.kstart, bp.nkeys + 1))) return st;
+    R* tpos = nullptr;
+    if ((st = dalloc_t(c, &tpos, (size_t)N * d))) return st;
+    bb.tpos = tpos;
+    if ((st = dalloc_t(c, &bb.tidx, N))) return st;
+  }
+  if ((st = dalloc_t(c, &bb.count, bp.nkeys))) return st;
   if ((st = dalloc_t(c, &bb.start, g.nbins + 1))) return st;
   Rec<R>* rec = nullptr;
   if ((st = dalloc_t(c, &rec, N))) return st;
@@ -668,8 +705,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
   }
   {
     StageTimer t(c, FRESCO_STAGE_INTERP);
-    launch_interp<R>(g,(const Rec<R>*)S->bb.rec, S->bb.start, S->bb.perm, S->v, grad,
-                     st);
+    launch_interp<R>(g, S->bp, S->bb, S->v, grad, st);
   }
   // attached soft-core pair term: its gradient is added to grad, its energy to
   // the loss
@@ -820,7 +856,7 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
     // that the history vectors never need permuting, and later binning passes
     // see nearly sorted points
     launch_bin(g, S->bp, pos, sizeof(R) == 8, S->bb, c->st);
-    HIPCHK(hipMemcpyAsync(S->perm0, S->bb.perm, sizeof(int) * N, hipMemcpyDeviceToDevice, c->st));
+    launch_sorted_index(g, S->bp, S->bb, S->perm0, c->st);
     if ((st = lbfgs_reset_state<R>(c))) return st;
     S->have_perm0 = true;
   }
@@ -1107,6 +1143,9 @@ int fresco_plan_info_get(const fresco_ctx* c, fresco_plan_info* o) {
   o->col_split = 1;
   if (c->dtype == FRESCO_F32 && ((const State<float>*)c->state)->long_cols) o->col_split = 2;
   if (c->dtype == FRESCO_F64 && ((const State<double>*)c->state)->long_cols) o->col_split = 2;
+  const BinPlan& bp = (c->dtype == FRESCO_F32) ? ((const State<float>*)c->state)->bp
+                                               : ((const State<double>*)c->state)->bp;
+  o->bin_ranges = bp.mode == BIN_RANGES ? (int32_t)bp.nkeys : bp.mode == BIN_TILES ? 0 : -1;
   return FRESCO_OK;
 }
 

@@ -107,20 +107,37 @@ struct alignas(4 * sizeof(R)) Rec {
 constexpr int kPolyDeg = 9;
 
 // Counting sort of the points by tile.
+//   BIN_TILES   block-private LDS histograms over the tiles (tiles <= 16384);
+//   BIN_RANGES  two levels for larger grids: block-private histograms over
+//               ranges of G consecutive tiles (at most 8192 ranges) place the
+//               points by range (positions copied to tpos, caller index to
+//               tidx), then one workgroup per range sorts its points by tile
+//               in LDS.  perm then maps a sorted record to its tpos index;
+//               interpolation writes through it into tpos and a gather pass
+//               restores the caller's order;
+//   BIN_ATOMIC  global atomic counts per tile (grids beyond both).
+enum BinMode { BIN_TILES = 0, BIN_RANGES = 1, BIN_ATOMIC = 2 };
 struct BinPlan {
-  bool privatized;  // block-private LDS histograms (tiles <= 16384) or global atomics
+  int mode;         // BinMode
   int nblk;         // blocks of the histogram pass
-  long long chunk;  // points per histogram block
+  long long chunk;  // points per histogram block (multiple of 256)
+  long long nkeys;  // histogram keys: tiles (BIN_TILES) or ranges (BIN_RANGES)
+  int G;            // tiles per range (BIN_RANGES), 1 otherwise
+  FastDiv kdiv;     // division by G
+  int shift;        // kr = key | rank << shift
 };
 struct BinBuffers {
-  uint32_t* kr = nullptr;     // privatized: tile | rank << 16; fallback: rank
-  uint32_t* key = nullptr;    // fallback: tile per point
-  uint32_t* H = nullptr;      // privatized: [tile][block] counts, then offsets
-  uint32_t* count = nullptr;  // points per tile
+  uint32_t* kr = nullptr;     // histogram passes: key | rank << shift; atomic: rank
+  uint32_t* key = nullptr;    // atomic: tile per point
+  uint32_t* H = nullptr;      // [key][block] counts, then offsets
+  uint32_t* count = nullptr;  // points per key
   long long* start = nullptr; // tile starts (nbins + 1)
+  long long* kstart = nullptr;  // BIN_RANGES: range starts (nkeys + 1)
+  void* tpos = nullptr;       // BIN_RANGES: positions in range order [N][d]
+  int* tidx = nullptr;        // BIN_RANGES: range order -> caller index
   void* rec = nullptr;        // Rec<R>[N], sorted
-  int* perm = nullptr;        // sorted position -> original index
-  int* flag = nullptr;        // set when a position is not finite
+  int* perm = nullptr;        // sorted position -> caller index (tpos index for BIN_RANGES)
+  int* flag = nullptr;        // bit 0: a position is not finite
 };
 
 // For each axis, the padded spreading tiles that cover every grid coordinate:
@@ -144,10 +161,13 @@ void launch_spread(const Geom& g, const Rec<R>* rec,
                    const long long* start, R* tiles, hipStream_t st);
 template <class R>
 void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, hipStream_t st);
+// interpolation of the field v at the binned points into grad (caller's order)
 template <class R>
-void launch_interp(const Geom& g, const Rec<R>* rec,
-                   const long long* start, const int* perm, const R* v, R* grad,
+void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const R* v, R* grad,
                    hipStream_t st);
+// out[j] = caller index of sorted record j
+void launch_sorted_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, int* out,
+                         hipStream_t st);
 template <class R>
 void launch_fill(R* p, long long n, R v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);

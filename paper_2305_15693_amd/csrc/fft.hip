@@ -222,9 +222,11 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
         cp = ((long long)(n0 + p.M0) * p.P1 + (n1 + p.M1)) * p.P2 + (nl + p.M2);
         cm = ((long long)(-n0 + p.M0) * p.P1 + (-n1 + p.M1)) * p.P2 + (-nl + p.M2);
       }
+      // the n_0 = 0 plane lists both members of each pair: each writes its own
+      // entry only (two writers of one entry would race)
       if ((MODE == COL_SF || MODE == COL_FUSED) && p.S_cube) {
         p.S_cube[cp] = S;
-        p.S_cube[cm] = S;
+        if (n0 > 0) p.S_cube[cm] = S;
       }
       if (MODE == COL_FUSED || MODE == COL_BWD) {
         // G: dL/dS symmetrised over the pair (n, -n)
@@ -321,7 +323,7 @@ __global__ void long_modes_kernel(ColParams<R> p, const cpx<R>* __restrict__ Y,
     const long long cm = (long long)(-n0 + p.M0) * p.P1 + (-nl + p.M1);
     if ((MODE == COL_SF || MODE == COL_FUSED) && p.S_cube) {
       p.S_cube[cp] = S;
-      p.S_cube[cm] = S;
+      if (n0 > 0) p.S_cube[cm] = S;  // the n_0 = 0 plane writes each entry itself
     }
     if (MODE == COL_FUSED || MODE == COL_BWD) {
       R G;

@@ -16,6 +16,16 @@
 //   rowscan  per tile, exclusive scan over the blocks -> offset of each block;
 //   scan     exclusive scan over tiles -> tile starts;
 //   scatter  sorted record written at start[tile] + offset[tile][block] + rank.
+// Grids with more tiles than an LDS histogram holds sort in two levels: the same
+// four passes over ranges of G consecutive tiles move each point's position into
+// its range's segment (runs of consecutive destinations, so the writes combine in
+// the caches), then one workgroup per range counts its segment per tile in LDS,
+// scans, and writes the sorted records (every write lands inside the segment).
+// Interpolation then writes the gradient into the segment order and a gather
+// pass, which recomputes each point's segment slot from the first level's
+// histogram offsets, restores the caller's order with coalesced stores; a
+// single-level sort would instead scatter every point's record and gradient to a
+// random address over the whole array.
 //
 // Spreading.  One workgroup per tile accumulates its points into an LDS copy of
 // the tile padded by w - 1 cells, in fixed point with integer LDS atomics
@@ -72,13 +82,14 @@ struct PointBin {
   double t[3];
 };
 
-template <class R>
-__device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* bad) {
+template <class R, int D>
+__device__ __forceinline__ PointBin bin_point_d(const Geom& g, const R* r, bool* bad) {
   PointBin pb;
   pb.cell = 0;
   uint32_t tile[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) pb.t[a] = 0.0;
-  for (int a = 0; a < g.d; ++a) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
     double x = (double)r[a];
     const double nf = (double)g.nf[a];
     double u = x * g.ufac[a];
@@ -104,16 +115,21 @@ __device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* b
   pb.bin = tile[0] + (uint32_t)g.nt[0] * (tile[1] + (uint32_t)g.nt[1] * tile[2]);
   return pb;
 }
+// g.d is uniform: both branches keep every index a compile-time constant
+template <class R>
+__device__ __forceinline__ PointBin bin_point(const Geom& g, const R* r, bool* bad) {
+  return g.d == 2 ? bin_point_d<R, 2>(g, r, bad) : bin_point_d<R, 3>(g, r, bad);
+}
 
-// Block-private histogram.  kr[i] = tile | rank << 16 (tile < 2^16, rank < 2^16);
-// H[tile * nblk + block] = points of the block in the tile.
+// Block-private histogram over the keys tile / G (G = 1: the tiles).
+// kr[i] = key | rank << shift (key < 2^shift, rank < 2^(32 - shift));
+// H[key * nblk + block] = points of the block with that key.
 template <class R>
 __global__ void bin_hist_kernel(Geom g, const R* __restrict__ pos, long long chunk, int nblk,
-                                uint32_t* __restrict__ kr, uint32_t* __restrict__ H,
-                                int* __restrict__ flag) {
+                                int nkeys, FastDiv kdiv, int shift, uint32_t* __restrict__ kr,
+                                uint32_t* __restrict__ H, int* __restrict__ flag) {
   extern __shared__ uint32_t hist[];
-  const int nb = (int)g.nbins;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0;
+  for (int i = threadIdx.x; i < nkeys; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   const long long i0 = (long long)blockIdx.x * chunk;
   long long i1 = i0 + chunk;
@@ -121,12 +137,14 @@ __global__ void bin_hist_kernel(Geom g, const R* __restrict__ pos, long long chu
   bool bad = false;
   for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
-    uint32_t r = atomicAdd(&hist[pb.bin], 1u);
-    kr[i] = pb.bin | (r << 16);
+    const uint32_t key = fdiv(pb.bin, kdiv);
+    uint32_t r = atomicAdd(&hist[key], 1u);
+    kr[i] = key | (r << shift);
   }
   if (bad) atomicOr(flag, 1);
   __syncthreads();
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) H[(long long)b * nblk + blockIdx.x] = hist[b];
+  for (int b = threadIdx.x; b < nkeys; b += blockDim.x)
+    H[(long long)b * nblk + blockIdx.x] = hist[b];
 }
 
 // Per tile: exclusive scan of H[tile][0..nblk) in place; count[tile] = total.
@@ -176,6 +194,177 @@ __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, uint32_t b
   o.cell = pb.cell;
   rec[dst] = o;
   perm[dst] = (int)i;
+}
+
+// Slot of point i in the range order (first level of BIN_RANGES); 256-thread
+// blocks, bpc blocks per histogram chunk.
+__device__ __forceinline__ long long range_slot(uint32_t v, int shift, uint32_t blk, int nblk,
+                                                const uint32_t* __restrict__ H,
+                                                const long long* __restrict__ kstart) {
+  const uint32_t key = v & ((1u << shift) - 1u), rank = v >> shift;
+  return kstart[key] + H[(long long)key * nblk + blk] + rank;
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin by index.  The range
+// passes give all 256-point blocks of one histogram chunk to one XCD (chunks
+// x, x + 8, ... to XCD x, each in order), so that the runs of consecutive slots a
+// chunk fills in every segment are written (or read) through one L2 and combine
+// there into whole lines.  Grid: 8 ceil(nblk / 8) bpc workgroups; returns the
+// point block of workgroup w and its chunk.
+__device__ __forceinline__ long long xcd_point_block(uint32_t w, uint32_t bpc, uint32_t* chunk) {
+  const uint32_t x = w & 7u, l = w >> 3;
+  const uint32_t gc = l / bpc, k = l - gc * bpc;
+  *chunk = gc * 8u + x;
+  return (long long)(*chunk) * bpc + k;
+}
+inline unsigned xcd_grid(int nblk, long long chunk) {
+  return (unsigned)(8ll * ((nblk + 7) / 8) * (chunk / 256));
+}
+
+// First level: copy each point's position and index into its range's segment.
+template <class R>
+__global__ void range_scatter_kernel(long long N, int d, const R* __restrict__ pos, uint32_t bpc,
+                                     int nblk, int shift, const uint32_t* __restrict__ kr,
+                                     const uint32_t* __restrict__ H,
+                                     const long long* __restrict__ kstart, R* __restrict__ tpos,
+                                     int* __restrict__ tidx) {
+  uint32_t c;
+  const long long q = xcd_point_block(blockIdx.x, bpc, &c);
+  const long long i = q * 256 + threadIdx.x;
+  if (c >= (uint32_t)nblk || i >= N) return;
+  const long long dst = range_slot(kr[i], shift, c, nblk, H, kstart);
+  for (int a = 0; a < d; ++a) tpos[dst * d + a] = pos[i * d + a];
+  tidx[dst] = (int)i;
+}
+
+// Second level: one workgroup per range of G tiles sorts its segment
+// tpos[kstart[s] .. kstart[s+1]) by tile.  LDS: cnt[G] counts, then the running
+// write offsets.  Writes start[] of the range's tiles (and start[nbins]).  Each
+// thread loads kRangeU positions before it bins them (several loads in flight
+// per wave; the passes are otherwise latency-bound).
+constexpr int kRangeU = 4;
+template <class R, int D>
+__device__ __forceinline__ int range_load(const R* __restrict__ tpos, long long j0, long long b,
+                                          R (&x)[kRangeU][D]) {
+  int n = 0;
+#pragma unroll
+  for (int u = 0; u < kRangeU; ++u) {
+    const long long j = j0 + (long long)u * blockDim.x;
+    if (j < b) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) x[u][a] = tpos[j * D + a];
+      n = u + 1;
+    }
+  }
+  return n;
+}
+template <class R, int D>
+__global__ void range_sort_kernel(Geom g, int G, const R* __restrict__ tpos,
+                                  const long long* __restrict__ kstart,
+                                  long long* __restrict__ start, Rec<R>* __restrict__ rec,
+                                  int* __restrict__ perm, int* __restrict__ flag) {
+  extern __shared__ uint32_t cnt[];
+  __shared__ uint32_t wsum[16];
+  const long long t0 = (long long)blockIdx.x * G;
+  const int nt = (int)((t0 + G <= g.nbins) ? G : g.nbins - t0);
+  const long long a = kstart[blockIdx.x], b = kstart[blockIdx.x + 1];
+  for (int i = threadIdx.x; i < G; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  bool bad = false, stray = false;
+  const long long step = (long long)kRangeU * blockDim.x;
+  for (long long j0 = a + threadIdx.x; j0 < b; j0 += step) {
+    R x[kRangeU][D];
+    const int n = range_load<R, D>(tpos, j0, b, x);
+#pragma unroll
+    for (int u = 0; u < kRangeU; ++u) {
+      if (u < n) {
+        PointBin pb = bin_point_d<R, D>(g, x[u], &bad);
+        uint32_t loc = pb.bin - (uint32_t)t0;
+        if (loc >= (uint32_t)nt) {  // the first level put it here from the same bits
+          stray = true;
+          loc = nt - 1;
+        }
+        atomicAdd(&cnt[loc], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  // exclusive scan of cnt[0..nt): contiguous chunks per thread, then the thread
+  // sums across the block
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int per = (nt + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int c0 = min((int)threadIdx.x * per, nt), c1 = min(c0 + per, nt);
+  uint32_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += cnt[c];
+  uint32_t x = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < nw; ++k) {
+      const uint32_t t = wsum[k];
+      wsum[k] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+  uint32_t base = wsum[wv] + x - sum;
+  for (int c = c0; c < c1; ++c) {
+    const uint32_t t = cnt[c];
+    cnt[c] = base;
+    start[t0 + c] = a + base;
+    base += t;
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) start[g.nbins] = b;
+  __syncthreads();
+  for (long long j0 = a + threadIdx.x; j0 < b; j0 += step) {
+    R x[kRangeU][D];
+    const int n = range_load<R, D>(tpos, j0, b, x);
+#pragma unroll
+    for (int u = 0; u < kRangeU; ++u) {
+      if (u < n) {
+        PointBin pb = bin_point_d<R, D>(g, x[u], &bad);
+        uint32_t loc = pb.bin - (uint32_t)t0;
+        if (loc >= (uint32_t)nt) loc = nt - 1;
+        const long long dst = a + atomicAdd(&cnt[loc], 1u);
+        Rec<R> o;
+        o.t[0] = (R)pb.t[0];
+        o.t[1] = (R)pb.t[1];
+        o.t[2] = (R)pb.t[2];
+        o.cell = pb.cell;
+        rec[dst] = o;
+        perm[dst] = (int)(j0 + (long long)u * blockDim.x);
+      }
+    }
+  }
+  if (stray) atomicOr(flag, 2);
+}
+
+// grad[i] = gseg[slot of i] (caller's order from the range order)
+template <class R>
+__global__ void range_gather_kernel(long long N, int d, uint32_t bpc, int nblk, int shift,
+                                    const uint32_t* __restrict__ kr,
+                                    const uint32_t* __restrict__ H,
+                                    const long long* __restrict__ kstart,
+                                    const R* __restrict__ gseg, R* __restrict__ grad) {
+  uint32_t c;
+  const long long q = xcd_point_block(blockIdx.x, bpc, &c);
+  const long long i = q * 256 + threadIdx.x;
+  if (c >= (uint32_t)nblk || i >= N) return;
+  const long long src = range_slot(kr[i], shift, c, nblk, H, kstart);
+  for (int a = 0; a < d; ++a) grad[i * d + a] = gseg[src * d + a];
+}
+
+// out[j] = tidx[perm[j]]
+__global__ void compose_index_kernel(long long N, const int* __restrict__ perm,
+                                     const int* __restrict__ tidx, int* __restrict__ out) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < N) out[j] = tidx[perm[j]];
 }
 
 // Fallback for very many tiles: global atomic counts (key, rank per point).
@@ -242,25 +431,59 @@ __global__ void scan_bins_kernel(const uint32_t* __restrict__ count, long long n
 void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, BinBuffers& b,
                 hipStream_t st) {
   const long long nblocks = (g.N + 255) / 256;
-  if (bp.privatized) {
-    const size_t lds = (size_t)g.nbins * sizeof(uint32_t);
+  if (bp.mode == BIN_TILES || bp.mode == BIN_RANGES) {
+    const size_t lds = (size_t)bp.nkeys * sizeof(uint32_t);
+    const int nk = (int)bp.nkeys;
     if (f64)
       bin_hist_kernel<double><<<bp.nblk, 1024, lds, st>>>(g, (const double*)pos, bp.chunk,
-                                                         bp.nblk, b.kr, b.H, b.flag);
+                                                         bp.nblk, nk, bp.kdiv, bp.shift, b.kr,
+                                                         b.H, b.flag);
     else
       bin_hist_kernel<float><<<bp.nblk, 1024, lds, st>>>(g, (const float*)pos, bp.chunk,
-                                                        bp.nblk, b.kr, b.H, b.flag);
-    bin_rowscan_kernel<<<(unsigned)((g.nbins + 3) / 4), 256, 0, st>>>(b.H, bp.nblk, g.nbins,
-                                                                       b.count);
-    scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, g.nbins, b.start);
-    if (f64)
-      bin_scatter_kernel<double><<<(unsigned)nblocks, 256, 0, st>>>(
-          g, (const double*)pos, (uint32_t)(bp.chunk / 256), bp.nblk, b.kr, b.H, b.start, (Rec<double>*)b.rec,
-          b.perm);
-    else
-      bin_scatter_kernel<float><<<(unsigned)nblocks, 256, 0, st>>>(
-          g, (const float*)pos, (uint32_t)(bp.chunk / 256), bp.nblk, b.kr, b.H, b.start, (Rec<float>*)b.rec,
-          b.perm);
+                                                        bp.nblk, nk, bp.kdiv, bp.shift, b.kr,
+                                                        b.H, b.flag);
+    bin_rowscan_kernel<<<(unsigned)((bp.nkeys + 3) / 4), 256, 0, st>>>(b.H, bp.nblk, bp.nkeys,
+                                                                        b.count);
+    const uint32_t bpc = (uint32_t)(bp.chunk / 256);
+    if (bp.mode == BIN_TILES) {
+      scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, g.nbins, b.start);
+      if (f64)
+        bin_scatter_kernel<double><<<(unsigned)nblocks, 256, 0, st>>>(
+            g, (const double*)pos, bpc, bp.nblk, b.kr, b.H, b.start, (Rec<double>*)b.rec,
+            b.perm);
+      else
+        bin_scatter_kernel<float><<<(unsigned)nblocks, 256, 0, st>>>(
+            g, (const float*)pos, bpc, bp.nblk, b.kr, b.H, b.start, (Rec<float>*)b.rec,
+            b.perm);
+    } else {
+      scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, bp.nkeys, b.kstart);
+      const size_t lds2 = (size_t)bp.G * sizeof(uint32_t);
+      if (f64) {
+        range_scatter_kernel<double><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
+            g.N, g.d, (const double*)pos, bpc, bp.nblk, bp.shift, b.kr, b.H, b.kstart,
+            (double*)b.tpos, b.tidx);
+        if (g.d == 2)
+          range_sort_kernel<double, 2><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
+              g, bp.G, (const double*)b.tpos, b.kstart, b.start, (Rec<double>*)b.rec, b.perm,
+              b.flag);
+        else
+          range_sort_kernel<double, 3><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
+              g, bp.G, (const double*)b.tpos, b.kstart, b.start, (Rec<double>*)b.rec, b.perm,
+              b.flag);
+      } else {
+        range_scatter_kernel<float><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
+            g.N, g.d, (const float*)pos, bpc, bp.nblk, bp.shift, b.kr, b.H, b.kstart,
+            (float*)b.tpos, b.tidx);
+        if (g.d == 2)
+          range_sort_kernel<float, 2><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
+              g, bp.G, (const float*)b.tpos, b.kstart, b.start, (Rec<float>*)b.rec, b.perm,
+              b.flag);
+        else
+          range_sort_kernel<float, 3><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
+              g, bp.G, (const float*)b.tpos, b.kstart, b.start, (Rec<float>*)b.rec, b.perm,
+              b.flag);
+      }
+    }
   } else {
     launch_fill<uint32_t>(b.count, g.nbins, 0u, st);
     if (f64)
@@ -606,12 +829,9 @@ void spread_prepare(const Geom& g) {
   } while (0)
   FRESCO_W_SWITCH(g.w, PREP)
 #undef PREP
-  // block-private histograms only up to 16384 tiles (larger grids bin with
-  // global atomics)
-  if (g.nbins <= 16384)
-    hipFuncSetAttribute((const void*)bin_hist_kernel<R>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)(g.nbins * 4 > 1024 ? g.nbins * 4 : 1024));
+  // block-private histograms: at most 16384 keys
+  hipFuncSetAttribute((const void*)bin_hist_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      16384 * 4);
 }
 
 template <class R>
@@ -642,22 +862,40 @@ void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, h
 }
 
 template <class R>
-void launch_interp(const Geom& g, const Rec<R>* rec,
-                   const long long* start, const int* perm, const R* v, R* grad,
+void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const R* v, R* grad,
                    hipStream_t st) {
   const size_t lds = interp_lds_bytes<R>(g);
   const int threads = (g.d == 3) ? 512 : 256;
+  const Rec<R>* rec = (const Rec<R>*)b.rec;
+  const long long* start = b.start;
+  const int* perm = b.perm;
+  // BIN_RANGES: the gradient goes to the range order first (tpos is free once
+  // the records are sorted), then to the caller's order
+  R* out = (bp.mode == BIN_RANGES) ? (R*)b.tpos : grad;
 #define IP(W)                                                                                 \
   do {                                                                                        \
     if (g.d == 2)                                                                             \
       interp_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
-                                                                      perm, v, grad);         \
+                                                                      perm, v, out);          \
     else                                                                                      \
       interp_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
-                                                                      perm, v, grad);         \
+                                                                      perm, v, out);          \
   } while (0)
   FRESCO_W_SWITCH(g.w, IP)
 #undef IP
+  if (bp.mode == BIN_RANGES)
+    range_gather_kernel<R><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
+        g.N, g.d, (uint32_t)(bp.chunk / 256), bp.nblk, bp.shift, b.kr, b.H, b.kstart, out,
+        grad);
+}
+
+void launch_sorted_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, int* out,
+                         hipStream_t st) {
+  if (bp.mode == BIN_RANGES)
+    compose_index_kernel<<<(unsigned)((g.N + 255) / 256), 256, 0, st>>>(g.N, b.perm, b.tidx,
+                                                                         out);
+  else
+    (void)hipMemcpyAsync(out, b.perm, sizeof(int) * g.N, hipMemcpyDeviceToDevice, st);
 }
 
 template size_t spread_lds_bytes<float>(const Geom&);
@@ -674,11 +912,9 @@ template void launch_fold<float>(const Geom&, const float*, float*, const FoldTa
                                  hipStream_t);
 template void launch_fold<double>(const Geom&, const double*, double*, const FoldTables&,
                                   hipStream_t);
-template void launch_interp<float>(const Geom&, const Rec<float>*,
-                                   const long long*, const int*, const float*, float*,
-                                   hipStream_t);
-template void launch_interp<double>(const Geom&, const Rec<double>*,
-                                    const long long*, const int*, const double*, double*,
-                                    hipStream_t);
+template void launch_interp<float>(const Geom&, const BinPlan&, const BinBuffers&, const float*,
+                                   float*, hipStream_t);
+template void launch_interp<double>(const Geom&, const BinPlan&, const BinBuffers&,
+                                    const double*, double*, hipStream_t);
 
 }  // namespace fresco

@@ -63,6 +63,7 @@ class PlanInfo(ctypes.Structure):
         ("n_constrained", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64),
         ("col_split", ctypes.c_int32),
+        ("bin_ranges", ctypes.c_int32),
     ]
 
 
@@ -250,7 +251,7 @@ class Context:
                     kmax=list(info.kmax)[:d], width=info.width, beta=info.beta,
                     tile=list(info.tile)[:d], nbins=info.nbins,
                     n_constrained=info.n_constrained, device_bytes=info.device_bytes,
-                    col_split=info.col_split)
+                    col_split=info.col_split, bin_ranges=info.bin_ranges)
 
     def default_max_step(self) -> float:
         """0.1 of the mean interparticle spacing L / N^(1/d) (smallest side)."""
