@@ -51,6 +51,8 @@ struct State {
   R* tiles = nullptr;  // padded spreading tiles
   int* fold_off[3] = {nullptr, nullptr, nullptr};
   int2* fold_ent[3] = {nullptr, nullptr, nullptr};
+  int fold_nent[3] = {0, 0, 0};    // entries per axis
+  bool fold_fused = false;         // fold done inside the forward row pass
   R* grid = nullptr;
   cpx<R>* A1 = nullptr;  // half spectrum after the row pass
   cpx<R>* A2 = nullptr;  // 3D: after the axis-1 pass
@@ -296,7 +298,7 @@ __global__ void finish_kernel(const double* __restrict__ part, long long n,
 }
 
 // per-axis CSR of the padded tiles covering each grid coordinate
-int build_fold_tables(fresco_ctx* c, int a, int** off_d, int2** ent_d) {
+int build_fold_tables(fresco_ctx* c, int a, int** off_d, int2** ent_d, int* nent) {
   const Geom& g = c->g;
   const int nf = g.nf[a], T = g.T[a], E = g.E[a], nt = g.nt[a];
   std::vector<std::vector<int2>> lists(nf);
@@ -312,6 +314,7 @@ int build_fold_tables(fresco_ctx* c, int a, int** off_d, int2** ent_d) {
     for (auto& e : lists[y]) ent.push_back(e);
   }
   off[nf] = (int)ent.size();
+  *nent = (int)ent.size();
   int st;
   if ((st = upload_raw(c, off_d, off))) return st;
   if ((st = upload_raw(c, ent_d, ent))) return st;
@@ -406,7 +409,8 @@ int create_state(fresco_ctx* c) {
   const long long tcells = (long long)g.E[0] * g.E[1] * (d == 3 ? g.E[2] : 1);
   if ((st = dalloc_t(c, &S->tiles, (size_t)(g.nbins * tcells)))) return st;
   for (int a = 0; a < d; ++a)
-    if ((st = build_fold_tables(c, a, &S->fold_off[a], &S->fold_ent[a]))) return st;
+    if ((st = build_fold_tables(c, a, &S->fold_off[a], &S->fold_ent[a], &S->fold_nent[a])))
+      return st;
   // grids
   const long long H0 = g.M[0] + 1;
   const long long P1 = 2 * g.M[1] + 1;
@@ -438,6 +442,31 @@ int create_state(fresco_ctx* c) {
   if (!shape_rows(g.nf[0] / 2, S->ax[0].rmin, rp.nrows, cs, &rp.lines_per_block, &rp.threads,
                   &rp.tw_lds))
     return FRESCO_ENOTSUP;
+  {
+    // fold inside the forward row pass when the first axis's cover lists fit
+    // in LDS beside the lines (FRESCO_FOLD=0 keeps the stand-alone fold kernel)
+    RowFold<R>& f = rp.fold;
+    f.tiles = S->tiles;
+    for (int a = 0; a < 3; ++a) {
+      f.off[a] = S->fold_off[a];
+      f.ent[a] = S->fold_ent[a];
+    }
+    f.nent0 = S->fold_nent[0];
+    f.d = d;
+    f.nf0 = g.nf[0];
+    f.nf1 = g.nf[1];
+    f.E0 = g.E[0];
+    f.E1 = g.E[1];
+    f.nt0 = g.nt[0];
+    f.nt1 = g.nt[1];
+    f.ncell = (long long)g.E[0] * g.E[1] * (d == 3 ? g.E[2] : 1);
+    bool fuse = true;
+    const char* ef = std::getenv("FRESCO_FOLD");
+    if (ef && ef[0] == '0') fuse = false;
+    if (fuse && rows_lds_bytes<R>(rp, S->ax[0]) > kLdsLimit) fuse = false;
+    if (!fuse) std::memset(&f, 0, sizeof(f));
+    S->fold_fused = fuse;
+  }
   auto fill_modes = [&](ColParams<R>& cp) {
     cp.d = d;
     cp.M0 = g.M[0];
@@ -598,7 +627,7 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
     launch_spread<R>(g,(const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
   }
-  {
+  if (!S->fold_fused) {
     StageTimer t(c, FRESCO_STAGE_FOLD);
     FoldTables ft;
     for (int a = 0; a < 3; ++a) {
@@ -697,6 +726,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
     HIPCHK(launch_cols<R>(COL_INV, inv, S->ax[1], 1, st));
   }
   RowParams<R> rp = S->rows;
+  rp.fold.tiles = nullptr;  // forward only
   rp.cin[0] = S->V1;
   rp.rout[0] = S->v;
   {

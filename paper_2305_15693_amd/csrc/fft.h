@@ -14,6 +14,20 @@ struct AxisFft {
   cpx<R>* twN = nullptr;  // rows only: exp(+2 pi i q / (2 F.n)), q in [0, F.n)
 };
 
+// Forward rows read straight from the padded spreading tiles (the fold fused
+// into the row pass): cover lists as in FoldTables, at most two entries per
+// grid coordinate on every axis; the first axis's lists are staged in LDS.
+template <class R>
+struct RowFold {
+  const R* tiles;        // null: rows read rin
+  const int* off[3];
+  const int2* ent[3];
+  int nent0;             // entries of the first-axis lists
+  int d, nf0, nf1;
+  int E0, E1, nt0, nt1;
+  long long ncell;       // cells of one padded tile
+};
+
 template <class R>
 struct RowParams {
   long long nrows;
@@ -25,6 +39,7 @@ struct RowParams {
   cpx<R>* cout;          // forward output rows (M0+1 complex)
   const cpx<R>* cin[3];  // inverse inputs per component
   R* rout[3];            // inverse outputs per component
+  RowFold<R> fold;       // forward only
 };
 
 template <class R>

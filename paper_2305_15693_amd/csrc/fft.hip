@@ -27,6 +27,122 @@ namespace fresco {
 // k in [0, M0], via z_m = x_2m + i x_2m+1 and a complex FFT of length H = nf/2:
 //   X[k] = (Z[k] + conj Z[H-k]) / 2 + exp(+2 pi i k / nf) (Z[k] - conj Z[H-k]) / (2i).
 // LDS: [twiddles H][lines x (H + 1)].
+// Copy src[k * sstride] to dst[k * dstride] for k = k0, k0 + step, ... < cnt,
+// four loads in flight per thread before the first store (line loads are
+// latency-bound otherwise).
+template <class T>
+__device__ __forceinline__ void copy_strided4(T* __restrict__ dst, long long dstride,
+                                              const T* __restrict__ src, long long sstride,
+                                              int k0, int step, int cnt) {
+  for (int k = k0; k < cnt; k += 4 * step) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k + u * step < cnt) v[u] = src[(long long)(k + u * step) * sstride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k + u * step < cnt) dst[(long long)(k + u * step) * dstride] = v[u];
+  }
+}
+
+// One grid line of the folded spread: cell (x, y, z) = sum over the padded
+// tiles that cover it, in the order of the stand-alone fold.  xoff / xent: the
+// first axis's cover lists in LDS.  Cells covered at most twice along every axis
+// (all but those next to the wrap of a grid that is not a whole number of tiles)
+// take a fixed set of loads issued together; the others walk their lists.
+template <class R>
+__device__ __forceinline__ R fold_cell_any(const RowFold<R>& f, int x, int yb, int ye, int zb,
+                                           int ze, const int* xoff, const int2* xent) {
+  R acc = R(0);
+  for (int iz = zb; iz < ze; ++iz) {
+    int tz = 0, lz = 0;
+    if (f.d == 3) {
+      const int2 e = f.ent[2][iz];
+      tz = e.x;
+      lz = e.y;
+    }
+    for (int iy = yb; iy < ye; ++iy) {
+      const int2 ey = f.ent[1][iy];
+      const long long base = (long long)f.nt0 * (ey.x + f.nt1 * tz) * f.ncell +
+                             (long long)(lz * f.E1 + ey.y) * f.E0;
+      for (int ix = xoff[x]; ix < xoff[x + 1]; ++ix) {
+        const int2 ex = xent[ix];
+        acc += f.tiles[base + (long long)ex.x * f.ncell + ex.y];
+      }
+    }
+  }
+  return acc;
+}
+
+template <class R>
+__device__ __forceinline__ void fold_line(const RowFold<R>& f, long long row, const int* xoff,
+                                          const int2* xent, cpx<R>* __restrict__ line, int tj,
+                                          int JT, int H) {
+  const int y = (f.d == 3) ? (int)(row % f.nf1) : (int)row;
+  const int z = (f.d == 3) ? (int)(row / f.nf1) : 0;
+  const int yb = f.off[1][y], ye = f.off[1][y + 1];
+  const int zb = (f.d == 3) ? f.off[2][z] : 0;
+  const int ze = (f.d == 3) ? f.off[2][z + 1] : 1;
+  const int ny = ye - yb, nz = ze - zb;
+  const bool fast_yz = ny <= 2 && nz <= 2;
+  long long base[2][2];
+  bool ok[2][2];
+#pragma unroll
+  for (int kz = 0; kz < 2; ++kz) {
+    int tz = 0, lz = 0;
+    if (f.d == 3 && kz < nz) {
+      const int2 e = f.ent[2][zb + kz];
+      tz = e.x;
+      lz = e.y;
+    }
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky) {
+      ok[kz][ky] = kz < nz && ky < ny;
+      base[kz][ky] = 0;
+      if (ok[kz][ky]) {
+        const int2 e = f.ent[1][yb + ky];
+        base[kz][ky] = (long long)f.nt0 * (e.x + f.nt1 * tz) * f.ncell +
+                       (long long)(lz * f.E1 + e.y) * f.E0;
+      }
+    }
+  }
+  for (int m = tj; m < H; m += JT) {
+    R acc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int x = 2 * m + h;
+      const int xb = xoff[x], nx = xoff[x + 1] - xb;
+      if (fast_yz && nx <= 2) {
+        // every load issued (unused taps read the first cell), then summed
+        const int2 e0 = xent[xb], e1 = xent[xb + (nx > 1 ? 1 : 0)];
+        R v[2][2][2];
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+          for (int ky = 0; ky < 2; ++ky) {
+            const long long b0 = ok[kz][ky] ? base[kz][ky] + e0.x * f.ncell + e0.y : 0;
+            const long long b1 = (ok[kz][ky] && nx > 1) ? base[kz][ky] + e1.x * f.ncell + e1.y : 0;
+            v[kz][ky][0] = f.tiles[b0];
+            v[kz][ky][1] = f.tiles[b1];
+          }
+        R a = R(0);
+#pragma unroll
+        for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+          for (int ky = 0; ky < 2; ++ky)
+            if (ok[kz][ky]) {
+              a += v[kz][ky][0];
+              if (nx > 1) a += v[kz][ky][1];
+            }
+        acc[h] = a;
+      } else {
+        acc[h] = fold_cell_any(f, x, yb, ye, zb, ze, xoff, xent);
+      }
+    }
+    line[m] = cpx<R>{acc[0], acc[1]};
+  }
+}
+
 template <class R, int MAXB>
 __global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __restrict__ twH,
                                 const cpx<R>* __restrict__ twN) {
@@ -41,9 +157,17 @@ __global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   const long long row = (long long)blockIdx.x * p.lines_per_block + b;
   const bool active = row < p.nrows;
   if (twl) load_twiddles(tws, twH, H);
-  const R* __restrict__ x = p.rin + row * (2LL * H);
-  if (active) {
-    for (int m = tj; m < H; m += JT) buf[b * ls + m] = *reinterpret_cast<const cpx<R>*>(x + 2 * m);
+  if (p.fold.tiles) {
+    int* xoff = reinterpret_cast<int*>(buf + (long long)p.lines_per_block * ls);
+    int2* xent = reinterpret_cast<int2*>(xoff + ((2 * H + 2) & ~1));
+    copy_strided4(xoff, 1ll, p.fold.off[0], 1ll, (int)threadIdx.x, (int)blockDim.x, 2 * H + 1);
+    copy_strided4(xent, 1ll, p.fold.ent[0], 1ll, (int)threadIdx.x, (int)blockDim.x,
+                  p.fold.nent0);
+    __syncthreads();
+    if (active) fold_line(p.fold, row, xoff, xent, buf + b * ls, tj, JT, H);
+  } else if (active) {
+    const R* __restrict__ x = p.rin + row * (2LL * H);
+    copy_strided4(buf + b * ls, 1ll, reinterpret_cast<const cpx<R>*>(x), 1ll, tj, JT, H);
   }
   __syncthreads();
   if (twl) lds_fft<R, MAXB, false>(buf, F, tws, active, b, ls, 1, tj, JT);
@@ -116,6 +240,10 @@ __device__ __forceinline__ long long col_base(long long c, const FastDiv& cdiv, 
   return (long long)q * outer + (c - (long long)q * cdiv.d);
 }
 
+// Mode-stage operands of up to kModePre modes per thread, loaded before the
+// forward transform so that their latency overlaps it.
+constexpr int kModePre = 4;
+
 template <class R, int MAXB, int MODE>
 __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restrict__ twg) {
   extern __shared__ unsigned long long smem_u64[];
@@ -140,12 +268,24 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
     else lds_fft<R, MAXB, INV>(buf, F, twg, active, b, 1, bc, tj, JT);           \
   } while (0)
 
+  // FUSED: weights and targets of this thread's modes m = tj + u JT
+  const bool pre = (MODE == COL_FUSED) && P <= kModePre * JT;
+  R pwp[kModePre], pwm[kModePre], psp[kModePre], psm[kModePre];
+  if (MODE == COL_FUSED && pre) {
+#pragma unroll
+    for (int u = 0; u < kModePre; ++u) {
+      const int m = tj + u * JT;
+      const long long h = c + (long long)p.ncols * m;
+      const bool ok = active && m < P;
+      pwp[u] = ok ? p.Wp[h] : R(0);
+      pwm[u] = ok ? p.Wm[h] : R(0);
+      psp[u] = ok ? p.S0p[h] : R(0);
+      psm[u] = ok ? p.S0m[h] : R(0);
+    }
+  }
   if (MODE == COL_FWD || MODE == COL_FUSED || MODE == COL_SF) {
     // forward: load the full spatial line, transform with exp(+i ...)
-    if (active) {
-      const cpx<R>* __restrict__ in = p.in[0];
-      for (int i = tj; i < n; i += JT) buf[i * bc + b] = in[ib + (long long)i * p.in_line];
-    }
+    if (active) copy_strided4(buf + b, (long long)bc, p.in[0] + ib, p.in_line, tj, JT, n);
     __syncthreads();
     COL_FFT(false);
   }
@@ -166,10 +306,20 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
     __syncthreads();
     if (active) {
       const cpx<R>* __restrict__ in = p.in[comp];
-      for (int m = tj; m < P; m += JT) {
-        int i = m - p.M;
-        if (i < 0) i += n;
-        buf[i * bc + b] = in[ib + (long long)m * p.in_line];
+      for (int m0 = tj; m0 < P; m0 += 4 * JT) {
+        cpx<R> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (m0 + u * JT < P) v[u] = in[ib + (long long)(m0 + u * JT) * p.in_line];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int m = m0 + u * JT;
+          if (m < P) {
+            int i = m - p.M;
+            if (i < 0) i += n;
+            buf[i * bc + b] = v[u];
+          }
+        }
       }
     }
     __syncthreads();
@@ -199,7 +349,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
     const int a1 = n1 < 0 ? -n1 : n1;
     const R dlead = p.dec[0][n0] * ((p.d == 3) ? p.dec[1][a1] : R(1));
     const R ilead = p.deci[0][n0] * ((p.d == 3) ? p.deci[1][a1] : R(1));
-    for (int m = tj; m < P; m += JT) {
+    auto mode_body = [&](int m, R wp, R wm, R s0p, R s0m) {
       const int nl = m - p.M;
       const int al = nl < 0 ? -nl : nl;
       const R dec = dlead * p.dec[p.d - 1][al];
@@ -232,8 +382,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
         // G: dL/dS symmetrised over the pair (n, -n)
         R G;
         if (MODE == COL_FUSED) {
-          const R wp = p.Wp[hidx], wm = p.Wm[hidx];
-          const R rp = S - p.S0p[hidx], rm = S - p.S0m[hidx];
+          const R rp = S - s0p, rm = S - s0m;
           // loss over the full set: n and -n both when n_0 > 0; the n_0 = 0 plane
           // lists both members of every pair itself
           lsum += (double)wp * (double)rp * (double)rp;
@@ -247,6 +396,19 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
         // C0 = 2 G rho / N, divided by psihat_i and scaled by h^d
         const R f = R(2) * G * p.invN * ilead * p.deci[p.d - 1][al];
         qbuf[m * bc + b] = cscale(rho, f);
+      }
+    };
+    if (MODE == COL_FUSED && pre) {
+#pragma unroll
+      for (int u = 0; u < kModePre; ++u) {
+        const int m = tj + u * JT;
+        if (m < P) mode_body(m, pwp[u], pwm[u], psp[u], psm[u]);
+      }
+    } else {
+      for (int m = tj; m < P; m += JT) {
+        const long long h = c + (long long)p.ncols * m;
+        if (MODE == COL_FUSED) mode_body(m, p.Wp[h], p.Wm[h], p.S0p[h], p.S0m[h]);
+        else mode_body(m, R(0), R(0), R(0), R(0));
       }
     }
   }
@@ -377,7 +539,10 @@ static int pick_maxb(int need) {
 template <class R>
 size_t rows_lds_bytes(const RowParams<R>& p, const AxisFft<R>& ax) {
   const int H = ax.F.n;
-  return ((p.tw_lds ? (size_t)H : 0) + (size_t)p.lines_per_block * (H + 1)) * sizeof(cpx<R>);
+  size_t b = ((p.tw_lds ? (size_t)H : 0) + (size_t)p.lines_per_block * (H + 1)) * sizeof(cpx<R>);
+  if (p.fold.tiles)  // first-axis cover lists (offsets padded to an even count)
+    b += (size_t)((2 * H + 2) & ~1) * sizeof(int) + (size_t)p.fold.nent0 * sizeof(int2);
+  return b;
 }
 template <class R>
 size_t cols_lds_bytes(int mode, const ColParams<R>& p, const AxisFft<R>& ax) {

@@ -122,11 +122,21 @@ __device__ void lds_fft(cpx<R>* buf, const FftFactors& F, const cpx<R>* __restri
   }
 }
 
-// Copy a twiddle table into LDS (all threads; followed by a barrier in caller).
+// Copy a twiddle table into LDS (all threads; followed by a barrier in caller),
+// four loads in flight per thread before the first store.
 template <class R>
 __device__ __forceinline__ void load_twiddles(cpx<R>* dst, const cpx<R>* __restrict__ src,
                                               int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  const int step = (int)blockDim.x;
+  for (int i = threadIdx.x; i < n; i += 4 * step) {
+    cpx<R> v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * step < n) v[u] = src[i + u * step];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * step < n) dst[i + u * step] = v[u];
+  }
 }
 
 }  // namespace fresco

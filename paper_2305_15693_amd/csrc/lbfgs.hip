@@ -175,12 +175,21 @@ __global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part,
   if (!dir) return;
   const int cnt = 4 * m + 1;
   if (step != LB_RESTART) {
-    // value c is reduced by wave c mod (waves): each lane sums a strided subset of
-    // the block partials, then the wave combines its lanes (fixed order)
+    // value c is reduced by wave c mod (waves): lane l loads the partials
+    // l, l + 64, ... (nb <= 1024: at most 16, all loads issued before the first
+    // add), sums them in that order, then the wave combines its lanes
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = wave; c < cnt; c += (int)(blockDim.x >> 6)) {
+      const double* pc = part + (long long)c * nb;
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int b = lane + 64 * u;
+        v[u] = (b < nb) ? pc[b] : 0.0;
+      }
       double t = 0.0;
-      for (int b = lane; b < nb; b += 64) t += part[(long long)c * nb + b];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t += v[u];
       for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
       if (lane == 0) red[c] = t;
     }
@@ -393,7 +402,7 @@ void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o
     case 16: CALL(16); break;                                                  \
   }
   LB_SWITCH(LB_A)
-  lb_small_kernel<<<1, 256, 0, st>>>(S, o, v.part0, v.nb, v.n);
+  lb_small_kernel<<<1, 1024, 0, st>>>(S, o, v.part0, v.nb, v.n);
   LB_SWITCH(LB_B)
 #undef LB_SWITCH
 #undef LB_B

@@ -712,16 +712,29 @@ __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const int o0 = t[0] * g.T[0] - 1 + g.nf[0];
   const int o1 = t[1] * g.T[1] - 1 + g.nf[1];
   const int o2 = (D == 3) ? t[2] * g.T[2] - 1 + g.nf[2] : 0;
-  for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-    const int c0 = c % E0;
-    const int r = c / E0;
-    const int c1 = r % E1;
-    const int c2 = r / E1;
-    int x = o0 + c0, y = o1 + c1, z = o2 + c2;
-    while (x >= g.nf[0]) x -= g.nf[0];
-    while (y >= g.nf[1]) y -= g.nf[1];
-    while (z >= g.nf[2]) z -= g.nf[2];
-    sub[c] = v[((long long)z * g.nf[1] + y) * g.nf[0] + x];
+  // four loads in flight per thread before the LDS stores
+  for (int cb = threadIdx.x; cb < ncell; cb += 4 * blockDim.x) {
+    R val[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = cb + u * (int)blockDim.x;
+      if (c < ncell) {
+        const int c0 = c % E0;
+        const int r = c / E0;
+        const int c1 = r % E1;
+        const int c2 = r / E1;
+        int x = o0 + c0, y = o1 + c1, z = o2 + c2;
+        while (x >= g.nf[0]) x -= g.nf[0];
+        while (y >= g.nf[1]) y -= g.nf[1];
+        while (z >= g.nf[2]) z -= g.nf[2];
+        val[u] = v[((long long)z * g.nf[1] + y) * g.nf[0] + x];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = cb + u * (int)blockDim.x;
+      if (c < ncell) sub[c] = val[u];
+    }
   }
   __syncthreads();
   const R beta = (R)g.beta_i;
