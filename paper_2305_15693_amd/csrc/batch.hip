@@ -745,10 +745,8 @@ int batch_lbfgs_setup(fresco_batch_ctx* c, int m) {
   if ((st = balloc(c, &v.gt, n))) return st;
   if ((st = balloc(c, &v.S, (size_t)n * m))) return st;
   if ((st = balloc(c, &v.Y, (size_t)n * m))) return st;
-  long long nb = (n + 2047) / 2048;
-  if (nb > 1024) nb = 1024;
-  if (nb < 1) nb = 1;
-  v.nb = (int)nb;
+  const int nb = lbfgs_blocks(n);
+  v.nb = nb;
   v.n = n;
   v.m = m;
   if ((st = balloc(c, &v.part0, (4 * (size_t)kLbfgsMaxM + 1) * nb))) return st;

@@ -813,12 +813,8 @@ int lbfgs_setup(fresco_ctx* c, int m) {
   if ((st = dalloc_t(c, &v.gt, n))) return st;
   if ((st = dalloc_t(c, &v.S, (size_t)n * m))) return st;
   if ((st = dalloc_t(c, &v.Y, (size_t)n * m))) return st;
-  // vector passes: enough blocks to fill the chip, few enough that the one-block
-  // reduction of their partials stays cheap
-  long long nb = (n + 2047) / 2048;
-  if (nb > 1024) nb = 1024;
-  if (nb < 1) nb = 1;
-  v.nb = (int)nb;
+  const int nb = lbfgs_blocks(n);
+  v.nb = nb;
   v.n = n;
   v.m = m;
   if ((st = dalloc_t(c, &v.part0, (4 * (size_t)kLbfgsMaxM + 1) * nb))) return st;

@@ -6,6 +6,16 @@
 namespace fresco {
 
 constexpr int kLbfgsMaxM = 16;
+// vector passes: blocks of kLbfgsThreads, enough to fill the chip, at most
+// kLbfgsMaxBlocks so that the one-block reduction of their partials stays cheap
+constexpr int kLbfgsThreads = 256;
+constexpr int kLbfgsMaxBlocks = 1024;
+inline int lbfgs_blocks(long long n) {
+  long long nb = (n + 8LL * kLbfgsThreads - 1) / (8LL * kLbfgsThreads);
+  if (nb > kLbfgsMaxBlocks) nb = kLbfgsMaxBlocks;
+  if (nb < 1) nb = 1;
+  return (int)nb;
+}
 
 // Lives in device memory; the host reads it back between batches of replays.
 struct LbfgsState {

@@ -14,16 +14,21 @@
 // S^T Y, D its diagonal and gamma = s.y / y.y of the newest pair.  The m x m
 // products S^T Y and Y^T Y are kept in the state and updated with the new pair.
 //
-// Per replay, after the loss/gradient evaluation at the trial point xt:
-//   decide   Armijo test f(xt) <= f(x) + c1 alpha g.p  -> ACCEPT or REJECT
-//            (REJECT: alpha *= shrink; after max_backtracks rejections the
-//            history is dropped and the search restarts along -g; a second
-//            failure sets the failure flag);
-//   pass A   s = alpha p, y = g(xt) - g(x) into the ring, x = xt, g = g(xt), and
-//            the new dot products s_j.y, y_j.y, s_j.g, y_j.g, g.g;
-//   small    store the pair when y.s > 0, solve for u, t (FP64, one thread);
-//   pass B   p = -(gamma g + S u - gamma Y t), max |p|;
+// Per replay, after the loss/gradient evaluation at the trial point xt, four
+// kernels:
+//   pass A   decision: Armijo test f(xt) <= f(x) + c1 alpha g.p -> ACCEPT or
+//            REJECT (REJECT: alpha *= shrink; after max_backtracks rejections
+//            the history is dropped and the search restarts along -g; a second
+//            failure sets the failure flag), computed by every block from the
+//            state; on ACCEPT s = alpha p, y = g(xt) - g(x) into the ring,
+//            x = xt, g = g(xt), and the new dot products s_j.y, y_j.y, s_j.g,
+//            y_j.g, g.g as block partials;
+//   small    one block: applies the decision, reduces the partials, stores the
+//            pair when y.s > 0 and solves for u, t (FP64, one thread);
+//   pass B   p = -(gamma g + S u - gamma Y t), max |p| per block;
 //   pass C   alpha = min(1, max_step / max|p|), xt = x + alpha p.
+// (Cross-block steps stay at kernel boundaries: a device-scope fence per block
+// writes back the L2 of its XCD and cost more than the launches it saved.)
 // Vectors are in the working precision; every dot product is accumulated in FP64
 // with a fixed reduction order.
 #include <cmath>
@@ -35,7 +40,7 @@ namespace fresco {
 
 enum { LB_IDLE = 0, LB_ACCEPT = 1, LB_REJECT = 2, LB_RESTART = 3, LB_INIT = 4 };
 
-constexpr int kThreads = 256;
+constexpr int kThreads = kLbfgsThreads;
 constexpr int kWaves = kThreads / 64;
 
 #define GRID_LOOP(i, n) \
@@ -64,144 +69,139 @@ __device__ __forceinline__ void block_partials(double* v, int cnt, double* part,
 }
 
 // ---------------------------------------------------------------- decide
-__global__ void lb_decide_kernel(LbfgsState* S, LbfgsOpts o) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  S->nevals += 1;
-  if (S->mode == LB_INIT) {
-    S->f_cur = S->f_trial;  // first evaluation of a call: take the point as current
-    S->step = LB_INIT;
-    S->nbt = 0;
-    return;
-  }
-  if (S->fail || S->iter >= S->target || S->converged) {
-    S->step = LB_IDLE;
-    return;
-  }
+// Decision on the evaluation just finished, as a function of the state (every
+// block of pass A computes it; the small step then applies it).
+__device__ __forceinline__ int lb_decided_step(const LbfgsState* S, const LbfgsOpts& o) {
+  if (S->mode == LB_INIT) return LB_INIT;  // first evaluation of a call
+  if (S->fail || S->iter >= S->target || S->converged) return LB_IDLE;
   const double f = S->f_trial;
-  if (isfinite(f) && f <= S->f_cur + o.c1 * S->alpha * S->gtp) {
-    S->step = LB_ACCEPT;
-    S->f_cur = f;
+  if (isfinite(f) && f <= S->f_cur + o.c1 * S->alpha * S->gtp) return LB_ACCEPT;
+  if (S->nbt + 1 > o.max_backtracks) return (S->k > 0 || !S->restarted) ? LB_RESTART : LB_IDLE;
+  return LB_REJECT;
+}
+__device__ void lb_decide(LbfgsState* S, const LbfgsOpts& o) {
+  const int step = lb_decided_step(S, o);
+  S->nevals += 1;
+  if (step == LB_INIT) {
+    S->f_cur = S->f_trial;  // take the point as current
+    S->nbt = 0;
+  } else if (step == LB_ACCEPT) {
+    S->f_cur = S->f_trial;
     S->iter += 1;
     S->nbt = 0;
-    return;
+  } else if (step == LB_RESTART) {
+    S->k = 0;  // drop the history, restart along the steepest descent direction
+    S->restarted = 1;
+    S->resets += 1;
+    S->nbt = 0;
+  } else if (step == LB_REJECT) {
+    S->nbt += 1;
+    S->alpha *= o.shrink;
+  } else if (!(S->fail || S->iter >= S->target || S->converged)) {
+    S->nbt += 1;  // second line-search failure
+    S->fail = 1;
   }
-  S->nbt += 1;
-  if (S->nbt > o.max_backtracks) {
-    if (S->k > 0 || !S->restarted) {
-      S->k = 0;  // drop the history, restart along the steepest descent direction
-      S->restarted = 1;
-      S->resets += 1;
-      S->nbt = 0;
-      S->step = LB_RESTART;
-    } else {
-      S->fail = 1;
-      S->step = LB_IDLE;
-    }
-    return;
-  }
-  S->alpha *= o.shrink;
-  S->step = LB_REJECT;
+  S->step = step;
 }
 
 // ---------------------------------------------------------------- pass A
-// Partial slots: [0, m) s_j.y_new, [m, 2m) y_j.y_new, [2m, 3m) s_j.g, [3m, 4m) y_j.g,
-// 4m g.g (slot j indexes the ring; the new pair's own entries sit at its slot).
-// MM = history length m (compile time, so the accumulators stay in registers)
-template <class R, int MM>
-__global__ void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S) {
-  __shared__ double sh[(4 * MM + 1) * kWaves];
-  const int step = S->step;
-  if (step != LB_ACCEPT && step != LB_INIT) return;
-  const bool acc = (step == LB_ACCEPT);
-  const int ns = (S->head + 1) % MM;  // slot of the new pair
-  const R alpha = (R)S->alpha;
-  // slots holding pairs after this step (the new slot included when accepting)
-  unsigned live = 0;
-  {
-    const int k = S->k;
-    for (int t = 0; t < k; ++t) live |= 1u << ((S->head - t + MM) % MM);
-    if (acc) live |= 1u << ns;
-  }
-  double acc_v[4 * MM + 1];
-#pragma unroll
-  for (int c = 0; c < 4 * MM + 1; ++c) acc_v[c] = 0.0;
-  R* Sn = v.S + (long long)ns * v.n;
-  R* Yn = v.Y + (long long)ns * v.n;
-  GRID_LOOP(i, v.n) {
-    const R gn = v.gt[i];
-    R yy = R(0);
-    if (acc) {
-      const R sy = alpha * v.p[i];
-      yy = gn - v.g[i];
-      Sn[i] = sy;
-      Yn[i] = yy;
-      v.x[i] = v.xt[i];
-    }
-    v.g[i] = gn;
-#pragma unroll
-    for (int j = 0; j < MM; ++j) {
-      if ((live >> j) & 1u) {
-        const R sj = v.S[(long long)j * v.n + i];
-        const R yj = v.Y[(long long)j * v.n + i];
-        if (acc) {
-          acc_v[j] += (double)sj * (double)yy;
-          acc_v[MM + j] += (double)yj * (double)yy;
-        }
-        acc_v[2 * MM + j] += (double)sj * (double)gn;
-        acc_v[3 * MM + j] += (double)yj * (double)gn;
-      }
-    }
-    acc_v[4 * MM] += (double)gn * (double)gn;
-  }
-  block_partials<4 * MM + 1>(acc_v, 4 * MM + 1, v.part0, v.nb, sh);
-}
-
-// ---------------------------------------------------------------- small
 __device__ __forceinline__ void lb_small_solve(LbfgsState* S, const LbfgsOpts& o,
                                                const double* red, int step, long long n);
 
-// One block: reduce the partials, update the pair products, solve for the
-// direction coefficients.
+// One block after pass A: apply the decision, reduce the partials, update the
+// pair products and solve for the direction coefficients.  The serial solve runs
+// on an LDS copy of the state (dependent global loads would dominate otherwise).
 __global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part, int nb,
                                 long long n) {
   __shared__ double red[4 * kLbfgsMaxM + 1];
-  // the serial solves run on an LDS copy of the state (dependent global loads
-  // would dominate otherwise); it is written back at the end
   __shared__ LbfgsState sh;
   static_assert(sizeof(LbfgsState) % 4 == 0, "state copied as 32-bit words");
+  constexpr int kWords = (int)(sizeof(LbfgsState) / 4);
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+    reinterpret_cast<uint32_t*>(&sh)[i] = reinterpret_cast<const uint32_t*>(Sg)[i];
+  __syncthreads();
+  if (threadIdx.x == 0) lb_decide(&sh, o);
+  __syncthreads();
+  const int step = sh.step;
   const int m = o.m;
-  const int step = Sg->step;
-  const bool dir = (step == LB_ACCEPT || step == LB_INIT || step == LB_RESTART);
-  if (!dir) return;
-  const int cnt = 4 * m + 1;
-  if (step != LB_RESTART) {
-    // value c is reduced by wave c mod (waves): lane l loads the partials
-    // l, l + 64, ... (nb <= 1024: at most 16, all loads issued before the first
-    // add), sums them in that order, then the wave combines its lanes
+  if (step == LB_ACCEPT || step == LB_INIT) {
+    // value c is reduced by wave c mod (waves): lane l sums the partials l,
+    // l + 64, ... (nb <= 1024: at most 16, all loads issued before the first add)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = wave; c < cnt; c += (int)(blockDim.x >> 6)) {
+    for (int c = wave; c < 4 * m + 1; c += (int)(blockDim.x >> 6)) {
       const double* pc = part + (long long)c * nb;
-      double v[16];
+      double v[kLbfgsMaxBlocks / 64];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
+      for (int u = 0; u < kLbfgsMaxBlocks / 64; ++u) {
         const int b = lane + 64 * u;
         v[u] = (b < nb) ? pc[b] : 0.0;
       }
       double t = 0.0;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) t += v[u];
+      for (int u = 0; u < kLbfgsMaxBlocks / 64; ++u) t += v[u];
       for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
       if (lane == 0) red[c] = t;
     }
   }
-  constexpr int kWords = (int)(sizeof(LbfgsState) / 4);
-  for (int i = threadIdx.x; i < kWords; i += blockDim.x)
-    reinterpret_cast<uint32_t*>(&sh)[i] = reinterpret_cast<const uint32_t*>(Sg)[i];
   __syncthreads();
-  if (threadIdx.x == 0) lb_small_solve(&sh, o, red, step, n);
+  if (threadIdx.x == 0 && (step == LB_ACCEPT || step == LB_INIT || step == LB_RESTART))
+    lb_small_solve(&sh, o, red, step, n);
   __syncthreads();
   for (int i = threadIdx.x; i < kWords; i += blockDim.x)
     reinterpret_cast<uint32_t*>(Sg)[i] = reinterpret_cast<const uint32_t*>(&sh)[i];
+}
+
+// Partial slots: [0, m) s_j.y_new, [m, 2m) y_j.y_new, [2m, 3m) s_j.g, [3m, 4m) y_j.g,
+// 4m g.g (slot j indexes the ring; the new pair's own entries sit at its slot).
+// MM = history length m (compile time, so the accumulators stay in registers)
+template <class R, int MM>
+__global__ void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
+  __shared__ double sh[(4 * MM + 1) * kWaves];
+  const int step = lb_decided_step(S, o);
+  if (step == LB_ACCEPT || step == LB_INIT) {
+    const bool acc = (step == LB_ACCEPT);
+    const int ns = (S->head + 1) % MM;  // slot of the new pair
+    const R alpha = (R)S->alpha;
+    // slots holding pairs after this step (the new slot included when accepting)
+    unsigned live = 0;
+    {
+      const int k = S->k;
+      for (int t = 0; t < k; ++t) live |= 1u << ((S->head - t + MM) % MM);
+      if (acc) live |= 1u << ns;
+    }
+    double acc_v[4 * MM + 1];
+#pragma unroll
+    for (int c = 0; c < 4 * MM + 1; ++c) acc_v[c] = 0.0;
+    R* Sn = v.S + (long long)ns * v.n;
+    R* Yn = v.Y + (long long)ns * v.n;
+    GRID_LOOP(i, v.n) {
+      const R gn = v.gt[i];
+      R yy = R(0);
+      if (acc) {
+        const R sy = alpha * v.p[i];
+        yy = gn - v.g[i];
+        Sn[i] = sy;
+        Yn[i] = yy;
+        v.x[i] = v.xt[i];
+      }
+      v.g[i] = gn;
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        if ((live >> j) & 1u) {
+          const R sj = v.S[(long long)j * v.n + i];
+          const R yj = v.Y[(long long)j * v.n + i];
+          if (acc) {
+            acc_v[j] += (double)sj * (double)yy;
+            acc_v[MM + j] += (double)yj * (double)yy;
+          }
+          acc_v[2 * MM + j] += (double)sj * (double)gn;
+          acc_v[3 * MM + j] += (double)yj * (double)gn;
+        }
+      }
+      acc_v[4 * MM] += (double)gn * (double)gn;
+    }
+    block_partials<4 * MM + 1>(acc_v, 4 * MM + 1, v.part0, v.nb, sh);
+  }
 }
 
 // serial part of the small step (one thread, state in LDS)
@@ -344,7 +344,8 @@ __global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
 }
 
 // ---------------------------------------------------------------- pass C
-// step length of a new direction, then the trial point
+// step length of a new direction (every block reduces the pass B maxima), or
+// the one shrunk by the decision; then the trial point
 template <class R>
 __global__ void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
   __shared__ double sh[kWaves];
@@ -389,8 +390,7 @@ __global__ void lb_set_mode_kernel(LbfgsState* S, int mode, int target) {
 template <class R>
 void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
                          hipStream_t st) {
-  lb_decide_kernel<<<1, 64, 0, st>>>(S, o);
-#define LB_A(MM) lb_pass_a_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S)
+#define LB_A(MM) lb_pass_a_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, o)
 #define LB_B(MM) lb_pass_b_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S)
 #define LB_SWITCH(CALL)                                                        \
   switch (v.m) {                                                               \
