@@ -96,6 +96,8 @@ typedef struct fresco_plan_info {
   int32_t bin_ranges;   /* points sorted by tile in one level (0), or in two levels
                            through this many ranges of consecutive tiles (grids with
                            more than 16384 tiles), or -1: global atomic counts */
+  int32_t bin_levels;   /* two-level sorts: 2 when a coarse pass over groups of
+                           ranges runs first (very many ranges), else 1 */
 } fresco_plan_info;
 
 /* Create a context for one problem.  Chooses the fine grid, kernel width and

@@ -110,13 +110,25 @@ constexpr int kPolyDeg = 9;
 //   BIN_TILES   block-private LDS histograms over the tiles (tiles <= 16384);
 //   BIN_RANGES  two levels for larger grids: block-private histograms over
 //               ranges of G consecutive tiles (at most 8192 ranges) place the
-//               points by range (positions copied to tpos, caller index to
-//               tidx), then one workgroup per range sorts its points by tile
+//               points by range (positions copied to tpos), then one
+//               workgroup per range sorts its points by tile
 //               in LDS.  perm then maps a sorted record to its tpos index;
 //               interpolation writes through it into tpos and a gather pass
 //               restores the caller's order;
+//               With two levels (very many ranges), a first pass places the
+//               points by coarse range (runs of consecutive ranges) the same
+//               way, so that every chunk of the range pass meets few keys;
 //   BIN_ATOMIC  global atomic counts per tile (grids beyond both).
 enum BinMode { BIN_TILES = 0, BIN_RANGES = 1, BIN_ATOMIC = 2 };
+// one histogram-and-scatter pass over keys tile / G
+struct BinLevel {
+  int nblk;         // blocks of the histogram pass
+  long long chunk;  // points per histogram block (multiple of 256)
+  long long nkeys;  // histogram keys
+  long long G;      // tiles per key
+  FastDiv kdiv;     // division by G
+  int shift;        // kr = key | rank << shift
+};
 struct BinPlan {
   int mode;         // BinMode
   int nblk;         // blocks of the histogram pass
@@ -125,6 +137,8 @@ struct BinPlan {
   int G;            // tiles per range (BIN_RANGES), 1 otherwise
   FastDiv kdiv;     // division by G
   int shift;        // kr = key | rank << shift
+  int levels;       // BIN_RANGES: 1, or 2 with the coarse pass `coarse` first
+  BinLevel coarse;
 };
 struct BinBuffers {
   uint32_t* kr = nullptr;     // histogram passes: key | rank << shift; atomic: rank
@@ -134,7 +148,16 @@ struct BinBuffers {
   long long* start = nullptr; // tile starts (nbins + 1)
   long long* kstart = nullptr;  // BIN_RANGES: range starts (nkeys + 1)
   void* tpos = nullptr;       // BIN_RANGES: positions in range order [N][d]
-  int* tidx = nullptr;        // BIN_RANGES: range order -> caller index
+  int* tidx = nullptr;        // BIN_RANGES: range order -> caller index (built
+                              // only when an L-BFGS call fixes its internal order)
+  // BIN_RANGES with two levels: the coarse pass (positions in coarse order,
+  // reused for the gradient in coarse order)
+  uint32_t* kr0 = nullptr;
+  uint32_t* H0 = nullptr;
+  uint32_t* count0 = nullptr;
+  long long* kstart0 = nullptr;
+  void* tpos0 = nullptr;
+  int* tidx0 = nullptr;
   void* rec = nullptr;        // Rec<R>[N], sorted
   int* perm = nullptr;        // sorted position -> caller index (tpos index for BIN_RANGES)
   int* flag = nullptr;        // bit 0: a position is not finite

@@ -268,19 +268,42 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
     else lds_fft<R, MAXB, INV>(buf, F, twg, active, b, 1, bc, tj, JT);           \
   } while (0)
 
-  // FUSED: weights and targets of this thread's modes m = tj + u JT
+  // Mode stage (FUSED, SF, BWD; this is the last axis): column c holds the
+  // half-spectrum modes (n_0, n_1[, n_2]) with n_last = m - M, where
+  // c = n0 + H0 * (n1 + M1) in 3D, c = n0 in 2D.  Its column factors, and in
+  // FUSED the weights, targets and kernel factors of this thread's modes
+  // m = tj + u JT, are loaded before the forward transform.
+  constexpr bool kModes = MODE == COL_FUSED || MODE == COL_SF || MODE == COL_BWD;
+  int n0 = 0, n1 = 0;
+  R dlead = R(0), ilead = R(0);
+  if (kModes && active) {
+    if (p.d == 2) {
+      n0 = (int)c;
+    } else {
+      uint32_t q = fdiv((uint32_t)c, p.h0div);
+      n0 = (int)(c - (long long)q * p.h0div.d);
+      n1 = (int)q - p.M1;
+    }
+    const int a1 = n1 < 0 ? -n1 : n1;
+    dlead = p.dec[0][n0] * ((p.d == 3) ? p.dec[1][a1] : R(1));
+    ilead = p.deci[0][n0] * ((p.d == 3) ? p.deci[1][a1] : R(1));
+  }
   const bool pre = (MODE == COL_FUSED) && P <= kModePre * JT;
-  R pwp[kModePre], pwm[kModePre], psp[kModePre], psm[kModePre];
+  R pwp[kModePre], pwm[kModePre], psp[kModePre], psm[kModePre], pdc[kModePre], pdi[kModePre];
   if (MODE == COL_FUSED && pre) {
 #pragma unroll
     for (int u = 0; u < kModePre; ++u) {
       const int m = tj + u * JT;
       const long long h = c + (long long)p.ncols * m;
       const bool ok = active && m < P;
+      const int nl = m - p.M;
+      const int al = ok ? (nl < 0 ? -nl : nl) : 0;
       pwp[u] = ok ? p.Wp[h] : R(0);
       pwm[u] = ok ? p.Wm[h] : R(0);
       psp[u] = ok ? p.S0p[h] : R(0);
       psm[u] = ok ? p.S0m[h] : R(0);
+      pdc[u] = ok ? p.dec[p.d - 1][al] : R(0);
+      pdi[u] = ok ? p.deci[p.d - 1][al] : R(0);
     }
   }
   if (MODE == COL_FWD || MODE == COL_FUSED || MODE == COL_SF) {
@@ -331,28 +354,13 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
     return;
   }
 
-  // ---- mode stage (FUSED, SF, BWD): this is the last axis; column c holds the
-  // half-spectrum modes (n_0, n_1[, n_2]) with n_last = m - M.
-  // Column -> leading mode indices: c = n0 + H0 * (n1 + M1) in 3D, c = n0 in 2D.
-  int n0 = 0, n1 = 0;
-  if (active) {
-    if (p.d == 2) {
-      n0 = (int)c;
-    } else {
-      uint32_t q = fdiv((uint32_t)c, p.h0div);
-      n0 = (int)(c - (long long)q * p.h0div.d);
-      n1 = (int)q - p.M1;
-    }
-  }
+  // ---- mode stage
   double lsum = 0.0;
   if (active) {
-    const int a1 = n1 < 0 ? -n1 : n1;
-    const R dlead = p.dec[0][n0] * ((p.d == 3) ? p.dec[1][a1] : R(1));
-    const R ilead = p.deci[0][n0] * ((p.d == 3) ? p.deci[1][a1] : R(1));
-    auto mode_body = [&](int m, R wp, R wm, R s0p, R s0m) {
+    // dk, dik: kernel factors of the last axis at |n_last|
+    auto mode_body = [&](int m, R wp, R wm, R s0p, R s0m, R dk, R dik) {
       const int nl = m - p.M;
-      const int al = nl < 0 ? -nl : nl;
-      const R dec = dlead * p.dec[p.d - 1][al];
+      const R dec = dlead * dk;
       const long long hidx = c + (long long)p.ncols * m;  // half-spectrum index
       cpx<R> rho;
       if (MODE == COL_BWD) {
@@ -394,7 +402,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
         }
         // type-2 input of the field whose derivative is the gradient:
         // C0 = 2 G rho / N, divided by psihat_i and scaled by h^d
-        const R f = R(2) * G * p.invN * ilead * p.deci[p.d - 1][al];
+        const R f = R(2) * G * p.invN * ilead * dik;
         qbuf[m * bc + b] = cscale(rho, f);
       }
     };
@@ -402,13 +410,16 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
 #pragma unroll
       for (int u = 0; u < kModePre; ++u) {
         const int m = tj + u * JT;
-        if (m < P) mode_body(m, pwp[u], pwm[u], psp[u], psm[u]);
+        if (m < P) mode_body(m, pwp[u], pwm[u], psp[u], psm[u], pdc[u], pdi[u]);
       }
     } else {
       for (int m = tj; m < P; m += JT) {
         const long long h = c + (long long)p.ncols * m;
-        if (MODE == COL_FUSED) mode_body(m, p.Wp[h], p.Wm[h], p.S0p[h], p.S0m[h]);
-        else mode_body(m, R(0), R(0), R(0), R(0));
+        const int nl = m - p.M;
+        const int al = nl < 0 ? -nl : nl;
+        const R dk = p.dec[p.d - 1][al], dik = p.deci[p.d - 1][al];
+        if (MODE == COL_FUSED) mode_body(m, p.Wp[h], p.Wm[h], p.S0p[h], p.S0m[h], dk, dik);
+        else mode_body(m, R(0), R(0), R(0), R(0), dk, dik);
       }
     }
   }

@@ -48,6 +48,7 @@
 // derivative at the support edge).  One workgroup per tile stages its padded
 // field tile in LDS.
 #include <cmath>
+#include <type_traits>
 #include <utility>
 
 #include "common.h"
@@ -221,20 +222,41 @@ inline unsigned xcd_grid(int nblk, long long chunk) {
   return (unsigned)(8ll * ((nblk + 7) / 8) * (chunk / 256));
 }
 
-// First level: copy each point's position and index into its range's segment.
+// Range pass: copy each point's position into its range's segment (one store
+// per point: the writes are bound by their count, not their bytes).
 template <class R>
 __global__ void range_scatter_kernel(long long N, int d, const R* __restrict__ pos, uint32_t bpc,
                                      int nblk, int shift, const uint32_t* __restrict__ kr,
                                      const uint32_t* __restrict__ H,
-                                     const long long* __restrict__ kstart, R* __restrict__ tpos,
-                                     int* __restrict__ tidx) {
+                                     const long long* __restrict__ kstart, R* __restrict__ tpos) {
   uint32_t c;
   const long long q = xcd_point_block(blockIdx.x, bpc, &c);
   const long long i = q * 256 + threadIdx.x;
   if (c >= (uint32_t)nblk || i >= N) return;
   const long long dst = range_slot(kr[i], shift, c, nblk, H, kstart);
-  for (int a = 0; a < d; ++a) tpos[dst * d + a] = pos[i * d + a];
-  tidx[dst] = (int)i;
+  if (d == 2) {
+    using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+    V2 v;
+    v.x = pos[2 * i];
+    v.y = pos[2 * i + 1];
+    reinterpret_cast<V2*>(tpos)[dst] = v;
+  } else {
+    for (int a = 0; a < d; ++a) tpos[dst * d + a] = pos[i * d + a];
+  }
+}
+
+// tidx[slot of i] = sidx[i] (or i): range order -> caller index, built when an
+// L-BFGS call fixes its internal order
+__global__ void range_index_kernel(long long N, uint32_t bpc, int nblk, int shift,
+                                   const uint32_t* __restrict__ kr,
+                                   const uint32_t* __restrict__ H,
+                                   const long long* __restrict__ kstart,
+                                   const int* __restrict__ sidx, int* __restrict__ tidx) {
+  uint32_t c;
+  const long long q = xcd_point_block(blockIdx.x, bpc, &c);
+  const long long i = q * 256 + threadIdx.x;
+  if (c >= (uint32_t)nblk || i >= N) return;
+  tidx[range_slot(kr[i], shift, c, nblk, H, kstart)] = sidx ? sidx[i] : (int)i;
 }
 
 // Second level: one workgroup per range of G tiles sorts its segment
@@ -251,8 +273,15 @@ __device__ __forceinline__ int range_load(const R* __restrict__ tpos, long long 
   for (int u = 0; u < kRangeU; ++u) {
     const long long j = j0 + (long long)u * blockDim.x;
     if (j < b) {
+      if constexpr (D == 2) {
+        using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+        const V2 v = reinterpret_cast<const V2*>(tpos)[j];
+        x[u][0] = v.x;
+        x[u][1] = v.y;
+      } else {
 #pragma unroll
-      for (int a = 0; a < D; ++a) x[u][a] = tpos[j * D + a];
+        for (int a = 0; a < D; ++a) x[u][a] = tpos[j * D + a];
+      }
       n = u + 1;
     }
   }
@@ -357,7 +386,18 @@ __global__ void range_gather_kernel(long long N, int d, uint32_t bpc, int nblk, 
   const long long i = q * 256 + threadIdx.x;
   if (c >= (uint32_t)nblk || i >= N) return;
   const long long src = range_slot(kr[i], shift, c, nblk, H, kstart);
-  for (int a = 0; a < d; ++a) grad[i * d + a] = gseg[src * d + a];
+  if (d == 2) {
+    using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+    const V2 v = reinterpret_cast<const V2*>(gseg)[src];
+    if (((uintptr_t)grad & (sizeof(V2) - 1)) == 0) {
+      reinterpret_cast<V2*>(grad)[i] = v;
+    } else {
+      grad[2 * i] = v.x;
+      grad[2 * i + 1] = v.y;
+    }
+  } else {
+    for (int a = 0; a < d; ++a) grad[i * d + a] = gseg[src * d + a];
+  }
 }
 
 // out[j] = tidx[perm[j]]
@@ -428,18 +468,57 @@ __global__ void scan_bins_kernel(const uint32_t* __restrict__ count, long long n
   if (threadIdx.x == 0) start[nb] = carry;
 }
 
+// BIN_RANGES after the range histogram: scatter into range order, then sort
+// every range by tile
+template <class R>
+void range_finish(const Geom& g, const BinPlan& bp, const R* src, BinBuffers& b,
+                  hipStream_t st) {
+  const uint32_t bpc = (uint32_t)(bp.chunk / 256);
+  range_scatter_kernel<R><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
+      g.N, g.d, src, bpc, bp.nblk, bp.shift, b.kr, b.H, b.kstart, (R*)b.tpos);
+  const size_t lds2 = (size_t)bp.G * sizeof(uint32_t);
+  if (g.d == 2)
+    range_sort_kernel<R, 2><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
+        g, bp.G, (const R*)b.tpos, b.kstart, b.start, (Rec<R>*)b.rec, b.perm, b.flag);
+  else
+    range_sort_kernel<R, 3><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
+        g, bp.G, (const R*)b.tpos, b.kstart, b.start, (Rec<R>*)b.rec, b.perm, b.flag);
+}
+
+// BIN_RANGES, two levels: the coarse pass into tpos0 / tidx0
+template <class R>
+void range_coarse(const Geom& g, const BinLevel& c, const R* pos, BinBuffers& b,
+                  hipStream_t st) {
+  bin_hist_kernel<R><<<c.nblk, 1024, (size_t)c.nkeys * sizeof(uint32_t), st>>>(
+      g, pos, c.chunk, c.nblk, (int)c.nkeys, c.kdiv, c.shift, b.kr0, b.H0, b.flag);
+  bin_rowscan_kernel<<<(unsigned)((c.nkeys + 3) / 4), 256, 0, st>>>(b.H0, c.nblk, c.nkeys,
+                                                                     b.count0);
+  scan_bins_kernel<<<1, 1024, 0, st>>>(b.count0, c.nkeys, b.kstart0);
+  range_scatter_kernel<R><<<xcd_grid(c.nblk, c.chunk), 256, 0, st>>>(
+      g.N, g.d, pos, (uint32_t)(c.chunk / 256), c.nblk, c.shift, b.kr0, b.H0, b.kstart0,
+      (R*)b.tpos0);
+}
+
 void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, BinBuffers& b,
                 hipStream_t st) {
   const long long nblocks = (g.N + 255) / 256;
   if (bp.mode == BIN_TILES || bp.mode == BIN_RANGES) {
+    // source of the (range or tile) histogram pass: the caller's positions, or
+    // the coarse pass's output
+    const void* src = pos;
+    if (bp.mode == BIN_RANGES && bp.levels == 2) {
+      if (f64) range_coarse<double>(g, bp.coarse, (const double*)pos, b, st);
+      else range_coarse<float>(g, bp.coarse, (const float*)pos, b, st);
+      src = b.tpos0;
+    }
     const size_t lds = (size_t)bp.nkeys * sizeof(uint32_t);
     const int nk = (int)bp.nkeys;
     if (f64)
-      bin_hist_kernel<double><<<bp.nblk, 1024, lds, st>>>(g, (const double*)pos, bp.chunk,
+      bin_hist_kernel<double><<<bp.nblk, 1024, lds, st>>>(g, (const double*)src, bp.chunk,
                                                          bp.nblk, nk, bp.kdiv, bp.shift, b.kr,
                                                          b.H, b.flag);
     else
-      bin_hist_kernel<float><<<bp.nblk, 1024, lds, st>>>(g, (const float*)pos, bp.chunk,
+      bin_hist_kernel<float><<<bp.nblk, 1024, lds, st>>>(g, (const float*)src, bp.chunk,
                                                         bp.nblk, nk, bp.kdiv, bp.shift, b.kr,
                                                         b.H, b.flag);
     bin_rowscan_kernel<<<(unsigned)((bp.nkeys + 3) / 4), 256, 0, st>>>(b.H, bp.nblk, bp.nkeys,
@@ -457,32 +536,8 @@ void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, Bin
             b.perm);
     } else {
       scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, bp.nkeys, b.kstart);
-      const size_t lds2 = (size_t)bp.G * sizeof(uint32_t);
-      if (f64) {
-        range_scatter_kernel<double><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
-            g.N, g.d, (const double*)pos, bpc, bp.nblk, bp.shift, b.kr, b.H, b.kstart,
-            (double*)b.tpos, b.tidx);
-        if (g.d == 2)
-          range_sort_kernel<double, 2><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
-              g, bp.G, (const double*)b.tpos, b.kstart, b.start, (Rec<double>*)b.rec, b.perm,
-              b.flag);
-        else
-          range_sort_kernel<double, 3><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
-              g, bp.G, (const double*)b.tpos, b.kstart, b.start, (Rec<double>*)b.rec, b.perm,
-              b.flag);
-      } else {
-        range_scatter_kernel<float><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
-            g.N, g.d, (const float*)pos, bpc, bp.nblk, bp.shift, b.kr, b.H, b.kstart,
-            (float*)b.tpos, b.tidx);
-        if (g.d == 2)
-          range_sort_kernel<float, 2><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
-              g, bp.G, (const float*)b.tpos, b.kstart, b.start, (Rec<float>*)b.rec, b.perm,
-              b.flag);
-        else
-          range_sort_kernel<float, 3><<<(unsigned)bp.nkeys, 512, lds2, st>>>(
-              g, bp.G, (const float*)b.tpos, b.kstart, b.start, (Rec<float>*)b.rec, b.perm,
-              b.flag);
-      }
+      if (f64) range_finish<double>(g, bp, (const double*)src, b, st);
+      else range_finish<float>(g, bp, (const float*)src, b, st);
     }
   } else {
     launch_fill<uint32_t>(b.count, g.nbins, 0u, st);
@@ -694,17 +749,33 @@ __global__ void fold_kernel(Geom g, FoldTables ft, const R* __restrict__ tiles,
 
 // ---------------------------------------------------------- interpolation
 // Field tile origin is one cell before the spreading tile (width w + 1), extent
-// T + w + 1 per axis (g.Ei).
+// T + w + 1 per axis (g.Ei).  In FP32 the LDS rows are padded to a multiple of
+// four floats (zeros) and a point reads each row of its footprint as kRowQ
+// aligned 16-byte words from the aligned cell at or below its first column; the
+// x weights are shifted by the alignment offset once per point (zeros outside
+// the footprint), so each row costs kRowQ LDS reads instead of w + 1 and the
+// sum over the row keeps its order (the extra terms add exact zeros).
+constexpr int interp_row_words(int wi) { return (wi + 3 + 3) / 4; }
+// the words of a row reach at most 4 ceil((wi + 3) / 4) - wi <= 6 cells past its
+// footprint
+constexpr int kInterpTail = 8;
+inline int interp_row_stride(const Geom& g, bool f32) {
+  return f32 ? (g.Ei[0] + 3) / 4 * 4 : g.Ei[0];
+}
+
 template <class R, int D, int W>
 __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, const int* __restrict__ perm,
                               const R* __restrict__ v, R* __restrict__ grad) {
   constexpr int WI = W + 1;
-  extern __shared__ unsigned long long smem_u64[];
-  R* sub = reinterpret_cast<R*>(smem_u64);
+  constexpr bool F32 = sizeof(R) == 4;
+  constexpr int NQ = interp_row_words(WI);
+  extern __shared__ float4 smem_f4[];
+  R* sub = reinterpret_cast<R*>(smem_f4);
   const long long bin = blockIdx.x;
   const int E0 = g.Ei[0], E1 = g.Ei[1], E2 = (D == 3) ? g.Ei[2] : 1;
-  const int ncell = E0 * E1 * E2;
+  const int E0s = F32 ? (E0 + 3) / 4 * 4 : E0;  // LDS row stride
+  const int ncell = E0s * E1 * E2;
   const long long s = start[bin], e = start[bin + 1];
   if (e == s) return;
   int t[3];
@@ -712,15 +783,17 @@ __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const int o0 = t[0] * g.T[0] - 1 + g.nf[0];
   const int o1 = t[1] * g.T[1] - 1 + g.nf[1];
   const int o2 = (D == 3) ? t[2] * g.T[2] - 1 + g.nf[2] : 0;
-  // four loads in flight per thread before the LDS stores
-  for (int cb = threadIdx.x; cb < ncell; cb += 4 * blockDim.x) {
+  // four loads in flight per thread before the LDS stores; row padding and the
+  // kInterpTail cells past the end (read by the last row's words) are zero
+  for (int cb = threadIdx.x; cb < ncell + kInterpTail; cb += 4 * blockDim.x) {
     R val[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int c = cb + u * (int)blockDim.x;
-      if (c < ncell) {
-        const int c0 = c % E0;
-        const int r = c / E0;
+      const int c0 = c % E0s;
+      val[u] = R(0);
+      if (c < ncell && c0 < E0) {
+        const int r = c / E0s;
         const int c1 = r % E1;
         const int c2 = r / E1;
         int x = o0 + c0, y = o1 + c1, z = o2 + c2;
@@ -733,7 +806,7 @@ __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int c = cb + u * (int)blockDim.x;
-      if (c < ncell) sub[c] = val[u];
+      if (c < ncell + kInterpTail) sub[c] = val[u];
     }
   }
   __syncthreads();
@@ -741,6 +814,8 @@ __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const R icb = (R)(1.0 / cosh(g.beta_i));
   R gs[3];
   for (int a = 0; a < 3; ++a) gs[a] = (a < D) ? (R)(-(double)g.nf[a] / g.L[a] * 2.0 / WI) : R(0);
+  // 2D rows stored as one pair when the output is aligned for it
+  const bool pair_store = ((uintptr_t)grad & (2 * sizeof(R) - 1)) == 0;
   for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
     const Rec<R> p = rec[j];
     R f0[WI], d0[WI], f1[WI], d1[WI], f2[WI], d2[WI];
@@ -758,19 +833,53 @@ __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
       else if (a == 1) interp_weights<R, WI>(ti, beta, icb, f1, d1);
       else interp_weights<R, WI>(ti, beta, icb, f2, d2);
     }
+    // FP32: x weights shifted by the alignment offset of the first column
+    const int xb = F32 ? (l[0] & ~3) : l[0];
+    R f0s[4 * NQ], d0s[4 * NQ];
+    if constexpr (F32) {
+      const int sh = l[0] & 3;
+#pragma unroll
+      for (int k = 0; k < 4 * NQ; ++k) {
+        R a = R(0), b = R(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (k - q >= 0 && k - q < WI && sh == q) {
+            a = f0[k - q];
+            b = d0[k - q];
+          }
+        f0s[k] = a;
+        d0s[k] = b;
+      }
+    }
     R gx = R(0), gy = R(0), gz = R(0);
     const int zmax = (D == 3) ? WI : 1;
     for (int dz = 0; dz < zmax; ++dz) {
       R sxy = R(0), sdxy = R(0), sxdy = R(0);
 #pragma unroll
       for (int dy = 0; dy < WI; ++dy) {
-        const R* row = sub + ((D == 3 ? (l[2] + dz) * E1 : 0) + (l[1] + dy)) * E0 + l[0];
+        const R* row = sub + ((D == 3 ? (l[2] + dz) * E1 : 0) + (l[1] + dy)) * E0s + xb;
         R sx = R(0), sdx = R(0);
+        if constexpr (F32) {
+          const float4* q4 = reinterpret_cast<const float4*>(row);
 #pragma unroll
-        for (int dx = 0; dx < WI; ++dx) {
-          const R vv = row[dx];
-          sx += vv * f0[dx];
-          sdx += vv * d0[dx];
+          for (int k4 = 0; k4 < NQ; ++k4) {
+            const float4 w4 = q4[k4];
+            sx += w4.x * f0s[4 * k4];
+            sdx += w4.x * d0s[4 * k4];
+            sx += w4.y * f0s[4 * k4 + 1];
+            sdx += w4.y * d0s[4 * k4 + 1];
+            sx += w4.z * f0s[4 * k4 + 2];
+            sdx += w4.z * d0s[4 * k4 + 2];
+            sx += w4.w * f0s[4 * k4 + 3];
+            sdx += w4.w * d0s[4 * k4 + 3];
+          }
+        } else {
+#pragma unroll
+          for (int dx = 0; dx < WI; ++dx) {
+            const R vv = row[dx];
+            sx += vv * f0[dx];
+            sdx += vv * d0[dx];
+          }
         }
         sxy += sx * f1[dy];
         sdxy += sdx * f1[dy];
@@ -786,9 +895,17 @@ __global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
       }
     }
     const long long o = (long long)perm[j] * D;
-    grad[o] = gx * gs[0];
-    grad[o + 1] = gy * gs[1];
-    if (D == 3) grad[o + 2] = gz * gs[2];
+    if (D == 2 && pair_store) {
+      using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
+      V2 w2;
+      w2.x = gx * gs[0];
+      w2.y = gy * gs[1];
+      reinterpret_cast<V2*>(grad)[perm[j]] = w2;
+    } else {
+      grad[o] = gx * gs[0];
+      grad[o + 1] = gy * gs[1];
+      if (D == 3) grad[o + 2] = gz * gs[2];
+    }
   }
 }
 
@@ -819,7 +936,10 @@ size_t spread_lds_bytes(const Geom& g) {
 }
 template <class R>
 size_t interp_lds_bytes(const Geom& g) {
-  return (size_t)g.Ei[0] * g.Ei[1] * (g.d == 3 ? g.Ei[2] : 1) * sizeof(R);
+  // rows padded in FP32, plus the cells past the end
+  return ((size_t)interp_row_stride(g, sizeof(R) == 4) * g.Ei[1] * (g.d == 3 ? g.Ei[2] : 1) +
+          kInterpTail) *
+         sizeof(R);
 }
 
 // one-time kernel attributes (dynamic LDS above the default limit)
@@ -896,18 +1016,40 @@ void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const 
   } while (0)
   FRESCO_W_SWITCH(g.w, IP)
 #undef IP
-  if (bp.mode == BIN_RANGES)
+  if (bp.mode == BIN_RANGES) {
+    // range order -> source order of the range pass (the caller's, or the
+    // coarse order, then the caller's)
+    R* mid = (bp.levels == 2) ? (R*)b.tpos0 : grad;
     range_gather_kernel<R><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
         g.N, g.d, (uint32_t)(bp.chunk / 256), bp.nblk, bp.shift, b.kr, b.H, b.kstart, out,
-        grad);
+        mid);
+    if (bp.levels == 2) {
+      const BinLevel& c = bp.coarse;
+      range_gather_kernel<R><<<xcd_grid(c.nblk, c.chunk), 256, 0, st>>>(
+          g.N, g.d, (uint32_t)(c.chunk / 256), c.nblk, c.shift, b.kr0, b.H0, b.kstart0, mid,
+          grad);
+    }
+  }
 }
 
 void launch_sorted_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, int* out,
                          hipStream_t st) {
-  if (bp.mode == BIN_RANGES)
+  if (bp.mode == BIN_RANGES) {
+    // range order -> caller index (through the coarse order with two levels),
+    // then sorted record -> caller index
+    const int* sidx = nullptr;
+    if (bp.levels == 2) {
+      const BinLevel& c = bp.coarse;
+      range_index_kernel<<<xcd_grid(c.nblk, c.chunk), 256, 0, st>>>(
+          g.N, (uint32_t)(c.chunk / 256), c.nblk, c.shift, b.kr0, b.H0, b.kstart0, nullptr,
+          b.tidx0);
+      sidx = b.tidx0;
+    }
+    range_index_kernel<<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
+        g.N, (uint32_t)(bp.chunk / 256), bp.nblk, bp.shift, b.kr, b.H, b.kstart, sidx, b.tidx);
     compose_index_kernel<<<(unsigned)((g.N + 255) / 256), 256, 0, st>>>(g.N, b.perm, b.tidx,
                                                                          out);
-  else
+  } else
     (void)hipMemcpyAsync(out, b.perm, sizeof(int) * g.N, hipMemcpyDeviceToDevice, st);
 }
 

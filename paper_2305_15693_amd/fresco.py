@@ -64,6 +64,7 @@ class PlanInfo(ctypes.Structure):
         ("device_bytes", ctypes.c_int64),
         ("col_split", ctypes.c_int32),
         ("bin_ranges", ctypes.c_int32),
+        ("bin_levels", ctypes.c_int32),
     ]
 
 
@@ -251,7 +252,8 @@ class Context:
                     kmax=list(info.kmax)[:d], width=info.width, beta=info.beta,
                     tile=list(info.tile)[:d], nbins=info.nbins,
                     n_constrained=info.n_constrained, device_bytes=info.device_bytes,
-                    col_split=info.col_split, bin_ranges=info.bin_ranges)
+                    col_split=info.col_split, bin_ranges=info.bin_ranges,
+                    bin_levels=info.bin_levels)
 
     def default_max_step(self) -> float:
         """0.1 of the mean interparticle spacing L / N^(1/d) (smallest side)."""

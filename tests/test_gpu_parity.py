@@ -243,26 +243,30 @@ def test_long_column_path(gpu, dtype, N, L, M, tol, bar):
     assert rel(gb, gbo) < bar
 
 
-def _range_ctx(gpu, ranges, d, N, L, M, w, s0, tol, dtype):
+def _range_ctx(gpu, ranges, levels, d, N, L, M, w, s0, tol, dtype):
     import os
-    if ranges:
-        os.environ["FRESCO_BIN_RANGES"] = str(ranges)
+    os.environ["FRESCO_BIN_RANGES"] = str(ranges)
+    os.environ["FRESCO_BIN_LEVELS"] = str(levels)
     try:
         return make_ctx(gpu, d, N, L, M, w, s0, tol, dtype)
     finally:
         os.environ.pop("FRESCO_BIN_RANGES", None)
+        os.environ.pop("FRESCO_BIN_LEVELS", None)
 
 
-@pytest.mark.parametrize("dtype,d,N,L,M,tol,ranges,bar",
-                         [("f64", 2, 1024, 32.0, 16, 1e-12, 2, 1e-11),
-                          ("f32", 2, 20000, 141.4, 40, 1e-6, 7, 1e-5),
-                          ("f32", 3, 4096, 16.0, 8, 1e-6, 5, 1e-5)])
-def test_range_binning_path(gpu, dtype, d, N, L, M, tol, ranges, bar):
-    # two-level binning (ranges of consecutive tiles, then tiles inside each
-    # range: the sort used for grids beyond 16384 tiles), forced at small sizes
-    # with a few ranges: oracle parity, bitwise equality with the one-level
-    # sort (fixed-point spreading makes the result independent of point order),
-    # and points outside the box and in one crowded cluster
+@pytest.mark.parametrize("dtype,d,N,L,M,tol,ranges,levels,bar",
+                         [("f64", 2, 1024, 32.0, 16, 1e-12, 2, 1, 1e-11),
+                          ("f32", 2, 20000, 141.4, 40, 1e-6, 7, 1, 1e-5),
+                          ("f32", 2, 20000, 141.4, 40, 1e-6, 7, 2, 1e-5),
+                          ("f64", 3, 4096, 16.0, 8, 1e-12, 5, 2, 1e-11),
+                          ("f32", 3, 4096, 16.0, 8, 1e-6, 5, 1, 1e-5)])
+def test_range_binning_path(gpu, dtype, d, N, L, M, tol, ranges, levels, bar):
+    # sorting by ranges of consecutive tiles, then tiles inside each range (the
+    # sort used for grids beyond 16384 tiles; with a coarse pass over groups of
+    # ranges first when there are very many), forced at small sizes with a few
+    # ranges: oracle parity, bitwise equality with the one-level sort
+    # (fixed-point spreading makes the result independent of point order), and
+    # points outside the box and in one crowded cluster
     import torch
     rdt = np.float32 if dtype == "f32" else np.float64
     pos = I.positions(N, d, L, rdt, seed=77)
@@ -273,10 +277,11 @@ def test_range_binning_path(gpu, dtype, d, N, L, M, tol, ranges, bar):
     tdt = torch.float32 if dtype == "f32" else torch.float64
     tpos = torch.from_numpy(pos).to(device=gpu, dtype=tdt)
     one = make_ctx(gpu, d, N, L, M, w, s0, tol, dtype)
-    two = _range_ctx(gpu, ranges, d, N, L, M, w, s0, tol, dtype)
+    two = _range_ctx(gpu, ranges, levels, d, N, L, M, w, s0, tol, dtype)
     assert one.plan_info()["bin_ranges"] == 0
     nr = two.plan_info()["bin_ranges"]
     assert 1 < nr <= ranges
+    assert two.plan_info()["bin_levels"] == levels
     res = {}
     for name, ctx in (("one", one), ("two", two)):
         S = ctx.structure_factor(tpos).cpu().numpy()
@@ -291,7 +296,7 @@ def test_range_binning_path(gpu, dtype, d, N, L, M, tol, ranges, bar):
     S, gb, loss, grad = res["two"]
     So, lo, go = oracle_case(pos, L, M, w, s0)
     gbo = O.sf_vjp(pos.astype(np.float64), L, O.mode_vectors(d, M), gS.reshape(-1))
-    print(f"range binning {dtype} {d}D ({nr} ranges): S {rel(S, So):.2e} "
+    print(f"range binning {dtype} {d}D ({nr} ranges, {levels} levels): S {rel(S, So):.2e} "
           f"loss {abs(loss - lo) / lo:.2e} grad {rel(grad, go):.2e} backward {rel(gb, gbo):.2e}",
           flush=True)
     assert rel(S, So) < bar
