@@ -89,3 +89,57 @@ def test_problem_validation_without_device():
     assert create(upsampfac=1.25) == F.EINVAL
     assert create(weight_mode=9) == F.EINVAL
     assert create(n=1 << 40) == F.ENOTSUP
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # every struct the binding passes through the ABI has the header's size and
+    # field offsets (compiled with the host C compiler; no device needed)
+    import shutil
+    import subprocess
+    from paper_2305_15693_amd import fresco as F
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    structs = {"fresco_problem": F.Problem, "fresco_plan_info": F.PlanInfo,
+               "fresco_pair_problem": F.PairProblem, "fresco_lbfgs_opts": F.LbfgsOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fresco.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", HEADER_DIR, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    seen = {}
+    for line in out.splitlines():
+        cname, field, value = line.split()
+        seen[(cname, field)] = int(value)
+    for cname, py in structs.items():
+        assert seen[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert seen[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_bench_algorithmic_bytes():
+    # the per-launch bytes the roofline divides by, for the 2D headline workload
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2305_15693_amd import inputs as I
+    cfg = I.WORKLOADS["2d_n1e6_stealthy300_f32"]
+    b = bench.stage_bytes(cfg, {"nf": [1250, 1250], "kmax": [300, 300]}, 4)
+    N, nf, s = 10**6, 1250, 4
+    assert b["spread"] == N * 2 * s + nf * nf * s
+    assert b["interp"] == nf * nf * s + 2 * N * 2 * s
+    assert b["fft_rows_fwd"] == nf * nf * s + nf * 301 * 8
