@@ -18,6 +18,12 @@ Prints one JSON line.  Besides the throughput it carries:
                 bounded sample (all modes for a subset of the points), scaled
                 to one full evaluation;
   stages_ms     average time of every stage of one evaluation;
+  rocfft        the library's transforms (torch.fft.rfftn / irfftn, rocFFT on
+                ROCm) timed on the same fine grid, as a comparison only, beside
+                the time of this path's own FFT chain (pruned, with the fold and
+                the mode stage inside);
+  copy_gbs      a plain 1 GiB device copy timed on this GPU (the achievable
+                streaming rate; the roofline also reports its fraction of it);
   secondary     the same measurements for the 3D workload (N = 1e7), plus the
                 torch.autograd evaluation of spectral loss + soft-core pair
                 term in one backward;
@@ -107,6 +113,52 @@ def measured_traffic(workload, stage):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
+def copy_rate(dev):
+    """GB/s of a plain 1 GiB device-to-device copy (bytes read + written)."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def rocfft_compare(nf, stages_ms, dev, reps=20):
+    """torch.fft.rfftn / irfftn (rocFFT) on a real grid of the fine-grid shape,
+    full and unpruned, against this path's FFT chain per evaluation."""
+    import torch
+    shape = tuple(reversed(nf))  # axis 0 fastest
+    x = torch.randn(shape, dtype=torch.float32, device=dev)
+    X = torch.fft.rfftn(x)
+    y = torch.fft.irfftn(X, s=shape)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        X = torch.fft.rfftn(x)
+    e[1].record()
+    for _ in range(reps):
+        y = torch.fft.irfftn(X, s=shape)
+    e[2].record()
+    torch.cuda.synchronize()
+    chain = [k for k in stages_ms if k.startswith("fft_") or k == "modes"]
+    del x, X, y
+    torch.cuda.empty_cache()
+    return {"grid": list(nf), "rfftn_ms": e[0].elapsed_time(e[1]) / reps,
+            "irfftn_ms": e[1].elapsed_time(e[2]) / reps,
+            "ours_fft_chain_ms": sum(stages_ms[k] for k in chain), "ours_stages": chain}
+
+
 def measure(name, steps, warmup, dev, lbfgs_steps):
     import numpy as np
     import torch
@@ -167,6 +219,7 @@ def measure(name, steps, warmup, dev, lbfgs_steps):
     achieved = sbytes[dominant] / (dom_ms * 1e-3) / 1e9
 
     res = dict(workload=name, cfg=cfg, info=info, stages_ms=stages_ms,
+               rocfft=rocfft_compare(info["nf"], stages_ms, dev),
                stage_gbs={k: sbytes[k] / (stages_ms[k] * 1e-3) / 1e9
                           for k in stages_ms if k in sbytes},
                plain_evals_per_s=steps / (ms_plain * 1e-3), plain_ms=ms_plain / steps,
@@ -415,7 +468,7 @@ def main():
                "lbfgs_iters": s["lbfgs_iters"], "lbfgs_evals": s["lbfgs_evals"],
                "lbfgs_ms": s["lbfgs_ms"], "plain_evals_per_s": s["plain_evals_per_s"],
                "plain_ms": s["plain_ms"], "roofline": s["roofline"],
-               "stages_ms": s["stages_ms"], "stage_gbs": s["stage_gbs"],
+               "stages_ms": s["stages_ms"], "stage_gbs": s["stage_gbs"], "rocfft": s["rocfft"],
                "nf": s["info"]["nf"], "width": s["info"]["width"]}
         if s["cfg"]["d"] == 3:
             ag = measure_autograd_pair(args.secondary, 5, dev)
@@ -435,6 +488,9 @@ def main():
         print(f"[bench] cpu baseline: {cpu['value']:.3g} evals/s", file=sys.stderr, flush=True)
     cfg = r["cfg"]
     info = r["info"]
+    copy_gbs = copy_rate(dev)
+    for rr in [r["roofline"]] + ([sec["roofline"]] if sec else []):
+        rr["frac_of_copy"] = rr["achieved"] / copy_gbs
     out = {
         "metric": METRIC,
         "value": r["plain_evals_per_s"] if args.plain else r["lbfgs_evals_per_s"],
@@ -460,6 +516,8 @@ def main():
         "cpu_baseline": cpu,
         "stages_ms": r["stages_ms"],
         "stage_gbs": r["stage_gbs"],
+        "rocfft": r["rocfft"],
+        "copy_gbs": copy_gbs,
         "secondary": sec,
         "batch": bat,
     }

@@ -136,11 +136,27 @@ __global__ void bin_hist_kernel(Geom g, const R* __restrict__ pos, long long chu
   long long i1 = i0 + chunk;
   if (i1 > g.N) i1 = g.N;
   bool bad = false;
-  for (long long i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
-    const uint32_t key = fdiv(pb.bin, kdiv);
-    uint32_t r = atomicAdd(&hist[key], 1u);
-    kr[i] = key | (r << shift);
+  // four points per thread loaded before any is binned (the loop is otherwise
+  // one dependent load at a time)
+  const long long step = 4LL * blockDim.x;
+  for (long long ib = i0 + threadIdx.x; ib < i1; ib += step) {
+    R x[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = ib + (long long)u * blockDim.x;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[u][a] = (i < i1 && a < g.d) ? pos[i * g.d + a] : R(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long i = ib + (long long)u * blockDim.x;
+      if (i < i1) {
+        PointBin pb = bin_point<R>(g, x[u], &bad);
+        const uint32_t key = fdiv(pb.bin, kdiv);
+        uint32_t r = atomicAdd(&hist[key], 1u);
+        kr[i] = key | (r << shift);
+      }
+    }
   }
   if (bad) atomicOr(flag, 1);
   __syncthreads();
@@ -445,24 +461,38 @@ __global__ void bin_scatter_atomic_kernel(Geom g, const R* __restrict__ pos,
 // chunks of 1024 in order).
 __global__ void scan_bins_kernel(const uint32_t* __restrict__ count, long long nb,
                                  long long* __restrict__ start) {
-  __shared__ long long s[1024];
+  // 1024 threads; each chunk of 1024 counts: wave scans by shuffles, then the 16
+  // wave totals by one wave
+  __shared__ long long wsum[16];
   __shared__ long long carry;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (long long base = 0; base < nb; base += 1024) {
-    long long i = base + threadIdx.x;
-    long long v = (i < nb) ? (long long)count[i] : 0;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      long long add = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
-      __syncthreads();
-      s[threadIdx.x] += add;
-      __syncthreads();
+    const long long i = base + threadIdx.x;
+    const long long v = (i < nb) ? (long long)count[i] : 0;
+    long long x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const long long y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
     }
-    if (i < nb) start[i] = carry + s[threadIdx.x] - v;
+    if (lane == 63) wsum[wv] = x;
     __syncthreads();
-    if (threadIdx.x == 1023) carry += s[1023];
+    if (wv == 0) {
+      long long t = (lane < 16) ? wsum[lane] : 0;
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const long long y = __shfl_up(t, off, 64);
+        if (lane >= off) t += y;
+      }
+      if (lane < 16) wsum[lane] = t;  // inclusive totals of waves 0..lane
+    }
+    __syncthreads();
+    const long long before = carry + (wv > 0 ? wsum[wv - 1] : 0);
+    if (i < nb) start[i] = before + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += wsum[15];
     __syncthreads();
   }
   if (threadIdx.x == 0) start[nb] = carry;
@@ -628,11 +658,22 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
     uint32_t* cnt = acc32;  // Ta Tb <= ncell words, before the accumulator is cleared
     for (int c = threadIdx.x; c < Ta * Tb; c += blockDim.x) cnt[c] = 0u;
     __syncthreads();
-    for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
-      const uint32_t cl = rec[j].cell;
-      const int la = (D == 3) ? (int)((cl >> 8) & 0xff) : (int)(cl & 0xff);
-      const int lb = (D == 3) ? (int)((cl >> 16) & 0xff) : (int)((cl >> 8) & 0xff);
-      atomicAdd(cnt + lb * Ta + la, 1u);
+    // four cells loaded per thread before the first count
+    for (long long jb = s + threadIdx.x; jb < e; jb += 4LL * blockDim.x) {
+      uint32_t cl[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long j = jb + (long long)u * blockDim.x;
+        cl[u] = (j < e) ? rec[j].cell : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (jb + (long long)u * blockDim.x < e) {
+          const int la = (D == 3) ? (int)((cl[u] >> 8) & 0xff) : (int)(cl[u] & 0xff);
+          const int lb = (D == 3) ? (int)((cl[u] >> 16) & 0xff) : (int)((cl[u] >> 8) & 0xff);
+          atomicAdd(cnt + lb * Ta + la, 1u);
+        }
+      }
     }
     __syncthreads();
     // separable box sum: along a into tmp[yb][ia], then along b
