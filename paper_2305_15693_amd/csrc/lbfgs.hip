@@ -24,7 +24,7 @@
 //            x = xt, g = g(xt), and the new dot products s_j.y, y_j.y, s_j.g,
 //            y_j.g, g.g as block partials;
 //   small    one block: applies the decision, reduces the partials, stores the
-//            pair when y.s > 0 and solves for u, t (FP64, one thread);
+//            pair when y.s > 0 and solves for u, t (FP64, one wavefront);
 //   pass B   p = -(gamma g + S u - gamma Y t), max |p| per block;
 //   pass C   alpha = min(1, max_step / max|p|), xt = x + alpha p.
 // (Cross-block steps stay at kernel boundaries: a device-scope fence per block
@@ -105,16 +105,21 @@ __device__ void lb_decide(LbfgsState* S, const LbfgsOpts& o) {
 }
 
 // ---------------------------------------------------------------- pass A
-__device__ __forceinline__ void lb_small_solve(LbfgsState* S, const LbfgsOpts& o,
-                                               const double* red, int step, long long n);
+__device__ __forceinline__ void lb_small_update(LbfgsState* S, const LbfgsOpts& o,
+                                                const double* red, int step, long long n,
+                                                int* cs);
+__device__ __forceinline__ void lb_small_direction(LbfgsState* S, const LbfgsOpts& o,
+                                                   const int* cs);
 
 // One block after pass A: apply the decision, reduce the partials, update the
-// pair products and solve for the direction coefficients.  The serial solve runs
-// on an LDS copy of the state (dependent global loads would dominate otherwise).
+// pair products (one thread) and solve for the direction coefficients (one
+// wavefront), on an LDS copy of the state (dependent global loads would
+// dominate otherwise).
 __global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part, int nb,
                                 long long n) {
   __shared__ double red[4 * kLbfgsMaxM + 1];
   __shared__ LbfgsState sh;
+  __shared__ int cs[kLbfgsMaxM];
   static_assert(sizeof(LbfgsState) % 4 == 0, "state copied as 32-bit words");
   constexpr int kWords = (int)(sizeof(LbfgsState) / 4);
   for (int i = threadIdx.x; i < kWords; i += blockDim.x)
@@ -144,8 +149,10 @@ __global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part,
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0 && (step == LB_ACCEPT || step == LB_INIT || step == LB_RESTART))
-    lb_small_solve(&sh, o, red, step, n);
+  const bool dir = step == LB_ACCEPT || step == LB_INIT || step == LB_RESTART;
+  if (threadIdx.x == 0 && dir) lb_small_update(&sh, o, red, step, n, cs);
+  __syncthreads();
+  if (threadIdx.x < 64 && dir) lb_small_direction(&sh, o, cs);
   __syncthreads();
   for (int i = threadIdx.x; i < kWords; i += blockDim.x)
     reinterpret_cast<uint32_t*>(Sg)[i] = reinterpret_cast<const uint32_t*>(&sh)[i];
@@ -204,9 +211,11 @@ __global__ void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
   }
 }
 
-// serial part of the small step (one thread, state in LDS)
-__device__ __forceinline__ void lb_small_solve(LbfgsState* S, const LbfgsOpts& o,
-                                               const double* red, int step, long long n) {
+// Serial part of the small step (one thread, state in LDS): the new pair's
+// products, and the chronological slots cs[0] (oldest) .. cs[k-1] (newest).
+__device__ __forceinline__ void lb_small_update(LbfgsState* S, const LbfgsOpts& o,
+                                                const double* red, int step, long long n,
+                                                int* cs) {
   const int m = o.m;
   if (step != LB_RESTART) {
     S->gg = red[4 * m];
@@ -235,71 +244,100 @@ __device__ __forceinline__ void lb_small_solve(LbfgsState* S, const LbfgsOpts& o
       S->k = 0;  // curvature condition failed: steepest descent
     }
   }
-  // chronological slots: c[0] oldest ... c[k-1] newest
   const int k = S->k;
-  // small arrays with runtime indices live in LDS (private arrays would go to
-  // scratch memory)
-  __shared__ int cs[kLbfgsMaxM];
   for (int i = 0; i < k; ++i) cs[i] = (S->head - (k - 1) + i + m) % m;
   for (int j = 0; j < m; ++j) {
     S->coefS[j] = 0.0;
     S->coefY[j] = 0.0;
   }
+}
+
+// Direction coefficients by one wavefront: lane i < k holds the pair of
+// chronological index i, with its row of R = S^T Y (upper triangle used), its
+// column of R and its row of Y^T Y in registers; the triangular solves pass
+// each solved unknown to the other lanes by shuffle.
+__device__ __forceinline__ void lb_small_direction(LbfgsState* S, const LbfgsOpts& o,
+                                                   const int* cs) {
+  const int lane = threadIdx.x & 63;
+  const int k = S->k;
   double gtp;
   if (k == 0) {
-    S->coefG = 1.0;
+    if (lane == 0) S->coefG = 1.0;
     gtp = -S->gg;
   } else {
     const double gam = S->gamma;
-    __shared__ double a[kLbfgsMaxM], b[kLbfgsMaxM], t[kLbfgsMaxM], w[kLbfgsMaxM],
-        u[kLbfgsMaxM];
-    for (int i = 0; i < k; ++i) {
-      a[i] = S->SG[cs[i]];
-      b[i] = S->YG[cs[i]];
+    const bool mine = lane < k;
+    const int si = mine ? cs[lane] : 0;
+    double Rrow[kLbfgsMaxM], Rcol[kLbfgsMaxM], Yrow[kLbfgsMaxM];
+#pragma unroll
+    for (int j = 0; j < kLbfgsMaxM; ++j) {
+      const bool on = mine && j < k;
+      const int sj = (j < k) ? cs[j] : 0;
+      Rrow[j] = on ? S->SY[si * kLbfgsMaxM + sj] : 0.0;  // s_i . y_j
+      Rcol[j] = on ? S->SY[sj * kLbfgsMaxM + si] : 0.0;  // s_j . y_i
+      Yrow[j] = on ? S->YY[si * kLbfgsMaxM + sj] : 0.0;  // y_i . y_j
     }
-    // R t = a, R_ij = s_i . y_j (i <= j), upper triangular
-    for (int i = k - 1; i >= 0; --i) {
-      double r = a[i];
-      for (int j = i + 1; j < k; ++j) r -= S->SY[cs[i] * kLbfgsMaxM + cs[j]] * t[j];
-      t[i] = r / S->SY[cs[i] * kLbfgsMaxM + cs[i]];
+    const double a = mine ? S->SG[si] : 0.0;  // s_i . g
+    const double b = mine ? S->YG[si] : 0.0;  // y_i . g
+    const double D = mine ? S->SY[si * kLbfgsMaxM + si] : 1.0;
+    // R t = a, from the newest pair down
+    double r = a, t = 0.0;
+#pragma unroll
+    for (int i0 = kLbfgsMaxM - 1; i0 >= 0; --i0) {
+      if (i0 < k) {
+        const double ti = __shfl(r, i0, 64) / __shfl(D, i0, 64);
+        if (lane == i0) t = ti;
+        if (lane < i0) r -= Rrow[i0] * ti;
+      }
     }
     // w = (D + gamma Y^T Y) t - gamma b
-    for (int i = 0; i < k; ++i) {
-      double r = S->SY[cs[i] * kLbfgsMaxM + cs[i]] * t[i] - gam * b[i];
-      for (int j = 0; j < k; ++j) r += gam * S->YY[cs[i] * kLbfgsMaxM + cs[j]] * t[j];
-      w[i] = r;
+    double w = D * t - gam * b;
+#pragma unroll
+    for (int j = 0; j < kLbfgsMaxM; ++j)
+      if (j < k) w += gam * Yrow[j] * __shfl(t, j, 64);
+    // R^T u = w, from the oldest pair up
+    double q = w, u = 0.0;
+#pragma unroll
+    for (int j0 = 0; j0 < kLbfgsMaxM; ++j0) {
+      if (j0 < k) {
+        const double uj = __shfl(q, j0, 64) / __shfl(D, j0, 64);
+        if (lane == j0) u = uj;
+        if (lane > j0) q -= Rcol[j0] * uj;
+      }
     }
-    // R^T u = w, lower triangular
-    for (int i = 0; i < k; ++i) {
-      double r = w[i];
-      for (int j = 0; j < i; ++j) r -= S->SY[cs[j] * kLbfgsMaxM + cs[i]] * u[j];
-      u[i] = r / S->SY[cs[i] * kLbfgsMaxM + cs[i]];
+    if (mine) {
+      S->coefS[si] = u;
+      S->coefY[si] = -gam * t;
     }
-    double ua = 0.0, tb = 0.0;
-    for (int i = 0; i < k; ++i) {
-      S->coefS[cs[i]] = u[i];
-      S->coefY[cs[i]] = -gam * t[i];
-      ua += u[i] * a[i];
-      tb += t[i] * b[i];
+    double ua = mine ? u * a : 0.0, tb = mine ? t * b : 0.0;
+    for (int off = 32; off > 0; off >>= 1) {
+      ua += __shfl_down(ua, off, 64);
+      tb += __shfl_down(tb, off, 64);
     }
-    S->coefG = gam;
+    ua = __shfl(ua, 0, 64);
+    tb = __shfl(tb, 0, 64);
+    if (lane == 0) S->coefG = gam;
     gtp = -(gam * S->gg + ua - gam * tb);
     if (!(gtp < 0.0) || !isfinite(gtp)) {
       // not a descent direction: drop the history, steepest descent
-      S->k = 0;
-      S->resets += 1;
-      for (int j = 0; j < m; ++j) {
-        S->coefS[j] = 0.0;
-        S->coefY[j] = 0.0;
+      if (mine) {
+        S->coefS[si] = 0.0;
+        S->coefY[si] = 0.0;
       }
-      S->coefG = 1.0;
+      if (lane == 0) {
+        S->k = 0;
+        S->resets += 1;
+        S->coefG = 1.0;
+      }
       gtp = -S->gg;
     }
   }
-  S->gtp = gtp;
-  if (!(gtp < 0.0)) {
-    S->converged = 1;  // zero gradient
-    S->step = LB_IDLE;
+  if (lane == 0) {
+    S->gtp = gtp;
+    if (!(gtp < 0.0)) {
+      S->converged = 1;  // zero gradient
+      S->step = LB_IDLE;
+    }
   }
 }
 
