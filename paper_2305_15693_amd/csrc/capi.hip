@@ -745,7 +745,9 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
   last.S0m = S->S0m;
   last.loss_part = S->loss_part;
   last.S_cube = S_cube;
-  last.rho_save = S->rho;
+  // the backward reads rho saved by the structure-factor pass; a loss
+  // evaluation keeps none (it also invalidates the reuse of that pass)
+  last.rho_save = (mode == COL_BWD) ? S->rho : nullptr;
   last.g_cube = g_cube;
   {
     StageTimer t(c, FRESCO_STAGE_MODES);
