@@ -410,6 +410,15 @@ int create_state(fresco_ctx* c) {
         if (plan_level((g.nbins + G0 - 1) / G0, G0, false, 8192, &bp.coarse)) bp.levels = 2;
       }
     }
+    // FRESCO_BIN_ATOMIC=1: the global-atomic fallback (grids or point counts
+    // beyond both sorts) at any size, for checks
+    const char* ea = std::getenv("FRESCO_BIN_ATOMIC");
+    if (ea && ea[0] == '1') {
+      bp.mode = BIN_ATOMIC;
+      bp.G = 1;
+      bp.nkeys = g.nbins;
+      bp.levels = 1;
+    }
   }
   bp.kdiv = make_fastdiv((uint32_t)bp.G);
   BinBuffers& bb = S->bb;

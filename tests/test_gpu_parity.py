@@ -336,3 +336,35 @@ def test_fold_in_row_pass_matches_fold_kernel(gpu, d, N, L, M):
         ctx.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+@pytest.mark.parametrize("dtype,d,N,L,M,tol,bar", [("f64", 2, 1024, 32.0, 16, 1e-12, 1e-11),
+                                                   ("f32", 3, 4096, 16.0, 8, 1e-6, 1e-5)])
+def test_atomic_binning_fallback(gpu, dtype, d, N, L, M, tol, bar):
+    # the global-atomic sort (used beyond both LDS-histogram sorts), forced at a
+    # small size: oracle parity and bitwise equality with the tile sort
+    import os
+    import torch
+    rdt = np.float32 if dtype == "f32" else np.float64
+    pos = I.positions(N, d, L, rdt, seed=55)
+    pos[::5] -= 2 * L
+    w, s0 = I.stealthy_target(d, M, M)
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    tpos = torch.from_numpy(pos).to(device=gpu, dtype=tdt)
+    one = make_ctx(gpu, d, N, L, M, w, s0, tol, dtype)
+    os.environ["FRESCO_BIN_ATOMIC"] = "1"
+    try:
+        atom = make_ctx(gpu, d, N, L, M, w, s0, tol, dtype)
+    finally:
+        os.environ.pop("FRESCO_BIN_ATOMIC", None)
+    assert atom.plan_info()["bin_ranges"] == -1
+    res = []
+    for ctx in (one, atom):
+        loss, grad = ctx.loss_grad(tpos)
+        res.append((loss, grad.cpu().numpy()))
+        ctx.close()
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+    So, lo, go = oracle_case(pos, L, M, w, s0)
+    assert abs(res[1][0] - lo) / lo < bar
+    assert rel(res[1][1], go) < bar
