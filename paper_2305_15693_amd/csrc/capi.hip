@@ -531,6 +531,7 @@ int create_state(fresco_ctx* c) {
       cp.deci[a] = (a < d) ? S->deci[a] : nullptr;
     }
     cp.invN = (R)(1.0 / (double)g.N);
+    cp.mcol = true;  // the long-column path (rows of modes) clears it
   };
   ColParams<R>& c1 = S->col1;
   std::memset(&c1, 0, sizeof(c1));
@@ -554,6 +555,7 @@ int create_state(fresco_ctx* c) {
       // columns too long for LDS: two half-length sub-transforms per column
       // (decimation by 2; nf1 is even and 2M + 1 <= nf1 / 2)
       S->long_cols = true;
+      c1.mcol = false;
       const int n = g.nf[1], m = n / 2;
       const long long P = 2LL * g.M[1] + 1;
       if ((st = setup_axis<R>(c, &S->ax[1], m, false))) return st;
@@ -632,6 +634,7 @@ int upload_weights(fresco_ctx* c, const std::vector<double>& Wc, const std::vect
   const long long H0 = g.M[0] + 1, P1 = 2 * g.M[1] + 1, P2 = (d == 3) ? 2 * g.M[2] + 1 : 1;
   const long long nlast = (d == 2) ? P1 : P2;
   const long long ncols = (d == 2) ? H0 : P1 * H0;
+  const bool long_cols = S->long_cols;
   std::vector<double> wp(g.nhalf), sp(g.nhalf), wm(g.nhalf), sm(g.nhalf);
   auto cube_index = [&](int n0, int n1, int n2) -> long long {
     if (d == 2) return (long long)(n0 + g.M[0]) * P1 + (n1 + g.M[1]);
@@ -648,7 +651,10 @@ int upload_weights(fresco_ctx* c, const std::vector<double>& Wc, const std::vect
         n1 = (int)(cidx / H0) - g.M[1];
         n2 = (int)m - g.M[2];
       }
-      const long long h = cidx + ncols * m;
+      // column-major [c][m] for the column pass (each column reads its modes
+      // contiguously); [m][c] for the long-column recombination, which walks
+      // rows of modes
+      const long long h = long_cols ? cidx + ncols * m : cidx * nlast + m;
       const long long ip = cube_index(n0, n1, n2), im = cube_index(-n0, -n1, -n2);
       wp[h] = Wc[ip];
       sp[h] = S0c[ip];

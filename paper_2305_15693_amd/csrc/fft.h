@@ -61,7 +61,8 @@ struct ColParams {
   const R* dec[3];   // spreading kernel: h_a / psihat_a(|n_a|), n_a in [0, M_a]
   const R* deci[3];  // interpolation kernel: h_a / psihat_i,a(|n_a|)
   R invN;
-  const R* Wp;       // half spectrum [m][c]: W(n), S0(n), W(-n), S0(-n)
+  bool mcol;         // mode-stage arrays below column-major [c][m] (else [m][c])
+  const R* Wp;       // half spectrum: W(n), S0(n), W(-n), S0(-n)
   const R* S0p;
   const R* Wm;
   const R* S0m;

@@ -294,7 +294,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
 #pragma unroll
     for (int u = 0; u < kModePre; ++u) {
       const int m = tj + u * JT;
-      const long long h = c + (long long)p.ncols * m;
+      const long long h = p.mcol ? c * P + m : c + (long long)p.ncols * m;
       const bool ok = active && m < P;
       const int nl = m - p.M;
       const int al = ok ? (nl < 0 ? -nl : nl) : 0;
@@ -361,7 +361,8 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
     auto mode_body = [&](int m, R wp, R wm, R s0p, R s0m, R dk, R dik) {
       const int nl = m - p.M;
       const R dec = dlead * dk;
-      const long long hidx = c + (long long)p.ncols * m;  // half-spectrum index
+      // half-spectrum index of the mode-stage arrays
+      const long long hidx = p.mcol ? c * P + m : c + (long long)p.ncols * m;
       cpx<R> rho;
       if (MODE == COL_BWD) {
         rho = p.rho_save[hidx];
@@ -414,7 +415,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       }
     } else {
       for (int m = tj; m < P; m += JT) {
-        const long long h = c + (long long)p.ncols * m;
+        const long long h = p.mcol ? c * P + m : c + (long long)p.ncols * m;
         const int nl = m - p.M;
         const int al = nl < 0 ? -nl : nl;
         const R dk = p.dec[p.d - 1][al], dik = p.deci[p.d - 1][al];
