@@ -490,6 +490,8 @@ int create_state(fresco_ctx* c) {
   std::memset(&rp, 0, sizeof(rp));
   rp.nrows = nf1 * nf2;
   rp.M0 = g.M[0];
+  rp.rstride = g.M[0] + 1;
+  rp.kstride = 1;
   if (!shape_rows(g.nf[0] / 2, S->ax[0].rmin, rp.nrows, cs, &rp.lines_per_block, &rp.threads,
                   &rp.tw_lds))
     return FRESCO_ENOTSUP;
@@ -548,6 +550,21 @@ int create_state(fresco_ctx* c) {
     if (!force_long &&
         shape_cols(g.nf[1], S->ax[1].rmin, c1.ncols, cs, &c1.bc, &c1.threads, &c1.tw_lds)) {
       S->nloss_part = (c1.ncols + c1.bc - 1) / c1.bc;
+      // half spectrum column-major (each column contiguous for the column
+      // pass; the row passes, which have one workgroup per row, take the
+      // strided accesses, with 16 consecutive rows per XCD).
+      // FRESCO_ROW_MAJOR=1 keeps the row-major layout.
+      const char* erm = std::getenv("FRESCO_ROW_MAJOR");
+      if (rp.lines_per_block == 1 && !(erm && erm[0] == '1')) {
+        rp.rstride = 1;
+        rp.kstride = nf1;
+        rp.xcd16 = 1;
+        c1.cdiv = make_fastdiv(1u);
+        c1.in_outer = nf1;
+        c1.out_outer = nf1;
+        c1.in_line = 1;
+        c1.out_line = 1;
+      }
       HIPCHK(prepare_cols<R>(COL_FUSED, c1, S->ax[1]));
       HIPCHK(prepare_cols<R>(COL_SF, c1, S->ax[1]));
       HIPCHK(prepare_cols<R>(COL_BWD, c1, S->ax[1]));

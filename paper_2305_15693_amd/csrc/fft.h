@@ -37,6 +37,13 @@ struct RowParams {
   int M0;
   const R* rin;          // forward input rows (real, length 2H)
   cpx<R>* cout;          // forward output rows (M0+1 complex)
+  // half-spectrum layout: mode k of row r at r * rstride + k * kstride
+  // (row-major: M0 + 1, 1; column-major: 1, nrows)
+  long long rstride, kstride;
+  // one row per workgroup, each group of 16 consecutive rows on one XCD
+  // (workgroups go to the 8 XCDs round-robin), so that a column-major
+  // half spectrum's lines fill in one L2
+  int xcd16;
   const cpx<R>* cin[3];  // inverse inputs per component
   R* rout[3];            // inverse outputs per component
   RowFold<R> fold;       // forward only

@@ -143,6 +143,14 @@ __device__ __forceinline__ void fold_line(const RowFold<R>& f, long long row, co
   }
 }
 
+// row served by line b of this workgroup
+template <class R>
+__device__ __forceinline__ long long row_of_block(const RowParams<R>& p, int b) {
+  if (!p.xcd16) return (long long)blockIdx.x * p.lines_per_block + b;
+  const uint32_t w = blockIdx.x, x = w & 7u, l = w >> 3;
+  return ((long long)((l >> 4) * 8u + x) << 4) + (l & 15u);
+}
+
 template <class R, int MAXB>
 __global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __restrict__ twH,
                                 const cpx<R>* __restrict__ twN) {
@@ -154,7 +162,8 @@ __global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   const int ls = H + 1;
   const int JT = blockDim.x / p.lines_per_block;
   const int b = threadIdx.x / JT, tj = threadIdx.x % JT;
-  const long long row = (long long)blockIdx.x * p.lines_per_block + b;
+  const long long row = row_of_block(p, b);
+  if (p.xcd16 && row >= p.nrows) return;  // whole workgroup
   const bool active = row < p.nrows;
   if (twl) load_twiddles(tws, twH, H);
   if (p.fold.tiles) {
@@ -173,13 +182,13 @@ __global__ void rows_r2c_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   if (twl) lds_fft<R, MAXB, false>(buf, F, tws, active, b, ls, 1, tj, JT);
   else lds_fft<R, MAXB, false>(buf, F, twH, active, b, ls, 1, tj, JT);
   if (active) {
-    cpx<R>* __restrict__ out = p.cout + row * (long long)(p.M0 + 1);
+    cpx<R>* __restrict__ out = p.cout + row * p.rstride;
     for (int k = tj; k <= p.M0; k += JT) {
       cpx<R> Zk = buf[b * ls + k];
       cpx<R> Zc = cconj(buf[b * ls + (k == 0 ? 0 : H - k)]);
       cpx<R> E = cscale(cadd(Zk, Zc), R(0.5));
       cpx<R> O = cscale(cmul_mi(csub(Zk, Zc)), R(0.5));  // (Zk - Zc) / (2i)
-      out[k] = cadd(E, cmul(twN[k], O));
+      out[k * p.kstride] = cadd(E, cmul(twN[k], O));
     }
   }
 }
@@ -201,18 +210,20 @@ __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   const int ls = H + 1;
   const int JT = blockDim.x / p.lines_per_block;
   const int b = threadIdx.x / JT, tj = threadIdx.x % JT;
-  const long long row = (long long)blockIdx.x * p.lines_per_block + b;
+  const long long row = row_of_block(p, b);
+  if (p.xcd16 && row >= p.nrows) return;  // whole workgroup
   const bool active = row < p.nrows;
   const int comp = blockIdx.y;
   const int M0 = p.M0;
   if (twl) load_twiddles(tws, twH, H);
   if (active) {
-    const cpx<R>* __restrict__ X = p.cin[comp] + row * (long long)(M0 + 1);
+    const cpx<R>* __restrict__ X = p.cin[comp] + row * p.rstride;
+    const long long ks = p.kstride;
     for (int k = tj; k < H; k += JT) {
       cpx<R> xk = {R(0), R(0)}, xm = {R(0), R(0)};
-      if (k <= M0) xk = X[k];
+      if (k <= M0) xk = X[k * ks];
       if (k == 0) xk.y = R(0);
-      if (k > 0 && H - k <= M0) xm = cconj(X[H - k]);
+      if (k > 0 && H - k <= M0) xm = cconj(X[(H - k) * ks]);
       cpx<R> E = cadd(xk, xm);
       cpx<R> O = cmulc(csub(xk, xm), twN[k]);  // * exp(-2 pi i k / nf)
       buf[b * ls + k] = cadd(E, cmul_i(O));
@@ -630,7 +641,10 @@ hipError_t launch_rows(bool inverse, const RowParams<R>& p, const AxisFft<R>& ax
   const int mb = rows_maxb(p, ax);
   if (mb < 0) return hipErrorInvalidValue;
   const size_t lds = rows_lds_bytes(p, ax);
-  dim3 grid((unsigned)((p.nrows + p.lines_per_block - 1) / p.lines_per_block), inverse ? ncomp : 1);
+  const long long groups = (p.nrows + 15) / 16;
+  const long long nblk = p.xcd16 ? 128 * ((groups + 7) / 8)
+                                 : (p.nrows + p.lines_per_block - 1) / p.lines_per_block;
+  dim3 grid((unsigned)nblk, inverse ? ncomp : 1);
   dim3 block(p.threads);
 #define ROWS(MB)                                                                   \
   do {                                                                             \

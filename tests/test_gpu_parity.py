@@ -368,3 +368,31 @@ def test_atomic_binning_fallback(gpu, dtype, d, N, L, M, tol, bar):
     So, lo, go = oracle_case(pos, L, M, w, s0)
     assert abs(res[1][0] - lo) / lo < bar
     assert rel(res[1][1], go) < bar
+
+
+def test_column_major_half_spectrum_matches_row_major(gpu):
+    # the 2D half spectrum stored column-major (row passes write and read it
+    # strided, the column pass contiguously) holds the same values as the
+    # row-major layout: identical S, loss, gradient and backward of S
+    import os
+    import torch
+    d, N, L, M = 2, 20000, 141.4, 40
+    pos = I.positions(N, d, L, np.float32, seed=93)
+    w, s0 = I.stealthy_target(d, M, M)
+    tpos = torch.from_numpy(pos).to(gpu)
+    out = []
+    for rm in ("0", "1"):
+        os.environ["FRESCO_ROW_MAJOR"] = rm
+        try:
+            ctx = make_ctx(gpu, d, N, L, M, w, s0, 1e-6, "f32")
+        finally:
+            os.environ.pop("FRESCO_ROW_MAJOR", None)
+        S = ctx.structure_factor(tpos).cpu().numpy()
+        gS = np.random.default_rng(6).normal(size=ctx.cube_shape)
+        gb = ctx.structure_factor_backward(tpos, torch.from_numpy(gS).to(device=gpu, dtype=torch.float32),
+                                           token=ctx.sf_token()).cpu().numpy()
+        loss, grad = ctx.loss_grad(tpos)
+        out.append((S, gb, loss, grad.cpu().numpy()))
+        ctx.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
