@@ -219,14 +219,27 @@ __global__ void rows_c2r_kernel(RowParams<R> p, FftFactors F, const cpx<R>* __re
   if (active) {
     const cpx<R>* __restrict__ X = p.cin[comp] + row * p.rstride;
     const long long ks = p.kstride;
-    for (int k = tj; k < H; k += JT) {
-      cpx<R> xk = {R(0), R(0)}, xm = {R(0), R(0)};
-      if (k <= M0) xk = X[k * ks];
-      if (k == 0) xk.y = R(0);
-      if (k > 0 && H - k <= M0) xm = cconj(X[(H - k) * ks]);
-      cpx<R> E = cadd(xk, xm);
-      cpx<R> O = cmulc(csub(xk, xm), twN[k]);  // * exp(-2 pi i k / nf)
-      buf[b * ls + k] = cadd(E, cmul_i(O));
+    // four iterations' strided loads are issued before any of them is used
+    constexpr int U = 4;
+    for (int k0 = tj; k0 < H; k0 += U * JT) {
+      cpx<R> xk[U], xm[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * JT;
+        xk[u] = cpx<R>{R(0), R(0)};
+        xm[u] = cpx<R>{R(0), R(0)};
+        if (k < H && k <= M0) xk[u] = X[k * ks];
+        if (k < H && k > 0 && H - k <= M0) xm[u] = cconj(X[(H - k) * ks]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * JT;
+        if (k >= H) break;
+        if (k == 0) xk[u].y = R(0);
+        cpx<R> E = cadd(xk[u], xm[u]);
+        cpx<R> O = cmulc(csub(xk[u], xm[u]), twN[k]);  // * exp(-2 pi i k / nf)
+        buf[b * ls + k] = cadd(E, cmul_i(O));
+      }
     }
   }
   __syncthreads();

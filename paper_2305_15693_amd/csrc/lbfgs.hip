@@ -160,7 +160,56 @@ __global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part,
 
 // Partial slots: [0, m) s_j.y_new, [m, 2m) y_j.y_new, [2m, 3m) s_j.g, [3m, 4m) y_j.g,
 // 4m g.g (slot j indexes the ring; the new pair's own entries sit at its slot).
-// MM = history length m (compile time, so the accumulators stay in registers)
+// MM = history length m (compile time, so the accumulators stay in registers).
+// Every load of an element is issued before its stores and products (the ring
+// slot of the new pair is read before it is overwritten and its value replaced
+// by the new pair's); ALL: every slot holds a pair (the steady state), so no
+// load waits behind a branch.
+template <class R, int MM, bool ACC, bool ALL>
+__device__ __forceinline__ void pass_a_loop(const LbfgsVec<R>& v, unsigned live, int ns, R alpha,
+                                            double (&acc_v)[4 * MM + 1]) {
+  R* Sn = v.S + (long long)ns * v.n;
+  R* Yn = v.Y + (long long)ns * v.n;
+  GRID_LOOP(i, v.n) {
+    R sj[MM], yj[MM];
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      const bool lj = ALL || ((live >> j) & 1u);
+      sj[j] = lj ? v.S[(long long)j * v.n + i] : R(0);
+      yj[j] = lj ? v.Y[(long long)j * v.n + i] : R(0);
+    }
+    const R gn = v.gt[i];
+    const R g0 = v.g[i];
+    R yy = R(0);
+    if (ACC) {
+      const R sy = alpha * v.p[i];
+      const R xt = v.xt[i];
+      yy = gn - g0;
+      Sn[i] = sy;
+      Yn[i] = yy;
+      v.x[i] = xt;
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        sj[j] = (j == ns) ? sy : sj[j];
+        yj[j] = (j == ns) ? yy : yj[j];
+      }
+    }
+    v.g[i] = gn;
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      if (ALL || ((live >> j) & 1u)) {
+        if (ACC) {
+          acc_v[j] += (double)sj[j] * (double)yy;
+          acc_v[MM + j] += (double)yj[j] * (double)yy;
+        }
+        acc_v[2 * MM + j] += (double)sj[j] * (double)gn;
+        acc_v[3 * MM + j] += (double)yj[j] * (double)gn;
+      }
+    }
+    acc_v[4 * MM] += (double)gn * (double)gn;
+  }
+}
+
 template <class R, int MM>
 __global__ void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
   __shared__ double sh[(4 * MM + 1) * kWaves];
@@ -179,34 +228,10 @@ __global__ void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
     double acc_v[4 * MM + 1];
 #pragma unroll
     for (int c = 0; c < 4 * MM + 1; ++c) acc_v[c] = 0.0;
-    R* Sn = v.S + (long long)ns * v.n;
-    R* Yn = v.Y + (long long)ns * v.n;
-    GRID_LOOP(i, v.n) {
-      const R gn = v.gt[i];
-      R yy = R(0);
-      if (acc) {
-        const R sy = alpha * v.p[i];
-        yy = gn - v.g[i];
-        Sn[i] = sy;
-        Yn[i] = yy;
-        v.x[i] = v.xt[i];
-      }
-      v.g[i] = gn;
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        if ((live >> j) & 1u) {
-          const R sj = v.S[(long long)j * v.n + i];
-          const R yj = v.Y[(long long)j * v.n + i];
-          if (acc) {
-            acc_v[j] += (double)sj * (double)yy;
-            acc_v[MM + j] += (double)yj * (double)yy;
-          }
-          acc_v[2 * MM + j] += (double)sj * (double)gn;
-          acc_v[3 * MM + j] += (double)yj * (double)gn;
-        }
-      }
-      acc_v[4 * MM] += (double)gn * (double)gn;
-    }
+    constexpr unsigned kAll = (MM >= 32) ? 0xffffffffu : ((1u << MM) - 1u);
+    if (acc && live == kAll) pass_a_loop<R, MM, true, true>(v, live, ns, alpha, acc_v);
+    else if (acc) pass_a_loop<R, MM, true, false>(v, live, ns, alpha, acc_v);
+    else pass_a_loop<R, MM, false, false>(v, live, ns, alpha, acc_v);
     block_partials<4 * MM + 1>(acc_v, 4 * MM + 1, v.part0, v.nb, sh);
   }
 }
@@ -342,6 +367,27 @@ __device__ __forceinline__ void lb_small_direction(LbfgsState* S, const LbfgsOpt
 }
 
 // ---------------------------------------------------------------- pass B
+// p = -(cg g + sum over live slots of cS S_j + cY Y_j); returns max |p| of the
+// thread's elements.  ALL: every slot holds a pair (no branch between loads).
+template <class R, int MM, bool ALL>
+__device__ __forceinline__ double pass_b_loop(const LbfgsVec<R>& v, unsigned live, R cg,
+                                              const R (&cS)[MM], const R (&cY)[MM]) {
+  double pm = 0.0;
+  GRID_LOOP(j, v.n) {
+    R r = cg * v.g[j];
+#pragma unroll
+    for (int i = 0; i < MM; ++i) {
+      if (ALL || ((live >> i) & 1u)) {
+        r += cS[i] * v.S[(long long)i * v.n + j];
+        r += cY[i] * v.Y[(long long)i * v.n + j];
+      }
+    }
+    v.p[j] = -r;
+    pm = fmax(pm, fabs((double)r));
+  }
+  return pm;
+}
+
 template <class R, int MM>
 __global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
   __shared__ double sh[kWaves];
@@ -359,17 +405,11 @@ __global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
   for (int t = 0; t < k; ++t) live |= 1u << ((S->head - t + MM) % MM);
   const R cg = (R)S->coefG;
   double pm = 0.0;
-  GRID_LOOP(j, v.n) {
-    R r = cg * v.g[j];
-#pragma unroll
-    for (int i = 0; i < MM; ++i) {
-      if ((live >> i) & 1u) {
-        r += cS[i] * v.S[(long long)i * v.n + j];
-        r += cY[i] * v.Y[(long long)i * v.n + j];
-      }
-    }
-    v.p[j] = -r;
-    pm = fmax(pm, fabs((double)r));
+  constexpr unsigned kAll = (MM >= 32) ? 0xffffffffu : ((1u << MM) - 1u);
+  if (live == kAll) {
+    pm = pass_b_loop<R, MM, true>(v, live, cg, cS, cY);
+  } else {
+    pm = pass_b_loop<R, MM, false>(v, live, cg, cS, cY);
   }
   for (int off = 32; off > 0; off >>= 1) pm = fmax(pm, __shfl_down(pm, off, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pm;
