@@ -954,11 +954,13 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   S->lb_opts = lo;
   const long long N = g.N;
   if (!S->have_perm0) {
-    // internal order = tile order of the starting positions; it stays fixed so
-    // that the history vectors never need permuting, and later binning passes
-    // see nearly sorted points
+    // internal order = tile order of the starting positions (stable: ties in
+    // the caller's order, so that the order and every dot product over it are
+    // the same from run to run); it stays fixed so that the history vectors
+    // never need permuting, and later binning passes see nearly sorted points
     launch_bin(g, S->bp, pos, sizeof(R) == 8, S->bb, c->st);
-    launch_sorted_index(g, S->bp, S->bb, S->perm0, c->st);
+    if (!launch_stable_index(g, S->bp, S->bb, pos, sizeof(R) == 8, S->perm0, c->st))
+      launch_sorted_index(g, S->bp, S->bb, S->perm0, c->st);
     if ((st = lbfgs_reset_state<R>(c))) return st;
     S->have_perm0 = true;
   }

@@ -191,6 +191,11 @@ void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const 
 // out[j] = caller index of sorted record j
 void launch_sorted_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, int* out,
                          hipStream_t st);
+// out[j] = caller index of slot j of a stable sort by the first-level key, after
+// launch_bin (histogram passes) at the same positions; false for plans without
+// first-level histograms of the caller's points (atomic sort, coarse pass)
+bool launch_stable_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, const void* pos,
+                         bool f64, int* out, hipStream_t st);
 template <class R>
 void launch_fill(R* p, long long n, R v, hipStream_t st);
 void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);

@@ -133,19 +133,45 @@ __global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part,
     // value c is reduced by wave c mod (waves): lane l sums the partials l,
     // l + 64, ... (nb <= 1024: at most 16, all loads issued before the first add)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = wave; c < 4 * m + 1; c += (int)(blockDim.x >> 6)) {
-      const double* pc = part + (long long)c * nb;
-      double v[kLbfgsMaxBlocks / 64];
+    const int nw = (int)(blockDim.x >> 6);
+    constexpr int kU = kLbfgsMaxBlocks / 64;
+    if (4 * m + 1 <= 3 * nw) {
+      // at most three values per wave: all of their loads issued together
+      double v[3][kU];
 #pragma unroll
-      for (int u = 0; u < kLbfgsMaxBlocks / 64; ++u) {
-        const int b = lane + 64 * u;
-        v[u] = (b < nb) ? pc[b] : 0.0;
+      for (int r = 0; r < 3; ++r) {
+        const int c = wave + r * nw;
+        const double* pc = part + (long long)c * nb;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int b = lane + 64 * u;
+          v[r][u] = (c < 4 * m + 1 && b < nb) ? pc[b] : 0.0;
+        }
       }
-      double t = 0.0;
 #pragma unroll
-      for (int u = 0; u < kLbfgsMaxBlocks / 64; ++u) t += v[u];
-      for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
-      if (lane == 0) red[c] = t;
+      for (int r = 0; r < 3; ++r) {
+        const int c = wave + r * nw;
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) t += v[r][u];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0 && c < 4 * m + 1) red[c] = t;
+      }
+    } else {
+      for (int c = wave; c < 4 * m + 1; c += nw) {
+        const double* pc = part + (long long)c * nb;
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int b = lane + 64 * u;
+          v[u] = (b < nb) ? pc[b] : 0.0;
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) t += v[u];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        if (lane == 0) red[c] = t;
+      }
     }
   }
   __syncthreads();
@@ -422,6 +448,25 @@ __global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
 }
 
 // ---------------------------------------------------------------- pass C
+// xt = x + alpha p, four elements of the thread in flight at once
+template <class R>
+__device__ __forceinline__ void trial_point(const R* __restrict__ x, const R* __restrict__ p,
+                                            R* __restrict__ xt, long long n, R alpha) {
+  const long long st = (long long)gridDim.x * blockDim.x;
+  long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; j + 3 * st < n; j += 4 * st) {
+    R a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = x[j + u * st];
+      b[u] = p[j + u * st];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xt[j + u * st] = a[u] + alpha * b[u];
+  }
+  for (; j < n; j += st) xt[j] = x[j] + alpha * p[j];
+}
+
 // step length of a new direction (every block reduces the pass B maxima), or
 // the one shrunk by the decision; then the trial point
 template <class R>
@@ -433,8 +478,17 @@ __global__ void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
   if (step == LB_REJECT) {
     if (threadIdx.x == 0) alpha_s = S->alpha;
   } else {
+    // nb <= kLbfgsMaxBlocks: every maximum a thread reads is loaded at once
+    constexpr int kU = (kLbfgsMaxBlocks + kThreads - 1) / kThreads;
+    double q[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = threadIdx.x + u * blockDim.x;
+      q[u] = (b < v.nb) ? v.part1[b] : 0.0;
+    }
     double pm = 0.0;
-    for (int b = threadIdx.x; b < v.nb; b += blockDim.x) pm = fmax(pm, v.part1[b]);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) pm = fmax(pm, q[u]);
     for (int off = 32; off > 0; off >>= 1) pm = fmax(pm, __shfl_down(pm, off, 64));
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pm;
     __syncthreads();
@@ -447,8 +501,7 @@ __global__ void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
     }
   }
   __syncthreads();
-  const R alpha = (R)alpha_s;
-  GRID_LOOP(j, v.n) v.xt[j] = v.x[j] + alpha * v.p[j];
+  trial_point<R>(v.x, v.p, v.xt, v.n, (R)alpha_s);
 }
 
 // set the mode read by the next decision (host-driven transitions)

@@ -424,17 +424,40 @@ __global__ void compose_index_kernel(long long N, const int* __restrict__ perm,
 }
 
 // Fallback for very many tiles: global atomic counts (key, rank per point).
+// Each run of consecutive lanes of a wavefront with the same tile takes its
+// ranks with one atomic (points that arrive in tile order share few; in random
+// order every run is one lane).
 template <class R>
 __global__ void bin_count_kernel(Geom g, const R* __restrict__ pos, uint32_t* __restrict__ key,
                                  uint32_t* __restrict__ rank, uint32_t* __restrict__ count,
                                  int* __restrict__ flag) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.N) return;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < g.N;
   bool bad = false;
-  PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
+  uint32_t k = 0xffffffffu;
+  if (valid) {
+    PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
+    k = pb.bin;
+  }
   if (bad) atomicOr(flag, 1);
-  key[i] = pb.bin;
-  rank[i] = atomicAdd(&count[pb.bin], 1u);
+  // points past N sit at the end of the last wavefront: each is a run of its own
+  // that takes no rank
+  const int lane = threadIdx.x & 63;
+  const uint32_t kp = __shfl_up(k, 1, 64);
+  const bool vp = __shfl_up((int)valid, 1, 64) != 0;
+  const bool head = lane == 0 || !valid || !vp || kp != k;
+  const unsigned long long hm = __ballot(head);
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int leader = 63 - __clzll(hm & upto);
+  const unsigned long long above = hm & ~upto;
+  const int end = above ? __ffsll((long long)above) - 1 : 64;
+  uint32_t base = 0;
+  if (head && valid) base = atomicAdd(&count[k], (uint32_t)(end - lane));
+  base = __shfl(base, leader, 64);
+  if (valid) {
+    key[i] = k;
+    rank[i] = base + (uint32_t)(lane - leader);
+  }
 }
 
 template <class R>
@@ -1071,6 +1094,87 @@ void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const 
           grad);
     }
   }
+}
+
+// Caller index per slot of a stable sort by the first-level key (the tile, or
+// the range of tiles): the points of one key keep their caller order.  Slot =
+// off[key] + H[key * nblk + chunk] (the histogram pass and its scans) + the
+// number of earlier points of the chunk with that key, counted in index order:
+// lanes of one wavefront with equal keys are grouped by ballots, and the
+// wavefronts of the block add to the running counts one after the other.  One
+// workgroup of 1024 threads per histogram chunk; LDS: nkeys running counts.
+template <class R>
+__global__ void bin_stable_kernel(Geom g, const R* __restrict__ pos, long long chunk, int nblk,
+                                  int nkeys, FastDiv kdiv, const uint32_t* __restrict__ H,
+                                  const long long* __restrict__ off, int* __restrict__ out) {
+  extern __shared__ uint32_t run[];
+  for (int k = threadIdx.x; k < nkeys; k += blockDim.x) run[k] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (int)(blockDim.x >> 6);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const long long i0 = (long long)blockIdx.x * chunk;
+  long long i1 = i0 + chunk;
+  if (i1 > g.N) i1 = g.N;
+  for (long long sb = i0; sb < i1; sb += blockDim.x) {
+    const long long i = sb + threadIdx.x;
+    const bool valid = i < i1;
+    uint32_t key = 0xffffffffu;
+    if (valid) {
+      bool bad = false;
+      key = fdiv(bin_point<R>(g, pos + i * g.d, &bad).bin, kdiv);
+    }
+    // lanes of this wavefront with the same key (the lowest unassigned lane's
+    // key per round)
+    unsigned long long peers = 0ull;
+    bool done = !valid;
+    for (;;) {
+      const unsigned long long act = __ballot(!done);
+      if (act == 0ull) break;
+      const int ld = __ffsll((long long)act) - 1;
+      const uint32_t lk = (uint32_t)__shfl((int)key, ld, 64);
+      const bool mine = !done && key == lk;
+      const unsigned long long m = __ballot(mine);
+      if (mine) {
+        peers = m;
+        done = true;
+      }
+    }
+    const uint32_t wr = (uint32_t)__popcll(peers & below);
+    const bool last = valid && (peers >> lane) == 1ull;
+    uint32_t r = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (wave == w && valid) r = run[key] + wr;
+      __syncthreads();
+      if (wave == w && last) run[key] += (uint32_t)__popcll(peers);
+      __syncthreads();
+    }
+    if (valid) out[off[key] + H[(long long)key * nblk + blockIdx.x] + r] = (int)i;
+  }
+}
+
+bool launch_stable_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, const void* pos,
+                         bool f64, int* out, hipStream_t st) {
+  const bool ok = bp.mode == BIN_TILES || (bp.mode == BIN_RANGES && bp.levels == 1);
+  if (!ok) return false;
+  const long long* off = (bp.mode == BIN_TILES) ? b.start : b.kstart;
+  const size_t lds = (size_t)bp.nkeys * sizeof(uint32_t);
+  const int nk = (int)bp.nkeys;
+  // at most 16384 keys, as for the histogram pass (never under stream capture:
+  // called when an optimiser call fixes its order)
+  if (f64)
+    hipFuncSetAttribute((const void*)bin_stable_kernel<double>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 16384 * 4);
+  else
+    hipFuncSetAttribute((const void*)bin_stable_kernel<float>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 16384 * 4);
+  if (f64)
+    bin_stable_kernel<double><<<bp.nblk, 1024, lds, st>>>(g, (const double*)pos, bp.chunk,
+                                                         bp.nblk, nk, bp.kdiv, b.H, off, out);
+  else
+    bin_stable_kernel<float><<<bp.nblk, 1024, lds, st>>>(g, (const float*)pos, bp.chunk,
+                                                        bp.nblk, nk, bp.kdiv, b.H, off, out);
+  return true;
 }
 
 void launch_sorted_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, int* out,

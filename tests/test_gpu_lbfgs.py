@@ -97,6 +97,37 @@ def test_lbfgs_graph_eager_resume_bitwise(gpu):
     b.close()
 
 
+@pytest.mark.parametrize("d,N,L,M,ranges", [(3, 8000, 20.0, 8, None), (2, 8000, 90.0, 20, "5")])
+def test_lbfgs_fp64_reproducible(gpu, d, N, L, M, ranges):
+    """The internal order is a stable sort by tile (or range of tiles): two
+    contexts give the same FP64 trajectory bit for bit (every dot product is
+    summed over the same order)."""
+    import os
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    pos0 = I.positions(N, d, L, np.float64, seed=73)
+    w, s0 = I.stealthy_target(d, M, float(M))
+    out = []
+    for _ in range(2):
+        if ranges:
+            os.environ["FRESCO_BIN_RANGES"] = ranges
+        try:
+            ctx = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-12, dtype="f64", device=gpu,
+                            stream=torch.cuda.Stream(device=gpu))
+        finally:
+            os.environ.pop("FRESCO_BIN_RANGES", None)
+        if ranges:
+            assert ctx.plan_info()["bin_ranges"] > 0
+        p = torch.from_numpy(pos0.copy()).to(gpu)
+        loss, nev = ctx.step(p, 10)
+        torch.cuda.synchronize()
+        out.append((loss, nev, p.cpu().numpy()))
+        ctx.close()
+    assert out[0][0] == out[1][0]
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
+
+
 def test_lbfgs_options_rejected(gpu):
     import torch
     from paper_2305_15693_amd import fresco as F

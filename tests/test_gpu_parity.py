@@ -314,20 +314,23 @@ def test_range_binning_path(gpu, dtype, d, N, L, M, tol, ranges, levels, bar):
     two.close()
 
 
-@pytest.mark.parametrize("d,N,L,M", [(2, 20000, 141.4, 40), (3, 4096, 16.0, 8)])
-def test_fold_in_row_pass_matches_fold_kernel(gpu, d, N, L, M):
+@pytest.mark.parametrize("dtype,tol,d,N,L,M", [("f32", 1e-6, 2, 20000, 141.4, 40),
+                                                ("f32", 1e-6, 3, 4096, 16.0, 8),
+                                                ("f64", 1e-12, 2, 5000, 70.7, 37),
+                                                ("f64", 1e-12, 3, 3000, 14.4, 11)])
+def test_fold_in_row_pass_matches_fold_kernel(gpu, dtype, tol, d, N, L, M):
     # the fold done inside the forward row pass sums each cell's covering tiles
     # in the same order as the stand-alone fold kernel: identical results
     import os
     import torch
-    pos = I.positions(N, d, L, np.float32, seed=91)
+    pos = I.positions(N, d, L, np.float32 if dtype == "f32" else np.float64, seed=91)
     w, s0 = I.stealthy_target(d, M, M)
     tpos = torch.from_numpy(pos).to(gpu)
     out = []
     for fold in ("1", "0"):
         os.environ["FRESCO_FOLD"] = fold
         try:
-            ctx = make_ctx(gpu, d, N, L, M, w, s0, 1e-6, "f32")
+            ctx = make_ctx(gpu, d, N, L, M, w, s0, tol, dtype)
         finally:
             os.environ.pop("FRESCO_FOLD", None)
         S = ctx.structure_factor(tpos).cpu().numpy()
