@@ -93,6 +93,10 @@ def test_lbfgs_graph_eager_resume_bitwise(gpu):
     assert la == lb2
     assert torch.equal(pa, pb)
     assert na == nb1 + nb2 - 1  # the second call re-evaluates its starting point
+    # the loss the update summed from the evaluation's partials is the one a
+    # plain evaluation at the returned positions gives (same partials, same order)
+    lc, _ = a.loss_grad(pa)
+    assert lc == la
     a.close()
     b.close()
 
