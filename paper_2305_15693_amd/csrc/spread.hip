@@ -827,8 +827,19 @@ inline int interp_row_stride(const Geom& g, bool f32) {
   return f32 ? (g.Ei[0] + 3) / 4 * 4 : g.Ei[0];
 }
 
+// Minimum waves per SIMD asked of the register allocator: 5 for the FP32 3D
+// kernels up to width 7 (width 7: 92 registers, no spill, against 105 at 4
+// waves; the 3D interpolation ran 885 -> 809 us); the compiler's own choice
+// elsewhere (the 2D and FP64 kernels spill under the same limit, and unrolling
+// the 2D row loop less to free registers measured slower).
 template <class R, int D, int W>
-__global__ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
+constexpr int interp_min_waves() {
+  return (sizeof(R) == 4 && D == 3 && W <= 7) ? 5 : 1;
+}
+
+template <class R, int D, int W>
+__global__ __attribute__((amdgpu_waves_per_eu(interp_min_waves<R, D, W>())))
+void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, const int* __restrict__ perm,
                               const R* __restrict__ v, R* __restrict__ grad) {
   constexpr int WI = W + 1;
