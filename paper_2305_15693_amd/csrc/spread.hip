@@ -827,18 +827,28 @@ inline int interp_row_stride(const Geom& g, bool f32) {
   return f32 ? (g.Ei[0] + 3) / 4 * 4 : g.Ei[0];
 }
 
-// Minimum waves per SIMD asked of the register allocator: 5 for the FP32 3D
-// kernels up to width 7 (width 7: 92 registers, no spill, against 105 at 4
-// waves; the 3D interpolation ran 885 -> 809 us); the compiler's own choice
-// elsewhere (the 2D and FP64 kernels spill under the same limit, and unrolling
-// the 2D row loop less to free registers measured slower).
+// Register budget of the interpolation (workgroups of at most 512 threads, so
+// up to 256 registers): FP32 kernels up to width 7 keep the occupancy they
+// were tuned at, 4 waves per SIMD in 2D (128 registers) and 5 in 3D (92
+// registers, no spill, against 105 at 4 waves: 3D interpolation 885 -> 809
+// us; a 2D limit of 5 or more spills, and unrolling the 2D row loop less to
+// free registers measured slower); wider and FP64 kernels take the registers
+// they need instead of spilling under the 128 of a 1024-thread bound.
 template <class R, int D, int W>
 constexpr int interp_min_waves() {
-  return (sizeof(R) == 4 && D == 3 && W <= 7) ? 5 : 1;
+  return (sizeof(R) == 4 && W <= 7) ? (D == 3 ? (W == 7 ? 5 : 1) : 4) : 1;
+}
+// footprint rows per unrolled step: all of them for FP32 up to width 8 (every
+// row's LDS words in flight together); two for wider or FP64 footprints, whose
+// hoisted rows would not fit in the registers
+template <class R, int W>
+constexpr int interp_row_unroll() {
+  return (sizeof(R) == 4 && W <= 8) ? W + 1 : 2;
 }
 
 template <class R, int D, int W>
-__global__ __attribute__((amdgpu_waves_per_eu(interp_min_waves<R, D, W>())))
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(interp_min_waves<R, D, W>())))
 void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, const int* __restrict__ perm,
                               const R* __restrict__ v, R* __restrict__ grad) {
@@ -893,6 +903,7 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const bool pair_store = ((uintptr_t)grad & (2 * sizeof(R) - 1)) == 0;
   for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
     const Rec<R> p = rec[j];
+    const int q = perm[j];
     R f0[WI], d0[WI], f1[WI], d1[WI], f2[WI], d2[WI];
     int l[3];
     const int cl[3] = {(int)(p.cell & 0xff), (int)((p.cell >> 8) & 0xff),
@@ -930,7 +941,7 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
     const int zmax = (D == 3) ? WI : 1;
     for (int dz = 0; dz < zmax; ++dz) {
       R sxy = R(0), sdxy = R(0), sxdy = R(0);
-#pragma unroll
+#pragma unroll(interp_row_unroll<R, W>())
       for (int dy = 0; dy < WI; ++dy) {
         const R* row = sub + ((D == 3 ? (l[2] + dz) * E1 : 0) + (l[1] + dy)) * E0s + xb;
         R sx = R(0), sdx = R(0);
@@ -969,13 +980,13 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
         gy = sxdy;
       }
     }
-    const long long o = (long long)perm[j] * D;
+    const long long o = (long long)q * D;
     if (D == 2 && pair_store) {
       using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
       V2 w2;
       w2.x = gx * gs[0];
       w2.y = gy * gs[1];
-      reinterpret_cast<V2*>(grad)[perm[j]] = w2;
+      reinterpret_cast<V2*>(grad)[q] = w2;
     } else {
       grad[o] = gx * gs[0];
       grad[o + 1] = gy * gs[1];
