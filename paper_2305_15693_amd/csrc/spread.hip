@@ -650,7 +650,6 @@ __device__ __forceinline__ void add_row_pairs(uint32_t* acc, int rb, const uint3
   add_pairs<W>(p, par, q, std::make_integer_sequence<int, (W + 2) / 2>{});
 }
 
-constexpr int kCovTmp = 32 * 48;  // T <= 32 along the last two axes, w <= 16
 
 template <class R, int D, int W>
 __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
@@ -673,12 +672,13 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
   // counted per column over the last two axes (2D: exactly per start cell), and
   // the largest w x w box sum of those counts bounds every cell's contributors.
   __shared__ uint32_t smax[16];
-  __shared__ uint32_t cov_tmp[kCovTmp];
   uint32_t cov;
   {
     const int Ta = (D == 3) ? g.T[1] : g.T[0], Tb = (D == 3) ? g.T[2] : g.T[1];
-    const int Ea = Ta + W - 1, Eb = Tb + W - 1;
     uint32_t* cnt = acc32;  // Ta Tb <= ncell words, before the accumulator is cleared
+    // Tb (Ta + W - 1) >= Tb Ta words after the accumulator (spread_lds_bytes)
+    uint32_t* cov_tmp =
+        F32 ? acc32 + (ncell + 2) : reinterpret_cast<uint32_t*>(acc64 + (ncell + 2));
     for (int c = threadIdx.x; c < Ta * Tb; c += blockDim.x) cnt[c] = 0u;
     __syncthreads();
     // four cells loaded per thread before the first count
@@ -699,32 +699,38 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
       }
     }
     __syncthreads();
-    // separable box sum: along a into tmp[yb][ia], then along b
+    // largest box sum over windows of W x W count cells (W x all when the tile
+    // is narrower), separable: along a into tmp[yb][ia], then along b.  Only the
+    // windows inside the tile: one that leaves it holds a subset of one that
+    // does not, the counts being non-negative.  Four neighbouring windows per
+    // thread as a running sum (unsigned arithmetic: every partial sum is exact).
     uint32_t mx = 0;
-    if (Tb * Ea <= kCovTmp) {
-      for (int o = threadIdx.x; o < Tb * Ea; o += blockDim.x) {
-        const int yb = o / Ea, ia = o - (o / Ea) * Ea;
+    {
+      const int wa = W < Ta ? W : Ta, wb = W < Tb ? W : Tb;
+      const int na = Ta - wa + 1, nb = Tb - wb + 1;
+      const int na4 = (na + 3) / 4, nb4 = (nb + 3) / 4;
+      for (int o = threadIdx.x; o < Tb * na4; o += blockDim.x) {
+        const int yb = o / na4, i0 = (o - yb * na4) * 4;
+        const uint32_t* row = cnt + yb * Ta;
         uint32_t sum = 0;
-#pragma unroll
-        for (int ta = 0; ta < W; ++ta) {
-          const int ya = ia - ta;
-          if (ya >= 0 && ya < Ta) sum += cnt[yb * Ta + ya];
+        for (int k = 0; k < wa; ++k) sum += row[i0 + k];
+        cov_tmp[yb * na + i0] = sum;
+        for (int u = 1; u < 4 && i0 + u < na; ++u) {
+          sum += row[i0 + u + wa - 1] - row[i0 + u - 1];
+          cov_tmp[yb * na + i0 + u] = sum;
         }
-        cov_tmp[o] = sum;
       }
       __syncthreads();
-      for (int o = threadIdx.x; o < Ea * Eb; o += blockDim.x) {
-        const int ib = o / Ea, ia = o - (o / Ea) * Ea;
+      for (int o = threadIdx.x; o < nb4 * na; o += blockDim.x) {
+        const int jc = o / na, ia = o - jc * na, j0 = jc * 4;
         uint32_t sum = 0;
-#pragma unroll
-        for (int tb = 0; tb < W; ++tb) {
-          const int yb = ib - tb;
-          if (yb >= 0 && yb < Tb) sum += cov_tmp[yb * Ea + ia];
-        }
+        for (int k = 0; k < wb; ++k) sum += cov_tmp[(j0 + k) * na + ia];
         mx = sum > mx ? sum : mx;
+        for (int u = 1; u < 4 && j0 + u < nb; ++u) {
+          sum += cov_tmp[(j0 + u + wb - 1) * na + ia] - cov_tmp[(j0 + u - 1) * na + ia];
+          mx = sum > mx ? sum : mx;
+        }
       }
-    } else {
-      mx = (uint32_t)(e - s);  // every point of the tile
     }
     for (int off = 32; off > 0; off >>= 1) {
       const uint32_t o = (uint32_t)__shfl_down((int)mx, off, 64);
@@ -1015,10 +1021,13 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
     case 16: CALL(16); break;     \
   }
 
+// accumulator (ncell + 2 words), then the coverage bound's row sums (Tb Ea
+// 32-bit words over the last two axes)
 template <class R>
 size_t spread_lds_bytes(const Geom& g) {
   size_t ncell = (size_t)g.E[0] * g.E[1] * (g.d == 3 ? g.E[2] : 1);
-  return (ncell + 2) * (sizeof(R) == 4 ? 4 : 8);
+  const size_t Ta = (g.d == 3) ? g.T[1] : g.T[0], Tb = (g.d == 3) ? g.T[2] : g.T[1];
+  return (ncell + 2) * (sizeof(R) == 4 ? 4 : 8) + Tb * (Ta + g.w - 1) * 4;
 }
 template <class R>
 size_t interp_lds_bytes(const Geom& g) {

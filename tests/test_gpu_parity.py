@@ -120,6 +120,23 @@ def test_power_law_relative_weights(gpu):
     assert rel(grad, go) < 1e-5
 
 
+def test_dense_tiles_fixed_point_scale(gpu):
+    # 1e5 points on an 80^2 grid: about 25,000 per spreading tile.  The fixed-point
+    # scale comes from the coverage bound (here a few hundred contributors per
+    # cell), not from the tile's point count, so FP32 stays at its floor.
+    N, L = 100000, 400.0
+    M, K = 19, 20.0
+    pos = I.positions(N, 2, L, np.float32, seed=79)
+    w, s0 = I.power_law_target(2, M, K, 1.5)
+    S, loss, grad = run_case(gpu, pos, L, M, w, s0, 1e-6, "f32", relative=True)
+    So, lo, go = oracle_case(pos, L, M, w, s0, relative=True)
+    # S and the loss at half the FP32 bar (a scale from the point count put the
+    # loss at 8e-6), the gradient at the FP32 bar
+    assert rel(S, So) < 5e-6
+    assert abs(loss - lo) / lo < 5e-6
+    assert rel(grad, go) < 1e-5
+
+
 def test_wrapping_and_tiny_inputs(gpu):
     # positions outside [0, L) are wrapped (exp(i k.r) is L-periodic); N = 1 and 2
     rng = np.random.default_rng(3)
