@@ -874,30 +874,51 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const int o0 = t[0] * g.T[0] - 1 + g.nf[0];
   const int o1 = t[1] * g.T[1] - 1 + g.nf[1];
   const int o2 = (D == 3) ? t[2] * g.T[2] - 1 + g.nf[2] : 0;
-  // four loads in flight per thread before the LDS stores; row padding and the
-  // kInterpTail cells past the end (read by the last row's words) are zero
-  for (int cb = threadIdx.x; cb < ncell + kInterpTail; cb += 4 * blockDim.x) {
-    R val[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = cb + u * (int)blockDim.x;
-      const int c0 = c % E0s;
-      val[u] = R(0);
-      if (c < ncell && c0 < E0) {
-        const int r = c / E0s;
-        const int c1 = r % E1;
-        const int c2 = r / E1;
-        int x = o0 + c0, y = o1 + c1, z = o2 + c2;
-        while (x >= g.nf[0]) x -= g.nf[0];
-        while (y >= g.nf[1]) y -= g.nf[1];
-        while (z >= g.nf[2]) z -= g.nf[2];
-        val[u] = v[((long long)z * g.nf[1] + y) * g.nf[0] + x];
-      }
+  // the field over the tile, KB loads in flight per thread before the LDS
+  // stores; row padding and the kInterpTail cells past the end (read by the last
+  // row's words) are zero.  Cell c = (c2 E1 + c1) E0s + c0: one division per
+  // thread, then the coordinates step by the block size.
+  {
+    constexpr int KB = 12;
+    const int bd = (int)blockDim.x;
+    const int total = ncell + kInterpTail;
+    const int dr = bd / E0s, dc = bd - dr * E0s;
+    int c0 = (int)threadIdx.x % E0s;
+    int c1 = (int)threadIdx.x / E0s;
+    int c2 = 0;
+    while (c1 >= E1) {
+      c1 -= E1;
+      ++c2;
     }
+    for (int cb = threadIdx.x; cb < total; cb += KB * bd) {
+      R val[KB];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int c = cb + u * (int)blockDim.x;
-      if (c < ncell + kInterpTail) sub[c] = val[u];
+      for (int u = 0; u < KB; ++u) {
+        const int c = cb + u * bd;
+        val[u] = R(0);
+        if (c < ncell && c0 < E0) {
+          int x = o0 + c0, y = o1 + c1, z = o2 + c2;
+          while (x >= g.nf[0]) x -= g.nf[0];
+          while (y >= g.nf[1]) y -= g.nf[1];
+          while (z >= g.nf[2]) z -= g.nf[2];
+          val[u] = v[((long long)z * g.nf[1] + y) * g.nf[0] + x];
+        }
+        c0 += dc;
+        c1 += dr;
+        if (c0 >= E0s) {
+          c0 -= E0s;
+          ++c1;
+        }
+        while (c1 >= E1) {
+          c1 -= E1;
+          ++c2;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int c = cb + u * bd;
+        if (c < total) sub[c] = val[u];
+      }
     }
   }
   __syncthreads();
