@@ -832,6 +832,15 @@ constexpr int kInterpTail = 8;
 inline int interp_row_stride(const Geom& g, bool f32) {
   return f32 ? (g.Ei[0] + 3) / 4 * 4 : g.Ei[0];
 }
+// FP32 2D with a footprint of a multiple of 4 cells: the field tile is held four
+// times in LDS, copy s shifted right by s cells (rows of interp_copy_stride
+// words), so that every point reads its footprint rows as whole aligned 16-byte
+// words of the copy s = -l0 mod 4, with its own weights, unshifted
+template <class R, int D, int WI>
+constexpr bool interp_shift4() {
+  return sizeof(R) == 4 && D == 2 && WI % 4 == 0;
+}
+constexpr int interp_copy_stride(int Ei0) { return (Ei0 + 6) / 4 * 4; }
 
 // Register budget of the interpolation (workgroups of at most 512 threads, so
 // up to 256 registers): FP32 kernels up to width 7 keep the occupancy they
@@ -867,6 +876,9 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const int E0 = g.Ei[0], E1 = g.Ei[1], E2 = (D == 3) ? g.Ei[2] : 1;
   const int E0s = F32 ? (E0 + 3) / 4 * 4 : E0;  // LDS row stride
   const int ncell = E0s * E1 * E2;
+  constexpr bool SH4 = interp_shift4<R, D, WI>();
+  const int Ec = interp_copy_stride(E0);  // row stride of the shifted copies
+  const int csz = Ec * E1;                // words per copy
   const long long s = start[bin], e = start[bin + 1];
   if (e == s) return;
   int t[3];
@@ -892,10 +904,12 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
     }
     for (int cb = threadIdx.x; cb < total; cb += KB * bd) {
       R val[KB];
+      int li[KB];  // shifted copies: index r Ec + x of the cell, or -1
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
         const int c = cb + u * bd;
         val[u] = R(0);
+        li[u] = (c < ncell && c0 < E0) ? (c2 * E1 + c1) * Ec + c0 : -1;
         if (c < ncell && c0 < E0) {
           int x = o0 + c0, y = o1 + c1, z = o2 + c2;
           while (x >= g.nf[0]) x -= g.nf[0];
@@ -914,10 +928,22 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
           ++c2;
         }
       }
+      if constexpr (SH4) {
+        // cell (row r, column x) to index r Ec + x + s of copy s, s = 0..3
 #pragma unroll
-      for (int u = 0; u < KB; ++u) {
-        const int c = cb + u * bd;
-        if (c < total) sub[c] = val[u];
+        for (int u = 0; u < KB; ++u) {
+          if (li[u] >= 0) {
+            R* d0p = sub + li[u];
+#pragma unroll
+            for (int sc = 0; sc < 4; ++sc) d0p[sc * csz + sc] = val[u];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+          const int c = cb + u * bd;
+          if (c < total) sub[c] = val[u];
+        }
       }
     }
   }
@@ -946,10 +972,13 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
       else if (a == 1) interp_weights<R, WI>(ti, beta, icb, f1, d1);
       else interp_weights<R, WI>(ti, beta, icb, f2, d2);
     }
-    // FP32: x weights shifted by the alignment offset of the first column
+    // FP32: x weights shifted by the alignment offset of the first column (or,
+    // with the shifted copies, the copy that aligns it)
     const int xb = F32 ? (l[0] & ~3) : l[0];
+    const int sc = (4 - (l[0] & 3)) & 3;
+    const R* sub4 = sub + sc * csz + l[0] + sc;
     R f0s[4 * NQ], d0s[4 * NQ];
-    if constexpr (F32) {
+    if constexpr (F32 && !SH4) {
       const int sh = l[0] & 3;
 #pragma unroll
       for (int k = 0; k < 4 * NQ; ++k) {
@@ -972,7 +1001,21 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
       for (int dy = 0; dy < WI; ++dy) {
         const R* row = sub + ((D == 3 ? (l[2] + dz) * E1 : 0) + (l[1] + dy)) * E0s + xb;
         R sx = R(0), sdx = R(0);
-        if constexpr (F32) {
+        if constexpr (SH4) {
+          const float4* q4 = reinterpret_cast<const float4*>(sub4 + (l[1] + dy) * Ec);
+#pragma unroll
+          for (int k4 = 0; k4 < WI / 4; ++k4) {
+            const float4 w4 = q4[k4];
+            sx += w4.x * f0[4 * k4];
+            sdx += w4.x * d0[4 * k4];
+            sx += w4.y * f0[4 * k4 + 1];
+            sdx += w4.y * d0[4 * k4 + 1];
+            sx += w4.z * f0[4 * k4 + 2];
+            sdx += w4.z * d0[4 * k4 + 2];
+            sx += w4.w * f0[4 * k4 + 3];
+            sdx += w4.w * d0[4 * k4 + 3];
+          }
+        } else if constexpr (F32) {
           const float4* q4 = reinterpret_cast<const float4*>(row);
 #pragma unroll
           for (int k4 = 0; k4 < NQ; ++k4) {
@@ -1052,6 +1095,8 @@ size_t spread_lds_bytes(const Geom& g) {
 }
 template <class R>
 size_t interp_lds_bytes(const Geom& g) {
+  if (sizeof(R) == 4 && g.d == 2 && g.wi % 4 == 0)  // four shifted copies
+    return (size_t)4 * interp_copy_stride(g.Ei[0]) * g.Ei[1] * sizeof(R);
   // rows padded in FP32, plus the cells past the end
   return ((size_t)interp_row_stride(g, sizeof(R) == 4) * g.Ei[1] * (g.d == 3 ? g.Ei[2] : 1) +
           kInterpTail) *
