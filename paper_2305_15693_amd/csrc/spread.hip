@@ -832,15 +832,19 @@ constexpr int kInterpTail = 8;
 inline int interp_row_stride(const Geom& g, bool f32) {
   return f32 ? (g.Ei[0] + 3) / 4 * 4 : g.Ei[0];
 }
-// FP32 2D with a footprint of a multiple of 4 cells: the field tile is held four
-// times in LDS, copy s shifted right by s cells (rows of interp_copy_stride
-// words), so that every point reads its footprint rows as whole aligned 16-byte
-// words of the copy s = -l0 mod 4, with its own weights, unshifted
+// FP32 2D: the field tile is held four times in LDS, copy s shifted right by s
+// cells (rows of interp_copy_stride words), so that every point reads its
+// footprint rows as whole aligned 16-byte words of the copy s = -l0 mod 4, with
+// its own weights, unshifted (footprints that are not a multiple of 4 cells read
+// zero-filled cells past their end with weight 0)
 template <class R, int D, int WI>
 constexpr bool interp_shift4() {
-  return sizeof(R) == 4 && D == 2 && WI % 4 == 0;
+  return sizeof(R) == 4 && D == 2;
 }
-constexpr int interp_copy_stride(int Ei0) { return (Ei0 + 6) / 4 * 4; }
+// a row read spans cells l0 + s .. l0 + s + 4 ceil(WI / 4) - 1, l0 <= Ei0 - WI
+constexpr int interp_copy_stride(int Ei0, int WI) {
+  return (Ei0 - WI + (WI + 3) / 4 * 4 + 6) / 4 * 4;
+}
 
 // Register budget of the interpolation (workgroups of at most 512 threads, so
 // up to 256 registers): FP32 kernels up to width 7 keep the occupancy they
@@ -877,7 +881,7 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const int E0s = F32 ? (E0 + 3) / 4 * 4 : E0;  // LDS row stride
   const int ncell = E0s * E1 * E2;
   constexpr bool SH4 = interp_shift4<R, D, WI>();
-  const int Ec = interp_copy_stride(E0);  // row stride of the shifted copies
+  const int Ec = interp_copy_stride(E0, WI);  // row stride of the shifted copies
   const int csz = Ec * E1;                // words per copy
   const long long s = start[bin], e = start[bin + 1];
   if (e == s) return;
@@ -890,6 +894,12 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   // stores; row padding and the kInterpTail cells past the end (read by the last
   // row's words) are zero.  Cell c = (c2 E1 + c1) E0s + c0: one division per
   // thread, then the coordinates step by the block size.
+  if constexpr (SH4 && WI % 4 != 0) {
+    // cells the copies do not receive read as zero
+    float4* z4 = reinterpret_cast<float4*>(sub);
+    for (int i = threadIdx.x; i < csz; i += blockDim.x) z4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+  }
   {
     constexpr int KB = 12;
     const int bd = (int)blockDim.x;
@@ -1003,17 +1013,17 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
         R sx = R(0), sdx = R(0);
         if constexpr (SH4) {
           const float4* q4 = reinterpret_cast<const float4*>(sub4 + (l[1] + dy) * Ec);
+          constexpr int NQ4 = (WI + 3) / 4;
 #pragma unroll
-          for (int k4 = 0; k4 < WI / 4; ++k4) {
+          for (int k4 = 0; k4 < NQ4; ++k4) {
             const float4 w4 = q4[k4];
-            sx += w4.x * f0[4 * k4];
-            sdx += w4.x * d0[4 * k4];
-            sx += w4.y * f0[4 * k4 + 1];
-            sdx += w4.y * d0[4 * k4 + 1];
-            sx += w4.z * f0[4 * k4 + 2];
-            sdx += w4.z * d0[4 * k4 + 2];
-            sx += w4.w * f0[4 * k4 + 3];
-            sdx += w4.w * d0[4 * k4 + 3];
+            const float v4[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int k = 4 * k4 + i;
+              sx += v4[i] * (k < WI ? f0[k < WI ? k : 0] : R(0));
+              sdx += v4[i] * (k < WI ? d0[k < WI ? k : 0] : R(0));
+            }
           }
         } else if constexpr (F32) {
           const float4* q4 = reinterpret_cast<const float4*>(row);
@@ -1095,8 +1105,8 @@ size_t spread_lds_bytes(const Geom& g) {
 }
 template <class R>
 size_t interp_lds_bytes(const Geom& g) {
-  if (sizeof(R) == 4 && g.d == 2 && g.wi % 4 == 0)  // four shifted copies
-    return (size_t)4 * interp_copy_stride(g.Ei[0]) * g.Ei[1] * sizeof(R);
+  if (sizeof(R) == 4 && g.d == 2)  // four shifted copies
+    return (size_t)4 * interp_copy_stride(g.Ei[0], g.wi) * g.Ei[1] * sizeof(R);
   // rows padded in FP32, plus the cells past the end
   return ((size_t)interp_row_stride(g, sizeof(R) == 4) * g.Ei[1] * (g.d == 3 ? g.Ei[2] : 1) +
           kInterpTail) *

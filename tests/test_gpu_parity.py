@@ -57,6 +57,7 @@ CASES = [
     ("3d_f32_n30000_m12", 3, 30000, 31.0, 12, 12.0, 1e-6, "f32", 1e-5),
     ("3d_f64_n3000_m6", 3, 3000, 14.4, 6, 6.0, 1e-12, "f64", 1e-11),
     ("2d_f32_n5000_m20_tol1e-5", 2, 5000, 70.7, 20, 20.0, 1e-5, "f32", 1e-4),
+    ("2d_f32_n8000_m30_tol1e-3", 2, 8000, 100.0, 30, 30.0, 1e-3, "f32", 1e-2),
 ]
 
 
