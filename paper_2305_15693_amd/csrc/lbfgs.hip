@@ -122,53 +122,59 @@ __global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part,
   __shared__ int cs[kLbfgsMaxM];
   static_assert(sizeof(LbfgsState) % 4 == 0, "state copied as 32-bit words");
   constexpr int kWords = (int)(sizeof(LbfgsState) / 4);
+  const int m = o.m;
+  // value c is reduced by wave c mod (waves): lane l sums the partials l,
+  // l + 64, ... (nb <= 1024: at most 16).  With at most three values per wave
+  // their loads are issued before the state copy, so that both wait on one
+  // memory round (they are used only when the decision accepts)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (int)(blockDim.x >> 6);
+  constexpr int kU = kLbfgsMaxBlocks / 64;
+  const bool fast = 4 * m + 1 <= 3 * nw;
+  double v[3][kU];
+  if (fast) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int c = wave + r * nw;
+      const double* pc = part + (long long)c * nb;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int b = lane + 64 * u;
+        v[r][u] = (c < 4 * m + 1 && b < nb) ? pc[b] : 0.0;
+      }
+    }
+  }
   for (int i = threadIdx.x; i < kWords; i += blockDim.x)
     reinterpret_cast<uint32_t*>(&sh)[i] = reinterpret_cast<const uint32_t*>(Sg)[i];
+  if (fast) {
+    // reduced whatever the decision (a rejection or restart does not read them)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int c = wave + r * nw;
+      double t = 0.0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) t += v[r][u];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+      if (lane == 0 && c < 4 * m + 1) red[c] = t;
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0) lb_decide(&sh, o);
   __syncthreads();
   const int step = sh.step;
-  const int m = o.m;
   if (step == LB_ACCEPT || step == LB_INIT) {
-    // value c is reduced by wave c mod (waves): lane l sums the partials l,
-    // l + 64, ... (nb <= 1024: at most 16, all loads issued before the first add)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nw = (int)(blockDim.x >> 6);
-    constexpr int kU = kLbfgsMaxBlocks / 64;
-    if (4 * m + 1 <= 3 * nw) {
-      // at most three values per wave: all of their loads issued together
-      double v[3][kU];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const int c = wave + r * nw;
-        const double* pc = part + (long long)c * nb;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int b = lane + 64 * u;
-          v[r][u] = (c < 4 * m + 1 && b < nb) ? pc[b] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const int c = wave + r * nw;
-        double t = 0.0;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) t += v[r][u];
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
-        if (lane == 0 && c < 4 * m + 1) red[c] = t;
-      }
-    } else {
+    if (!fast) {
       for (int c = wave; c < 4 * m + 1; c += nw) {
         const double* pc = part + (long long)c * nb;
-        double v[kU];
+        double w[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int b = lane + 64 * u;
-          v[u] = (b < nb) ? pc[b] : 0.0;
+          w[u] = (b < nb) ? pc[b] : 0.0;
         }
         double t = 0.0;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) t += v[u];
+        for (int u = 0; u < kU; ++u) t += w[u];
         for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
         if (lane == 0) red[c] = t;
       }
