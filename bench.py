@@ -41,6 +41,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loss+grad evals/sec (N=1e6 2D, N=1e7 3D) + spread/interp HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
+DOM_REPS = 30  # launches of the dominant spread / interp kernel per timing bracket
 
 
 def stage_bytes(cfg, info, dtype_bytes):
@@ -209,8 +210,11 @@ def measure(name, steps, warmup, dev, lbfgs_steps):
     ms_plain = e0.elapsed_time(e1)
     loss0 = float(loss_dev.item())
 
-    # the dominant kernel, event-timed on the library's stream over as many evaluations
-    ctx.set_timing([dominant])
+    # the dominant kernel, event-timed on the library's stream over as many
+    # evaluations; the spread and interp kernels run DOM_REPS times back to back
+    # inside each bracket, so that the time per launch is the kernel's own rather
+    # than the bracket's launch overhead (it agrees with the kernel trace)
+    ctx.set_timing([dominant], reps=DOM_REPS if dominant in ("spread", "interp") else 1)
     for _ in range(steps):
         ctx.loss_grad_async(pos, loss_dev, grad)
     dom = ctx.read_timing(reset=True)[dominant]
@@ -507,6 +511,7 @@ def main():
         "config": {"workload": args.workload, "d": cfg["d"], "N": cfg["N"], "L": cfg["L"],
                    "kmax": cfg["M"], "k_cut": cfg["kcut"], "n_constrained": info["n_constrained"],
                    "tol": cfg["tol"], "nf": info["nf"], "width": info["width"],
+                   "tiles": info["nbins"],
                    "step": ("one loss + gradient evaluation" if args.plain else
                             "one L-BFGS iteration (line-search evaluations + update)"),
                    "lbfgs_evals": r.get("lbfgs_evals"), "loss_start": r["loss0"],

@@ -303,11 +303,20 @@ enum fresco_stage {
  * Errors: EINVAL. */
 int fresco_set_timing(fresco_ctx* ctx, uint32_t stage_mask);
 
+/* Diagnostics: with timing on, the spreading and interpolation stages launch
+ * their kernels `reps` times back to back between their events (those kernels
+ * read only their inputs and write all of their outputs, so the results are
+ * unchanged), which brings the timed duration per launch close to the kernel's
+ * own by spreading the launch overhead of the brackets.  Default 1.
+ * Errors: EINVAL (reps outside 1..1000). */
+int fresco_set_timing_reps(fresco_ctx* ctx, int32_t reps);
+
 /* Synchronise the stream, add the durations of all bracketed launches since the
  * last read to the running totals and return them: ms_total[s] is the summed
- * duration in milliseconds and launches[s] the number of timed evaluations of
- * stage s (arrays of FRESCO_STAGE_COUNT entries; either may be NULL).  reset != 0
- * clears the totals after copying.  Errors: EINVAL, EHIP. */
+ * duration in milliseconds and launches[s] the number of timed launches of
+ * stage s (evaluations times the stage's repetitions; arrays of
+ * FRESCO_STAGE_COUNT entries; either may be NULL).  reset != 0 clears the
+ * totals after copying.  Errors: EINVAL, EHIP. */
 int fresco_read_timing(fresco_ctx* ctx, double* ms_total, int64_t* launches, int reset);
 
 /* Describe a status code (static string). */

@@ -120,8 +120,10 @@ struct fresco_ctx {
   double pair_w = 0.0;
   // per-stage timing (diagnostics): event pairs recorded on the stream
   uint32_t timing_mask = 0;
+  int timing_reps = 1;  // launches per timed spreading / interpolation stage
   std::vector<hipEvent_t> event_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[FRESCO_STAGE_COUNT];
+  std::vector<int> pending_reps[FRESCO_STAGE_COUNT];
   double stage_ms[FRESCO_STAGE_COUNT] = {};
   long long stage_n[FRESCO_STAGE_COUNT] = {};
 };
@@ -140,21 +142,27 @@ hipEvent_t take_event(fresco_ctx* c) {
 }
 
 // Brackets the launches of one stage with events when its timing bit is set.
+// reps: how many times the bracketed launches run (the timing repetitions of
+// the spreading and interpolation stages, whose kernels only read their inputs
+// and write their outputs; 1 otherwise and when the stage is not timed)
 struct StageTimer {
   fresco_ctx* c;
   int s;
+  int reps = 1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   StageTimer(fresco_ctx* c_, int s_) : c(c_), s(s_) {
     if (c->timing_mask & (1u << s)) {
       e0 = take_event(c);
       e1 = take_event(c);
       if (e0 && e1) (void)hipEventRecord(e0, c->st);
+      if (e0 && e1 && (s == FRESCO_STAGE_SPREAD || s == FRESCO_STAGE_INTERP)) reps = c->timing_reps;
     }
   }
   ~StageTimer() {
     if (e0 && e1) {
       (void)hipEventRecord(e1, c->st);
       c->pending[s].push_back({e0, e1});
+      c->pending_reps[s].push_back(reps);
     } else {
       if (e0) c->event_pool.push_back(e0);
       if (e1) c->event_pool.push_back(e1);
@@ -699,7 +707,8 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
   }
   {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
-    launch_spread<R>(g,(const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
+    for (int r = 0; r < t.reps; ++r)
+      launch_spread<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
   }
   if (!S->fold_fused) {
     StageTimer t(c, FRESCO_STAGE_FOLD);
@@ -811,7 +820,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
   }
   {
     StageTimer t(c, FRESCO_STAGE_INTERP);
-    launch_interp<R>(g, S->bp, S->bb, S->v, grad, st);
+    for (int r = 0; r < t.reps; ++r) launch_interp<R>(g, S->bp, S->bb, S->v, grad, st);
   }
   // attached soft-core pair term: its gradient is added to grad, its energy to
   // the loss
@@ -1262,19 +1271,27 @@ int fresco_set_timing(fresco_ctx* c, uint32_t mask) {
   return FRESCO_OK;
 }
 
+int fresco_set_timing_reps(fresco_ctx* c, int32_t reps) {
+  if (!c || reps < 1 || reps > 1000) return FRESCO_EINVAL;
+  c->timing_reps = reps;
+  return FRESCO_OK;
+}
+
 int fresco_read_timing(fresco_ctx* c, double* ms_total, int64_t* launches, int reset) {
   if (!c) return FRESCO_EINVAL;
   HIPCHK(hipStreamSynchronize(c->st));
   for (int s = 0; s < FRESCO_STAGE_COUNT; ++s) {
-    for (auto& pr : c->pending[s]) {
+    for (size_t i = 0; i < c->pending[s].size(); ++i) {
+      auto& pr = c->pending[s][i];
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
       c->stage_ms[s] += ms;
-      c->stage_n[s] += 1;
+      c->stage_n[s] += c->pending_reps[s][i];
       c->event_pool.push_back(pr.first);
       c->event_pool.push_back(pr.second);
     }
     c->pending[s].clear();
+    c->pending_reps[s].clear();
     if (ms_total) ms_total[s] = c->stage_ms[s];
     if (launches) launches[s] = c->stage_n[s];
     if (reset) {

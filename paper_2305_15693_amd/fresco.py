@@ -118,6 +118,8 @@ def _load():
     lib.fresco_reset_history.restype = i
     lib.fresco_set_timing.argtypes = [vp, ctypes.c_uint32]
     lib.fresco_set_timing.restype = i
+    lib.fresco_set_timing_reps.argtypes = [vp, ctypes.c_int32]
+    lib.fresco_set_timing_reps.restype = i
     lib.fresco_read_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64), i]
     lib.fresco_read_timing.restype = i
@@ -284,12 +286,14 @@ class Context:
     def reset_history(self):
         _check(_lib.fresco_reset_history(self._h), "fresco_reset_history")
 
-    def set_timing(self, stages):
-        """Bracket the named stages (see STAGES) with HIP events; [] turns it off."""
+    def set_timing(self, stages, reps: int = 1):
+        """Bracket the named stages (see STAGES) with HIP events; [] turns it off.
+        reps: launches of the spread and interp kernels per bracket (timing only)."""
         mask = 0
         for s in stages:
             mask |= 1 << STAGES.index(s)
         _check(_lib.fresco_set_timing(self._h, mask), "fresco_set_timing")
+        _check(_lib.fresco_set_timing_reps(self._h, int(reps)), "fresco_set_timing_reps")
 
     def read_timing(self, reset: bool = True) -> dict:
         """{stage: (total ms, timed evaluations)} since the last reset."""

@@ -417,3 +417,25 @@ def test_column_major_half_spectrum_matches_row_major(gpu):
         ctx.close()
     for a, b in zip(out[0], out[1]):
         assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_timing_repetitions_leave_results_unchanged(gpu):
+    # timed spread and interp stages launched several times back to back (the
+    # kernels only read their inputs and write all their outputs): same loss and
+    # gradient bit for bit, and every launch counted
+    import torch
+    d, N, L, M = 2, 20000, 141.4, 40
+    pos = torch.from_numpy(I.positions(N, d, L, np.float32, seed=97)).to(gpu)
+    w, s0 = I.stealthy_target(d, M, M)
+    ctx = make_ctx(gpu, d, N, L, M, w, s0, 1e-6, "f32")
+    l1, g1 = ctx.loss_grad(pos)
+    ctx.set_timing(["spread", "interp"], reps=4)
+    l2, g2 = ctx.loss_grad(pos)
+    t = ctx.read_timing(reset=True)
+    ctx.set_timing([])
+    l3, g3 = ctx.loss_grad(pos)
+    assert l1 == l2 == l3
+    assert torch.equal(g1, g2) and torch.equal(g1, g3)
+    assert t["spread"][1] == 4 and t["interp"][1] == 4
+    assert t["spread"][0] > 0 and t["interp"][0] > 0
+    ctx.close()
