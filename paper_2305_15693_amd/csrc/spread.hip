@@ -188,21 +188,38 @@ __global__ void bin_rowscan_kernel(uint32_t* __restrict__ H, int nblk, long long
   if (lane == 0) count[tile] = carry;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by index.  The range
+// passes give all 256-point blocks of one histogram chunk to one XCD (chunks
+// x, x + 8, ... to XCD x, each in order), so that the runs of consecutive slots a
+// chunk fills in every segment are written (or read) through one L2 and combine
+// there into whole lines.  Grid: 8 ceil(nblk / 8) bpc workgroups; returns the
+// point block of workgroup w and its chunk.
+__device__ __forceinline__ long long xcd_point_block(uint32_t w, uint32_t bpc, uint32_t* chunk) {
+  const uint32_t x = w & 7u, l = w >> 3;
+  const uint32_t gc = l / bpc, k = l - gc * bpc;
+  *chunk = gc * 8u + x;
+  return (long long)(*chunk) * bpc + k;
+}
+inline unsigned xcd_grid(int nblk, long long chunk) {
+  return (unsigned)(8ll * ((nblk + 7) / 8) * (chunk / 256));
+}
+
 // 256 threads per block; chunk is a multiple of 256, bpc = chunk / 256 blocks per
-// histogram chunk
+// histogram chunk, all on one XCD (xcd_point_block; grid xcd_grid(nblk, chunk))
 template <class R>
 __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, uint32_t bpc, int nblk,
                                    const uint32_t* __restrict__ kr,
                                    const uint32_t* __restrict__ H,
                                    const long long* __restrict__ start, Rec<R>* __restrict__ rec,
                                    int* __restrict__ perm) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.N) return;
+  uint32_t blk;
+  const long long q = xcd_point_block(blockIdx.x, bpc, &blk);
+  const long long i = q * 256 + threadIdx.x;
+  if (blk >= (uint32_t)nblk || i >= g.N) return;
   bool bad = false;
   PointBin pb = bin_point<R>(g, pos + i * g.d, &bad);
   const uint32_t v = kr[i];
   const uint32_t tile = v & 0xffffu, rank = v >> 16;
-  const uint32_t blk = blockIdx.x / bpc;
   const long long dst = start[tile] + H[(long long)tile * nblk + blk] + rank;
   Rec<R> o;
   o.t[0] = (R)pb.t[0];
@@ -222,21 +239,6 @@ __device__ __forceinline__ long long range_slot(uint32_t v, int shift, uint32_t 
   return kstart[key] + H[(long long)key * nblk + blk] + rank;
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin by index.  The range
-// passes give all 256-point blocks of one histogram chunk to one XCD (chunks
-// x, x + 8, ... to XCD x, each in order), so that the runs of consecutive slots a
-// chunk fills in every segment are written (or read) through one L2 and combine
-// there into whole lines.  Grid: 8 ceil(nblk / 8) bpc workgroups; returns the
-// point block of workgroup w and its chunk.
-__device__ __forceinline__ long long xcd_point_block(uint32_t w, uint32_t bpc, uint32_t* chunk) {
-  const uint32_t x = w & 7u, l = w >> 3;
-  const uint32_t gc = l / bpc, k = l - gc * bpc;
-  *chunk = gc * 8u + x;
-  return (long long)(*chunk) * bpc + k;
-}
-inline unsigned xcd_grid(int nblk, long long chunk) {
-  return (unsigned)(8ll * ((nblk + 7) / 8) * (chunk / 256));
-}
 
 // Range pass: copy each point's position into its range's segment (one store
 // per point: the writes are bound by their count, not their bytes).
@@ -580,11 +582,11 @@ void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, Bin
     if (bp.mode == BIN_TILES) {
       scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, g.nbins, b.start);
       if (f64)
-        bin_scatter_kernel<double><<<(unsigned)nblocks, 256, 0, st>>>(
+        bin_scatter_kernel<double><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
             g, (const double*)pos, bpc, bp.nblk, b.kr, b.H, b.start, (Rec<double>*)b.rec,
             b.perm);
       else
-        bin_scatter_kernel<float><<<(unsigned)nblocks, 256, 0, st>>>(
+        bin_scatter_kernel<float><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
             g, (const float*)pos, bpc, bp.nblk, b.kr, b.H, b.start, (Rec<float>*)b.rec,
             b.perm);
     } else {
