@@ -130,9 +130,15 @@ __global__ void bin_hist_kernel(Geom g, const R* __restrict__ pos, long long chu
                                 int nkeys, FastDiv kdiv, int shift, uint32_t* __restrict__ kr,
                                 uint32_t* __restrict__ H, int* __restrict__ flag) {
   extern __shared__ uint32_t hist[];
+  // consecutive chunks on one XCD (chunk x per + l for workgroup 8 l + x), so
+  // that the histogram entries of neighbouring chunks (one line of H holds 32)
+  // are written through one L2; grid 8 ceil(nblk / 8)
+  const int per = (nblk + 7) / 8;
+  const int blk = (int)(blockIdx.x & 7u) * per + (int)(blockIdx.x >> 3);
+  if (blk >= nblk) return;  // whole workgroup, before any barrier
   for (int i = threadIdx.x; i < nkeys; i += blockDim.x) hist[i] = 0;
   __syncthreads();
-  const long long i0 = (long long)blockIdx.x * chunk;
+  const long long i0 = (long long)blk * chunk;
   long long i1 = i0 + chunk;
   if (i1 > g.N) i1 = g.N;
   bool bad = false;
@@ -161,7 +167,7 @@ __global__ void bin_hist_kernel(Geom g, const R* __restrict__ pos, long long chu
   if (bad) atomicOr(flag, 1);
   __syncthreads();
   for (int b = threadIdx.x; b < nkeys; b += blockDim.x)
-    H[(long long)b * nblk + blockIdx.x] = hist[b];
+    H[(long long)b * nblk + blk] = hist[b];
 }
 
 // Per tile: exclusive scan of H[tile][0..nblk) in place; count[tile] = total.
@@ -544,7 +550,7 @@ void range_finish(const Geom& g, const BinPlan& bp, const R* src, BinBuffers& b,
 template <class R>
 void range_coarse(const Geom& g, const BinLevel& c, const R* pos, BinBuffers& b,
                   hipStream_t st) {
-  bin_hist_kernel<R><<<c.nblk, 1024, (size_t)c.nkeys * sizeof(uint32_t), st>>>(
+  bin_hist_kernel<R><<<8 * ((c.nblk + 7) / 8), 1024, (size_t)c.nkeys * sizeof(uint32_t), st>>>(
       g, pos, c.chunk, c.nblk, (int)c.nkeys, c.kdiv, c.shift, b.kr0, b.H0, b.flag);
   bin_rowscan_kernel<<<(unsigned)((c.nkeys + 3) / 4), 256, 0, st>>>(b.H0, c.nblk, c.nkeys,
                                                                      b.count0);
@@ -569,11 +575,11 @@ void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, Bin
     const size_t lds = (size_t)bp.nkeys * sizeof(uint32_t);
     const int nk = (int)bp.nkeys;
     if (f64)
-      bin_hist_kernel<double><<<bp.nblk, 1024, lds, st>>>(g, (const double*)src, bp.chunk,
+      bin_hist_kernel<double><<<8 * ((bp.nblk + 7) / 8), 1024, lds, st>>>(g, (const double*)src, bp.chunk,
                                                          bp.nblk, nk, bp.kdiv, bp.shift, b.kr,
                                                          b.H, b.flag);
     else
-      bin_hist_kernel<float><<<bp.nblk, 1024, lds, st>>>(g, (const float*)src, bp.chunk,
+      bin_hist_kernel<float><<<8 * ((bp.nblk + 7) / 8), 1024, lds, st>>>(g, (const float*)src, bp.chunk,
                                                         bp.nblk, nk, bp.kdiv, bp.shift, b.kr,
                                                         b.H, b.flag);
     bin_rowscan_kernel<<<(unsigned)((bp.nkeys + 3) / 4), 256, 0, st>>>(b.H, bp.nblk, bp.nkeys,
