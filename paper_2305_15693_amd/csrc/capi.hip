@@ -362,9 +362,12 @@ int create_state(fresco_ctx* c) {
     while ((1ll << shift) < nkeys) ++shift;
     if (tiles) shift = 16;
     const long long cmax = ((1ll << (32 - shift)) - 1) / 256 * 256;
+    // tiles: chunks of 4096 points, at most 256 of them (longer runs per tile
+    // for the scatter, a smaller count table; 3D 1e7 points: bin 422 -> 353 us
+    // against 1024 chunks)
     long long nblk = tiles ? N / 4096 : N / 65536;
     if (nblk < 1) nblk = 1;
-    if (nblk > (tiles ? 1024 : 2048)) nblk = (tiles ? 1024 : 2048);
+    if (nblk > (tiles ? 256 : 2048)) nblk = (tiles ? 256 : 2048);
     long long chunk = ((N + nblk - 1) / nblk + 255) / 256 * 256;
     if (chunk > cmax) chunk = cmax;
     nblk = (N + chunk - 1) / chunk;
