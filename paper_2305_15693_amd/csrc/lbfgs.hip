@@ -454,12 +454,13 @@ __global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
 }
 
 // ---------------------------------------------------------------- pass C
-// xt = x + alpha p, four elements of the thread in flight at once
+// xt = x + alpha p from element j of the thread on (stride: the grid), four
+// elements in flight at once
 template <class R>
 __device__ __forceinline__ void trial_point(const R* __restrict__ x, const R* __restrict__ p,
-                                            R* __restrict__ xt, long long n, R alpha) {
+                                            R* __restrict__ xt, long long n, R alpha,
+                                            long long j) {
   const long long st = (long long)gridDim.x * blockDim.x;
-  long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (; j + 3 * st < n; j += 4 * st) {
     R a[4], b[4];
 #pragma unroll
@@ -481,6 +482,17 @@ __global__ void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
   __shared__ double alpha_s;
   const int step = S->step;
   if (step == LB_IDLE) return;
+  // the thread's first four elements of x and p, loaded before the step length
+  // is known (their latency overlaps the reduction of the block maxima)
+  const long long st = (long long)gridDim.x * blockDim.x;
+  const long long j0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  R xa[4], pa[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const long long j = j0 + u * st;
+    xa[u] = (j < v.n) ? v.x[j] : R(0);
+    pa[u] = (j < v.n) ? v.p[j] : R(0);
+  }
   if (step == LB_REJECT) {
     if (threadIdx.x == 0) alpha_s = S->alpha;
   } else {
@@ -507,7 +519,13 @@ __global__ void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
     }
   }
   __syncthreads();
-  trial_point<R>(v.x, v.p, v.xt, v.n, (R)alpha_s);
+  const R alpha = (R)alpha_s;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const long long j = j0 + u * st;
+    if (j < v.n) v.xt[j] = xa[u] + alpha * pa[u];
+  }
+  trial_point<R>(v.x, v.p, v.xt, v.n, alpha, j0 + 4 * st);
 }
 
 // set the mode read by the next decision (host-driven transitions)
