@@ -59,6 +59,12 @@ def test_invalid_arguments_without_device():
         f = getattr(lib, fn)
         f.restype = ctypes.c_int
         assert f(None, None, None, None) == -1
+    lib.fresco_set_timing_reps.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.fresco_set_timing_reps.restype = ctypes.c_int
+    assert lib.fresco_set_timing_reps(None, 4) == -1
+    lib.fresco_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    lib.fresco_set_timing.restype = ctypes.c_int
+    assert lib.fresco_set_timing(None, 1) == -1
 
 
 def test_problem_validation_without_device():

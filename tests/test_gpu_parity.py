@@ -438,4 +438,7 @@ def test_timing_repetitions_leave_results_unchanged(gpu):
     assert torch.equal(g1, g2) and torch.equal(g1, g3)
     assert t["spread"][1] == 4 and t["interp"][1] == 4
     assert t["spread"][0] > 0 and t["interp"][0] > 0
+    with pytest.raises(Exception):
+        ctx.set_timing(["interp"], reps=0)
+    ctx.set_timing([])
     ctx.close()
