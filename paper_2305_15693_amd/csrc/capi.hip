@@ -255,7 +255,11 @@ bool shape_rows(int H, int rmin, long long nrows, size_t cs, int* lpb, int* thre
 bool shape_cols(int n, int rmin, long long ncols, size_t cs, int* bc, int* threads, bool* twl) {
   int b = 1;
   while (b * 2 <= 16 && (size_t)(b * 2) * n * cs <= 49152 && ncols / (b * 2) >= 512) b *= 2;
-  int t = 256;
+  // one column per workgroup (few, long columns: the 2D mode pass, 301 columns
+  // of 1250): 512 threads to start with, fewer butterflies per thread in every
+  // stage (22.5 -> 20.2 us); several columns: 256 (the 3D passes measured
+  // slower with 512)
+  int t = (b == 1) ? 512 : 256;
   for (;;) {
     int JT = t / b;
     int need = (n + rmin * JT - 1) / (rmin * JT);
