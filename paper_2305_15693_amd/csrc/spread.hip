@@ -1150,7 +1150,7 @@ template <class R>
 void launch_spread(const Geom& g, const Rec<R>* rec,
                    const long long* start, R* tiles, hipStream_t st) {
   const size_t lds = spread_lds_bytes<R>(g);
-  const int threads = (g.d == 3) ? 512 : 256;
+  const int threads = 512;  // (2D: 26.7 -> 23.5 us against 256)
 #define SP(W)                                                                                 \
   do {                                                                                        \
     if (g.d == 2)                                                                             \
