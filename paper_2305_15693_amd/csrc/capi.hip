@@ -651,7 +651,7 @@ int create_state(fresco_ctx* c) {
     HIPCHK(prepare_cols<R>(COL_BWD, c2, S->ax[2]));
   }
   HIPCHK(prepare_rows<R>(rp, S->ax[0]));
-  spread_prepare<R>(g);
+  HIPCHK(spread_prepare<R>(g));
   HIPCHK(hipGetLastError());
   if ((st = dalloc_t(c, &S->loss_part, S->nloss_part))) return st;
   return FRESCO_OK;

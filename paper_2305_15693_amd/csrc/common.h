@@ -178,7 +178,7 @@ size_t spread_lds_bytes(const Geom& g);
 template <class R>
 size_t interp_lds_bytes(const Geom& g);
 template <class R>
-void spread_prepare(const Geom& g);
+hipError_t spread_prepare(const Geom& g);
 template <class R>
 void launch_spread(const Geom& g, const Rec<R>* rec,
                    const long long* start, R* tiles, hipStream_t st);
@@ -193,7 +193,8 @@ void launch_sorted_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, 
                          hipStream_t st);
 // out[j] = caller index of slot j of a stable sort by the first-level key, after
 // launch_bin (histogram passes) at the same positions; false for plans without
-// first-level histograms of the caller's points (atomic sort, coarse pass)
+// first-level histograms of the caller's points (atomic sort, coarse pass) and
+// when the kernel's LDS limit cannot be raised
 bool launch_stable_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, const void* pos,
                          bool f64, int* out, hipStream_t st);
 template <class R>

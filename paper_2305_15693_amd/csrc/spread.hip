@@ -1121,29 +1121,30 @@ size_t interp_lds_bytes(const Geom& g) {
          sizeof(R);
 }
 
-// one-time kernel attributes (dynamic LDS above the default limit)
+// one-time kernel attributes (dynamic LDS above the default limit); returns
+// the first failure
 template <class R>
-void spread_prepare(const Geom& g) {
+hipError_t spread_prepare(const Geom& g) {
   const int sl = (int)spread_lds_bytes<R>(g), il = (int)interp_lds_bytes<R>(g);
-#define PREP(W)                                                                                  \
-  do {                                                                                           \
-    if (g.d == 2) {                                                                              \
-      hipFuncSetAttribute((const void*)spread_kernel<R, 2, W>,                                  \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, sl);                       \
-      hipFuncSetAttribute((const void*)interp_kernel<R, 2, W>,                                  \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, il);                       \
-    } else {                                                                                     \
-      hipFuncSetAttribute((const void*)spread_kernel<R, 3, W>,                                  \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, sl);                       \
-      hipFuncSetAttribute((const void*)interp_kernel<R, 3, W>,                                  \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, il);                       \
-    }                                                                                            \
+  hipError_t e = hipSuccess;
+  auto lds = [&e](const void* f, int bytes) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  };
+#define PREP(W)                                                 \
+  do {                                                          \
+    if (g.d == 2) {                                             \
+      lds((const void*)spread_kernel<R, 2, W>, sl);             \
+      lds((const void*)interp_kernel<R, 2, W>, il);             \
+    } else {                                                    \
+      lds((const void*)spread_kernel<R, 3, W>, sl);             \
+      lds((const void*)interp_kernel<R, 3, W>, il);             \
+    }                                                           \
   } while (0)
   FRESCO_W_SWITCH(g.w, PREP)
 #undef PREP
   // block-private histograms: at most 16384 keys
-  hipFuncSetAttribute((const void*)bin_hist_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      16384 * 4);
+  lds((const void*)bin_hist_kernel<R>, 16384 * 4);
+  return e;
 }
 
 template <class R>
@@ -1277,12 +1278,9 @@ bool launch_stable_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, 
   const int nk = (int)bp.nkeys;
   // at most 16384 keys, as for the histogram pass (never under stream capture:
   // called when an optimiser call fixes its order)
-  if (f64)
-    hipFuncSetAttribute((const void*)bin_stable_kernel<double>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 16384 * 4);
-  else
-    hipFuncSetAttribute((const void*)bin_stable_kernel<float>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 16384 * 4);
+  const void* fn = f64 ? (const void*)bin_stable_kernel<double> : (const void*)bin_stable_kernel<float>;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 16384 * 4) != hipSuccess)
+    return false;  // the caller takes the sorted-index path
   if (f64)
     bin_stable_kernel<double><<<bp.nblk, 1024, lds, st>>>(g, (const double*)pos, bp.chunk,
                                                          bp.nblk, nk, bp.kdiv, b.H, off, out);
@@ -1317,8 +1315,8 @@ template size_t spread_lds_bytes<float>(const Geom&);
 template size_t spread_lds_bytes<double>(const Geom&);
 template size_t interp_lds_bytes<float>(const Geom&);
 template size_t interp_lds_bytes<double>(const Geom&);
-template void spread_prepare<float>(const Geom&);
-template void spread_prepare<double>(const Geom&);
+template hipError_t spread_prepare<float>(const Geom&);
+template hipError_t spread_prepare<double>(const Geom&);
 template void launch_spread<float>(const Geom&, const Rec<float>*,
                                    const long long*, float*, hipStream_t);
 template void launch_spread<double>(const Geom&, const Rec<double>*,
