@@ -16,15 +16,36 @@ rho_i = 1 / y_i.s_i,
   q *= gamma = s.y / y.y (newest pair)
   for i oldest..newest: b = rho_i y_i.q;  q += (a_i - b) s_i
   p = -q.
+The recursion is written out in two_loop(), which run() calls for every
+direction; the pins check it against the dense inverse-Hessian update.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def run(fg, x0, n_iter, m=8, max_step=0.1, c1=1e-4, shrink=0.5, max_backtracks=20, gtol=0.0):
+def two_loop(g, S, Y, R, gamma):
+    """H g for the limited-memory inverse Hessian H of the stored pairs (lists S,
+    Y, R = 1/y.s, oldest first) with initial matrix gamma I (Nocedal & Wright,
+    Algorithm 7.4).  With no pairs, H = I."""
+    q = np.array(g, dtype=np.float64, copy=True)
+    a = [0.0] * len(S)
+    for i in range(len(S) - 1, -1, -1):
+        a[i] = R[i] * float(S[i] @ q)
+        q -= a[i] * Y[i]
+    if S:
+        q *= gamma
+    for i in range(len(S)):
+        b = R[i] * float(Y[i] @ q)
+        q += (a[i] - b) * S[i]
+    return q
+
+
+def run(fg, x0, n_iter, m=8, max_step=0.1, c1=1e-4, shrink=0.5, max_backtracks=20, gtol=0.0,
+        direction=two_loop):
     """fg(x) -> (f, g) on flat FP64 vectors; stops early when the RMS gradient is at
-    most gtol.  Returns dict(x, f, fs, nevals, xs)."""
+    most gtol.  direction(g, S, Y, R, gamma) returns H g (default: the two-loop
+    recursion).  Returns dict(x, f, fs, nevals, xs)."""
     x = np.array(x0, dtype=np.float64).ravel().copy()
     f, g = fg(x)
     nevals = 1
@@ -80,17 +101,7 @@ def run(fg, x0, n_iter, m=8, max_step=0.1, c1=1e-4, shrink=0.5, max_backtracks=2
                 R.pop(0)
         else:
             S, Y, R = [], [], []
-        q = g.copy()
-        a = [0.0] * len(S)
-        for i in range(len(S) - 1, -1, -1):
-            a[i] = R[i] * float(S[i] @ q)
-            q -= a[i] * Y[i]
-        if S:
-            q *= gamma
-        for i in range(len(S)):
-            b = R[i] * float(Y[i] @ q)
-            q += (a[i] - b) * S[i]
-        p = -q
+        p = -direction(g, S, Y, R, gamma)
         gtp = float(g @ p)
         if not gtp < 0:
             S, Y, R = [], [], []

@@ -268,6 +268,94 @@ def test_lbfgs_oracle_on_a_quadratic():
     assert all(f2 <= f1 for f1, f2 in zip(r["fs"], r["fs"][1:]))
 
 
+def _random_pairs(n, m, seed):
+    """m curvature pairs (s, y = A s) of a random SPD matrix A, so y.s > 0."""
+    rng = np.random.default_rng(seed)
+    Q = rng.normal(size=(n, n))
+    A = Q @ Q.T + 0.5 * np.eye(n)
+    S = [rng.normal(size=n) for _ in range(m)]
+    Y = [A @ s for s in S]
+    R = [1.0 / float(y @ s) for s, y in zip(S, Y)]
+    return S, Y, R, rng
+
+
+def _dense_inverse_hessian(S, Y, gamma):
+    """BFGS inverse-Hessian update applied to gamma I, oldest pair first:
+    H <- V^T H V + rho s s^T with V = I - rho y s^T (Nocedal & Wright, Eq. 6.17)."""
+    n = S[0].size
+    H = gamma * np.eye(n)
+    for s, y in zip(S, Y):
+        rho = 1.0 / float(y @ s)
+        V = np.eye(n) - rho * np.outer(y, s)
+        H = V.T @ H @ V + rho * np.outer(s, s)
+    return H
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 8])
+def test_lbfgs_two_loop_is_the_dense_bfgs_update(m):
+    # the two-loop recursion computes H g for H built by m BFGS updates of
+    # gamma I, taken oldest to newest; reversing either loop's order, dropping
+    # the gamma scaling or a rho factor changes H g far beyond rounding
+    from oracle import lbfgs as LB
+    n = 10
+    S, Y, R, rng = _random_pairs(n, m, seed=30 + m)
+    gamma = float(S[-1] @ Y[-1]) / float(Y[-1] @ Y[-1])
+    H = _dense_inverse_hessian(S, Y, gamma)
+    for _ in range(4):
+        g = rng.normal(size=n)
+        ref = H @ g
+        got = LB.two_loop(g, S, Y, R, gamma)
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    # secant condition of the newest pair: H y = s
+    hy = LB.two_loop(Y[-1], S, Y, R, gamma)
+    assert np.linalg.norm(hy - S[-1]) <= 1e-12 * np.linalg.norm(S[-1])
+    # symmetric positive definite, as every BFGS inverse Hessian with y.s > 0
+    u, v = rng.normal(size=n), rng.normal(size=n)
+    assert abs(u @ LB.two_loop(v, S, Y, R, gamma) - v @ LB.two_loop(u, S, Y, R, gamma)) \
+        <= 1e-12 * np.linalg.norm(H, 2) * np.linalg.norm(u) * np.linalg.norm(v)
+    assert np.all(np.linalg.eigvalsh(0.5 * (H + H.T)) > 0)
+    # no pairs: steepest descent
+    g = rng.normal(size=n)
+    assert np.array_equal(LB.two_loop(g, [], [], [], 1.0), g)
+
+
+def test_lbfgs_run_keeps_the_newest_pairs():
+    # every direction of run() uses the last min(k, m) steps s = x_{k+1} - x_k
+    # and gradient changes y, oldest first, with gamma = s.y / y.y of the newest
+    from oracle import lbfgs as LB
+    rng = np.random.default_rng(12)
+    n, m = 8, 3
+    Q = rng.normal(size=(n, n))
+    A = Q @ Q.T + n * np.eye(n)
+    b = rng.normal(size=n)
+
+    def fg(x):
+        # a convex quartic, so the curvature pairs change from step to step
+        return 0.5 * x @ A @ x - b @ x + 0.25 * np.sum(x ** 4), A @ x - b + x ** 3
+
+    seen = []
+
+    def spy(g, S, Y, R, gamma):
+        seen.append(([s.copy() for s in S], [y.copy() for y in Y], list(R), gamma, g.copy()))
+        return LB.two_loop(g, S, Y, R, gamma)
+
+    r = LB.run(fg, np.zeros(n), 7, m=m, max_step=0.3, direction=spy)
+    xs = r["xs"]
+    assert len(seen) == 7
+    for k, (S, Y, R, gamma, g) in enumerate(seen):
+        steps = [xs[i + 1] - xs[i] for i in range(k + 1)]
+        grads = [fg(x)[1] for x in xs[:k + 2]]
+        ys = [grads[i + 1] - grads[i] for i in range(k + 1)]
+        keep = min(k + 1, m)
+        assert len(S) == keep
+        for j in range(keep):
+            np.testing.assert_allclose(S[j], steps[k + 1 - keep + j], rtol=1e-12, atol=1e-15)
+            np.testing.assert_allclose(Y[j], ys[k + 1 - keep + j], rtol=1e-12, atol=1e-14)
+            assert R[j] == pytest.approx(1.0 / float(S[j] @ Y[j]), rel=1e-14)
+        assert gamma == pytest.approx(float(S[-1] @ Y[-1]) / float(Y[-1] @ Y[-1]), rel=1e-14)
+        np.testing.assert_allclose(g, grads[k + 1], rtol=1e-12, atol=1e-14)
+
+
 def test_lbfgs_oracle_decreases_structure_factor_loss():
     from oracle import lbfgs as LB
     N, L, M = 64, 8.0, 3
