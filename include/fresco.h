@@ -106,7 +106,12 @@ typedef struct fresco_plan_info {
  * Errors: EINVAL (null out/p, dim not 2 or 3, n < 1, L <= 0, M < 0, tol not in
  * (0, 0.1], upsampfac != 2, a weight < 0 or non-finite, dtype unknown),
  * ENOTSUP (more than 2^31 - 1 points, or a grid beyond the 32-bit index
- * ranges of the passes), ENOMEM, EHIP.  On error *out is set to NULL. */
+ * ranges of the passes), ENOMEM, EHIP.  On error *out is set to NULL.
+ * The environment variable FRESCO_DEVICE_MEMORY_LIMIT (bytes), read here, caps
+ * the device memory the context may ever hold (scratch, and the optimiser's
+ * buffers allocated by fresco_step); an allocation beyond it fails with ENOMEM
+ * as if the device were full, and what the failing call had allocated is
+ * released. */
 int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream);
 
 /* Release a context (synchronises its stream first).  NULL is accepted. */
@@ -148,7 +153,11 @@ int fresco_loss_grad(fresco_ctx* ctx, const void* pos, double* loss, void* grad)
 
 /* As fresco_loss_grad, but loss_dev is a DEVICE pointer to one double and the
  * call only enqueues work (no synchronisation, no non-finite report), so it can
- * be captured in a HIP graph.  Errors: EINVAL, EHIP. */
+ * be captured in a HIP graph.  Outside a capture the library captures the
+ * evaluation itself on first use and replays that graph when it sees the same
+ * pos, loss_dev and grad pointers again; while the caller is capturing the
+ * context's stream, the launches are enqueued as they are and become nodes of
+ * the caller's graph.  Errors: EINVAL, EHIP. */
 int fresco_loss_grad_async(fresco_ctx* ctx, const void* pos, double* loss_dev, void* grad);
 
 /* Options of the L-BFGS minimiser (main text, "Algorithm": L-BFGS with a cap on
@@ -170,12 +179,18 @@ typedef struct fresco_lbfgs_opts {
  * internal point order persist in the context across calls, so a run can be
  * continued by calling again with the returned positions; fresco_reset_history
  * starts afresh.  The iterations run as replays of one captured HIP graph (on a
- * non-default stream) with no host synchronisation inside a batch.
+ * non-default stream), enqueued in chunks of 8 with two chunks in flight: the
+ * host reads the optimiser's state after each chunk while the next one runs, so
+ * after a stop (n_iter reached, gtol reached, line-search failure) at most two
+ * chunks of replays run idle -- they change nothing and are not counted.
  * loss_out (host, may be NULL): loss at the final positions; n_eval_out (host,
- * may be NULL): loss/gradient evaluations used.  Synchronises the stream.
+ * may be NULL): loss/gradient evaluations the optimiser used (the first one at
+ * the starting point included).  Synchronises the stream.  The first call, and
+ * a call with another m, allocates the optimiser's buffers ((5 + 2m) N d values;
+ * those of another m are freed).
  * Errors: EINVAL (null ctx/pos/opts, n_iter < 0, options out of range), EHIP,
- * ELINESEARCH (no decrease even along the steepest descent direction; pos holds
- * the last accepted point). */
+ * ENOMEM, ELINESEARCH (no decrease even along the steepest descent direction;
+ * pos holds the last accepted point). */
 int fresco_step(fresco_ctx* ctx, void* pos, const fresco_lbfgs_opts* opts, int32_t n_iter,
                 double* loss_out, int32_t* n_eval_out);
 

@@ -25,18 +25,21 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB: an alternative build of oracle.c to load (the host-sanitizer run
+# of the tests uses one); by default liboracle.so beside this file
+_BUILT_SO = os.path.join(_HERE, "liboracle.so")
+_SO = os.environ.get("ORACLE_LIB") or _BUILT_SO
 _lib = None
 
 
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (gcc, OpenMP, portable x86-64 code)."""
-    if force or not os.path.exists(_SO):
+    if force or not os.path.exists(_BUILT_SO):
         cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-ffp-contract=off",
-               os.path.join(_HERE, "oracle.c"), "-o", _SO + ".tmp", "-lm"]
+               os.path.join(_HERE, "oracle.c"), "-o", _BUILT_SO + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(_SO + ".tmp", _SO)
-    return _SO
+        os.replace(_BUILT_SO + ".tmp", _BUILT_SO)
+    return _BUILT_SO
 
 
 def _load():

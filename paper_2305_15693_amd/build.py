@@ -46,14 +46,21 @@ def _generate_tables() -> None:
     os.replace(out + ".tmp", out)
 
 
-def _compile(src: str) -> str:
-    os.makedirs(OBJDIR, exist_ok=True)
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer (device code is
+# compiled as usual): the argument checks and host logic of the C ABI can run
+# under the sanitizers on a machine without a GPU.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def _compile(src: str, objdir: str = OBJDIR, extra=()) -> str:
+    os.makedirs(objdir, exist_ok=True)
+    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = [HIPCC, "-c", "-x", "hip", *DEVICE_FLAGS, *COMMON, path, "-o", obj]
+        cmd = [HIPCC, "-c", "-x", "hip", *DEVICE_FLAGS, *COMMON, *extra, path, "-o", obj]
     else:
-        cmd = [HIPCC, "-c", *COMMON, "-D__HIP_PLATFORM_AMD__", path, "-o", obj]
+        cmd = [HIPCC, "-c", *COMMON, *extra, "-D__HIP_PLATFORM_AMD__", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -75,6 +82,33 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print("built", LIB)
     return LIB
+
+
+def build_host_sanitized(out_dir: str) -> str:
+    """libfresco.so with host-side ASan + UBSan in out_dir (objects there too).
+    Load it with the clang ASan runtime preloaded (host_sanitizer_runtime())."""
+    _generate_tables()
+    objdir = os.path.join(out_dir, "obj")
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(lambda s: _compile(s, objdir, HOST_SANITIZE), SOURCES))
+    lib = os.path.join(out_dir, "libfresco_hostsan.so")
+    cmd = [HIPCC, "-shared", "-fPIC", *DEVICE_FLAGS, *HOST_SANITIZE, "-shared-libasan", *objs,
+           "-o", lib]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("link failed")
+    return lib
+
+
+def host_sanitizer_runtime() -> str:
+    """Path of the clang ASan runtime that a sanitized build needs preloaded."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    r = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True, check=True)
+    return r.stdout.strip()
 
 
 if __name__ == "__main__":

@@ -451,7 +451,8 @@ struct fresco_batch_ctx {
   // L-BFGS over the concatenated batch
   void* lv = nullptr;       // LbfgsVec<R>
   LbfgsState* lst = nullptr;
-  LbfgsState* lst_host = nullptr;
+  LbfgsState* lst_host = nullptr;  // pinned [2] (one per chunk in flight)
+  hipEvent_t lb_ev[2] = {nullptr, nullptr};
   int lb_m = 0;
   bool lb_fresh = true;
   LbfgsOpts lb_opts{};
@@ -752,7 +753,9 @@ int batch_lbfgs_setup(fresco_batch_ctx* c, int m) {
   if ((st = balloc(c, &v.part0, (4 * (size_t)kLbfgsMaxM + 1) * nb))) return st;
   if ((st = balloc(c, &v.part1, (size_t)nb))) return st;
   if (!c->lst && (st = balloc(c, &c->lst, 1))) return st;
-  if (!c->lst_host) BHIP(hipHostMalloc((void**)&c->lst_host, sizeof(LbfgsState)));
+  if (!c->lst_host) BHIP(hipHostMalloc((void**)&c->lst_host, 2 * sizeof(LbfgsState)));
+  for (int i = 0; i < 2; ++i)
+    if (!c->lb_ev[i]) BHIP(hipEventCreateWithFlags(&c->lb_ev[i], hipEventDisableTiming));
   c->lb_m = m;
   c->lb_fresh = true;
   return FRESCO_OK;
@@ -802,34 +805,34 @@ int batch_step_impl(fresco_batch_ctx* c, void* pos, const fresco_lbfgs_opts* o, 
   if ((st = batch_trial<R>(c))) return st;
   launch_lbfgs_set_mode(c->lst, 0, -1, c->st);
   const bool graphs = c->use_graphs && c->st != nullptr;
-  for (int guard = 0; guard < 1000000; ++guard) {
-    BHIP(hipMemcpyAsync(c->lst_host, c->lst, sizeof(LbfgsState), hipMemcpyDeviceToHost, c->st));
-    BHIP(hipStreamSynchronize(c->st));
-    const LbfgsState& h = *c->lst_host;
-    if (h.iter >= n_iter || h.fail || h.converged) break;
-    const int k = n_iter - h.iter;
-    if (graphs && !c->lb_graph) {
-      hipGraph_t graph = nullptr;
-      BHIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-      st = batch_trial<R>(c);
-      hipError_t e = hipStreamEndCapture(c->st, &graph);
-      if (st) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return st;
-      }
-      BHIP(e);
-      e = hipGraphInstantiate(&c->lb_graph, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      BHIP(e);
+  if (graphs && !c->lb_graph) {
+    hipGraph_t graph = nullptr;
+    BHIP(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    st = batch_trial<R>(c);
+    hipError_t e = hipStreamEndCapture(c->st, &graph);
+    if (st) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
     }
-    for (int r = 0; r < k; ++r) {
+    BHIP(e);
+    e = hipGraphInstantiate(&c->lb_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    BHIP(e);
+  }
+  auto replay = [&](int count) -> int {
+    for (int r = 0; r < count; ++r) {
       if (graphs) {
         BHIP(hipGraphLaunch(c->lb_graph, c->st));
-      } else if ((st = batch_trial<R>(c))) {
-        return st;
+      } else {
+        const int s2 = batch_trial<R>(c);
+        if (s2) return s2;
       }
     }
-  }
+    return FRESCO_OK;
+  };
+  st = lbfgs_replay_until_stop(c->st, c->lst, c->lst_host, c->lb_ev, n_iter, kLbfgsReplayChunk,
+                               replay, &g_batch_hip);
+  if (st) return st;
   BHIP(hipMemcpyAsync(pos, v.x, vbytes, hipMemcpyDeviceToDevice, c->st));
   BHIP(hipMemcpyAsync(c->lst_host, c->lst, sizeof(LbfgsState), hipMemcpyDeviceToHost, c->st));
   BHIP(hipStreamSynchronize(c->st));
@@ -851,6 +854,8 @@ int fresco_batch_destroy(fresco_batch_ctx* c) {
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->host) (void)hipHostFree(c->host);
   if (c->lst_host) (void)hipHostFree(c->lst_host);
+  for (hipEvent_t e : c->lb_ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->lv) {
     if (c->dtype == FRESCO_F32) delete (LbfgsVec<float>*)c->lv;
     else delete (LbfgsVec<double>*)c->lv;

@@ -83,7 +83,8 @@ struct State {
   // L-BFGS (allocated on the first fresco_step)
   LbfgsVec<R> lv{};
   LbfgsState* lst = nullptr;
-  LbfgsState* lst_host = nullptr;  // pinned copy
+  LbfgsState* lst_host = nullptr;  // pinned copies [2] (one per chunk in flight)
+  hipEvent_t lb_ev[2] = {nullptr, nullptr};
   int* perm0 = nullptr;            // internal order -> caller's index
   bool have_perm0 = false;
   int lb_m = 0;
@@ -107,6 +108,8 @@ struct fresco_ctx {
   long long n_constrained;
   long long bytes = 0;
   std::vector<void*> allocs;
+  std::vector<size_t> alloc_bytes;  // size of each entry of allocs
+  long long mem_limit = 0;          // device bytes the context may hold (0: no limit)
   double* host_loss = nullptr;  // pinned
   int* host_flag = nullptr;     // pinned
   void* state = nullptr;
@@ -173,6 +176,10 @@ struct StageTimer {
 int dalloc(fresco_ctx* c, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  if (c->mem_limit > 0 && c->bytes + (long long)bytes > c->mem_limit) {
+    g_last_hip = (int)hipErrorOutOfMemory;
+    return FRESCO_ENOMEM;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     g_last_hip = (int)e;
@@ -180,8 +187,25 @@ int dalloc(fresco_ctx* c, void** p, size_t bytes) {
     return FRESCO_ENOMEM;
   }
   c->allocs.push_back(*p);
+  c->alloc_bytes.push_back(bytes);
   c->bytes += (long long)bytes;
   return FRESCO_OK;
+}
+
+// Frees one buffer of the context (no-op for NULL); the caller has made sure
+// the stream no longer uses it.
+template <class T>
+void dfree(fresco_ctx* c, T*& p) {
+  if (!p) return;
+  for (size_t i = 0; i < c->allocs.size(); ++i)
+    if (c->allocs[i] == (void*)p) {
+      (void)hipFree(c->allocs[i]);
+      c->bytes -= (long long)c->alloc_bytes[i];
+      c->allocs.erase(c->allocs.begin() + (long)i);
+      c->alloc_bytes.erase(c->alloc_bytes.begin() + (long)i);
+      break;
+    }
+  p = nullptr;
 }
 
 template <class T>
@@ -854,9 +878,14 @@ int loss_grad_eager(fresco_ctx* c, const void* pos, double* loss_dev, void* grad
 template <class R>
 int loss_grad_impl(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
   c->sf_pos = nullptr;
-  // the legacy default stream cannot be captured; timed stages run eagerly
+  // the legacy default stream cannot be captured; timed stages run eagerly; so
+  // do calls made while the caller captures the stream into a graph of its own
+  // (the launches then become nodes of that graph)
   if (!c->use_graphs || c->timing_mask || c->st == nullptr)
     return loss_grad_eager<R>(c, pos, loss_dev, grad);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(c->st, &cap));
+  if (cap != hipStreamCaptureStatusNone) return loss_grad_eager<R>(c, pos, loss_dev, grad);
   for (auto& e : c->graphs)
     if (e.pos == pos && e.loss == loss_dev && e.grad == grad) {
       HIPCHK(hipGraphLaunch(e.exec, c->st));
@@ -885,16 +914,29 @@ int loss_grad_impl(fresco_ctx* c, const void* pos, double* loss_dev, void* grad)
 }
 
 // ------------------------------------------------------------- L-BFGS
+// Frees the optimiser's device buffers (any that exist); the stream must have
+// drained.
 template <class R>
-int lbfgs_setup(fresco_ctx* c, int m) {
+void lbfgs_free(fresco_ctx* c) {
   State<R>* S = (State<R>*)c->state;
-  if (S->lst && S->lb_m == m) return FRESCO_OK;
-  // (re)allocate for this history length; earlier buffers stay with the context
-  if (S->lb_graph) {
-    (void)hipGraphExecDestroy(S->lb_graph);
-    S->lb_graph = nullptr;
-  }
-  S->have_perm0 = false;
+  LbfgsVec<R>& v = S->lv;
+  dfree(c, v.x);
+  dfree(c, v.g);
+  dfree(c, v.p);
+  dfree(c, v.xt);
+  dfree(c, v.gt);
+  dfree(c, v.S);
+  dfree(c, v.Y);
+  dfree(c, v.part0);
+  dfree(c, v.part1);
+  dfree(c, S->lst);
+  dfree(c, S->perm0);
+  S->lb_m = 0;
+}
+
+template <class R>
+int lbfgs_alloc(fresco_ctx* c, int m) {
+  State<R>* S = (State<R>*)c->state;
   const long long n = c->g.N * c->g.d;
   LbfgsVec<R>& v = S->lv;
   int st;
@@ -913,9 +955,31 @@ int lbfgs_setup(fresco_ctx* c, int m) {
   if ((st = dalloc_t(c, &v.part1, (size_t)nb))) return st;
   if ((st = dalloc_t(c, &S->lst, 1))) return st;
   if ((st = dalloc_t(c, &S->perm0, c->g.N))) return st;
-  if (!S->lst_host) HIPCHK(hipHostMalloc((void**)&S->lst_host, sizeof(LbfgsState)));
+  if (!S->lst_host) HIPCHK(hipHostMalloc((void**)&S->lst_host, 2 * sizeof(LbfgsState)));
+  for (int i = 0; i < 2; ++i)
+    if (!S->lb_ev[i]) HIPCHK(hipEventCreateWithFlags(&S->lb_ev[i], hipEventDisableTiming));
   S->lb_m = m;
   return FRESCO_OK;
+}
+
+// Buffers of the optimiser for history length m, allocated on the first call
+// and again when m changes: the buffers of the earlier length are freed first
+// (after the stream has drained), so that changing m does not accumulate them,
+// and so are the ones of an allocation that failed part way.
+template <class R>
+int lbfgs_setup(fresco_ctx* c, int m) {
+  State<R>* S = (State<R>*)c->state;
+  if (S->lst && S->lb_m == m) return FRESCO_OK;
+  if (S->lb_graph) {
+    (void)hipGraphExecDestroy(S->lb_graph);
+    S->lb_graph = nullptr;
+  }
+  S->have_perm0 = false;
+  HIPCHK(hipStreamSynchronize(c->st));
+  lbfgs_free<R>(c);
+  const int st = lbfgs_alloc<R>(c, m);
+  if (st) lbfgs_free<R>(c);
+  return st;
 }
 
 template <class R>
@@ -986,33 +1050,34 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   if ((st = lbfgs_trial<R>(c))) return st;
   launch_lbfgs_set_mode(S->lst, 0, -1, c->st);
   const bool graphs = c->use_graphs && !c->timing_mask && c->st != nullptr;
-  for (int guard = 0; guard < 1000000; ++guard) {
-    if ((st = lbfgs_read<R>(c))) return st;
-    const LbfgsState& h = *S->lst_host;
-    if (h.iter >= n_iter || h.fail || h.converged) break;
-    const int k = n_iter - h.iter;
-    if (graphs && !S->lb_graph) {
-      hipGraph_t graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-      st = lbfgs_trial<R>(c);
-      hipError_t e = hipStreamEndCapture(c->st, &graph);
-      if (st) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return st;
-      }
-      HIPCHK(e);
-      e = hipGraphInstantiate(&S->lb_graph, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      HIPCHK(e);
+  if (graphs && !S->lb_graph) {
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    st = lbfgs_trial<R>(c);
+    hipError_t e = hipStreamEndCapture(c->st, &graph);
+    if (st) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
     }
-    for (int r = 0; r < k; ++r) {
+    HIPCHK(e);
+    e = hipGraphInstantiate(&S->lb_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+  }
+  auto replay = [&](int count) -> int {
+    for (int r = 0; r < count; ++r) {
       if (graphs) {
         HIPCHK(hipGraphLaunch(S->lb_graph, c->st));
-      } else if ((st = lbfgs_trial<R>(c))) {
-        return st;
+      } else {
+        const int s2 = lbfgs_trial<R>(c);
+        if (s2) return s2;
       }
     }
-  }
+    return FRESCO_OK;
+  };
+  if ((st = lbfgs_replay_until_stop(c->st, S->lst, S->lst_host, S->lb_ev, n_iter,
+                                    kLbfgsReplayChunk, replay, &g_last_hip)))
+    return st;
   launch_scatter_rows<R>(S->lv.x, S->perm0, N, g.d, (R*)pos, c->st);
   if ((st = lbfgs_read<R>(c))) return st;
   const LbfgsState& h = *S->lst_host;
@@ -1098,11 +1163,15 @@ int fresco_destroy(fresco_ctx* c) {
       State<float>* S = (State<float>*)c->state;
       if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
       if (S->lst_host) (void)hipHostFree(S->lst_host);
+      for (hipEvent_t e : S->lb_ev)
+        if (e) (void)hipEventDestroy(e);
       delete S;
     } else {
       State<double>* S = (State<double>*)c->state;
       if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
       if (S->lst_host) (void)hipHostFree(S->lst_host);
+      for (hipEvent_t e : S->lb_ev)
+        if (e) (void)hipEventDestroy(e);
       delete S;
     }
   }
@@ -1135,6 +1204,10 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
   c->st = (hipStream_t)stream;
   const char* eg = std::getenv("FRESCO_GRAPHS");
   c->use_graphs = !(eg && eg[0] == '0');
+  // optional cap on the device memory of the context (bytes), for callers that
+  // share the GPU; allocations beyond it fail with FRESCO_ENOMEM
+  const char* ml = std::getenv("FRESCO_DEVICE_MEMORY_LIMIT");
+  c->mem_limit = ml ? std::atoll(ml) : 0;
   Geom& g = c->g;
   std::memset(&g, 0, sizeof(g));
   g.d = d;

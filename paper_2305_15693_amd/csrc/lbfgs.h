@@ -72,6 +72,66 @@ struct LbfgsVec {
   int nb;         // blocks of the vector kernels
 };
 
+// Host side of an optimiser call: replays trial steps (replay(count) enqueues
+// count of them) until the state reports a stop -- target iterations reached,
+// convergence or line-search failure.  Replays go out in chunks of at most
+// `chunk`, each followed by an asynchronous copy of the state to its own pinned
+// host slot and an event; two chunks are in flight, so the host reads one
+// chunk's copy while the next runs and the stream never waits on the host.
+// Replays that run after the stop find the optimiser idle: they change no
+// state and are not counted as evaluations (at most two chunks of them).
+// host: pinned LbfgsState[2]; ev: two events.  Returns FRESCO_OK, replay's own
+// status, or FRESCO_EHIP with the HIP error in *hip_err.
+template <class F>
+int lbfgs_replay_until_stop(hipStream_t st, LbfgsState* dev, LbfgsState* host, hipEvent_t ev[2],
+                            int n_iter, int chunk, F&& replay, int* hip_err) {
+#define LB_RCHK(x)                   \
+  do {                               \
+    hipError_t e_ = (x);             \
+    if (e_ != hipSuccess) {          \
+      *hip_err = (int)e_;            \
+      return FRESCO_EHIP;            \
+    }                                \
+  } while (0)
+  LB_RCHK(hipMemcpyAsync(&host[0], dev, sizeof(LbfgsState), hipMemcpyDeviceToHost, st));
+  LB_RCHK(hipStreamSynchronize(st));
+  LbfgsState h = host[0];
+  int q_slot[2] = {0, 0}, q_cnt[2] = {0, 0};
+  int q_head = 0, q_len = 0, next_slot = 0;
+  long long inflight = 0;  // replays enqueued whose state copy has not been read
+  while (!(h.iter >= n_iter || h.fail || h.converged)) {
+    const long long need = (long long)n_iter - h.iter - inflight;
+    if (need > 0 && q_len < 2) {
+      const int cnt = (int)(need < chunk ? need : chunk);
+      const int s = replay(cnt);
+      if (s) return s;
+      const int slot = next_slot;
+      next_slot ^= 1;
+      LB_RCHK(hipMemcpyAsync(&host[slot], dev, sizeof(LbfgsState), hipMemcpyDeviceToHost, st));
+      LB_RCHK(hipEventRecord(ev[slot], st));
+      const int q = (q_head + q_len) & 1;
+      q_slot[q] = slot;
+      q_cnt[q] = cnt;
+      ++q_len;
+      inflight += cnt;
+      continue;
+    }
+    // here a chunk is in flight (with none, need = n_iter - iter > 0)
+    const int slot = q_slot[q_head];
+    inflight -= q_cnt[q_head];
+    q_head ^= 1;
+    --q_len;
+    LB_RCHK(hipEventSynchronize(ev[slot]));
+    h = host[slot];
+  }
+  LB_RCHK(hipStreamSynchronize(st));
+#undef LB_RCHK
+  return FRESCO_OK;
+}
+
+// replays per chunk of an optimiser call
+constexpr int kLbfgsReplayChunk = 8;
+
 template <class R>
 void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
                          hipStream_t st);

@@ -81,7 +81,9 @@ __device__ __forceinline__ int lb_decided_step(const LbfgsState* S, const LbfgsO
 }
 __device__ void lb_decide(LbfgsState* S, const LbfgsOpts& o) {
   const int step = lb_decided_step(S, o);
-  S->nevals += 1;
+  // an evaluation counts when it can inform a decision: replays that run after
+  // the call has stopped (target reached, converged, failed) are not counted
+  if (S->mode == LB_INIT || !(S->fail || S->iter >= S->target || S->converged)) S->nevals += 1;
   if (step == LB_INIT) {
     S->f_cur = S->f_trial;  // take the point as current
     S->nbt = 0;

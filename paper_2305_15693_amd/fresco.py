@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfresco.so")
+# FRESCO_LIB: an alternative build of the library to load (the host-sanitizer
+# run of the argument checks uses one); by default libfresco.so beside this file
+LIB_PATH = os.environ.get("FRESCO_LIB") or os.path.join(_HERE, "libfresco.so")
 
 F32, F64 = 0, 1
 WEIGHT_ABS, WEIGHT_RELATIVE = 0, 1

@@ -11,6 +11,8 @@ HEADER_DIR = os.path.join(ROOT, "include")
 
 
 def _lib_path():
+    if os.environ.get("FRESCO_LIB"):
+        return os.environ["FRESCO_LIB"]
     from paper_2305_15693_amd import build as B
     if not os.path.exists(B.LIB):
         B.build()
@@ -149,3 +151,33 @@ def test_bench_algorithmic_bytes():
     assert b["spread"] == N * 2 * s + nf * nf * s
     assert b["interp"] == nf * nf * s + 2 * N * 2 * s
     assert b["fft_rows_fwd"] == nf * nf * s + nf * 301 * 8
+
+
+def test_failed_creation_releases_everything():
+    # without a device the first allocation fails: every create reports ENOMEM,
+    # leaves *out NULL and releases what it had set up (run under the host
+    # sanitizers too); with a device the objects are created and destroyed
+    from paper_2305_15693_amd import fresco as F
+    lib = F.lib()
+    p = F.Problem()
+    p.dim, p.dtype, p.n = 2, F.F32, 100
+    p.box[0] = p.box[1] = 10.0
+    p.kmax[0] = p.kmax[1] = 4
+    p.k_cut, p.tol, p.upsampfac = 4.0, 1e-6, 2.0
+    pp = F.PairProblem()
+    pp.dim, pp.dtype, pp.n = 2, F.F32, 100
+    pp.box[0] = pp.box[1] = 10.0
+    pp.sigma, pp.eps, pp.alpha = 0.5, 1.0, 2.0
+    batch = (F.Problem * 2)(p, p)
+    calls = [(lib.fresco_create, (ctypes.byref(p),), lib.fresco_destroy),
+             (lib.fresco_pair_create, (ctypes.byref(pp),), lib.fresco_pair_destroy),
+             (lib.fresco_batch_create, (2, batch), lib.fresco_batch_destroy)]
+    for create, args, destroy in calls:
+        h = ctypes.c_void_p()
+        st = create(ctypes.byref(h), *args, None)
+        if st == F.OK:
+            assert h.value is not None
+            assert destroy(h) == F.OK
+        else:
+            assert st == F.ENOMEM
+            assert h.value is None

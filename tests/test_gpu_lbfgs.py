@@ -144,3 +144,136 @@ def test_lbfgs_options_rejected(gpu):
     with pytest.raises(F.FrescoError):
         ctx.step(pos, -1)
     ctx.close()
+
+
+def _fp64_case(gpu, wscale=1.0):
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    d, N, L, M = 2, 300, 17.3, 6
+    pos0 = I.positions(N, d, L, np.float64, seed=52)
+    w, s0 = I.stealthy_target(d, M, float(M))
+    w = w * wscale
+    ctx = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-12, dtype="f64", device=gpu,
+                    stream=torch.cuda.Stream(device=gpu))
+    modes, W, S0 = O.constrained_set(d, M, w, s0)
+    return ctx, pos0, _oracle_fg(N, d, L, modes, W, S0), (d, N, L, M)
+
+
+def test_lbfgs_gtol_stop_counts_like_oracle(gpu):
+    # gtol between the RMS gradients of the oracle's iterations 12 and 13 (5.4e-3
+    # and 2.0e-3): both stop after 13 accepted iterations of a 500-iteration call
+    # with the same number of evaluations; the replays issued after the stop are
+    # bounded by two chunks (counted here through the per-stage launch counts)
+    import torch
+    ctx, pos0, fg, (d, N, L, M) = _fp64_case(gpu)
+    gtol = 3.3e-3
+    ms = ctx.default_max_step()
+    ref = LB.run(fg, pos0, 500, m=8, max_step=ms, gtol=gtol)
+    assert len(ref["xs"]) - 1 == 13
+    pos = torch.from_numpy(pos0.copy()).to(gpu)
+    ctx.set_timing(["interp"])
+    loss, nev = ctx.step(pos, 500, max_step=ms, gtol=gtol)
+    t = ctx.read_timing(reset=True)
+    ctx.set_timing([])
+    x = pos.cpu().numpy()
+    print(f"gtol stop: evaluations {nev} (oracle {ref['nevals']}), executed {t['interp'][1]}, "
+          f"loss {loss:.6e} (oracle {ref['f']:.6e})", flush=True)
+    assert nev == ref["nevals"]
+    assert abs(loss - ref["f"]) <= 1e-9 * ref["fs"][0]
+    assert np.linalg.norm(x.ravel() - ref["x"]) <= 1e-7 * np.linalg.norm(ref["x"] - pos0.ravel())
+    assert nev <= t["interp"][1] <= nev + 2 * 8
+    ctx.close()
+
+
+def test_lbfgs_line_search_failure_keeps_last_accepted_point(gpu):
+    # weights scaled by 1e30 (the L-BFGS trajectory does not depend on the scale
+    # of the loss): after 8 ordinary iterations and a reset of the history, a call
+    # with a cap of one point spacing and no backtracking.  The gradient is so
+    # large that the cap sets the steepest-descent step to a whole spacing, which
+    # raises the loss (2.4e30 -> 1.5e31 in the oracle); the history is already
+    # empty, so the second rejection ends the search: the call reports
+    # ELINESEARCH, as the oracle raises, and leaves the positions at the last
+    # accepted point, bit for bit
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    ctx, pos0, fg, (d, N, L, M) = _fp64_case(gpu, wscale=1e30)
+    ms = ctx.default_max_step()
+    ref = LB.run(fg, pos0, 8, m=8, max_step=ms)
+    with pytest.raises(RuntimeError):
+        LB.run(fg, ref["x"], 5, m=8, max_step=10 * ms, max_backtracks=0)
+    pos = torch.from_numpy(pos0.copy()).to(gpu)
+    loss8, _ = ctx.step(pos, 8, max_step=ms)
+    torch.cuda.synchronize()
+    keep = pos.clone()
+    ctx.reset_history()  # first trial along -g with the large cap, as in the oracle run
+    with pytest.raises(F.FrescoError) as e:
+        ctx.step(pos, 5, max_step=10 * ms, max_backtracks=0)
+    assert e.value.code == F.ELINESEARCH
+    torch.cuda.synchronize()
+    assert torch.equal(pos, keep)
+    assert abs(loss8 - ref["f"]) <= 1e-9 * ref["fs"][0]
+    # the context stays usable: an ordinary call continues from there
+    loss, nev = ctx.step(pos, 2, max_step=ms)
+    assert loss < loss8
+    ctx.close()
+
+
+def test_lbfgs_history_length_change_frees_buffers(gpu):
+    # changing m reallocates the optimiser's vectors; the previous ones are freed,
+    # so the context's device memory returns to the same size for the same m
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    d, N, L, M = 2, 20000, 141.4, 20
+    w, s0 = I.stealthy_target(d, M, float(M))
+    ctx = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-6, dtype="f32", device=gpu,
+                    stream=torch.cuda.Stream(device=gpu))
+    pos = torch.from_numpy(I.positions(N, d, L, np.float32, seed=88)).to(gpu)
+    base = ctx.plan_info()["device_bytes"]
+    sizes = []
+    for m in (4, 12, 4, 12, 4):
+        ctx.step(pos, 2, m=m)
+        sizes.append(ctx.plan_info()["device_bytes"])
+    print("device bytes", base, sizes, flush=True)
+    assert sizes[0] == sizes[2] == sizes[4]
+    assert sizes[1] == sizes[3]
+    assert sizes[1] - sizes[0] == 2 * 8 * N * d * 4  # 8 more pairs of s and y
+    ctx.close()
+
+
+def test_device_memory_limit_reports_enomem(gpu):
+    # FRESCO_DEVICE_MEMORY_LIMIT caps the context's device memory: creation below
+    # what the plan needs fails with ENOMEM; a cap that fits the plan but not the
+    # optimiser's buffers makes fresco_step fail with ENOMEM, releases what it had
+    # allocated, and leaves the context usable for evaluations
+    import os
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    d, N, L, M = 2, 20000, 141.4, 20
+    w, s0 = I.stealthy_target(d, M, float(M))
+    pos = torch.from_numpy(I.positions(N, d, L, np.float32, seed=89)).to(gpu)
+
+    def make():
+        return F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-6, dtype="f32", device=gpu,
+                         stream=torch.cuda.Stream(device=gpu))
+
+    free = make()
+    need = free.plan_info()["device_bytes"]
+    ref_loss, ref_grad = free.loss_grad(pos)
+    free.close()
+    try:
+        os.environ["FRESCO_DEVICE_MEMORY_LIMIT"] = str(need // 2)
+        with pytest.raises(F.FrescoError) as e:
+            make()
+        assert e.value.code == F.ENOMEM
+        os.environ["FRESCO_DEVICE_MEMORY_LIMIT"] = str(need + N * d * 4 * 3)
+        ctx = make()
+    finally:
+        os.environ.pop("FRESCO_DEVICE_MEMORY_LIMIT", None)
+    assert ctx.plan_info()["device_bytes"] == need
+    with pytest.raises(F.FrescoError) as e:
+        ctx.step(pos.clone(), 3)
+    assert e.value.code == F.ENOMEM
+    assert ctx.plan_info()["device_bytes"] == need
+    loss, grad = ctx.loss_grad(pos)
+    assert loss == ref_loss and torch.equal(grad, ref_grad)
+    ctx.close()
