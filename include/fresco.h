@@ -236,6 +236,26 @@ int fresco_pair_energy_grad(fresco_pair_ctx* pair, const void* pos, double* ener
 int fresco_pair_energy_grad_async(fresco_pair_ctx* pair, const void* pos, double* energy_dev,
                                   void* grad);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as fresco_pair_energy_grad_async for the problem p, without a pair
+ * context.  The cell list lives in a fixed 32 MiB device array inside the
+ * library (one per GPU, held until the process ends); the call allocates
+ * nothing and only enqueues work on stream (NULL: the legacy default stream),
+ * which must belong to the current device.  pos, grad: device [n][d] of p's
+ * dtype (grad overwritten); energy_dev: DEVICE pointer to one double.  Size
+ * limit: the cell list needs about n (8 + 16) + 8 ncell bytes in FP32 and
+ * n (8 + 32) + 8 ncell in FP64 (ncell = cells of side >= sigma), which must fit
+ * in 32 MiB -- for example 3e5 points at unit density in 3D with sigma = 0.5;
+ * larger problems fail with ENOTSUP before any work is enqueued (use a pair
+ * context).  Every call on one GPU uses that GPU's array and overwrites what the
+ * previous call left there, so calls whose work overlaps on one GPU (other
+ * streams, other threads) race; calls in one stream are ordered.  No non-finite
+ * report.  Errors: EINVAL (null pointers, problem as for fresco_pair_create, a
+ * stream of another device), ENOTSUP (beyond the size limit), EHIP. */
+int fresco_pair_energy_grad_noalloc(const fresco_pair_problem* p, const void* pos,
+                                    double* energy_dev, void* grad, void* stream);
+
 /* Add weight * E to every loss evaluation of ctx (fresco_loss_grad,
  * fresco_loss_grad_async and fresco_step then minimise L_S + weight E); the pair
  * work runs on ctx's stream.  pair = NULL detaches.  The pair context must match

@@ -23,6 +23,7 @@
 // minimum image add no error in the FP32 build.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -362,29 +363,9 @@ int pair_enqueue(fresco_pair_ctx* pc, const void* pos, void* grad, bool accumula
 
 using namespace fresco;
 
-template <class T>
-static int pair_alloc(fresco_pair_ctx* pc, T** p, size_t count) {
-  void* q = nullptr;
-  if (hipMalloc(&q, sizeof(T) * (count ? count : 1)) != hipSuccess) return FRESCO_ENOMEM;
-  pc->allocs.push_back(q);
-  *p = (T*)q;
-  return FRESCO_OK;
-}
-
-extern "C" {
-
-int fresco_pair_destroy(fresco_pair_ctx* pc) {
-  if (!pc) return FRESCO_OK;
-  (void)hipStreamSynchronize(pc->st);
-  for (void* p : pc->allocs) (void)hipFree(p);
-  if (pc->energy_host) (void)hipHostFree(pc->energy_host);
-  delete pc;
-  return FRESCO_OK;
-}
-
-int fresco_pair_create(fresco_pair_ctx** out, const fresco_pair_problem* p, void* stream) {
-  if (!out) return FRESCO_EINVAL;
-  *out = nullptr;
+// Checks a pair problem and fills the cell geometry of pc: cells of side
+// >= sigma, grown until there are at most kMaxCells; scan and force block counts.
+static int pair_plan(const fresco_pair_problem* p, fresco_pair_ctx* pc) {
   if (!p) return FRESCO_EINVAL;
   if (p->dim != 2 && p->dim != 3) return FRESCO_EINVAL;
   if (p->dtype != FRESCO_F32 && p->dtype != FRESCO_F64) return FRESCO_EINVAL;
@@ -395,16 +376,12 @@ int fresco_pair_create(fresco_pair_ctx** out, const fresco_pair_problem* p, void
     return FRESCO_EINVAL;
   for (int a = 0; a < p->dim; ++a)
     if (!(p->box[a] > 2.0 * p->sigma) || !std::isfinite(p->box[a])) return FRESCO_EINVAL;
-  fresco_pair_ctx* pc = new (std::nothrow) fresco_pair_ctx();
-  if (!pc) return FRESCO_ENOMEM;
   pc->d = p->dim;
   pc->dtype = p->dtype;
   pc->n = p->n;
-  pc->st = (hipStream_t)stream;
   pc->sigma = p->sigma;
   pc->eps = p->eps;
   pc->alpha = p->alpha;
-  // cells of side >= sigma, grown until there are at most kMaxCells
   double side = p->sigma;
   for (;;) {
     long long tot = 1;
@@ -428,8 +405,141 @@ int fresco_pair_create(fresco_pair_ctx** out, const fresco_pair_problem* p, void
     side *= 1.05;
   }
   pc->nscan_blocks = (int)((pc->ncell + kScanPer - 1) / kScanPer);
-  const size_t rs = (p->dtype == FRESCO_F32) ? sizeof(PairRec<float>) : sizeof(PairRec<double>);
   pc->nblocks = (int)((pc->n + 255) / 256);
+  return FRESCO_OK;
+}
+
+static void pair_copy_geometry(const fresco_pair_ctx& g, fresco_pair_ctx* pc) {
+  pc->d = g.d;
+  pc->dtype = g.dtype;
+  pc->n = g.n;
+  for (int a = 0; a < 3; ++a) {
+    pc->L[a] = g.L[a];
+    pc->nc[a] = g.nc[a];
+  }
+  pc->sigma = g.sigma;
+  pc->eps = g.eps;
+  pc->alpha = g.alpha;
+  pc->ncell = g.ncell;
+  pc->nscan_blocks = g.nscan_blocks;
+  pc->nblocks = g.nblocks;
+}
+
+template <class T>
+static int pair_alloc(fresco_pair_ctx* pc, T** p, size_t count) {
+  void* q = nullptr;
+  if (hipMalloc(&q, sizeof(T) * (count ? count : 1)) != hipSuccess) return FRESCO_ENOMEM;
+  pc->allocs.push_back(q);
+  *p = (T*)q;
+  return FRESCO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of fresco_pair_energy_grad_noalloc: the cell list of one evaluation
+// (keys, ranks, counts, starts, scan sums, records, energy partials, flag) in a
+// file-scope device array, so that the call allocates nothing.  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code the
+// array's name is not a device address: the address is taken once per device
+// with hipGetSymbolAddress (with that device current) and only that address is
+// passed to kernels.
+constexpr size_t kPairScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kPairScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (looked up on the first call).
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return FRESCO_ENOTSUP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return FRESCO_EHIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return FRESCO_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Carves the cell-list buffers of geometry pc out of base; returns the bytes
+// used (the caller compares them with the scratch size before launching).
+size_t pair_carve(fresco_pair_ctx* pc, unsigned char* base) {
+  const size_t rs = (pc->dtype == FRESCO_F32) ? sizeof(PairRec<float>) : sizeof(PairRec<double>);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base ? base + off : nullptr;
+    off = align256(off + bytes);
+    return p;
+  };
+  pc->key = (uint32_t*)take(sizeof(uint32_t) * pc->n);
+  pc->rank = (uint32_t*)take(sizeof(uint32_t) * pc->n);
+  pc->count = (uint32_t*)take(sizeof(uint32_t) * pc->ncell);
+  pc->start = (uint32_t*)take(sizeof(uint32_t) * (pc->ncell + 1));
+  pc->bsum = (uint32_t*)take(sizeof(uint32_t) * pc->nscan_blocks);
+  pc->sorted = take(rs * pc->n);
+  pc->part = (double*)take(sizeof(double) * pc->nblocks);
+  pc->flag = (int*)take(sizeof(int));
+  return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fresco_pair_energy_grad_noalloc(const fresco_pair_problem* p, const void* pos,
+                                    double* energy_dev, void* grad, void* stream) {
+  if (!pos || !energy_dev || !grad) return FRESCO_EINVAL;
+  fresco_pair_ctx pc;  // geometry and scratch views only; owns nothing
+  int st = pair_plan(p, &pc);
+  if (st) return st;
+  if (pair_carve(&pc, nullptr) > kPairScratchBytes) return FRESCO_ENOTSUP;
+  hipStream_t hs = (hipStream_t)stream;
+  int cur = -1, sdev = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FRESCO_EHIP;
+  if (hs) {
+    if (hipStreamGetDevice(hs, &sdev) != hipSuccess) return FRESCO_EHIP;
+    if (sdev != cur) return FRESCO_EINVAL;  // the stream must belong to the current device
+  }
+  void* base = nullptr;
+  if ((st = scratch_address(cur, &base))) return st;
+  pair_carve(&pc, (unsigned char*)base);
+  pc.st = hs;
+  // the flag must start at zero: the array keeps the previous call's contents
+  // (a fill kernel rather than a memset node, so that the call can be captured)
+  pair_fill_kernel<<<1, 64, 0, hs>>>((uint32_t*)pc.flag, 1);
+  if ((st = pair_enqueue(&pc, pos, grad, false, 1.0, hs))) return st;
+  pair_finish_kernel<<<1, 256, 0, hs>>>(pc.part, pc.nblocks, energy_dev, pc.flag, nullptr);
+  return hipGetLastError() == hipSuccess ? FRESCO_OK : FRESCO_EHIP;
+}
+
+int fresco_pair_destroy(fresco_pair_ctx* pc) {
+  if (!pc) return FRESCO_OK;
+  (void)hipStreamSynchronize(pc->st);
+  for (void* p : pc->allocs) (void)hipFree(p);
+  if (pc->energy_host) (void)hipHostFree(pc->energy_host);
+  delete pc;
+  return FRESCO_OK;
+}
+
+int fresco_pair_create(fresco_pair_ctx** out, const fresco_pair_problem* p, void* stream) {
+  if (!out) return FRESCO_EINVAL;
+  *out = nullptr;
+  fresco_pair_ctx geom;
+  int vs = pair_plan(p, &geom);
+  if (vs) return vs;
+  fresco_pair_ctx* pc = new (std::nothrow) fresco_pair_ctx();
+  if (!pc) return FRESCO_ENOMEM;
+  pair_copy_geometry(geom, pc);
+  pc->st = (hipStream_t)stream;
+  const size_t rs = (p->dtype == FRESCO_F32) ? sizeof(PairRec<float>) : sizeof(PairRec<double>);
   int st = FRESCO_OK;
   void* sorted = nullptr;
   if (!st) st = pair_alloc(pc, &pc->key, pc->n);

@@ -133,6 +133,8 @@ def _load():
     lib.fresco_pair_energy_grad.restype = i
     lib.fresco_pair_energy_grad_async.argtypes = [vp, vp, vp, vp]
     lib.fresco_pair_energy_grad_async.restype = i
+    lib.fresco_pair_energy_grad_noalloc.argtypes = [ctypes.POINTER(PairProblem), vp, vp, vp, vp]
+    lib.fresco_pair_energy_grad_noalloc.restype = i
     lib.fresco_attach_pair.argtypes = [vp, vp, ctypes.c_double]
     lib.fresco_attach_pair.restype = i
     lib.fresco_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32,
@@ -358,6 +360,39 @@ class Context:
         _check(_lib.fresco_loss_grad_async(self._h, self._pos(pos), ctypes.c_void_p(loss_dev.data_ptr()),
                                            ctypes.c_void_p(grad.data_ptr())), "fresco_loss_grad_async")
         return loss_dev, grad
+
+
+def pair_energy_grad_noalloc(pos, energy_dev, grad, box, *, sigma: float = 0.5, eps: float = 1.0,
+                             alpha: float = 2.0, stream=None):
+    """Pair energy (into the device double energy_dev) and gradient (into grad) at
+    pos without a pair context and without any allocation (the library's fixed
+    scratch; include/fresco.h, fresco_pair_energy_grad_noalloc).  pos and grad are
+    [n][d] tensors of one dtype on the current device; enqueued on stream
+    (default: the current stream)."""
+    torch = _torch()
+    n, dim = int(pos.shape[0]), int(pos.shape[1])
+    if pos.dtype not in (torch.float32, torch.float64) or grad.dtype != pos.dtype:
+        raise ValueError("pos and grad must both be float32 or both float64")
+    if tuple(grad.shape) != (n, dim) or not pos.is_contiguous() or not grad.is_contiguous():
+        raise ValueError("pos and grad must be contiguous [n][d] tensors")
+    if energy_dev.dtype != torch.float64 or energy_dev.numel() < 1:
+        raise ValueError("energy_dev must hold a float64")
+    box = np.broadcast_to(np.asarray(box, dtype=np.float64), (dim,))
+    p = PairProblem()
+    p.dim = dim
+    p.dtype = F32 if pos.dtype == torch.float32 else F64
+    p.n = n
+    for a in range(3):
+        p.box[a] = float(box[a]) if a < dim else 1.0
+    p.sigma, p.eps, p.alpha = float(sigma), float(eps), float(alpha)
+    if stream is None:
+        stream = torch.cuda.current_stream(pos.device)
+    _check(_lib.fresco_pair_energy_grad_noalloc(ctypes.byref(p), ctypes.c_void_p(pos.data_ptr()),
+                                                ctypes.c_void_p(energy_dev.data_ptr()),
+                                                ctypes.c_void_p(grad.data_ptr()),
+                                                ctypes.c_void_p(stream.cuda_stream)),
+           "fresco_pair_energy_grad_noalloc")
+    return energy_dev, grad
 
 
 class PairContext:
