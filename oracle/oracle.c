@@ -101,9 +101,10 @@ static inline void mode_exp(int d, const int* n, const int* M, const long long* 
 
 #define BLOCK 512
 
-/* rho(k) = sum_j exp(+i k.r_j) over the listed modes; rho is [K][2] (re, im). */
-int oracle_rho(int d, long long N, const double* L, const double* pos, long long K,
-               const int* modes, double* rho) {
+/* rho(k) = sum_j c_j exp(+i k.r_j) over the listed modes (c NULL: c_j = 1);
+ * rho is [K][2] (re, im). */
+static int rho_impl(int d, long long N, const double* L, const double* pos, const double* c,
+                    long long K, const int* modes, double* rho) {
   if (d < 1 || d > 3 || N < 0 || K < 0 || !L || (N && !pos) || (K && (!modes || !rho)))
     return OR_EINVAL;
   int M[3];
@@ -124,8 +125,9 @@ int oracle_rho(int d, long long N, const double* L, const double* pos, long long
       for (long long b = 0; b < nb; ++b) {
         double er, ei;
         mode_exp(d, modes + q * d, M, off, tabs + 2 * tlen * b, &er, &ei);
-        sr += er;
-        si += ei;
+        const double cj = c ? c[j0 + b] : 1.0;
+        sr += cj * er;
+        si += cj * ei;
       }
       rho[2 * q] += sr;
       rho[2 * q + 1] += si;
@@ -133,6 +135,17 @@ int oracle_rho(int d, long long N, const double* L, const double* pos, long long
   }
   free(tabs);
   return OR_OK;
+}
+
+int oracle_rho(int d, long long N, const double* L, const double* pos, long long K,
+               const int* modes, double* rho) {
+  return rho_impl(d, N, L, pos, NULL, K, modes, rho);
+}
+
+int oracle_rho_c(int d, long long N, const double* L, const double* pos, const double* c,
+                 long long K, const int* modes, double* rho) {
+  if (!c) return OR_EINVAL;
+  return rho_impl(d, N, L, pos, c, K, modes, rho);
 }
 
 /*
@@ -280,6 +293,176 @@ int oracle_fd(int d, long long N, const double* L, const double* pos, long long 
 }
 
 /*
+ * Real point strengths c_j (Methods, "Analytical gradients": the density field
+ * sum_j c_j delta(r - r_j); polydisperse packings weigh each particle by its
+ * volume over the mean volume):
+ *   rho(k)    = sum_j c_j exp(+i k.r_j),   rho0 = sum_j c_j^2,
+ *   S(k)      = |rho(k)|^2 / rho0,         L = sum_K W (S - S0)^2,
+ *   dS/dr_j   = (2 / rho0) Re[-i k c_j rho(k) exp(-i k.r_j)]
+ *   dL/dr_j   = c_j Re sum_K C(k) exp(-i k.r_j),   C(k) = -4 i k W (S - S0) rho / rho0
+ *   dS/dc_j   = (2 / rho0) Re[rho(k) exp(-i k.r_j)] - (2 c_j / rho0) S(k)   (Eq. weightgradient)
+ *   dL/dc_j   = Re sum_K Cc(k) exp(-i k.r_j) - Fc_j,                        (Eq. lossweightgradient)
+ *               Cc = 4 W (S - S0) rho / rho0,  Fc_j = (4 c_j / rho0) sum_K W S (S - S0).
+ * With c_j = 1 everything reduces to the functions above (rho0 = N).  The
+ * position gradient divides by rho0, the normalisation of S with strengths;
+ * the paper writes N there, the two agreeing for unit strengths.
+ *   grad_pos [G][d], grad_c [G] (either may be NULL) for the points gidx[0..G)
+ *   (gidx NULL: 0..G-1).
+ */
+int oracle_loss_grad_c(int d, long long N, const double* L, const double* pos, const double* c,
+                       long long K, const int* modes, const double* W, const double* S0,
+                       double* S_out, double* loss_out, long long G, const long long* gidx,
+                       double* grad_pos, double* grad_c) {
+  if (d < 1 || d > 3 || N <= 0 || K < 0 || !L || !pos || !c || (K && (!modes || !W || !S0)))
+    return OR_EINVAL;
+  if (G < 0) return OR_EINVAL;
+  double rho0 = 0.0;
+  for (long long j = 0; j < N; ++j) rho0 += c[j] * c[j];
+  if (!(rho0 > 0.0)) return OR_EINVAL;
+  double* rho = (double*)malloc(sizeof(double) * 2 * (K ? K : 1));
+  double* C = (double*)malloc(sizeof(double) * 2 * (d + 1) * (K ? K : 1));
+  if (!rho || !C) { free(rho); free(C); return OR_ENOMEM; }
+  int st = rho_impl(d, N, L, pos, c, K, modes, rho);
+  if (st) { free(rho); free(C); return st; }
+  double loss = 0.0, fsum = 0.0;
+  for (long long q = 0; q < K; ++q) {
+    double S = (rho[2 * q] * rho[2 * q] + rho[2 * q + 1] * rho[2 * q + 1]) / rho0;
+    double res = S - S0[q];
+    loss += W[q] * res * res;
+    fsum += W[q] * S * res;
+    if (S_out) S_out[q] = S;
+    double* Cq = C + 2 * (d + 1) * q;
+    /* C_a = -4 i k_a W res rho / rho0 = (4 k_a W res / rho0) (-i rho) */
+    for (int a = 0; a < d; ++a) {
+      double ka = TWO_PI * (double)modes[q * d + a] / L[a];
+      double f = 4.0 * ka * W[q] * res / rho0;
+      Cq[2 * a] = f * rho[2 * q + 1];
+      Cq[2 * a + 1] = -f * rho[2 * q];
+    }
+    /* Cc = 4 W res rho / rho0 */
+    Cq[2 * d] = 4.0 * W[q] * res / rho0 * rho[2 * q];
+    Cq[2 * d + 1] = 4.0 * W[q] * res / rho0 * rho[2 * q + 1];
+  }
+  if (loss_out) *loss_out = loss;
+  if (G && (grad_pos || grad_c)) {
+    int M[3];
+    mode_extent(d, K, modes, M);
+    long long off[3], tlen = 0;
+    for (int a = 0; a < d; ++a) { off[a] = tlen; tlen += 2 * M[a] + 1; }
+    int fail = 0;
+#pragma omp parallel
+    {
+      double* tab = (double*)malloc(sizeof(double) * 2 * tlen);
+      if (!tab) {
+#pragma omp atomic write
+        fail = 1;
+      } else {
+#pragma omp for schedule(dynamic, 16)
+        for (long long g = 0; g < G; ++g) {
+          long long j = gidx ? gidx[g] : g;
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+          if (j >= 0 && j < N) {
+            point_table(d, L, pos + j * d, M, off, tab);
+            for (long long q = 0; q < K; ++q) {
+              double er, ei;
+              mode_exp(d, modes + q * d, M, off, tab, &er, &ei);
+              const double* Cq = C + 2 * (d + 1) * q;
+              /* Re[x (er - i ei)] = x_re er + x_im ei */
+              for (int a = 0; a <= d; ++a) acc[a] += Cq[2 * a] * er + Cq[2 * a + 1] * ei;
+            }
+          }
+          const double cj = (j >= 0 && j < N) ? c[j] : 0.0;
+          if (grad_pos)
+            for (int a = 0; a < d; ++a) grad_pos[g * d + a] = cj * acc[a];
+          if (grad_c) grad_c[g] = acc[d] - 4.0 * cj / rho0 * fsum;
+        }
+        free(tab);
+      }
+    }
+    if (fail) { free(rho); free(C); return OR_ENOMEM; }
+  }
+  free(rho);
+  free(C);
+  return OR_OK;
+}
+
+/*
+ * Cancellation-free central differences with strengths.  Coordinate entries
+ * ca[c] in 0..d-1 move position r_{j,a} by +-h:
+ *   delta_pm = c_j exp(i k.r_j) (exp(+-i k_a h) - 1),  S_pm - S = [2 Re(conj(rho) delta_pm) + |delta_pm|^2] / rho0;
+ * ca[c] = d moves the strength c_j by +-h, which also changes rho0:
+ *   rho_pm = rho +- h e,  rho0_pm = rho0 +- 2 h c_j + h^2,
+ *   S_pm - S = [rho0 (+-2 h Re(conj(rho) e) + h^2) - |rho|^2 (+-2 h c_j + h^2)] / (rho0 rho0_pm).
+ * Then L_+ - L_- = sum_K W (S_+ - S_-) (S_+ + S_- - 2 S0); out[c] = (L_+ - L_-) / 2h.
+ */
+int oracle_fd_c(int d, long long N, const double* L, const double* pos, const double* c,
+                long long K, const int* modes, const double* W, const double* S0, long long nc,
+                const long long* cj, const int* ca, double h, double* out) {
+  if (d < 1 || d > 3 || N <= 0 || K < 0 || !L || !pos || !c || nc < 0 ||
+      (nc && (!cj || !ca || !out)))
+    return OR_EINVAL;
+  double rho0 = 0.0;
+  for (long long j = 0; j < N; ++j) rho0 += c[j] * c[j];
+  if (!(rho0 > 0.0)) return OR_EINVAL;
+  double* rho = (double*)malloc(sizeof(double) * 2 * (K ? K : 1));
+  if (!rho) return OR_ENOMEM;
+  int st = rho_impl(d, N, L, pos, c, K, modes, rho);
+  if (st) { free(rho); return st; }
+  int M[3];
+  mode_extent(d, K, modes, M);
+  long long off[3], tlen = 0;
+  for (int a = 0; a < d; ++a) { off[a] = tlen; tlen += 2 * M[a] + 1; }
+  int fail = 0;
+#pragma omp parallel
+  {
+    double* tab = (double*)malloc(sizeof(double) * 2 * tlen);
+    if (!tab) {
+#pragma omp atomic write
+      fail = 1;
+    } else {
+#pragma omp for schedule(dynamic, 1)
+      for (long long q0 = 0; q0 < nc; ++q0) {
+        long long j = cj[q0];
+        int a = ca[q0];
+        double dl = 0.0;
+        if (j >= 0 && j < N && a >= 0 && a <= d) {
+          point_table(d, L, pos + j * d, M, off, tab);
+          for (long long q = 0; q < K; ++q) {
+            double er, ei;
+            mode_exp(d, modes + q * d, M, off, tab, &er, &ei);
+            double rr = rho[2 * q], ri = rho[2 * q + 1];
+            double r2 = rr * rr + ri * ri;
+            double S = r2 / rho0, dSp, dSm;
+            if (a < d) {
+              double ka = TWO_PI * (double)modes[q * d + a] / L[a];
+              double t = ka * h;
+              double s2 = sin(0.5 * t);
+              double cm1 = -2.0 * s2 * s2;
+              double sn = sin(t);
+              double ecr = c[j] * er, eci = c[j] * ei;
+              double dpr = ecr * cm1 - eci * sn, dpi = ecr * sn + eci * cm1;
+              double dmr = ecr * cm1 + eci * sn, dmi = -ecr * sn + eci * cm1;
+              dSp = (2.0 * (rr * dpr + ri * dpi) + dpr * dpr + dpi * dpi) / rho0;
+              dSm = (2.0 * (rr * dmr + ri * dmi) + dmr * dmr + dmi * dmi) / rho0;
+            } else {
+              double re = rr * er + ri * ei; /* Re(conj(rho) e) */
+              double r0p = rho0 + 2.0 * h * c[j] + h * h, r0m = rho0 - 2.0 * h * c[j] + h * h;
+              dSp = (rho0 * (2.0 * h * re + h * h) - r2 * (2.0 * h * c[j] + h * h)) / (rho0 * r0p);
+              dSm = (rho0 * (-2.0 * h * re + h * h) - r2 * (-2.0 * h * c[j] + h * h)) / (rho0 * r0m);
+            }
+            dl += W[q] * (dSp - dSm) * (2.0 * S + dSp + dSm - 2.0 * S0[q]);
+          }
+        }
+        out[q0] = dl / (2.0 * h);
+      }
+      free(tab);
+    }
+  }
+  free(rho);
+  return fail ? OR_ENOMEM : OR_OK;
+}
+
+/*
  * Vector-Jacobian product of the structure factor (the derivative of S with
  * respect to a position, Methods, "Analytical gradients"):
  *   dS(k)/dr_ja = (2/N) Re[conj(rho(k)) i k_a exp(i k.r_j)]
@@ -401,6 +584,41 @@ int oracle_pair(int d, long long N, const double* L, const double* pos, double s
       for (int a = 0; a < d; ++a) grad[i * d + a] = acc[a];
   }
   if (energy) *energy = e;
+  return OR_OK;
+}
+
+/*
+ * Central difference of the pair energy in single coordinates, by brute force:
+ * moving point j along axis a changes only the pairs (i, j), so
+ *   (E(r_ja + h) - E(r_ja - h)) / 2h = sum_{i != j} (U(r+_ij) - U(r-_ij)) / 2h,
+ * each pair's difference taken directly (no difference of two large totals).
+ * O(N) per coordinate.  cj, ca: the nc coordinates (point, axis); out [nc].
+ */
+int oracle_pair_fd(int d, long long N, const double* L, const double* pos, double sigma,
+                   double eps, double alpha, long long nc, const long long* cj, const int* ca,
+                   double h, double* out) {
+  int st = pair_check(d, N, L, pos, sigma, alpha);
+  if (st) return st;
+  if (nc < 0 || (nc && (!cj || !ca || !out))) return OR_EINVAL;
+  for (long long c = 0; c < nc; ++c) {
+    const long long j = cj[c];
+    const int a = ca[c];
+    if (j < 0 || j >= N || a < 0 || a >= d) return OR_EINVAL;
+    double rp[3], rm[3];
+    for (int b = 0; b < d; ++b) rp[b] = rm[b] = pos[j * d + b];
+    rp[a] += h;
+    rm[a] -= h;
+    double du = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : du)
+    for (long long i = 0; i < N; ++i) {
+      if (i == j) continue;
+      double up, um, g[3];
+      pair_term(d, L, rp, pos + i * d, sigma, eps, alpha, &up, g);
+      pair_term(d, L, rm, pos + i * d, sigma, eps, alpha, &um, g);
+      du += up - um;
+    }
+    out[c] = du / (2.0 * h);
+  }
   return OR_OK;
 }
 

@@ -72,6 +72,17 @@ def _load():
             f.argtypes = [ctypes.c_int, ll, dp, dp, ctypes.c_double, ctypes.c_double,
                           ctypes.c_double, dp, dp]
             f.restype = ctypes.c_int
+        lib.oracle_pair_fd.argtypes = [ctypes.c_int, ll, dp, dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ll, lp, ip, ctypes.c_double, dp]
+        lib.oracle_pair_fd.restype = ctypes.c_int
+        lib.oracle_rho_c.argtypes = [ctypes.c_int, ll, dp, dp, dp, ll, ip, dp]
+        lib.oracle_rho_c.restype = ctypes.c_int
+        lib.oracle_loss_grad_c.argtypes = [ctypes.c_int, ll, dp, dp, dp, ll, ip, dp, dp, dp, dp,
+                                           ll, lp, dp, dp]
+        lib.oracle_loss_grad_c.restype = ctypes.c_int
+        lib.oracle_fd_c.argtypes = [ctypes.c_int, ll, dp, dp, dp, ll, ip, dp, dp, ll, lp, ip,
+                                    ctypes.c_double, dp]
+        lib.oracle_fd_c.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -252,6 +263,103 @@ def pair(pos, L, sigma: float, eps: float = 1.0, alpha: float = 2.0, cells: bool
     if st:
         raise RuntimeError(f"oracle pair term failed ({st})")
     return float(e[0]), grad
+
+
+def _strengths(c, N):
+    c = np.ascontiguousarray(np.asarray(c, dtype=np.float64).ravel())
+    if c.size != N:
+        raise ValueError("one strength per point")
+    return c
+
+
+def rho_strengths(pos, c, L, modes) -> np.ndarray:
+    """rho(k) = sum_j c_j exp(+i k.r_j) (Methods, Eq. ft) for the listed modes."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    c = _strengths(c, N)
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    out = np.zeros((len(modes), 2))
+    st = _load().oracle_rho_c(d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double),
+                              _p(c, ctypes.c_double), len(modes), _p(modes, ctypes.c_int),
+                              _p(out, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle rho with strengths failed ({st})")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def loss_grad_strengths(pos, c, L, modes, W, S0, grad_points=None, want_grad: bool = True):
+    """Loss with real strengths c (S = |rho|^2 / rho0, rho0 = sum c^2) and its gradients
+    with respect to positions and strengths (Methods, Eqs. losspositiongradient and
+    lossweightgradient).  Returns dict(S, loss, grad [G][d], grad_c [G])."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    c = _strengths(c, N)
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    K = len(modes)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    S0 = np.ascontiguousarray(S0, dtype=np.float64)
+    S = np.zeros(K)
+    loss = np.zeros(1)
+    if not want_grad:
+        G, gidx = 0, None
+    elif grad_points is None:
+        G, gidx = N, None
+    else:
+        gidx = np.ascontiguousarray(grad_points, dtype=np.int64)
+        G = len(gidx)
+    grad = np.zeros((max(G, 1), d))
+    grad_c = np.zeros(max(G, 1))
+    st = _load().oracle_loss_grad_c(d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double),
+                                    _p(c, ctypes.c_double), K, _p(modes, ctypes.c_int),
+                                    _p(W, ctypes.c_double), _p(S0, ctypes.c_double),
+                                    _p(S, ctypes.c_double), _p(loss, ctypes.c_double), G,
+                                    _p(gidx, ctypes.c_longlong), _p(grad, ctypes.c_double),
+                                    _p(grad_c, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle loss with strengths failed ({st})")
+    return {"S": S, "loss": float(loss[0]), "grad": grad[:G], "grad_c": grad_c[:G]}
+
+
+def finite_difference_strengths(pos, c, L, modes, W, S0, coords, h: float) -> np.ndarray:
+    """Cancellation-free central differences of the loss with strengths: coords
+    [(j, a), ...] with a < d a position coordinate and a = d the strength c_j."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    c = _strengths(c, N)
+    modes = np.ascontiguousarray(modes, dtype=np.int32).reshape(-1, d)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    S0 = np.ascontiguousarray(S0, dtype=np.float64)
+    coords = np.asarray(coords, dtype=np.int64).reshape(-1, 2)
+    cj = np.ascontiguousarray(coords[:, 0], dtype=np.int64)
+    ca = np.ascontiguousarray(coords[:, 1], dtype=np.int32)
+    out = np.zeros(len(coords))
+    st = _load().oracle_fd_c(d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double),
+                             _p(c, ctypes.c_double), len(modes), _p(modes, ctypes.c_int),
+                             _p(W, ctypes.c_double), _p(S0, ctypes.c_double), len(coords),
+                             _p(cj, ctypes.c_longlong), _p(ca, ctypes.c_int), float(h),
+                             _p(out, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle finite difference with strengths failed ({st})")
+    return out
+
+
+def pair_finite_difference(pos, L, coords, h: float, sigma: float, eps: float = 1.0,
+                           alpha: float = 2.0) -> np.ndarray:
+    """(E(r_ja + h) - E(r_ja - h)) / 2h of the soft-core energy for coords [(j, a), ...],
+    each from the differences of point j's own pairs (brute force, O(N) each)."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    coords = np.asarray(coords, dtype=np.int64).reshape(-1, 2)
+    cj = np.ascontiguousarray(coords[:, 0], dtype=np.int64)
+    ca = np.ascontiguousarray(coords[:, 1], dtype=np.int32)
+    out = np.zeros(len(coords))
+    st = _load().oracle_pair_fd(d, N, _p(_box(L, d), ctypes.c_double), _p(pos, ctypes.c_double),
+                                float(sigma), float(eps), float(alpha), len(coords),
+                                _p(cj, ctypes.c_longlong), _p(ca, ctypes.c_int), float(h),
+                                _p(out, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle pair finite difference failed ({st})")
+    return out
 
 
 def rho_direct(pos, L, modes, chunk: int = 100_000_000) -> np.ndarray:

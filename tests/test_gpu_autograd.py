@@ -212,3 +212,53 @@ def test_f32_composed_gradient_matches_oracle_sampled(gpu):
     assert abs(float(total) - (r["loss"] + e_p)) < 1e-5 * (r["loss"] + e_p)
     ctx.close()
     pctx.close()
+
+
+def test_composed_loss_finite_differences_full_3d_shape(gpu):
+    # The 3D workload's shape: N = 1e7 points at unit density (L = N^(1/3)),
+    # modes |n| <= 60 (the 250^3 fine grid), soft core of diameter 0.5, FP64
+    # build.  The stealthy weights sit on 96 random constrained modes (and their
+    # mirrors) so that the oracle's direct sums stay affordable; grids, tiles and
+    # launch shapes are those of the full problem.  Spectral loss + pair energy
+    # through one backward, against central differences with h = 1e-4 on 64
+    # random coordinates: the spectral part from the oracle's cancellation-free
+    # differences, the pair part from the differences of each moved point's own
+    # pairs (brute force over all points).
+    import torch
+    from paper_2305_15693_amd import autograd as A
+    from paper_2305_15693_amd import fresco as F
+    d, N, M = 3, 10_000_000, 60
+    L = N ** (1.0 / 3.0)
+    print("composed FD at the full 3D shape: N=1e7 M=60 f64", flush=True)
+    pos_np = I.positions(N, d, L, np.float64, seed=1003)
+    rng = np.random.default_rng(1004)
+    w_full, _ = I.stealthy_target(d, M, float(M))
+    idx = np.flatnonzero(w_full.ravel())
+    w = np.zeros(w_full.size)
+    w[rng.choice(idx, 96, replace=False)] = 1.0
+    w = w.reshape(w_full.shape)
+    w = np.maximum(w, w[::-1, ::-1, ::-1])
+    ctx = F.Context(d, N, L, M, w_cube=w, tol=1e-12, dtype="f64", device=gpu)
+    pctx = F.PairContext(d, N, L, sigma=0.5, eps=1.0, alpha=2.0, dtype="f64", device=gpu)
+    assert ctx.plan_info()["nf"][:3] == [250, 250, 250]
+    pos = _t(gpu, pos_np, "f64").requires_grad_(True)
+    total = A.loss(ctx, pos) + A.soft_core(pctx, pos)
+    total.backward()
+    torch.cuda.synchronize()
+    coords = np.stack([rng.integers(0, N, 64), rng.integers(0, d, 64)], 1)
+    got = pos.grad.detach()[torch.from_numpy(coords[:, 0]).to(gpu),
+                           torch.from_numpy(coords[:, 1]).to(gpu)].cpu().numpy()
+    ctx.close()
+    pctx.close()
+    del pos, total
+    modes, W, S0 = O.constrained_set(d, M, w, None)
+    h = 1e-4
+    fd_s = O.finite_difference(pos_np, L, modes, W, S0, coords, h)
+    fd_p = O.pair_finite_difference(pos_np, L, coords, h, 0.5)
+    fd = fd_s + fd_p
+    e = rel(got, fd)
+    print(f"  {len(modes)} modes, {int(np.count_nonzero(fd_p))} of 64 coordinates with pair terms; "
+          f"autograd vs central differences: {e:.3e} (spectral part alone {rel(got - fd_p, fd_s):.3e})",
+          flush=True)
+    assert np.count_nonzero(fd_p) > 0
+    assert e < 1e-6

@@ -496,6 +496,34 @@ def test_pair_gradient_matches_finite_differences():
     assert checked == 6
 
 
+@pytest.mark.parametrize("alpha", [2.0, 2.5])
+def test_pair_finite_difference_equals_energy_differences(alpha):
+    # The per-coordinate pair difference (only the moved point's pairs) equals the
+    # difference of the whole brute-force energies, and the two-particle closed
+    # form: (U(r+) - U(r-)) / 2h along the pair axis for two isolated particles.
+    rng = np.random.default_rng(43)
+    L = np.array([4.0, 5.0, 3.5])
+    pos = rng.uniform(0, 1, (90, 3)) * L
+    h = 1e-4
+    coords = [(j, a) for j in range(0, 90, 7) for a in range(3)]
+    got = O.pair_finite_difference(pos, L, coords, h, 0.5, 1.2, alpha)
+    ref = []
+    for j, a in coords:
+        pp, pm = pos.copy(), pos.copy()
+        pp[j, a] += h
+        pm[j, a] -= h
+        ref.append((O.pair(pp, L, 0.5, 1.2, alpha)[0] - O.pair(pm, L, 0.5, 1.2, alpha)[0]) / (2 * h))
+    ref = np.array(ref)
+    assert np.abs(ref).max() > 0
+    np.testing.assert_allclose(got, ref, rtol=1e-8, atol=1e-9)
+    two = np.array([[1.0, 1.0, 1.0], [1.3, 1.0, 1.0]])
+    r = 0.3
+    x = lambda rr: 1 - rr / 0.5
+    closed = (1.2 / alpha) * (x(r - h) ** alpha - x(r + h) ** alpha) / (2 * h)
+    assert O.pair_finite_difference(two, L, [(0, 0)], h, 0.5, 1.2, alpha)[0] == \
+        pytest.approx(closed, rel=1e-12)
+
+
 def test_rho_direct_lattice_and_table_form():
     # The direct-evaluation form (used for a few modes over very many points) on a
     # 16 x 16 lattice: |rho| = N exactly on the Bragg peak (16, 0), 0 off it; and it
@@ -526,3 +554,117 @@ def test_loss_grad_from_rho_matches_direct_sums():
     assert r["loss"] == pytest.approx(ref["loss"], rel=1e-12)
     np.testing.assert_allclose(r["S"], ref["S"], rtol=1e-12, atol=1e-13)
     np.testing.assert_allclose(r["grad"], ref["grad"][gp], rtol=1e-11, atol=1e-12)
+
+
+# ------------------------------------------------------------ point strengths
+def _strength_case(N=60, d=2, L=9.0, M=4, seed=90, signed=False):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0, L, (N, d))
+    c = rng.lognormal(0.0, 0.4, N)
+    if signed:
+        c *= rng.choice([-1.0, 1.0], N)
+    modes = _modes_ball(d, float(M))
+    W = rng.uniform(0.5, 1.5, len(modes))
+    S0 = rng.uniform(0.0, 2.0, len(modes))
+    return pos, c, L, modes, W, S0
+
+
+def test_strengths_unit_reduce_to_plain_loss():
+    # c = 1: rho0 = N and every quantity is the plain one
+    pos, _, L, modes, W, S0 = _strength_case()
+    c = np.ones(len(pos))
+    a = O.loss_grad_strengths(pos, c, L, modes, W, S0)
+    b = O.loss_grad(pos, L, modes, W, S0)
+    np.testing.assert_allclose(a["S"], b["S"], rtol=1e-13)
+    assert a["loss"] == pytest.approx(b["loss"], rel=1e-13)
+    np.testing.assert_allclose(a["grad"], b["grad"], rtol=1e-12, atol=1e-13)
+
+
+def test_strengths_rho_is_linear_in_the_strengths():
+    # two points at one position act as one point carrying the sum of their
+    # strengths; rho(0) = sum c
+    rng = np.random.default_rng(91)
+    L = 7.0
+    r = rng.uniform(0, L, (3, 2))
+    modes = np.array([[0, 0], [1, 0], [2, -3], [-1, 4]])
+    a, b, e = 0.7, -1.9, 1.3
+    split = O.rho_strengths(np.stack([r[0], r[0], r[1]]), [a, b, e], L, modes)
+    merged = O.rho_strengths(np.stack([r[0], r[1]]), [a + b, e], L, modes)
+    np.testing.assert_allclose(split, merged, rtol=1e-13, atol=1e-14)
+    assert split[0] == pytest.approx(a + b + e, rel=1e-14)
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_strengths_scale_invariance(signed):
+    # S, L and dL/dr do not change under c -> lambda c; dL/dc scales as 1/lambda
+    pos, c, L, modes, W, S0 = _strength_case(signed=signed)
+    a = O.loss_grad_strengths(pos, c, L, modes, W, S0)
+    b = O.loss_grad_strengths(pos, 3.5 * c, L, modes, W, S0)
+    np.testing.assert_allclose(b["S"], a["S"], rtol=1e-12)
+    assert b["loss"] == pytest.approx(a["loss"], rel=1e-12)
+    np.testing.assert_allclose(b["grad"], a["grad"], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(3.5 * b["grad_c"], a["grad_c"], rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_strengths_euler_identity_and_sum_rule(signed):
+    # L(lambda c) = L(c) for every lambda, so sum_j c_j dL/dc_j = 0; translation
+    # invariance gives sum_j dL/dr_j = 0
+    pos, c, L, modes, W, S0 = _strength_case(signed=signed)
+    r = O.loss_grad_strengths(pos, c, L, modes, W, S0)
+    terms = c * r["grad_c"]
+    assert abs(terms.sum()) <= 1e-12 * np.abs(terms).sum()
+    assert np.abs(r["grad"].sum(0)).max() <= 1e-12 * np.abs(r["grad"]).sum()
+
+
+def test_strengths_two_points_closed_form():
+    # N = 2: S(k) = 1 + 2 c1 c2 cos(k.D) / rho0 with D = r1 - r2, rho0 = c1^2 + c2^2;
+    # dS/dr1 = -2 c1 c2 sin(k.D) k / rho0; dS/dc1 = 2 c2 cos(k.D) / rho0 - 4 c1^2 c2 cos(k.D) / rho0^2
+    rng = np.random.default_rng(92)
+    L = np.array([5.0, 6.5, 4.0])
+    pos = rng.uniform(0, 1, (2, 3)) * L
+    c1, c2 = 1.7, -0.6
+    modes = _modes_ball(3, 2.5)
+    k = 2 * np.pi * modes / L
+    W = rng.uniform(0.5, 1.5, len(modes))
+    S0 = rng.uniform(0.0, 2.0, len(modes))
+    rho0 = c1 * c1 + c2 * c2
+    th = k @ (pos[0] - pos[1])
+    S = 1 + 2 * c1 * c2 * np.cos(th) / rho0
+    G = 2 * W * (S - S0)
+    g1 = np.sum((G * (-2 * c1 * c2 * np.sin(th) / rho0))[:, None] * k, axis=0)
+    gc1 = np.sum(G * (2 * c2 * np.cos(th) / rho0 - 4 * c1 * c1 * c2 * np.cos(th) / rho0 ** 2))
+    gc2 = np.sum(G * (2 * c1 * np.cos(th) / rho0 - 4 * c2 * c2 * c1 * np.cos(th) / rho0 ** 2))
+    r = O.loss_grad_strengths(pos, [c1, c2], L, modes, W, S0)
+    np.testing.assert_allclose(r["S"], S, rtol=1e-13, atol=1e-14)
+    assert r["loss"] == pytest.approx(np.sum(W * (S - S0) ** 2), rel=1e-13)
+    np.testing.assert_allclose(r["grad"][0], g1, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(r["grad"][1], -g1, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(r["grad_c"], [gc1, gc2], rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_strengths_finite_differences(signed):
+    # the analytic gradients against the cancellation-free differences, and those
+    # against plain differences of whole losses
+    pos, c, L, modes, W, S0 = _strength_case(N=40, d=3, L=5.0, M=3, seed=93, signed=signed)
+    r = O.loss_grad_strengths(pos, c, L, modes, W, S0)
+    d = pos.shape[1]
+    coords = [(j, a) for j in (0, 7, 19, 33) for a in range(d + 1)]
+    h = 1e-5
+    fd = O.finite_difference_strengths(pos, c, L, modes, W, S0, coords, h)
+    ana = np.array([r["grad"][j, a] if a < d else r["grad_c"][j] for j, a in coords])
+    np.testing.assert_allclose(fd, ana, rtol=1e-7, atol=1e-9 * np.abs(ana).max())
+    hh = 1e-4
+    for (j, a), f in zip(coords[:6], O.finite_difference_strengths(pos, c, L, modes, W, S0,
+                                                                   coords[:6], hh)):
+        pp, pm, cp, cm = pos.copy(), pos.copy(), c.copy(), c.copy()
+        if a < d:
+            pp[j, a] += hh
+            pm[j, a] -= hh
+        else:
+            cp[j] += hh
+            cm[j] -= hh
+        plain = (O.loss_grad_strengths(pp, cp, L, modes, W, S0, want_grad=False)["loss"] -
+                 O.loss_grad_strengths(pm, cm, L, modes, W, S0, want_grad=False)["loss"]) / (2 * hh)
+        assert f == pytest.approx(plain, rel=1e-6, abs=1e-9)
