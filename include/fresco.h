@@ -160,6 +160,33 @@ int fresco_loss_grad(fresco_ctx* ctx, const void* pos, double* loss, void* grad)
  * the caller's graph.  Errors: EINVAL, EHIP. */
 int fresco_loss_grad_async(fresco_ctx* ctx, const void* pos, double* loss_dev, void* grad);
 
+/* Point strengths (Methods, "Analytical gradients": the density field
+ * sum_j c_j delta(r - r_j); Results: polydisperse packings weigh each particle
+ * by its volume over the mean volume, c_j = V_j / <V>).  With real strengths c_j
+ * of any sign:
+ *   rho(k) = sum_j c_j exp(+i k.r_j),   rho0 = sum_j c_j^2,   S(k) = |rho(k)|^2 / rho0,
+ *   dL/dr_j = c_j Re sum_k C(k) exp(-i k.r_j),  C = -4 i k W (S - S0) rho / rho0,
+ *   dL/dc_j = Re sum_k Cc(k) exp(-i k.r_j) - (4 c_j / rho0) sum_K W S (S - S0),
+ *             Cc = 4 W (S - S0) rho / rho0                (Eq. lossweightgradient).
+ * (The paper's position gradient divides by N; with strengths rho0 is the
+ * normalisation of S, and the two agree for unit strengths.)
+ * fresco_set_strengths copies c (device [n] of the dtype, the caller's point
+ * order) into the context; every later evaluation of the context -- S, the
+ * loss and gradient, the backward of S, fresco_step (positions optimised at
+ * fixed strengths) -- uses them, and S(0) = (sum c)^2 / rho0.  c = NULL returns
+ * to unit strengths.  Synchronises the stream and drops the captured graphs.
+ * Errors: EINVAL (null ctx, a non-finite strength, rho0 = 0), ENOTSUP (grids
+ * sorted in two levels, more than 16384 tiles, or 2D columns too long for one
+ * LDS pass), ENOMEM, EHIP. */
+int fresco_set_strengths(fresco_ctx* ctx, const void* c);
+
+/* Loss, position gradient (device [n][d]) and strength gradient grad_c
+ * (device [n]) with the context's strengths (fresco_set_strengths first;
+ * EINVAL without).  loss: HOST pointer; synchronises and reports non-finite
+ * positions (ENONFINITE).  Errors: EINVAL, EHIP, ENONFINITE. */
+int fresco_loss_grad_strengths(fresco_ctx* ctx, const void* pos, double* loss, void* grad,
+                               void* grad_c);
+
 /* Options of the L-BFGS minimiser (main text, "Algorithm": L-BFGS with a cap on
  * the step and a backtracking line search; the constants are this library's).  Defaults used by the Python layer: m = 8,
  * max_backtracks = 20, max_step = 0.1 L / N^(1/d), c1 = 1e-4, shrink = 0.5,

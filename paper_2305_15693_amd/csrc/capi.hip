@@ -90,7 +90,20 @@ struct State {
   int lb_m = 0;
   LbfgsOpts lb_opts{};
   hipGraphExec_t lb_graph = nullptr;
+  // point strengths (fresco_set_strengths): a copy in the caller's order, the
+  // optimiser's internal order, S normalised by rho0 = sum c^2
+  bool has_str = false;
+  R* cdev = nullptr;
+  R* cint = nullptr;
+  double* cstat = nullptr;      // [3 * kStatBlocks + 3] partials, then sum c^2, max |c|, bad
+  double* fsum_part = nullptr;  // [nloss_part] partials of sum_K W S (S - S0)
+  double rho0 = 0.0, cmax = 1.0;
+  // strengths and field-value output of the evaluation being enqueued
+  const R* str_eval = nullptr;
+  R* val_eval = nullptr;
 };
+
+constexpr int kStatBlocks = 256;
 
 struct GraphEntry {
   const void* pos;
@@ -738,8 +751,12 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
   }
   {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
+    Strengths<R> cs;
+    cs.c = S->str_eval;
+    cs.perm = S->bb.perm;
+    cs.cmax = S->cmax;
     for (int r = 0; r < t.reps; ++r)
-      launch_spread<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, st);
+      launch_spread<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, cs, st);
   }
   if (!S->fold_fused) {
     StageTimer t(c, FRESCO_STAGE_FOLD);
@@ -816,6 +833,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
   last.Wm = S->Wm;
   last.S0m = S->S0m;
   last.loss_part = S->loss_part;
+  last.fsum_part = (mode == COL_FUSED && S->val_eval) ? S->fsum_part : nullptr;
   last.S_cube = S_cube;
   // the backward reads rho saved by the structure-factor pass; a loss
   // evaluation keeps none (it also invalidates the reuse of that pass)
@@ -851,7 +869,12 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
   }
   {
     StageTimer t(c, FRESCO_STAGE_INTERP);
-    for (int r = 0; r < t.reps; ++r) launch_interp<R>(g, S->bp, S->bb, S->v, grad, st);
+    Strengths<R> cs;
+    cs.c = S->str_eval;
+    cs.perm = S->bb.perm;
+    cs.cmax = S->cmax;
+    cs.val = (mode == COL_FUSED) ? S->val_eval : nullptr;
+    for (int r = 0; r < t.reps; ++r) launch_interp<R>(g, S->bp, S->bb, S->v, grad, cs, st);
   }
   // attached soft-core pair term: its gradient is added to grad, its energy to
   // the loss
@@ -870,6 +893,9 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
 
 template <class R>
 int loss_grad_eager(fresco_ctx* c, const void* pos, double* loss_dev, void* grad) {
+  State<R>* S = (State<R>*)c->state;
+  S->str_eval = S->has_str ? S->cdev : nullptr;
+  S->val_eval = nullptr;
   int st;
   if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
   return run_modes_to_grad<R>(c, COL_FUSED, (const R*)pos, nullptr, nullptr, (R*)grad, loss_dev);
@@ -998,7 +1024,13 @@ template <class R>
 int lbfgs_trial(fresco_ctx* c) {
   State<R>* S = (State<R>*)c->state;
   int st;
-  if ((st = loss_grad_eager<R>(c, S->lv.xt, &S->lst->f_trial, S->lv.gt))) return st;
+  // the optimiser's positions are in its internal order, and so are the strengths
+  S->str_eval = S->has_str ? S->cint : nullptr;
+  S->val_eval = nullptr;
+  if ((st = run_bin_spread_rows<R>(c, S->lv.xt))) return st;
+  if ((st = run_modes_to_grad<R>(c, COL_FUSED, S->lv.xt, nullptr, nullptr, S->lv.gt,
+                                 &S->lst->f_trial)))
+    return st;
   launch_lbfgs_update<R>(S->lv, S->lst, S->lb_opts, c->st);
   HIPCHK(hipGetLastError());
   return FRESCO_OK;
@@ -1045,6 +1077,7 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
     S->have_perm0 = true;
   }
   launch_gather_rows<R>((const R*)pos, S->perm0, N, g.d, S->lv.x, c->st);
+  if (S->has_str) launch_gather_rows<R>(S->cdev, S->perm0, N, 1, S->cint, c->st);
   HIPCHK(hipMemcpyAsync(S->lv.xt, S->lv.x, sizeof(R) * N * g.d, hipMemcpyDeviceToDevice, c->st));
   launch_lbfgs_set_mode(S->lst, 4, n_iter, c->st);  // first evaluation of the call
   if ((st = lbfgs_trial<R>(c))) return st;
@@ -1094,6 +1127,8 @@ int structure_factor_impl(fresco_ctx* c, const void* pos, void* Sout) {
   const Geom& g = c->g;
   int st;
   c->sf_pos = nullptr;
+  S->str_eval = S->has_str ? S->cdev : nullptr;
+  S->val_eval = nullptr;
   if ((st = run_bin_spread_rows<R>(c, (const R*)pos))) return st;
   ColParams<R> last = (g.d == 2) ? S->col1 : S->col2;
   last.in[0] = (g.d == 2) ? S->A1 : S->A2;
@@ -1119,10 +1154,172 @@ int structure_factor_impl(fresco_ctx* c, const void* pos, void* Sout) {
 // gradient with dL/dS replaced by the caller's gS.
 template <class R>
 int sf_backward_impl(fresco_ctx* c, const void* pos, const void* gS, void* grad, int reuse) {
+  State<R>* S = (State<R>*)c->state;
   int st;
   if (reuse && c->sf_pos != pos) return FRESCO_EINVAL;
   if (!reuse && (st = structure_factor_impl<R>(c, pos, nullptr))) return st;
+  S->str_eval = S->has_str ? S->cdev : nullptr;
+  S->val_eval = nullptr;
   return run_modes_to_grad<R>(c, COL_BWD, (const R*)pos, nullptr, (const R*)gS, (R*)grad, nullptr);
+}
+
+// ------------------------------------------------------------ strengths
+// Block partials of sum c^2 (FP64), max |c| and a count of non-finite values,
+// in a fixed order (kStatBlocks blocks of 256 threads, grid-stride).
+template <class R>
+__global__ void strength_stats_kernel(const R* __restrict__ c, long long n,
+                                      double* __restrict__ part) {
+  __shared__ double s2[256], sm[256], sb[256];
+  double a = 0.0, m = 0.0, bad = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = (double)c[i];
+    if (!isfinite(v)) {
+      bad += 1.0;
+      continue;
+    }
+    a += v * v;
+    m = fmax(m, fabs(v));
+  }
+  s2[threadIdx.x] = a;
+  sm[threadIdx.x] = m;
+  sb[threadIdx.x] = bad;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      s2[threadIdx.x] += s2[threadIdx.x + off];
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + off]);
+      sb[threadIdx.x] += sb[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s2[0];
+    part[gridDim.x + blockIdx.x] = sm[0];
+    part[2 * gridDim.x + blockIdx.x] = sb[0];
+  }
+}
+__global__ void strength_stats_final_kernel(double* part, int nb) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0, m = 0.0, bad = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    a += part[b];
+    m = fmax(m, part[nb + b]);
+    bad += part[2 * nb + b];
+  }
+  part[3 * nb] = a;
+  part[3 * nb + 1] = m;
+  part[3 * nb + 2] = bad;
+}
+
+// dL/dc_j = F(r_j) - (4 c_j / rho0) sum_K W S (S - S0) (Methods, Eq.
+// lossweightgradient), in place over the field values F(r_j); every block sums
+// the mode-stage partials in the same order.
+template <class R>
+__global__ void strength_grad_kernel(R* __restrict__ gc, const R* __restrict__ c, long long n,
+                                     const double* __restrict__ fpart, long long np,
+                                     double four_over_rho0) {
+  __shared__ double fs;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (long long i = 0; i < np; ++i) t += fpart[i];
+    fs = t * four_over_rho0;
+  }
+  __syncthreads();
+  const R f = (R)fs;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    gc[i] = gc[i] - f * c[i];
+}
+
+template <class R>
+void set_inv_norm(fresco_ctx* c, double norm) {
+  State<R>* S = (State<R>*)c->state;
+  const R inv = (R)(1.0 / norm);
+  S->col1.invN = inv;
+  S->col2.invN = inv;
+  S->lfw.invN = inv;
+  S->linv.invN = inv;
+}
+
+// drop every captured graph (their launch parameters changed)
+template <class R>
+void drop_graphs(fresco_ctx* c) {
+  State<R>* S = (State<R>*)c->state;
+  for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
+  c->graphs.clear();
+  if (S->lb_graph) {
+    (void)hipGraphExecDestroy(S->lb_graph);
+    S->lb_graph = nullptr;
+  }
+}
+
+template <class R>
+int set_strengths_impl(fresco_ctx* c, const void* cin) {
+  State<R>* S = (State<R>*)c->state;
+  const long long N = c->g.N;
+  HIPCHK(hipStreamSynchronize(c->st));
+  drop_graphs<R>(c);
+  c->sf_pos = nullptr;
+  if (!cin) {
+    S->has_str = false;
+    S->rho0 = 0.0;
+    S->cmax = 1.0;
+    set_inv_norm<R>(c, (double)N);
+    return FRESCO_OK;
+  }
+  int st;
+  if (!S->cdev) {
+    if ((st = dalloc_t(c, &S->cdev, N))) return st;
+    if ((st = dalloc_t(c, &S->cint, N))) return st;
+    if ((st = dalloc_t(c, &S->cstat, 3 * kStatBlocks + 3))) return st;
+    if ((st = dalloc_t(c, &S->fsum_part, S->nloss_part))) return st;
+  }
+  HIPCHK(hipMemcpyAsync(S->cdev, cin, sizeof(R) * N, hipMemcpyDeviceToDevice, c->st));
+  strength_stats_kernel<R><<<kStatBlocks, 256, 0, c->st>>>(S->cdev, N, S->cstat);
+  strength_stats_final_kernel<<<1, 64, 0, c->st>>>(S->cstat, kStatBlocks);
+  HIPCHK(hipGetLastError());
+  double h[3];
+  HIPCHK(hipMemcpyAsync(h, S->cstat + 3 * kStatBlocks, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (h[2] != 0.0 || !(h[0] > 0.0) || !std::isfinite(h[0])) {
+    S->has_str = false;
+    set_inv_norm<R>(c, (double)N);
+    return FRESCO_EINVAL;
+  }
+  S->has_str = true;
+  S->rho0 = h[0];
+  S->cmax = h[1];
+  set_inv_norm<R>(c, h[0]);
+  return FRESCO_OK;
+}
+
+// loss, position gradient and strength gradient with the context's strengths
+// (eager: the strength gradient is an occasional request)
+template <class R>
+int loss_grad_strengths_impl(fresco_ctx* c, const void* pos, double* loss, void* grad,
+                             void* grad_c) {
+  State<R>* S = (State<R>*)c->state;
+  if (!S->has_str) return FRESCO_EINVAL;
+  c->sf_pos = nullptr;
+  S->str_eval = S->cdev;
+  S->val_eval = (R*)grad_c;
+  int st = run_bin_spread_rows<R>(c, (const R*)pos);
+  if (!st) st = run_modes_to_grad<R>(c, COL_FUSED, (const R*)pos, nullptr, nullptr, (R*)grad,
+                                     S->loss_dev);
+  S->val_eval = nullptr;
+  if (st) return st;
+  long long blocks = (c->g.N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  strength_grad_kernel<R><<<(unsigned)blocks, 256, 0, c->st>>>(
+      (R*)grad_c, S->cdev, c->g.N, S->fsum_part, S->nloss_part, 4.0 / S->rho0);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->host_loss, S->loss_dev, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(c->host_flag, S->flag_out, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  *loss = *c->host_loss;
+  if (*c->host_flag) return FRESCO_ENONFINITE;
+  return FRESCO_OK;
 }
 
 }  // namespace
@@ -1436,6 +1633,30 @@ int fresco_attach_pair(fresco_ctx* c, fresco_pair_ctx* pc, double weight) {
   c->pair = pc;
   c->pair_w = pc ? weight : 0.0;
   return FRESCO_OK;
+}
+
+int fresco_set_strengths(fresco_ctx* c, const void* cs) {
+  if (!c) return FRESCO_EINVAL;
+  // the signed spreading words take 8 bytes per cell of the padded tile
+  if (c->dtype == FRESCO_F32) {
+    State<float>* S = (State<float>*)c->state;
+    if (cs && (S->bp.mode == BIN_RANGES || S->long_cols ||
+               spread_lds_bytes<float>(c->g, true) > (size_t)kMaxSpreadLds))
+      return FRESCO_ENOTSUP;
+    return set_strengths_impl<float>(c, cs);
+  }
+  State<double>* S = (State<double>*)c->state;
+  if (cs && (S->bp.mode == BIN_RANGES || S->long_cols ||
+             spread_lds_bytes<double>(c->g, true) > (size_t)kMaxSpreadLds))
+    return FRESCO_ENOTSUP;
+  return set_strengths_impl<double>(c, cs);
+}
+
+int fresco_loss_grad_strengths(fresco_ctx* c, const void* pos, double* loss, void* grad,
+                               void* grad_c) {
+  if (!c || !pos || !loss || !grad || !grad_c) return FRESCO_EINVAL;
+  if (c->dtype == FRESCO_F32) return loss_grad_strengths_impl<float>(c, pos, loss, grad, grad_c);
+  return loss_grad_strengths_impl<double>(c, pos, loss, grad, grad_c);
 }
 
 int fresco_reset_history(fresco_ctx* c) {

@@ -170,24 +170,41 @@ struct FoldTables {
   const int2* ent[3];
 };
 
+// Point strengths of an evaluation (Methods, "Analytical gradients": the density
+// sum_j c_j delta(r - r_j)); c == NULL means unit strengths.
+//   c     strengths in the caller's order of the evaluation's positions
+//   perm  sorted record -> caller index (the binning's permutation)
+//   cmax  max |c| (fixed-point range of the spreading)
+//   val   if not NULL: the field's value at each point (caller's order), for
+//         the gradient with respect to the strengths
+template <class R>
+struct Strengths {
+  const R* c = nullptr;
+  const int* perm = nullptr;
+  double cmax = 1.0;
+  R* val = nullptr;
+};
+// Largest dynamic LDS of a spreading workgroup (bytes).
+constexpr int kMaxSpreadLds = 160 * 1024;
+
 // Launchers exported by the translation units (all enqueue on `st`).
 void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, BinBuffers& b,
                 hipStream_t st);
 template <class R>
-size_t spread_lds_bytes(const Geom& g);
+size_t spread_lds_bytes(const Geom& g, bool str);
 template <class R>
 size_t interp_lds_bytes(const Geom& g);
 template <class R>
 hipError_t spread_prepare(const Geom& g);
 template <class R>
-void launch_spread(const Geom& g, const Rec<R>* rec,
-                   const long long* start, R* tiles, hipStream_t st);
+void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* tiles,
+                   const Strengths<R>& cs, hipStream_t st);
 template <class R>
 void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, hipStream_t st);
 // interpolation of the field v at the binned points into grad (caller's order)
 template <class R>
 void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const R* v, R* grad,
-                   hipStream_t st);
+                   const Strengths<R>& cs, hipStream_t st);
 // out[j] = caller index of sorted record j
 void launch_sorted_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, int* out,
                          hipStream_t st);

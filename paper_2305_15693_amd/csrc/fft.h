@@ -74,6 +74,7 @@ struct ColParams {
   const R* Wm;
   const R* S0m;
   double* loss_part; // one partial per block (FUSED)
+  double* fsum_part; // optional (FUSED): one partial of sum_K W S (S - S0) per block
   R* S_cube;         // optional full-cube S
   cpx<R>* rho_save;  // optional half-spectrum rho (written by FUSED / SF, read by BWD)
   const R* g_cube;   // BWD: dL/dS on the full cube

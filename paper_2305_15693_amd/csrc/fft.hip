@@ -379,7 +379,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
   }
 
   // ---- mode stage
-  double lsum = 0.0;
+  double lsum = 0.0, fsum = 0.0;
   if (active) {
     // dk, dik: kernel factors of the last axis at |n_last|
     auto mode_body = [&](int m, R wp, R wm, R s0p, R s0m, R dk, R dik) {
@@ -420,6 +420,10 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
           // lists both members of every pair itself
           lsum += (double)wp * (double)rp * (double)rp;
           if (n0 > 0) lsum += (double)wm * (double)rm * (double)rm;
+          if (p.fsum_part) {
+            fsum += (double)wp * (double)S * (double)rp;
+            if (n0 > 0) fsum += (double)wm * (double)S * (double)rm;
+          }
           G = wp * rp + wm * rm;
         } else {
           // S(0) = N does not depend on the positions
@@ -460,6 +464,18 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       double t = 0.0;
       for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
       p.loss_part[blockIdx.x] = t;
+    }
+    if (p.fsum_part) {  // uniform: the strength gradient's sum, same order
+      __syncthreads();
+      double f = fsum;
+      for (int off = 32; off > 0; off >>= 1) f += __shfl_down(f, off, 64);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = f;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+        p.fsum_part[blockIdx.x] = t;
+      }
     }
   }
   // inverse transform of the field coefficients along this axis

@@ -659,10 +659,15 @@ __device__ __forceinline__ void add_row_pairs(uint32_t* acc, int rb, const uint3
 }
 
 
-template <class R, int D, int W>
+// STR: point strengths c_j (any sign), read through the permutation; every cell
+// is then one 64-bit two's-complement fixed-point word (in FP32 too), which adds
+// signed contributions exactly; the scale also covers max |c|.
+template <class R, int D, int W, bool STR>
 __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
-                              const long long* __restrict__ start, R* __restrict__ tiles) {
-  constexpr bool F32 = sizeof(R) == 4;
+                              const long long* __restrict__ start, R* __restrict__ tiles,
+                              const R* __restrict__ cstr, const int* __restrict__ perm,
+                              double cmax) {
+  constexpr bool F32 = sizeof(R) == 4 && !STR;  // 32-bit cells added in pairs
   extern __shared__ unsigned long long smem_u64[];
   uint32_t* acc32 = reinterpret_cast<uint32_t*>(smem_u64);
   unsigned long long* acc64 = smem_u64;
@@ -754,13 +759,17 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
     if (F32) acc32[c] = 0u;
     else acc64[c] = 0ull;
   }
-  const int ex = fixed_exponent((long long)cov, F32 ? 31 : 63);
+  // with strengths every contribution is at most max |c| in magnitude, and the
+  // signed words keep one bit for the sign
+  const int ex = STR ? (int)floor(log2(ldexp(1.0, 62) / ((double)(cov + 1) * cmax)))
+                     : fixed_exponent((long long)cov, F32 ? 31 : 63);
   const R scale = (R)ldexp(1.0, ex);
-  const R inv_scale = (R)ldexp(1.0, -ex);
+  const double inv_scale = ldexp(1.0, -ex);
   const R beta = (R)g.beta;
   __syncthreads();
   for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
     const Rec<R> p = rec[j];
+    const R cj = STR ? cstr[perm[j]] * scale : scale;
     R k0[W], k1[W], k2[W];
     spread_weights<R, W>(p.t[0], beta, k0);
     spread_weights<R, W>(p.t[1], beta, k1);
@@ -768,7 +777,7 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
     const int l0 = p.cell & 0xff, l1 = (p.cell >> 8) & 0xff, l2 = (p.cell >> 16) & 0xff;
     const int zmax = (D == 3) ? W : 1;
     for (int dz = 0; dz < zmax; ++dz) {
-      const R pz = (D == 3) ? k2[dz] * scale : scale;
+      const R pz = (D == 3) ? k2[dz] * cj : cj;
 #pragma unroll
       for (int dy = 0; dy < W; ++dy) {
         const R py = k1[dy] * pz;
@@ -778,6 +787,11 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
 #pragma unroll
           for (int dx = 0; dx < W; ++dx) q[dx] = __float2uint_rn((float)(py * k0[dx]));
           add_row_pairs<W>(acc32, rb, q);
+        } else if (STR) {
+#pragma unroll
+          for (int dx = 0; dx < W; ++dx)
+            atomicAdd(acc64 + rb + dx,
+                      (unsigned long long)(long long)llrint((double)(py * k0[dx])));
         } else {
 #pragma unroll
           for (int dx = 0; dx < W; ++dx)
@@ -788,8 +802,9 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
   }
   __syncthreads();
   for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-    if (F32) out[c] = (R)acc32[c] * inv_scale;
-    else out[c] = (R)acc64[c] * inv_scale;
+    if (F32) out[c] = (R)((R)acc32[c] * (R)inv_scale);
+    else if (STR) out[c] = (R)((double)(long long)acc64[c] * inv_scale);
+    else out[c] = (R)((R)acc64[c] * (R)inv_scale);
   }
 }
 
@@ -878,7 +893,8 @@ __global__ __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(interp_min_waves<R, D, W>())))
 void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, const int* __restrict__ perm,
-                              const R* __restrict__ v, R* __restrict__ grad) {
+                              const R* __restrict__ v, R* __restrict__ grad,
+                              const R* __restrict__ cstr, R* __restrict__ val) {
   constexpr int WI = W + 1;
   constexpr bool F32 = sizeof(R) == 4;
   constexpr int NQ = interp_row_words(WI);
@@ -1011,7 +1027,7 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
         d0s[k] = b;
       }
     }
-    R gx = R(0), gy = R(0), gz = R(0);
+    R gx = R(0), gy = R(0), gz = R(0), gv = R(0);
     const int zmax = (D == 3) ? WI : 1;
     for (int dz = 0; dz < zmax; ++dz) {
       R sxy = R(0), sdxy = R(0), sxdy = R(0);
@@ -1063,22 +1079,34 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
         gx += sdxy * f2[dz];
         gy += sxdy * f2[dz];
         gz += sxy * d2[dz];
+        gv += sxy * f2[dz];
       } else {
         gx = sdxy;
         gy = sxdy;
+        gv = sxy;
       }
     }
+    // point strengths scale the position gradient (the field's value, for the
+    // strength gradient, is not scaled)
+    R sg[3] = {gs[0], gs[1], gs[2]};
+    if (cstr) {
+      const R cq = cstr[q];
+      sg[0] *= cq;
+      sg[1] *= cq;
+      sg[2] *= cq;
+    }
+    if (val) val[q] = gv;
     const long long o = (long long)q * D;
     if (D == 2 && pair_store) {
       using V2 = typename std::conditional<sizeof(R) == 4, float2, double2>::type;
       V2 w2;
-      w2.x = gx * gs[0];
-      w2.y = gy * gs[1];
+      w2.x = gx * sg[0];
+      w2.y = gy * sg[1];
       reinterpret_cast<V2*>(grad)[q] = w2;
     } else {
-      grad[o] = gx * gs[0];
-      grad[o + 1] = gy * gs[1];
-      if (D == 3) grad[o + 2] = gz * gs[2];
+      grad[o] = gx * sg[0];
+      grad[o + 1] = gy * sg[1];
+      if (D == 3) grad[o + 2] = gz * sg[2];
     }
   }
 }
@@ -1106,10 +1134,10 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
 // accumulator (ncell + 2 words), then the coverage bound's row sums (Tb Ea
 // 32-bit words over the last two axes)
 template <class R>
-size_t spread_lds_bytes(const Geom& g) {
+size_t spread_lds_bytes(const Geom& g, bool str) {
   size_t ncell = (size_t)g.E[0] * g.E[1] * (g.d == 3 ? g.E[2] : 1);
   const size_t Ta = (g.d == 3) ? g.T[1] : g.T[0], Tb = (g.d == 3) ? g.T[2] : g.T[1];
-  return (ncell + 2) * (sizeof(R) == 4 ? 4 : 8) + Tb * (Ta + g.w - 1) * 4;
+  return (ncell + 2) * (sizeof(R) == 4 && !str ? 4 : 8) + Tb * (Ta + g.w - 1) * 4;
 }
 template <class R>
 size_t interp_lds_bytes(const Geom& g) {
@@ -1125,7 +1153,8 @@ size_t interp_lds_bytes(const Geom& g) {
 // the first failure
 template <class R>
 hipError_t spread_prepare(const Geom& g) {
-  const int sl = (int)spread_lds_bytes<R>(g), il = (int)interp_lds_bytes<R>(g);
+  const int sl = (int)spread_lds_bytes<R>(g, false), il = (int)interp_lds_bytes<R>(g);
+  const int slc = (int)spread_lds_bytes<R>(g, true);
   hipError_t e = hipSuccess;
   auto lds = [&e](const void* f, int bytes) {
     if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -1133,11 +1162,15 @@ hipError_t spread_prepare(const Geom& g) {
 #define PREP(W)                                                 \
   do {                                                          \
     if (g.d == 2) {                                             \
-      lds((const void*)spread_kernel<R, 2, W>, sl);             \
+      lds((const void*)spread_kernel<R, 2, W, false>, sl);      \
       lds((const void*)interp_kernel<R, 2, W>, il);             \
+      if (slc <= kMaxSpreadLds)                                 \
+        lds((const void*)spread_kernel<R, 2, W, true>, slc);    \
     } else {                                                    \
-      lds((const void*)spread_kernel<R, 3, W>, sl);             \
+      lds((const void*)spread_kernel<R, 3, W, false>, sl);      \
       lds((const void*)interp_kernel<R, 3, W>, il);             \
+      if (slc <= kMaxSpreadLds)                                 \
+        lds((const void*)spread_kernel<R, 3, W, true>, slc);    \
     }                                                           \
   } while (0)
   FRESCO_W_SWITCH(g.w, PREP)
@@ -1148,18 +1181,25 @@ hipError_t spread_prepare(const Geom& g) {
 }
 
 template <class R>
-void launch_spread(const Geom& g, const Rec<R>* rec,
-                   const long long* start, R* tiles, hipStream_t st) {
-  const size_t lds = spread_lds_bytes<R>(g);
+void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* tiles,
+                   const Strengths<R>& cs, hipStream_t st) {
+  const bool str = cs.c != nullptr;
+  const size_t lds = spread_lds_bytes<R>(g, str);
   const int threads = 512;  // (2D: 26.7 -> 23.5 us against 256)
 #define SP(W)                                                                                 \
   do {                                                                                        \
-    if (g.d == 2)                                                                             \
-      spread_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
-                                                                      tiles);                 \
+    if (g.d == 2 && !str)                                                                     \
+      spread_kernel<R, 2, W, false><<<(unsigned)g.nbins, threads, lds, st>>>(                \
+          g, rec, start, tiles, nullptr, nullptr, 1.0);                                       \
+    else if (g.d == 2)                                                                        \
+      spread_kernel<R, 2, W, true><<<(unsigned)g.nbins, threads, lds, st>>>(                 \
+          g, rec, start, tiles, cs.c, cs.perm, cs.cmax);                                      \
+    else if (!str)                                                                            \
+      spread_kernel<R, 3, W, false><<<(unsigned)g.nbins, threads, lds, st>>>(                \
+          g, rec, start, tiles, nullptr, nullptr, 1.0);                                       \
     else                                                                                      \
-      spread_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
-                                                                      tiles);                 \
+      spread_kernel<R, 3, W, true><<<(unsigned)g.nbins, threads, lds, st>>>(                 \
+          g, rec, start, tiles, cs.c, cs.perm, cs.cmax);                                      \
   } while (0)
   FRESCO_W_SWITCH(g.w, SP)
 #undef SP
@@ -1176,7 +1216,7 @@ void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, h
 
 template <class R>
 void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const R* v, R* grad,
-                   hipStream_t st) {
+                   const Strengths<R>& cs, hipStream_t st) {
   const size_t lds = interp_lds_bytes<R>(g);
   const int threads = (g.d == 3) ? 512 : 256;
   const Rec<R>* rec = (const Rec<R>*)b.rec;
@@ -1188,11 +1228,11 @@ void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const 
 #define IP(W)                                                                                 \
   do {                                                                                        \
     if (g.d == 2)                                                                             \
-      interp_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
-                                                                      perm, v, out);          \
+      interp_kernel<R, 2, W><<<(unsigned)g.nbins, threads, lds, st>>>(                       \
+          g, rec, start, perm, v, out, cs.c, cs.val);                                         \
     else                                                                                      \
-      interp_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start,      \
-                                                                      perm, v, out);          \
+      interp_kernel<R, 3, W><<<(unsigned)g.nbins, threads, lds, st>>>(                       \
+          g, rec, start, perm, v, out, cs.c, cs.val);                                         \
   } while (0)
   FRESCO_W_SWITCH(g.w, IP)
 #undef IP
@@ -1311,23 +1351,23 @@ void launch_sorted_index(const Geom& g, const BinPlan& bp, const BinBuffers& b, 
     (void)hipMemcpyAsync(out, b.perm, sizeof(int) * g.N, hipMemcpyDeviceToDevice, st);
 }
 
-template size_t spread_lds_bytes<float>(const Geom&);
-template size_t spread_lds_bytes<double>(const Geom&);
+template size_t spread_lds_bytes<float>(const Geom&, bool);
+template size_t spread_lds_bytes<double>(const Geom&, bool);
 template size_t interp_lds_bytes<float>(const Geom&);
 template size_t interp_lds_bytes<double>(const Geom&);
 template hipError_t spread_prepare<float>(const Geom&);
 template hipError_t spread_prepare<double>(const Geom&);
-template void launch_spread<float>(const Geom&, const Rec<float>*,
-                                   const long long*, float*, hipStream_t);
-template void launch_spread<double>(const Geom&, const Rec<double>*,
-                                    const long long*, double*, hipStream_t);
+template void launch_spread<float>(const Geom&, const Rec<float>*, const long long*, float*,
+                                   const Strengths<float>&, hipStream_t);
+template void launch_spread<double>(const Geom&, const Rec<double>*, const long long*, double*,
+                                    const Strengths<double>&, hipStream_t);
 template void launch_fold<float>(const Geom&, const float*, float*, const FoldTables&,
                                  hipStream_t);
 template void launch_fold<double>(const Geom&, const double*, double*, const FoldTables&,
                                   hipStream_t);
 template void launch_interp<float>(const Geom&, const BinPlan&, const BinBuffers&, const float*,
-                                   float*, hipStream_t);
+                                   float*, const Strengths<float>&, hipStream_t);
 template void launch_interp<double>(const Geom&, const BinPlan&, const BinBuffers&,
-                                    const double*, double*, hipStream_t);
+                                    const double*, double*, const Strengths<double>&, hipStream_t);
 
 }  // namespace fresco

@@ -118,6 +118,10 @@ def _load():
     lib.fresco_step.restype = i
     lib.fresco_reset_history.argtypes = [vp]
     lib.fresco_reset_history.restype = i
+    lib.fresco_set_strengths.argtypes = [vp, vp]
+    lib.fresco_set_strengths.restype = i
+    lib.fresco_loss_grad_strengths.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp]
+    lib.fresco_loss_grad_strengths.restype = i
     lib.fresco_set_timing.argtypes = [vp, ctypes.c_uint32]
     lib.fresco_set_timing.restype = i
     lib.fresco_set_timing_reps.argtypes = [vp, ctypes.c_int32]
@@ -289,6 +293,32 @@ class Context:
 
     def reset_history(self):
         _check(_lib.fresco_reset_history(self._h), "fresco_reset_history")
+
+    def set_strengths(self, c):
+        """Point strengths for every later evaluation (a [n] tensor of the context's
+        dtype on its device; the context keeps a copy), or None for unit strengths."""
+        if c is None:
+            _check(_lib.fresco_set_strengths(self._h, None), "fresco_set_strengths")
+            return
+        if c.device != self.device or c.dtype != self.torch_dtype or c.numel() != self.n \
+                or not c.is_contiguous():
+            raise ValueError(f"strengths must be a contiguous [{self.n}] {self.torch_dtype} "
+                             f"tensor on {self.device}")
+        _check(_lib.fresco_set_strengths(self._h, ctypes.c_void_p(c.data_ptr())),
+               "fresco_set_strengths")
+
+    def loss_grad_strengths(self, pos, grad=None, grad_c=None):
+        """(loss, dL/dr [n][d], dL/dc [n]) with the strengths set on the context."""
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty((self.n, self.dim), dtype=self.torch_dtype, device=self.device)
+        if grad_c is None:
+            grad_c = torch.empty((self.n,), dtype=self.torch_dtype, device=self.device)
+        _check(_lib.fresco_loss_grad_strengths(self._h, self._pos(pos), ctypes.byref(self._loss),
+                                               ctypes.c_void_p(grad.data_ptr()),
+                                               ctypes.c_void_p(grad_c.data_ptr())),
+               "fresco_loss_grad_strengths")
+        return float(self._loss.value), grad, grad_c
 
     def set_timing(self, stages, reps: int = 1):
         """Bracket the named stages (see STAGES) with HIP events; [] turns it off.

@@ -95,6 +95,20 @@ def ragged_batch(nb: int = 256, nmin: int = 1000, nmax: int = 100_000, kcut: int
                  seed=seed * 1000 + b) for b in range(nb)]
 
 
+def polydisperse_strengths(N: int, d: int, seed: int = 0, ratio: float = 1.4,
+                           signed: bool = False) -> np.ndarray:
+    """Strengths of a 50:50 bidisperse packing of diameters 1 and `ratio`: each
+    particle weighs its volume over the mean volume, c = D^d / <D^d> (float64).
+    signed=True flips a random half of them (a real field of either sign)."""
+    rng = np.random.default_rng(seed)
+    D = np.where(rng.random(N) < 0.5, 1.0, ratio)
+    v = D ** d
+    c = v / v.mean()
+    if signed:
+        c = c * rng.choice([-1.0, 1.0], N)
+    return c
+
+
 def square_lattice(m: int, L: float, d: int = 2, shift=None, dtype=np.float64) -> np.ndarray:
     """m^d points on a simple cubic lattice of spacing L/m (optionally shifted)."""
     ax = (np.arange(m, dtype=np.float64) + 0.0) * (L / m)
