@@ -12,8 +12,13 @@ Inputs are resident in device memory before timing starts.
 Prints one JSON line.  Besides the throughput it carries:
   plain_eval    stateless evaluations (fresco_loss_grad_async) per second on the
                 same workload, points in the caller's random order;
-  roofline      achieved algorithmic GB/s of the dominant kernel, timed with HIP
-                events on the library's stream, against the 8 TB/s HBM peak;
+  roofline      the dominant kernel, timed with HIP events on the library's
+                stream: algorithmic bytes against the 8 TB/s HBM peak and
+                algorithmic flops against the vector ALU peak (the bound is the
+                larger fraction; the spreading and interpolation kernels are
+                bound by vector-instruction issue), the measured VALU issue
+                fraction, and whether the working set fits in the 256 MB
+                Infinity Cache (the 2D workload's does);
   cpu_baseline  the FP64 direct-sum oracle timed on this host's cores on a
                 bounded sample (all modes for a subset of the points), scaled
                 to one full evaluation;
@@ -24,6 +29,8 @@ Prints one JSON line.  Besides the throughput it carries:
                 the mode stage inside);
   copy_gbs      a plain 1 GiB device copy timed on this GPU (the achievable
                 streaming rate; the roofline also reports its fraction of it);
+  fp64_context  plain evaluations per second of the same workload in the FP64
+                build at tolerance 1e-12;
   secondary     the same measurements for the 3D workload (N = 1e7), plus the
                 torch.autograd evaluation of spectral loss + soft-core pair
                 term in one backward;
@@ -41,7 +48,36 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loss+grad evals/sec (N=1e6 2D, N=1e7 3D) + spread/interp HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak without packed FP32 (this library's device code is built with
+# packed FP32 off): 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.
+# The 157.3 TFLOP/s datasheet FP32 figure needs packed FP32 (two lanes' worth
+# per instruction); FP64 vector is 78.6 either way.
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+ALU_PEAK_DATASHEET = {"f32": 157.3, "f64": 78.6}
+# wave64 vector instructions the chip issues per second (1024 SIMDs, one every
+# 4 cycles each)
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
+INFINITY_CACHE_MB = 256.0
 DOM_REPS = 30  # launches of the dominant spread / interp kernel per timing bracket
+KERNEL_POLY_FMAS = 9  # FP32 kernel values: degree-9 polynomials per cell and axis
+
+
+def stage_flops(cfg, info):
+    """Algorithmic flops per point of the spreading and interpolation kernels: the
+    kernel values along each axis (degree-9 polynomials; with their derivatives
+    for the interpolation, at width w + 1) and the tensor-product contraction.
+      spread:  d w polynomials + the w + w^2 (+ w^3) footprint products
+      interp:  2 d wi polynomials + 2 wi^d row FMAs + 3 wi^(d-1) (+ 4 wi in 3D)
+    (FMA = 2 flops)."""
+    d, N = cfg["d"], cfg["N"]
+    w = info["width"]
+    wi = w + 1
+    sp = 2 * KERNEL_POLY_FMAS * d * w + sum(w ** k for k in range(1, d + 1))
+    if d == 2:
+        ip = 2 * (2 * KERNEL_POLY_FMAS * d * wi + 2 * wi ** 2 + 3 * wi)
+    else:
+        ip = 2 * (2 * KERNEL_POLY_FMAS * d * wi + 2 * wi ** 3 + 3 * wi ** 2 + 4 * wi)
+    return {"spread": sp * N, "interp": ip * N, "per_point": {"spread": sp, "interp": ip}}
 
 
 def stage_bytes(cfg, info, dtype_bytes):
@@ -114,6 +150,21 @@ def measured_traffic(workload, stage):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
+def measured_valu(workload, stage):
+    """Wave64 vector instructions per launch of a stage's kernel from the committed
+    counter summary (SQ_INSTS_VALU), or None when there is none or the kernel's
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    k = t.get("kernels", {}).get(stage)
+    if not k or k.get("source_sha256") != stage_source_hash(stage):
+        return None
+    return k["valu_insts"]
+
+
 def copy_rate(dev):
     """GB/s of a plain 1 GiB device-to-device copy (bytes read + written)."""
     import torch
@@ -158,6 +209,77 @@ def rocfft_compare(nf, stages_ms, dev, reps=20):
     return {"grid": list(nf), "rfftn_ms": e[0].elapsed_time(e[1]) / reps,
             "irfftn_ms": e[1].elapsed_time(e[2]) / reps,
             "ours_fft_chain_ms": sum(stages_ms[k] for k in chain), "ours_stages": chain}
+
+
+def roofline(name, cfg, info, kernel, avg_ms, alg_bytes):
+    """Roofline of the dominant kernel: HBM (algorithmic bytes / 8 TB/s) and vector
+    ALU (algorithmic flops / the non-packed FP32 or FP64 peak) fractions; the
+    bound is the larger.  The measured VALU issue fraction (instructions from the
+    committed counters over the chip's issue rate, against the same duration) is
+    reported beside them.  The working set of the context (its device scratch,
+    positions and gradient) is compared with the 256 MB Infinity Cache: below it,
+    the bytes stream from that cache rather than from HBM."""
+    dt = 4 if cfg["dtype"] == "f32" else 8
+    gbs = alg_bytes / (avg_ms * 1e-3) / 1e9
+    hbm = {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+           "algorithmic_bytes": alg_bytes, "traffic": measured_traffic(name, kernel)}
+    fl = stage_flops(cfg, info)
+    alu = None
+    if kernel in ("spread", "interp"):
+        tf = fl[kernel] / (avg_ms * 1e-3) / 1e12
+        ds = ALU_PEAK_DATASHEET[cfg["dtype"]]
+        alu = {"achieved": tf, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": tf / ALU_PEAK_TFLOPS, "flops_per_point": fl["per_point"][kernel],
+               "peak_datasheet": ds, "frac_of_datasheet": tf / ds}
+        vi = measured_valu(name, kernel)
+        if vi is not None:
+            alu["valu_insts_per_launch"] = vi
+            alu["valu_issue_frac"] = vi / VALU_ISSUE_PER_S / (avg_ms * 1e-3)
+    ws_mb = (info["device_bytes"] + 2 * cfg["N"] * cfg["d"] * dt) / 1e6
+    out = {"kernel": kernel, "avg_ms": avg_ms, "hbm": hbm, "alu": alu,
+           "working_set_mb": ws_mb, "infinity_cache_resident": ws_mb < INFINITY_CACHE_MB}
+    main = alu if (alu is not None and alu["frac"] > hbm["frac"]) else hbm
+    out.update(bound="alu" if main is alu else "hbm", achieved=main["achieved"],
+               peak=main["peak"], unit=main["unit"], frac=main["frac"],
+               traffic=hbm["traffic"])
+    return out
+
+
+def measure_fp64_context(name, steps, dev):
+    """The same workload in the FP64 build (tolerance 1e-12, as the paper's FP64
+    runs): plain evaluations per second, for precision context."""
+    import numpy as np
+    import torch
+
+    from paper_2305_15693_amd import fresco as F
+    from paper_2305_15693_amd import inputs as I
+
+    cfg = I.WORKLOADS[name]
+    d, N, L, M = cfg["d"], cfg["N"], cfg["L"], cfg["M"]
+    w, s0 = I.stealthy_target(d, M, cfg["kcut"])
+    stream = torch.cuda.Stream(device=dev)
+    ctx = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-12, dtype="f64", device=dev,
+                    stream=stream)
+    pos = torch.from_numpy(I.positions(N, d, L, np.float64, seed=cfg["seed"])).to(dev)
+    grad = torch.empty_like(pos)
+    loss_dev = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(2):
+        ctx.loss_grad_async(pos, loss_dev, grad)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.loss_grad_async(pos, loss_dev, grad)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = {"workload": name.replace("_f32", "_f64"), "tol": 1e-12,
+           "width": ctx.plan_info()["width"], "plain_evals_per_s": 1e3 / ms, "plain_ms": ms}
+    ctx.close()
+    del pos, grad
+    torch.cuda.empty_cache()
+    return out
 
 
 def measure(name, steps, warmup, dev, lbfgs_steps):
@@ -221,17 +343,14 @@ def measure(name, steps, warmup, dev, lbfgs_steps):
     ctx.set_timing([])
     dom_ms = dom[0] / dom[1]
     achieved = sbytes[dominant] / (dom_ms * 1e-3) / 1e9
+    roof = roofline(name, cfg, info, dominant, dom_ms, sbytes[dominant])
 
     res = dict(workload=name, cfg=cfg, info=info, stages_ms=stages_ms,
                rocfft=rocfft_compare(info["nf"], stages_ms, dev),
                stage_gbs={k: sbytes[k] / (stages_ms[k] * 1e-3) / 1e9
                           for k in stages_ms if k in sbytes},
                plain_evals_per_s=steps / (ms_plain * 1e-3), plain_ms=ms_plain / steps,
-               loss0=loss0,
-               roofline={"bound": "hbm", "kernel": dominant, "achieved": achieved,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                         "traffic": measured_traffic(name, dominant),
-                         "algorithmic_bytes": sbytes[dominant], "avg_ms": dom_ms},
+               loss0=loss0, hbm_gbs=achieved, roofline=roof,
                pos_np=pos_np, w=w, s0=s0)
 
     if lbfgs_steps:
@@ -430,6 +549,7 @@ def main():
                     help="second workload measured the same way ('' to skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the ragged-batch measurement")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-build context line")
     ap.add_argument("--plain", action="store_true",
                     help="a step is one loss + gradient evaluation (no optimiser), e.g. for "
                          "the N = 1e9 workload")
@@ -492,9 +612,14 @@ def main():
         print(f"[bench] cpu baseline: {cpu['value']:.3g} evals/s", file=sys.stderr, flush=True)
     cfg = r["cfg"]
     info = r["info"]
+    f64 = None
+    if not args.plain and not args.no_fp64:
+        f64 = measure_fp64_context(args.workload, 10, dev)
+        print(f"[bench] {f64['workload']} (FP64 build, tol 1e-12): plain "
+              f"{f64['plain_evals_per_s']:.1f} evals/s", file=sys.stderr, flush=True)
     copy_gbs = copy_rate(dev)
     for rr in [r["roofline"]] + ([sec["roofline"]] if sec else []):
-        rr["frac_of_copy"] = rr["achieved"] / copy_gbs
+        rr["hbm"]["frac_of_copy"] = rr["hbm"]["achieved"] / copy_gbs
     out = {
         "metric": METRIC,
         "value": r["plain_evals_per_s"] if args.plain else r["lbfgs_evals_per_s"],
@@ -523,6 +648,7 @@ def main():
         "stage_gbs": r["stage_gbs"],
         "rocfft": r["rocfft"],
         "copy_gbs": copy_gbs,
+        "fp64_context": f64,
         "secondary": sec,
         "batch": bat,
     }

@@ -181,3 +181,22 @@ def test_failed_creation_releases_everything():
         else:
             assert st == F.ENOMEM
             assert h.value is None
+
+
+def test_bench_algorithmic_flops():
+    # the per-point flops the ALU roofline divides by: kernel polynomials
+    # (degree 9 per cell and axis) and the tensor-product contraction
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2305_15693_amd import inputs as I
+    cfg = I.WORKLOADS["2d_n1e6_stealthy300_f32"]
+    f = bench.stage_flops(cfg, {"width": 7})
+    wi = 8
+    assert f["per_point"]["interp"] == 2 * (2 * 9 * 2 * wi + 2 * wi * wi + 3 * wi) == 880
+    assert f["per_point"]["spread"] == 2 * 9 * 2 * 7 + 7 + 49
+    cfg3 = I.WORKLOADS["3d_n1e7_stealthy60_f32"]
+    f3 = bench.stage_flops(cfg3, {"width": 7})
+    assert f3["per_point"]["interp"] == 2 * (2 * 9 * 3 * wi + 2 * wi ** 3 + 3 * wi ** 2 + 4 * wi)
+    assert f3["interp"] == 10_000_000 * f3["per_point"]["interp"]
+    assert abs(bench.ALU_PEAK_TFLOPS - 78.6432) < 1e-3
