@@ -224,6 +224,31 @@ int fresco_step(fresco_ctx* ctx, void* pos, const fresco_lbfgs_opts* opts, int32
 /* Drop the L-BFGS history and internal point order kept by the context. */
 int fresco_reset_history(fresco_ctx* ctx);
 
+/* Replace the target and weights of a context without planning it again (same
+ * meaning and layout as s0, w, k_cut and weight_mode of fresco_problem; the
+ * geometry, kmax and tolerance stay).  For sequences of targets minimised one
+ * after the other from the previous result (SI, a movie encoded frame by frame
+ * into successive structure factors).  Synchronises the stream; resets the
+ * L-BFGS history; captured graphs stay valid (the arrays are overwritten in
+ * place).  Errors: EINVAL (as for fresco_create's weights), EHIP. */
+int fresco_set_target(fresco_ctx* ctx, const double* s0, const double* w, double k_cut,
+                      int32_t weight_mode);
+
+/* Warm-started sequence (SI, movie encoding): for t = 0 .. n_targets-1, set the
+ * target s0s[t] and weights ws[t] (host mode cubes as in fresco_set_target; a
+ * NULL array, or a NULL entry, means S0 = 0, or the k_cut rule, for those
+ * frames; one weight_mode for all) and run fresco_step from the current
+ * positions for n_iter iterations.  pos (device [n][d]) is updated in place and ends at the
+ * last frame; losses[t], n_evals[t] (host, may be NULL) receive each frame's
+ * final loss and evaluations; frames (device [n_targets][n][d] of the dtype,
+ * may be NULL) receives each frame's positions.  A frame whose line search fails
+ * keeps its last accepted point and the sequence goes on.  Synchronises.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+int fresco_step_sequence(fresco_ctx* ctx, void* pos, int32_t n_targets, const double* const* s0s,
+                         const double* const* ws, double k_cut, int32_t weight_mode,
+                         const fresco_lbfgs_opts* opts, int32_t n_iter, double* losses,
+                         int32_t* n_evals, void* frames);
+
 /* ---------------------------------------------------------------------------
  * Soft-core pair repulsion (Results, stealthy hyperuniform packings: a short-
  * range repulsion combined with the spectral loss keeps particles apart):
@@ -282,6 +307,36 @@ int fresco_pair_energy_grad_async(fresco_pair_ctx* pair, const void* pos, double
  * stream of another device), ENOTSUP (beyond the size limit), EHIP. */
 int fresco_pair_energy_grad_noalloc(const fresco_pair_problem* p, const void* pos,
                                     double* energy_dev, void* grad, void* stream);
+
+/* Overlap removal (main text, quasicrystalline structures: between minimisation
+ * cycles, points that sit on top of others are removed and redrawn uniformly in
+ * the box, keeping N).  A point is an overlap when a point of LOWER index lies
+ * closer than threshold to it (minimum image); every overlapping point is
+ * replaced, in increasing index order, by the next row of fresh (device
+ * [n_fresh][d] of the dtype, positions the caller drew, e.g. uniform in the
+ * box).  threshold in (0, sigma] of the pair context (its cell list finds the
+ * candidates).  pos (device [n][d]) is updated in place; *n_replaced receives
+ * the number of overlapping points.  Runs on the pair context's stream and
+ * synchronises it.  Errors: EINVAL (null pointers, threshold out of range, more
+ * overlaps than fresh rows: then pos is untouched and *n_replaced holds the
+ * number needed), EHIP. */
+int fresco_pair_replace_overlaps(fresco_pair_ctx* pair, void* pos, double threshold,
+                                 const void* fresh, int64_t n_fresh, int64_t* n_replaced);
+
+/* Cycles of minimisation and overlap removal (main text, quasicrystalline
+ * structures): up to max_cycles times, fresco_step(ctx, pos, opts, n_iter)
+ * followed by fresco_pair_replace_overlaps(pair, pos, threshold, ...) with the
+ * unused rows of fresh; stops after the first cycle that finds no overlap.  The
+ * pair context (matching ctx in n, dim and dtype) only supplies the cell list
+ * here; it need not be attached.  loss_out: loss at the end of the last
+ * minimisation; cycles_out: cycles run; replaced_out: points replaced in total
+ * (all may be NULL).  The L-BFGS history is reset after every replacement.
+ * Errors: as fresco_step (a failed line search ends that cycle's minimisation
+ * only) and fresco_pair_replace_overlaps. */
+int fresco_overlap_cycles(fresco_ctx* ctx, fresco_pair_ctx* pair, void* pos,
+                          const fresco_lbfgs_opts* opts, int32_t n_iter, int32_t max_cycles,
+                          double threshold, const void* fresh, int64_t n_fresh, double* loss_out,
+                          int32_t* cycles_out, int64_t* replaced_out);
 
 /* Add weight * E to every loss evaluation of ctx (fresco_loss_grad,
  * fresco_loss_grad_async and fresco_step then minimise L_S + weight E); the pair

@@ -229,10 +229,14 @@ int dalloc_t(fresco_ctx* c, T** p, size_t count) {
   return st;
 }
 
+// copy to the device array *dst, allocated on first use and overwritten in place
+// afterwards (same size; the caller has drained the stream)
 template <class R>
 int upload(fresco_ctx* c, R** dst, const std::vector<double>& src) {
-  int st = dalloc_t(c, dst, src.size());
-  if (st) return st;
+  if (!*dst) {
+    int st = dalloc_t(c, dst, src.size());
+    if (st) return st;
+  }
   std::vector<R> tmp(src.size());
   for (size_t i = 0; i < src.size(); ++i) tmp[i] = (R)src[i];
   HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice));
@@ -737,6 +741,44 @@ int upload_weights(fresco_ctx* c, const std::vector<double>& Wc, const std::vect
   if ((st = upload<R>(c, &S->Wm, wm))) return st;
   if ((st = upload<R>(c, &S->S0m, sm))) return st;
   return FRESCO_OK;
+}
+
+// Targets and weights on the full mode cube from the caller's arrays (Methods,
+// "Analytical gradients": W = w / S0^2 where S0 != 0 for the relative loss);
+// w NULL: weight 1 on 0 < |n| <= k_cut.  Returns 1 for a negative or
+// non-finite weight or a non-finite target.
+int build_weights(const Geom& g, const double* s0, const double* w, double k_cut,
+                  int weight_mode, std::vector<double>& Wc, std::vector<double>& S0c,
+                  long long* ncons) {
+  const int d = g.d;
+  Wc.assign(g.ncube, 0.0);
+  S0c.assign(g.ncube, 0.0);
+  if (s0)
+    for (long long i = 0; i < g.ncube; ++i) S0c[i] = s0[i];
+  *ncons = 0;
+  int bad = 0;
+  for (long long i = 0; i < g.ncube; ++i) {
+    long long r = i;
+    long long n2 = 0;
+    bool zero = true;
+    for (int a = d - 1; a >= 0; --a) {
+      long long P = 2LL * g.M[a] + 1;
+      long long na = r % P - g.M[a];
+      r /= P;
+      n2 += na * na;
+      if (na != 0) zero = false;
+    }
+    double wv;
+    if (w) wv = w[i];
+    else wv = (n2 > 0 && (double)n2 <= k_cut * k_cut) ? 1.0 : 0.0;
+    if (!(wv >= 0.0) || !std::isfinite(wv) || !std::isfinite(S0c[i])) bad = 1;
+    if (zero) wv = 0.0;  // k = 0 is never constrained
+    double W = wv;
+    if (weight_mode == FRESCO_WEIGHT_RELATIVE && S0c[i] != 0.0) W = wv / (S0c[i] * S0c[i]);
+    Wc[i] = W;
+    if (W != 0.0) ++*ncons;
+  }
+  return bad;
 }
 
 // ---------------------------------------------------------------- stages
@@ -1460,33 +1502,9 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
   }
 
   // weights and targets on the full cube (FP64, host)
-  std::vector<double> Wc(g.ncube, 0.0), S0c(g.ncube, 0.0);
-  if (p->s0)
-    for (long long i = 0; i < g.ncube; ++i) S0c[i] = p->s0[i];
+  std::vector<double> Wc, S0c;
   long long ncons = 0;
-  int bad = 0;
-  for (long long i = 0; i < g.ncube; ++i) {
-    long long r = i;
-    long long n2 = 0;
-    bool zero = true;
-    for (int a = d - 1; a >= 0; --a) {
-      long long P = 2LL * g.M[a] + 1;
-      long long na = r % P - g.M[a];
-      r /= P;
-      n2 += na * na;
-      if (na != 0) zero = false;
-    }
-    double w;
-    if (p->w) w = p->w[i];
-    else w = (n2 > 0 && (double)n2 <= p->k_cut * p->k_cut) ? 1.0 : 0.0;
-    if (!(w >= 0.0) || !std::isfinite(w) || !std::isfinite(S0c[i])) bad = 1;
-    if (zero) w = 0.0;  // k = 0 is never constrained
-    double W = w;
-    if (p->weight_mode == FRESCO_WEIGHT_RELATIVE && S0c[i] != 0.0) W = w / (S0c[i] * S0c[i]);
-    Wc[i] = W;
-    if (W != 0.0) ++ncons;
-  }
-  if (bad) {
+  if (build_weights(g, p->s0, p->w, p->k_cut, p->weight_mode, Wc, S0c, &ncons)) {
     delete c;
     return FRESCO_EINVAL;
   }
@@ -1663,6 +1681,86 @@ int fresco_reset_history(fresco_ctx* c) {
   if (!c) return FRESCO_EINVAL;
   if (c->dtype == FRESCO_F32) ((State<float>*)c->state)->have_perm0 = false;
   else ((State<double>*)c->state)->have_perm0 = false;
+  return FRESCO_OK;
+}
+
+int fresco_set_target(fresco_ctx* c, const double* s0, const double* w, double k_cut,
+                      int32_t weight_mode) {
+  if (!c) return FRESCO_EINVAL;
+  if (weight_mode != FRESCO_WEIGHT_ABS && weight_mode != FRESCO_WEIGHT_RELATIVE)
+    return FRESCO_EINVAL;
+  if (!w && !(k_cut >= 0.0)) return FRESCO_EINVAL;
+  std::vector<double> Wc, S0c;
+  long long ncons = 0;
+  if (build_weights(c->g, s0, w, k_cut, weight_mode, Wc, S0c, &ncons)) return FRESCO_EINVAL;
+  // the arrays are overwritten in place, so captured graphs stay valid
+  HIPCHK(hipStreamSynchronize(c->st));
+  int st = (c->dtype == FRESCO_F32) ? upload_weights<float>(c, Wc, S0c)
+                                    : upload_weights<double>(c, Wc, S0c);
+  if (st) return st;
+  c->n_constrained = ncons;
+  c->sf_pos = nullptr;
+  return fresco_reset_history(c);
+}
+
+int fresco_step_sequence(fresco_ctx* c, void* pos, int32_t n_targets, const double* const* s0s,
+                         const double* const* ws, double k_cut, int32_t weight_mode,
+                         const fresco_lbfgs_opts* o, int32_t n_iter, double* losses,
+                         int32_t* n_evals, void* frames) {
+  if (!c || !pos || n_targets < 0 || !o) return FRESCO_EINVAL;
+  const size_t fbytes = (size_t)c->g.N * c->g.d * (c->dtype == FRESCO_F32 ? 4 : 8);
+  for (int t = 0; t < n_targets; ++t) {
+    int st = fresco_set_target(c, s0s ? s0s[t] : nullptr, ws ? ws[t] : nullptr, k_cut,
+                               weight_mode);
+    if (st) return st;
+    double loss = 0.0;
+    int32_t nev = 0;
+    // a frame whose line search fails keeps its last accepted point; the next
+    // frame starts from there
+    st = fresco_step(c, pos, o, n_iter, &loss, &nev);
+    if (st && st != FRESCO_ELINESEARCH) return st;
+    if (losses) losses[t] = loss;
+    if (n_evals) n_evals[t] = nev;
+    if (frames)
+      HIPCHK(hipMemcpyAsync((char*)frames + fbytes * (size_t)t, pos, fbytes,
+                            hipMemcpyDeviceToDevice, c->st));
+  }
+  HIPCHK(hipStreamSynchronize(c->st));
+  return FRESCO_OK;
+}
+
+int fresco_overlap_cycles(fresco_ctx* c, fresco_pair_ctx* pc, void* pos,
+                          const fresco_lbfgs_opts* o, int32_t n_iter, int32_t max_cycles,
+                          double threshold, const void* fresh, int64_t n_fresh, double* loss_out,
+                          int32_t* cycles_out, int64_t* replaced_out) {
+  if (!c || !pc || !pos || !o || max_cycles < 0 || (n_fresh > 0 && !fresh) || n_fresh < 0)
+    return FRESCO_EINVAL;
+  if (pc->n != c->g.N || pc->d != c->g.d || pc->dtype != c->dtype) return FRESCO_EINVAL;
+  const size_t rowb = (size_t)c->g.d * (c->dtype == FRESCO_F32 ? 4 : 8);
+  int64_t used = 0;
+  double loss = 0.0;
+  int cyc = 0;
+  for (; cyc < max_cycles; ++cyc) {
+    int32_t nev = 0;
+    int st = fresco_step(c, pos, o, n_iter, &loss, &nev);
+    if (st && st != FRESCO_ELINESEARCH) return st;
+    // the pair context runs on its own stream: order it after this one
+    HIPCHK(hipStreamSynchronize(c->st));
+    int64_t rep = 0;
+    st = fresco_pair_replace_overlaps(pc, pos, threshold,
+                                      fresh ? (const char*)fresh + rowb * (size_t)used : nullptr,
+                                      n_fresh - used, &rep);
+    if (st) return st;
+    used += rep;
+    if (rep == 0) {
+      ++cyc;
+      break;
+    }
+    fresco_reset_history(c);  // replaced points invalidate the curvature pairs
+  }
+  if (loss_out) *loss_out = loss;
+  if (cycles_out) *cycles_out = cyc;
+  if (replaced_out) *replaced_out = used;
   return FRESCO_OK;
 }
 

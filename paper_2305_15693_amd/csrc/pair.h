@@ -32,6 +32,12 @@ struct fresco_pair_ctx {
   double* edev = nullptr;      // energy of the synchronous call
   int* fout = nullptr;         // flag of the synchronous call
   double* energy_host = nullptr;  // pinned: energy, then the flag
+  // overlap replacement (allocated on first use): flags, their exclusive scan
+  // (n + 1 entries, the last the count), scan block sums
+  uint32_t* oflag = nullptr;
+  uint32_t* orank = nullptr;
+  uint32_t* obsum = nullptr;
+  uint32_t* ocount_host = nullptr;  // pinned copy of the count
 };
 
 namespace fresco {

@@ -289,6 +289,73 @@ __global__ void pair_force_kernel(PairGeom g, const PairRec<R>* __restrict__ sor
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// Overlaps (main text, quasicrystalline structures: points that end up on top
+// of one another are removed and redrawn between minimisation cycles): flag[i]
+// = 1 when a point of lower index lies closer than sqrt(thr2) to point i under
+// the minimum image (thr at most the cell side, so that the neighbour cells hold
+// every candidate).  Differences in FP64 from the stored coordinates.
+template <class R>
+__global__ void overlap_flag_kernel(PairGeom g, const PairRec<R>* __restrict__ sorted,
+                                    const uint32_t* __restrict__ start, double thr2,
+                                    uint32_t* __restrict__ flag) {
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.n) return;
+  const PairRec<R> me = sorted[s];
+  bool bad = false;
+  int k[3];
+  (void)pair_cell<R>(g, me.x, k, &bad);
+  // distinct neighbour cells per axis: all of them on an axis of one or two
+  // cells, else k - 1, k, k + 1 (periodic)
+  int lo[3], cnt[3];
+  for (int a = 0; a < 3; ++a) {
+    if (g.nc[a] <= 2) {
+      lo[a] = 0;
+      cnt[a] = g.nc[a];
+    } else {
+      lo[a] = k[a] - 1 + g.nc[a];
+      cnt[a] = 3;
+    }
+  }
+  uint32_t hit = 0;
+  for (int iz = 0; iz < cnt[2] && !hit; ++iz) {
+    const int cz = (lo[2] + iz) % g.nc[2];
+    for (int iy = 0; iy < cnt[1] && !hit; ++iy) {
+      const int cy = (lo[1] + iy) % g.nc[1];
+      for (int ix = 0; ix < cnt[0] && !hit; ++ix) {
+        const int cx = (lo[0] + ix) % g.nc[0];
+        const uint32_t cell =
+            (uint32_t)cx + (uint32_t)g.nc[0] * ((uint32_t)cy + (uint32_t)g.nc[1] * (uint32_t)cz);
+        for (uint32_t t = start[cell]; t < start[cell + 1]; ++t) {
+          const PairRec<R> o = sorted[t];
+          if (o.idx >= me.idx) continue;
+          double r2 = 0.0;
+          for (int a = 0; a < g.d; ++a) {
+            double v = (double)me.x[a] - (double)o.x[a];
+            v -= g.L[a] * rint(v * g.invL[a]);
+            r2 += v * v;
+          }
+          if (r2 < thr2) {
+            hit = 1;
+            break;
+          }
+        }
+      }
+    }
+  }
+  flag[me.idx] = hit;
+}
+
+// pos[i] = fresh[rank[i]] for every flagged point (rank: exclusive scan of the
+// flags in index order)
+template <class R>
+__global__ void overlap_replace_kernel(R* __restrict__ pos, const uint32_t* __restrict__ flag,
+                                       const uint32_t* __restrict__ rank,
+                                       const R* __restrict__ fresh, long long n, int d) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  for (int a = 0; a < d; ++a) pos[i * d + a] = fresh[(long long)rank[i] * d + a];
+}
+
 __global__ void pair_fill_kernel(uint32_t* p, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -331,9 +398,9 @@ static PairGeom pair_geom(const fresco_pair_ctx* pc) {
   return g;
 }
 
+// the cell list of pos: keys, scan, records in cell order sorted by index
 template <class R>
-static int pair_enqueue_t(fresco_pair_ctx* pc, const R* pos, R* grad, bool accumulate,
-                          double weight, hipStream_t st) {
+static void pair_cells_t(fresco_pair_ctx* pc, const R* pos, hipStream_t st) {
   const PairGeom g = pair_geom(pc);
   const unsigned nb = (unsigned)((pc->n + 255) / 256);
   long long fb = (pc->ncell + 255) / 256;
@@ -347,8 +414,22 @@ static int pair_enqueue_t(fresco_pair_ctx* pc, const R* pos, R* grad, bool accum
   pair_scatter_kernel<R><<<nb, 256, 0, st>>>(g, pos, pc->key, pc->rank, pc->start, sorted);
   pair_order_kernel<R><<<(unsigned)((pc->ncell + 255) / 256), 256, 0, st>>>(pc->ncell, pc->start,
                                                                             sorted);
-  pair_force_kernel<R><<<nb, 256, 0, st>>>(g, sorted, pc->start, grad, accumulate ? 1 : 0, weight,
-                                           pc->part);
+}
+
+template <class R>
+static int pair_enqueue_t(fresco_pair_ctx* pc, const R* pos, R* grad, bool accumulate,
+                          double weight, hipStream_t st) {
+  const PairGeom g = pair_geom(pc);
+  const unsigned nb = (unsigned)((pc->n + 255) / 256);
+  pair_cells_t<R>(pc, pos, st);
+  pair_force_kernel<R><<<nb, 256, 0, st>>>(g, (const PairRec<R>*)pc->sorted, pc->start, grad,
+                                           accumulate ? 1 : 0, weight, pc->part);
+  return hipGetLastError() == hipSuccess ? FRESCO_OK : FRESCO_EHIP;
+}
+
+static int pair_enqueue_cells(fresco_pair_ctx* pc, const void* pos, hipStream_t st) {
+  if (pc->dtype == FRESCO_F32) pair_cells_t<float>(pc, (const float*)pos, st);
+  else pair_cells_t<double>(pc, (const double*)pos, st);
   return hipGetLastError() == hipSuccess ? FRESCO_OK : FRESCO_EHIP;
 }
 
@@ -525,6 +606,7 @@ int fresco_pair_destroy(fresco_pair_ctx* pc) {
   (void)hipStreamSynchronize(pc->st);
   for (void* p : pc->allocs) (void)hipFree(p);
   if (pc->energy_host) (void)hipHostFree(pc->energy_host);
+  if (pc->ocount_host) (void)hipHostFree(pc->ocount_host);
   delete pc;
   return FRESCO_OK;
 }
@@ -571,6 +653,61 @@ int fresco_pair_energy_grad_async(fresco_pair_ctx* pc, const void* pos, double* 
   if (st) return st;
   pair_finish_kernel<<<1, 256, 0, pc->st>>>(pc->part, pc->nblocks, energy_dev, pc->flag, nullptr);
   return hipGetLastError() == hipSuccess ? FRESCO_OK : FRESCO_EHIP;
+}
+
+int fresco_pair_replace_overlaps(fresco_pair_ctx* pc, void* pos, double threshold,
+                                 const void* fresh, int64_t n_fresh, int64_t* n_replaced) {
+  if (!pc || !pos || !n_replaced || n_fresh < 0 || (n_fresh > 0 && !fresh)) return FRESCO_EINVAL;
+  if (!(threshold > 0.0) || threshold > pc->sigma) return FRESCO_EINVAL;
+  *n_replaced = 0;
+  const long long n = pc->n;
+  const int nsb = (int)((n + kScanPer - 1) / kScanPer);
+  int st = FRESCO_OK;
+  if (!pc->oflag) {
+    if (!st) st = pair_alloc(pc, &pc->oflag, n);
+    if (!st) st = pair_alloc(pc, &pc->orank, n + 1);
+    if (!st) st = pair_alloc(pc, &pc->obsum, nsb);
+    if (!st && hipHostMalloc((void**)&pc->ocount_host, sizeof(uint32_t)) != hipSuccess)
+      st = FRESCO_ENOMEM;
+    if (st) return st;
+  }
+  hipStream_t hs = pc->st;
+  // the cell list of the current positions (the gradient output is scratch here)
+  st = pair_enqueue_cells(pc, pos, hs);
+  if (st) return st;
+  const PairGeom g = pair_geom(pc);
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (pc->dtype == FRESCO_F32)
+    overlap_flag_kernel<float><<<nb, 256, 0, hs>>>(g, (const PairRec<float>*)pc->sorted, pc->start,
+                                                  threshold * threshold, pc->oflag);
+  else
+    overlap_flag_kernel<double><<<nb, 256, 0, hs>>>(
+        g, (const PairRec<double>*)pc->sorted, pc->start, threshold * threshold, pc->oflag);
+  scan_reduce_kernel<<<nsb, 1024, 0, hs>>>(pc->oflag, n, pc->obsum);
+  scan_top_kernel<<<1, 1024, 0, hs>>>(pc->obsum, nsb, pc->orank, n);
+  scan_down_kernel<<<nsb, 1024, 0, hs>>>(pc->oflag, n, pc->obsum, pc->orank);
+  if (hipGetLastError() != hipSuccess) return FRESCO_EHIP;
+  if (hipMemcpyAsync(pc->ocount_host, pc->orank + n, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                     hs) != hipSuccess ||
+      hipStreamSynchronize(hs) != hipSuccess)
+    return FRESCO_EHIP;
+  const int64_t count = (int64_t)*pc->ocount_host;
+  if (count > n_fresh) {
+    *n_replaced = count;  // how many would be needed; positions untouched
+    return FRESCO_EINVAL;
+  }
+  if (count > 0) {
+    if (pc->dtype == FRESCO_F32)
+      overlap_replace_kernel<float><<<nb, 256, 0, hs>>>((float*)pos, pc->oflag, pc->orank,
+                                                        (const float*)fresh, n, pc->d);
+    else
+      overlap_replace_kernel<double><<<nb, 256, 0, hs>>>((double*)pos, pc->oflag, pc->orank,
+                                                         (const double*)fresh, n, pc->d);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(hs) != hipSuccess)
+      return FRESCO_EHIP;
+  }
+  *n_replaced = count;
+  return FRESCO_OK;
 }
 
 int fresco_pair_energy_grad(fresco_pair_ctx* pc, const void* pos, double* energy, void* grad) {

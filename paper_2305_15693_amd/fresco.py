@@ -118,6 +118,23 @@ def _load():
     lib.fresco_step.restype = i
     lib.fresco_reset_history.argtypes = [vp]
     lib.fresco_reset_history.restype = i
+    dpp = ctypes.POINTER(ctypes.c_double)
+    lib.fresco_set_target.argtypes = [vp, dpp, dpp, ctypes.c_double, ctypes.c_int32]
+    lib.fresco_set_target.restype = i
+    lib.fresco_step_sequence.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(dpp),
+                                         ctypes.POINTER(dpp),
+                                         ctypes.c_double, ctypes.c_int32,
+                                         ctypes.POINTER(LbfgsOpts), ctypes.c_int32, dpp,
+                                         ctypes.POINTER(ctypes.c_int32), vp]
+    lib.fresco_step_sequence.restype = i
+    lib.fresco_pair_replace_overlaps.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.c_int64,
+                                                 ctypes.POINTER(ctypes.c_int64)]
+    lib.fresco_pair_replace_overlaps.restype = i
+    lib.fresco_overlap_cycles.argtypes = [vp, vp, vp, ctypes.POINTER(LbfgsOpts), ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_double, vp, ctypes.c_int64,
+                                          dpp, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int64)]
+    lib.fresco_overlap_cycles.restype = i
     lib.fresco_set_strengths.argtypes = [vp, vp]
     lib.fresco_set_strengths.restype = i
     lib.fresco_loss_grad_strengths.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp]
@@ -293,6 +310,74 @@ class Context:
 
     def reset_history(self):
         _check(_lib.fresco_reset_history(self._h), "fresco_reset_history")
+
+    def _cube(self, a):
+        if a is None:
+            return None, None
+        arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(self.cube_shape))
+        return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def _opts(self, m=8, max_step=None, c1=1e-4, shrink=0.5, max_backtracks=20, gtol=0.0):
+        o = LbfgsOpts()
+        o.m = m
+        o.max_backtracks = max_backtracks
+        o.max_step = self.default_max_step() if max_step is None else float(max_step)
+        o.c1 = c1
+        o.shrink = shrink
+        o.gtol = gtol
+        return o
+
+    def set_target(self, s0_cube=None, w_cube=None, k_cut: float = 0.0, relative: bool = False):
+        """New target and weights for the same geometry (fresco_set_target)."""
+        s0, s0p = self._cube(s0_cube)
+        w, wp = self._cube(w_cube)
+        _check(_lib.fresco_set_target(self._h, s0p, wp, float(k_cut),
+                                      WEIGHT_RELATIVE if relative else WEIGHT_ABS),
+               "fresco_set_target")
+
+    def step_sequence(self, pos, n_iter: int, *, s0_cubes=None, w_cubes=None, k_cut: float = 0.0,
+                      relative: bool = False, frames: bool = True, **opts):
+        """Warm-started minimisations over a sequence of targets (fresco_step_sequence):
+        per-frame lists of S0 and weight cubes (either may be None: S0 = 0, or weight 1
+        on 0 < |n| <= k_cut).  Returns (losses, evaluations, frames [T][n][d] or None)."""
+        torch = _torch()
+        T = len(s0_cubes) if s0_cubes is not None else len(w_cubes)
+
+        def table(cubes):
+            if cubes is None:
+                return [], None
+            keep = [self._cube(c) for c in cubes]
+            return keep, (ctypes.POINTER(ctypes.c_double) * max(T, 1))(*[k[1] for k in keep])
+
+        ks, s0a = table(s0_cubes)
+        kw, wa = table(w_cubes)
+        losses = (ctypes.c_double * max(T, 1))()
+        nev = (ctypes.c_int32 * max(T, 1))()
+        fr = (torch.empty((T, self.n, self.dim), dtype=self.torch_dtype, device=self.device)
+              if frames else None)
+        o = self._opts(**opts)
+        _check(_lib.fresco_step_sequence(self._h, self._pos(pos), T, s0a, wa, float(k_cut),
+                                         WEIGHT_RELATIVE if relative else WEIGHT_ABS,
+                                         ctypes.byref(o), int(n_iter), losses, nev,
+                                         ctypes.c_void_p(fr.data_ptr()) if fr is not None else None),
+               "fresco_step_sequence")
+        del ks, kw
+        return list(losses)[:T], list(nev)[:T], fr
+
+    def overlap_cycles(self, pair, pos, n_iter: int, max_cycles: int, threshold: float, fresh,
+                       **opts):
+        """Minimisation / overlap-removal cycles (fresco_overlap_cycles).  fresh: [m][d]
+        replacement positions.  Returns (loss, cycles, replaced)."""
+        o = self._opts(**opts)
+        loss = ctypes.c_double(0.0)
+        cyc = ctypes.c_int32(0)
+        rep = ctypes.c_int64(0)
+        _check(_lib.fresco_overlap_cycles(self._h, pair.handle, self._pos(pos), ctypes.byref(o),
+                                          int(n_iter), int(max_cycles), float(threshold),
+                                          ctypes.c_void_p(fresh.data_ptr()), int(fresh.shape[0]),
+                                          ctypes.byref(loss), ctypes.byref(cyc), ctypes.byref(rep)),
+               "fresco_overlap_cycles")
+        return float(loss.value), int(cyc.value), int(rep.value)
 
     def set_strengths(self, c):
         """Point strengths for every later evaluation (a [n] tensor of the context's
@@ -476,6 +561,20 @@ class PairContext:
         if tuple(pos.shape) != (self.n, self.dim) or not pos.is_contiguous():
             raise ValueError(f"positions must be a contiguous [{self.n}][{self.dim}] tensor")
         return ctypes.c_void_p(pos.data_ptr())
+
+    def replace_overlaps(self, pos, threshold: float, fresh) -> int:
+        """Replace every point that lies closer than threshold to a point of lower index
+        by the next row of fresh, in index order (fresco_pair_replace_overlaps); returns
+        the number replaced."""
+        n = ctypes.c_int64(0)
+        st = _lib.fresco_pair_replace_overlaps(self._h, self._pos(pos), float(threshold),
+                                               ctypes.c_void_p(fresh.data_ptr()),
+                                               int(fresh.shape[0]), ctypes.byref(n))
+        if st == EINVAL and n.value > fresh.shape[0]:
+            raise FrescoError(st, f"fresco_pair_replace_overlaps ({n.value} overlaps, "
+                                  f"{fresh.shape[0]} fresh rows)")
+        _check(st, "fresco_pair_replace_overlaps")
+        return int(n.value)
 
     def energy_grad(self, pos, grad=None):
         torch = _torch()
