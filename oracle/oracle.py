@@ -343,6 +343,44 @@ def finite_difference_strengths(pos, c, L, modes, W, S0, coords, h: float) -> np
     return out
 
 
+def pair_correlation(pos, L, M, xs) -> np.ndarray:
+    """g(x) at the points xs [P][d] (Methods, pair correlation function
+    optimisation): the periodic box turns the integral over k into a sum over the
+    mode cube |n_a| <= M_a, n = 0 included,
+        g(x) = Re[(1/N) sum_n (S(n) - 1) exp(-i k.x)] = (1/N) sum_n (S(n) - 1) cos(k.x)
+    (unit strengths; S is even in k)."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    Lv = _box(L, d)
+    modes = mode_vectors(d, M)
+    S = structure_factor_cube(pos, L, M).ravel()
+    k = 2 * np.pi * modes / Lv
+    xs = np.asarray(xs, dtype=np.float64).reshape(-1, d)
+    return np.cos(xs @ k.T) @ (S - 1.0) / N
+
+
+def pair_correlation_loss_grad(pos, L, M, xs, wg, g0):
+    """L_g = sum_x W_g (g - g0)^2 over the points xs and its position gradient
+        dL_g/dr_j = sum_n gS(n) dS(n)/dr_j,   gS(n) = (1/N) sum_x 2 W_g (g - g0) cos(k.x)
+    (the derivative of g in the Methods, written through the backward of S).
+    Returns dict(loss, grad [N][d], g [P])."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    Lv = _box(L, d)
+    modes = mode_vectors(d, M)
+    k = 2 * np.pi * modes / Lv
+    xs = np.asarray(xs, dtype=np.float64).reshape(-1, d)
+    wg = np.asarray(wg, dtype=np.float64).ravel()
+    g0 = np.asarray(g0, dtype=np.float64).ravel()
+    C = np.cos(xs @ k.T)
+    S = structure_factor_cube(pos, L, M).ravel()
+    g = C @ (S - 1.0) / N
+    r = g - g0
+    gS = C.T @ (2.0 * wg * r) / N
+    grad = sf_vjp(pos, L, modes, gS)
+    return {"loss": float(np.sum(wg * r * r)), "grad": grad, "g": g}
+
+
 def pair_finite_difference(pos, L, coords, h: float, sigma: float, eps: float = 1.0,
                            alpha: float = 2.0) -> np.ndarray:
     """(E(r_ja + h) - E(r_ja - h)) / 2h of the soft-core energy for coords [(j, a), ...],

@@ -668,3 +668,71 @@ def test_strengths_finite_differences(signed):
         plain = (O.loss_grad_strengths(pp, cp, L, modes, W, S0, want_grad=False)["loss"] -
                  O.loss_grad_strengths(pm, cm, L, modes, W, S0, want_grad=False)["loss"]) / (2 * hh)
         assert f == pytest.approx(plain, rel=1e-6, abs=1e-9)
+
+
+# ------------------------------------------------------- pair correlation loss
+def _dirichlet(y, M, L):
+    """sum_{|n| <= M} exp(2 pi i n y / L) = sin((2M+1) pi y / L) / sin(pi y / L)."""
+    t = np.pi * np.asarray(y, dtype=np.float64) / L
+    s = np.sin(t)
+    out = np.empty_like(t)
+    small = np.abs(s) < 1e-12
+    out[~small] = np.sin((2 * M + 1) * t[~small]) / s[~small]
+    out[small] = (2 * M + 1) * np.cos((2 * M + 1) * t[small]) / np.cos(t[small])
+    return out
+
+
+def test_pair_correlation_equals_pair_sum_with_dirichlet_kernel():
+    # g(x) = (1/N^2) sum_{i != j} prod_a D_{M_a}((r_i - r_j - x)_a): the pair-sum
+    # definition of g truncated to the mode cube, evaluated without S
+    rng = np.random.default_rng(101)
+    N, L, M = 40, np.array([7.0, 9.0]), (5, 4)
+    pos = rng.uniform(0, 1, (N, 2)) * L
+    xs = rng.uniform(-1, 1, (20, 2)) * L
+    g = O.pair_correlation(pos, L, M, xs)
+    ref = np.zeros(len(xs))
+    for q, x in enumerate(xs):
+        for i in range(N):
+            y = pos[i] - pos - x
+            term = _dirichlet(y[:, 0], M[0], L[0]) * _dirichlet(y[:, 1], M[1], L[1])
+            ref[q] += term.sum() - term[i]
+    ref /= N * N
+    np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_pair_correlation_grid_mean():
+    # on a grid of P_a >= 2 M_a + 1 points per axis every mode but n = 0 averages
+    # to zero, so the mean of g is (S(0) - 1) / N = 1 - 1/N for any points
+    rng = np.random.default_rng(102)
+    N, L, M = 30, np.array([5.0, 6.0, 4.0]), (3, 2, 3)
+    pos = rng.uniform(0, 1, (N, 3)) * L
+    P = (8, 5, 9)
+    grids = np.meshgrid(*[np.arange(p) * l / p for p, l in zip(P, L)], indexing="ij")
+    xs = np.stack([gg.ravel() for gg in grids], 1)
+    g = O.pair_correlation(pos, L, M, xs)
+    assert g.mean() == pytest.approx(1 - 1 / N, rel=1e-12)
+    # and g is even: g(-x) = g(x)
+    np.testing.assert_allclose(O.pair_correlation(pos, L, M, -xs), g, rtol=1e-12, atol=1e-13)
+
+
+def test_pair_correlation_loss_gradient_finite_differences():
+    rng = np.random.default_rng(103)
+    N, L, M = 25, 6.0, 4
+    pos = rng.uniform(0, L, (N, 2))
+    P = 12
+    gx = np.arange(P) * L / P
+    xs = np.stack(np.meshgrid(gx, gx, indexing="ij"), -1).reshape(-1, 2)
+    r2 = np.sum(np.minimum(xs, L - xs) ** 2, 1)
+    g0 = (r2 > 1.0).astype(float)  # an exclusion target
+    wg = np.where(r2 < 2.5, 1.0, 0.2)
+    r = O.pair_correlation_loss_grad(pos, L, M, xs, wg, g0)
+    assert r["loss"] == pytest.approx(np.sum(wg * (O.pair_correlation(pos, L, M, xs) - g0) ** 2),
+                                      rel=1e-13)
+    h = 1e-5
+    for j, a in [(0, 0), (3, 1), (11, 0), (24, 1)]:
+        pp, pm = pos.copy(), pos.copy()
+        pp[j, a] += h
+        pm[j, a] -= h
+        fd = (O.pair_correlation_loss_grad(pp, L, M, xs, wg, g0)["loss"] -
+              O.pair_correlation_loss_grad(pm, L, M, xs, wg, g0)["loss"]) / (2 * h)
+        assert r["grad"][j, a] == pytest.approx(fd, rel=1e-6, abs=1e-9)
