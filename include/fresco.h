@@ -187,6 +187,30 @@ int fresco_set_strengths(fresco_ctx* ctx, const void* c);
 int fresco_loss_grad_strengths(fresco_ctx* ctx, const void* pos, double* loss, void* grad,
                                void* grad_c);
 
+/* Pair-correlation loss (Methods, pair correlation function optimisation).  In
+ * the periodic box the pair correlation function is the truncated Fourier sum
+ *   g(x) = (1/N) sum_{n in cube} (S(n) - 1) exp(-i k.x)      (n = 0 included),
+ * evaluated here on the fine grid x_l = (l_a L_a / nf_a) (nf from
+ * fresco_plan_info_get), and
+ *   L_g = sum_x W_g(x) (g(x) - g0(x))^2,
+ *   dL_g/dr_j = sum_n gS(n) dS(n)/dr_j,  gS(n) = (1/N) sum_x 2 W_g (g - g0) cos(k.x),
+ * i.e. the backward of S with dF/dS = gS; both sums over x are transforms on the
+ * fine grid.  g0, wg: HOST arrays of prod nf doubles in the fine grid's layout
+ * (C order over (l_{d-1}, ..., l_0): axis 0 fastest); g0 NULL means 0; wg >= 0,
+ * NULL disables the term.  The context keeps copies.  Synchronises.
+ * Errors: EINVAL (null ctx, a negative or non-finite weight, a non-finite
+ * target), ENOMEM, EHIP. */
+int fresco_set_pair_correlation_target(fresco_ctx* ctx, const double* g0, const double* wg);
+
+/* L_g and dL_g/dr at pos (device [n][d]); grad (device [n][d]) is overwritten;
+ * g_out (device, prod nf values of the dtype, fine-grid layout; may be NULL)
+ * receives g.  loss: HOST pointer; synchronises and reports non-finite
+ * positions (ENONFINITE).  Unit strengths only.  Errors: EINVAL (null pointers,
+ * no target set), ENOTSUP (strengths set, or 2D columns too long for one LDS
+ * pass), EHIP, ENONFINITE. */
+int fresco_pair_correlation_loss_grad(fresco_ctx* ctx, const void* pos, double* loss, void* grad,
+                                      void* g_out);
+
 /* Options of the L-BFGS minimiser (main text, "Algorithm": L-BFGS with a cap on
  * the step and a backtracking line search; the constants are this library's).  Defaults used by the Python layer: m = 8,
  * max_backtracks = 20, max_step = 0.1 L / N^(1/d), c1 = 1e-4, shrink = 0.5,

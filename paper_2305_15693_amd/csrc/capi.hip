@@ -101,7 +101,16 @@ struct State {
   // strengths and field-value output of the evaluation being enqueued
   const R* str_eval = nullptr;
   R* val_eval = nullptr;
+  // pair-correlation loss (fresco_set_pair_correlation_target): target and
+  // weights on the fine grid, the grid b = 2 W_g (g - g0), loss partials
+  R* g0 = nullptr;
+  R* wg = nullptr;
+  R* gb = nullptr;
+  double* gpart = nullptr;
+  bool has_g = false;
 };
+
+constexpr int kGlossBlocks = 1024;
 
 constexpr int kStatBlocks = 256;
 
@@ -229,14 +238,22 @@ int dalloc_t(fresco_ctx* c, T** p, size_t count) {
   return st;
 }
 
-// copy to the device array *dst, allocated on first use and overwritten in place
-// afterwards (same size; the caller has drained the stream)
+// a new device array *dst holding src in the working precision
 template <class R>
 int upload(fresco_ctx* c, R** dst, const std::vector<double>& src) {
-  if (!*dst) {
-    int st = dalloc_t(c, dst, src.size());
-    if (st) return st;
-  }
+  int st = dalloc_t(c, dst, src.size());
+  if (st) return st;
+  std::vector<R> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (R)src[i];
+  HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice));
+  return FRESCO_OK;
+}
+
+// src into the device array *dst: a new one when *dst is NULL, else the existing
+// one overwritten in place (same size; the caller has drained the stream)
+template <class R>
+int upload_into(fresco_ctx* c, R** dst, const std::vector<double>& src) {
+  if (!*dst) return upload<R>(c, dst, src);
   std::vector<R> tmp(src.size());
   for (size_t i = 0; i < src.size(); ++i) tmp[i] = (R)src[i];
   HIPCHK(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(R), hipMemcpyHostToDevice));
@@ -589,6 +606,7 @@ int create_state(fresco_ctx* c) {
       cp.deci[a] = (a < d) ? S->deci[a] : nullptr;
     }
     cp.invN = (R)(1.0 / (double)g.N);
+    cp.g_scale = (R)(1.0 / (double)g.N);
     cp.mcol = true;  // the long-column path (rows of modes) clears it
   };
   ColParams<R>& c1 = S->col1;
@@ -624,6 +642,8 @@ int create_state(fresco_ctx* c) {
       HIPCHK(prepare_cols<R>(COL_FUSED, c1, S->ax[1]));
       HIPCHK(prepare_cols<R>(COL_SF, c1, S->ax[1]));
       HIPCHK(prepare_cols<R>(COL_BWD, c1, S->ax[1]));
+      HIPCHK(prepare_cols<R>(COL_GFIELD, c1, S->ax[1]));
+      HIPCHK(prepare_cols<R>(COL_GBACK, c1, S->ax[1]));
     } else {
       // columns too long for LDS: two half-length sub-transforms per column
       // (decimation by 2; nf1 is even and 2M + 1 <= nf1 / 2)
@@ -690,6 +710,8 @@ int create_state(fresco_ctx* c) {
     HIPCHK(prepare_cols<R>(COL_FUSED, c2, S->ax[2]));
     HIPCHK(prepare_cols<R>(COL_SF, c2, S->ax[2]));
     HIPCHK(prepare_cols<R>(COL_BWD, c2, S->ax[2]));
+    HIPCHK(prepare_cols<R>(COL_GFIELD, c2, S->ax[2]));
+    HIPCHK(prepare_cols<R>(COL_GBACK, c2, S->ax[2]));
   }
   HIPCHK(prepare_rows<R>(rp, S->ax[0]));
   HIPCHK(spread_prepare<R>(g));
@@ -736,10 +758,10 @@ int upload_weights(fresco_ctx* c, const std::vector<double>& Wc, const std::vect
     }
   }
   int st;
-  if ((st = upload<R>(c, &S->Wp, wp))) return st;
-  if ((st = upload<R>(c, &S->S0p, sp))) return st;
-  if ((st = upload<R>(c, &S->Wm, wm))) return st;
-  if ((st = upload<R>(c, &S->S0m, sm))) return st;
+  if ((st = upload_into<R>(c, &S->Wp, wp))) return st;
+  if ((st = upload_into<R>(c, &S->S0p, sp))) return st;
+  if ((st = upload_into<R>(c, &S->Wm, wm))) return st;
+  if ((st = upload_into<R>(c, &S->S0m, sm))) return st;
   return FRESCO_OK;
 }
 
@@ -879,7 +901,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
   last.S_cube = S_cube;
   // the backward reads rho saved by the structure-factor pass; a loss
   // evaluation keeps none (it also invalidates the reuse of that pass)
-  last.rho_save = (mode == COL_BWD) ? S->rho : nullptr;
+  last.rho_save = (mode == COL_BWD || mode == COL_GFIELD || mode == COL_GBACK) ? S->rho : nullptr;
   last.g_cube = g_cube;
   {
     StageTimer t(c, FRESCO_STAGE_MODES);
@@ -909,6 +931,7 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
     StageTimer t(c, FRESCO_STAGE_FFT_ROWS_INV);
     HIPCHK(launch_rows<R>(true, rp, S->ax[0], 1, st));
   }
+  if (mode == COL_GFIELD) return FRESCO_OK;  // the pair correlation function is in v
   {
     StageTimer t(c, FRESCO_STAGE_INTERP);
     Strengths<R> cs;
@@ -918,6 +941,9 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
     cs.val = (mode == COL_FUSED) ? S->val_eval : nullptr;
     for (int r = 0; r < t.reps; ++r) launch_interp<R>(g, S->bp, S->bb, S->v, grad, cs, st);
   }
+  // the pair-correlation backward has no loss partials here, and the point
+  // flag was handed over by the structure-factor pass before it
+  if (mode == COL_GBACK) return FRESCO_OK;
   // attached soft-core pair term: its gradient is added to grad, its energy to
   // the loss
   const bool pair = (mode == COL_FUSED && c->pair);
@@ -1203,6 +1229,105 @@ int sf_backward_impl(fresco_ctx* c, const void* pos, const void* gS, void* grad,
   S->str_eval = S->has_str ? S->cdev : nullptr;
   S->val_eval = nullptr;
   return run_modes_to_grad<R>(c, COL_BWD, (const R*)pos, nullptr, (const R*)gS, (R*)grad, nullptr);
+}
+
+// ------------------------------------------------- pair correlation loss
+// L_g partials over the fine grid (fixed grid-stride order, kGlossBlocks blocks
+// of 256): sum W_g (g - g0)^2; b = 2 W_g (g - g0) for the backward; g copied out
+// when asked.
+template <class R>
+__global__ void gloss_kernel(const R* __restrict__ g, const R* __restrict__ g0,
+                             const R* __restrict__ wg, long long n, R* __restrict__ b,
+                             R* __restrict__ gout, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const R gi = g[i];
+    const R r = gi - g0[i];
+    const R w = wg[i];
+    acc += (double)w * (double)r * (double)r;
+    b[i] = R(2) * w * r;
+    if (gout) gout[i] = gi;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void sum_parts_kernel(const double* __restrict__ part, int np, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double t = 0.0;
+  for (int i = 0; i < np; ++i) t += part[i];
+  out[0] = t;
+}
+
+// L_g and its gradient (Methods, pair correlation function optimisation):
+// S and rho (type-1 pass), g on the fine grid from (S - 1)/N (inverse passes),
+// L_g and b on the grid, then the forward transform of b whose real part is
+// dL_g/dS, fed to the backward of S (inverse passes and interpolation).
+template <class R>
+int gloss_impl(fresco_ctx* c, const void* pos, double* loss_dev, void* grad, void* g_out) {
+  State<R>* S = (State<R>*)c->state;
+  const Geom& g = c->g;
+  int st;
+  if ((st = structure_factor_impl<R>(c, pos, nullptr))) return st;
+  c->sf_pos = nullptr;
+  S->str_eval = nullptr;
+  S->val_eval = nullptr;
+  if ((st = run_modes_to_grad<R>(c, COL_GFIELD, (const R*)pos, nullptr, nullptr, nullptr, nullptr)))
+    return st;
+  gloss_kernel<R><<<kGlossBlocks, 256, 0, c->st>>>(S->v, S->g0, S->wg, g.ngrid, S->gb, (R*)g_out,
+                                                  S->gpart);
+  sum_parts_kernel<<<1, 64, 0, c->st>>>(S->gpart, kGlossBlocks, loss_dev);
+  HIPCHK(hipGetLastError());
+  // forward transforms of b (rows from the grid, no fold; 3D: axis 1)
+  RowParams<R> rp = S->rows;
+  rp.fold.tiles = nullptr;
+  rp.rin = S->gb;
+  rp.cout = S->A1;
+  HIPCHK(launch_rows<R>(false, rp, S->ax[0], 1, c->st));
+  if (g.d == 3) {
+    const long long H0 = g.M[0] + 1, P1 = 2 * g.M[1] + 1;
+    ColParams<R> fw = S->col1;
+    fw.in_outer = (long long)g.nf[1] * H0;
+    fw.in_line = H0;
+    fw.out_outer = P1 * H0;
+    fw.out_line = H0;
+    fw.in[0] = S->A1;
+    fw.out[0] = S->A2;
+    HIPCHK(launch_cols<R>(COL_FWD, fw, S->ax[1], 1, c->st));
+  }
+  return run_modes_to_grad<R>(c, COL_GBACK, (const R*)pos, nullptr, nullptr, (R*)grad, nullptr);
+}
+
+template <class R>
+int set_gtarget_impl(fresco_ctx* c, const double* g0, const double* wg) {
+  State<R>* S = (State<R>*)c->state;
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (!wg) {
+    S->has_g = false;
+    return FRESCO_OK;
+  }
+  const long long n = c->g.ngrid;
+  std::vector<double> a(n), b(n);
+  for (long long i = 0; i < n; ++i) {
+    a[i] = g0 ? g0[i] : 0.0;
+    b[i] = wg[i];
+    if (!std::isfinite(a[i]) || !(b[i] >= 0.0) || !std::isfinite(b[i])) return FRESCO_EINVAL;
+  }
+  int st;
+  if ((st = upload_into<R>(c, &S->g0, a))) return st;
+  if ((st = upload_into<R>(c, &S->wg, b))) return st;
+  if (!S->gb) {
+    if ((st = dalloc_t(c, &S->gb, n))) return st;
+    if ((st = dalloc_t(c, &S->gpart, kGlossBlocks))) return st;
+  }
+  S->has_g = true;
+  return FRESCO_OK;
 }
 
 // ------------------------------------------------------------ strengths
@@ -1650,6 +1775,42 @@ int fresco_attach_pair(fresco_ctx* c, fresco_pair_ctx* pc, double weight) {
   }
   c->pair = pc;
   c->pair_w = pc ? weight : 0.0;
+  return FRESCO_OK;
+}
+
+int fresco_set_pair_correlation_target(fresco_ctx* c, const double* g0, const double* wg) {
+  if (!c) return FRESCO_EINVAL;
+  if (c->dtype == FRESCO_F32) return set_gtarget_impl<float>(c, g0, wg);
+  return set_gtarget_impl<double>(c, g0, wg);
+}
+
+int fresco_pair_correlation_loss_grad(fresco_ctx* c, const void* pos, double* loss, void* grad,
+                                      void* g_out) {
+  if (!c || !pos || !loss || !grad) return FRESCO_EINVAL;
+  double* ldev;
+  int* fout;
+  int st;
+  if (c->dtype == FRESCO_F32) {
+    State<float>* S = (State<float>*)c->state;
+    if (!S->has_g) return FRESCO_EINVAL;
+    if (S->has_str || S->long_cols) return FRESCO_ENOTSUP;
+    ldev = S->loss_dev;
+    fout = S->flag_out;
+    st = gloss_impl<float>(c, pos, ldev, grad, g_out);
+  } else {
+    State<double>* S = (State<double>*)c->state;
+    if (!S->has_g) return FRESCO_EINVAL;
+    if (S->has_str || S->long_cols) return FRESCO_ENOTSUP;
+    ldev = S->loss_dev;
+    fout = S->flag_out;
+    st = gloss_impl<double>(c, pos, ldev, grad, g_out);
+  }
+  if (st) return st;
+  HIPCHK(hipMemcpyAsync(c->host_loss, ldev, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(c->host_flag, fout, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  *loss = *c->host_loss;
+  if (*c->host_flag) return FRESCO_ENONFINITE;
   return FRESCO_OK;
 }
 

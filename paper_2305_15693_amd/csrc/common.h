@@ -220,6 +220,17 @@ void launch_fill_u32(uint32_t* p, long long n, uint32_t v, hipStream_t st);
 
 // FFT passes (see fft.hip)
 struct FftTables;  // device twiddles and factors per axis
-enum ColMode { COL_FWD = 0, COL_INV = 1, COL_FUSED = 2, COL_SF = 3, COL_BWD = 4 };
+// GFIELD: (S - 1) g_scale from the saved rho as input of the inverse transform
+// (the pair correlation function on the fine grid); GBACK: forward transform of
+// a real grid b, then the backward of S with dF/dS = Re B g_scale.
+enum ColMode {
+  COL_FWD = 0,
+  COL_INV = 1,
+  COL_FUSED = 2,
+  COL_SF = 3,
+  COL_BWD = 4,
+  COL_GFIELD = 5,
+  COL_GBACK = 6
+};
 
 }  // namespace fresco

@@ -68,6 +68,7 @@ struct ColParams {
   const R* dec[3];   // spreading kernel: h_a / psihat_a(|n_a|), n_a in [0, M_a]
   const R* deci[3];  // interpolation kernel: h_a / psihat_i,a(|n_a|)
   R invN;
+  R g_scale;         // GFIELD / GBACK: 1 / N, the factor of the pair correlation function
   bool mcol;         // mode-stage arrays below column-major [c][m] (else [m][c])
   const R* Wp;       // half spectrum: W(n), S0(n), W(-n), S0(-n)
   const R* S0p;

@@ -297,7 +297,8 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
   // c = n0 + H0 * (n1 + M1) in 3D, c = n0 in 2D.  Its column factors, and in
   // FUSED the weights, targets and kernel factors of this thread's modes
   // m = tj + u JT, are loaded before the forward transform.
-  constexpr bool kModes = MODE == COL_FUSED || MODE == COL_SF || MODE == COL_BWD;
+  constexpr bool kModes = MODE == COL_FUSED || MODE == COL_SF || MODE == COL_BWD ||
+                          MODE == COL_GFIELD || MODE == COL_GBACK;
   int n0 = 0, n1 = 0;
   R dlead = R(0), ilead = R(0);
   if (kModes && active) {
@@ -330,7 +331,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       pdi[u] = ok ? p.deci[p.d - 1][al] : R(0);
     }
   }
-  if (MODE == COL_FWD || MODE == COL_FUSED || MODE == COL_SF) {
+  if (MODE == COL_FWD || MODE == COL_FUSED || MODE == COL_SF || MODE == COL_GBACK) {
     // forward: load the full spatial line, transform with exp(+i ...)
     if (active) copy_strided4(buf + b, (long long)bc, p.in[0] + ib, p.in_line, tj, JT, n);
     __syncthreads();
@@ -388,7 +389,7 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       // half-spectrum index of the mode-stage arrays
       const long long hidx = p.mcol ? c * P + m : c + (long long)p.ncols * m;
       cpx<R> rho;
-      if (MODE == COL_BWD) {
+      if (MODE == COL_BWD || MODE == COL_GFIELD || MODE == COL_GBACK) {
         rho = p.rho_save[hidx];
       } else {
         const int i = nl < 0 ? nl + n : nl;
@@ -410,6 +411,19 @@ __global__ void cols_kernel(ColParams<R> p, FftFactors F, const cpx<R>* __restri
       if ((MODE == COL_SF || MODE == COL_FUSED) && p.S_cube) {
         p.S_cube[cp] = S;
         if (n0 > 0) p.S_cube[cm] = S;
+      }
+      if (MODE == COL_GFIELD) {
+        // g(x) = (1/N) sum_n (S(n) - 1) exp(-i k.x): plain coefficients, no
+        // kernel deconvolution (the inverse transform lands on grid points)
+        qbuf[m * bc + b] = cpx<R>{(S - R(1)) * p.g_scale, R(0)};
+      }
+      if (MODE == COL_GBACK) {
+        // dL_g/dS(n) = g_scale Re B(n), B the forward transform of b = 2 W_g (g - g0)
+        // (real and even in n); S(0) = N does not depend on the positions
+        const int i = nl < 0 ? nl + n : nl;
+        const R G = (cp == cm) ? R(0) : buf[i * bc + b].x * p.g_scale;
+        const R f = R(2) * G * p.invN * ilead * dik;
+        qbuf[m * bc + b] = cscale(rho, f);
       }
       if (MODE == COL_FUSED || MODE == COL_BWD) {
         // G: dL/dS symmetrised over the pair (n, -n)
@@ -600,7 +614,8 @@ template <class R>
 size_t cols_lds_bytes(int mode, const ColParams<R>& p, const AxisFft<R>& ax) {
   const int n = ax.F.n;
   size_t e = (p.tw_lds ? (size_t)n : 0) + (size_t)n * p.bc;
-  if (mode == COL_FUSED || mode == COL_BWD) e += (size_t)(2 * p.M + 1) * p.bc;
+  if (mode == COL_FUSED || mode == COL_BWD || mode == COL_GFIELD || mode == COL_GBACK)
+    e += (size_t)(2 * p.M + 1) * p.bc;
   return e * sizeof(cpx<R>);
 }
 
@@ -656,6 +671,8 @@ hipError_t prepare_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax) {
       case COL_FUSED: PREP1(MB, COL_FUSED); break;      \
       case COL_SF: PREP1(MB, COL_SF); break;            \
       case COL_BWD: PREP1(MB, COL_BWD); break;          \
+      case COL_GFIELD: PREP1(MB, COL_GFIELD); break;    \
+      case COL_GBACK: PREP1(MB, COL_GBACK); break;      \
     }                                                   \
   } while (0)
   FRESCO_MB_SWITCH(mb, PREP)
@@ -704,6 +721,8 @@ hipError_t launch_cols(int mode, const ColParams<R>& p, const AxisFft<R>& ax, in
       case COL_FUSED: COLS1(MB, COL_FUSED); break;      \
       case COL_SF: COLS1(MB, COL_SF); break;            \
       case COL_BWD: COLS1(MB, COL_BWD); break;          \
+      case COL_GFIELD: COLS1(MB, COL_GFIELD); break;    \
+      case COL_GBACK: COLS1(MB, COL_GBACK); break;      \
     }                                                   \
   } while (0)
   FRESCO_MB_SWITCH(mb, COLS)

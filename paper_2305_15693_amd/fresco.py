@@ -135,6 +135,11 @@ def _load():
                                           dpp, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_int64)]
     lib.fresco_overlap_cycles.restype = i
+    lib.fresco_set_pair_correlation_target.argtypes = [vp, dpp, dpp]
+    lib.fresco_set_pair_correlation_target.restype = i
+    lib.fresco_pair_correlation_loss_grad.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double),
+                                                      vp, vp]
+    lib.fresco_pair_correlation_loss_grad.restype = i
     lib.fresco_set_strengths.argtypes = [vp, vp]
     lib.fresco_set_strengths.restype = i
     lib.fresco_loss_grad_strengths.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), vp, vp]
@@ -378,6 +383,34 @@ class Context:
                                           ctypes.byref(loss), ctypes.byref(cyc), ctypes.byref(rep)),
                "fresco_overlap_cycles")
         return float(loss.value), int(cyc.value), int(rep.value)
+
+    def grid_shape(self):
+        """Shape of arrays on the fine grid, C order (axis 0 fastest): (nf_{d-1}, ..., nf_0)."""
+        return tuple(reversed(self.plan_info()["nf"]))
+
+    def set_pair_correlation_target(self, g0=None, wg=None):
+        """Target g0 and weights W_g of the pair-correlation loss on the fine grid
+        (arrays of grid_shape(); wg None disables the term)."""
+        shape = self.grid_shape()
+        a = None if g0 is None else np.ascontiguousarray(np.asarray(g0, np.float64).reshape(shape))
+        b = None if wg is None else np.ascontiguousarray(np.asarray(wg, np.float64).reshape(shape))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(_lib.fresco_set_pair_correlation_target(
+            self._h, None if a is None else a.ctypes.data_as(dp),
+            None if b is None else b.ctypes.data_as(dp)), "fresco_set_pair_correlation_target")
+
+    def pair_correlation_loss_grad(self, pos, grad=None, want_g: bool = False):
+        """(L_g, dL_g/dr [n][d], g on the fine grid or None)."""
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty((self.n, self.dim), dtype=self.torch_dtype, device=self.device)
+        g = (torch.empty(self.grid_shape(), dtype=self.torch_dtype, device=self.device)
+             if want_g else None)
+        _check(_lib.fresco_pair_correlation_loss_grad(
+            self._h, self._pos(pos), ctypes.byref(self._loss), ctypes.c_void_p(grad.data_ptr()),
+            ctypes.c_void_p(g.data_ptr()) if g is not None else None),
+            "fresco_pair_correlation_loss_grad")
+        return float(self._loss.value), grad, g
 
     def set_strengths(self, c):
         """Point strengths for every later evaluation (a [n] tensor of the context's

@@ -127,6 +127,14 @@ def test_set_target_matches_a_new_context(gpu):
     pa = pos0.clone()
     a.step(pa, 3)
     a.set_target(sb, wb, relative=True)
+    # the re-targeted context evaluates the new loss (oracle, direct sums)
+    from oracle import oracle as O
+    modes, W, S0 = O.constrained_set(d, M, wb, sb, relative=True)
+    xa = pa.cpu().numpy().astype(np.float64)
+    ref = O.loss_grad(xa, L, modes, W, S0)
+    l_new, g_new = a.loss_grad(pa)
+    assert abs(l_new - ref["loss"]) <= 1e-5 * ref["loss"]
+    assert np.linalg.norm(g_new.cpu().numpy() - ref["grad"]) <= 1e-5 * np.linalg.norm(ref["grad"])
     pb = pa.clone()
     la, na = a.step(pa, 5)
     b = F.Context(d, N, L, M, w_cube=wb, s0_cube=sb, relative=True, tol=1e-6, dtype="f32",
