@@ -463,6 +463,83 @@ int oracle_fd_c(int d, long long N, const double* L, const double* pos, const do
 }
 
 /*
+ * Non-uniform wave vectors (Methods, the NUwNU variant and the Ewald
+ * construction: free boundary conditions, constraints at any continuous q):
+ *   rho(q) = sum_j c_j exp(+i q.r_j) at the listed q [K][d] (c NULL: c_j = 1),
+ * by direct sums with libm cos/sin of the FP64 phase q.r_j (positions as given,
+ * no wrapping).  rho [K][2].
+ */
+int oracle_rho_q(int d, long long N, const double* pos, const double* c, long long K,
+                 const double* q, double* rho) {
+  if (d < 1 || d > 3 || N < 0 || K < 0 || (N && !pos) || (K && (!q || !rho))) return OR_EINVAL;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long long k = 0; k < K; ++k) {
+    double sr = 0.0, si = 0.0;
+    for (long long j = 0; j < N; ++j) {
+      double ph = 0.0;
+      for (int a = 0; a < d; ++a) ph += q[k * d + a] * pos[j * d + a];
+      const double cj = c ? c[j] : 1.0;
+      sr += cj * cos(ph);
+      si += cj * sin(ph);
+    }
+    rho[2 * k] = sr;
+    rho[2 * k + 1] = si;
+  }
+  return OR_OK;
+}
+
+/*
+ * Loss over non-uniform wave vectors and its position gradient:
+ *   S_k = |rho(q_k)|^2 / rho0 (rho0 = sum c^2, N for unit strengths),
+ *   L = sum_k W_k (S_k - S0_k)^2,
+ *   dL/dr_j = c_j sum_k (4 W_k (S_k - S0_k) / rho0) q_k Re[i conj(rho_k) exp(i q_k.r_j)].
+ * S_out [K], grad [N][d] (either may be NULL).
+ */
+int oracle_loss_grad_q(int d, long long N, const double* pos, const double* c, long long K,
+                       const double* q, const double* W, const double* S0, double* S_out,
+                       double* loss_out, double* grad) {
+  if (d < 1 || d > 3 || N <= 0 || K < 0 || !pos || (K && (!q || !W || !S0))) return OR_EINVAL;
+  double rho0 = 0.0;
+  for (long long j = 0; j < N; ++j) rho0 += c ? c[j] * c[j] : 1.0;
+  if (!(rho0 > 0.0)) return OR_EINVAL;
+  double* rho = (double*)malloc(sizeof(double) * 2 * (K ? K : 1));
+  double* A = (double*)malloc(sizeof(double) * 2 * (K ? K : 1));
+  if (!rho || !A) { free(rho); free(A); return OR_ENOMEM; }
+  int st = oracle_rho_q(d, N, pos, c, K, q, rho);
+  if (st) { free(rho); free(A); return st; }
+  double loss = 0.0;
+  for (long long k = 0; k < K; ++k) {
+    const double S = (rho[2 * k] * rho[2 * k] + rho[2 * k + 1] * rho[2 * k + 1]) / rho0;
+    const double res = S - S0[k];
+    loss += W[k] * res * res;
+    if (S_out) S_out[k] = S;
+    const double f = 4.0 * W[k] * res / rho0;
+    A[2 * k] = f * rho[2 * k];       /* f conj(rho): re */
+    A[2 * k + 1] = -f * rho[2 * k + 1]; /* im */
+  }
+  if (loss_out) *loss_out = loss;
+  if (grad) {
+#pragma omp parallel for schedule(static)
+    for (long long j = 0; j < N; ++j) {
+      double acc[3] = {0.0, 0.0, 0.0};
+      for (long long k = 0; k < K; ++k) {
+        double ph = 0.0;
+        for (int a = 0; a < d; ++a) ph += q[k * d + a] * pos[j * d + a];
+        const double er = cos(ph), ei = sin(ph);
+        /* Re[i A e] = -Im[A e] = -(A_re ei + A_im er) */
+        const double v = -(A[2 * k] * ei + A[2 * k + 1] * er);
+        for (int a = 0; a < d; ++a) acc[a] += q[k * d + a] * v;
+      }
+      const double cj = c ? c[j] : 1.0;
+      for (int a = 0; a < d; ++a) grad[j * d + a] = cj * acc[a];
+    }
+  }
+  free(rho);
+  free(A);
+  return OR_OK;
+}
+
+/*
  * Vector-Jacobian product of the structure factor (the derivative of S with
  * respect to a position, Methods, "Analytical gradients"):
  *   dS(k)/dr_ja = (2/N) Re[conj(rho(k)) i k_a exp(i k.r_j)]

@@ -75,6 +75,10 @@ def _load():
         lib.oracle_pair_fd.argtypes = [ctypes.c_int, ll, dp, dp, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ll, lp, ip, ctypes.c_double, dp]
         lib.oracle_pair_fd.restype = ctypes.c_int
+        lib.oracle_rho_q.argtypes = [ctypes.c_int, ll, dp, dp, ll, dp, dp]
+        lib.oracle_rho_q.restype = ctypes.c_int
+        lib.oracle_loss_grad_q.argtypes = [ctypes.c_int, ll, dp, dp, ll, dp, dp, dp, dp, dp, dp]
+        lib.oracle_loss_grad_q.restype = ctypes.c_int
         lib.oracle_rho_c.argtypes = [ctypes.c_int, ll, dp, dp, dp, ll, ip, dp]
         lib.oracle_rho_c.restype = ctypes.c_int
         lib.oracle_loss_grad_c.argtypes = [ctypes.c_int, ll, dp, dp, dp, ll, ip, dp, dp, dp, dp,
@@ -341,6 +345,86 @@ def finite_difference_strengths(pos, c, L, modes, W, S0, coords, h: float) -> np
     if st:
         raise RuntimeError(f"oracle finite difference with strengths failed ({st})")
     return out
+
+
+def rho_q(pos, q, c=None) -> np.ndarray:
+    """rho(q) = sum_j c_j exp(+i q.r_j) at arbitrary wave vectors q [K][d] (free
+    boundary conditions: positions as given), by direct sums."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, d))
+    cc = None if c is None else _strengths(c, N)
+    out = np.zeros((len(q), 2))
+    st = _load().oracle_rho_q(d, N, _p(pos, ctypes.c_double), _p(cc, ctypes.c_double), len(q),
+                              _p(q, ctypes.c_double), _p(out, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle rho_q failed ({st})")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def structure_factor_q(pos, q, c=None) -> np.ndarray:
+    """S(q) = |rho(q)|^2 / rho0 at arbitrary q (rho0 = sum c^2, N for unit strengths)."""
+    pos = _pos(pos)
+    rho0 = float(len(pos)) if c is None else float(np.sum(np.asarray(c, np.float64) ** 2))
+    return np.abs(rho_q(pos, q, c)) ** 2 / rho0
+
+
+def loss_grad_q(pos, q, W, S0, c=None, want_grad: bool = True):
+    """Loss over arbitrary wave vectors (NUwNU): L = sum_k W_k (S(q_k) - S0_k)^2 and its
+    position gradient.  Returns dict(S, loss, grad)."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, d))
+    K = len(q)
+    W = np.ascontiguousarray(W, dtype=np.float64).ravel()
+    S0 = np.ascontiguousarray(S0, dtype=np.float64).ravel()
+    cc = None if c is None else _strengths(c, N)
+    S = np.zeros(K)
+    loss = np.zeros(1)
+    grad = np.zeros((N, d)) if want_grad else None
+    st = _load().oracle_loss_grad_q(d, N, _p(pos, ctypes.c_double), _p(cc, ctypes.c_double), K,
+                                    _p(q, ctypes.c_double), _p(W, ctypes.c_double),
+                                    _p(S0, ctypes.c_double), _p(S, ctypes.c_double),
+                                    _p(loss, ctypes.c_double), _p(grad, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle loss_grad_q failed ({st})")
+    return {"S": S, "loss": float(loss[0]), "grad": grad}
+
+
+def ewald_directions(d: int, e_inc, ns: int):
+    """Scattered directions of the Ewald construction for the incident direction
+    e_inc (a unit vector) and whether each lies in the forward half (main text,
+    Eq. ewald; SI, single scattering): in 2D the ns - 1 directions at angles
+    2 pi m / ns, m = 1 .. ns - 1, from e_inc (m = 0, the incident direction itself,
+    is left out); in 3D an ns-point Fibonacci lattice on the sphere, z_i = 1 -
+    (2i + 1)/ns, phi_i = i pi (3 - sqrt 5), in the frame whose z axis is e_inc
+    (x axis: a x e_inc normalised, with a = e_z, or e_x when |e_inc . e_z| > 0.9).
+    Forward: e_s . e_inc > 0."""
+    e = np.asarray(e_inc, dtype=np.float64)
+    if d == 2:
+        th = np.arctan2(e[1], e[0]) + 2 * np.pi * np.arange(1, ns) / ns
+        es = np.stack([np.cos(th), np.sin(th)], 1)
+    else:
+        i = np.arange(ns)
+        z = 1.0 - (2 * i + 1) / ns
+        ph = i * np.pi * (3.0 - np.sqrt(5.0))
+        rr = np.sqrt(1.0 - z * z)
+        u = np.stack([rr * np.cos(ph), rr * np.sin(ph), z], 1)
+        a = np.array([1.0, 0.0, 0.0]) if abs(e[2]) > 0.9 else np.array([0.0, 0.0, 1.0])
+        e1 = np.cross(a, e)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(e, e1)
+        es = u[:, :1] * e1 + u[:, 1:2] * e2 + u[:, 2:] * e
+    return es, es @ e > 0.0
+
+
+def ewald_transmission(S_of_q, d: int, k: float, e_inc, ns: int) -> float:
+    """T(k e_inc) = sum over forward scattered directions of S(q) / sum over all of
+    them, q = k (e_s - e_inc) (Eq. ewald, the integrals by the quadrature of
+    ewald_directions).  S_of_q: callable on [K][d] wave vectors."""
+    es, fwd = ewald_directions(d, e_inc, ns)
+    S = np.asarray(S_of_q(k * (es - np.asarray(e_inc, np.float64))), dtype=np.float64)
+    return float(S[fwd].sum() / S.sum())
 
 
 def pair_correlation(pos, L, M, xs) -> np.ndarray:

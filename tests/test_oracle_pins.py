@@ -736,3 +736,87 @@ def test_pair_correlation_loss_gradient_finite_differences():
         fd = (O.pair_correlation_loss_grad(pp, L, M, xs, wg, g0)["loss"] -
               O.pair_correlation_loss_grad(pm, L, M, xs, wg, g0)["loss"]) / (2 * h)
         assert r["grad"][j, a] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+# -------------------------------------------- non-uniform wave vectors (NUwNU)
+def test_rho_q_equals_the_periodic_oracle_on_lattice_vectors():
+    # at q = 2 pi n / L the free-boundary direct sum is the periodic one
+    rng = np.random.default_rng(111)
+    L = np.array([6.0, 8.5])
+    pos = rng.uniform(0, 1, (70, 2)) * L
+    modes = _modes_ball(2, 3.0)
+    q = 2 * np.pi * modes / L
+    np.testing.assert_allclose(O.rho_q(pos, q), O.rho(pos, L, modes), rtol=1e-12, atol=1e-11)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_peak_echo_on_a_sheared_lattice(d):
+    # points on a lattice whose dual basis is the constrained set {k_j}, cut to a
+    # ball (free boundary): S(k_j) = N, and every integer combination of the k_j
+    # is a peak S = N too (SI, saturating peaks and echoes); other q are not
+    rng = np.random.default_rng(112 + d)
+    K = rng.normal(size=(d, d)) + 2 * np.eye(d)       # rows: k_1 .. k_d
+    A = 2 * np.pi * np.linalg.inv(K).T                 # rows a_i with a_i . k_j = 2 pi delta_ij
+    m = np.stack(np.meshgrid(*[np.arange(-9, 10)] * d, indexing="ij"), -1).reshape(-1, d)
+    pos = m @ A + rng.normal(size=d)
+    pos = pos[np.linalg.norm(pos - pos.mean(0), axis=1) < 6.0 * np.abs(A).max()]
+    N = len(pos)
+    combos = [np.eye(d)[0], np.eye(d)[-1], 2 * np.eye(d)[0] - 3 * np.eye(d)[-1]]
+    q = np.array([c @ K for c in combos])
+    np.testing.assert_allclose(O.structure_factor_q(pos, q), N, rtol=1e-10)
+    assert O.structure_factor_q(pos, 0.5 * K[:1])[0] < 0.9 * N
+
+
+def test_structure_factor_q_translation_and_friedel():
+    rng = np.random.default_rng(114)
+    pos = rng.uniform(-3, 5, (60, 3))
+    q = rng.normal(size=(15, 3)) * 2.0
+    S = O.structure_factor_q(pos, q)
+    np.testing.assert_allclose(O.structure_factor_q(pos + rng.normal(size=3) * 7, q), S,
+                               rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(O.structure_factor_q(pos, -q), S, rtol=1e-12, atol=1e-13)
+
+
+def test_loss_grad_q_finite_differences_and_sum_rule():
+    rng = np.random.default_rng(115)
+    pos = rng.uniform(0, 6, (30, 2))
+    c = rng.lognormal(0, 0.3, 30)
+    q = rng.normal(size=(12, 2)) * 2.0
+    W = rng.uniform(0.5, 1.5, 12)
+    S0 = rng.uniform(0, 2, 12)
+    for cc in (None, c):
+        r = O.loss_grad_q(pos, q, W, S0, cc)
+        assert np.abs(r["grad"].sum(0)).max() <= 1e-12 * np.abs(r["grad"]).sum()
+        h = 1e-5
+        for j, a in [(0, 0), (7, 1), (29, 0)]:
+            pp, pm = pos.copy(), pos.copy()
+            pp[j, a] += h
+            pm[j, a] -= h
+            fd = (O.loss_grad_q(pp, q, W, S0, cc, want_grad=False)["loss"] -
+                  O.loss_grad_q(pm, q, W, S0, cc, want_grad=False)["loss"]) / (2 * h)
+            assert r["grad"][j, a] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+@pytest.mark.parametrize("d,ns", [(2, 360), (3, 2000)])
+def test_ewald_transmission_edges(d, ns):
+    # a structure factor that vanishes inside |q| < K (stealthy) and is 1 outside:
+    # below k_b = K/2 the whole circle (sphere) stays inside, T is the forward
+    # fraction of the quadrature; above k_b the backward directions scatter and
+    # forward ones do not, T = 0, until k_f = K/sqrt 2 where forward scattering
+    # sets in (main text, Fig. ewald)
+    Kc = 3.0
+    eps = 1e-30
+
+    def S_of_q(q):
+        return np.where(np.linalg.norm(q, axis=1) >= Kc, 1.0, eps)
+
+    e = np.zeros(d)
+    e[0] = 0.6
+    e[1] = 0.8
+    es, fwd = O.ewald_directions(d, e, ns)
+    np.testing.assert_allclose(np.linalg.norm(es, axis=1), 1.0, rtol=1e-13)
+    assert abs(fwd.mean() - 0.5) < 0.01
+    assert O.ewald_transmission(S_of_q, d, 0.48 * Kc, e, ns) == pytest.approx(fwd.mean(), rel=1e-12)
+    assert O.ewald_transmission(S_of_q, d, 0.52 * Kc, e, ns) < 1e-20
+    assert O.ewald_transmission(S_of_q, d, 0.69 * Kc, e, ns) < 1e-20
+    assert O.ewald_transmission(S_of_q, d, 0.75 * Kc, e, ns) > 1e-3
