@@ -425,6 +425,65 @@ int fresco_batch_autotune(fresco_batch_ctx* batch, const void* pos, void* grad, 
 /* Last hipError_t seen by the batch functions (0 if none). */
 int fresco_batch_last_hip_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Structure factor at arbitrary wave vectors, free boundary conditions (the
+ * NUwNU variant of the Methods: constraints at any continuous q, such as Bragg
+ * peaks of rotational symmetries no lattice has; the Ewald construction of the
+ * main text):
+ *   rho(q_k) = sum_j c_j exp(+i q_k . r_j)   (positions as given, not wrapped),
+ *   S_k = |rho(q_k)|^2 / rho0,  rho0 = sum_j c_j^2 (N for unit strengths),
+ *   L = sum_k W_k (S_k - S0_k)^2,
+ *   dL/dr_j = c_j sum_k (4 W_k (S_k - S0_k) / rho0) q_k Re[i conj(rho_k) exp(i q_k . r_j)].
+ * Evaluated by direct sums on the GPU, O(N K) (exact; suited to constraint sets
+ * of tens to thousands of wave vectors), phases in FP64, sums in FP64. */
+typedef struct fresco_q_ctx fresco_q_ctx;
+
+/* Context for n points in dim (2, 3) dimensions of the dtype and at most max_q
+ * wave vectors at a time, bound to a stream.  Errors: EINVAL, ENOTSUP (n >= 2^31,
+ * max_q > 2^26), ENOMEM. */
+int fresco_q_create(fresco_q_ctx** out, int32_t dim, int32_t dtype, int64_t n, int64_t max_q,
+                    void* stream);
+int fresco_q_destroy(fresco_q_ctx* ctx);
+
+/* The wave vectors q (HOST [K][dim] doubles, K <= max_q), weights W (NULL: 1)
+ * and targets S0 (NULL: 0) of the loss.  Synchronises.  Errors: EINVAL (K out of
+ * range, non-finite values, a negative weight), EHIP. */
+int fresco_q_set(fresco_q_ctx* ctx, int64_t K, const double* q, const double* W, const double* S0);
+
+/* S at the wave vectors set (DEVICE S [K] doubles) and optionally rho (DEVICE
+ * [K][2] doubles, may be NULL).  pos: device [n][dim]; c: device [n] strengths
+ * of the dtype or NULL (unit).  Enqueues only.  Errors: EINVAL, EHIP. */
+int fresco_q_structure_factor(fresco_q_ctx* ctx, const void* pos, const void* c, double* S,
+                              double* rho);
+
+/* Loss over the wave vectors set and its position gradient (grad: device
+ * [n][dim], overwritten).  loss: HOST pointer; synchronises.  Errors: EINVAL,
+ * EHIP. */
+int fresco_q_loss_grad(fresco_q_ctx* ctx, const void* pos, const void* c, double* loss,
+                       void* grad);
+
+/* Forward-scattered transmission of the Ewald construction (main text, Eq.
+ * ewald; SI, single scattering): for each incident wave vector k_i e_j (k: HOST
+ * [n_k] magnitudes > 0; dirs: HOST [n_dir][dim] unit directions),
+ *   T = sum_{forward s} S(k (e_s - e_j)) / sum_{all s} S(k (e_s - e_j)),
+ * over the scattered directions e_s of a quadrature: in 2D the ns - 1 directions
+ * at angles 2 pi m / ns from e_j, m = 1 .. ns - 1 (the incident direction, where
+ * S(0) = N, left out); in 3D the ns-point Fibonacci lattice z_m = 1 - (2m+1)/ns,
+ * phi_m = m pi (3 - sqrt 5) in the frame whose z axis is e_j (x axis: a x e_j
+ * normalised, a = e_z, or e_x when |e_j . e_z| > 0.9).  Forward: e_s . e_j > 0
+ * strictly, decided on integers (2D: 4m < ns or 4m > 3ns; 3D: 2m + 1 < ns).
+ * The paper cuts the pattern to a disk (ball) first, which is the caller's
+ * choice of points.  T: HOST [n_k][n_dir].  Uses the context's wave-vector
+ * buffer (ns - 1 or ns <= max_q), dropping the set of fresco_q_set.
+ * Synchronises.  Errors: EINVAL, ENOTSUP (quadrature larger than max_q), ENOMEM,
+ * EHIP. */
+int fresco_ewald_transmission(fresco_q_ctx* ctx, const void* pos, const void* c, int32_t n_k,
+                              const double* k, int32_t n_dir, const double* dirs, int32_t ns,
+                              double* T);
+
+/* Last hipError_t seen by a wave-vector context (0 if none). */
+int fresco_q_last_hip_error(const fresco_q_ctx* ctx);
+
 /* Stages of one evaluation, for fresco_set_timing / fresco_read_timing. */
 enum fresco_stage {
   FRESCO_STAGE_BIN = 0,          /* wrap, split, counting sort by tile (4 kernels) */

@@ -399,11 +399,15 @@ def ewald_directions(d: int, e_inc, ns: int):
     is left out); in 3D an ns-point Fibonacci lattice on the sphere, z_i = 1 -
     (2i + 1)/ns, phi_i = i pi (3 - sqrt 5), in the frame whose z axis is e_inc
     (x axis: a x e_inc normalised, with a = e_z, or e_x when |e_inc . e_z| > 0.9).
-    Forward: e_s . e_inc > 0."""
+    Forward: e_s . e_inc > 0 strictly, decided on the quadrature's integers so that
+    the directions at exactly 90 degrees are not forward (2D: 4m < ns or 4m > 3ns;
+    3D: z_i > 0, i.e. 2i + 1 < ns)."""
     e = np.asarray(e_inc, dtype=np.float64)
     if d == 2:
-        th = np.arctan2(e[1], e[0]) + 2 * np.pi * np.arange(1, ns) / ns
+        m = np.arange(1, ns)
+        th = np.arctan2(e[1], e[0]) + 2 * np.pi * m / ns
         es = np.stack([np.cos(th), np.sin(th)], 1)
+        return es, (4 * m < ns) | (4 * m > 3 * ns)
     else:
         i = np.arange(ns)
         z = 1.0 - (2 * i + 1) / ns
@@ -415,7 +419,7 @@ def ewald_directions(d: int, e_inc, ns: int):
         e1 /= np.linalg.norm(e1)
         e2 = np.cross(e, e1)
         es = u[:, :1] * e1 + u[:, 1:2] * e2 + u[:, 2:] * e
-    return es, es @ e > 0.0
+        return es, 2 * i + 1 < ns
 
 
 def ewald_transmission(S_of_q, d: int, k: float, e_inc, ns: int) -> float:

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfresco.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["plan.cpp", "spread.hip", "fft.hip", "lbfgs.hip", "pair.hip", "batch.hip", "capi.hip"]
+SOURCES = ["plan.cpp", "spread.hip", "fft.hip", "lbfgs.hip", "pair.hip", "batch.hip", "type3.hip",
+           "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

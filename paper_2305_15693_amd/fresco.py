@@ -135,6 +135,22 @@ def _load():
                                           dpp, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_int64)]
     lib.fresco_overlap_cycles.restype = i
+    lib.fresco_q_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int64, ctypes.c_int64, vp]
+    lib.fresco_q_create.restype = i
+    lib.fresco_q_destroy.argtypes = [vp]
+    lib.fresco_q_destroy.restype = i
+    lib.fresco_q_set.argtypes = [vp, ctypes.c_int64, dpp, dpp, dpp]
+    lib.fresco_q_set.restype = i
+    lib.fresco_q_structure_factor.argtypes = [vp, vp, vp, vp, vp]
+    lib.fresco_q_structure_factor.restype = i
+    lib.fresco_q_loss_grad.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.fresco_q_loss_grad.restype = i
+    lib.fresco_ewald_transmission.argtypes = [vp, vp, vp, ctypes.c_int32, dpp, ctypes.c_int32,
+                                              dpp, ctypes.c_int32, dpp]
+    lib.fresco_ewald_transmission.restype = i
+    lib.fresco_q_last_hip_error.argtypes = [vp]
+    lib.fresco_q_last_hip_error.restype = i
     lib.fresco_set_pair_correlation_target.argtypes = [vp, dpp, dpp]
     lib.fresco_set_pair_correlation_target.restype = i
     lib.fresco_pair_correlation_loss_grad.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double),
@@ -541,6 +557,96 @@ def pair_energy_grad_noalloc(pos, energy_dev, grad, box, *, sigma: float = 0.5, 
                                                 ctypes.c_void_p(stream.cuda_stream)),
            "fresco_pair_energy_grad_noalloc")
     return energy_dev, grad
+
+
+class QContext:
+    """Structure factor, NUwNU loss and Ewald transmission at arbitrary wave vectors
+    with free boundary conditions (include/fresco.h, fresco_q_*)."""
+
+    def __init__(self, dim: int, n: int, max_q: int, *, dtype: str = "f32", stream=None,
+                 device=None):
+        torch = _torch()
+        self.dim, self.n, self.max_q, self.dtype = int(dim), int(n), int(max_q), dtype
+        self.torch_dtype = torch.float32 if dtype == "f32" else torch.float64
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self.K = 0
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.fresco_q_create(ctypes.byref(h), self.dim, F32 if dtype == "f32" else F64,
+                                        self.n, self.max_q, ctypes.c_void_p(stream.cuda_stream)),
+                   "fresco_q_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.fresco_q_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _pos(self, pos):
+        if pos.device != self.device or pos.dtype != self.torch_dtype:
+            raise ValueError(f"positions must be {self.torch_dtype} on {self.device}")
+        if tuple(pos.shape) != (self.n, self.dim) or not pos.is_contiguous():
+            raise ValueError(f"positions must be a contiguous [{self.n}][{self.dim}] tensor")
+        return ctypes.c_void_p(pos.data_ptr())
+
+    def _c(self, c):
+        if c is None:
+            return None
+        if c.device != self.device or c.dtype != self.torch_dtype or c.numel() != self.n:
+            raise ValueError("strengths must be [n] of the context's dtype on its device")
+        return ctypes.c_void_p(c.data_ptr())
+
+    def set(self, q, W=None, S0=None):
+        dp = ctypes.POINTER(ctypes.c_double)
+        q = np.ascontiguousarray(np.asarray(q, np.float64).reshape(-1, self.dim))
+        K = len(q)
+        Wa = None if W is None else np.ascontiguousarray(np.asarray(W, np.float64).ravel())
+        Sa = None if S0 is None else np.ascontiguousarray(np.asarray(S0, np.float64).ravel())
+        _check(_lib.fresco_q_set(self._h, K, q.ctypes.data_as(dp),
+                                 None if Wa is None else Wa.ctypes.data_as(dp),
+                                 None if Sa is None else Sa.ctypes.data_as(dp)), "fresco_q_set")
+        self.K = K
+
+    def structure_factor(self, pos, c=None, want_rho: bool = False):
+        torch = _torch()
+        S = torch.empty(self.K, dtype=torch.float64, device=self.device)
+        rho = torch.empty((self.K, 2), dtype=torch.float64, device=self.device) if want_rho else None
+        _check(_lib.fresco_q_structure_factor(self._h, self._pos(pos), self._c(c),
+                                              ctypes.c_void_p(S.data_ptr()),
+                                              ctypes.c_void_p(rho.data_ptr()) if want_rho else None),
+               "fresco_q_structure_factor")
+        return (S, rho) if want_rho else S
+
+    def loss_grad(self, pos, c=None, grad=None):
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty((self.n, self.dim), dtype=self.torch_dtype, device=self.device)
+        loss = ctypes.c_double(0.0)
+        _check(_lib.fresco_q_loss_grad(self._h, self._pos(pos), self._c(c), ctypes.byref(loss),
+                                       ctypes.c_void_p(grad.data_ptr())), "fresco_q_loss_grad")
+        return float(loss.value), grad
+
+    def ewald_transmission(self, pos, k, dirs, ns: int, c=None):
+        """T[n_k][n_dir] of the Ewald construction (fresco_ewald_transmission)."""
+        dp = ctypes.POINTER(ctypes.c_double)
+        k = np.ascontiguousarray(np.asarray(k, np.float64).ravel())
+        dirs = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(-1, self.dim))
+        T = np.zeros((len(k), len(dirs)))
+        _check(_lib.fresco_ewald_transmission(self._h, self._pos(pos), self._c(c), len(k),
+                                              k.ctypes.data_as(dp), len(dirs),
+                                              dirs.ctypes.data_as(dp), int(ns), T.ctypes.data_as(dp)),
+               "fresco_ewald_transmission")
+        self.K = 0
+        return T
 
 
 class PairContext:
