@@ -372,9 +372,14 @@ int fresco_attach_pair(fresco_ctx* ctx, fresco_pair_ctx* pair, double weight);
 /* ---------------------------------------------------------------------------
  * Ragged batches: many independent problems of the kind above (each with its
  * own n, box, targets and weights; all with the same dim, dtype, kmax and tol)
- * evaluated by one persistent kernel launch in which a workgroup keeps the whole
- * fine grid of one configuration in LDS (spread, FFT, modes, inverse FFT and
- * interpolation never leave the CU).  The grid must fit: roughly
+ * evaluated together, every configuration's whole fine grid held in LDS.  One
+ * evaluation of the batch is three launches, captured with the optimiser
+ * kernels in one HIP graph: spreading over work items of at most `chunk` points
+ * (into per-item partial grids), one workgroup per configuration for the sum of
+ * its partial grids, the FFT, the modes and the inverse FFT (all in LDS), and
+ * interpolation over the work items.  (A single launch with one workgroup per
+ * configuration measured 8.8 times slower on 256 configurations of 1e3 to 1e5
+ * points: the largest configurations ran on one CU each.)  The grid must fit: roughly
  * (16 or 24 bytes) x prod nf_a <= 156 KiB, e.g. kmax <= 19 in 2D for FP32 and
  * FP64.  Positions and gradients are the configurations' [n_b][d] rows
  * concatenated in order (row offsets from fresco_batch_offsets). */
@@ -405,8 +410,8 @@ int fresco_batch_loss_grad_async(fresco_batch_ctx* batch, const void* pos, doubl
 
 /* L-BFGS on the sum of the configurations' losses (the configurations are
  * independent, so its gradient is the concatenation of theirs) for n_iter
- * accepted iterations; one trial step = one persistent launch plus the optimiser
- * kernels, replayed from a captured HIP graph.  pos is updated in place; the
+ * accepted iterations; one trial step = the batch evaluation's three launches
+ * plus the optimiser kernels, replayed from one captured HIP graph.  pos is updated in place; the
  * history persists across calls (fresco_batch_reset_history clears it).
  * loss_out: total loss at the final positions.  Errors as fresco_step. */
 int fresco_batch_step(fresco_batch_ctx* batch, void* pos, const fresco_lbfgs_opts* opts,
@@ -415,10 +420,12 @@ int fresco_batch_step(fresco_batch_ctx* batch, void* pos, const fresco_lbfgs_opt
 /* Drop the batch's L-BFGS history. */
 int fresco_batch_reset_history(fresco_batch_ctx* batch);
 
-/* Autotuner: time `reps` evaluations at pos (grad: scratch [rows][d]) for each
- * candidate workgroup size (256, 512, 1024 threads) and keep the fastest for
- * all later calls; *threads_out (may be NULL) receives it.  Synchronises.
- * Errors: EINVAL, EHIP. */
+/* Autotuner: time `reps` evaluations at pos (grad: scratch [rows][d]) for every
+ * pair of work-item size (points per spreading / interpolation item; the
+ * spreading tile of a batch is the configuration's whole grid, so the item is
+ * the shape left to choose) and workgroup size (256, 512, 1024 threads), and
+ * keep the fastest pair for all later calls; *threads_out (may be NULL)
+ * receives the workgroup size.  Synchronises.  Errors: EINVAL, EHIP. */
 int fresco_batch_autotune(fresco_batch_ctx* batch, const void* pos, void* grad, int32_t reps,
                           int32_t* threads_out);
 
