@@ -540,6 +540,48 @@ int oracle_loss_grad_q(int d, long long N, const double* pos, const double* c, l
 }
 
 /*
+ * Gradient of the loss over arbitrary wave vectors with respect to real
+ * strengths (Methods, Eq. lossweightgradient; the UwU / UwNU variants optimise
+ * the weights of fixed points, e.g. the pixels of a uniform grid):
+ *   dL/dc_j = Re sum_k Cc_k exp(-i q_k.r_j) - (4 c_j / rho0) sum_k W_k S_k (S_k - S0_k),
+ *   Cc_k = 4 W_k (S_k - S0_k) rho_k / rho0.      grad_c [N].
+ */
+int oracle_grad_c_q(int d, long long N, const double* pos, const double* c, long long K,
+                    const double* q, const double* W, const double* S0, double* grad_c) {
+  if (d < 1 || d > 3 || N <= 0 || K < 0 || !pos || !c || !grad_c || (K && (!q || !W || !S0)))
+    return OR_EINVAL;
+  double rho0 = 0.0;
+  for (long long j = 0; j < N; ++j) rho0 += c[j] * c[j];
+  if (!(rho0 > 0.0)) return OR_EINVAL;
+  double* rho = (double*)malloc(sizeof(double) * 2 * (K ? K : 1));
+  if (!rho) return OR_ENOMEM;
+  int st = oracle_rho_q(d, N, pos, c, K, q, rho);
+  if (st) { free(rho); return st; }
+  double fsum = 0.0;
+  for (long long k = 0; k < K; ++k) {
+    const double S = (rho[2 * k] * rho[2 * k] + rho[2 * k + 1] * rho[2 * k + 1]) / rho0;
+    const double res = S - S0[k];
+    fsum += W[k] * S * res;
+    const double f = 4.0 * W[k] * res / rho0;
+    rho[2 * k] *= f; /* Cc_k */
+    rho[2 * k + 1] *= f;
+  }
+#pragma omp parallel for schedule(static)
+  for (long long j = 0; j < N; ++j) {
+    double acc = 0.0;
+    for (long long k = 0; k < K; ++k) {
+      double ph = 0.0;
+      for (int a = 0; a < d; ++a) ph += q[k * d + a] * pos[j * d + a];
+      /* Re[Cc (cos - i sin)] = Cc_re cos + Cc_im sin */
+      acc += rho[2 * k] * cos(ph) + rho[2 * k + 1] * sin(ph);
+    }
+    grad_c[j] = acc - 4.0 * c[j] / rho0 * fsum;
+  }
+  free(rho);
+  return OR_OK;
+}
+
+/*
  * Vector-Jacobian product of the structure factor (the derivative of S with
  * respect to a position, Methods, "Analytical gradients"):
  *   dS(k)/dr_ja = (2/N) Re[conj(rho(k)) i k_a exp(i k.r_j)]

@@ -79,6 +79,8 @@ def _load():
         lib.oracle_rho_q.restype = ctypes.c_int
         lib.oracle_loss_grad_q.argtypes = [ctypes.c_int, ll, dp, dp, ll, dp, dp, dp, dp, dp, dp]
         lib.oracle_loss_grad_q.restype = ctypes.c_int
+        lib.oracle_grad_c_q.argtypes = [ctypes.c_int, ll, dp, dp, ll, dp, dp, dp, dp]
+        lib.oracle_grad_c_q.restype = ctypes.c_int
         lib.oracle_rho_c.argtypes = [ctypes.c_int, ll, dp, dp, dp, ll, ip, dp]
         lib.oracle_rho_c.restype = ctypes.c_int
         lib.oracle_loss_grad_c.argtypes = [ctypes.c_int, ll, dp, dp, dp, ll, ip, dp, dp, dp, dp,
@@ -389,6 +391,25 @@ def loss_grad_q(pos, q, W, S0, c=None, want_grad: bool = True):
     if st:
         raise RuntimeError(f"oracle loss_grad_q failed ({st})")
     return {"S": S, "loss": float(loss[0]), "grad": grad}
+
+
+def grad_strengths_q(pos, q, W, S0, c) -> np.ndarray:
+    """dL/dc_j of the loss over arbitrary wave vectors (Methods, Eq.
+    lossweightgradient): the weights of fixed points, e.g. the pixels of a
+    uniform grid (the UwNU variant)."""
+    pos = _pos(pos)
+    N, d = pos.shape
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64).reshape(-1, d))
+    W = np.ascontiguousarray(W, dtype=np.float64).ravel()
+    S0 = np.ascontiguousarray(S0, dtype=np.float64).ravel()
+    cc = _strengths(c, N)
+    out = np.zeros(N)
+    st = _load().oracle_grad_c_q(d, N, _p(pos, ctypes.c_double), _p(cc, ctypes.c_double), len(q),
+                                 _p(q, ctypes.c_double), _p(W, ctypes.c_double),
+                                 _p(S0, ctypes.c_double), _p(out, ctypes.c_double))
+    if st:
+        raise RuntimeError(f"oracle grad_c_q failed ({st})")
+    return out
 
 
 def ewald_directions(d: int, e_inc, ns: int):

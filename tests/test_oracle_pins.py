@@ -820,3 +820,35 @@ def test_ewald_transmission_edges(d, ns):
     assert O.ewald_transmission(S_of_q, d, 0.52 * Kc, e, ns) < 1e-20
     assert O.ewald_transmission(S_of_q, d, 0.69 * Kc, e, ns) < 1e-20
     assert O.ewald_transmission(S_of_q, d, 0.75 * Kc, e, ns) > 1e-3
+
+
+def test_uwnu_weight_gradient_pins():
+    # weights of the pixels of a uniform grid constrained at arbitrary wave
+    # vectors (UwNU): the strength gradient satisfies the Euler identity
+    # sum_j c_j dL/dc_j = 0 (S is invariant under c -> lambda c), matches
+    # plain differences of the loss, and at lattice vectors of a periodic box
+    # equals the periodic oracle's strength gradient
+    rng = np.random.default_rng(116)
+    m, L = 9, 6.0
+    g = (np.arange(m) + 0.5) * L / m
+    pos = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    c = rng.normal(size=m * m)
+    q = rng.normal(size=(14, 2)) * 2.5
+    W = rng.uniform(0.5, 1.5, 14)
+    S0 = rng.uniform(0, 2, 14)
+    gc = O.grad_strengths_q(pos, q, W, S0, c)
+    assert abs(np.sum(c * gc)) <= 1e-12 * np.sum(np.abs(c * gc))
+    h = 1e-5
+    for j in (0, 17, 80):
+        cp, cm = c.copy(), c.copy()
+        cp[j] += h
+        cm[j] -= h
+        fd = (O.loss_grad_q(pos, q, W, S0, cp, want_grad=False)["loss"] -
+              O.loss_grad_q(pos, q, W, S0, cm, want_grad=False)["loss"]) / (2 * h)
+        assert gc[j] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    modes = _modes_ball(2, 2.0)
+    ql = 2 * np.pi * modes / L
+    Wl = rng.uniform(0.5, 1.5, len(modes))
+    S0l = rng.uniform(0, 2, len(modes))
+    ref = O.loss_grad_strengths(pos, c, L, modes, Wl, S0l)["grad_c"]
+    np.testing.assert_allclose(O.grad_strengths_q(pos, ql, Wl, S0l, c), ref, rtol=1e-10, atol=1e-12)
