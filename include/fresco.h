@@ -469,6 +469,17 @@ int fresco_q_structure_factor(fresco_q_ctx* ctx, const void* pos, const void* c,
 int fresco_q_loss_grad(fresco_q_ctx* ctx, const void* pos, const void* c, double* loss,
                        void* grad);
 
+/* Loss over the wave vectors set and its gradient with respect to the strengths
+ * c (device [n] of the dtype, required), for optimising the weights of fixed
+ * points -- e.g. the pixels of a uniform grid constrained at non-uniform k, the
+ * UwNU variant of the Methods (Eq. lossweightgradient):
+ *   dL/dc_j = Re sum_k Cc_k exp(-i q_k . r_j) - (4 c_j / rho0) sum_k W_k S_k (S_k - S0_k),
+ *   Cc_k = 4 W_k (S_k - S0_k) rho_k / rho0.
+ * grad_c: device [n], overwritten.  loss: HOST pointer; synchronises.
+ * Errors: EINVAL, EHIP. */
+int fresco_q_loss_grad_strengths(fresco_q_ctx* ctx, const void* pos, const void* c, double* loss,
+                                 void* grad_c);
+
 /* Forward-scattered transmission of the Ewald construction (main text, Eq.
  * ewald; SI, single scattering): for each incident wave vector k_i e_j (k: HOST
  * [n_k] magnitudes > 0; dirs: HOST [n_dir][dim] unit directions),

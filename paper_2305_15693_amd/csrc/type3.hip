@@ -46,7 +46,7 @@ struct fresco_q_ctx {
   double2* rho = nullptr;  // [max_q]
   double* S = nullptr;     // [max_q]
   double2* A = nullptr;    // [max_q] gradient coefficients
-  double* red = nullptr;   // [kRed + 2] strength partials, rho0, loss
+  double* red = nullptr;   // [kRed + 3] strength partials, rho0, loss, sum W S (S - S0)
   double* T = nullptr;     // [max incidences per batch]
   double* host = nullptr;  // pinned scratch
   long long host_cap = 0;
@@ -180,22 +180,66 @@ __global__ void rho0_final_kernel(double* red, int nb, double unit_n) {
 __global__ void nuwnu_coef_kernel(const double* __restrict__ S, const double2* __restrict__ rho,
                                   const double* __restrict__ W, const double* __restrict__ S0,
                                   long long K, double* __restrict__ red, double2* __restrict__ A) {
-  __shared__ double sh[1024];
+  __shared__ double sh[1024], sf[1024];
   const double r0 = red[kRed];
-  double l = 0.0;
+  double l = 0.0, fs = 0.0;
   for (long long k = threadIdx.x; k < K; k += blockDim.x) {
     const double res = S[k] - S0[k];
     l += W[k] * res * res;
+    fs += W[k] * S[k] * res;
     const double f = 4.0 * W[k] * res / r0;
     A[k] = make_double2(f * rho[k].x, -f * rho[k].y);
   }
   sh[threadIdx.x] = l;
+  sf[threadIdx.x] = fs;
   __syncthreads();
   for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    if ((int)threadIdx.x < off) {
+      sh[threadIdx.x] += sh[threadIdx.x + off];
+      sf[threadIdx.x] += sf[threadIdx.x + off];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) red[kRed + 1] = sh[0];
+  if (threadIdx.x == 0) {
+    red[kRed + 1] = sh[0];
+    red[kRed + 2] = sf[0];  // sum W S (S - S0), for the strength gradient
+  }
+}
+
+// dL/dc_j = Re sum_k conj(A_k) exp(-i q_k . r_j) - (4 c_j / rho0) sum_k W S (S - S0)
+// (Eq. lossweightgradient at arbitrary q; conj(A_k) = 4 W (S - S0) rho_k / rho0)
+template <class R>
+__global__ __launch_bounds__(256) void q_grad_c_kernel(int d, long long n,
+                                                       const R* __restrict__ pos,
+                                                       const R* __restrict__ c,
+                                                       const double* __restrict__ q,
+                                                       const double2* __restrict__ A, long long K,
+                                                       const double* __restrict__ red,
+                                                       R* __restrict__ gc) {
+  __shared__ double sq[256 * 3];
+  __shared__ double2 sa[256];
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double r[3] = {0.0, 0.0, 0.0};
+  if (j < n)
+    for (int a = 0; a < d; ++a) r[a] = (double)pos[j * d + a];
+  double acc = 0.0;
+  for (long long base = 0; base < K; base += 256) {
+    __syncthreads();
+    const long long k = base + threadIdx.x;
+    if (k < K) {
+      for (int a = 0; a < 3; ++a) sq[threadIdx.x * 3 + a] = a < d ? q[k * d + a] : 0.0;
+      sa[threadIdx.x] = A[k];
+    }
+    __syncthreads();
+    const int cnt = (K - base < 256) ? (int)(K - base) : 256;
+    for (int t = 0; t < cnt; ++t) {
+      const double ph = sq[t * 3] * r[0] + sq[t * 3 + 1] * r[1] + sq[t * 3 + 2] * r[2];
+      R s, co;
+      sincos_rev<R>(ph, &s, &co);
+      acc += sa[t].x * (double)co - sa[t].y * (double)s;
+    }
+  }
+  if (j < n) gc[j] = (R)(acc - 4.0 * (double)c[j] / red[kRed] * red[kRed + 2]);
 }
 
 template <class R>
@@ -408,7 +452,7 @@ int fresco_q_create(fresco_q_ctx** out, int32_t dim, int32_t dtype, int64_t n, i
   if (!st) st = qalloc(qc, &qc->rho, (size_t)max_q);
   if (!st) st = qalloc(qc, &qc->S, (size_t)max_q);
   if (!st) st = qalloc(qc, &qc->A, (size_t)max_q);
-  if (!st) st = qalloc(qc, &qc->red, (size_t)kRed + 2);
+  if (!st) st = qalloc(qc, &qc->red, (size_t)kRed + 3);
   if (!st) st = qalloc(qc, &qc->T, (size_t)max_q);
   if (st) {
     fresco_q_destroy(qc);
@@ -464,6 +508,30 @@ int fresco_q_loss_grad(fresco_q_ctx* qc, const void* pos, const void* c, double*
     nuwnu_grad_kernel<double><<<nb, 256, 0, qc->st>>>(qc->d, qc->n, (const double*)pos,
                                                      (const double*)c, qc->q, qc->A, qc->K,
                                                      (double*)grad);
+  QCHK(hipGetLastError());
+  QCHK(hipMemcpyAsync(qc->host, qc->red + kRed + 1, sizeof(double), hipMemcpyDeviceToHost, qc->st));
+  QCHK(hipStreamSynchronize(qc->st));
+  *loss = qc->host[0];
+  return FRESCO_OK;
+}
+
+int fresco_q_loss_grad_strengths(fresco_q_ctx* qc, const void* pos, const void* c, double* loss,
+                                 void* grad_c) {
+  if (!qc || !pos || !c || !loss || !grad_c) return FRESCO_EINVAL;
+  int st;
+  if ((st = enqueue_rho0(qc, c))) return st;
+  if ((st = enqueue_rho_q(qc, pos, c, qc->q, qc->K, qc->rho, qc->S))) return st;
+  if ((st = host_space(qc, 1))) return st;
+  nuwnu_coef_kernel<<<1, 1024, 0, qc->st>>>(qc->S, qc->rho, qc->W, qc->S0, qc->K, qc->red, qc->A);
+  const unsigned nb = (unsigned)((qc->n + 255) / 256);
+  if (qc->dtype == FRESCO_F32)
+    q_grad_c_kernel<float><<<nb, 256, 0, qc->st>>>(qc->d, qc->n, (const float*)pos,
+                                                  (const float*)c, qc->q, qc->A, qc->K, qc->red,
+                                                  (float*)grad_c);
+  else
+    q_grad_c_kernel<double><<<nb, 256, 0, qc->st>>>(qc->d, qc->n, (const double*)pos,
+                                                   (const double*)c, qc->q, qc->A, qc->K, qc->red,
+                                                   (double*)grad_c);
   QCHK(hipGetLastError());
   QCHK(hipMemcpyAsync(qc->host, qc->red + kRed + 1, sizeof(double), hipMemcpyDeviceToHost, qc->st));
   QCHK(hipStreamSynchronize(qc->st));

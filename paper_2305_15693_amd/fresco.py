@@ -146,6 +146,8 @@ def _load():
     lib.fresco_q_structure_factor.restype = i
     lib.fresco_q_loss_grad.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.fresco_q_loss_grad.restype = i
+    lib.fresco_q_loss_grad_strengths.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.fresco_q_loss_grad_strengths.restype = i
     lib.fresco_ewald_transmission.argtypes = [vp, vp, vp, ctypes.c_int32, dpp, ctypes.c_int32,
                                               dpp, ctypes.c_int32, dpp]
     lib.fresco_ewald_transmission.restype = i
@@ -634,6 +636,18 @@ class QContext:
         _check(_lib.fresco_q_loss_grad(self._h, self._pos(pos), self._c(c), ctypes.byref(loss),
                                        ctypes.c_void_p(grad.data_ptr())), "fresco_q_loss_grad")
         return float(loss.value), grad
+
+    def loss_grad_strengths(self, pos, c, grad_c=None):
+        """(loss, dL/dc [n]) for the weights c of the points (fresco_q_loss_grad_strengths)."""
+        torch = _torch()
+        if grad_c is None:
+            grad_c = torch.empty(self.n, dtype=self.torch_dtype, device=self.device)
+        loss = ctypes.c_double(0.0)
+        _check(_lib.fresco_q_loss_grad_strengths(self._h, self._pos(pos), self._c(c),
+                                                 ctypes.byref(loss),
+                                                 ctypes.c_void_p(grad_c.data_ptr())),
+               "fresco_q_loss_grad_strengths")
+        return float(loss.value), grad_c
 
     def ewald_transmission(self, pos, k, dirs, ns: int, c=None):
         """T[n_k][n_dir] of the Ewald construction (fresco_ewald_transmission)."""

@@ -102,3 +102,32 @@ def test_q_errors(gpu):
     with pytest.raises(F.FrescoError):
         qc.ewald_transmission(pos, [1.0], [[1.0, 1.0]], 8)  # not a unit direction
     qc.close()
+
+
+@pytest.mark.parametrize("dtype,bar", [("f64", 1e-11), ("f32", 1e-5)])
+def test_uwnu_weight_gradient(gpu, dtype, bar):
+    # signed weights on the pixels of a uniform 2D grid, constrained at wave
+    # vectors off any lattice (UwNU): loss and strength gradient against the oracle
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    rng = np.random.default_rng(530)
+    m, L = 96, 48.0
+    g = (np.arange(m) + 0.5) * L / m
+    pos = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    c = rng.normal(size=m * m)
+    q = rng.normal(size=(300, 2)) * 3.0
+    W = rng.uniform(0.5, 1.5, 300)
+    S0 = rng.uniform(0, 2, 300)
+    ndt = np.float32 if dtype == "f32" else np.float64
+    qc = F.QContext(2, m * m, 512, dtype=dtype, device=gpu)
+    qc.set(q, W, S0)
+    loss, gc = qc.loss_grad_strengths(torch.from_numpy(pos.astype(ndt)).to(gpu),
+                                      torch.from_numpy(c.astype(ndt)).to(gpu))
+    qc.close()
+    p64, c64 = pos.astype(ndt).astype(np.float64), c.astype(ndt).astype(np.float64)
+    ref = O.loss_grad_q(p64, q, W, S0, c64, want_grad=False)["loss"]
+    gref = O.grad_strengths_q(p64, q, W, S0, c64)
+    print(f"UwNU {dtype}: loss {abs(loss - ref) / ref:.2e} grad_c {rel(gc.cpu().numpy(), gref):.2e}",
+          flush=True)
+    assert abs(loss - ref) <= bar * ref
+    assert rel(gc.cpu().numpy(), gref) < bar
