@@ -59,24 +59,36 @@ ALU_PEAK_DATASHEET = {"f32": 157.3, "f64": 78.6}
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 INFINITY_CACHE_MB = 256.0
 DOM_REPS = 30  # launches of the dominant spread / interp kernel per timing bracket
-KERNEL_POLY_FMAS = 9  # FP32 kernel values: degree-9 polynomials per cell and axis
+def kernel_eval_flops(width):
+    """Flops of the FP32 kernel values along one axis at one width: degree-9 per-cell
+    polynomials in x, with mirrored cells (j and width - 1 - j) sharing one even and
+    one odd part in y = x^2 (two 4-FMA chains and two combining FMAs per pair, four
+    FMAs for the middle cell of an odd width) and y itself (one product)."""
+    fmas = 10 * (width // 2) + 4 * (width % 2)
+    return 2 * fmas + 1
 
 
 def stage_flops(cfg, info):
     """Algorithmic flops per point of the spreading and interpolation kernels: the
-    kernel values along each axis (degree-9 polynomials; with their derivatives
-    for the interpolation, at width w + 1) and the tensor-product contraction.
-      spread:  d w polynomials + the w + w^2 (+ w^3) footprint products
-      interp:  2 d wi polynomials + 2 wi^d row FMAs + 3 wi^(d-1) (+ 4 wi in 3D)
-    (FMA = 2 flops)."""
+    kernel values along each axis (with their derivatives for the interpolation, at
+    width wi = w + 1; the derivative shares y = x^2 with the kernel) and the
+    tensor-product contraction:
+      spread:  d kernel evaluations + the w + w^2 (+ w^3) footprint products
+      interp:  d (kernel + derivative) evaluations + 2 wi^d row FMAs
+               + 3 wi^(d-1) (+ 4 wi in 3D)
+    (FMA = 2 flops).  In FP64 the kernel values are exp and sqrt per cell, not
+    polynomials; their flops are not counted (a lower bound)."""
     d, N = cfg["d"], cfg["N"]
     w = info["width"]
     wi = w + 1
-    sp = 2 * KERNEL_POLY_FMAS * d * w + sum(w ** k for k in range(1, d + 1))
+    poly = cfg.get("dtype", "f32") == "f32"
+    ev_s = kernel_eval_flops(w) if poly else 0
+    ev_i = 2 * kernel_eval_flops(wi) - 1 if poly else 0
+    sp = d * ev_s + sum(w ** k for k in range(1, d + 1))
     if d == 2:
-        ip = 2 * (2 * KERNEL_POLY_FMAS * d * wi + 2 * wi ** 2 + 3 * wi)
+        ip = d * ev_i + 2 * (2 * wi ** 2 + 3 * wi)
     else:
-        ip = 2 * (2 * KERNEL_POLY_FMAS * d * wi + 2 * wi ** 3 + 3 * wi ** 2 + 4 * wi)
+        ip = d * ev_i + 2 * (2 * wi ** 3 + 3 * wi ** 2 + 4 * wi)
     return {"spread": sp * N, "interp": ip * N, "per_point": {"spread": sp, "interp": ip}}
 
 

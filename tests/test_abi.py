@@ -183,20 +183,41 @@ def test_failed_creation_releases_everything():
             assert h.value is None
 
 
+def _generated_eval_ops(width, fn):
+    """(FMAs, products) of one kernel-value function in the generated FP32 header."""
+    from paper_2305_15693_amd import build as B
+    path = os.path.join(B.OBJDIR, "kernel_tables.h")
+    if not os.path.exists(path):
+        B._generate_tables()
+    text = open(path).read()
+    body = text[text.index("struct Poly<%d> {" % width):]
+    body = body[body.index(" void %s(float x" % fn):]
+    body = body[:body.index("\n  }\n")]
+    return body.count("fmaf("), body.count(" * ")
+
+
 def test_bench_algorithmic_flops():
-    # the per-point flops the ALU roofline divides by: kernel polynomials
-    # (degree 9 per cell and axis) and the tensor-product contraction
+    # the per-point flops the ALU roofline divides by: the kernel values as the
+    # generated evaluators compute them (operations counted in the generated
+    # header) and the tensor-product contraction
     import sys
     sys.path.insert(0, ROOT)
     import bench
     from paper_2305_15693_amd import inputs as I
+    ops = {}
+    for w, fn in ((7, "es"), (8, "ch"), (8, "dch")):
+        fm, mul = _generated_eval_ops(w, fn)
+        ops[fn] = 2 * fm + mul
+        assert bench.kernel_eval_flops(w) == ops[fn], (w, fn, fm, mul)
     cfg = I.WORKLOADS["2d_n1e6_stealthy300_f32"]
     f = bench.stage_flops(cfg, {"width": 7})
     wi = 8
-    assert f["per_point"]["interp"] == 2 * (2 * 9 * 2 * wi + 2 * wi * wi + 3 * wi) == 880
-    assert f["per_point"]["spread"] == 2 * 9 * 2 * 7 + 7 + 49
+    # the derivative shares y = x^2 with the kernel value
+    both = ops["ch"] + ops["dch"] - 1
+    assert f["per_point"]["interp"] == 2 * both + 2 * (2 * wi * wi + 3 * wi) == 626
+    assert f["per_point"]["spread"] == 2 * ops["es"] + 7 + 49
     cfg3 = I.WORKLOADS["3d_n1e7_stealthy60_f32"]
     f3 = bench.stage_flops(cfg3, {"width": 7})
-    assert f3["per_point"]["interp"] == 2 * (2 * 9 * 3 * wi + 2 * wi ** 3 + 3 * wi ** 2 + 4 * wi)
+    assert f3["per_point"]["interp"] == 3 * both + 2 * (2 * wi ** 3 + 3 * wi ** 2 + 4 * wi)
     assert f3["interp"] == 10_000_000 * f3["per_point"]["interp"]
     assert abs(bench.ALU_PEAK_TFLOPS - 78.6432) < 1e-3
