@@ -744,11 +744,13 @@ int batch_lbfgs_setup(fresco_batch_ctx* c, int m) {
   if ((st = balloc(c, &v.p, n))) return st;
   if ((st = balloc(c, &v.xt, n))) return st;
   if ((st = balloc(c, &v.gt, n))) return st;
-  if ((st = balloc(c, &v.S, (size_t)n * m))) return st;
-  if ((st = balloc(c, &v.Y, (size_t)n * m))) return st;
+  const long long ld = lbfgs_slot_stride(n);
+  if ((st = balloc(c, &v.S, (size_t)ld * m))) return st;
+  if ((st = balloc(c, &v.Y, (size_t)ld * m))) return st;
   const int nb = lbfgs_blocks(n);
   v.nb = nb;
   v.n = n;
+  v.ld = ld;
   v.m = m;
   if ((st = balloc(c, &v.part0, (4 * (size_t)kLbfgsMaxM + 1) * nb))) return st;
   if ((st = balloc(c, &v.part1, (size_t)nb))) return st;

@@ -89,7 +89,13 @@ struct State {
   bool have_perm0 = false;
   int lb_m = 0;
   LbfgsOpts lb_opts{};
-  hipGraphExec_t lb_graph = nullptr;
+  hipGraphExec_t lb_graph = nullptr;        // one trial step
+  hipGraphExec_t lb_graph_chunk = nullptr;  // kLbfgsReplayChunk trial steps
+  void drop_lb_graphs() {
+    if (lb_graph) (void)hipGraphExecDestroy(lb_graph);
+    if (lb_graph_chunk) (void)hipGraphExecDestroy(lb_graph_chunk);
+    lb_graph = lb_graph_chunk = nullptr;
+  }
   // point strengths (fresco_set_strengths): a copy in the caller's order, the
   // optimiser's internal order, S normalised by rho0 = sum c^2
   bool has_str = false;
@@ -1039,11 +1045,13 @@ int lbfgs_alloc(fresco_ctx* c, int m) {
   if ((st = dalloc_t(c, &v.p, n))) return st;
   if ((st = dalloc_t(c, &v.xt, n))) return st;
   if ((st = dalloc_t(c, &v.gt, n))) return st;
-  if ((st = dalloc_t(c, &v.S, (size_t)n * m))) return st;
-  if ((st = dalloc_t(c, &v.Y, (size_t)n * m))) return st;
+  const long long ld = lbfgs_slot_stride(n);
+  if ((st = dalloc_t(c, &v.S, (size_t)ld * m))) return st;
+  if ((st = dalloc_t(c, &v.Y, (size_t)ld * m))) return st;
   const int nb = lbfgs_blocks(n);
   v.nb = nb;
   v.n = n;
+  v.ld = ld;
   v.m = m;
   if ((st = dalloc_t(c, &v.part0, (4 * (size_t)kLbfgsMaxM + 1) * nb))) return st;
   if ((st = dalloc_t(c, &v.part1, (size_t)nb))) return st;
@@ -1064,10 +1072,7 @@ template <class R>
 int lbfgs_setup(fresco_ctx* c, int m) {
   State<R>* S = (State<R>*)c->state;
   if (S->lst && S->lb_m == m) return FRESCO_OK;
-  if (S->lb_graph) {
-    (void)hipGraphExecDestroy(S->lb_graph);
-    S->lb_graph = nullptr;
-  }
+  S->drop_lb_graphs();
   S->have_perm0 = false;
   HIPCHK(hipStreamSynchronize(c->st));
   lbfgs_free<R>(c);
@@ -1127,10 +1132,7 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   lo.c1 = o->c1;
   lo.shrink = o->shrink;
   lo.gtol = o->gtol;
-  if (std::memcmp(&lo, &S->lb_opts, sizeof(lo)) != 0 && S->lb_graph) {
-    (void)hipGraphExecDestroy(S->lb_graph);
-    S->lb_graph = nullptr;
-  }
+  if (std::memcmp(&lo, &S->lb_opts, sizeof(lo)) != 0) S->drop_lb_graphs();
   S->lb_opts = lo;
   const long long N = g.N;
   if (!S->have_perm0) {
@@ -1151,21 +1153,36 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   if ((st = lbfgs_trial<R>(c))) return st;
   launch_lbfgs_set_mode(S->lst, 0, -1, c->st);
   const bool graphs = c->use_graphs && !c->timing_mask && c->st != nullptr;
-  if (graphs && !S->lb_graph) {
+  // two graphs: one trial step, and a full chunk of them (one launch per chunk,
+  // so that consecutive steps are not separated by a graph launch)
+  auto capture = [&](int steps, hipGraphExec_t* out) -> int {
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
-    st = lbfgs_trial<R>(c);
+    int s2 = FRESCO_OK;
+    for (int r = 0; r < steps && !s2; ++r) s2 = lbfgs_trial<R>(c);
     hipError_t e = hipStreamEndCapture(c->st, &graph);
-    if (st) {
+    if (s2) {
       if (graph) (void)hipGraphDestroy(graph);
-      return st;
+      return s2;
     }
     HIPCHK(e);
-    e = hipGraphInstantiate(&S->lb_graph, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     HIPCHK(e);
+    return FRESCO_OK;
+  };
+  if (graphs && !S->lb_graph_chunk) {
+    S->drop_lb_graphs();
+    if ((st = capture(1, &S->lb_graph)) || (st = capture(kLbfgsReplayChunk, &S->lb_graph_chunk))) {
+      S->drop_lb_graphs();
+      return st;
+    }
   }
   auto replay = [&](int count) -> int {
+    if (graphs && count == kLbfgsReplayChunk) {
+      HIPCHK(hipGraphLaunch(S->lb_graph_chunk, c->st));
+      return FRESCO_OK;
+    }
     for (int r = 0; r < count; ++r) {
       if (graphs) {
         HIPCHK(hipGraphLaunch(S->lb_graph, c->st));
@@ -1415,10 +1432,7 @@ void drop_graphs(fresco_ctx* c) {
   State<R>* S = (State<R>*)c->state;
   for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
   c->graphs.clear();
-  if (S->lb_graph) {
-    (void)hipGraphExecDestroy(S->lb_graph);
-    S->lb_graph = nullptr;
-  }
+  S->drop_lb_graphs();
 }
 
 template <class R>
@@ -1525,14 +1539,14 @@ int fresco_destroy(fresco_ctx* c) {
   if (c->state) {
     if (c->dtype == FRESCO_F32) {
       State<float>* S = (State<float>*)c->state;
-      if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
+      S->drop_lb_graphs();
       if (S->lst_host) (void)hipHostFree(S->lst_host);
       for (hipEvent_t e : S->lb_ev)
         if (e) (void)hipEventDestroy(e);
       delete S;
     } else {
       State<double>* S = (State<double>*)c->state;
-      if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
+      S->drop_lb_graphs();
       if (S->lst_host) (void)hipHostFree(S->lst_host);
       for (hipEvent_t e : S->lb_ev)
         if (e) (void)hipEventDestroy(e);
@@ -1765,13 +1779,9 @@ int fresco_attach_pair(fresco_ctx* c, fresco_pair_ctx* pc, double weight) {
   for (auto& e : c->graphs) (void)hipGraphExecDestroy(e.exec);
   c->graphs.clear();
   if (c->dtype == FRESCO_F32) {
-    State<float>* S = (State<float>*)c->state;
-    if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
-    S->lb_graph = nullptr;
+    ((State<float>*)c->state)->drop_lb_graphs();
   } else {
-    State<double>* S = (State<double>*)c->state;
-    if (S->lb_graph) (void)hipGraphExecDestroy(S->lb_graph);
-    S->lb_graph = nullptr;
+    ((State<double>*)c->state)->drop_lb_graphs();
   }
   c->pair = pc;
   c->pair_w = pc ? weight : 0.0;

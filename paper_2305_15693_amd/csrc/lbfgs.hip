@@ -46,25 +46,24 @@ constexpr int kWaves = kThreads / 64;
 #define GRID_LOOP(i, n) \
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
 
-// Reduce `cnt` per-thread values across the block (fixed order) and write them to
-// part[c * nb + blockIdx.x].
-template <int CNT>
-__device__ __forceinline__ void block_partials(double* v, int cnt, double* part, int nb,
-                                               double* sh /* [CNT][kWaves] */) {
+// Reduce CNT per-thread values across the block (fixed order) and write value c
+// to part[row(c) * nb + blockIdx.x] (not written when row(c) < 0).
+template <int CNT, class Row>
+__device__ __forceinline__ void block_partials(const double* v, double* part, int nb,
+                                               double* sh /* [CNT][kWaves] */, Row row) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < CNT; ++c) {
-    if (c < cnt) {
-      double x = v[c];
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-      if (lane == 0) sh[c * kWaves + wave] = x;
-    }
+    double x = v[c];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) sh[c * kWaves + wave] = x;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+  for (int c = threadIdx.x; c < CNT; c += blockDim.x) {
     double t = 0.0;
     for (int w = 0; w < kWaves; ++w) t += sh[c * kWaves + w];
-    part[(long long)c * nb + blockIdx.x] = t;
+    const int r = row(c);
+    if (r >= 0) part[(long long)r * nb + blockIdx.x] = t;
   }
 }
 
@@ -192,81 +191,159 @@ __global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part,
     reinterpret_cast<uint32_t*>(Sg)[i] = reinterpret_cast<const uint32_t*>(&sh)[i];
 }
 
-// Partial slots: [0, m) s_j.y_new, [m, 2m) y_j.y_new, [2m, 3m) s_j.g, [3m, 4m) y_j.g,
-// 4m g.g (slot j indexes the ring; the new pair's own entries sit at its slot).
-// MM = history length m (compile time, so the accumulators stay in registers).
-// Every load of an element is issued before its stores and products (the ring
-// slot of the new pair is read before it is overwritten and its value replaced
-// by the new pair's); ALL: every slot holds a pair (the steady state), so no
-// load waits behind a branch.
-template <class R, int MM, bool ACC, bool ALL>
-__device__ __forceinline__ void pass_a_loop(const LbfgsVec<R>& v, unsigned live, int ns, R alpha,
-                                            double (&acc_v)[4 * MM + 1]) {
-  R* Sn = v.S + (long long)ns * v.n;
-  R* Yn = v.Y + (long long)ns * v.n;
-  GRID_LOOP(i, v.n) {
-    R sj[MM], yj[MM];
+// ------------------------------------------------------- packed access
+// The vector passes move U consecutive elements per thread and step with one
+// 16-byte access per array (U = 4 in FP32, 2 in FP64): fewer, wider requests
+// than one element per lane.  Every array is a separate allocation and the
+// history slots are v.ld elements apart (a multiple of 4), so the packs are
+// aligned; the launcher falls back to single elements (vec = 0) otherwise.
+template <class R, int U>
+struct alignas(sizeof(R) * U) Pack {
+  R e[U];
+};
+template <class R, int U>
+__device__ __forceinline__ Pack<R, U> ldp(const R* p, long long i) {
+  return *reinterpret_cast<const Pack<R, U>*>(p + i);
+}
+template <class R, int U>
+__device__ __forceinline__ void stp(R* p, long long i, const Pack<R, U>& x) {
+  *reinterpret_cast<Pack<R, U>*>(p + i) = x;
+}
+// elements per pack: B bytes for history length MM <= 8, half that beyond,
+// whose loaded slots would not fit in the registers otherwise
+template <class R, int MM, int B>
+constexpr int pack_u() {
+  constexpr int b = MM <= 8 ? B : B / 2;
+  return b / (int)sizeof(R) > 0 ? b / (int)sizeof(R) : 1;
+}
+// Pass A holds 4m + 5 FP64 accumulators besides the loaded slots: it reads single
+// elements (packs took more registers and measured no faster), within 128
+// registers up to m = 8 (four waves per SIMD, so that 1024 blocks of four waves
+// are resident at once); passes B and C take 16-byte packs.
+constexpr int kPackBytesA = 4;
+constexpr int kPackBytesBC = 16;
+
+// Pass A on elements [i, i + U).  The old pairs are read by age (age a sits in
+// slot (head - a) mod m; pointers pS[a], pY[a]), every load issued before the
+// first product; MASK: only ages below k hold pairs, the others read their
+// slot's first pack (index i & im[a] = 0: one cache line for the whole grid, no
+// branch between the loads) and are replaced by zeros.  acc: [0, NA) s_a.y_new, [NA, 2 NA) y_a.y_new,
+// [2 NA, 3 NA) s_a.g, [3 NA, 4 NA) y_a.g, then s.y, y.y, s.g, y.g of the new pair
+// and g.g.
+template <class R, int U, int NA, bool ACC, bool MASK>
+__device__ __forceinline__ void pass_a_elems(const LbfgsVec<R>& v, const R* const* pS,
+                                             const R* const* pY, const long long* im, R* Sn,
+                                             R* Yn, int k, R alpha, long long i, double* acc) {
+  constexpr int NB = NA > 0 ? NA : 1;
+  Pack<R, U> sa[NB], ya[NB];
 #pragma unroll
-    for (int j = 0; j < MM; ++j) {
-      const bool lj = ALL || ((live >> j) & 1u);
-      sj[j] = lj ? v.S[(long long)j * v.n + i] : R(0);
-      yj[j] = lj ? v.Y[(long long)j * v.n + i] : R(0);
+  for (int a = 0; a < NA; ++a) {
+    const long long ia = MASK ? (i & im[a]) : i;
+    sa[a] = ldp<R, U>(pS[a], ia);
+    ya[a] = ldp<R, U>(pY[a], ia);
+  }
+  const Pack<R, U> gn = ldp<R, U>(v.gt, i);
+  const Pack<R, U> g0 = ldp<R, U>(v.g, i);
+  Pack<R, U> sy, yy;
+  if (ACC) {
+    const Pack<R, U> pp = ldp<R, U>(v.p, i);
+    const Pack<R, U> xt = ldp<R, U>(v.xt, i);
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      sy.e[e] = alpha * pp.e[e];
+      yy.e[e] = gn.e[e] - g0.e[e];
     }
-    const R gn = v.gt[i];
-    const R g0 = v.g[i];
-    R yy = R(0);
+    stp<R, U>(Sn, i, sy);
+    stp<R, U>(Yn, i, yy);
+    stp<R, U>(v.x, i, xt);
+  }
+  stp<R, U>(v.g, i, gn);
+#pragma unroll
+  for (int e = 0; e < U; ++e) {
+    const double gd = (double)gn.e[e];
+    const double yd = ACC ? (double)yy.e[e] : 0.0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const double sv = (MASK && a >= k) ? 0.0 : (double)sa[a].e[e];
+      const double yv = (MASK && a >= k) ? 0.0 : (double)ya[a].e[e];
+      if (ACC) {
+        acc[a] += sv * yd;
+        acc[NA + a] += yv * yd;
+      }
+      acc[2 * NA + a] += sv * gd;
+      acc[3 * NA + a] += yv * gd;
+    }
     if (ACC) {
-      const R sy = alpha * v.p[i];
-      const R xt = v.xt[i];
-      yy = gn - g0;
-      Sn[i] = sy;
-      Yn[i] = yy;
-      v.x[i] = xt;
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        sj[j] = (j == ns) ? sy : sj[j];
-        yj[j] = (j == ns) ? yy : yj[j];
-      }
+      const double sd = (double)sy.e[e];
+      acc[4 * NA] += sd * yd;
+      acc[4 * NA + 1] += yd * yd;
+      acc[4 * NA + 2] += sd * gd;
+      acc[4 * NA + 3] += yd * gd;
     }
-    v.g[i] = gn;
-#pragma unroll
-    for (int j = 0; j < MM; ++j) {
-      if (ALL || ((live >> j) & 1u)) {
-        if (ACC) {
-          acc_v[j] += (double)sj[j] * (double)yy;
-          acc_v[MM + j] += (double)yj[j] * (double)yy;
-        }
-        acc_v[2 * MM + j] += (double)sj[j] * (double)gn;
-        acc_v[3 * MM + j] += (double)yj[j] * (double)gn;
-      }
-    }
-    acc_v[4 * MM] += (double)gn * (double)gn;
+    acc[4 * NA + 4] += gd * gd;
   }
 }
 
-template <class R, int MM>
-__global__ void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
-  __shared__ double sh[(4 * MM + 1) * kWaves];
-  const int step = lb_decided_step(S, o);
-  if (step == LB_ACCEPT || step == LB_INIT) {
-    const bool acc = (step == LB_ACCEPT);
-    const int ns = (S->head + 1) % MM;  // slot of the new pair
-    const R alpha = (R)S->alpha;
-    // slots holding pairs after this step (the new slot included when accepting)
-    unsigned live = 0;
-    {
-      const int k = S->k;
-      for (int t = 0; t < k; ++t) live |= 1u << ((S->head - t + MM) % MM);
-      if (acc) live |= 1u << ns;
-    }
-    double acc_v[4 * MM + 1];
+// Pass A of one decision: packs of U elements strided over the grid (vec), then
+// the elements past the last whole pack one at a time; the products go out as
+// block partials in slot order: [0, m) s_j.y_new, [m, 2m) y_j.y_new,
+// [2m, 3m) s_j.g, [3m, 4m) y_j.g, 4m g.g (slot j indexes the ring; the new pair's
+// products sit at its slot ns).  Accepting, the oldest pair is dropped when the
+// ring is full: its slot ns is never read.
+template <class R, int MM, int NA, bool ACC, bool MASK>
+__device__ __forceinline__ void pass_a_run(const LbfgsVec<R>& v, int head, int k, int ns,
+                                           R alpha, bool vec, double* sh) {
+  constexpr int NB = NA > 0 ? NA : 1;
+  const R* pS[NB];
+  const R* pY[NB];
+  long long im[NB];
 #pragma unroll
-    for (int c = 0; c < 4 * MM + 1; ++c) acc_v[c] = 0.0;
-    constexpr unsigned kAll = (MM >= 32) ? 0xffffffffu : ((1u << MM) - 1u);
-    if (acc && live == kAll) pass_a_loop<R, MM, true, true>(v, live, ns, alpha, acc_v);
-    else if (acc) pass_a_loop<R, MM, true, false>(v, live, ns, alpha, acc_v);
-    else pass_a_loop<R, MM, false, false>(v, live, ns, alpha, acc_v);
-    block_partials<4 * MM + 1>(acc_v, 4 * MM + 1, v.part0, v.nb, sh);
+  for (int a = 0; a < NA; ++a) {
+    const long long slot = (head - a + MM) % MM;
+    pS[a] = v.S + slot * v.ld;
+    pY[a] = v.Y + slot * v.ld;
+    im[a] = (a < k) ? ~0LL : 0LL;
+  }
+  R* Sn = v.S + (long long)ns * v.ld;
+  R* Yn = v.Y + (long long)ns * v.ld;
+  double acc[4 * NA + 5];
+#pragma unroll
+  for (int c = 0; c < 4 * NA + 5; ++c) acc[c] = 0.0;
+  constexpr int U = pack_u<R, MM, kPackBytesA>();
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gs = (long long)gridDim.x * blockDim.x;
+  const long long nq = vec ? v.n / U : 0;
+  for (long long q = gid; q < nq; q += gs)
+    pass_a_elems<R, U, NA, ACC, MASK>(v, pS, pY, im, Sn, Yn, k, alpha, q * U, acc);
+  for (long long i = nq * U + gid; i < v.n; i += gs)
+    pass_a_elems<R, 1, NA, ACC, MASK>(v, pS, pY, im, Sn, Yn, k, alpha, i, acc);
+  // rows of the partials: kind * m + slot for the old pairs by age, the new
+  // pair's four products at slot ns (zeros when not accepting; not written when
+  // an old pair's age already covers ns), g.g at 4m; every row is written once
+  // (ages without a pair hold zeros)
+  block_partials<4 * NA + 5>(acc, v.part0, v.nb, sh, [&](int c) {
+    if (c < 4 * NA) return (c / NA) * MM + (head - c % NA + MM) % MM;
+    if (c < 4 * NA + 4) return NA == MM ? -1 : (c - 4 * NA) * MM + ns;
+    return 4 * MM;
+  });
+}
+
+// MM = history length m (compile time, so the accumulators stay in registers).
+template <class R, int MM>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MM <= 8 ? 4 : 1))) void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o, int vec) {
+  __shared__ double sh[(4 * MM + 5) * kWaves];
+  const int step = lb_decided_step(S, o);
+  if (step != LB_ACCEPT && step != LB_INIT) return;  // uniform: before any barrier
+  const int head = S->head, k = S->k;
+  const int ns = (head + 1) % MM;  // slot of the new pair
+  const R alpha = (R)S->alpha;
+  if (step == LB_ACCEPT) {
+    // the pairs kept are the k newest, at most m - 1 of them
+    if (k >= MM - 1) pass_a_run<R, MM, MM - 1, true, false>(v, head, k, ns, alpha, vec, sh);
+    else pass_a_run<R, MM, MM - 1, true, true>(v, head, k, ns, alpha, vec, sh);
+  } else {
+    if (k == MM) pass_a_run<R, MM, MM, false, false>(v, head, k, ns, alpha, vec, sh);
+    else pass_a_run<R, MM, MM - 1, false, true>(v, head, k, ns, alpha, vec, sh);
   }
 }
 
@@ -401,34 +478,62 @@ __device__ __forceinline__ void lb_small_direction(LbfgsState* S, const LbfgsOpt
 }
 
 // ---------------------------------------------------------------- pass B
-// p = -(cg g + sum over live slots of cS S_j + cY Y_j); returns max |p| of the
-// thread's elements.  ALL: every slot holds a pair (no branch between loads).
-template <class R, int MM, bool ALL>
-__device__ __forceinline__ double pass_b_loop(const LbfgsVec<R>& v, unsigned live, R cg,
-                                              const R (&cS)[MM], const R (&cY)[MM]) {
-  double pm = 0.0;
-  GRID_LOOP(j, v.n) {
-    R r = cg * v.g[j];
+// p = -(cg g + sum over slots of cS_j S_j + cY_j Y_j) on elements [i, i + U), the
+// slots in ring order; MASK: slots without a pair (live bit clear) read their
+// first pack (one cache line, no branch between the loads) and are replaced by
+// zeros.  Returns max |p| over the elements.
+template <class R, int U, int MM, bool MASK>
+__device__ __forceinline__ double pass_b_elems(const LbfgsVec<R>& v, unsigned live, R cg,
+                                               const R (&cS)[MM], const R (&cY)[MM],
+                                               long long i) {
+  Pack<R, U> sj[MM], yj[MM];
 #pragma unroll
-    for (int i = 0; i < MM; ++i) {
-      if (ALL || ((live >> i) & 1u)) {
-        r += cS[i] * v.S[(long long)i * v.n + j];
-        r += cY[i] * v.Y[(long long)i * v.n + j];
-      }
+  for (int j = 0; j < MM; ++j) {
+    const long long ij = (MASK && !((live >> j) & 1u)) ? 0LL : i;
+    sj[j] = ldp<R, U>(v.S + (long long)j * v.ld, ij);
+    yj[j] = ldp<R, U>(v.Y + (long long)j * v.ld, ij);
+  }
+  const Pack<R, U> g = ldp<R, U>(v.g, i);
+  Pack<R, U> out;
+  double pm = 0.0;
+#pragma unroll
+  for (int e = 0; e < U; ++e) {
+    R r = cg * g.e[e];
+#pragma unroll
+    for (int j = 0; j < MM; ++j) {
+      const bool on = !MASK || ((live >> j) & 1u);
+      r += cS[j] * (on ? sj[j].e[e] : R(0));
+      r += cY[j] * (on ? yj[j].e[e] : R(0));
     }
-    v.p[j] = -r;
+    out.e[e] = -r;
     pm = fmax(pm, fabs((double)r));
   }
+  stp<R, U>(v.p, i, out);
+  return pm;
+}
+
+template <class R, int MM, bool MASK>
+__device__ __forceinline__ double pass_b_run(const LbfgsVec<R>& v, unsigned live, R cg,
+                                             const R (&cS)[MM], const R (&cY)[MM], bool vec) {
+  constexpr int U = pack_u<R, MM, kPackBytesBC>();
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gs = (long long)gridDim.x * blockDim.x;
+  const long long nq = vec ? v.n / U : 0;
+  double pm = 0.0;
+  for (long long q = gid; q < nq; q += gs)
+    pm = fmax(pm, pass_b_elems<R, U, MM, MASK>(v, live, cg, cS, cY, q * U));
+  for (long long i = nq * U + gid; i < v.n; i += gs)
+    pm = fmax(pm, pass_b_elems<R, 1, MM, MASK>(v, live, cg, cS, cY, i));
   return pm;
 }
 
 template <class R, int MM>
-__global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
+__global__ __launch_bounds__(kThreads) void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S, int vec) {
   __shared__ double sh[kWaves];
   const int step = S->step;
   if (step != LB_ACCEPT && step != LB_INIT && step != LB_RESTART) return;
   const int k = S->k;
-  // coefficients by slot; slots without a pair have coefficient 0 and are skipped
+  // coefficients by slot; slots without a pair have coefficient 0 (and zeros)
   R cS[MM], cY[MM];
   unsigned live = 0;
 #pragma unroll
@@ -438,13 +543,10 @@ __global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
   }
   for (int t = 0; t < k; ++t) live |= 1u << ((S->head - t + MM) % MM);
   const R cg = (R)S->coefG;
-  double pm = 0.0;
   constexpr unsigned kAll = (MM >= 32) ? 0xffffffffu : ((1u << MM) - 1u);
-  if (live == kAll) {
-    pm = pass_b_loop<R, MM, true>(v, live, cg, cS, cY);
-  } else {
-    pm = pass_b_loop<R, MM, false>(v, live, cg, cS, cY);
-  }
+  const double pm0 = (live == kAll) ? pass_b_run<R, MM, false>(v, live, cg, cS, cY, vec != 0)
+                                    : pass_b_run<R, MM, true>(v, live, cg, cS, cY, vec != 0);
+  double pm = pm0;
   for (int off = 32; off > 0; off >>= 1) pm = fmax(pm, __shfl_down(pm, off, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pm;
   __syncthreads();
@@ -456,44 +558,25 @@ __global__ void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S) {
 }
 
 // ---------------------------------------------------------------- pass C
-// xt = x + alpha p from element j of the thread on (stride: the grid), four
-// elements in flight at once
-template <class R>
-__device__ __forceinline__ void trial_point(const R* __restrict__ x, const R* __restrict__ p,
-                                            R* __restrict__ xt, long long n, R alpha,
-                                            long long j) {
-  const long long st = (long long)gridDim.x * blockDim.x;
-  for (; j + 3 * st < n; j += 4 * st) {
-    R a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = x[j + u * st];
-      b[u] = p[j + u * st];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) xt[j + u * st] = a[u] + alpha * b[u];
-  }
-  for (; j < n; j += st) xt[j] = x[j] + alpha * p[j];
-}
-
 // step length of a new direction (every block reduces the pass B maxima), or
-// the one shrunk by the decision; then the trial point
+// the one shrunk by the decision; then the trial point xt = x + alpha p (packs
+// of U elements strided over the grid, then the elements past the last whole
+// pack; the thread's first pack is loaded before the step length is known, so
+// that its latency overlaps the reduction)
 template <class R>
-__global__ void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
+__global__ __launch_bounds__(kThreads) void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o, int vec) {
   __shared__ double sh[kWaves];
   __shared__ double alpha_s;
   const int step = S->step;
   if (step == LB_IDLE) return;
-  // the thread's first four elements of x and p, loaded before the step length
-  // is known (their latency overlaps the reduction of the block maxima)
-  const long long st = (long long)gridDim.x * blockDim.x;
-  const long long j0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  R xa[4], pa[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const long long j = j0 + u * st;
-    xa[u] = (j < v.n) ? v.x[j] : R(0);
-    pa[u] = (j < v.n) ? v.p[j] : R(0);
+  constexpr int U = pack_u<R, 1, kPackBytesBC>();
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gs = (long long)gridDim.x * blockDim.x;
+  const long long nq = vec ? v.n / U : 0;
+  Pack<R, U> xa, pa;
+  if (gid < nq) {
+    xa = ldp<R, U>(v.x, gid * U);
+    pa = ldp<R, U>(v.p, gid * U);
   }
   if (step == LB_REJECT) {
     if (threadIdx.x == 0) alpha_s = S->alpha;
@@ -522,12 +605,20 @@ __global__ void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o) {
   }
   __syncthreads();
   const R alpha = (R)alpha_s;
+  if (gid < nq) {
+    Pack<R, U> t;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const long long j = j0 + u * st;
-    if (j < v.n) v.xt[j] = xa[u] + alpha * pa[u];
+    for (int e = 0; e < U; ++e) t.e[e] = xa.e[e] + alpha * pa.e[e];
+    stp<R, U>(v.xt, gid * U, t);
   }
-  trial_point<R>(v.x, v.p, v.xt, v.n, alpha, j0 + 4 * st);
+  for (long long q = gid + gs; q < nq; q += gs) {
+    const Pack<R, U> x = ldp<R, U>(v.x, q * U), p = ldp<R, U>(v.p, q * U);
+    Pack<R, U> t;
+#pragma unroll
+    for (int e = 0; e < U; ++e) t.e[e] = x.e[e] + alpha * p.e[e];
+    stp<R, U>(v.xt, q * U, t);
+  }
+  for (long long i = nq * U + gid; i < v.n; i += gs) v.xt[i] = v.x[i] + alpha * v.p[i];
 }
 
 // set the mode read by the next decision (host-driven transitions)
@@ -547,8 +638,13 @@ __global__ void lb_set_mode_kernel(LbfgsState* S, int mode, int target) {
 template <class R>
 void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
                          hipStream_t st) {
-#define LB_A(MM) lb_pass_a_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, o)
-#define LB_B(MM) lb_pass_b_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S)
+  // packed access needs every array and history slot aligned to a pack
+  constexpr size_t kPackBytes = sizeof(R) * pack_u<R, 1, kPackBytesBC>();
+  auto al = [&](const void* q) { return ((uintptr_t)q % kPackBytes) == 0; };
+  const int vec = al(v.x) && al(v.g) && al(v.p) && al(v.xt) && al(v.gt) && al(v.S) && al(v.Y) &&
+                  (v.ld % pack_u<R, 1, kPackBytesBC>()) == 0;
+#define LB_A(MM) lb_pass_a_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, o, vec)
+#define LB_B(MM) lb_pass_b_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, vec)
 #define LB_SWITCH(CALL)                                                        \
   switch (v.m) {                                                               \
     case 1: CALL(1); break;   case 2: CALL(2); break;   case 3: CALL(3); break;   \
@@ -564,7 +660,7 @@ void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o
 #undef LB_SWITCH
 #undef LB_B
 #undef LB_A
-  lb_pass_c_kernel<R><<<v.nb, kThreads, 0, st>>>(v, S, o);
+  lb_pass_c_kernel<R><<<v.nb, kThreads, 0, st>>>(v, S, o, vec);
 }
 
 void launch_lbfgs_set_mode(LbfgsState* S, int mode, int target, hipStream_t st) {
