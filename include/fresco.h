@@ -98,6 +98,11 @@ typedef struct fresco_plan_info {
                            more than 16384 tiles), or -1: global atomic counts */
   int32_t bin_levels;   /* two-level sorts: 2 when a coarse pass over groups of
                            ranges runs first (very many ranges), else 1 */
+  int32_t slack;        /* cells by which the padded tiles extend past their tile on
+                           each side (2 in 2D, 0 in 3D; FRESCO_SLACK overrides):
+                           fresco_step keeps the tile order of a binned trial step
+                           for the next ones while the step cap keeps their points
+                           within it (0: every trial step is binned) */
 } fresco_plan_info;
 
 /* Create a context for one problem.  Chooses the fine grid, kernel width and
@@ -229,11 +234,18 @@ typedef struct fresco_lbfgs_opts {
  * PLACE (the only mutated argument).  The history of (s, y) pairs and the
  * internal point order persist in the context across calls, so a run can be
  * continued by calling again with the returned positions; fresco_reset_history
- * starts afresh.  The iterations run as replays of one captured HIP graph (on a
- * non-default stream), enqueued in chunks of 8 with two chunks in flight: the
- * host reads the optimiser's state after each chunk while the next one runs, so
- * after a stop (n_iter reached, gtol reached, line-search failure) at most two
- * chunks of replays run idle -- they change nothing and are not counted.
+ * starts afresh.  The trial steps run as replays of captured HIP graphs (on a
+ * non-default stream: one graph of 8 trial steps, one of a single step for the
+ * rest), enqueued in chunks of 8 with two chunks in flight: the host reads the
+ * optimiser's state after each chunk while the next one runs, so after a stop
+ * (n_iter reached, gtol reached, line-search failure) at most two chunks of
+ * replays run idle -- they change nothing and are not counted.  Within a chunk
+ * of 8, a trial step may keep the tile order of the previous binned one (only
+ * its per-point records are recomputed) while r + 2 step caps, r the steps since
+ * that binning, stay below the plan's slack (fresco_plan_info.slack, in grid
+ * cells): every trial point is within max_step per coordinate of the current
+ * point, which moves by at most max_step per accepted step, so its footprint
+ * stays inside the padded tiles of that binning.
  * loss_out (host, may be NULL): loss at the final positions; n_eval_out (host,
  * may be NULL): loss/gradient evaluations the optimiser used (the first one at
  * the starting point included).  Synchronises the stream.  The first call, and
@@ -241,7 +253,9 @@ typedef struct fresco_lbfgs_opts {
  * those of another m are freed).
  * Errors: EINVAL (null ctx/pos/opts, n_iter < 0, options out of range), EHIP,
  * ENOMEM, ELINESEARCH (no decrease even along the steepest descent direction;
- * pos holds the last accepted point). */
+ * pos holds the last accepted point), ENOTSUP (a trial point left the slack of
+ * its kept tile order, which the step cap excludes; the result is not to be
+ * used). */
 int fresco_step(fresco_ctx* ctx, void* pos, const fresco_lbfgs_opts* opts, int32_t n_iter,
                 double* loss_out, int32_t* n_eval_out);
 

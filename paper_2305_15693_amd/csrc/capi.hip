@@ -89,6 +89,7 @@ struct State {
   bool have_perm0 = false;
   int lb_m = 0;
   LbfgsOpts lb_opts{};
+  bool cached_eval = false;  // the last binning kept the previous tile order
   hipGraphExec_t lb_graph = nullptr;        // one trial step
   hipGraphExec_t lb_graph_chunk = nullptr;  // kLbfgsReplayChunk trial steps
   void drop_lb_graphs() {
@@ -380,7 +381,8 @@ int build_fold_tables(fresco_ctx* c, int a, int** off_d, int2** ent_d, int* nent
   std::vector<std::vector<int2>> lists(nf);
   for (int t = 0; t < nt; ++t)
     for (int l = 0; l < E; ++l) {
-      const int y = (int)(((long long)t * T + l) % nf);
+      // the padded tile starts g.slack cells before the tile
+      const int y = (int)((((long long)t * T - g.slack + l) % nf + nf) % nf);
       lists[y].push_back(make_int2(t, l));
     }
   std::vector<int> off(nf + 1, 0);
@@ -531,6 +533,7 @@ int create_state(fresco_ctx* c) {
   if ((st = dalloc_t(c, &rec, N))) return st;
   bb.rec = rec;
   if ((st = dalloc_t(c, &bb.perm, N))) return st;
+  if (g.slack > 0 && bp.mode == BIN_TILES && (st = dalloc_t(c, &bb.home, N))) return st;
   if ((st = dalloc_t(c, &bb.flag, 1))) return st;
   if ((st = dalloc_t(c, &S->flag_out, 1))) return st;
   HIPCHK(hipMemset(bb.flag, 0, sizeof(int)));
@@ -810,14 +813,26 @@ int build_weights(const Geom& g, const double* s0, const double* w, double k_cut
 }
 
 // ---------------------------------------------------------------- stages
+// optimiser: an optimiser trial step, whose binning keeps each point's tile
+// (b.home) for the trial steps after it; cached: keep the order of the last
+// binning and only recompute the records (optimiser trial steps that stay within
+// the slack of the binned positions)
 template <class R>
-int run_bin_spread_rows(fresco_ctx* c, const R* pos) {
+int run_bin_spread_rows(fresco_ctx* c, const R* pos, bool optimiser = false,
+                        bool cached = false) {
   State<R>* S = (State<R>*)c->state;
   const Geom& g = c->g;
   hipStream_t st = c->st;
+  S->cached_eval = cached;
   {
     StageTimer t(c, FRESCO_STAGE_BIN);
-    launch_bin(g, S->bp, pos, sizeof(R) == 8, S->bb, st);
+    if (cached) {
+      launch_bin_refresh(g, pos, sizeof(R) == 8, S->bb, &S->lst->drift, st);
+    } else {
+      BinBuffers b = S->bb;
+      if (!optimiser) b.home = nullptr;  // scattered writes that no one reads
+      launch_bin(g, S->bp, pos, sizeof(R) == 8, b, st);
+    }
   }
   {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
@@ -945,7 +960,8 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
     cs.perm = S->bb.perm;
     cs.cmax = S->cmax;
     cs.val = (mode == COL_FUSED) ? S->val_eval : nullptr;
-    for (int r = 0; r < t.reps; ++r) launch_interp<R>(g, S->bp, S->bb, S->v, grad, cs, st);
+    const Geom gi = interp_geom(g, S->cached_eval);
+    for (int r = 0; r < t.reps; ++r) launch_interp<R>(gi, S->bp, S->bb, S->v, grad, cs, st);
   }
   // the pair-correlation backward has no loss partials here, and the point
   // flag was handed over by the structure-factor pass before it
@@ -1092,15 +1108,16 @@ int lbfgs_reset_state(fresco_ctx* c) {
   return FRESCO_OK;
 }
 
-// one trial step: evaluation at xt, then the optimiser update
+// one trial step: evaluation at xt, then the optimiser update; cached: the
+// binning order of the previous trial step is kept
 template <class R>
-int lbfgs_trial(fresco_ctx* c) {
+int lbfgs_trial(fresco_ctx* c, bool cached = false) {
   State<R>* S = (State<R>*)c->state;
   int st;
   // the optimiser's positions are in its internal order, and so are the strengths
   S->str_eval = S->has_str ? S->cint : nullptr;
   S->val_eval = nullptr;
-  if ((st = run_bin_spread_rows<R>(c, S->lv.xt))) return st;
+  if ((st = run_bin_spread_rows<R>(c, S->lv.xt, true, cached))) return st;
   if ((st = run_modes_to_grad<R>(c, COL_FUSED, S->lv.xt, nullptr, nullptr, S->lv.gt,
                                  &S->lst->f_trial)))
     return st;
@@ -1153,13 +1170,25 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   if ((st = lbfgs_trial<R>(c))) return st;
   launch_lbfgs_set_mode(S->lst, 0, -1, c->st);
   const bool graphs = c->use_graphs && !c->timing_mask && c->st != nullptr;
+  // Cached tile order inside a chunk: every trial point lies within max_step
+  // (per coordinate) of the current point, which moves by at most max_step per
+  // accepted step, so trial r after a binned trial 0 is within (r + 2) max_step
+  // of it; while that is at most the slack (less a margin for rounding) in grid
+  // cells, its footprint starts stay inside the padded tiles of that binning.
+  int bin_every = 1;  // trials per binning in a chunk
+  if (g.slack > 0 && S->bb.home && S->bp.mode == BIN_TILES && lo.max_step > 0.0) {
+    double cells = 0.0;  // grid cells per max_step, largest over the axes
+    for (int a = 0; a < g.d; ++a) cells = std::max(cells, lo.max_step * g.ufac[a]);
+    const double r = std::floor((g.slack - 0.25) / cells) - 2.0;  // last cached trial
+    if (r >= 1.0) bin_every = (int)std::min<double>(r + 1.0, kLbfgsReplayChunk);
+  }
   // two graphs: one trial step, and a full chunk of them (one launch per chunk,
   // so that consecutive steps are not separated by a graph launch)
   auto capture = [&](int steps, hipGraphExec_t* out) -> int {
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
     int s2 = FRESCO_OK;
-    for (int r = 0; r < steps && !s2; ++r) s2 = lbfgs_trial<R>(c);
+    for (int r = 0; r < steps && !s2; ++r) s2 = lbfgs_trial<R>(c, r % bin_every != 0);
     hipError_t e = hipStreamEndCapture(c->st, &graph);
     if (s2) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -1187,7 +1216,9 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
       if (graphs) {
         HIPCHK(hipGraphLaunch(S->lb_graph, c->st));
       } else {
-        const int s2 = lbfgs_trial<R>(c);
+        // eager launches follow the graphs' binning pattern (same arithmetic)
+        const bool cached = count == kLbfgsReplayChunk && r % bin_every != 0;
+        const int s2 = lbfgs_trial<R>(c, cached);
         if (s2) return s2;
       }
     }
@@ -1201,6 +1232,8 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   const LbfgsState& h = *S->lst_host;
   if (loss_out) *loss_out = h.f_cur;
   if (n_eval_out) *n_eval_out = h.nevals;
+  // a trial point beyond the slack of its binning (excluded by the step cap)
+  if (h.drift) return FRESCO_ENOTSUP;
   if (h.fail) return FRESCO_ELINESEARCH;
   return FRESCO_OK;
 }
@@ -1600,7 +1633,9 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
   g.ncube = 1;
   // spreading tile edge: measured over 32..64 in 2D (40: 1024 tiles on the 1250^2
   // grid, the fastest spread, fold and evaluation) and 12..20 in 3D (FP32)
-  const int tdef = (d == 2) ? 40 : (p->dtype == FRESCO_F32 ? 16 : 8);
+  int tdef = (d == 2) ? 40 : (p->dtype == FRESCO_F32 ? 16 : 8);
+  // FRESCO_TILE overrides the tile edge (4 to 64; checks and tuning)
+  if (const char* et = std::getenv("FRESCO_TILE")) tdef = std::max(4, std::min(64, std::atoi(et)));
   for (int a = 0; a < 3; ++a) {
     if (a < d) {
       g.L[a] = p->box[a];
@@ -1616,8 +1651,6 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
       g.T[a] = tdef < g.nf[a] ? tdef : g.nf[a];
       g.tdiv[a] = make_fastdiv((uint32_t)g.T[a]);
       g.nt[a] = (g.nf[a] + g.T[a] - 1) / g.T[a];
-      g.E[a] = g.T[a] + g.w - 1;
-      g.Ei[a] = g.T[a] + g.wi;
       g.nbins *= g.nt[a];
       g.ngrid *= g.nf[a];
       g.ncube *= 2LL * g.M[a] + 1;
@@ -1632,6 +1665,26 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
       g.nt[a] = 1;
       g.E[a] = 1;
       g.Ei[a] = 1;
+    }
+  }
+  // Slack of the padded spreading tiles: footprint starts may lie this many
+  // cells outside their tile, so that the optimiser's trial steps can keep the
+  // tile order of an earlier binning (2D: 2 cells, +18% padded cells at the
+  // 40-cell tiles; the interpolation's field tiles cover the slack only in those
+  // cached evaluations; 3D: none).  FRESCO_SLACK overrides it
+  // in 2D (0 to 8).  Only where the padded tiles stay well inside one grid
+  // period.
+  {
+    int slack = (d == 2) ? 2 : 0;
+    if (const char* es = std::getenv("FRESCO_SLACK"))
+      if (d == 2) slack = std::max(0, std::min(8, std::atoi(es)));
+    for (int a = 0; a < d; ++a)
+      if (g.nf[a] < g.T[a] + 2 * slack + g.wi + 1) slack = 0;
+    g.slack = slack;
+    g.islack = 0;
+    for (int a = 0; a < d; ++a) {
+      g.E[a] = g.T[a] + 2 * slack + g.w - 1;
+      g.Ei[a] = g.T[a] + g.wi;
     }
   }
   // 32-bit index ranges of the passes
@@ -1696,6 +1749,7 @@ int fresco_plan_info_get(const fresco_ctx* c, fresco_plan_info* o) {
                                                : ((const State<double>*)c->state)->bp;
   o->bin_ranges = bp.mode == BIN_RANGES ? (int32_t)bp.nkeys : bp.mode == BIN_TILES ? 0 : -1;
   o->bin_levels = bp.mode == BIN_RANGES ? bp.levels : 1;
+  o->slack = c->g.slack;
   return FRESCO_OK;
 }
 

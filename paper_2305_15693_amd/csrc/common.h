@@ -81,8 +81,12 @@ struct Geom {
   double beta_i;  // ES shape parameter of the interpolation kernel
   int T[3];       // tile size per dimension (1 beyond d)
   int nt[3];      // tiles per dimension (1 beyond d)
-  int E[3];       // padded spreading tile extent T + w - 1 (1 beyond d)
-  int Ei[3];      // interpolation field tile extent T + wi (1 beyond d)
+  int slack;      // cells a footprint start may lie outside its tile (cached
+                  // tile order of the optimiser's trial steps; 0: none)
+  int islack;     // of those, the cells the interpolation's field tiles cover
+                  // on each side (slack for cached evaluations, else 0)
+  int E[3];       // padded spreading tile extent T + 2 slack + w - 1 (1 beyond d)
+  int Ei[3];      // interpolation field tile extent T + 2 islack + wi (1 beyond d)
   double ufac[3];   // nf / L: position -> grid coordinate
   FastDiv tdiv[3];  // division by T
   long long nbins;
@@ -95,7 +99,8 @@ struct Geom {
 // the local cell.
 //   t[a]  = tau_a = l0_a - u_a + w/2 in [0, 1), u_a = grid coordinate of the point,
 //           l0_a = ceil(u_a - w/2) = first grid index of its footprint;
-//   cell  = local index of l0 inside its tile, 8 bits per dimension.
+//   cell  = local index of l0 inside its tile plus the slack (the padded tile
+//           starts slack cells before the tile), 8 bits per dimension.
 template <class R>
 struct alignas(4 * sizeof(R)) Rec {
   R t[3];
@@ -160,6 +165,8 @@ struct BinBuffers {
   int* tidx0 = nullptr;
   void* rec = nullptr;        // Rec<R>[N], sorted
   int* perm = nullptr;        // sorted position -> caller index (tpos index for BIN_RANGES)
+  uint32_t* home = nullptr;   // tile of each sorted position (BIN_TILES with slack:
+                              // the cached order of the optimiser's trial steps)
   int* flag = nullptr;        // bit 0: a position is not finite
 };
 
@@ -190,10 +197,24 @@ constexpr int kMaxSpreadLds = 160 * 1024;
 // Launchers exported by the translation units (all enqueue on `st`).
 void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, BinBuffers& b,
                 hipStream_t st);
+// Records of the sorted positions from pos with the order of the last launch_bin
+// kept (b.perm, b.start, b.home; BIN_TILES with slack): every point stays in the
+// tile it was binned into.  A finite point whose footprint start left that tile
+// by more than the slack is clamped and flagged in *drift.
+void launch_bin_refresh(const Geom& g, const void* pos, bool f64, const BinBuffers& b,
+                        int* drift, hipStream_t st);
 template <class R>
 size_t spread_lds_bytes(const Geom& g, bool str);
 template <class R>
 size_t interp_lds_bytes(const Geom& g);
+// the geometry an interpolation launch uses: field tiles covering the slack for
+// a cached evaluation, the tiles alone otherwise
+inline Geom interp_geom(const Geom& g, bool cached) {
+  Geom h = g;
+  h.islack = cached ? g.slack : 0;
+  for (int a = 0; a < g.d; ++a) h.Ei[a] = g.T[a] + 2 * h.islack + g.wi;
+  return h;
+}
 template <class R>
 hipError_t spread_prepare(const Geom& g);
 template <class R>

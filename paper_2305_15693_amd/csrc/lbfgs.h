@@ -36,6 +36,7 @@ struct LbfgsState {
   int converged;  // gradient RMS below gtol (or zero)
   int restarted;  // last restart not yet followed by a stored pair
   int resets;     // history resets
+  int drift;      // a trial point left the slack of its cached tile order
   double f_cur;   // loss at the current point
   double f_trial; // loss at the trial point (written by the evaluation)
   double gtp;     // g . p at the current point

@@ -631,6 +631,7 @@ __global__ void lb_set_mode_kernel(LbfgsState* S, int mode, int target) {
       S->nevals = 0;
       S->fail = 0;
       S->converged = 0;
+      S->drift = 0;
     }
   }
 }

@@ -109,7 +109,7 @@ __device__ __forceinline__ PointBin bin_point_d(const Geom& g, const R* r, bool*
     if (li < 0) li += g.nf[a];
     if (li >= g.nf[a]) li -= g.nf[a];
     uint32_t ta = fdiv((uint32_t)li, g.tdiv[a]);
-    uint32_t loc = (uint32_t)li - ta * (uint32_t)g.T[a];
+    uint32_t loc = (uint32_t)li - ta * (uint32_t)g.T[a] + (uint32_t)g.slack;
     tile[a] = ta;
     pb.cell |= loc << (8 * a);
   }
@@ -217,7 +217,7 @@ __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, uint32_t b
                                    const uint32_t* __restrict__ kr,
                                    const uint32_t* __restrict__ H,
                                    const long long* __restrict__ start, Rec<R>* __restrict__ rec,
-                                   int* __restrict__ perm) {
+                                   int* __restrict__ perm, uint32_t* __restrict__ home) {
   uint32_t blk;
   const long long q = xcd_point_block(blockIdx.x, bpc, &blk);
   const long long i = q * 256 + threadIdx.x;
@@ -234,6 +234,76 @@ __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, uint32_t b
   o.cell = pb.cell;
   rec[dst] = o;
   perm[dst] = (int)i;
+  if (home) home[dst] = tile;
+}
+
+// Cached tile order: slot j keeps point perm[j] in tile home[j]; its record is
+// recomputed from the current position as in bin_point_d, the footprint start
+// taken relative to the home tile (periodically, within one grid period of it)
+// and stored with the slack offset.
+template <class R, int D>
+__global__ void bin_refresh_kernel(Geom g, const R* __restrict__ pos, const int* __restrict__ perm,
+                                   const uint32_t* __restrict__ home, Rec<R>* __restrict__ rec,
+                                   int* __restrict__ flag, int* __restrict__ drift) {
+  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= g.N) return;
+  const long long i = perm[j];
+  uint32_t tile = home[j];
+  R x[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = pos[i * D + a];
+  bool bad = false, off = false;
+  Rec<R> o;
+  o.t[0] = o.t[1] = o.t[2] = R(0);
+  o.cell = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const uint32_t ta = tile % (uint32_t)g.nt[a];
+    tile /= (uint32_t)g.nt[a];
+    const double nf = (double)g.nf[a];
+    double u = (double)x[a] * g.ufac[a];
+    if (!isfinite(u)) {
+      bad = true;
+      u = 0.0;
+    }
+    if (!(u >= 0.0 && u < nf)) {
+      u = fmod(u, nf);
+      if (u < 0.0) u += nf;
+      if (u >= nf) u = 0.0;
+    }
+    const double l0 = ceil(u - 0.5 * g.w);
+    o.t[a] = (R)(l0 - u + 0.5 * g.w);
+    int li = (int)l0;
+    if (li < 0) li += g.nf[a];
+    if (li >= g.nf[a]) li -= g.nf[a];
+    int rel = li - (int)ta * g.T[a];
+    if (rel < -g.slack) rel += g.nf[a];
+    if (rel >= g.T[a] + g.slack) rel -= g.nf[a];
+    if (rel < -g.slack || rel >= g.T[a] + g.slack) {
+      off = true;
+      rel = rel < -g.slack ? -g.slack : g.T[a] + g.slack - 1;
+    }
+    o.cell |= (uint32_t)(rel + g.slack) << (8 * a);
+  }
+  rec[j] = o;
+  if (bad) atomicOr(flag, 1);
+  else if (off) atomicOr(drift, 1);
+}
+
+void launch_bin_refresh(const Geom& g, const void* pos, bool f64, const BinBuffers& b,
+                        int* drift, hipStream_t st) {
+  const unsigned nb = (unsigned)((g.N + 255) / 256);
+#define REFRESH(R, D)                                                                       \
+  bin_refresh_kernel<R, D><<<nb, 256, 0, st>>>(g, (const R*)pos, b.perm, b.home,           \
+                                               (Rec<R>*)b.rec, b.flag, drift)
+  if (f64) {
+    if (g.d == 2) REFRESH(double, 2);
+    else REFRESH(double, 3);
+  } else {
+    if (g.d == 2) REFRESH(float, 2);
+    else REFRESH(float, 3);
+  }
+#undef REFRESH
 }
 
 // Slot of point i in the range order (first level of BIN_RANGES); 256-thread
@@ -590,11 +660,11 @@ void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, Bin
       if (f64)
         bin_scatter_kernel<double><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
             g, (const double*)pos, bpc, bp.nblk, b.kr, b.H, b.start, (Rec<double>*)b.rec,
-            b.perm);
+            b.perm, b.home);
       else
         bin_scatter_kernel<float><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
             g, (const float*)pos, bpc, bp.nblk, b.kr, b.H, b.start, (Rec<float>*)b.rec,
-            b.perm);
+            b.perm, b.home);
     } else {
       scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, bp.nkeys, b.kstart);
       if (f64) range_finish<double>(g, bp, (const double*)src, b, st);
@@ -687,7 +757,9 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
   __shared__ uint32_t smax[16];
   uint32_t cov;
   {
-    const int Ta = (D == 3) ? g.T[1] : g.T[0], Tb = (D == 3) ? g.T[2] : g.T[1];
+    // footprint starts span the tile and the slack on both sides
+    const int Ta = ((D == 3) ? g.T[1] : g.T[0]) + 2 * g.slack;
+    const int Tb = ((D == 3) ? g.T[2] : g.T[1]) + 2 * g.slack;
     uint32_t* cnt = acc32;  // Ta Tb <= ncell words, before the accumulator is cleared
     // Tb (Ta + W - 1) >= Tb Ta words after the accumulator (spread_lds_bytes)
     uint32_t* cov_tmp =
@@ -842,7 +914,9 @@ __global__ void fold_kernel(Geom g, FoldTables ft, const R* __restrict__ tiles,
 
 // ---------------------------------------------------------- interpolation
 // Field tile origin is one cell before the spreading tile (width w + 1), extent
-// T + w + 1 per axis (g.Ei).  In FP32 the LDS rows are padded to a multiple of
+// T + w + 1 per axis (g.Ei); with the cached tile order of the optimiser's trial
+// steps, whose footprints may start g.slack cells outside their tile, the field
+// tile grows by g.islack = g.slack on each side (Ei = T + 2 slack + w + 1).  In FP32 the LDS rows are padded to a multiple of
 // four floats (zeros) and a point reads each row of its footprint as kRowQ
 // aligned 16-byte words from the aligned cell at or below its first column; the
 // x weights are shifted by the alignment offset once per point (zeros outside
@@ -888,6 +962,15 @@ constexpr int interp_row_unroll() {
   return (sizeof(R) == 4 && W <= 8) ? W + 1 : 2;
 }
 
+// LDS bytes of the field tile (the outlier list follows it)
+template <class R>
+__host__ __device__ inline size_t interp_tile_bytes(const Geom& g) {
+  if (sizeof(R) == 4 && g.d == 2)  // four shifted copies
+    return (size_t)4 * interp_copy_stride(g.Ei[0], g.wi) * g.Ei[1] * sizeof(R);
+  // rows padded in FP32, plus the cells past the end
+  const int rs = sizeof(R) == 4 ? (g.Ei[0] + 3) / 4 * 4 : g.Ei[0];
+  return ((size_t)rs * g.Ei[1] * (g.d == 3 ? g.Ei[2] : 1) + kInterpTail) * sizeof(R);
+}
 template <class R, int D, int W>
 __global__ __launch_bounds__(512)
 __attribute__((amdgpu_waves_per_eu(interp_min_waves<R, D, W>())))
@@ -911,9 +994,9 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   if (e == s) return;
   int t[3];
   tile_coords(g, bin, t);
-  const int o0 = t[0] * g.T[0] - 1 + g.nf[0];
-  const int o1 = t[1] * g.T[1] - 1 + g.nf[1];
-  const int o2 = (D == 3) ? t[2] * g.T[2] - 1 + g.nf[2] : 0;
+  const int o0 = t[0] * g.T[0] - 1 - g.islack + g.nf[0];
+  const int o1 = t[1] * g.T[1] - 1 - g.islack + g.nf[1];
+  const int o2 = (D == 3) ? t[2] * g.T[2] - 1 - g.islack + g.nf[2] : 0;
   // the field over the tile, KB loads in flight per thread before the LDS
   // stores; row padding and the kInterpTail cells past the end (read by the last
   // row's words) are zero.  Cell c = (c2 E1 + c1) E0s + c0: one division per
@@ -1001,7 +1084,7 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
     for (int a = 0; a < D; ++a) {
       const int k = (p.t[a] >= R(0.5)) ? 1 : 0;
       const R ti = k ? p.t[a] - R(0.5) : p.t[a] + R(0.5);
-      l[a] = cl[a] - k + 1;
+      l[a] = cl[a] - (g.slack - g.islack) - k + 1;
       if (a == 0) interp_weights<R, WI>(ti, beta, icb, f0, d0);
       else if (a == 1) interp_weights<R, WI>(ti, beta, icb, f1, d1);
       else interp_weights<R, WI>(ti, beta, icb, f2, d2);
@@ -1136,24 +1219,22 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
 template <class R>
 size_t spread_lds_bytes(const Geom& g, bool str) {
   size_t ncell = (size_t)g.E[0] * g.E[1] * (g.d == 3 ? g.E[2] : 1);
-  const size_t Ta = (g.d == 3) ? g.T[1] : g.T[0], Tb = (g.d == 3) ? g.T[2] : g.T[1];
+  const size_t Ta = ((g.d == 3) ? g.T[1] : g.T[0]) + 2 * g.slack;
+  const size_t Tb = ((g.d == 3) ? g.T[2] : g.T[1]) + 2 * g.slack;
   return (ncell + 2) * (sizeof(R) == 4 && !str ? 4 : 8) + Tb * (Ta + g.w - 1) * 4;
 }
 template <class R>
 size_t interp_lds_bytes(const Geom& g) {
-  if (sizeof(R) == 4 && g.d == 2)  // four shifted copies
-    return (size_t)4 * interp_copy_stride(g.Ei[0], g.wi) * g.Ei[1] * sizeof(R);
-  // rows padded in FP32, plus the cells past the end
-  return ((size_t)interp_row_stride(g, sizeof(R) == 4) * g.Ei[1] * (g.d == 3 ? g.Ei[2] : 1) +
-          kInterpTail) *
-         sizeof(R);
+  return interp_tile_bytes<R>(g);
 }
 
 // one-time kernel attributes (dynamic LDS above the default limit); returns
 // the first failure
 template <class R>
 hipError_t spread_prepare(const Geom& g) {
-  const int sl = (int)spread_lds_bytes<R>(g, false), il = (int)interp_lds_bytes<R>(g);
+  const int sl = (int)spread_lds_bytes<R>(g, false);
+  const int il = (int)std::max(interp_lds_bytes<R>(interp_geom(g, false)),
+                               interp_lds_bytes<R>(interp_geom(g, true)));
   const int slc = (int)spread_lds_bytes<R>(g, true);
   hipError_t e = hipSuccess;
   auto lds = [&e](const void* f, int bytes) {

@@ -67,6 +67,7 @@ class PlanInfo(ctypes.Structure):
         ("col_split", ctypes.c_int32),
         ("bin_ranges", ctypes.c_int32),
         ("bin_levels", ctypes.c_int32),
+        ("slack", ctypes.c_int32),
     ]
 
 
@@ -303,7 +304,7 @@ class Context:
                     tile=list(info.tile)[:d], nbins=info.nbins,
                     n_constrained=info.n_constrained, device_bytes=info.device_bytes,
                     col_split=info.col_split, bin_ranges=info.bin_ranges,
-                    bin_levels=info.bin_levels)
+                    bin_levels=info.bin_levels, slack=info.slack)
 
     def default_max_step(self) -> float:
         """0.1 of the mean interparticle spacing L / N^(1/d) (smallest side)."""

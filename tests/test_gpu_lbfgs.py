@@ -72,18 +72,56 @@ def test_lbfgs_fp32_decreases_like_oracle(gpu):
     ctx.close()
 
 
-def test_lbfgs_graph_eager_resume_bitwise(gpu):
-    """Graph replays and eager launches give the same trajectory bit for bit, and
-    two calls of 6 iterations continue exactly like one call of 12."""
+def _f32_pair(gpu, streams, slack=None):
+    import os
     import torch
     from paper_2305_15693_amd import fresco as F
     d, N, L, M = 2, 30000, 173.2, 30
     pos0 = I.positions(N, d, L, np.float32, seed=71)
     w, s0 = I.stealthy_target(d, M, float(M))
-    a = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-6, dtype="f32", device=gpu,
-                  stream=torch.cuda.Stream(device=gpu))
-    b = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-6, dtype="f32", device=gpu,
-                  stream=torch.cuda.default_stream(gpu))
+    ctxs = []
+    for st in streams:
+        if slack is not None:
+            os.environ["FRESCO_SLACK"] = str(slack)
+        try:
+            ctxs.append(F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-6, dtype="f32",
+                                  device=gpu, stream=st))
+        finally:
+            os.environ.pop("FRESCO_SLACK", None)
+    return ctxs, pos0
+
+
+def test_lbfgs_graph_eager_bitwise(gpu):
+    """Graph replays and eager launches give the same trajectory bit for bit (the
+    eager launches keep the cached tile order on the same trial steps)."""
+    import torch
+    (a, b), pos0 = _f32_pair(gpu, [torch.cuda.Stream(device=gpu), torch.cuda.default_stream(gpu)])
+    assert a.plan_info()["slack"] == 2
+    pa = torch.from_numpy(pos0.copy()).to(gpu)
+    pb = torch.from_numpy(pos0.copy()).to(gpu)
+    la, na = a.step(pa, 12)
+    lb, nb = b.step(pb, 12)
+    torch.cuda.synchronize()
+    assert la == lb and na == nb
+    assert torch.equal(pa, pb)
+    # the loss of the last accepted trial step (its tile order possibly kept from
+    # an earlier binning) against a plain evaluation at the returned positions
+    lc, _ = a.loss_grad(pa)
+    print(f"loss {la:.9e}, plain evaluation {lc:.9e}", flush=True)
+    assert abs(lc - la) <= 1e-6 * abs(la)
+    a.close()
+    b.close()
+
+
+def test_lbfgs_resume_bitwise_without_slack(gpu):
+    """Without the cached tile order (slack 0) every trial step is binned: two
+    calls of 6 iterations continue exactly like one call of 12, and the loss the
+    update summed from the evaluation's partials is the one a plain evaluation
+    at the returned positions gives (same partials, same order)."""
+    import torch
+    (a, b), pos0 = _f32_pair(gpu, [torch.cuda.Stream(device=gpu),
+                                   torch.cuda.default_stream(gpu)], slack=0)
+    assert a.plan_info()["slack"] == 0
     pa = torch.from_numpy(pos0.copy()).to(gpu)
     pb = torch.from_numpy(pos0.copy()).to(gpu)
     la, na = a.step(pa, 12)
@@ -93,12 +131,74 @@ def test_lbfgs_graph_eager_resume_bitwise(gpu):
     assert la == lb2
     assert torch.equal(pa, pb)
     assert na == nb1 + nb2 - 1  # the second call re-evaluates its starting point
-    # the loss the update summed from the evaluation's partials is the one a
-    # plain evaluation at the returned positions gives (same partials, same order)
     lc, _ = a.loss_grad(pa)
     assert lc == la
     a.close()
     b.close()
+
+
+def test_lbfgs_cached_tile_order_follows_full_binning(gpu):
+    """One chunk of 8 trial steps with the cached tile order (slack 2) against
+    the same call binning every trial step (slack 0): the FP32 trajectories
+    agree to the transform accuracy (later iterations of this non-convex
+    minimisation amplify last-bit differences, so the comparison stops at the
+    first chunk); a 40-iteration call converges like the binned one, and its
+    returned loss is the oracle's at the returned positions."""
+    import torch
+    (a,), pos0 = _f32_pair(gpu, [torch.cuda.Stream(device=gpu)])
+    (b,), _ = _f32_pair(gpu, [torch.cuda.Stream(device=gpu)], slack=0)
+    f0, _ = a.loss_grad(torch.from_numpy(pos0.copy()).to(gpu))
+    pa = torch.from_numpy(pos0.copy()).to(gpu)
+    pb = torch.from_numpy(pos0.copy()).to(gpu)
+    la, na = a.step(pa, 8)
+    lb, nb = b.step(pb, 8)
+    xa = pa.cpu().numpy().astype(np.float64)
+    xb = pb.cpu().numpy().astype(np.float64)
+    move = np.abs(xa - pos0).max()
+    print(f"8 iterations: cached {la:.9e} ({na} evals), binned {lb:.9e} ({nb} evals), "
+          f"largest move {move:.3f}, largest difference {np.abs(xa - xb).max():.2e}", flush=True)
+    assert na == nb
+    assert abs(la - lb) <= 1e-6 * abs(lb)
+    assert np.abs(xa - xb).max() <= 1e-4 * move
+    la, na = a.step(pa, 32)
+    lb, nb = b.step(pb, 32)
+    torch.cuda.synchronize()
+    print(f"40 iterations: cached {la:.6e}, binned {lb:.6e}, start {f0:.6e}", flush=True)
+    assert la < 1e-5 * f0 and lb < 1e-5 * f0
+    d, N, L, M = 2, 30000, 173.2, 30
+    w, s0 = I.stealthy_target(d, M, float(M))
+    modes, W, S0 = O.constrained_set(d, M, w, s0)
+    xa = pa.cpu().numpy().astype(np.float64)
+    ref = O.loss_grad(xa, L, modes, W, S0, want_grad=False)["loss"]
+    assert abs(ref - la) <= 1e-9 * f0
+    a.close()
+    b.close()
+
+
+def test_lbfgs_cached_tile_order_matches_oracle_fp64(gpu):
+    """One call of 24 iterations (three chunks of 8 trial steps, the tile order
+    kept between binnings) follows the FP64 oracle's trajectory."""
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    d, N, L, M = 2, 1024, 32.0, 16
+    pos0 = I.positions(N, d, L, np.float64, seed=54)
+    w, s0 = I.stealthy_target(d, M, float(M))
+    ctx = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-12, dtype="f64", device=gpu,
+                    stream=torch.cuda.Stream(device=gpu))
+    assert ctx.plan_info()["slack"] == 2
+    ms = ctx.default_max_step()
+    modes, W, S0 = O.constrained_set(d, M, w, s0)
+    ref = LB.run(_oracle_fg(N, d, L, modes, W, S0), pos0, 24, m=8, max_step=ms)
+    pos = torch.from_numpy(pos0.copy()).to(gpu)
+    loss, nev = ctx.step(pos, 24, max_step=ms)
+    x = pos.cpu().numpy().ravel()
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"] - pos0.ravel())
+    print(f"loss {loss:.12e} (oracle {ref['f']:.12e}), evaluations {nev} ({ref['nevals']}), "
+          f"position error {err:.2e}", flush=True)
+    assert nev == ref["nevals"]
+    assert abs(loss - ref["f"]) <= 1e-9 * ref["fs"][0]
+    assert err < 1e-7
+    ctx.close()
 
 
 @pytest.mark.parametrize("d,N,L,M,ranges", [(3, 8000, 20.0, 8, None), (2, 8000, 90.0, 20, "5")])
