@@ -814,9 +814,9 @@ int build_weights(const Geom& g, const double* s0, const double* w, double k_cut
 
 // ---------------------------------------------------------------- stages
 // optimiser: an optimiser trial step, whose binning keeps each point's tile
-// (b.home) for the trial steps after it; cached: keep the order of the last
-// binning and only recompute the records (optimiser trial steps that stay within
-// the slack of the binned positions)
+// (b.home) for the trial steps after it; cached: the order of the last binning is
+// kept and the records were written with the trial point (optimiser trial steps
+// that stay within the slack of the binned positions): no binning pass
 template <class R>
 int run_bin_spread_rows(fresco_ctx* c, const R* pos, bool optimiser = false,
                         bool cached = false) {
@@ -824,15 +824,11 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos, bool optimiser = false,
   const Geom& g = c->g;
   hipStream_t st = c->st;
   S->cached_eval = cached;
-  {
+  if (!cached) {
     StageTimer t(c, FRESCO_STAGE_BIN);
-    if (cached) {
-      launch_bin_refresh(g, pos, sizeof(R) == 8, S->bb, &S->lst->drift, st);
-    } else {
-      BinBuffers b = S->bb;
-      if (!optimiser) b.home = nullptr;  // scattered writes that no one reads
-      launch_bin(g, S->bp, pos, sizeof(R) == 8, b, st);
-    }
+    BinBuffers b = S->bb;
+    if (!optimiser) b.home = nullptr;  // scattered writes that no one reads
+    launch_bin(g, S->bp, pos, sizeof(R) == 8, b, st);
   }
   {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
@@ -1108,10 +1104,12 @@ int lbfgs_reset_state(fresco_ctx* c) {
   return FRESCO_OK;
 }
 
-// one trial step: evaluation at xt, then the optimiser update; cached: the
-// binning order of the previous trial step is kept
+// one trial step: evaluation at xt, then the optimiser update; cached: this
+// evaluation keeps the tile order of the last binning (its records were written
+// by the previous update); keep_next: so does the next one, whose records this
+// update writes
 template <class R>
-int lbfgs_trial(fresco_ctx* c, bool cached = false) {
+int lbfgs_trial(fresco_ctx* c, bool cached = false, bool keep_next = false) {
   State<R>* S = (State<R>*)c->state;
   int st;
   // the optimiser's positions are in its internal order, and so are the strengths
@@ -1121,7 +1119,13 @@ int lbfgs_trial(fresco_ctx* c, bool cached = false) {
   if ((st = run_modes_to_grad<R>(c, COL_FUSED, S->lv.xt, nullptr, nullptr, S->lv.gt,
                                  &S->lst->f_trial)))
     return st;
-  launch_lbfgs_update<R>(S->lv, S->lst, S->lb_opts, c->st);
+  KeptOrder<R> ko;
+  ko.g = c->g;
+  ko.perm = S->bb.perm;
+  ko.home = S->bb.home;
+  ko.rec = (Rec<R>*)S->bb.rec;
+  ko.flag = S->bb.flag;
+  launch_lbfgs_update<R>(S->lv, S->lst, S->lb_opts, c->st, keep_next ? &ko : nullptr);
   HIPCHK(hipGetLastError());
   return FRESCO_OK;
 }
@@ -1188,7 +1192,8 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
     int s2 = FRESCO_OK;
-    for (int r = 0; r < steps && !s2; ++r) s2 = lbfgs_trial<R>(c, r % bin_every != 0);
+    for (int r = 0; r < steps && !s2; ++r)
+      s2 = lbfgs_trial<R>(c, r % bin_every != 0, r + 1 < steps && (r + 1) % bin_every != 0);
     hipError_t e = hipStreamEndCapture(c->st, &graph);
     if (s2) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -1217,8 +1222,9 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
         HIPCHK(hipGraphLaunch(S->lb_graph, c->st));
       } else {
         // eager launches follow the graphs' binning pattern (same arithmetic)
-        const bool cached = count == kLbfgsReplayChunk && r % bin_every != 0;
-        const int s2 = lbfgs_trial<R>(c, cached);
+        const bool chunk = count == kLbfgsReplayChunk;
+        const int s2 = lbfgs_trial<R>(c, chunk && r % bin_every != 0,
+                                      chunk && r + 1 < count && (r + 1) % bin_every != 0);
         if (s2) return s2;
       }
     }
@@ -1679,7 +1685,7 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
     if (const char* es = std::getenv("FRESCO_SLACK"))
       if (d == 2) slack = std::max(0, std::min(8, std::atoi(es)));
     for (int a = 0; a < d; ++a)
-      if (g.nf[a] < g.T[a] + 2 * slack + g.wi + 1) slack = 0;
+      if (g.nf[a] < g.T[a] + 2 * slack + g.wi + 1 || g.nt[a] > 1024) slack = 0;
     g.slack = slack;
     g.islack = 0;
     for (int a = 0; a < d; ++a) {

@@ -107,6 +107,64 @@ struct alignas(4 * sizeof(R)) Rec {
   uint32_t cell;
 };
 
+// Record of a point kept in tile `tile` (cached tile order of the optimiser's
+// trial steps): tau and the footprint start as the binning computes them, the
+// start taken relative to that tile (periodically, within one grid period of
+// it) and stored with the slack offset.  *bad: a coordinate is not finite;
+// *off: a finite footprint start lies beyond the slack (clamped).
+// tile coordinates of a kept tile, 10 bits per axis (a slack needs nt <= 1024)
+__host__ __device__ inline uint32_t kept_tile_pack(const uint32_t* t) {
+  return t[0] | (t[1] << 10) | (t[2] << 20);
+}
+template <class R, int D>
+__device__ __forceinline__ Rec<R> kept_tile_record(const Geom& g, const R* x, uint32_t tile,
+                                                    bool* bad, bool* off) {
+  Rec<R> o;
+  o.t[0] = o.t[1] = o.t[2] = R(0);
+  o.cell = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const uint32_t ta = (tile >> (10 * a)) & 1023u;
+    const double nf = (double)g.nf[a];
+    double u = (double)x[a] * g.ufac[a];
+    if (!isfinite(u)) {
+      *bad = true;
+      u = 0.0;
+    }
+    if (!(u >= 0.0 && u < nf)) {
+      u = fmod(u, nf);
+      if (u < 0.0) u += nf;
+      if (u >= nf) u = 0.0;
+    }
+    const double l0 = ceil(u - 0.5 * g.w);
+    o.t[a] = (R)(l0 - u + 0.5 * g.w);
+    int li = (int)l0;
+    if (li < 0) li += g.nf[a];
+    if (li >= g.nf[a]) li -= g.nf[a];
+    int rel = li - (int)ta * g.T[a];
+    if (rel < -g.slack) rel += g.nf[a];
+    if (rel >= g.T[a] + g.slack) rel -= g.nf[a];
+    if (rel < -g.slack || rel >= g.T[a] + g.slack) {
+      *off = true;
+      rel = rel < -g.slack ? -g.slack : g.T[a] + g.slack - 1;
+    }
+    o.cell |= (uint32_t)(rel + g.slack) << (8 * a);
+  }
+  return o;
+}
+
+// Where the optimiser's trial point update also writes the records of the next
+// (cached) evaluation: the kept order (slot -> point, slot -> tile) and the
+// outputs.
+template <class R>
+struct KeptOrder {
+  Geom g;
+  const int* perm;
+  const uint32_t* home;  // tile coordinates, 10 bits per axis (kept_tile_pack)
+  Rec<R>* rec;
+  int* flag;  // a coordinate is not finite
+};
+
 // FP32 kernels evaluate the spreading and interpolation kernels as per-cell
 // polynomials of this degree in x = 2 tau - 1 (see plan.h, kernel_poly).
 constexpr int kPolyDeg = 9;
@@ -197,12 +255,7 @@ constexpr int kMaxSpreadLds = 160 * 1024;
 // Launchers exported by the translation units (all enqueue on `st`).
 void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, BinBuffers& b,
                 hipStream_t st);
-// Records of the sorted positions from pos with the order of the last launch_bin
-// kept (b.perm, b.start, b.home; BIN_TILES with slack): every point stays in the
-// tile it was binned into.  A finite point whose footprint start left that tile
-// by more than the slack is clamped and flagged in *drift.
-void launch_bin_refresh(const Geom& g, const void* pos, bool f64, const BinBuffers& b,
-                        int* drift, hipStream_t st);
+
 template <class R>
 size_t spread_lds_bytes(const Geom& g, bool str);
 template <class R>

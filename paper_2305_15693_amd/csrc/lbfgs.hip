@@ -26,7 +26,9 @@
 //   small    one block: applies the decision, reduces the partials, stores the
 //            pair when y.s > 0 and solves for u, t (FP64, one wavefront);
 //   pass B   p = -(gamma g + S u - gamma Y t), max |p| per block;
-//   pass C   alpha = min(1, max_step / max|p|), xt = x + alpha p.
+//   pass C   alpha = min(1, max_step / max|p|), xt = x + alpha p (and, when the
+//            next evaluation keeps the tile order of the last binning, its
+//            point records).
 // (Cross-block steps stay at kernel boundaries: a device-scope fence per block
 // writes back the L2 of its XCD and cost more than the launches it saved.)
 // Vectors are in the working precision; every dot product is accumulated in FP64
@@ -559,27 +561,13 @@ __global__ __launch_bounds__(kThreads) void lb_pass_b_kernel(LbfgsVec<R> v, Lbfg
 
 // ---------------------------------------------------------------- pass C
 // step length of a new direction (every block reduces the pass B maxima), or
-// the one shrunk by the decision; then the trial point xt = x + alpha p (packs
-// of U elements strided over the grid, then the elements past the last whole
-// pack; the thread's first pack is loaded before the step length is known, so
-// that its latency overlaps the reduction)
+// the one shrunk by the decision
 template <class R>
-__global__ __launch_bounds__(kThreads) void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o, int vec) {
-  __shared__ double sh[kWaves];
-  __shared__ double alpha_s;
-  const int step = S->step;
-  if (step == LB_IDLE) return;
-  constexpr int U = pack_u<R, 1, kPackBytesBC>();
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long gs = (long long)gridDim.x * blockDim.x;
-  const long long nq = vec ? v.n / U : 0;
-  Pack<R, U> xa, pa;
-  if (gid < nq) {
-    xa = ldp<R, U>(v.x, gid * U);
-    pa = ldp<R, U>(v.p, gid * U);
-  }
+__device__ __forceinline__ R pass_c_alpha(const LbfgsVec<R>& v, LbfgsState* S,
+                                          const LbfgsOpts& o, int step, double* sh,
+                                          double* alpha_s) {
   if (step == LB_REJECT) {
-    if (threadIdx.x == 0) alpha_s = S->alpha;
+    if (threadIdx.x == 0) *alpha_s = S->alpha;
   } else {
     // nb <= kLbfgsMaxBlocks: every maximum a thread reads is loaded at once
     constexpr int kU = (kLbfgsMaxBlocks + kThreads - 1) / kThreads;
@@ -599,12 +587,33 @@ __global__ __launch_bounds__(kThreads) void lb_pass_c_kernel(LbfgsVec<R> v, Lbfg
       double t = 0.0;
       for (int w = 0; w < kWaves; ++w) t = fmax(t, sh[w]);
       const double a = (t > o.max_step) ? o.max_step / t : 1.0;
-      alpha_s = a;
+      *alpha_s = a;
       if (blockIdx.x == 0) S->alpha = a;
     }
   }
   __syncthreads();
-  const R alpha = (R)alpha_s;
+  return (R)*alpha_s;
+}
+
+// the trial point xt = x + alpha p (packs of U elements strided over the grid,
+// then the elements past the last whole pack; the thread's first pack is loaded
+// before the step length is known, so that its latency overlaps the reduction)
+template <class R>
+__global__ __launch_bounds__(kThreads) void lb_pass_c_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o, int vec) {
+  __shared__ double sh[kWaves];
+  __shared__ double alpha_s;
+  const int step = S->step;
+  if (step == LB_IDLE) return;
+  constexpr int U = pack_u<R, 1, kPackBytesBC>();
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long gs = (long long)gridDim.x * blockDim.x;
+  const long long nq = vec ? v.n / U : 0;
+  Pack<R, U> xa, pa;
+  if (gid < nq) {
+    xa = ldp<R, U>(v.x, gid * U);
+    pa = ldp<R, U>(v.p, gid * U);
+  }
+  const R alpha = pass_c_alpha<R>(v, S, o, step, sh, &alpha_s);
   if (gid < nq) {
     Pack<R, U> t;
 #pragma unroll
@@ -619,6 +628,34 @@ __global__ __launch_bounds__(kThreads) void lb_pass_c_kernel(LbfgsVec<R> v, Lbfg
     stp<R, U>(v.xt, q * U, t);
   }
   for (long long i = nq * U + gid; i < v.n; i += gs) v.xt[i] = v.x[i] + alpha * v.p[i];
+}
+
+// The same trial point, point by point in the kept tile order, with the records
+// of the next evaluation (it keeps that order: its binning is this pass).  A
+// finite point beyond the slack sets the state's drift flag.
+template <class R, int D>
+__global__ __launch_bounds__(kThreads) void lb_pass_c_kept_kernel(LbfgsVec<R> v, LbfgsState* S,
+                                                                  LbfgsOpts o, KeptOrder<R> ko) {
+  __shared__ double sh[kWaves];
+  __shared__ double alpha_s;
+  const int step = S->step;
+  if (step == LB_IDLE) return;
+  const R alpha = pass_c_alpha<R>(v, S, o, step, sh, &alpha_s);
+  const long long gs = (long long)gridDim.x * blockDim.x;
+  bool bad = false, off = false;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < ko.g.N; j += gs) {
+    const long long i = ko.perm[j];
+    R x[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const long long e = i * D + a;
+      x[a] = v.x[e] + alpha * v.p[e];
+      v.xt[e] = x[a];
+    }
+    ko.rec[j] = kept_tile_record<R, D>(ko.g, x, ko.home[j], &bad, &off);
+  }
+  if (bad) atomicOr(ko.flag, 1);
+  if (off && !bad) atomicOr(&S->drift, 1);
 }
 
 // set the mode read by the next decision (host-driven transitions)
@@ -638,7 +675,7 @@ __global__ void lb_set_mode_kernel(LbfgsState* S, int mode, int target) {
 
 template <class R>
 void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
-                         hipStream_t st) {
+                         hipStream_t st, const KeptOrder<R>* kept) {
   // packed access needs every array and history slot aligned to a pack
   constexpr size_t kPackBytes = sizeof(R) * pack_u<R, 1, kPackBytesBC>();
   auto al = [&](const void* q) { return ((uintptr_t)q % kPackBytes) == 0; };
@@ -661,7 +698,9 @@ void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o
 #undef LB_SWITCH
 #undef LB_B
 #undef LB_A
-  lb_pass_c_kernel<R><<<v.nb, kThreads, 0, st>>>(v, S, o, vec);
+  if (kept && kept->g.d == 2) lb_pass_c_kept_kernel<R, 2><<<v.nb, kThreads, 0, st>>>(v, S, o, *kept);
+  else if (kept) lb_pass_c_kept_kernel<R, 3><<<v.nb, kThreads, 0, st>>>(v, S, o, *kept);
+  else lb_pass_c_kernel<R><<<v.nb, kThreads, 0, st>>>(v, S, o, vec);
 }
 
 void launch_lbfgs_set_mode(LbfgsState* S, int mode, int target, hipStream_t st) {
@@ -701,7 +740,7 @@ void launch_scatter_rows(const R* src, const int* idx, long long n, int d, R* ds
 
 #define FRESCO_LB_INST(R)                                                                       \
   template void launch_lbfgs_update<R>(const LbfgsVec<R>&, LbfgsState*, const LbfgsOpts&,       \
-                                       hipStream_t);                                            \
+                                       hipStream_t, const KeptOrder<R>*);                       \
   template void launch_gather_rows<R>(const R*, const int*, long long, int, R*, hipStream_t);   \
   template void launch_scatter_rows<R>(const R*, const int*, long long, int, R*, hipStream_t);
 FRESCO_LB_INST(float)

@@ -80,6 +80,7 @@ template void launch_fill<double>(double*, long long, double, hipStream_t);
 struct PointBin {
   uint32_t bin;
   uint32_t cell;
+  uint32_t tc;  // tile coordinates (kept_tile_pack)
   double t[3];
 };
 
@@ -114,6 +115,7 @@ __device__ __forceinline__ PointBin bin_point_d(const Geom& g, const R* r, bool*
     pb.cell |= loc << (8 * a);
   }
   pb.bin = tile[0] + (uint32_t)g.nt[0] * (tile[1] + (uint32_t)g.nt[1] * tile[2]);
+  pb.tc = kept_tile_pack(tile);
   return pb;
 }
 // g.d is uniform: both branches keep every index a compile-time constant
@@ -234,76 +236,7 @@ __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, uint32_t b
   o.cell = pb.cell;
   rec[dst] = o;
   perm[dst] = (int)i;
-  if (home) home[dst] = tile;
-}
-
-// Cached tile order: slot j keeps point perm[j] in tile home[j]; its record is
-// recomputed from the current position as in bin_point_d, the footprint start
-// taken relative to the home tile (periodically, within one grid period of it)
-// and stored with the slack offset.
-template <class R, int D>
-__global__ void bin_refresh_kernel(Geom g, const R* __restrict__ pos, const int* __restrict__ perm,
-                                   const uint32_t* __restrict__ home, Rec<R>* __restrict__ rec,
-                                   int* __restrict__ flag, int* __restrict__ drift) {
-  const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= g.N) return;
-  const long long i = perm[j];
-  uint32_t tile = home[j];
-  R x[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) x[a] = pos[i * D + a];
-  bool bad = false, off = false;
-  Rec<R> o;
-  o.t[0] = o.t[1] = o.t[2] = R(0);
-  o.cell = 0;
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const uint32_t ta = tile % (uint32_t)g.nt[a];
-    tile /= (uint32_t)g.nt[a];
-    const double nf = (double)g.nf[a];
-    double u = (double)x[a] * g.ufac[a];
-    if (!isfinite(u)) {
-      bad = true;
-      u = 0.0;
-    }
-    if (!(u >= 0.0 && u < nf)) {
-      u = fmod(u, nf);
-      if (u < 0.0) u += nf;
-      if (u >= nf) u = 0.0;
-    }
-    const double l0 = ceil(u - 0.5 * g.w);
-    o.t[a] = (R)(l0 - u + 0.5 * g.w);
-    int li = (int)l0;
-    if (li < 0) li += g.nf[a];
-    if (li >= g.nf[a]) li -= g.nf[a];
-    int rel = li - (int)ta * g.T[a];
-    if (rel < -g.slack) rel += g.nf[a];
-    if (rel >= g.T[a] + g.slack) rel -= g.nf[a];
-    if (rel < -g.slack || rel >= g.T[a] + g.slack) {
-      off = true;
-      rel = rel < -g.slack ? -g.slack : g.T[a] + g.slack - 1;
-    }
-    o.cell |= (uint32_t)(rel + g.slack) << (8 * a);
-  }
-  rec[j] = o;
-  if (bad) atomicOr(flag, 1);
-  else if (off) atomicOr(drift, 1);
-}
-
-void launch_bin_refresh(const Geom& g, const void* pos, bool f64, const BinBuffers& b,
-                        int* drift, hipStream_t st) {
-  const unsigned nb = (unsigned)((g.N + 255) / 256);
-#define REFRESH(R, D)                                                                       \
-  bin_refresh_kernel<R, D><<<nb, 256, 0, st>>>(g, (const R*)pos, b.perm, b.home,           \
-                                               (Rec<R>*)b.rec, b.flag, drift)
-  if (f64) {
-    if (g.d == 2) REFRESH(double, 2);
-    else REFRESH(double, 3);
-  } else {
-    if (g.d == 2) REFRESH(float, 2);
-    else REFRESH(float, 3);
-  }
-#undef REFRESH
+  if (home) home[dst] = pb.tc;
 }
 
 // Slot of point i in the range order (first level of BIN_RANGES); 256-thread
