@@ -1232,7 +1232,10 @@ template <class R>
 void launch_interp(const Geom& g, const BinPlan& bp, const BinBuffers& b, const R* v, R* grad,
                    const Strengths<R>& cs, hipStream_t st) {
   const size_t lds = interp_lds_bytes<R>(g);
-  const int threads = (g.d == 3) ? 512 : 256;
+  // 2D: 256 threads, four workgroups per CU; field tiles covering a slack hold
+  // more than a quarter of the LDS, so 512 threads, two workgroups per CU (whole
+  // rounds of 512 tiles instead of 768 and a tail)
+  const int threads = (g.d == 3 || g.islack > 0) ? 512 : 256;
   const Rec<R>* rec = (const Rec<R>*)b.rec;
   const long long* start = b.start;
   const int* perm = b.perm;
