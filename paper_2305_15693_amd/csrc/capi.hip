@@ -342,21 +342,6 @@ bool shape_cols(int n, int rmin, long long ncols, size_t cs, int* bc, int* threa
   return true;
 }
 
-// sum of n partials in a fixed order (one block of 256 threads)
-__device__ double block_sum_256(const double* __restrict__ part, long long n, double* s) {
-  double v = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 256) v += part[i];
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  const double r = s[0];
-  __syncthreads();
-  return r;
-}
-
 // loss = sum of the block partials (fixed order), plus w2 times the sum of a
 // second set (an attached pair term); hand the non-finite flag to the
 // host-visible slot and clear it for the next evaluation
@@ -899,7 +884,7 @@ int run_long_cols(fresco_ctx* c, int mode, const ColParams<R>& last) {
 // mode stage + inverse transforms + interpolation; mode = COL_FUSED or COL_BWD
 template <class R>
 int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R* g_cube, R* grad,
-                      double* loss_dev) {
+                      double* loss_dev, LossParts* defer = nullptr) {
   State<R>* S = (State<R>*)c->state;
   const Geom& g = c->g;
   const int d = g.d;
@@ -969,10 +954,21 @@ int run_modes_to_grad(fresco_ctx* c, int mode, const R* pos, R* S_cube, const R*
     int ps = pair_enqueue(c->pair, pos, grad, true, c->pair_w, st);
     if (ps) return ps;
   }
-  finish_kernel<<<1, 256, 0, st>>>(S->loss_part, mode == COL_FUSED ? S->nloss_part : 0,
-                                   pair ? c->pair->part : nullptr, pair ? c->pair->nblocks : 0,
-                                   c->pair_w, mode == COL_FUSED ? loss_dev : nullptr, S->bb.flag,
-                                   S->flag_out);
+  LossParts lp;
+  lp.part = S->loss_part;
+  lp.n = mode == COL_FUSED ? S->nloss_part : 0;
+  lp.part2 = pair ? c->pair->part : nullptr;
+  lp.n2 = pair ? c->pair->nblocks : 0;
+  lp.w2 = c->pair_w;
+  lp.flag = S->bb.flag;
+  lp.flag_out = S->flag_out;
+  // defer: the caller's next kernel sums the partials (the optimiser update)
+  if (defer) {
+    *defer = lp;
+    return FRESCO_OK;
+  }
+  finish_kernel<<<1, 256, 0, st>>>(lp.part, lp.n, lp.part2, lp.n2, lp.w2,
+                                   mode == COL_FUSED ? loss_dev : nullptr, lp.flag, lp.flag_out);
   HIPCHK(hipGetLastError());
   return FRESCO_OK;
 }
@@ -1116,8 +1112,10 @@ int lbfgs_trial(fresco_ctx* c, bool cached = false, bool keep_next = false) {
   S->str_eval = S->has_str ? S->cint : nullptr;
   S->val_eval = nullptr;
   if ((st = run_bin_spread_rows<R>(c, S->lv.xt, true, cached))) return st;
+  // the update's first pass sums the loss partials into f_trial itself
+  LossParts lp;
   if ((st = run_modes_to_grad<R>(c, COL_FUSED, S->lv.xt, nullptr, nullptr, S->lv.gt,
-                                 &S->lst->f_trial)))
+                                 &S->lst->f_trial, &lp)))
     return st;
   KeptOrder<R> ko;
   ko.g = c->g;
@@ -1125,7 +1123,7 @@ int lbfgs_trial(fresco_ctx* c, bool cached = false, bool keep_next = false) {
   ko.home = S->bb.home;
   ko.rec = (Rec<R>*)S->bb.rec;
   ko.flag = S->bb.flag;
-  launch_lbfgs_update<R>(S->lv, S->lst, S->lb_opts, c->st, keep_next ? &ko : nullptr);
+  launch_lbfgs_update<R>(S->lv, S->lst, S->lb_opts, c->st, keep_next ? &ko : nullptr, &lp);
   HIPCHK(hipGetLastError());
   return FRESCO_OK;
 }

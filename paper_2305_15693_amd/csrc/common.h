@@ -153,6 +153,36 @@ __device__ __forceinline__ Rec<R> kept_tile_record(const Geom& g, const R* x, ui
   return o;
 }
 
+// sum of n partials in a fixed order (one block of 256 threads; s: 256 doubles)
+__device__ __forceinline__ double block_sum_256(const double* __restrict__ part, long long n,
+                                                double* s) {
+  double v = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) v += part[i];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// The loss of an evaluation as its block partials (and those of an attached
+// pair term, weight w2), summed by whoever finishes the evaluation: the loss is
+// sum(part) + w2 sum(part2) (just sum(part) when n2 = 0), the non-finite flag is
+// handed to flag_out and cleared.
+struct LossParts {
+  const double* part;
+  long long n;
+  const double* part2;
+  long long n2;
+  double w2;
+  int* flag;
+  int* flag_out;
+};
+
 // Where the optimiser's trial point update also writes the records of the next
 // (cached) evaluation: the kept order (slot -> point, slot -> tile) and the
 // outputs.

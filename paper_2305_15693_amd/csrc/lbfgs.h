@@ -139,10 +139,13 @@ int lbfgs_replay_until_stop(hipStream_t st, LbfgsState* dev, LbfgsState* host, h
 // replays per chunk of an optimiser call
 constexpr int kLbfgsReplayChunk = 8;
 
-// kept: also write the records of the next evaluation in that kept tile order
+// kept: also write the records of the next evaluation in that kept tile order;
+// loss: the evaluation's loss partials, summed into f_trial by the first pass
+// (else f_trial holds the loss already)
 template <class R>
 void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
-                         hipStream_t st, const KeptOrder<R>* kept = nullptr);
+                         hipStream_t st, const KeptOrder<R>* kept = nullptr,
+                         const LossParts* loss = nullptr);
 void launch_lbfgs_set_mode(LbfgsState* S, int mode, int target, hipStream_t st);
 template <class R>
 void launch_gather_rows(const R* src, const int* idx, long long n, int d, R* dst, hipStream_t st);

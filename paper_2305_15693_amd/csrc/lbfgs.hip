@@ -34,6 +34,7 @@
 // Vectors are in the working precision; every dot product is accumulated in FP64
 // with a fixed reduction order.
 #include <cmath>
+#include <cstring>
 
 #include "common.h"
 #include "lbfgs.h"
@@ -72,16 +73,16 @@ __device__ __forceinline__ void block_partials(const double* v, double* part, in
 // ---------------------------------------------------------------- decide
 // Decision on the evaluation just finished, as a function of the state (every
 // block of pass A computes it; the small step then applies it).
-__device__ __forceinline__ int lb_decided_step(const LbfgsState* S, const LbfgsOpts& o) {
+__device__ __forceinline__ int lb_decided_step(const LbfgsState* S, const LbfgsOpts& o,
+                                               double f) {
   if (S->mode == LB_INIT) return LB_INIT;  // first evaluation of a call
   if (S->fail || S->iter >= S->target || S->converged) return LB_IDLE;
-  const double f = S->f_trial;
   if (isfinite(f) && f <= S->f_cur + o.c1 * S->alpha * S->gtp) return LB_ACCEPT;
   if (S->nbt + 1 > o.max_backtracks) return (S->k > 0 || !S->restarted) ? LB_RESTART : LB_IDLE;
   return LB_REJECT;
 }
 __device__ void lb_decide(LbfgsState* S, const LbfgsOpts& o) {
-  const int step = lb_decided_step(S, o);
+  const int step = lb_decided_step(S, o, S->f_trial);
   // an evaluation counts when it can inform a decision: replays that run after
   // the call has stopped (target reached, converged, failed) are not counted
   if (S->mode == LB_INIT || !(S->fail || S->iter >= S->target || S->converged)) S->nevals += 1;
@@ -331,10 +332,28 @@ __device__ __forceinline__ void pass_a_run(const LbfgsVec<R>& v, int head, int k
 }
 
 // MM = history length m (compile time, so the accumulators stay in registers).
+// loss.n >= 0: the evaluation's loss partials, summed here in the order of the
+// loss finish (every block, for its decision; block 0 stores f_trial and hands
+// over the flag); else f_trial holds the loss.
 template <class R, int MM>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MM <= 8 ? 4 : 1))) void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o, int vec) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MM <= 8 ? 4 : 1))) void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o, int vec, LossParts loss) {
   __shared__ double sh[(4 * MM + 5) * kWaves];
-  const int step = lb_decided_step(S, o);
+  double f;
+  if (loss.n >= 0) {
+    __shared__ double s256[kThreads];
+    static_assert(kThreads == 256, "the loss partials are summed as by the 256-thread finish");
+    const double a = block_sum_256(loss.part, loss.n, s256);
+    const double b = (loss.n2 > 0) ? block_sum_256(loss.part2, loss.n2, s256) : 0.0;
+    f = (loss.n2 > 0) ? a + loss.w2 * b : a;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      S->f_trial = f;
+      *loss.flag_out = *loss.flag;
+      *loss.flag = 0;
+    }
+  } else {
+    f = S->f_trial;
+  }
+  const int step = lb_decided_step(S, o, f);
   if (step != LB_ACCEPT && step != LB_INIT) return;  // uniform: before any barrier
   const int head = S->head, k = S->k;
   const int ns = (head + 1) % MM;  // slot of the new pair
@@ -675,13 +694,20 @@ __global__ void lb_set_mode_kernel(LbfgsState* S, int mode, int target) {
 
 template <class R>
 void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
-                         hipStream_t st, const KeptOrder<R>* kept) {
+                         hipStream_t st, const KeptOrder<R>* kept, const LossParts* loss) {
+  LossParts lp;
+  if (loss) {
+    lp = *loss;
+  } else {
+    std::memset(&lp, 0, sizeof(lp));
+    lp.n = -1;
+  }
   // packed access needs every array and history slot aligned to a pack
   constexpr size_t kPackBytes = sizeof(R) * pack_u<R, 1, kPackBytesBC>();
   auto al = [&](const void* q) { return ((uintptr_t)q % kPackBytes) == 0; };
   const int vec = al(v.x) && al(v.g) && al(v.p) && al(v.xt) && al(v.gt) && al(v.S) && al(v.Y) &&
                   (v.ld % pack_u<R, 1, kPackBytesBC>()) == 0;
-#define LB_A(MM) lb_pass_a_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, o, vec)
+#define LB_A(MM) lb_pass_a_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, o, vec, lp)
 #define LB_B(MM) lb_pass_b_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, vec)
 #define LB_SWITCH(CALL)                                                        \
   switch (v.m) {                                                               \
@@ -740,7 +766,7 @@ void launch_scatter_rows(const R* src, const int* idx, long long n, int d, R* ds
 
 #define FRESCO_LB_INST(R)                                                                       \
   template void launch_lbfgs_update<R>(const LbfgsVec<R>&, LbfgsState*, const LbfgsOpts&,       \
-                                       hipStream_t, const KeptOrder<R>*);                       \
+                                       hipStream_t, const KeptOrder<R>*, const LossParts*);     \
   template void launch_gather_rows<R>(const R*, const int*, long long, int, R*, hipStream_t);   \
   template void launch_scatter_rows<R>(const R*, const int*, long long, int, R*, hipStream_t);
 FRESCO_LB_INST(float)
