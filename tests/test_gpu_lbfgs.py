@@ -377,3 +377,43 @@ def test_device_memory_limit_reports_enomem(gpu):
     loss, grad = ctx.loss_grad(pos)
     assert loss == ref_loss and torch.equal(grad, ref_grad)
     ctx.close()
+
+
+def test_lbfgs_cached_tile_order_with_strengths_and_pair_fp64(gpu):
+    """The kept tile order with polydisperse strengths (read through the kept
+    permutation) and an attached soft-core pair term (which reads the trial
+    points the record pass writes): one call of 24 iterations follows the FP64
+    oracle L-BFGS on L_S + E."""
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    d, N, L, M = 2, 1024, 32.0, 16
+    pos0 = I.positions(N, d, L, np.float64, seed=55)
+    c = I.polydisperse_strengths(N, d, seed=56)
+    w, s0 = I.stealthy_target(d, M, float(M))
+    ctx = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-12, dtype="f64", device=gpu,
+                    stream=torch.cuda.Stream(device=gpu))
+    assert ctx.plan_info()["slack"] == 2
+    ctx.set_strengths(torch.from_numpy(c).to(gpu))
+    sigma, eps, alpha, wp = 0.6, 1.0, 2.0, 3.0
+    pc = F.PairContext(d, N, L, sigma=sigma, eps=eps, alpha=alpha, dtype="f64", device=gpu)
+    ctx.attach_pair(pc, wp)
+    ms = ctx.default_max_step()
+    modes, W, S0 = O.constrained_set(d, M, w, s0)
+
+    def fg(x):
+        r = O.loss_grad_strengths(x.reshape(N, d), c, L, modes, W, S0)
+        e, ge = O.pair(x.reshape(N, d), L, sigma, eps, alpha)
+        return r["loss"] + wp * e, r["grad"].ravel() + wp * ge.ravel()
+
+    ref = LB.run(fg, pos0, 24, m=8, max_step=ms)
+    pos = torch.from_numpy(pos0.copy()).to(gpu)
+    loss, nev = ctx.step(pos, 24, max_step=ms)
+    x = pos.cpu().numpy().ravel()
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"] - pos0.ravel())
+    print(f"loss {loss:.12e} (oracle {ref['f']:.12e}, start {ref['fs'][0]:.6e}), evaluations "
+          f"{nev} ({ref['nevals']}), position error {err:.2e}", flush=True)
+    assert nev == ref["nevals"]
+    assert abs(loss - ref["f"]) <= 1e-9 * ref["fs"][0]
+    assert err < 1e-7
+    ctx.close()
+    pc.close()
