@@ -1677,13 +1677,16 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
   // 40-cell tiles; the interpolation's field tiles cover the slack only in those
   // cached evaluations; 3D: none).  FRESCO_SLACK overrides it
   // in 2D (0 to 8).  Only where the padded tiles stay well inside one grid
-  // period.
+  // period and the points are sorted by tile in one level.
   {
     int slack = (d == 2) ? 2 : 0;
     if (const char* es = std::getenv("FRESCO_SLACK"))
       if (d == 2) slack = std::max(0, std::min(8, std::atoi(es)));
     for (int a = 0; a < d; ++a)
       if (g.nf[a] < g.T[a] + 2 * slack + g.wi + 1 || g.nt[a] > 1024) slack = 0;
+    // the kept order needs the one-level tile sort (at most 16384 tiles)
+    if (g.nbins > 16384 || std::getenv("FRESCO_BIN_RANGES") || std::getenv("FRESCO_BIN_ATOMIC"))
+      slack = 0;
     g.slack = slack;
     g.islack = 0;
     for (int a = 0; a < d; ++a) {
