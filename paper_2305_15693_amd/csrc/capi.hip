@@ -518,7 +518,6 @@ int create_state(fresco_ctx* c) {
   if ((st = dalloc_t(c, &rec, N))) return st;
   bb.rec = rec;
   if ((st = dalloc_t(c, &bb.perm, N))) return st;
-  if (g.slack > 0 && bp.mode == BIN_TILES && (st = dalloc_t(c, &bb.home, N))) return st;
   if ((st = dalloc_t(c, &bb.flag, 1))) return st;
   if ((st = dalloc_t(c, &S->flag_out, 1))) return st;
   HIPCHK(hipMemset(bb.flag, 0, sizeof(int)));
@@ -798,22 +797,18 @@ int build_weights(const Geom& g, const double* s0, const double* w, double k_cut
 }
 
 // ---------------------------------------------------------------- stages
-// optimiser: an optimiser trial step, whose binning keeps each point's tile
-// (b.home) for the trial steps after it; cached: the order of the last binning is
-// kept and the records were written with the trial point (optimiser trial steps
-// that stay within the slack of the binned positions): no binning pass
+// cached: the order of the last binning is kept (optimiser trial steps that stay
+// within the slack of the binned positions): no binning pass, the spreading pass
+// forms the trial point and the records
 template <class R>
-int run_bin_spread_rows(fresco_ctx* c, const R* pos, bool optimiser = false,
-                        bool cached = false) {
+int run_bin_spread_rows(fresco_ctx* c, const R* pos, bool cached = false) {
   State<R>* S = (State<R>*)c->state;
   const Geom& g = c->g;
   hipStream_t st = c->st;
   S->cached_eval = cached;
   if (!cached) {
     StageTimer t(c, FRESCO_STAGE_BIN);
-    BinBuffers b = S->bb;
-    if (!optimiser) b.home = nullptr;  // scattered writes that no one reads
-    launch_bin(g, S->bp, pos, sizeof(R) == 8, b, st);
+    launch_bin(g, S->bp, pos, sizeof(R) == 8, S->bb, st);
   }
   {
     StageTimer t(c, FRESCO_STAGE_SPREAD);
@@ -821,8 +816,25 @@ int run_bin_spread_rows(fresco_ctx* c, const R* pos, bool optimiser = false,
     cs.c = S->str_eval;
     cs.perm = S->bb.perm;
     cs.cmax = S->cmax;
+    KeptSpread<R> ks;
+    if (cached) {
+      const LbfgsVec<R>& v = S->lv;
+      ks.x = v.x;
+      ks.p = v.p;
+      ks.xt = v.xt;
+      ks.perm = S->bb.perm;
+      ks.rec = (Rec<R>*)S->bb.rec;
+      ks.part1 = v.part1;
+      ks.nb = v.nb;
+      ks.max_step = S->lb_opts.max_step;
+      ks.step = &S->lst->step;
+      ks.alpha = &S->lst->alpha;
+      ks.flag = S->bb.flag;
+      ks.drift = &S->lst->drift;
+    }
     for (int r = 0; r < t.reps; ++r)
-      launch_spread<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, cs, st);
+      launch_spread<R>(g, (const Rec<R>*)S->bb.rec, S->bb.start, S->tiles, cs, st,
+                       cached ? &ks : nullptr);
   }
   if (!S->fold_fused) {
     StageTimer t(c, FRESCO_STAGE_FOLD);
@@ -1101,9 +1113,9 @@ int lbfgs_reset_state(fresco_ctx* c) {
 }
 
 // one trial step: evaluation at xt, then the optimiser update; cached: this
-// evaluation keeps the tile order of the last binning (its records were written
-// by the previous update); keep_next: so does the next one, whose records this
-// update writes
+// evaluation keeps the tile order of the last binning (its spreading pass forms
+// the trial point the previous update left out); keep_next: so does the next one,
+// and this update leaves out the trial point pass
 template <class R>
 int lbfgs_trial(fresco_ctx* c, bool cached = false, bool keep_next = false) {
   State<R>* S = (State<R>*)c->state;
@@ -1111,19 +1123,13 @@ int lbfgs_trial(fresco_ctx* c, bool cached = false, bool keep_next = false) {
   // the optimiser's positions are in its internal order, and so are the strengths
   S->str_eval = S->has_str ? S->cint : nullptr;
   S->val_eval = nullptr;
-  if ((st = run_bin_spread_rows<R>(c, S->lv.xt, true, cached))) return st;
+  if ((st = run_bin_spread_rows<R>(c, S->lv.xt, cached))) return st;
   // the update's first pass sums the loss partials into f_trial itself
   LossParts lp;
   if ((st = run_modes_to_grad<R>(c, COL_FUSED, S->lv.xt, nullptr, nullptr, S->lv.gt,
                                  &S->lst->f_trial, &lp)))
     return st;
-  KeptOrder<R> ko;
-  ko.g = c->g;
-  ko.perm = S->bb.perm;
-  ko.home = S->bb.home;
-  ko.rec = (Rec<R>*)S->bb.rec;
-  ko.flag = S->bb.flag;
-  launch_lbfgs_update<R>(S->lv, S->lst, S->lb_opts, c->st, keep_next ? &ko : nullptr, &lp);
+  launch_lbfgs_update<R>(S->lv, S->lst, S->lb_opts, c->st, keep_next, &lp);
   HIPCHK(hipGetLastError());
   return FRESCO_OK;
 }
@@ -1178,7 +1184,7 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   // of it; while that is at most the slack (less a margin for rounding) in grid
   // cells, its footprint starts stay inside the padded tiles of that binning.
   int bin_every = 1;  // trials per binning in a chunk
-  if (g.slack > 0 && S->bb.home && S->bp.mode == BIN_TILES && lo.max_step > 0.0) {
+  if (g.slack > 0 && S->bp.mode == BIN_TILES && lo.max_step > 0.0) {
     double cells = 0.0;  // grid cells per max_step, largest over the axes
     for (int a = 0; a < g.d; ++a) cells = std::max(cells, lo.max_step * g.ufac[a]);
     const double r = std::floor((g.slack - 0.25) / cells) - 2.0;  // last cached trial

@@ -112,7 +112,7 @@ struct alignas(4 * sizeof(R)) Rec {
 // start taken relative to that tile (periodically, within one grid period of
 // it) and stored with the slack offset.  *bad: a coordinate is not finite;
 // *off: a finite footprint start lies beyond the slack (clamped).
-// tile coordinates of a kept tile, 10 bits per axis (a slack needs nt <= 1024)
+// tile coordinates, 10 bits per axis (a slack needs nt <= 1024)
 __host__ __device__ inline uint32_t kept_tile_pack(const uint32_t* t) {
   return t[0] | (t[1] << 10) | (t[2] << 20);
 }
@@ -183,16 +183,25 @@ struct LossParts {
   int* flag_out;
 };
 
-// Where the optimiser's trial point update also writes the records of the next
-// (cached) evaluation: the kept order (slot -> point, slot -> tile) and the
-// outputs.
+// Trial steps of the optimiser that keep the tile order of the last binning:
+// the spreading pass forms the trial point xt = x + alpha p of each of its
+// slots (alpha: the decision's step length, or min(1, max_step / max |p|) from
+// the direction pass's block maxima for a new direction, stored by block 0) and
+// writes the point records in the kept order for itself and the interpolation.
 template <class R>
-struct KeptOrder {
-  Geom g;
-  const int* perm;
-  const uint32_t* home;  // tile coordinates, 10 bits per axis (kept_tile_pack)
-  Rec<R>* rec;
-  int* flag;  // a coordinate is not finite
+struct KeptSpread {
+  const R* x;
+  const R* p;
+  R* xt;
+  const int* perm;         // slot -> point (the last binning)
+  Rec<R>* rec;             // records, written
+  const double* part1;     // block maxima of |p|
+  int nb;
+  double max_step;
+  const int* step;         // the decision (LB_*)
+  double* alpha;           // step length: read, or written for a new direction
+  int* flag;               // a coordinate is not finite
+  int* drift;              // a point beyond the slack
 };
 
 // FP32 kernels evaluate the spreading and interpolation kernels as per-cell
@@ -253,8 +262,6 @@ struct BinBuffers {
   int* tidx0 = nullptr;
   void* rec = nullptr;        // Rec<R>[N], sorted
   int* perm = nullptr;        // sorted position -> caller index (tpos index for BIN_RANGES)
-  uint32_t* home = nullptr;   // tile of each sorted position (BIN_TILES with slack:
-                              // the cached order of the optimiser's trial steps)
   int* flag = nullptr;        // bit 0: a position is not finite
 };
 
@@ -302,7 +309,8 @@ template <class R>
 hipError_t spread_prepare(const Geom& g);
 template <class R>
 void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* tiles,
-                   const Strengths<R>& cs, hipStream_t st);
+                   const Strengths<R>& cs, hipStream_t st,
+                   const KeptSpread<R>* kept = nullptr);
 template <class R>
 void launch_fold(const Geom& g, const R* tiles, R* grid, const FoldTables& ft, hipStream_t st);
 // interpolation of the field v at the binned points into grad (caller's order)

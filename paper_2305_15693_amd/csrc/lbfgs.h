@@ -6,6 +6,9 @@
 namespace fresco {
 
 constexpr int kLbfgsMaxM = 16;
+
+// decision of a trial step
+enum { LB_IDLE = 0, LB_ACCEPT = 1, LB_REJECT = 2, LB_RESTART = 3, LB_INIT = 4 };
 // vector passes: blocks of kLbfgsThreads, enough to fill the chip, at most
 // kLbfgsMaxBlocks so that the one-block reduction of their partials stays cheap
 constexpr int kLbfgsThreads = 256;
@@ -139,13 +142,13 @@ int lbfgs_replay_until_stop(hipStream_t st, LbfgsState* dev, LbfgsState* host, h
 // replays per chunk of an optimiser call
 constexpr int kLbfgsReplayChunk = 8;
 
-// kept: also write the records of the next evaluation in that kept tile order;
+// skip_c: no trial point pass (the next evaluation keeps the tile order of the
+// last binning and forms the trial point in its spreading pass, KeptSpread);
 // loss: the evaluation's loss partials, summed into f_trial by the first pass
 // (else f_trial holds the loss already)
 template <class R>
 void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
-                         hipStream_t st, const KeptOrder<R>* kept = nullptr,
-                         const LossParts* loss = nullptr);
+                         hipStream_t st, bool skip_c = false, const LossParts* loss = nullptr);
 void launch_lbfgs_set_mode(LbfgsState* S, int mode, int target, hipStream_t st);
 template <class R>
 void launch_gather_rows(const R* src, const int* idx, long long n, int d, R* dst, hipStream_t st);

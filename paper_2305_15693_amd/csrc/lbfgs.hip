@@ -26,9 +26,9 @@
 //   small    one block: applies the decision, reduces the partials, stores the
 //            pair when y.s > 0 and solves for u, t (FP64, one wavefront);
 //   pass B   p = -(gamma g + S u - gamma Y t), max |p| per block;
-//   pass C   alpha = min(1, max_step / max|p|), xt = x + alpha p (and, when the
-//            next evaluation keeps the tile order of the last binning, its
-//            point records).
+//   pass C   alpha = min(1, max_step / max|p|), xt = x + alpha p (not run when
+//            the next evaluation keeps the tile order of the last binning: its
+//            spreading pass forms the trial point and its records).
 // (Cross-block steps stay at kernel boundaries: a device-scope fence per block
 // writes back the L2 of its XCD and cost more than the launches it saved.)
 // Vectors are in the working precision; every dot product is accumulated in FP64
@@ -41,7 +41,6 @@
 
 namespace fresco {
 
-enum { LB_IDLE = 0, LB_ACCEPT = 1, LB_REJECT = 2, LB_RESTART = 3, LB_INIT = 4 };
 
 constexpr int kThreads = kLbfgsThreads;
 constexpr int kWaves = kThreads / 64;
@@ -649,34 +648,6 @@ __global__ __launch_bounds__(kThreads) void lb_pass_c_kernel(LbfgsVec<R> v, Lbfg
   for (long long i = nq * U + gid; i < v.n; i += gs) v.xt[i] = v.x[i] + alpha * v.p[i];
 }
 
-// The same trial point, point by point in the kept tile order, with the records
-// of the next evaluation (it keeps that order: its binning is this pass).  A
-// finite point beyond the slack sets the state's drift flag.
-template <class R, int D>
-__global__ __launch_bounds__(kThreads) void lb_pass_c_kept_kernel(LbfgsVec<R> v, LbfgsState* S,
-                                                                  LbfgsOpts o, KeptOrder<R> ko) {
-  __shared__ double sh[kWaves];
-  __shared__ double alpha_s;
-  const int step = S->step;
-  if (step == LB_IDLE) return;
-  const R alpha = pass_c_alpha<R>(v, S, o, step, sh, &alpha_s);
-  const long long gs = (long long)gridDim.x * blockDim.x;
-  bool bad = false, off = false;
-  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < ko.g.N; j += gs) {
-    const long long i = ko.perm[j];
-    R x[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const long long e = i * D + a;
-      x[a] = v.x[e] + alpha * v.p[e];
-      v.xt[e] = x[a];
-    }
-    ko.rec[j] = kept_tile_record<R, D>(ko.g, x, ko.home[j], &bad, &off);
-  }
-  if (bad) atomicOr(ko.flag, 1);
-  if (off && !bad) atomicOr(&S->drift, 1);
-}
-
 // set the mode read by the next decision (host-driven transitions)
 __global__ void lb_set_mode_kernel(LbfgsState* S, int mode, int target) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -694,7 +665,7 @@ __global__ void lb_set_mode_kernel(LbfgsState* S, int mode, int target) {
 
 template <class R>
 void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o,
-                         hipStream_t st, const KeptOrder<R>* kept, const LossParts* loss) {
+                         hipStream_t st, bool skip_c, const LossParts* loss) {
   LossParts lp;
   if (loss) {
     lp = *loss;
@@ -724,9 +695,8 @@ void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o
 #undef LB_SWITCH
 #undef LB_B
 #undef LB_A
-  if (kept && kept->g.d == 2) lb_pass_c_kept_kernel<R, 2><<<v.nb, kThreads, 0, st>>>(v, S, o, *kept);
-  else if (kept) lb_pass_c_kept_kernel<R, 3><<<v.nb, kThreads, 0, st>>>(v, S, o, *kept);
-  else lb_pass_c_kernel<R><<<v.nb, kThreads, 0, st>>>(v, S, o, vec);
+  // skip_c: the next evaluation forms the trial point itself (kept tile order)
+  if (!skip_c) lb_pass_c_kernel<R><<<v.nb, kThreads, 0, st>>>(v, S, o, vec);
 }
 
 void launch_lbfgs_set_mode(LbfgsState* S, int mode, int target, hipStream_t st) {
@@ -766,7 +736,7 @@ void launch_scatter_rows(const R* src, const int* idx, long long n, int d, R* ds
 
 #define FRESCO_LB_INST(R)                                                                       \
   template void launch_lbfgs_update<R>(const LbfgsVec<R>&, LbfgsState*, const LbfgsOpts&,       \
-                                       hipStream_t, const KeptOrder<R>*, const LossParts*);     \
+                                       hipStream_t, bool, const LossParts*);                    \
   template void launch_gather_rows<R>(const R*, const int*, long long, int, R*, hipStream_t);   \
   template void launch_scatter_rows<R>(const R*, const int*, long long, int, R*, hipStream_t);
 FRESCO_LB_INST(float)

@@ -48,11 +48,13 @@
 // derivative at the support edge).  One workgroup per tile stages its padded
 // field tile in LDS.
 #include <cmath>
+#include <cstring>
 #include <type_traits>
 #include <utility>
 
 #include "common.h"
 #include "kernels.h"
+#include "lbfgs.h"
 
 namespace fresco {
 
@@ -80,7 +82,6 @@ template void launch_fill<double>(double*, long long, double, hipStream_t);
 struct PointBin {
   uint32_t bin;
   uint32_t cell;
-  uint32_t tc;  // tile coordinates (kept_tile_pack)
   double t[3];
 };
 
@@ -115,7 +116,6 @@ __device__ __forceinline__ PointBin bin_point_d(const Geom& g, const R* r, bool*
     pb.cell |= loc << (8 * a);
   }
   pb.bin = tile[0] + (uint32_t)g.nt[0] * (tile[1] + (uint32_t)g.nt[1] * tile[2]);
-  pb.tc = kept_tile_pack(tile);
   return pb;
 }
 // g.d is uniform: both branches keep every index a compile-time constant
@@ -219,7 +219,7 @@ __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, uint32_t b
                                    const uint32_t* __restrict__ kr,
                                    const uint32_t* __restrict__ H,
                                    const long long* __restrict__ start, Rec<R>* __restrict__ rec,
-                                   int* __restrict__ perm, uint32_t* __restrict__ home) {
+                                   int* __restrict__ perm) {
   uint32_t blk;
   const long long q = xcd_point_block(blockIdx.x, bpc, &blk);
   const long long i = q * 256 + threadIdx.x;
@@ -236,7 +236,6 @@ __global__ void bin_scatter_kernel(Geom g, const R* __restrict__ pos, uint32_t b
   o.cell = pb.cell;
   rec[dst] = o;
   perm[dst] = (int)i;
-  if (home) home[dst] = pb.tc;
 }
 
 // Slot of point i in the range order (first level of BIN_RANGES); 256-thread
@@ -593,11 +592,11 @@ void launch_bin(const Geom& g, const BinPlan& bp, const void* pos, bool f64, Bin
       if (f64)
         bin_scatter_kernel<double><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
             g, (const double*)pos, bpc, bp.nblk, b.kr, b.H, b.start, (Rec<double>*)b.rec,
-            b.perm, b.home);
+            b.perm);
       else
         bin_scatter_kernel<float><<<xcd_grid(bp.nblk, bp.chunk), 256, 0, st>>>(
             g, (const float*)pos, bpc, bp.nblk, b.kr, b.H, b.start, (Rec<float>*)b.rec,
-            b.perm, b.home);
+            b.perm);
     } else {
       scan_bins_kernel<<<1, 1024, 0, st>>>(b.count, bp.nkeys, b.kstart);
       if (f64) range_finish<double>(g, bp, (const double*)src, b, st);
@@ -665,11 +664,15 @@ __device__ __forceinline__ void add_row_pairs(uint32_t* acc, int rb, const uint3
 // STR: point strengths c_j (any sign), read through the permutation; every cell
 // is then one 64-bit two's-complement fixed-point word (in FP32 too), which adds
 // signed contributions exactly; the scale also covers max |c|.
-template <class R, int D, int W, bool STR>
+// KEPT: an optimiser trial step that keeps the tile order of the last binning
+// (kp): the block first forms the trial point and the record of each of its
+// slots (kept_tile_record, relative to this tile), writes both, and spreads
+// from the records it wrote.
+template <class R, int D, int W, bool STR, bool KEPT = false>
 __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
                               const long long* __restrict__ start, R* __restrict__ tiles,
                               const R* __restrict__ cstr, const int* __restrict__ perm,
-                              double cmax) {
+                              double cmax, KeptSpread<R> kp) {
   constexpr bool F32 = sizeof(R) == 4 && !STR;  // 32-bit cells added in pairs
   extern __shared__ unsigned long long smem_u64[];
   uint32_t* acc32 = reinterpret_cast<uint32_t*>(smem_u64);
@@ -677,11 +680,58 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
   const long long bin = blockIdx.x;
   const int E0 = g.E[0], E1 = g.E[1], E2 = (D == 3) ? g.E[2] : 1;
   const int ncell = E0 * E1 * E2;
+  R alpha = R(0);
+  if constexpr (KEPT) {
+    // step length, as the trial point pass takes it (every block; block 0
+    // stores a new direction's)
+    __shared__ double ksh[16];
+    __shared__ double ka;
+    const int step = *kp.step;
+    if (step == LB_REJECT || step == LB_IDLE) {
+      if (threadIdx.x == 0) ka = *kp.alpha;
+    } else {
+      double pm = 0.0;
+      for (int b = threadIdx.x; b < kp.nb; b += blockDim.x) pm = fmax(pm, kp.part1[b]);
+      for (int off = 32; off > 0; off >>= 1) pm = fmax(pm, __shfl_down(pm, off, 64));
+      if ((threadIdx.x & 63) == 0) ksh[threadIdx.x >> 6] = pm;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = fmax(t, ksh[w]);
+        const double a = (t > kp.max_step) ? kp.max_step / t : 1.0;
+        ka = a;
+        if (blockIdx.x == 0) *kp.alpha = a;
+      }
+    }
+    __syncthreads();
+    alpha = (R)ka;
+  }
   const long long s = start[bin], e = start[bin + 1];
   R* __restrict__ out = tiles + bin * (long long)ncell;
   if (e == s) {
     for (int c = threadIdx.x; c < ncell; c += blockDim.x) out[c] = R(0);
     return;  // uniform across the block
+  }
+  if constexpr (KEPT) {
+    int tcv[3];
+    tile_coords(g, bin, tcv);
+    const uint32_t tu[3] = {(uint32_t)tcv[0], (uint32_t)tcv[1], (uint32_t)tcv[2]};
+    const uint32_t tc = kept_tile_pack(tu);
+    bool bad = false, off = false;
+    for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
+      const long long i = kp.perm[j];
+      R xv[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const long long q = i * D + a;
+        xv[a] = kp.x[q] + alpha * kp.p[q];
+        kp.xt[q] = xv[a];
+      }
+      kp.rec[j] = kept_tile_record<R, D>(g, xv, tc, &bad, &off);
+    }
+    if (bad) atomicOr(kp.flag, 1);
+    if (off && !bad) atomicOr(kp.drift, 1);
+    __syncthreads();  // the records are read back below by other threads
   }
   // Fixed-point scale from a bound on the number of points whose footprints
   // cover one cell (each contributes at most 1): the tile's footprint starts are
@@ -1177,9 +1227,12 @@ hipError_t spread_prepare(const Geom& g) {
   do {                                                          \
     if (g.d == 2) {                                             \
       lds((const void*)spread_kernel<R, 2, W, false>, sl);      \
+      lds((const void*)spread_kernel<R, 2, W, false, true>, sl); \
       lds((const void*)interp_kernel<R, 2, W>, il);             \
       if (slc <= kMaxSpreadLds)                                 \
         lds((const void*)spread_kernel<R, 2, W, true>, slc);    \
+      if (slc <= kMaxSpreadLds)                                 \
+        lds((const void*)spread_kernel<R, 2, W, true, true>, slc); \
     } else {                                                    \
       lds((const void*)spread_kernel<R, 3, W, false>, sl);      \
       lds((const void*)interp_kernel<R, 3, W>, il);             \
@@ -1196,24 +1249,34 @@ hipError_t spread_prepare(const Geom& g) {
 
 template <class R>
 void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* tiles,
-                   const Strengths<R>& cs, hipStream_t st) {
+                   const Strengths<R>& cs, hipStream_t st, const KeptSpread<R>* kept) {
   const bool str = cs.c != nullptr;
   const size_t lds = spread_lds_bytes<R>(g, str);
   const int threads = 512;  // (2D: 26.7 -> 23.5 us against 256)
+  KeptSpread<R> kp;
+  std::memset(&kp, 0, sizeof(kp));
+  if (kept) kp = *kept;
+  // the kept tile order exists in 2D only (a slack)
 #define SP(W)                                                                                 \
   do {                                                                                        \
-    if (g.d == 2 && !str)                                                                     \
+    if (g.d == 2 && kept && !str)                                                             \
+      spread_kernel<R, 2, W, false, true><<<(unsigned)g.nbins, threads, lds, st>>>(          \
+          g, rec, start, tiles, nullptr, nullptr, 1.0, kp);                                   \
+    else if (g.d == 2 && kept)                                                                \
+      spread_kernel<R, 2, W, true, true><<<(unsigned)g.nbins, threads, lds, st>>>(           \
+          g, rec, start, tiles, cs.c, cs.perm, cs.cmax, kp);                                  \
+    else if (g.d == 2 && !str)                                                                \
       spread_kernel<R, 2, W, false><<<(unsigned)g.nbins, threads, lds, st>>>(                \
-          g, rec, start, tiles, nullptr, nullptr, 1.0);                                       \
+          g, rec, start, tiles, nullptr, nullptr, 1.0, kp);                                   \
     else if (g.d == 2)                                                                        \
       spread_kernel<R, 2, W, true><<<(unsigned)g.nbins, threads, lds, st>>>(                 \
-          g, rec, start, tiles, cs.c, cs.perm, cs.cmax);                                      \
+          g, rec, start, tiles, cs.c, cs.perm, cs.cmax, kp);                                  \
     else if (!str)                                                                            \
       spread_kernel<R, 3, W, false><<<(unsigned)g.nbins, threads, lds, st>>>(                \
-          g, rec, start, tiles, nullptr, nullptr, 1.0);                                       \
+          g, rec, start, tiles, nullptr, nullptr, 1.0, kp);                                   \
     else                                                                                      \
       spread_kernel<R, 3, W, true><<<(unsigned)g.nbins, threads, lds, st>>>(                 \
-          g, rec, start, tiles, cs.c, cs.perm, cs.cmax);                                      \
+          g, rec, start, tiles, cs.c, cs.perm, cs.cmax, kp);                                  \
   } while (0)
   FRESCO_W_SWITCH(g.w, SP)
 #undef SP
@@ -1375,9 +1438,11 @@ template size_t interp_lds_bytes<double>(const Geom&);
 template hipError_t spread_prepare<float>(const Geom&);
 template hipError_t spread_prepare<double>(const Geom&);
 template void launch_spread<float>(const Geom&, const Rec<float>*, const long long*, float*,
-                                   const Strengths<float>&, hipStream_t);
+                                   const Strengths<float>&, hipStream_t,
+                                   const KeptSpread<float>*);
 template void launch_spread<double>(const Geom&, const Rec<double>*, const long long*, double*,
-                                    const Strengths<double>&, hipStream_t);
+                                    const Strengths<double>&, hipStream_t,
+                                    const KeptSpread<double>*);
 template void launch_fold<float>(const Geom&, const float*, float*, const FoldTables&,
                                  hipStream_t);
 template void launch_fold<double>(const Geom&, const double*, double*, const FoldTables&,
