@@ -712,27 +712,7 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
     for (int c = threadIdx.x; c < ncell; c += blockDim.x) out[c] = R(0);
     return;  // uniform across the block
   }
-  if constexpr (KEPT) {
-    int tcv[3];
-    tile_coords(g, bin, tcv);
-    const uint32_t tu[3] = {(uint32_t)tcv[0], (uint32_t)tcv[1], (uint32_t)tcv[2]};
-    const uint32_t tc = kept_tile_pack(tu);
-    bool bad = false, off = false;
-    for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
-      const long long i = kp.perm[j];
-      R xv[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const long long q = i * D + a;
-        xv[a] = kp.x[q] + alpha * kp.p[q];
-        kp.xt[q] = xv[a];
-      }
-      kp.rec[j] = kept_tile_record<R, D>(g, xv, tc, &bad, &off);
-    }
-    if (bad) atomicOr(kp.flag, 1);
-    if (off && !bad) atomicOr(kp.drift, 1);
-    __syncthreads();  // the records are read back below by other threads
-  }
+
   // Fixed-point scale from a bound on the number of points whose footprints
   // cover one cell (each contributes at most 1): the tile's footprint starts are
   // counted per column over the last two axes (2D: exactly per start cell), and
@@ -749,21 +729,67 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
         F32 ? acc32 + (ncell + 2) : reinterpret_cast<uint32_t*>(acc64 + (ncell + 2));
     for (int c = threadIdx.x; c < Ta * Tb; c += blockDim.x) cnt[c] = 0u;
     __syncthreads();
-    // four cells loaded per thread before the first count
-    for (long long jb = s + threadIdx.x; jb < e; jb += 4LL * blockDim.x) {
-      uint32_t cl[4];
+    auto count_cell = [&](uint32_t cl) {
+      const int la = (D == 3) ? (int)((cl >> 8) & 0xff) : (int)(cl & 0xff);
+      const int lb = (D == 3) ? (int)((cl >> 16) & 0xff) : (int)((cl >> 8) & 0xff);
+      atomicAdd(cnt + lb * Ta + la, 1u);
+    };
+    if constexpr (KEPT) {
+      // the trial point and record of every slot of the tile, counted as they
+      // are formed (the records are written for the spreading below, the
+      // interpolation and the next update)
+      int tcv[3];
+      tile_coords(g, bin, tcv);
+      const uint32_t tu[3] = {(uint32_t)tcv[0], (uint32_t)tcv[1], (uint32_t)tcv[2]};
+      const uint32_t tc = kept_tile_pack(tu);
+      bool bad = false, off = false;
+      // two slots per thread and trip, every load of both issued before the
+      // first use (the loads are a chain: slot -> point -> position)
+      const long long bd = blockDim.x;
+      for (long long j0 = s + threadIdx.x; j0 < e; j0 += 2 * bd) {
+        const long long j1 = j0 + bd;
+        const bool has1 = j1 < e;
+        const long long i0 = kp.perm[j0];
+        const long long i1 = has1 ? kp.perm[j1] : i0;
+        R x0[D], p0[D], x1[D], p1[D];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const long long j = jb + (long long)u * blockDim.x;
-        cl[u] = (j < e) ? rec[j].cell : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (jb + (long long)u * blockDim.x < e) {
-          const int la = (D == 3) ? (int)((cl[u] >> 8) & 0xff) : (int)(cl[u] & 0xff);
-          const int lb = (D == 3) ? (int)((cl[u] >> 16) & 0xff) : (int)((cl[u] >> 8) & 0xff);
-          atomicAdd(cnt + lb * Ta + la, 1u);
+        for (int a = 0; a < D; ++a) {
+          x0[a] = kp.x[i0 * D + a];
+          p0[a] = kp.p[i0 * D + a];
+          x1[a] = kp.x[i1 * D + a];
+          p1[a] = kp.p[i1 * D + a];
         }
+        R v0[D], v1[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          v0[a] = x0[a] + alpha * p0[a];
+          v1[a] = x1[a] + alpha * p1[a];
+          kp.xt[i0 * D + a] = v0[a];
+          if (has1) kp.xt[i1 * D + a] = v1[a];
+        }
+        const Rec<R> r0 = kept_tile_record<R, D>(g, v0, tc, &bad, &off);
+        kp.rec[j0] = r0;
+        count_cell(r0.cell);
+        if (has1) {
+          const Rec<R> r1 = kept_tile_record<R, D>(g, v1, tc, &bad, &off);
+          kp.rec[j1] = r1;
+          count_cell(r1.cell);
+        }
+      }
+      if (bad) atomicOr(kp.flag, 1);
+      if (off && !bad) atomicOr(kp.drift, 1);
+    } else {
+      // four cells loaded per thread before the first count
+      for (long long jb = s + threadIdx.x; jb < e; jb += 4LL * blockDim.x) {
+        uint32_t cl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long j = jb + (long long)u * blockDim.x;
+          cl[u] = (j < e) ? rec[j].cell : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (jb + (long long)u * blockDim.x < e) count_cell(cl[u]);
       }
     }
     __syncthreads();
