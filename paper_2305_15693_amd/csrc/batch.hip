@@ -754,7 +754,7 @@ int batch_lbfgs_setup(fresco_batch_ctx* c, int m) {
   v.m = m;
   if ((st = balloc(c, &v.part0, (4 * (size_t)kLbfgsMaxM + 1) * nb))) return st;
   if ((st = balloc(c, &v.part1, (size_t)nb))) return st;
-  if (!c->lst && (st = balloc(c, &c->lst, 1))) return st;
+  if (!c->lst && (st = balloc(c, &c->lst, 2))) return st;  // the state and pass A's snapshot
   if (!c->lst_host) BHIP(hipHostMalloc((void**)&c->lst_host, 2 * sizeof(LbfgsState)));
   for (int i = 0; i < 2; ++i)
     if (!c->lb_ev[i]) BHIP(hipEventCreateWithFlags(&c->lb_ev[i], hipEventDisableTiming));

@@ -1075,7 +1075,7 @@ int lbfgs_alloc(fresco_ctx* c, int m) {
   v.m = m;
   if ((st = dalloc_t(c, &v.part0, (4 * (size_t)kLbfgsMaxM + 1) * nb))) return st;
   if ((st = dalloc_t(c, &v.part1, (size_t)nb))) return st;
-  if ((st = dalloc_t(c, &S->lst, 1))) return st;
+  if ((st = dalloc_t(c, &S->lst, 2))) return st;  // the state and pass A's snapshot
   if ((st = dalloc_t(c, &S->perm0, c->g.N))) return st;
   if (!S->lst_host) HIPCHK(hipHostMalloc((void**)&S->lst_host, 2 * sizeof(LbfgsState)));
   for (int i = 0; i < 2; ++i)

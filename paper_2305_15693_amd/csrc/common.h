@@ -153,12 +153,15 @@ __device__ __forceinline__ Rec<R> kept_tile_record(const Geom& g, const R* x, ui
   return o;
 }
 
-// sum of n partials in a fixed order (one block of 256 threads; s: 256 doubles)
+// sum of n partials in a fixed order by the first 256 threads of a block of 256
+// or more (s: 256 doubles); every thread gets the sum
 __device__ __forceinline__ double block_sum_256(const double* __restrict__ part, long long n,
                                                 double* s) {
-  double v = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 256) v += part[i];
-  s[threadIdx.x] = v;
+  if (threadIdx.x < 256) {
+    double v = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256) v += part[i];
+    s[threadIdx.x] = v;
+  }
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];

@@ -9,15 +9,17 @@ constexpr int kLbfgsMaxM = 16;
 
 // decision of a trial step
 enum { LB_IDLE = 0, LB_ACCEPT = 1, LB_REJECT = 2, LB_RESTART = 3, LB_INIT = 4 };
-// vector passes: blocks of kLbfgsThreads, enough to fill the chip, at most
-// kLbfgsMaxBlocks so that the one-block reduction of their partials stays cheap
-constexpr int kLbfgsThreads = 256;
-constexpr int kLbfgsMaxBlocks = 1024;
-// at least 16 elements per thread (four 16-byte packs in FP32): on the 2e6-element
-// vectors of the 2D workload 489 blocks ran the optimiser update 4% faster than
-// 977 (about one pack per thread and step, more block partials to reduce)
+// vector passes: blocks of kLbfgsThreads; at least 16 elements per thread, but
+// one block per CU of the chip (256) while a thread keeps 4 or more; at most
+// kLbfgsMaxBlocks.  Every block of pass B reduces the partials of all blocks of
+// pass A, with eight waves: 33 rows of 256 partials (m = 8, the 2D workload) in
+// one round of loads.
+constexpr int kLbfgsThreads = 512;
+constexpr int kLbfgsMaxBlocks = 512;
 inline int lbfgs_blocks(long long n) {
   long long nb = (n + 16LL * kLbfgsThreads - 1) / (16LL * kLbfgsThreads);
+  const long long fill = (n + 4LL * kLbfgsThreads - 1) / (4LL * kLbfgsThreads);
+  if (nb < fill && nb < 256) nb = fill < 256 ? fill : 256;
   if (nb > kLbfgsMaxBlocks) nb = kLbfgsMaxBlocks;
   if (nb < 1) nb = 1;
   return (int)nb;
@@ -25,7 +27,8 @@ inline int lbfgs_blocks(long long n) {
 
 inline long long lbfgs_slot_stride(long long n) { return (n + 3) / 4 * 4; }
 
-// Lives in device memory; the host reads it back between batches of replays.
+// Lives in device memory (followed by the snapshot the direction pass reads); the
+// host reads it back between batches of replays.
 struct LbfgsState {
   int mode;       // 0 normal, 4 = first evaluation of a call
   int step;       // decision of the last replay (idle / accept / reject / restart / init)
@@ -54,6 +57,10 @@ struct LbfgsState {
   double YG[kLbfgsMaxM];  // y_j . g
   double SY[kLbfgsMaxM * kLbfgsMaxM];  // [i][j] = s_i . y_j (ring slots)
   double YY[kLbfgsMaxM * kLbfgsMaxM];  // [i][j] = y_i . y_j
+  // [i][j] = (R^-1)_ij for pair i not newer than pair j (ring slots), R the upper
+  // triangle of S^T Y in chronological order; extended by one column per stored
+  // pair
+  double RI[kLbfgsMaxM * kLbfgsMaxM];
 };
 
 struct LbfgsOpts {
@@ -142,6 +149,8 @@ int lbfgs_replay_until_stop(hipStream_t st, LbfgsState* dev, LbfgsState* host, h
 // replays per chunk of an optimiser call
 constexpr int kLbfgsReplayChunk = 8;
 
+// S: two states in device memory, S[0] the state and S[1] the snapshot of it that
+// the first pass leaves for the second (whose block 0 rewrites S[0]).
 // skip_c: no trial point pass (the next evaluation keeps the tile order of the
 // last binning and forms the trial point in its spreading pass, KeptSpread);
 // loss: the evaluation's loss partials, summed into f_trial by the first pass

@@ -14,7 +14,7 @@
 // S^T Y, D its diagonal and gamma = s.y / y.y of the newest pair.  The m x m
 // products S^T Y and Y^T Y are kept in the state and updated with the new pair.
 //
-// Per replay, after the loss/gradient evaluation at the trial point xt, four
+// Per replay, after the loss/gradient evaluation at the trial point xt, three
 // kernels:
 //   pass A   decision: Armijo test f(xt) <= f(x) + c1 alpha g.p -> ACCEPT or
 //            REJECT (REJECT: alpha *= shrink; after max_backtracks rejections
@@ -22,10 +22,13 @@
 //            failure sets the failure flag), computed by every block from the
 //            state; on ACCEPT s = alpha p, y = g(xt) - g(x) into the ring,
 //            x = xt, g = g(xt), and the new dot products s_j.y, y_j.y, s_j.g,
-//            y_j.g, g.g as block partials;
-//   small    one block: applies the decision, reduces the partials, stores the
-//            pair when y.s > 0 and solves for u, t (FP64, one wavefront);
-//   pass B   p = -(gamma g + S u - gamma Y t), max |p| per block;
+//            y_j.g, g.g as block partials; block 0 leaves a snapshot of the
+//            state with f(xt);
+//   pass B   the small step, in every block on its LDS copy of the snapshot:
+//            applies the decision, reduces the partials, stores the pair when
+//            y.s > 0 and solves for u, t (FP64, one wavefront), block 0
+//            writing the new state back; then p = -(gamma g + S u - gamma Y t),
+//            max |p| per block;
 //   pass C   alpha = min(1, max_step / max|p|), xt = x + alpha p (not run when
 //            the next evaluation keeps the tile order of the last binning: its
 //            spreading pass forms the trial point and its records).
@@ -48,22 +51,22 @@ constexpr int kWaves = kThreads / 64;
 #define GRID_LOOP(i, n) \
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
 
-// Reduce CNT per-thread values across the block (fixed order) and write value c
-// to part[row(c) * nb + blockIdx.x] (not written when row(c) < 0).
-template <int CNT, class Row>
+// Reduce CNT per-thread values across a block of NW waves (fixed order) and
+// write value c to part[row(c) * nb + blockIdx.x] (not written when row(c) < 0).
+template <int CNT, int NW, class Row>
 __device__ __forceinline__ void block_partials(const double* v, double* part, int nb,
-                                               double* sh /* [CNT][kWaves] */, Row row) {
+                                               double* sh /* [CNT][NW] */, Row row) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < CNT; ++c) {
     double x = v[c];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
-    if (lane == 0) sh[c * kWaves + wave] = x;
+    if (lane == 0) sh[c * NW + wave] = x;
   }
   __syncthreads();
   for (int c = threadIdx.x; c < CNT; c += blockDim.x) {
     double t = 0.0;
-    for (int w = 0; w < kWaves; ++w) t += sh[c * kWaves + w];
+    for (int w = 0; w < NW; ++w) t += sh[c * NW + w];
     const int r = row(c);
     if (r >= 0) part[(long long)r * nb + blockIdx.x] = t;
   }
@@ -80,7 +83,7 @@ __device__ __forceinline__ int lb_decided_step(const LbfgsState* S, const LbfgsO
   if (S->nbt + 1 > o.max_backtracks) return (S->k > 0 || !S->restarted) ? LB_RESTART : LB_IDLE;
   return LB_REJECT;
 }
-__device__ void lb_decide(LbfgsState* S, const LbfgsOpts& o) {
+__device__ __forceinline__ void lb_decide(LbfgsState* S, const LbfgsOpts& o) {
   const int step = lb_decided_step(S, o, S->f_trial);
   // an evaluation counts when it can inform a decision: replays that run after
   // the call has stopped (target reached, converged, failed) are not counted
@@ -107,90 +110,74 @@ __device__ void lb_decide(LbfgsState* S, const LbfgsOpts& o) {
   S->step = step;
 }
 
-// ---------------------------------------------------------------- pass A
-__device__ __forceinline__ void lb_small_update(LbfgsState* S, const LbfgsOpts& o,
-                                                const double* red, int step, long long n,
-                                                int* cs);
-__device__ __forceinline__ void lb_small_direction(LbfgsState* S, const LbfgsOpts& o,
-                                                   const int* cs);
+// ---------------------------------------------------------------- small step
+// LDS writes of this wavefront visible to its later LDS reads by other lanes:
+// the wave's LDS accesses are performed in order once issued; the fence waits
+// for them and keeps the compiler from moving accesses across.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
 
-// One block after pass A: apply the decision, reduce the partials, update the
-// pair products (one thread) and solve for the direction coefficients (one
-// wavefront), on an LDS copy of the state (dependent global loads would
-// dominate otherwise).
-__global__ void lb_small_kernel(LbfgsState* Sg, LbfgsOpts o, const double* part, int nb,
-                                long long n) {
-  __shared__ double red[4 * kLbfgsMaxM + 1];
-  __shared__ LbfgsState sh;
-  __shared__ int cs[kLbfgsMaxM];
+template <int MM>
+__device__ __forceinline__ void lb_small_wave(LbfgsState* S, const LbfgsOpts& o,
+                                              const double* red, long long n);
+
+// Small step, run by every block of pass B on its LDS copy of the snapshot that
+// pass A left (block 0 rewrites the state itself while the other blocks may still
+// be reading, so none of them reads it): reduce the pass A partials, then on one
+// wavefront apply the decision, update the pair products and solve for the
+// direction coefficients.  Every block computes the same values in the same
+// order, so no block waits for another and no one-block launch sits between the
+// two streaming passes.
+template <int MM>
+__device__ __forceinline__ void lb_small_step(const LbfgsState* __restrict__ snap,
+                                              const LbfgsOpts& o, const double* __restrict__ part,
+                                              int nb, long long n, LbfgsState& ss,
+                                              double* red) {
   static_assert(sizeof(LbfgsState) % 4 == 0, "state copied as 32-bit words");
   constexpr int kWords = (int)(sizeof(LbfgsState) / 4);
-  const int m = o.m;
-  // value c is reduced by wave c mod (waves): lane l sums the partials l,
-  // l + 64, ... (nb <= 1024: at most 16).  With at most three values per wave
-  // their loads are issued before the state copy, so that both wait on one
-  // memory round (they are used only when the decision accepts)
+  const int nv = 4 * o.m + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nw = (int)(blockDim.x >> 6);
-  constexpr int kU = kLbfgsMaxBlocks / 64;
-  const bool fast = 4 * m + 1 <= 3 * nw;
-  double v[3][kU];
-  if (fast) {
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int c = wave + r * nw;
-      const double* pc = part + (long long)c * nb;
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int b = lane + 64 * u;
-        v[r][u] = (c < 4 * m + 1 && b < nb) ? pc[b] : 0.0;
-      }
-    }
-  }
   for (int i = threadIdx.x; i < kWords; i += blockDim.x)
-    reinterpret_cast<uint32_t*>(&sh)[i] = reinterpret_cast<const uint32_t*>(Sg)[i];
-  if (fast) {
-    // reduced whatever the decision (a rejection or restart does not read them)
+    reinterpret_cast<uint32_t*>(&ss)[i] = reinterpret_cast<const uint32_t*>(snap)[i];
+  // value c is reduced by wave c mod kWaves: lane l sums the partials l, l + 64,
+  // ... in index order, then the wave's shuffle tree.  Five values of a wave and
+  // four of each value's loads per round: one round for the 33 values of m = 8
+  // over 256 partials.  Reduced whatever the decision (a rejection or restart
+  // does not read them).
+  constexpr int kR = 5, kU = 4;
+  for (int c0 = wave; c0 < nv; c0 += kR * kWaves) {
+    double t[kR];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int c = wave + r * nw;
-      double t = 0.0;
+    for (int r = 0; r < kR; ++r) t[r] = 0.0;
+    for (int u0 = 0; 64 * u0 < nb; u0 += kU) {
+      double w[kR][kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) t += v[r][u];
-      for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
-      if (lane == 0 && c < 4 * m + 1) red[c] = t;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) lb_decide(&sh, o);
-  __syncthreads();
-  const int step = sh.step;
-  if (step == LB_ACCEPT || step == LB_INIT) {
-    if (!fast) {
-      for (int c = wave; c < 4 * m + 1; c += nw) {
-        const double* pc = part + (long long)c * nb;
-        double w[kU];
+      for (int r = 0; r < kR; ++r) {
+        const int c = c0 + r * kWaves;
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-          const int b = lane + 64 * u;
-          w[u] = (b < nb) ? pc[b] : 0.0;
+          const int b = lane + 64 * (u0 + u);
+          w[r][u] = (c < nv && b < nb) ? part[(long long)c * nb + b] : 0.0;
         }
-        double t = 0.0;
-#pragma unroll
-        for (int u = 0; u < kU; ++u) t += w[u];
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
-        if (lane == 0) red[c] = t;
       }
+#pragma unroll
+      for (int r = 0; r < kR; ++r)
+#pragma unroll
+        for (int u = 0; u < kU; ++u) t[r] += w[r][u];
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const int c = c0 + r * kWaves;
+      double x = t[r];
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0 && c < nv) red[c] = x;
     }
   }
   __syncthreads();
-  const bool dir = step == LB_ACCEPT || step == LB_INIT || step == LB_RESTART;
-  if (threadIdx.x == 0 && dir) lb_small_update(&sh, o, red, step, n, cs);
+  if (threadIdx.x < 64) lb_small_wave<MM>(&ss, o, red, n);
   __syncthreads();
-  if (threadIdx.x < 64 && dir) lb_small_direction(&sh, o, cs);
-  __syncthreads();
-  for (int i = threadIdx.x; i < kWords; i += blockDim.x)
-    reinterpret_cast<uint32_t*>(Sg)[i] = reinterpret_cast<const uint32_t*>(&sh)[i];
 }
 
 // ------------------------------------------------------- packed access
@@ -218,11 +205,11 @@ constexpr int pack_u() {
   constexpr int b = MM <= 8 ? B : B / 2;
   return b / (int)sizeof(R) > 0 ? b / (int)sizeof(R) : 1;
 }
-// Pass A holds 4m + 5 FP64 accumulators besides the loaded slots: it reads single
-// elements (packs took more registers and measured no faster), within 128
-// registers up to m = 8 (four waves per SIMD, so that 1024 blocks of four waves
-// are resident at once); passes B and C take 16-byte packs.
-constexpr int kPackBytesA = 4;
+// Every pass moves 16-byte packs (half that beyond m = 8).  Pass A holds 4m + 5
+// FP64 accumulators besides the loaded packs: up to m = 8 it takes up to 168
+// registers (three waves per SIMD); with single elements it fitted four waves per
+// SIMD in 128 registers but ran 5% slower (fewer bytes in flight per wave).
+constexpr int kPackBytesA = 16;
 constexpr int kPackBytesBC = 16;
 
 // Pass A on elements [i, i + U).  The old pairs are read by age (age a sits in
@@ -323,7 +310,7 @@ __device__ __forceinline__ void pass_a_run(const LbfgsVec<R>& v, int head, int k
   // pair's four products at slot ns (zeros when not accepting; not written when
   // an old pair's age already covers ns), g.g at 4m; every row is written once
   // (ages without a pair hold zeros)
-  block_partials<4 * NA + 5>(acc, v.part0, v.nb, sh, [&](int c) {
+  block_partials<4 * NA + 5, kWaves>(acc, v.part0, v.nb, sh, [&](int c) {
     if (c < 4 * NA) return (c / NA) * MM + (head - c % NA + MM) % MM;
     if (c < 4 * NA + 4) return NA == MM ? -1 : (c - 4 * NA) * MM + ns;
     return 4 * MM;
@@ -335,22 +322,37 @@ __device__ __forceinline__ void pass_a_run(const LbfgsVec<R>& v, int head, int k
 // loss finish (every block, for its decision; block 0 stores f_trial and hands
 // over the flag); else f_trial holds the loss.
 template <class R, int MM>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MM <= 8 ? 4 : 1))) void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o, int vec, LossParts loss) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MM <= 8 ? 3 : 2))) void lb_pass_a_kernel(LbfgsVec<R> v, LbfgsState* S, LbfgsOpts o, int vec, LossParts loss) {
   __shared__ double sh[(4 * MM + 5) * kWaves];
   double f;
   if (loss.n >= 0) {
-    __shared__ double s256[kThreads];
-    static_assert(kThreads == 256, "the loss partials are summed as by the 256-thread finish");
+    // summed as by the 256-thread loss finish
+    __shared__ double s256[256];
     const double a = block_sum_256(loss.part, loss.n, s256);
     const double b = (loss.n2 > 0) ? block_sum_256(loss.part2, loss.n2, s256) : 0.0;
     f = (loss.n2 > 0) ? a + loss.w2 * b : a;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      S->f_trial = f;
       *loss.flag_out = *loss.flag;
       *loss.flag = 0;
     }
   } else {
     f = S->f_trial;
+  }
+  if (blockIdx.x == 0) {
+    // the snapshot S[1] that every block of pass B starts from, with this
+    // evaluation's loss as f_trial (pass B's block 0 writes the state back)
+    static_assert(sizeof(LbfgsState) % 4 == 0, "state copied as 32-bit words");
+    constexpr int kWords = (int)(sizeof(LbfgsState) / 4);
+    constexpr int kF = (int)(offsetof(LbfgsState, f_trial) / 4);
+    const unsigned long long fb = (unsigned long long)__double_as_longlong(f);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(S);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(S + 1);
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) {
+      uint32_t w = src[i];
+      if (i == kF) w = (uint32_t)fb;
+      if (i == kF + 1) w = (uint32_t)(fb >> 32);
+      dst[i] = w;
+    }
   }
   const int step = lb_decided_step(S, o, f);
   if (step != LB_ACCEPT && step != LB_INIT) return;  // uniform: before any barrier
@@ -367,55 +369,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MM <= 
   }
 }
 
-// Serial part of the small step (one thread, state in LDS): the new pair's
-// products, and the chronological slots cs[0] (oldest) .. cs[k-1] (newest).
-__device__ __forceinline__ void lb_small_update(LbfgsState* S, const LbfgsOpts& o,
-                                                const double* red, int step, long long n,
-                                                int* cs) {
-  const int m = o.m;
-  if (step != LB_RESTART) {
-    S->gg = red[4 * m];
-    for (int j = 0; j < m; ++j) {
-      S->SG[j] = red[2 * m + j];
-      S->YG[j] = red[3 * m + j];
-    }
-  }
-  S->gnorm_rms = sqrt(S->gg / (double)n);
-  if (o.gtol > 0.0 && S->gnorm_rms <= o.gtol) S->converged = 1;
-  if (step == LB_ACCEPT) {
-    const int ns = (S->head + 1) % m;
-    const double ys = red[ns], yy = red[m + ns];
-    if (ys > 0.0 && yy > 0.0) {
-      // dropping the oldest pair when the ring is full: its slot is ns
-      for (int j = 0; j < m; ++j) {
-        S->SY[j * kLbfgsMaxM + ns] = red[j];      // s_j . y_new
-        S->YY[j * kLbfgsMaxM + ns] = red[m + j];  // y_j . y_new
-        S->YY[ns * kLbfgsMaxM + j] = red[m + j];
-      }
-      S->head = ns;
-      if (S->k < m) S->k += 1;
-      S->gamma = ys / yy;
-      S->restarted = 0;
-    } else {
-      S->k = 0;  // curvature condition failed: steepest descent
-    }
-  }
-  const int k = S->k;
-  for (int i = 0; i < k; ++i) cs[i] = (S->head - (k - 1) + i + m) % m;
-  for (int j = 0; j < m; ++j) {
-    S->coefS[j] = 0.0;
-    S->coefY[j] = 0.0;
-  }
-}
-
-// Direction coefficients by one wavefront: lane i < k holds the pair of
-// chronological index i, with its row of R = S^T Y (upper triangle used), its
-// column of R and its row of Y^T Y in registers; the triangular solves pass
-// each solved unknown to the other lanes by shuffle.
-__device__ __forceinline__ void lb_small_direction(LbfgsState* S, const LbfgsOpts& o,
-                                                   const int* cs) {
+// Direction coefficients (one wavefront; lane i < k holds the pair of
+// chronological index i, ring slot sl[i]).  R^-1 is kept in the state and
+// extended by the new pair's column (dropping the oldest pair leaves the rest of
+// it as it is), so t and u are products rather than dependent triangular solves:
+//   R^-1[i][new] = -(sum over i <= j < new of R^-1[i][j] R[j][new]) / R[new][new],
+//   R^-1[new][new] = 1 / R[new][new].
+// Every lane loads its rows for all MM chronological indices at once (indices at
+// or past k read slot 0 and are masked), so that no LDS load waits inside a
+// divergent branch.
+template <int MM>
+__device__ __forceinline__ void lb_small_direction(LbfgsState* S, int head, int k, int m,
+                                                   bool added) {
+  constexpr int M = kLbfgsMaxM;
   const int lane = threadIdx.x & 63;
-  const int k = S->k;
   double gtp;
   if (k == 0) {
     if (lane == 0) S->coefG = 1.0;
@@ -423,43 +390,56 @@ __device__ __forceinline__ void lb_small_direction(LbfgsState* S, const LbfgsOpt
   } else {
     const double gam = S->gamma;
     const bool mine = lane < k;
-    const int si = mine ? cs[lane] : 0;
-    double Rrow[kLbfgsMaxM], Rcol[kLbfgsMaxM], Yrow[kLbfgsMaxM];
+    // ring slot of chronological index j: (head - (k - 1) + j) mod m
+    int sl[MM];
+    const int s0 = (head - (k - 1) + m) % m;
 #pragma unroll
-    for (int j = 0; j < kLbfgsMaxM; ++j) {
-      const bool on = mine && j < k;
-      const int sj = (j < k) ? cs[j] : 0;
-      Rrow[j] = on ? S->SY[si * kLbfgsMaxM + sj] : 0.0;  // s_i . y_j
-      Rcol[j] = on ? S->SY[sj * kLbfgsMaxM + si] : 0.0;  // s_j . y_i
-      Yrow[j] = on ? S->YY[si * kLbfgsMaxM + sj] : 0.0;  // y_i . y_j
+    for (int j = 0; j < MM; ++j) {
+      const int q = s0 + j < m ? s0 + j : s0 + j - m;
+      sl[j] = j < k ? q : 0;
+    }
+    int si = 0;
+#pragma unroll
+    for (int j = 0; j < MM; ++j) si = (j == lane) ? sl[j] : si;
+    if (added) {
+      const int sn = head;  // the new pair, chronological index k - 1
+      const double rho = S->SY[sn * M + sn];
+      double x = 0.0;
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        const double r = S->RI[si * M + sl[j]];
+        const double c = S->SY[sl[j] * M + sn];
+        x += (j >= lane && j < k - 1) ? r * c : 0.0;
+      }
+      if (lane < k - 1) S->RI[si * M + sn] = -x / rho;
+      else if (lane == k - 1) S->RI[sn * M + sn] = 1.0 / rho;
+      wave_lds_fence();
     }
     const double a = mine ? S->SG[si] : 0.0;  // s_i . g
     const double b = mine ? S->YG[si] : 0.0;  // y_i . g
-    const double D = mine ? S->SY[si * kLbfgsMaxM + si] : 1.0;
-    // R t = a, from the newest pair down
-    double r = a, t = 0.0;
+    const double D = mine ? S->SY[si * M + si] : 0.0;
+    // t = R^-1 a: lane i sums over i <= j < k (row i of R^-1)
+    double t = 0.0;
 #pragma unroll
-    for (int i0 = kLbfgsMaxM - 1; i0 >= 0; --i0) {
-      if (i0 < k) {
-        const double ti = __shfl(r, i0, 64) / __shfl(D, i0, 64);
-        if (lane == i0) t = ti;
-        if (lane < i0) r -= Rrow[i0] * ti;
-      }
+    for (int j = 0; j < MM; ++j) {
+      const double r = S->RI[si * M + sl[j]], aj = S->SG[sl[j]];
+      t += (mine && j >= lane && j < k) ? r * aj : 0.0;
     }
     // w = (D + gamma Y^T Y) t - gamma b
     double w = D * t - gam * b;
 #pragma unroll
-    for (int j = 0; j < kLbfgsMaxM; ++j)
-      if (j < k) w += gam * Yrow[j] * __shfl(t, j, 64);
-    // R^T u = w, from the oldest pair up
-    double q = w, u = 0.0;
+    for (int j = 0; j < MM; ++j) {
+      const double yij = S->YY[si * M + sl[j]];
+      const double tj = __shfl(t, j, 64);
+      w = (mine && j < k) ? w + gam * yij * tj : w;
+    }
+    // u = R^-T w: lane j sums over i <= j (column j of R^-1)
+    double u = 0.0;
 #pragma unroll
-    for (int j0 = 0; j0 < kLbfgsMaxM; ++j0) {
-      if (j0 < k) {
-        const double uj = __shfl(q, j0, 64) / __shfl(D, j0, 64);
-        if (lane == j0) u = uj;
-        if (lane > j0) q -= Rcol[j0] * uj;
-      }
+    for (int i = 0; i < MM; ++i) {
+      const double r = S->RI[sl[i] * M + si];
+      const double wi = __shfl(w, i, 64);
+      u += (mine && i <= lane && i < k) ? r * wi : 0.0;
     }
     if (mine) {
       S->coefS[si] = u;
@@ -495,6 +475,64 @@ __device__ __forceinline__ void lb_small_direction(LbfgsState* S, const LbfgsOpt
       S->step = LB_IDLE;
     }
   }
+}
+
+// The small step on one wavefront, state in LDS: the decision (lane 0), the new
+// pair's products (lanes by ring slot), then the direction coefficients.
+template <int MM>
+__device__ __forceinline__ void lb_small_wave(LbfgsState* S, const LbfgsOpts& o,
+                                              const double* red, long long n) {
+  constexpr int M = kLbfgsMaxM;
+  const int lane = threadIdx.x & 63;
+  if (lane == 0) lb_decide(S, o);
+  wave_lds_fence();
+  const int step = S->step;
+  if (step != LB_ACCEPT && step != LB_INIT && step != LB_RESTART) return;  // uniform
+  const int m = o.m;
+  double gg = S->gg;
+  if (step != LB_RESTART) {
+    gg = red[4 * m];
+    if (lane < m) {
+      S->SG[lane] = red[2 * m + lane];
+      S->YG[lane] = red[3 * m + lane];
+    }
+  }
+  int head = S->head, k = S->k;
+  bool added = false;
+  if (step == LB_ACCEPT) {
+    const int ns = (head + 1) % m;
+    const double ys = red[ns], yy = red[m + ns];
+    if (ys > 0.0 && yy > 0.0) {
+      // dropping the oldest pair when the ring is full: its slot is ns
+      if (lane < m) {
+        S->SY[lane * M + ns] = red[lane];      // s_j . y_new
+        S->YY[lane * M + ns] = red[m + lane];  // y_j . y_new
+        S->YY[ns * M + lane] = red[m + lane];
+      }
+      head = ns;
+      if (k < m) k += 1;
+      added = true;
+      if (lane == 0) {
+        S->gamma = ys / yy;
+        S->restarted = 0;
+      }
+    } else {
+      k = 0;  // curvature condition failed: steepest descent
+    }
+  }
+  if (lane == 0) {
+    S->gg = gg;
+    S->gnorm_rms = sqrt(gg / (double)n);
+    if (o.gtol > 0.0 && S->gnorm_rms <= o.gtol) S->converged = 1;
+    S->head = head;
+    S->k = k;
+  }
+  if (lane < m) {
+    S->coefS[lane] = 0.0;
+    S->coefY[lane] = 0.0;
+  }
+  wave_lds_fence();
+  lb_small_direction<MM>(S, head, k, m, added);
 }
 
 // ---------------------------------------------------------------- pass B
@@ -547,9 +585,23 @@ __device__ __forceinline__ double pass_b_run(const LbfgsVec<R>& v, unsigned live
   return pm;
 }
 
+// The small step on the snapshot (every block), block 0 writing the new state
+// back, then the direction pass with the coefficients from the block's copy.
+// (Loading each thread's first packs before the small step, to overlap their
+// latency with it, measured no faster: those loads delay the small step's own.)
 template <class R, int MM>
-__global__ __launch_bounds__(kThreads) void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* S, int vec) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(MM <= 8 ? 4 : 2))) void lb_pass_b_kernel(LbfgsVec<R> v, LbfgsState* Sg,
+                                                             LbfgsOpts o, int vec) {
   __shared__ double sh[kWaves];
+  __shared__ LbfgsState ss;
+  __shared__ double red[4 * kLbfgsMaxM + 1];
+  lb_small_step<MM>(Sg + 1, o, v.part0, v.nb, v.n, ss, red);
+  if (blockIdx.x == 0) {
+    constexpr int kWords = (int)(sizeof(LbfgsState) / 4);
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+      reinterpret_cast<uint32_t*>(Sg)[i] = reinterpret_cast<const uint32_t*>(&ss)[i];
+  }
+  const LbfgsState* S = &ss;
   const int step = S->step;
   if (step != LB_ACCEPT && step != LB_INIT && step != LB_RESTART) return;
   const int k = S->k;
@@ -679,7 +731,7 @@ void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o
   const int vec = al(v.x) && al(v.g) && al(v.p) && al(v.xt) && al(v.gt) && al(v.S) && al(v.Y) &&
                   (v.ld % pack_u<R, 1, kPackBytesBC>()) == 0;
 #define LB_A(MM) lb_pass_a_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, o, vec, lp)
-#define LB_B(MM) lb_pass_b_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, vec)
+#define LB_B(MM) lb_pass_b_kernel<R, MM><<<v.nb, kThreads, 0, st>>>(v, S, o, vec)
 #define LB_SWITCH(CALL)                                                        \
   switch (v.m) {                                                               \
     case 1: CALL(1); break;   case 2: CALL(2); break;   case 3: CALL(3); break;   \
@@ -690,7 +742,6 @@ void launch_lbfgs_update(const LbfgsVec<R>& v, LbfgsState* S, const LbfgsOpts& o
     case 16: CALL(16); break;                                                  \
   }
   LB_SWITCH(LB_A)
-  lb_small_kernel<<<1, 1024, 0, st>>>(S, o, v.part0, v.nb, v.n);
   LB_SWITCH(LB_B)
 #undef LB_SWITCH
 #undef LB_B
