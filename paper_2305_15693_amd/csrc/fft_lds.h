@@ -72,53 +72,124 @@ __device__ __forceinline__ void dft5(cpx<R>* v) {
   v[3] = csub(C, D);
 }
 
+template <class R, bool INV, int RAD>
+__device__ __forceinline__ void dft(cpx<R>* v) {
+  if constexpr (RAD == 2) dft2<R, INV>(v);
+  else if constexpr (RAD == 3) dft3<R, INV>(v);
+  else if constexpr (RAD == 4) dft4<R, INV>(v);
+  else dft5<R, INV>(v);
+}
+
+// One radix-RAD Stockham stage s (radix fixed at compile time, so that the
+// loads, twiddles and butterfly carry no run-time radix tests); both barriers
+// inside.
+template <class R, int MAXB, bool INV, int RAD>
+__device__ __forceinline__ void lds_stage(cpx<R>* buf, const FftFactors& F, int s,
+                                          const cpx<R>* __restrict__ tw, bool active, int b,
+                                          int ls, int es, int tj, int JT) {
+  const int nr = F.n / RAD;
+  const FastDiv nsd = F.ns[s];
+  const uint32_t tstep = F.twstep[s];
+  cpx<R> v[MAXB][RAD];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int j = tj + q * JT;
+    if (active && j < nr) {
+#pragma unroll
+      for (int t = 0; t < RAD; ++t) v[q][t] = buf[b * ls + (j + t * nr) * es];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int j = tj + q * JT;
+    if (active && j < nr) {
+      const uint32_t jd = fdiv((uint32_t)j, nsd);
+      const uint32_t k = (uint32_t)j - jd * nsd.d;
+      const uint32_t step = k * tstep;
+#pragma unroll
+      for (int t = 1; t < RAD; ++t) {
+        const cpx<R> w = tw[t * step];
+        v[q][t] = INV ? cmulc(v[q][t], w) : cmul(v[q][t], w);
+      }
+      dft<R, INV, RAD>(v[q]);
+      const uint32_t ob = jd * nsd.d * RAD + k;
+#pragma unroll
+      for (int u = 0; u < RAD; ++u) buf[b * ls + (ob + u * nsd.d) * es] = v[q][u];
+    }
+  }
+  __syncthreads();
+}
+
+// One Stockham stage of run-time radix r (every radix's loads and butterflies
+// behind run-time tests): fewer registers than the fixed-radix stage when a
+// thread serves many butterflies (MAXB > 2: all its loads are issued together).
+template <class R, int MAXB, bool INV>
+__device__ __forceinline__ void lds_stage_any(cpx<R>* buf, const FftFactors& F, int s,
+                                              const cpx<R>* __restrict__ tw, bool active, int b,
+                                              int ls, int es, int tj, int JT) {
+  const int n = F.n;
+  const int r = F.radix[s];
+  const int nr = n / r;
+  cpx<R> v[MAXB][5];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    int j = tj + q * JT;
+    if (active && j < nr) {
+#pragma unroll
+      for (int t = 0; t < 5; ++t)
+        if (t < r) v[q][t] = buf[b * ls + (j + t * nr) * es];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    int j = tj + q * JT;
+    if (active && j < nr) {
+      uint32_t jd = fdiv((uint32_t)j, F.ns[s]);
+      uint32_t k = (uint32_t)j - jd * F.ns[s].d;
+      uint32_t step = k * F.twstep[s];
+#pragma unroll
+      for (int t = 1; t < 5; ++t) {
+        if (t < r) {
+          cpx<R> w = tw[t * step];
+          v[q][t] = INV ? cmulc(v[q][t], w) : cmul(v[q][t], w);
+        }
+      }
+      if (r == 2) dft2<R, INV>(v[q]);
+      else if (r == 3) dft3<R, INV>(v[q]);
+      else if (r == 4) dft4<R, INV>(v[q]);
+      else dft5<R, INV>(v[q]);
+      uint32_t ob = jd * F.ns[s].d * r + k;
+#pragma unroll
+      for (int u = 0; u < 5; ++u)
+        if (u < r) buf[b * ls + (ob + u * F.ns[s].d) * es] = v[q][u];
+    }
+  }
+  __syncthreads();
+}
+
 // In-LDS Stockham FFT of the lines this thread group serves.
 // buf element (line b, index i) lives at buf[b * ls + i * es]; this thread works
 // on line `b` and on butterflies j = tj, tj + JT, ... of every stage.  All
-// threads of the block must call it (it contains barriers).
+// threads of the block must call it (it contains barriers).  Up to two
+// butterflies per thread and stage (the 2D row and column passes) the stages
+// are specialised by radix; more (the 3D column passes) take the run-time radix
+// stage, whose registers fit.
 template <class R, int MAXB, bool INV>
 __device__ void lds_fft(cpx<R>* buf, const FftFactors& F, const cpx<R>* __restrict__ tw,
                         bool active, int b, int ls, int es, int tj, int JT) {
-  const int n = F.n;
   for (int s = 0; s < F.nfac; ++s) {
-    const int r = F.radix[s];
-    const int nr = n / r;
-    cpx<R> v[MAXB][5];
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-      int j = tj + q * JT;
-      if (active && j < nr) {
-#pragma unroll
-        for (int t = 0; t < 5; ++t)
-          if (t < r) v[q][t] = buf[b * ls + (j + t * nr) * es];
+    if constexpr (MAXB <= 2) {
+      switch (F.radix[s]) {
+        case 2: lds_stage<R, MAXB, INV, 2>(buf, F, s, tw, active, b, ls, es, tj, JT); break;
+        case 3: lds_stage<R, MAXB, INV, 3>(buf, F, s, tw, active, b, ls, es, tj, JT); break;
+        case 4: lds_stage<R, MAXB, INV, 4>(buf, F, s, tw, active, b, ls, es, tj, JT); break;
+        default: lds_stage<R, MAXB, INV, 5>(buf, F, s, tw, active, b, ls, es, tj, JT); break;
       }
+    } else {
+      lds_stage_any<R, MAXB, INV>(buf, F, s, tw, active, b, ls, es, tj, JT);
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-      int j = tj + q * JT;
-      if (active && j < nr) {
-        uint32_t jd = fdiv((uint32_t)j, F.ns[s]);
-        uint32_t k = (uint32_t)j - jd * F.ns[s].d;
-        uint32_t step = k * F.twstep[s];
-#pragma unroll
-        for (int t = 1; t < 5; ++t) {
-          if (t < r) {
-            cpx<R> w = tw[t * step];
-            v[q][t] = INV ? cmulc(v[q][t], w) : cmul(v[q][t], w);
-          }
-        }
-        if (r == 2) dft2<R, INV>(v[q]);
-        else if (r == 3) dft3<R, INV>(v[q]);
-        else if (r == 4) dft4<R, INV>(v[q]);
-        else dft5<R, INV>(v[q]);
-        uint32_t ob = jd * F.ns[s].d * r + k;
-#pragma unroll
-        for (int u = 0; u < 5; ++u)
-          if (u < r) buf[b * ls + (ob + u * F.ns[s].d) * es] = v[q][u];
-      }
-    }
-    __syncthreads();
   }
 }
 
