@@ -668,11 +668,12 @@ __device__ __forceinline__ void add_row_pairs(uint32_t* acc, int rb, const uint3
 // (kp): the block first forms the trial point and the record of each of its
 // slots (kept_tile_record, relative to this tile), writes both, and spreads
 // from the records it wrote.
-template <class R, int D, int W, bool STR, bool KEPT = false>
-__global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
-                              const long long* __restrict__ start, R* __restrict__ tiles,
-                              const R* __restrict__ cstr, const int* __restrict__ perm,
-                              double cmax, KeptSpread<R> kp) {
+template <class R, int D, int W, bool STR, bool KEPT>
+__device__ __forceinline__ void spread_body(const Geom& g, const Rec<R>* __restrict__ rec,
+                                            const long long* __restrict__ start,
+                                            R* __restrict__ tiles, const R* __restrict__ cstr,
+                                            const int* __restrict__ perm, double cmax,
+                                            const KeptSpread<R>& kp) {
   constexpr bool F32 = sizeof(R) == 4 && !STR;  // 32-bit cells added in pairs
   extern __shared__ unsigned long long smem_u64[];
   uint32_t* acc32 = reinterpret_cast<uint32_t*>(smem_u64);
@@ -887,6 +888,24 @@ __global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
     else if (STR) out[c] = (R)((double)(long long)acc64[c] * inv_scale);
     else out[c] = (R)((R)acc64[c] * (R)inv_scale);
   }
+}
+
+template <class R, int D, int W, bool STR, bool KEPT = false>
+__global__ void spread_kernel(Geom g, const Rec<R>* __restrict__ rec,
+                              const long long* __restrict__ start, R* __restrict__ tiles,
+                              const R* __restrict__ cstr, const int* __restrict__ perm,
+                              double cmax, KeptSpread<R> kp) {
+  spread_body<R, D, W, STR, KEPT>(g, rec, start, tiles, cstr, perm, cmax, kp);
+}
+// The kept-order variant without strengths: its pointers took 83 scalar
+// registers, with which only three of its 512-thread workgroups were resident
+// per CU (a quarter of the tiles started when the first finished); within 64
+// (the rest kept in vector lanes) all four are, 29.3 -> 26.2 us.
+template <class R, int W>
+__global__ __attribute__((amdgpu_num_sgpr(64))) void spread_kept_kernel(
+    Geom g, const Rec<R>* __restrict__ rec, const long long* __restrict__ start,
+    R* __restrict__ tiles, KeptSpread<R> kp) {
+  spread_body<R, 2, W, false, true>(g, rec, start, tiles, nullptr, nullptr, 1.0, kp);
 }
 
 // Fold: grid cell (x, y, z) = sum over the padded tiles that cover it.  For each
@@ -1253,7 +1272,7 @@ hipError_t spread_prepare(const Geom& g) {
   do {                                                          \
     if (g.d == 2) {                                             \
       lds((const void*)spread_kernel<R, 2, W, false>, sl);      \
-      lds((const void*)spread_kernel<R, 2, W, false, true>, sl); \
+      lds((const void*)spread_kept_kernel<R, W>, sl);          \
       lds((const void*)interp_kernel<R, 2, W>, il);             \
       if (slc <= kMaxSpreadLds)                                 \
         lds((const void*)spread_kernel<R, 2, W, true>, slc);    \
@@ -1286,8 +1305,8 @@ void launch_spread(const Geom& g, const Rec<R>* rec, const long long* start, R* 
 #define SP(W)                                                                                 \
   do {                                                                                        \
     if (g.d == 2 && kept && !str)                                                             \
-      spread_kernel<R, 2, W, false, true><<<(unsigned)g.nbins, threads, lds, st>>>(          \
-          g, rec, start, tiles, nullptr, nullptr, 1.0, kp);                                   \
+      spread_kept_kernel<R, W><<<(unsigned)g.nbins, threads, lds, st>>>(g, rec, start, tiles, \
+                                                                        kp);                  \
     else if (g.d == 2 && kept)                                                                \
       spread_kernel<R, 2, W, true, true><<<(unsigned)g.nbins, threads, lds, st>>>(           \
           g, rec, start, tiles, cs.c, cs.perm, cs.cmax, kp);                                  \
