@@ -235,17 +235,19 @@ typedef struct fresco_lbfgs_opts {
  * internal point order persist in the context across calls, so a run can be
  * continued by calling again with the returned positions; fresco_reset_history
  * starts afresh.  The trial steps run as replays of captured HIP graphs (on a
- * non-default stream: one graph of 8 trial steps, one of a single step for the
- * rest), enqueued in chunks of 8 with two chunks in flight: the host reads the
- * optimiser's state after each chunk while the next one runs, so after a stop
- * (n_iter reached, gtol reached, line-search failure) at most two chunks of
- * replays run idle -- they change nothing and are not counted.  Within a chunk
- * of 8, a trial step may keep the tile order of the previous binned one (only
- * its per-point records are recomputed) while r + 2 step caps, r the steps since
- * that binning, stay below the plan's slack (fresco_plan_info.slack, in grid
- * cells): every trial point is within max_step per coordinate of the current
- * point, which moves by at most max_step per accepted step, so its footprint
- * stays inside the padded tiles of that binning.
+ * non-default stream: one graph of a chunk of trial steps, one of a single
+ * step for the rest), enqueued in chunks with two chunks in flight: the host
+ * reads the optimiser's state after each chunk while the next one runs, so
+ * after a stop (n_iter reached, gtol reached, line-search failure) at most two
+ * chunks of replays run idle -- they change nothing and are not counted.
+ * Within a chunk, a trial step may keep the tile order of the previous binned
+ * one (only its per-point records are recomputed) while r + 2 step caps, r the
+ * steps since that binning, stay below the plan's slack (fresco_plan_info.slack,
+ * in grid cells): every trial point is within max_step per coordinate of the
+ * current point, which moves by at most max_step per accepted step, so its
+ * footprint stays inside the padded tiles of that binning.  A chunk holds 8
+ * trial steps, or as many as one binning can serve when that is more (at most
+ * 16).
  * loss_out (host, may be NULL): loss at the final positions; n_eval_out (host,
  * may be NULL): loss/gradient evaluations the optimiser used (the first one at
  * the starting point included).  Synchronises the stream.  The first call, and

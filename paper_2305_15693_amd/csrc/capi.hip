@@ -91,7 +91,8 @@ struct State {
   LbfgsOpts lb_opts{};
   bool cached_eval = false;  // the last binning kept the previous tile order
   hipGraphExec_t lb_graph = nullptr;        // one trial step
-  hipGraphExec_t lb_graph_chunk = nullptr;  // kLbfgsReplayChunk trial steps
+  hipGraphExec_t lb_graph_chunk = nullptr;  // one chunk of trial steps (its length
+                                            // follows the options, which drop it)
   void drop_lb_graphs() {
     if (lb_graph) (void)hipGraphExecDestroy(lb_graph);
     if (lb_graph_chunk) (void)hipGraphExecDestroy(lb_graph_chunk);
@@ -1188,8 +1189,11 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
     double cells = 0.0;  // grid cells per max_step, largest over the axes
     for (int a = 0; a < g.d; ++a) cells = std::max(cells, lo.max_step * g.ufac[a]);
     const double r = std::floor((g.slack - 0.25) / cells) - 2.0;  // last cached trial
-    if (r >= 1.0) bin_every = (int)std::min<double>(r + 1.0, kLbfgsReplayChunk);
+    if (r >= 1.0) bin_every = (int)std::min<double>(r + 1.0, kLbfgsMaxReplayChunk);
   }
+  // trial steps per chunk: kLbfgsReplayChunk, or one binning's worth when that
+  // is more (fewer binnings and graph launches per trial step)
+  const int chunk_len = std::max(kLbfgsReplayChunk, bin_every);
   // two graphs: one trial step, and a full chunk of them (one launch per chunk,
   // so that consecutive steps are not separated by a graph launch)
   auto capture = [&](int steps, hipGraphExec_t* out) -> int {
@@ -1211,13 +1215,13 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
   };
   if (graphs && !S->lb_graph_chunk) {
     S->drop_lb_graphs();
-    if ((st = capture(1, &S->lb_graph)) || (st = capture(kLbfgsReplayChunk, &S->lb_graph_chunk))) {
+    if ((st = capture(1, &S->lb_graph)) || (st = capture(chunk_len, &S->lb_graph_chunk))) {
       S->drop_lb_graphs();
       return st;
     }
   }
   auto replay = [&](int count) -> int {
-    if (graphs && count == kLbfgsReplayChunk) {
+    if (graphs && count == chunk_len) {
       HIPCHK(hipGraphLaunch(S->lb_graph_chunk, c->st));
       return FRESCO_OK;
     }
@@ -1226,7 +1230,7 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
         HIPCHK(hipGraphLaunch(S->lb_graph, c->st));
       } else {
         // eager launches follow the graphs' binning pattern (same arithmetic)
-        const bool chunk = count == kLbfgsReplayChunk;
+        const bool chunk = count == chunk_len;
         const int s2 = lbfgs_trial<R>(c, chunk && r % bin_every != 0,
                                       chunk && r + 1 < count && (r + 1) % bin_every != 0);
         if (s2) return s2;
@@ -1234,8 +1238,8 @@ int step_impl(fresco_ctx* c, void* pos, const fresco_lbfgs_opts* o, int n_iter, 
     }
     return FRESCO_OK;
   };
-  if ((st = lbfgs_replay_until_stop(c->st, S->lst, S->lst_host, S->lb_ev, n_iter,
-                                    kLbfgsReplayChunk, replay, &g_last_hip)))
+  if ((st = lbfgs_replay_until_stop(c->st, S->lst, S->lst_host, S->lb_ev, n_iter, chunk_len,
+                                    replay, &g_last_hip)))
     return st;
   launch_scatter_rows<R>(S->lv.x, S->perm0, N, g.d, (R*)pos, c->st);
   if ((st = lbfgs_read<R>(c))) return st;

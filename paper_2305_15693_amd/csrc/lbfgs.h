@@ -146,8 +146,10 @@ int lbfgs_replay_until_stop(hipStream_t st, LbfgsState* dev, LbfgsState* host, h
   return FRESCO_OK;
 }
 
-// replays per chunk of an optimiser call
+// replays per chunk of an optimiser call (at least; up to the max when one
+// binning of the kept tile order serves that many trial steps)
 constexpr int kLbfgsReplayChunk = 8;
+constexpr int kLbfgsMaxReplayChunk = 16;
 
 // S: two states in device memory, S[0] the state and S[1] the snapshot of it that
 // the first pass leaves for the second (whose block 0 rewrites S[0]).
