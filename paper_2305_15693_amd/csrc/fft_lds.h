@@ -169,16 +169,99 @@ __device__ __forceinline__ void lds_stage_any(cpx<R>* buf, const FftFactors& F, 
   __syncthreads();
 }
 
+// A stage of a plan fixed at compile time (length N, NS = product of the earlier
+// radices): the index arithmetic folds to constants, bitwise the same results as
+// lds_stage.
+template <class R, int MAXB, bool INV, int RAD, int N, int NS>
+__device__ __forceinline__ void lds_stage_fixed(cpx<R>* buf, const cpx<R>* __restrict__ tw,
+                                                bool active, int b, int ls, int es, int tj,
+                                                int JT) {
+  constexpr int nr = N / RAD;
+  constexpr uint32_t tstep = N / (NS * RAD);
+  cpx<R> v[MAXB][RAD];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int j = tj + q * JT;
+    if (active && j < nr) {
+#pragma unroll
+      for (int t = 0; t < RAD; ++t) v[q][t] = buf[b * ls + (j + t * nr) * es];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int j = tj + q * JT;
+    if (active && j < nr) {
+      const uint32_t jd = (uint32_t)j / NS;
+      const uint32_t k = (uint32_t)j - jd * NS;
+      const uint32_t step = k * tstep;
+#pragma unroll
+      for (int t = 1; t < RAD; ++t) {
+        const cpx<R> w = tw[t * step];
+        v[q][t] = INV ? cmulc(v[q][t], w) : cmul(v[q][t], w);
+      }
+      dft<R, INV, RAD>(v[q]);
+      const uint32_t ob = jd * NS * RAD + k;
+#pragma unroll
+      for (int u = 0; u < RAD; ++u) buf[b * ls + (ob + u * NS) * es] = v[q][u];
+    }
+  }
+  __syncthreads();
+}
+
+template <int... RS>
+constexpr int plan_length() {
+  return (RS * ... * 1);
+}
+// the stages of the fixed plan RS... (NS: product of the radices before RAD)
+template <class R, int MAXB, bool INV, int N, int NS, int RAD, int... REST>
+__device__ __forceinline__ void lds_fixed_plan(cpx<R>* buf, const cpx<R>* __restrict__ tw,
+                                               bool active, int b, int ls, int es, int tj,
+                                               int JT) {
+  lds_stage_fixed<R, MAXB, INV, RAD, N, NS>(buf, tw, active, b, ls, es, tj, JT);
+  if constexpr (sizeof...(REST) > 0)
+    lds_fixed_plan<R, MAXB, INV, N, NS * RAD, REST...>(buf, tw, active, b, ls, es, tj, JT);
+}
+template <int... RS>
+__device__ __forceinline__ bool plan_is(const FftFactors& F) {
+  constexpr int rs[] = {RS...};
+  if (F.nfac != (int)sizeof...(RS)) return false;
+  bool same = true;
+#pragma unroll
+  for (int s = 0; s < (int)sizeof...(RS); ++s) same = same && F.radix[s] == rs[s];
+  return same;
+}
+// Runs the transform if F is the fixed plan RS...; returns whether it did.
+template <class R, int MAXB, bool INV, int... RS>
+__device__ __forceinline__ bool lds_try_plan(cpx<R>* buf, const FftFactors& F,
+                                             const cpx<R>* __restrict__ tw, bool active, int b,
+                                             int ls, int es, int tj, int JT) {
+  if (!plan_is<RS...>(F)) return false;  // uniform across the block
+  lds_fixed_plan<R, MAXB, INV, plan_length<RS...>(), 1, RS...>(buf, tw, active, b, ls, es, tj,
+                                                                JT);
+  return true;
+}
+
 // In-LDS Stockham FFT of the lines this thread group serves.
 // buf element (line b, index i) lives at buf[b * ls + i * es]; this thread works
 // on line `b` and on butterflies j = tj, tj + JT, ... of every stage.  All
 // threads of the block must call it (it contains barriers).  Up to two
 // butterflies per thread and stage (the 2D row and column passes) the stages
-// are specialised by radix; more (the 3D column passes) take the run-time radix
-// stage, whose registers fit.
+// are specialised by radix, and the plans of the lengths the planner picks for
+// the 2D and 3D workloads (1250 = 5 5 5 5 2, 625, 250, 125) run as fixed stage
+// sequences, their index arithmetic folded to constants (forward and inverse
+// column FFTs of the 2D mode pass 3.4 and 2.9 -> 2.5 and 2.1 us); more
+// butterflies per thread (the 3D column passes) take the run-time radix stage,
+// whose registers fit.
 template <class R, int MAXB, bool INV>
 __device__ void lds_fft(cpx<R>* buf, const FftFactors& F, const cpx<R>* __restrict__ tw,
                         bool active, int b, int ls, int es, int tj, int JT) {
+  if constexpr (MAXB <= 2) {
+    if (lds_try_plan<R, MAXB, INV, 5, 5, 5, 5, 2>(buf, F, tw, active, b, ls, es, tj, JT)) return;
+    if (lds_try_plan<R, MAXB, INV, 5, 5, 5, 5>(buf, F, tw, active, b, ls, es, tj, JT)) return;
+    if (lds_try_plan<R, MAXB, INV, 5, 5, 5, 2>(buf, F, tw, active, b, ls, es, tj, JT)) return;
+    if (lds_try_plan<R, MAXB, INV, 5, 5, 5>(buf, F, tw, active, b, ls, es, tj, JT)) return;
+  }
   for (int s = 0; s < F.nfac; ++s) {
     if constexpr (MAXB <= 2) {
       switch (F.radix[s]) {
