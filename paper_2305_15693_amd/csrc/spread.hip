@@ -715,25 +715,28 @@ __device__ __forceinline__ void spread_body(const Geom& g, const Rec<R>* __restr
   }
 
   // Fixed-point scale from a bound on the number of points whose footprints
-  // cover one cell (each contributes at most 1): the tile's footprint starts are
-  // counted per column over the last two axes (2D: exactly per start cell), and
-  // the largest w x w box sum of those counts bounds every cell's contributors.
+  // cover one cell (each contributes at most 1): a cell's contributors have
+  // their footprint starts in one w x w window of start cells (over the last two
+  // axes; in 3D every start of the column counts), and every such window lies
+  // within K x K blocks of 2 x 2 start cells, K = w / 2 + 1.  The starts are
+  // counted per block, and the largest sum over K x K blocks bounds every cell's
+  // contributors (at most 64 / 49 of the exact w x w maximum in area at w = 7,
+  // so the scale keeps all but a fraction of a bit; the exact box sums took 13%
+  // of the spreading kernel).
   __shared__ uint32_t smax[16];
   uint32_t cov;
   {
     // footprint starts span the tile and the slack on both sides
     const int Ta = ((D == 3) ? g.T[1] : g.T[0]) + 2 * g.slack;
     const int Tb = ((D == 3) ? g.T[2] : g.T[1]) + 2 * g.slack;
-    uint32_t* cnt = acc32;  // Ta Tb <= ncell words, before the accumulator is cleared
-    // Tb (Ta + W - 1) >= Tb Ta words after the accumulator (spread_lds_bytes)
-    uint32_t* cov_tmp =
-        F32 ? acc32 + (ncell + 2) : reinterpret_cast<uint32_t*>(acc64 + (ncell + 2));
-    for (int c = threadIdx.x; c < Ta * Tb; c += blockDim.x) cnt[c] = 0u;
+    const int Sa = (Ta + 1) >> 1, Sb = (Tb + 1) >> 1;  // 2 x 2 blocks of start cells
+    uint32_t* cnt = acc32;  // Sa Sb <= ncell words, before the accumulator is cleared
+    for (int c = threadIdx.x; c < Sa * Sb; c += blockDim.x) cnt[c] = 0u;
     __syncthreads();
     auto count_cell = [&](uint32_t cl) {
       const int la = (D == 3) ? (int)((cl >> 8) & 0xff) : (int)(cl & 0xff);
       const int lb = (D == 3) ? (int)((cl >> 16) & 0xff) : (int)((cl >> 8) & 0xff);
-      atomicAdd(cnt + lb * Ta + la, 1u);
+      atomicAdd(cnt + (lb >> 1) * Sa + (la >> 1), 1u);
     };
     if constexpr (KEPT) {
       // the trial point and record of every slot of the tile, counted as they
@@ -794,37 +797,19 @@ __device__ __forceinline__ void spread_body(const Geom& g, const Rec<R>* __restr
       }
     }
     __syncthreads();
-    // largest box sum over windows of W x W count cells (W x all when the tile
-    // is narrower), separable: along a into tmp[yb][ia], then along b.  Only the
-    // windows inside the tile: one that leaves it holds a subset of one that
-    // does not, the counts being non-negative.  Four neighbouring windows per
-    // thread as a running sum (unsigned arithmetic: every partial sum is exact).
+    // largest sum over K x K blocks (K x all when the tile has fewer): a block
+    // window that leaves the grid holds a subset of one that does not
+    constexpr int K = W / 2 + 1;
     uint32_t mx = 0;
     {
-      const int wa = W < Ta ? W : Ta, wb = W < Tb ? W : Tb;
-      const int na = Ta - wa + 1, nb = Tb - wb + 1;
-      const int na4 = (na + 3) / 4, nb4 = (nb + 3) / 4;
-      for (int o = threadIdx.x; o < Tb * na4; o += blockDim.x) {
-        const int yb = o / na4, i0 = (o - yb * na4) * 4;
-        const uint32_t* row = cnt + yb * Ta;
+      const int ka = K < Sa ? K : Sa, kb = K < Sb ? K : Sb;
+      const int na = Sa - ka + 1, nb = Sb - kb + 1;
+      for (int o = threadIdx.x; o < na * nb; o += blockDim.x) {
+        const int jb = o / na, ia = o - jb * na;
         uint32_t sum = 0;
-        for (int k = 0; k < wa; ++k) sum += row[i0 + k];
-        cov_tmp[yb * na + i0] = sum;
-        for (int u = 1; u < 4 && i0 + u < na; ++u) {
-          sum += row[i0 + u + wa - 1] - row[i0 + u - 1];
-          cov_tmp[yb * na + i0 + u] = sum;
-        }
-      }
-      __syncthreads();
-      for (int o = threadIdx.x; o < nb4 * na; o += blockDim.x) {
-        const int jc = o / na, ia = o - jc * na, j0 = jc * 4;
-        uint32_t sum = 0;
-        for (int k = 0; k < wb; ++k) sum += cov_tmp[(j0 + k) * na + ia];
+        for (int y = 0; y < kb; ++y)
+          for (int x = 0; x < ka; ++x) sum += cnt[(jb + y) * Sa + ia + x];
         mx = sum > mx ? sum : mx;
-        for (int u = 1; u < 4 && j0 + u < nb; ++u) {
-          sum += cov_tmp[(j0 + u + wb - 1) * na + ia] - cov_tmp[(j0 + u - 1) * na + ia];
-          mx = sum > mx ? sum : mx;
-        }
       }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -1246,10 +1231,10 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
 // 32-bit words over the last two axes)
 template <class R>
 size_t spread_lds_bytes(const Geom& g, bool str) {
-  size_t ncell = (size_t)g.E[0] * g.E[1] * (g.d == 3 ? g.E[2] : 1);
-  const size_t Ta = ((g.d == 3) ? g.T[1] : g.T[0]) + 2 * g.slack;
-  const size_t Tb = ((g.d == 3) ? g.T[2] : g.T[1]) + 2 * g.slack;
-  return (ncell + 2) * (sizeof(R) == 4 && !str ? 4 : 8) + Tb * (Ta + g.w - 1) * 4;
+  // the accumulator (the start-block counts of the coverage bound use its first
+  // words before it is cleared)
+  const size_t ncell = (size_t)g.E[0] * g.E[1] * (g.d == 3 ? g.E[2] : 1);
+  return (ncell + 2) * (sizeof(R) == 4 && !str ? 4 : 8);
 }
 template <class R>
 size_t interp_lds_bytes(const Geom& g) {
