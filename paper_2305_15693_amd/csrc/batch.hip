@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
 
     for (int i = threadIdx.x; i < g.ngrid; i += blockDim.x) acc[i] = (U)0;
-    const int ex = (int)floor(log2(ldexp(1.0, F32 ? 31 : 63) / (cov + 1.0)));
+    const int ex = fixed_exponent((long long)cov, F32 ? 31 : 63);
     const R scale = (R)ldexp(1.0, ex);
     const R inv_scale = (R)ldexp(1.0, -ex);
     __syncthreads();

@@ -153,6 +153,16 @@ __device__ __forceinline__ Rec<R> kept_tile_record(const Geom& g, const R* x, ui
   return o;
 }
 
+// Fixed-point exponent for `cnt` contributions of at most 1 each:
+// (cnt + 1) 2^ex <= 2^bits, ex = bits - ceil(log2(cnt + 1)), in integer
+// arithmetic (the FP64 logarithm it replaces cost every thread of a block about
+// a hundred instructions for the same value; equal for every cnt below 2^49)
+__device__ __forceinline__ int fixed_exponent(long long cnt, int bits) {
+  const unsigned long long v = (unsigned long long)cnt + 1ull;  // >= 1
+  const int up = (v <= 1ull) ? 0 : 64 - __clzll((long long)(v - 1ull));
+  return bits - up;
+}
+
 // sum of n partials in a fixed order by the first 256 threads of a block of 256
 // or more (s: 256 doubles); every thread gets the sum
 __device__ __forceinline__ double block_sum_256(const double* __restrict__ part, long long n,

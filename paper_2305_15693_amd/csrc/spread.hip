@@ -628,11 +628,6 @@ __device__ __forceinline__ void tile_coords(const Geom& g, long long bin, int* t
   t[2] = (int)(r / g.nt[1]);
 }
 
-// Fixed-point exponent for a tile of `cnt` points: (cnt + 1) 2^ex <= 2^bits.
-__device__ __forceinline__ int fixed_exponent(long long cnt, int bits) {
-  return (int)floor(log2(ldexp(1.0, bits) / (double)(cnt + 1)));
-}
-
 // add a row of W fixed-point values starting at acc[rb] with 64-bit atomics on
 // aligned pairs of 32-bit cells (no carry can cross: every cell stays < 2^32)
 template <int W, int I>
