@@ -53,6 +53,7 @@ struct BatchGeom {
   int JT[3];  // threads per line of the FFT along each axis
   int w, wi;
   double beta, beta_i;
+  double icb;  // 1 / cosh(beta_i), set with the plan (no FP64 cosh per thread)
   int ngrid, ncube, nb;
   int lds_tw;  // twiddle slots in LDS (largest nf)
 };
@@ -331,7 +332,7 @@ __global__ void __launch_bounds__(1024)
   R* fl = reinterpret_cast<R*>(smem_u64);
   const int nf0 = g.nf[0], nf1 = g.nf[1], nf2 = g.nf[2];
   const R beta_i = (R)g.beta_i;
-  const R icb = (R)(1.0 / cosh(g.beta_i));
+  const R icb = (R)g.icb;
   const double hw = 0.5 * W;
   for (int it = blockIdx.x; it < nwork; it += gridDim.x) {
     const int4 wk = work[it];
@@ -905,6 +906,7 @@ int fresco_batch_create(fresco_batch_ctx** out, int32_t nb, const fresco_problem
   g.beta = kernel_beta(g.w);
   g.wi = g.w + 1;
   g.beta_i = kernel_beta(g.wi);
+  g.icb = 1.0 / std::cosh(g.beta_i);
   g.ngrid = 1;
   g.ncube = 1;
   g.lds_tw = 1;

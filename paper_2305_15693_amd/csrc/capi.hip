@@ -1641,6 +1641,7 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
   g.beta = kernel_beta(g.w);
   g.wi = g.w + 1;
   g.beta_i = kernel_beta(g.wi);
+  g.icb = 1.0 / std::cosh(g.beta_i);
   g.nbins = 1;
   g.ngrid = 1;
   g.nhalf = 1;
@@ -1662,6 +1663,7 @@ int fresco_create(fresco_ctx** out, const fresco_problem* p, void* stream) {
       }
       g.nf[a] = next_smooth_even(need);
       g.ufac[a] = (double)g.nf[a] / g.L[a];
+      g.gsc[a] = -(double)g.nf[a] / g.L[a] * 2.0 / g.wi;
       g.T[a] = tdef < g.nf[a] ? tdef : g.nf[a];
       g.tdiv[a] = make_fastdiv((uint32_t)g.T[a]);
       g.nt[a] = (g.nf[a] + g.T[a] - 1) / g.T[a];

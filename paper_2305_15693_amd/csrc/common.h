@@ -79,6 +79,10 @@ struct Geom {
   double beta;    // ES shape parameter of the spreading kernel
   int wi;         // interpolation kernel width (w + 1)
   double beta_i;  // ES shape parameter of the interpolation kernel
+  double icb;     // 1 / cosh(beta_i) (interpolation kernel normalisation)
+  double gsc[3];  // -2 nf / (L wi): grid-to-position derivative scale of the
+                  // interpolation (0 beyond d); per-plan constants, so that no
+                  // thread computes them in FP64
   int T[3];       // tile size per dimension (1 beyond d)
   int nt[3];      // tiles per dimension (1 beyond d)
   int slack;      // cells a footprint start may lie outside its tile (cached

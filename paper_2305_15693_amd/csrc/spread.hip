@@ -1074,9 +1074,9 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
   }
   __syncthreads();
   const R beta = (R)g.beta_i;
-  const R icb = (R)(1.0 / cosh(g.beta_i));
+  const R icb = (R)g.icb;
   R gs[3];
-  for (int a = 0; a < 3; ++a) gs[a] = (a < D) ? (R)(-(double)g.nf[a] / g.L[a] * 2.0 / WI) : R(0);
+  for (int a = 0; a < 3; ++a) gs[a] = (a < D) ? (R)g.gsc[a] : R(0);
   // 2D rows stored as one pair when the output is aligned for it
   const bool pair_store = ((uintptr_t)grad & (2 * sizeof(R) - 1)) == 0;
   for (long long j = s + threadIdx.x; j < e; j += blockDim.x) {
