@@ -46,6 +46,34 @@ def test_lbfgs_trajectory_matches_oracle_fp64(gpu, d, N, L, M):
     ctx.close()
 
 
+@pytest.mark.parametrize("m", [5, 16])
+def test_lbfgs_history_lengths_match_oracle_fp64(gpu, m):
+    """History lengths other than 4 and 8 -- an odd one and the largest, whose
+    update kernels hold half-width packs -- follow the oracle over 24 iterations:
+    the ring fills and then drops its oldest pair every step, so the kept R^-1
+    is extended and truncated many times."""
+    import torch
+    from paper_2305_15693_amd import fresco as F
+    d, N, L, M = 2, 1024, 32.0, 16
+    pos0 = I.positions(N, d, L, np.float64, seed=60 + m)
+    w, s0 = I.stealthy_target(d, M, float(M))
+    ctx = F.Context(d, N, L, M, w_cube=w, s0_cube=s0, tol=1e-12, dtype="f64", device=gpu,
+                    stream=torch.cuda.Stream(device=gpu))
+    ms = ctx.default_max_step()
+    modes, W, S0 = O.constrained_set(d, M, w, s0)
+    ref = LB.run(_oracle_fg(N, d, L, modes, W, S0), pos0, 24, m=m, max_step=ms)
+    pos = torch.from_numpy(pos0.copy()).to(gpu)
+    loss, nev = ctx.step(pos, 24, m=m, max_step=ms)
+    x = pos.cpu().numpy().ravel()
+    err = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"] - pos0.ravel())
+    print(f"m = {m}: loss {loss:.12e} (oracle {ref['f']:.12e}), evaluations {nev} "
+          f"({ref['nevals']}), position error {err:.2e}", flush=True)
+    assert nev == ref["nevals"]
+    assert abs(loss - ref["f"]) <= 1e-9 * ref["fs"][0]
+    assert err < 1e-7
+    ctx.close()
+
+
 def test_lbfgs_fp32_decreases_like_oracle(gpu):
     import torch
     from paper_2305_15693_amd import fresco as F
