@@ -392,7 +392,7 @@ __device__ __forceinline__ void lb_small_direction(LbfgsState* S, int head, int 
     const bool mine = lane < k;
     // ring slot of chronological index j: (head - (k - 1) + j) mod m
     int sl[MM];
-    const int s0 = (head - (k - 1) + m) % m;
+    const int s0 = (head - (k - 1) + m) >= m ? head - (k - 1) : head - (k - 1) + m;
 #pragma unroll
     for (int j = 0; j < MM; ++j) {
       const int q = s0 + j < m ? s0 + j : s0 + j - m;
@@ -445,13 +445,16 @@ __device__ __forceinline__ void lb_small_direction(LbfgsState* S, int head, int 
       S->coefS[si] = u;
       S->coefY[si] = -gam * t;
     }
+    // sums over the k <= MM lanes: a butterfly over the smallest power of two
+    // holding them (every lane gets the sum; the additions are those of a
+    // shuffle-down tree, the other lanes holding zeros)
     double ua = mine ? u * a : 0.0, tb = mine ? t * b : 0.0;
-    for (int off = 32; off > 0; off >>= 1) {
-      ua += __shfl_down(ua, off, 64);
-      tb += __shfl_down(tb, off, 64);
+    constexpr int kSpan = MM <= 1 ? 1 : MM <= 2 ? 2 : MM <= 4 ? 4 : MM <= 8 ? 8 : MM <= 16 ? 16 : 64;
+#pragma unroll
+    for (int off = kSpan / 2; off > 0; off >>= 1) {
+      ua += __shfl_xor(ua, off, 64);
+      tb += __shfl_xor(tb, off, 64);
     }
-    ua = __shfl(ua, 0, 64);
-    tb = __shfl(tb, 0, 64);
     if (lane == 0) S->coefG = gam;
     gtp = -(gam * S->gg + ua - gam * tb);
     if (!(gtp < 0.0) || !isfinite(gtp)) {
@@ -484,9 +487,11 @@ __device__ __forceinline__ void lb_small_wave(LbfgsState* S, const LbfgsOpts& o,
                                               const double* red, long long n) {
   constexpr int M = kLbfgsMaxM;
   const int lane = threadIdx.x & 63;
+  // every lane takes the decision from the state as it stands (the same value);
+  // lane 0 then applies it (of what it changes, only the history count is read
+  // below, and that follows from the decision)
+  const int step = lb_decided_step(S, o, S->f_trial);
   if (lane == 0) lb_decide(S, o);
-  wave_lds_fence();
-  const int step = S->step;
   if (step != LB_ACCEPT && step != LB_INIT && step != LB_RESTART) return;  // uniform
   const int m = o.m;
   double gg = S->gg;
@@ -497,10 +502,10 @@ __device__ __forceinline__ void lb_small_wave(LbfgsState* S, const LbfgsOpts& o,
       S->YG[lane] = red[3 * m + lane];
     }
   }
-  int head = S->head, k = S->k;
+  int head = S->head, k = (step == LB_RESTART) ? 0 : S->k;
   bool added = false;
   if (step == LB_ACCEPT) {
-    const int ns = (head + 1) % m;
+    const int ns = head + 1 == m ? 0 : head + 1;
     const double ys = red[ns], yy = red[m + ns];
     if (ys > 0.0 && yy > 0.0) {
       // dropping the oldest pair when the ring is full: its slot is ns
