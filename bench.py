@@ -517,7 +517,7 @@ def measure_batch(dev, steps):
             "lbfgs_loss_start": float(losses.sum()), "lbfgs_loss_end": loss}
 
 
-def cpu_baseline(res, rho_points=20000, grad_points=10000):
+def cpu_baseline(res, rho_points=200000, grad_points=60000):
     """Oracle timed on a bounded sample of the same evaluation, scaled to one
     full evaluation.  Both of the oracle's sums are linear in the points: rho(k)
     over all constrained modes is timed on `rho_points` of the points and the
