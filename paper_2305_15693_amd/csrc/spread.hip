@@ -1120,6 +1120,9 @@ void interp_kernel(Geom g, const Rec<R>* __restrict__ rec,
     }
     R gx = R(0), gy = R(0), gz = R(0), gv = R(0);
     const int zmax = (D == 3) ? WI : 1;
+    // one footprint plane at a time: unrolled, the compiler hoists the row reads
+    // of several planes and spills registers
+#pragma nounroll
     for (int dz = 0; dz < zmax; ++dz) {
       R sxy = R(0), sdxy = R(0), sxdy = R(0);
 #pragma unroll(interp_row_unroll<R, W>())
