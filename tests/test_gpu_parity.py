@@ -73,8 +73,9 @@ CASES = [
     ("3d_f64_n3000_m6", 3, 3000, 14.4, 6, 6.0, 1e-12, "f64", 1e-11),
     ("2d_f32_n5000_m20_tol1e-5", 2, 5000, 70.7, 20, 20.0, 1e-5, "f32", 1e-4),
     ("2d_f32_n8000_m30_tol1e-3", 2, 8000, 100.0, 30, 30.0, 1e-3, "f32", 1e-2),
-    # narrower 3D kernels (w = 6 and 4)
+    # narrower 3D kernels (w = 6, 5 and 4)
     ("3d_f32_n20000_m10_tol1e-5", 3, 20000, 27.1, 10, 10.0, 1e-5, "f32", 1e-4),
+    ("3d_f32_n16000_m9_tol1e-4", 3, 16000, 25.2, 9, 9.0, 1e-4, "f32", 1e-3),
     ("3d_f32_n12000_m8_tol1e-3", 3, 12000, 22.9, 8, 8.0, 1e-3, "f32", 1e-2),
 ]
 
