@@ -46,10 +46,11 @@ def test_lbfgs_trajectory_matches_oracle_fp64(gpu, d, N, L, M):
     ctx.close()
 
 
-@pytest.mark.parametrize("m", [5, 16])
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 16])
 def test_lbfgs_history_lengths_match_oracle_fp64(gpu, m):
-    """History lengths other than 4 and 8 -- an odd one and the largest, whose
-    update kernels hold half-width packs -- follow the oracle over 24 iterations:
+    """History lengths other than 4 and 8 -- the shortest ones, odd ones and the
+    largest, whose update kernels hold half-width packs -- follow the oracle over
+    24 iterations:
     the ring fills and then drops its oldest pair every step, so the kept R^-1
     is extended and truncated many times."""
     import torch
